@@ -1,0 +1,109 @@
+/*
+ * lbo.h -- CPU oracle for the D2Q9 lattice-Boltzmann method of
+ * Basagaoglu, Harwell, Nguyen & Succi, "Enhanced computational performance of
+ * the lattice Boltzmann model for simulating micron- and submicron-size particle
+ * flows and non-Newtonian fluid flows" (arXiv:2006.12910).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, double-precision solver
+ * that executes the method step by step in the order the paper describes.
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+ * load it.  It shares no code, header, table or constant with the GPU library
+ * (paper_2006_12910_amd/csrc); the two are independent implementations of the
+ * same equations.
+ *
+ * Per-step order (one call of the inner step):
+ *   1. moments rho = sum f, j = sum f e                           (Sec. 2)
+ *   2. relaxation time: tau, or the power-law tau* (Sec. 5, Eqs. nn1-nn5)
+ *   3. equilibrium with u_eq = j/rho + tau* g                     (Sec. 2, Eq. LB2)
+ *   4. BGK collision f* = f - (f - feq)/tau*                      (Eq. LB1 / nn5)
+ *   5. thermal noise added to f*                                  (Sec. 4, Eqs. NP1-NP2)
+ *   6. particle forces from f*: link momentum exchange, covered/uncovered
+ *      node terms, LJ-type repulsion                              (Sec. 3, Eqs. MP1-MP4)
+ *   7. streaming with stationary and moving-wall bounce-back      (Eqs. MP7-MP8)
+ *      followed by Zou-He pressure nodes where configured
+ *   8. Newton-Euler particle update                               (Eqs. MP5-MP6)
+ *   9. relabelling of particle interiors, covered/uncovered terms
+ *
+ * Parity: every function is pinned by the oracle tests against closed
+ * forms, invariants, published known-answer vectors or brute force, except the
+ * covered/uncovered-node force and the LJ repulsion, whose values are
+ * "parity unpinned" (only their symmetry properties are tested).
+ */
+#ifndef LBO_H
+#define LBO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { LBO_PERIODIC = 0, LBO_WALL = 1, LBO_PRESSURE = 2 };
+
+typedef struct lbo_params {
+  int32_t nx, ny;
+  int32_t bc_x, bc_y;           /* LBO_PERIODIC | LBO_WALL | LBO_PRESSURE (x only)   */
+  double rho_in, rho_out;       /* Zou-He densities at x = 0 and x = nx-1            */
+  double tau, rho0, gx, gy;     /* relaxation time, reference density, body accel.   */
+  double kT;                    /* thermal energy; 0 disables noise                  */
+  uint64_t seed;                /* noise generator seed                              */
+  uint32_t domain_id;           /* folded into the generator key                     */
+  int32_t power_law;            /* 0 Newtonian, 1 power-law local tau*               */
+  double n_index, K;            /* flow index n and consistency xi (Eq. nn1)         */
+  double tau_min, tau_max;      /* clamp of tau*                                     */
+  double lj_psi, lj_rit, lj_floor; /* repulsion stiffness, threshold, gap floor      */
+} lbo_params;
+
+enum { LBO_PARTICLE_FIXED = 1 };   /* position and velocities prescribed */
+
+typedef struct lbo_particle {
+  double x, y, radius, density_ratio;
+  double ux, uy, omega;
+  double fx, fy, torque;        /* output: total force / torque of the last step     */
+  int32_t flags;
+  int32_t pad_;
+} lbo_particle;
+
+typedef struct lbo_sim lbo_sim;
+
+/* Returns NULL on invalid parameters.  obstacle_mask ([ny][nx], 1 = solid) may be
+ * NULL; rho/ux/uy ([ny][nx]) may be NULL (rest state rho0, u = 0).  The initial
+ * populations are the equilibria of the given fields. */
+lbo_sim *lbo_create(const lbo_params *p, const uint8_t *obstacle_mask,
+                    const double *rho, const double *ux, const double *uy);
+void lbo_destroy(lbo_sim *s);
+/* 0 on success, -1 if the disc overlaps a solid node or another particle. */
+int lbo_add_particle(lbo_sim *s, const lbo_particle *p);
+void lbo_run(lbo_sim *s, int64_t nsteps);
+int64_t lbo_time(const lbo_sim *s);
+
+/* rho and the reported velocity u = j/rho + g/2; zero on solid nodes. */
+void lbo_moments(const lbo_sim *s, double *rho, double *ux, double *uy);
+/* pre-collision populations f(t), layout [9][ny][nx] */
+void lbo_populations(const lbo_sim *s, double *f);
+void lbo_set_populations(lbo_sim *s, const double *f);
+/* 0 fluid, 1 solid, 2+p inside particle p */
+void lbo_labels(const lbo_sim *s, uint8_t *out);
+int lbo_num_particles(const lbo_sim *s);
+void lbo_get_particles(const lbo_sim *s, lbo_particle *out);
+/* sum of rho over non-solid nodes */
+double lbo_mass(const lbo_sim *s);
+/* total momentum sum j over non-solid nodes (pre-collision) */
+void lbo_momentum(const lbo_sim *s, double *jx, double *jy);
+/* link momentum exchange of the last step, per particle [np][6]: exterior
+ * side (Fx, Fy, T; the force of Eq. MP1 that moves the particle), then the
+ * interior side (diagnostic) */
+void lbo_link_forces(const lbo_sim *s, double *out);
+
+/* Thermal-noise building blocks (exposed for known-answer and bit tests). */
+void lbo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+float lbo_logf(float u);
+void lbo_sincos2pi(float u, float *s, float *c);
+/* the six standard normals Theta_3..Theta_8 of one node and step */
+void lbo_normals(uint64_t seed, uint32_t domain_id, uint32_t node, uint32_t step,
+                 float out[6]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,128 @@
+"""Pins of the oracle's particle module (Sec. 3, Eqs. MP1-MP8).
+
+Link momentum exchange and moving-wall bounce-back are pinned by exact
+momentum identities, lattice symmetry and two closed-form flows (rotating disc
+torque, periodic-array drag).  The covered/uncovered-node force (Eq. MP3) and
+the LJ repulsion (Eq. MP2) are parity unpinned: only their antisymmetry and
+cut-off are checked here.
+"""
+import numpy as np
+import pytest
+
+import closed_forms as cf
+from oracle import Oracle, OracleParams
+from oracle.oracle import WALL
+
+
+def test_labels_match_disc_definition_across_periodic_corner():
+    nx, ny = 30, 26
+    o = Oracle(OracleParams(nx=nx, ny=ny))
+    o.add_particle(1.3, 24.6, 4.7)
+    o.add_particle(15.2, 12.9, 3.1)
+    lab = o.labels()
+    y, x = np.mgrid[0:ny, 0:nx]
+    for q, (cx, cy, R) in enumerate(((1.3, 24.6, 4.7), (15.2, 12.9, 3.1))):
+        dx = (x - cx + nx / 2) % nx - nx / 2
+        dy = (y - cy + ny / 2) % ny - ny / 2
+        assert np.array_equal(lab == 2 + q, dx * dx + dy * dy < R * R)
+
+
+def test_link_force_equals_fluid_momentum_loss():
+    """With the particle held at a prescribed translation and rotation, the
+    fluid momentum changes by exactly minus the momentum exchanged on both
+    sides of the surface: the exterior pulls (Eq. MP1, the particle force) and
+    the interior pulls (Eq. MP7, exchanged with the interior fluid)."""
+    o = Oracle(OracleParams(nx=40, ny=36, tau=0.8))
+    o.add_particle(17.3, 18.6, 6.2, ux=0.01, uy=-0.004, omega=0.002, fixed=True)
+    j0 = np.array(o.momentum())
+    for _ in range(6):
+        o.run(1)
+        j1 = np.array(o.momentum())
+        F = o.link_forces()[0]
+        assert np.abs(j1 - j0 + F[0:2] + F[3:5]).max() < 1e-13
+        assert np.abs(F[:2]).max() > 1e-3 and np.abs(F[3:5]).max() > 1e-3
+        assert np.array_equal(o.particles()[0][7:10], F[0:3])  # no LJ, no covering
+        j0 = j1
+
+
+def test_free_particle_momentum_balance():
+    """Fluid + particle momentum changes only by the interior-side exchange."""
+    o = Oracle(OracleParams(nx=40, ny=36, tau=0.8))
+    o.add_particle(17.5, 18.5, 6.0, density_ratio=1.3, ux=1e-4, uy=-5e-5, omega=1e-4)
+    m = 1.3 * np.pi * 36.0
+
+    def total():
+        return np.array(o.momentum()) + m * o.particles()[0][4:6]
+    for _ in range(20):
+        p0 = total()
+        o.run(1)
+        assert np.abs(total() - p0 + o.link_forces()[0][3:5]).max() < 1e-13
+
+
+@pytest.mark.parametrize("density_ratio", [1.0, 1.05])
+def test_near_neutral_particle_is_stable(density_ratio):
+    o = Oracle(OracleParams(nx=48, ny=40, tau=0.7))
+    o.add_particle(12.2, 20.3, 5.5, density_ratio=density_ratio, ux=0.04, uy=0.01)
+    o.run(400)
+    p = o.particles()[0]
+    assert np.all(np.isfinite(p)) and np.abs(p[4:6]).max() < 0.04
+
+
+def test_mass_conserved_with_moving_particle():
+    o = Oracle(OracleParams(nx=48, ny=40, tau=0.7))
+    o.add_particle(12.2, 20.3, 5.5, ux=0.04, uy=0.01)
+    m0 = o.mass()
+    o.run(150)
+    assert abs(o.mass() - m0) / m0 < 1e-13
+    assert o.particles()[0][0] > 13.2  # the disc edge swept across nodes
+
+
+def test_symmetric_flow_gives_no_lift_no_torque():
+    L, g = 32, 1e-6
+    o = Oracle(OracleParams(nx=L, ny=L, tau=1.0, gx=g))
+    o.add_particle(L / 2, L / 2, 5.0, fixed=True)
+    o.run(3000)
+    p = o.particles()[0]
+    assert p[7] > 0
+    assert abs(p[8]) < 1e-15 and abs(p[9]) < 1e-14
+
+
+def test_rotating_disc_torque():
+    L, R, Om, tau = 48, 6.0, 1e-3, 1.0
+    o = Oracle(OracleParams(nx=L, ny=L, bc_x=WALL, bc_y=WALL, tau=tau))
+    o.add_particle(L / 2 - 0.5, L / 2 - 0.5, R, omega=Om, fixed=True)
+    o.run(20000)
+    T = o.particles()[0][9]
+    r_out = (L - 2) / np.sqrt(np.pi)  # circle of the same area as the cavity
+    ref = cf.couette_torque(cf.nu_of_tau(tau), Om, R, r_out)
+    assert abs(T / ref - 1) < 0.03
+
+
+@pytest.mark.parametrize("R", [4.0, 6.0])
+def test_periodic_array_drag(R):
+    L, g, tau = 48, 1e-6, 1.0
+    o = Oracle(OracleParams(nx=L, ny=L, tau=tau, gx=g))
+    o.add_particle(L / 2, L / 2, R, fixed=True)
+    o.run(30000)
+    r, ux, uy = o.moments()
+    lab = o.labels()
+    U = (r * ux)[lab == 0].sum() / (L * L)
+    F = o.particles()[0][7]
+    # steady state: the drag balances the body force on the exterior fluid
+    assert abs(F / (g * r[lab == 0].sum()) - 1) < 5e-5
+    ref = cf.square_array_drag(cf.nu_of_tau(tau), U, np.pi * R * R / (L * L))
+    assert abs(F / ref - 1) < 0.08
+
+
+def test_repulsion_is_antisymmetric_with_cutoff():
+    o = Oracle(OracleParams(nx=50, ny=30, tau=1.0))
+    o.add_particle(15.5, 15.5, 5.0, fixed=True)
+    o.add_particle(27.3, 16.1, 5.0, fixed=True)  # surface gap ~1.8 < r_it
+    o.add_particle(44.0, 15.0, 3.0, fixed=True)  # far from both
+    o.run(1)
+    p = o.particles()
+    d = p[0, :2] - p[1, :2]
+    np.testing.assert_allclose(p[0, 7:9], -p[1, 7:9], rtol=1e-12)
+    cosang = np.dot(p[0, 7:9], d) / (np.linalg.norm(p[0, 7:9]) * np.linalg.norm(d))
+    assert cosang > 1 - 1e-12  # repulsive, along the centre line
+    assert np.abs(p[2, 7:10]).max() < 1e-14
