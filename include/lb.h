@@ -1,0 +1,204 @@
+/*
+ * lb.h -- C ABI of the MI355X (gfx950) D2Q9 lattice-Boltzmann library.
+ *
+ * The library advances the lattice-Boltzmann model of Basagaoglu, Harwell,
+ * Nguyen & Succi (arXiv:2006.12910) on one GPU:
+ *   - BGK collision with the velocity-shift body force (Sec. 2, Eqs. LB1-LB2),
+ *   - pull streaming with halfway bounce-back on walls and obstacles,
+ *     Zou-He density faces for pressure-driven flow,
+ *   - moving-wall bounce-back and link momentum exchange on circular particles,
+ *     LJ-type repulsion and Newton-Euler updates (Sec. 3, Eqs. MP1-MP8),
+ *   - thermal noise on the non-conserved moments (Sec. 4, Eqs. NP1-NP2,
+ *     Table t1) from a counter-based Philox4x32-10 generator,
+ *   - a local power-law relaxation time (Sec. 5, Eqs. nn1-nn5).
+ *
+ * Conventions
+ *   - Every function returns lb_status (LB_OK = 0, negative on error); no C++
+ *     exception and no abort crosses the ABI.  lb_last_error() returns a
+ *     thread-local description of the last failure on the calling thread.
+ *   - Lattice units (dx = dt = 1).  Host arrays are row-major [ny][nx]
+ *     (x fastest); populations are [9][ny][nx] in the paper's direction order:
+ *     rest, (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1), (-1,-1), (1,-1).
+ *   - Device memory: the caller owns every workspace (any device allocation,
+ *     e.g. a torch uint8 tensor), keeps it alive and unmodified until the
+ *     matching destroy call, and sizes it with the *_workspace_bytes query.
+ *     The library allocates no device memory of its own.
+ *   - Streams: every call is ordered on the HIP stream given at creation
+ *     (hipStream_t passed as void*; NULL is the default stream).  lb_step /
+ *     lb_batch_step only enqueue work.  Calls that return data to the host
+ *     (lb_moments, lb_get_particles, lb_mass, lb_get_populations) synchronise
+ *     that stream and report errors the device latched since the last such
+ *     call (LB_EUNSTABLE for a non-finite density or a particle faster than
+ *     half a node per step).
+ *   - Host arrays passed in are copied before the call returns.
+ *   - A handle is not thread-safe; distinct handles may be used concurrently.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_ABI_VERSION 1u
+
+typedef int32_t lb_status;
+#define LB_OK 0
+#define LB_EINVAL (-1)        /* bad argument or unsupported value             */
+#define LB_ENOMEM (-2)        /* workspace smaller than the query returned     */
+#define LB_EHIP (-3)          /* a HIP runtime call failed                     */
+#define LB_ESTATE (-4)        /* call not allowed in the handle's state        */
+#define LB_EUNSTABLE (-5)     /* device latched a non-finite or runaway value  */
+#define LB_EUNSUPPORTED (-6)  /* valid but not implemented combination         */
+
+/* boundary kinds: per axis */
+#define LB_PERIODIC 0
+#define LB_WALL 1             /* outermost rows (y) / columns (x) are solid     */
+#define LB_PRESSURE 2         /* x only: Zou-He density faces rho_in / rho_out  */
+
+/* population storage.  Arithmetic is FP64 for LB_F64 and FP32 otherwise; the
+ * stored value is the deviation f_i - w_i rho0 (scaled by 2, 8, 32 for the
+ * rest, axis and diagonal directions in the 16-bit formats). */
+#define LB_F64 0
+#define LB_F32 1
+#define LB_F16_DELTA 2
+#define LB_BF16_DELTA 3
+
+#define LB_ROUND_NEAREST 0
+#define LB_ROUND_STOCHASTIC 1  /* 16-bit storage only */
+
+#define LB_INIT_REST 0        /* rho = rho0, u = 0                               */
+#define LB_INIT_FIELDS 1      /* f = equilibrium of init_rho/init_ux/init_uy     */
+
+typedef struct lb_domain_desc {
+  uint32_t abi_version;       /* LB_ABI_VERSION                                  */
+  int32_t nx, ny;             /* lattice size, each in [3, 65536]               */
+  int32_t bc_x, bc_y;         /* LB_PERIODIC | LB_WALL | LB_PRESSURE (x only)   */
+  int32_t storage;            /* LB_F64 | LB_F32 | LB_F16_DELTA | LB_BF16_DELTA */
+  int32_t rounding;           /* LB_ROUND_NEAREST | LB_ROUND_STOCHASTIC         */
+  int32_t obstacles;          /* nonzero: reserve a label plane for lb_set_obstacles */
+  int32_t max_particles;      /* capacity of lb_add_particles, 0..250            */
+  int32_t power_law;          /* nonzero: local tau* of Sec. 5                   */
+  int32_t init_kind;          /* LB_INIT_REST | LB_INIT_FIELDS                   */
+  uint32_t domain_id;         /* folded into the noise key                       */
+  uint64_t seed;              /* noise key                                       */
+  double rho0;                /* reference density (> 0)                         */
+  double tau;                 /* relaxation time (> 1/2); unused with power_law  */
+  double gx, gy;              /* body acceleration g (Sec. 2)                    */
+  double rho_in, rho_out;     /* LB_PRESSURE densities at x = 0 and x = nx-1     */
+  double kT;                  /* thermal energy k_B T; 0 disables noise (Sec. 4) */
+  double n_index, K;          /* power-law index n and consistency xi (Eq. nn1)  */
+  double tau_min, tau_max;    /* clamp of tau*, 1/2 < tau_min <= tau_max         */
+  double lj_psi, lj_rit;      /* repulsion stiffness and threshold (Eq. MP2)     */
+  double lj_floor;            /* smallest gap used in the repulsion (> 0)        */
+  const double *init_rho;     /* LB_INIT_FIELDS: host [ny][nx] fields, copied    */
+  const double *init_ux;
+  const double *init_uy;
+} lb_domain_desc;
+
+#define LB_PARTICLE_FIXED 1   /* position and velocities are held fixed          */
+
+typedef struct lb_particle {
+  double x, y;                /* centre (lattice units; nodes at integers)       */
+  double radius;              /* > 0; interior nodes: |r - r_c| < radius         */
+  double density_ratio;       /* rho_p / rho0 (> 0)                              */
+  double ux, uy, omega;       /* translational and angular velocity              */
+  double fx, fy, torque;      /* output: total force/torque of the last step     */
+  int32_t flags;              /* LB_PARTICLE_FIXED                               */
+  int32_t reserved;
+} lb_particle;
+
+typedef struct lb_domain lb_domain;
+typedef struct lb_batch lb_batch;
+
+/* Workspace size in bytes for a domain described by *desc (validates desc). */
+lb_status lb_workspace_bytes(const lb_domain_desc *desc, size_t *bytes);
+
+/* Create a domain in the caller's device workspace and initialise the
+ * populations (Sec. 2: equilibrium of the initial fields, then the collision
+ * of step 0).  dev_workspace must be 256-byte aligned.  *out receives the
+ * handle.  Errors: LB_EINVAL (desc), LB_ENOMEM (bytes too small), LB_EHIP. */
+lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size_t bytes,
+                           void *hip_stream, lb_domain **out);
+
+/* Mark stationary solid nodes: host mask [ny][nx] (n = nx*ny), nonzero = solid,
+ * bounced back halfway (Sec. 3 obstacles and walls).  Requires desc.obstacles
+ * and no particles yet (LB_ESTATE otherwise). */
+lb_status lb_set_obstacles(lb_domain *d, const uint8_t *host_mask, size_t n);
+
+/* Add n circular particles (Sec. 3).  *first_id receives the index of the
+ * first one.  LB_EINVAL if a disc covers a solid node or another particle,
+ * exceeds max_particles, or its bounding box (radius + lj_rit + 3 nodes each
+ * side) does not fit in a periodic axis; LB_ESTATE if the domain is in a batch. */
+lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_t *first_id);
+
+/* Enqueue nsteps full time steps (collision, noise, streaming, boundaries,
+ * particle coupling) on the domain's stream; nsteps >= 0. */
+lb_status lb_step(lb_domain *d, int64_t nsteps);
+
+/* Density and reported velocity u = j/rho + g/2 at every node (zero on solid
+ * nodes), host FP64 [ny][nx] each.  Synchronises. */
+lb_status lb_moments(lb_domain *d, double *rho, double *ux, double *uy);
+
+/* Same, into device FP64 arrays [ny][nx] (no synchronisation). */
+lb_status lb_moments_device(lb_domain *d, double *dev_rho, double *dev_ux, double *dev_uy);
+
+/* Copy out the first n particles' state (n <= count).  Synchronises. */
+lb_status lb_get_particles(lb_domain *d, lb_particle *out, int32_t n);
+
+/* FP64 sum of rho over non-solid nodes.  Synchronises. */
+lb_status lb_mass(lb_domain *d, double *total);
+
+/* Completed step count. */
+lb_status lb_time(lb_domain *d, int64_t *t);
+
+/* Post-collision state as deviations f*_i - w_i rho0, host FP64 [9][ny][nx]
+ * (get synchronises; set rounds to the storage format).  Together with
+ * lb_time this checkpoints a particle-free domain bit-exactly. */
+lb_status lb_get_populations(lb_domain *d, double *host_dev_f);
+lb_status lb_set_populations(lb_domain *d, const double *host_dev_f);
+
+/* Options (see LB_OPT_*).  Changing one drops the cached step graphs. */
+#define LB_OPT_USE_GRAPH 1     /* 1 (default): lb_step replays a captured hipGraph */
+#define LB_OPT_TILE_WIDTH 2    /* threads per tile row: 64, 128 or 256            */
+#define LB_OPT_ROWS_PER_THREAD 3 /* nodes per thread along y: 1..16               */
+#define LB_OPT_GRAPH_CHUNK 4   /* steps per captured graph, 1..4096 (default 256) */
+lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value);
+lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value);
+
+/* Destroy the handle (the workspace can then be reused).  Synchronises. */
+lb_status lb_destroy_domain(lb_domain *d);
+
+/* Batching: several independent domains with the same storage and features
+ * advance together, one sweep launch per step over the tiles of all of them,
+ * replayed from a hipGraph.  Every domain keeps its own parameters, noise key
+ * and step counter; a batched run is bit-identical to running each domain
+ * alone.  The batch workspace is caller-owned device memory. */
+lb_status lb_batch_workspace_bytes(lb_domain *const *domains, int32_t n, size_t *bytes);
+lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_workspace,
+                          size_t bytes, void *hip_stream, lb_batch **out);
+lb_status lb_batch_step(lb_batch *b, int64_t nsteps);
+lb_status lb_batch_set_option(lb_batch *b, int32_t key, int64_t value);
+lb_status lb_batch_destroy(lb_batch *b);
+
+/* Diagnostic: the six standard normals Theta_3..Theta_8 that the collision of
+ * step `step` adds at nodes node0 .. node0+count-1 of a domain with this seed
+ * and domain_id; device FP32 output [count][6].  Synchronises the stream. */
+lb_status lb_noise_normals(uint64_t seed, uint32_t domain_id, uint32_t step, uint32_t node0,
+                           uint32_t count, float *dev_out, void *hip_stream);
+
+/* Autotune the sweep tile for this domain: times each candidate tile width /
+ * rows-per-thread pair over `steps` steps (the state advances) and keeps the
+ * fastest.  *best_ms receives its time per step. */
+lb_status lb_autotune(lb_domain *d, int32_t steps, double *best_ms);
+
+const char *lb_status_string(lb_status s);
+const char *lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LB_H */

@@ -3,4 +3,5 @@
 TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
 CPU-baseline leg use it to check the GPU library; the library never imports it.
 """
-from .oracle import Oracle, OracleParams, philox4x32_10, normals, own_logf, own_sincos2pi  # noqa: F401
+from .oracle import (Oracle, OracleParams, normals, normals_bulk, own_logf,  # noqa: F401
+                     own_sincos2pi, philox4x32_10)

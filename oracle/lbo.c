@@ -184,6 +184,11 @@ void lbo_normals(uint64_t seed, uint32_t domain_id, uint32_t node, uint32_t step
   box_muller(b0, b1, &out[4], &out[5]);
 }
 
+void lbo_normals_bulk(uint64_t seed, uint32_t domain_id, uint32_t step, uint32_t node0,
+                      uint32_t count, float *out) {
+  for (uint32_t n = 0; n < count; ++n) lbo_normals(seed, domain_id, node0 + n, step, out + 6 * (size_t)n);
+}
+
 /* ---------------------------------------------------------------------- */
 /* Table t1: the nine D2Q9 basis polynomials e_ki of the reduced velocity
  * e_i, their lengths w_k = sum_i omega_i e_ki^2, chi_ki = e_ki / sqrt(w_k). */

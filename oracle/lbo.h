@@ -102,6 +102,9 @@ void lbo_sincos2pi(float u, float *s, float *c);
 /* the six standard normals Theta_3..Theta_8 of one node and step */
 void lbo_normals(uint64_t seed, uint32_t domain_id, uint32_t node, uint32_t step,
                  float out[6]);
+/* the same for nodes node0 .. node0+count-1, out [count][6] */
+void lbo_normals_bulk(uint64_t seed, uint32_t domain_id, uint32_t step, uint32_t node0,
+                      uint32_t count, float *out);
 
 #ifdef __cplusplus
 }

@@ -76,6 +76,8 @@ def _load():
     lib.lbo_logf.argtypes = [C.c_float]
     lib.lbo_sincos2pi.argtypes = [C.c_float, P(C.c_float), P(C.c_float)]
     lib.lbo_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, P(C.c_float)]
+    lib.lbo_normals_bulk.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                     P(C.c_float)]
     _lib = lib
     return lib
 
@@ -218,6 +220,15 @@ def normals(seed, domain_id, node, step):
     lib.lbo_normals(seed & (2**64 - 1), domain_id & 0xFFFFFFFF, node & 0xFFFFFFFF,
                     step & 0xFFFFFFFF, o)
     return np.array([o[i] for i in range(6)], dtype=np.float32)
+
+
+def normals_bulk(seed, domain_id, step, node0, count):
+    """[count][6] FP32 normals of nodes node0 .. node0+count-1 at `step`."""
+    out = np.empty((count, 6), dtype=np.float32)
+    _load().lbo_normals_bulk(seed & (2**64 - 1), domain_id & 0xFFFFFFFF, step & 0xFFFFFFFF,
+                             node0 & 0xFFFFFFFF, count,
+                             out.ctypes.data_as(C.POINTER(C.c_float)))
+    return out
 
 
 def own_logf(u):

@@ -1,0 +1,146 @@
+// aux_impl.h -- reductions and data movement around the sweep: FP64 mass
+// check with a non-finite latch, moments, population export/import, the
+// noise-normal diagnostic and the step counter.
+#pragma once
+
+#include "lb_device.h"
+
+namespace lbk {
+
+__device__ __forceinline__ bool node_is_solid(const DevDomain &D, int x, int y) {
+  if (D.label) return D.label[(size_t)y * D.pitch + x] == LBL_SOLID;
+  return (D.bc_y == BC_WALL && (y == 0 || y == D.ny - 1)) ||
+         (D.bc_x == BC_WALL && (x == 0 || x == D.nx - 1));
+}
+
+// Partial FP64 sums of rho over non-solid nodes, one per block (grid-stride
+// over rows, fixed order inside the block).
+template <int ST>
+__global__ __launch_bounds__(256) void k_mass_partial(const DevDomain *__restrict__ Dp,
+                                                      double *partials) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  __shared__ double red[4];
+  const DevDomain &D = *Dp;
+  const uint64_t T0 = *D.tstep;
+  const T *src = (const T *)D.f[T0 & 1];
+  const size_t plane = (size_t)D.ny * D.pitch;
+  double acc = 0.0;
+  const long long total = (long long)D.ny * D.nx;
+  for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < total;
+       n += (long long)gridDim.x * 256) {
+    const int y = (int)(n / D.nx), x = (int)(n - (long long)y * D.nx);
+    if (node_is_solid(D, x, y)) continue;
+    const uint32_t here = (uint32_t)y * D.pitch + x;
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r += (double)S::load(src + i * plane, here, i);
+    acc += D.rho0 + r;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+#ifdef LBK_COMMON_KERNELS
+__global__ void k_mass_final(const DevDomain *__restrict__ Dp, const double *partials, int n,
+                             double *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += partials[i];
+  *out = s;
+  if (!(fabs(s) < 1e300)) atomicOr(Dp->health, HEALTH_NONFINITE);
+}
+#endif  // LBK_COMMON_KERNELS
+
+// rho and u = j/rho + g/2 of the pre-collision state f(T), recovered from
+// f*(T): collision keeps rho and adds rho g to j.  Band rows [row0, row0+nrows).
+template <int ST>
+__global__ __launch_bounds__(256) void k_moments(const DevDomain *__restrict__ Dp, double *rho_o,
+                                                 double *ux_o, double *uy_o, int row0, int nrows) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  const DevDomain &D = *Dp;
+  const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (n >= (long long)nrows * D.nx) return;
+  const int yl = (int)(n / D.nx), x = (int)(n - (long long)yl * D.nx);
+  const int y = row0 + yl;
+  if (node_is_solid(D, x, y)) {
+    rho_o[n] = 0.0; ux_o[n] = 0.0; uy_o[n] = 0.0;
+    return;
+  }
+  const uint64_t T0 = *D.tstep;
+  const T *src = (const T *)D.f[T0 & 1];
+  const size_t plane = (size_t)D.ny * D.pitch;
+  const uint32_t here = (uint32_t)y * D.pitch + x;
+  double dr = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double v = (double)S::load(src + i * plane, here, i);
+    dr += v;
+    jx += v * cx(i);
+    jy += v * cy(i);
+  }
+  const double rho = D.rho0 + dr;
+  rho_o[n] = rho;
+  ux_o[n] = jx / rho - 0.5 * D.gx;
+  uy_o[n] = jy / rho - 0.5 * D.gy;
+}
+
+// Export / import of the stored deviations as FP64, band layout [9][nrows][nx].
+template <int ST>
+__global__ __launch_bounds__(256) void k_export(const DevDomain *__restrict__ Dp, double *out,
+                                                int row0, int nrows) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  const DevDomain &D = *Dp;
+  const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (n >= (long long)nrows * D.nx) return;
+  const int yl = (int)(n / D.nx), x = (int)(n - (long long)yl * D.nx);
+  const uint64_t T0 = *D.tstep;
+  const T *src = (const T *)D.f[T0 & 1];
+  const size_t plane = (size_t)D.ny * D.pitch;
+  const uint32_t here = (uint32_t)(row0 + yl) * D.pitch + x;
+  for (int i = 0; i < 9; ++i)
+    out[(size_t)i * nrows * D.nx + n] = (double)S::load(src + i * plane, here, i);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_import(const DevDomain *__restrict__ Dp, const double *in,
+                                                int row0, int nrows) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
+  const DevDomain &D = *Dp;
+  const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (n >= (long long)nrows * D.nx) return;
+  const int yl = (int)(n / D.nx), x = (int)(n - (long long)yl * D.nx);
+  const uint64_t T0 = *D.tstep;
+  T *dst = (T *)D.f[T0 & 1];
+  const size_t plane = (size_t)D.ny * D.pitch;
+  const uint32_t here = (uint32_t)(row0 + yl) * D.pitch + x;
+  for (int i = 0; i < 9; ++i)
+    S::put(dst + i * plane, here, i, (R)in[(size_t)i * nrows * D.nx + n], 0u);
+}
+
+#ifdef LBK_COMMON_KERNELS
+__global__ __launch_bounds__(256) void k_normals(uint32_t k0, uint32_t k1, uint32_t step,
+                                                 uint32_t node0, uint32_t count, float *out) {
+  const uint32_t n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= count) return;
+  float th[6];
+  noise_normals(k0, k1, node0 + n, step, th);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) out[(size_t)n * 6 + k] = th[k];
+}
+
+// Advance the step counters of a batch's domains after n captured steps.
+__global__ void k_advance(const DevDomain *__restrict__ doms, int ndom, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ndom) *doms[i].tstep += (uint64_t)n;
+}
+#endif  // LBK_COMMON_KERNELS
+
+}  // namespace lbk

@@ -1,0 +1,32 @@
+// Storage-independent kernels: particle update, relabelling, mass total,
+// noise diagnostic, step counter.
+#define LBK_COMMON_KERNELS 1
+#include "aux_impl.h"
+#include "launch.h"
+#include "particles_impl.h"
+
+namespace lbk {
+
+void launch_pupdate(const DevDomain *doms, const PItem *items, int nitems, int kstep,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_pupdate, dim3((nitems + 63) / 64), dim3(64), 0, s, doms, items, nitems,
+                     kstep);
+}
+void launch_relabel(const DevDomain *doms, const PItem *items, int nitems, int kstep,
+                    int time_offset, hipStream_t s) {
+  hipLaunchKernelGGL(k_relabel, dim3(nitems), dim3(256), 0, s, doms, items, kstep, time_offset);
+}
+void launch_mass_final(const DevDomain *dom, const double *partials, int n, double *out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(64), 0, s, dom, partials, n, out);
+}
+void launch_normals(uint32_t k0, uint32_t k1, uint32_t step, uint32_t node0, uint32_t count,
+                    float *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_normals, dim3((count + 255) / 256), dim3(256), 0, s, k0, k1, step, node0,
+                     count, out);
+}
+void launch_advance(const DevDomain *doms, int ndom, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3((ndom + 63) / 64), dim3(64), 0, s, doms, ndom, n);
+}
+
+}  // namespace lbk

@@ -1,0 +1,90 @@
+// kernels_st.h -- instantiates the kernels of one storage format (LBK_ST) and
+// exposes them through a KernelSet.  Included once per kern_*.hip file so the
+// formats compile in parallel.
+#pragma once
+
+#include "aux_impl.h"
+#include "launch.h"
+#include "particles_impl.h"
+#include "sweep_impl.h"
+
+namespace lbk {
+namespace {
+
+constexpr int ST = LBK_ST;
+
+template <int FEAT, int PLM>
+void sweep_l(const DevDomain *doms, const int *prefix, int ndom, int kstep, int blocks,
+             hipStream_t s) {
+  hipLaunchKernelGGL((k_sweep<ST, FEAT, PLM>), dim3(blocks), dim3(256), 0, s, doms, prefix, ndom,
+                     kstep);
+}
+template <int FEAT, int PLM>
+void init_l(const DevDomain *dom, const double *rho, const double *ux, const double *uy, int row0,
+            int nrows, int pitch, hipStream_t s) {
+  const long long n = (long long)nrows * pitch;
+  hipLaunchKernelGGL((k_init<ST, FEAT, PLM>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     dom, rho, ux, uy, row0, nrows);
+}
+void link_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
+  hipLaunchKernelGGL((k_link<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
+}
+void cover_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
+  hipLaunchKernelGGL((k_cover<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
+}
+void mass_l(const DevDomain *dom, double *partials, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_mass_partial<ST>), dim3(blocks), dim3(256), 0, s, dom, partials);
+}
+void moments_l(const DevDomain *dom, double *rho, double *ux, double *uy, int row0, int nrows,
+               int nx, hipStream_t s) {
+  const long long n = (long long)nrows * nx;
+  hipLaunchKernelGGL((k_moments<ST>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dom,
+                     rho, ux, uy, row0, nrows);
+}
+void export_l(const DevDomain *dom, double *out, int row0, int nrows, int nx, hipStream_t s) {
+  const long long n = (long long)nrows * nx;
+  hipLaunchKernelGGL((k_export<ST>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dom, out,
+                     row0, nrows);
+}
+void import_l(const DevDomain *dom, const double *in, int row0, int nrows, int nx,
+              hipStream_t s) {
+  const long long n = (long long)nrows * nx;
+  hipLaunchKernelGGL((k_import<ST>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dom, in,
+                     row0, nrows);
+}
+
+template <int FEAT, int PLM> void fill(KernelSet *k) {
+  k->sweep = sweep_l<FEAT, PLM>;
+  k->init = init_l<FEAT, PLM>;
+  k->link = link_l;
+  k->cover = cover_l;
+  k->mass_partial = mass_l;
+  k->moments = moments_l;
+  k->export_f = export_l;
+  k->import_f = import_l;
+}
+
+template <int BASE> bool pick_power(int feat, int plm, KernelSet *k) {
+  if (!(feat & F_POWER)) { fill<BASE, PL_GENERIC>(k); return true; }
+  switch (plm) {
+    case PL_GENERIC: fill<BASE | F_POWER, PL_GENERIC>(k); return true;
+    case PL_HALF: fill<BASE | F_POWER, PL_HALF>(k); return true;
+    case PL_3Q: fill<BASE | F_POWER, PL_3Q>(k); return true;
+    case PL_3H: fill<BASE | F_POWER, PL_3H>(k); return true;
+  }
+  return false;
+}
+
+}  // namespace
+
+bool LBK_GETTER(int feat, int plm, KernelSet *k) {
+  switch (feat & (F_LABELS | F_NOISE)) {
+    case 0: return pick_power<0>(feat, plm, k);
+    case F_LABELS: return pick_power<F_LABELS>(feat, plm, k);
+    case F_NOISE: return pick_power<F_NOISE>(feat, plm, k);
+    case F_LABELS | F_NOISE: return pick_power<F_LABELS | F_NOISE>(feat, plm, k);
+  }
+  return false;
+}
+
+}  // namespace lbk

@@ -1,0 +1,39 @@
+// launch.h -- host-side entry points into the kernels (internal to the library).
+#pragma once
+
+#include "lb_device.h"
+
+namespace lbk {
+
+struct KernelSet {
+  void (*sweep)(const DevDomain *doms, const int *prefix, int ndom, int kstep, int blocks,
+                hipStream_t s);
+  void (*init)(const DevDomain *dom, const double *rho, const double *ux, const double *uy,
+               int row0, int nrows, int pitch, hipStream_t s);
+  void (*link)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
+  void (*cover)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
+  void (*mass_partial)(const DevDomain *dom, double *partials, int blocks, hipStream_t s);
+  void (*moments)(const DevDomain *dom, double *rho, double *ux, double *uy, int row0, int nrows,
+                  int nx, hipStream_t s);
+  void (*export_f)(const DevDomain *dom, double *out, int row0, int nrows, int nx, hipStream_t s);
+  void (*import_f)(const DevDomain *dom, const double *in, int row0, int nrows, int nx,
+                   hipStream_t s);
+};
+
+// Kernel set of a storage format / feature set / power-law specialisation.
+bool kernels_f64(int feat, int plm, KernelSet *k);
+bool kernels_f32(int feat, int plm, KernelSet *k);
+bool kernels_f16(int feat, int plm, KernelSet *k);
+bool kernels_bf16(int feat, int plm, KernelSet *k);
+
+void launch_pupdate(const DevDomain *doms, const PItem *items, int nitems, int kstep,
+                    hipStream_t s);
+void launch_relabel(const DevDomain *doms, const PItem *items, int nitems, int kstep,
+                    int time_offset, hipStream_t s);
+void launch_mass_final(const DevDomain *dom, const double *partials, int n, double *out,
+                       hipStream_t s);
+void launch_normals(uint32_t k0, uint32_t k1, uint32_t step, uint32_t node0, uint32_t count,
+                    float *out, hipStream_t s);
+void launch_advance(const DevDomain *doms, int ndom, int n, hipStream_t s);
+
+}  // namespace lbk

@@ -1,0 +1,847 @@
+// lb_api.hip -- C ABI of the library (declared in include/lb.h): argument
+// validation, workspace layout, per-step launch sequence, hipGraph capture of
+// step chunks, batching, host<->device transfers and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "lb.h"
+#include "launch.h"
+
+using namespace lbk;
+
+namespace {
+
+thread_local std::string g_err;
+
+lb_status fail(lb_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(LB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+int storage_bytes(int st) { return st == LB_F64 ? 8 : (st == LB_F32 ? 4 : 2); }
+
+constexpr int MAX_PARTICLES = 250;
+constexpr int NPARTIALS = 1024;
+constexpr size_t STAGE_TARGET = size_t(16) << 20;  // bytes of the host-transfer staging band
+
+struct Layout {
+  int pitch = 0, band_rows = 0;
+  size_t desc = 0, hdr = 0, f0 = 0, f1 = 0, label = 0, ps0 = 0, ps1 = 0, pforce = 0, items = 0,
+         partials = 0, stage = 0, prefix = 0, total = 0;
+};
+
+// header block: step counter, health word, mass result
+struct Header {
+  uint64_t tstep;
+  uint32_t health;
+  uint32_t pad;
+  double mass;
+};
+
+bool needs_labels(const lb_domain_desc *d) { return d->obstacles != 0 || d->max_particles > 0; }
+
+Layout layout_of(const lb_domain_desc *d) {
+  Layout L;
+  L.pitch = (d->nx + 63) / 64 * 64;
+  const size_t plane = (size_t)d->ny * L.pitch;
+  const size_t fbytes = 9 * plane * storage_bytes(d->storage);
+  const size_t row_stage = (size_t)9 * d->nx * sizeof(double);
+  L.band_rows = (int)std::max<size_t>(1, std::min<size_t>(d->ny, STAGE_TARGET / row_stage));
+  size_t o = 0;
+  L.desc = o; o += align256(sizeof(DevDomain));
+  L.hdr = o; o += align256(sizeof(Header));
+  L.f0 = o; o += align256(fbytes);
+  L.f1 = o; o += align256(fbytes);
+  L.label = o; if (needs_labels(d)) o += align256(plane);
+  const size_t np = (size_t)std::max(d->max_particles, 0);
+  L.ps0 = o; o += align256(np * sizeof(PState));
+  L.ps1 = o; o += align256(np * sizeof(PState));
+  L.pforce = o; o += align256(np * sizeof(PForce));
+  L.items = o; o += align256(np * sizeof(PItem));
+  L.partials = o; o += align256(NPARTIALS * sizeof(double));
+  L.stage = o; o += align256((size_t)L.band_rows * row_stage);
+  L.prefix = o; o += align256(2 * sizeof(int));
+  L.total = o;
+  return L;
+}
+
+lb_status validate(const lb_domain_desc *d) {
+  if (!d) return fail(LB_EINVAL, "desc is null");
+  if (d->abi_version != LB_ABI_VERSION) return fail(LB_EINVAL, "abi_version mismatch");
+  if (d->nx < 3 || d->ny < 3 || d->nx > 65536 || d->ny > 65536)
+    return fail(LB_EINVAL, "nx, ny must be in [3, 65536]");
+  if ((long long)d->nx * d->ny * 9 >= (1LL << 32) / 2)
+    return fail(LB_EINVAL, "lattice too large for 32-bit plane offsets");
+  if (d->bc_x < LB_PERIODIC || d->bc_x > LB_PRESSURE) return fail(LB_EINVAL, "bad bc_x");
+  if (d->bc_y != LB_PERIODIC && d->bc_y != LB_WALL) return fail(LB_EINVAL, "bad bc_y");
+  if (d->storage < LB_F64 || d->storage > LB_BF16_DELTA) return fail(LB_EINVAL, "bad storage");
+  if (d->rounding != LB_ROUND_NEAREST && d->rounding != LB_ROUND_STOCHASTIC)
+    return fail(LB_EINVAL, "bad rounding");
+  if (d->rounding == LB_ROUND_STOCHASTIC && d->storage < LB_F16_DELTA)
+    return fail(LB_EINVAL, "stochastic rounding needs 16-bit storage");
+  if (d->max_particles < 0 || d->max_particles > MAX_PARTICLES)
+    return fail(LB_EINVAL, "max_particles must be in [0, 250]");
+  if (!(d->rho0 > 0.0) || !std::isfinite(d->rho0)) return fail(LB_EINVAL, "rho0 must be > 0");
+  if (!d->power_law && !(d->tau > 0.5)) return fail(LB_EINVAL, "tau must be > 1/2");
+  if (d->power_law) {
+    if (!(d->tau_min > 0.5) || !(d->tau_max >= d->tau_min) || !(d->n_index > 0.0) || !(d->K > 0.0))
+      return fail(LB_EINVAL, "power law needs n > 0, K > 0, 1/2 < tau_min <= tau_max");
+  }
+  if (!(d->kT >= 0.0)) return fail(LB_EINVAL, "kT must be >= 0");
+  if (!std::isfinite(d->gx) || !std::isfinite(d->gy)) return fail(LB_EINVAL, "g not finite");
+  if (d->bc_x == LB_PRESSURE && (!(d->rho_in > 0.0) || !(d->rho_out > 0.0)))
+    return fail(LB_EINVAL, "pressure faces need rho_in, rho_out > 0");
+  if (d->max_particles > 0 && (!(d->lj_rit > 0.0) || !(d->lj_floor > 0.0) || !(d->lj_psi >= 0.0)))
+    return fail(LB_EINVAL, "particles need lj_rit > 0, lj_floor > 0, lj_psi >= 0");
+  if (d->init_kind != LB_INIT_REST && d->init_kind != LB_INIT_FIELDS)
+    return fail(LB_EINVAL, "bad init_kind");
+  if (d->init_kind == LB_INIT_FIELDS && (!d->init_rho || !d->init_ux || !d->init_uy))
+    return fail(LB_EINVAL, "LB_INIT_FIELDS needs init_rho, init_ux, init_uy");
+  return LB_OK;
+}
+
+int plm_of(double n) {
+  if (n == 0.5) return PL_HALF;
+  if (n == 0.75) return PL_3Q;
+  if (n == 1.5) return PL_3H;
+  return PL_GENERIC;
+}
+
+int feat_of(const lb_domain_desc *d) {
+  int f = 0;
+  if (needs_labels(d)) f |= F_LABELS;
+  if (d->kT > 0.0) f |= F_NOISE;
+  if (d->power_law) f |= F_POWER;
+  if (d->bc_x == LB_PRESSURE) f |= F_PRESSURE;
+  if (d->rounding == LB_ROUND_STOCHASTIC) f |= F_STOCH;
+  return f;
+}
+
+bool get_kernels(int st, int feat, int plm, KernelSet *k) {
+  switch (st) {
+    case LB_F64: return kernels_f64(feat, plm, k);
+    case LB_F32: return kernels_f32(feat, plm, k);
+    case LB_F16_DELTA: return kernels_f16(feat, plm, k);
+    case LB_BF16_DELTA: return kernels_bf16(feat, plm, k);
+  }
+  return false;
+}
+
+int default_tile_w(int nx) { return nx >= 256 ? 256 : (nx >= 128 ? 128 : 64); }
+
+// Graph cache of captured step chunks, keyed by chunk length.
+struct GraphCache {
+  std::map<int, hipGraphExec_t> execs;
+  void clear() {
+    for (auto &kv : execs) (void)hipGraphExecDestroy(kv.second);
+    execs.clear();
+  }
+};
+
+}  // namespace
+
+struct lb_domain {
+  lb_domain_desc desc{};
+  Layout L;
+  char *ws = nullptr;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  DevDomain hd{};
+  int feat = 0, plm = 0;
+  KernelSet ks{};
+  int np = 0;
+  int64_t t = 0;
+  bool use_graph = true;
+  int chunk = 256;
+  GraphCache graphs;
+  int in_batches = 0;
+  std::vector<uint8_t> host_labels;  // walls + obstacles, [ny][pitch]
+
+  DevDomain *ddesc() const { return (DevDomain *)(ws + L.desc); }
+  Header *dhdr() const { return (Header *)(ws + L.hdr); }
+  int *dprefix() const { return (int *)(ws + L.prefix); }
+  PItem *ditems() const { return (PItem *)(ws + L.items); }
+  int ntiles() const { return hd.tiles_x * hd.tiles_y; }
+};
+
+struct lb_batch {
+  std::vector<lb_domain *> doms;
+  char *ws = nullptr;
+  hipStream_t stream = nullptr, cap = nullptr;
+  KernelSet ks{};
+  int total_tiles = 0, nitems = 0;
+  size_t off_desc = 0, off_prefix = 0, off_items = 0, bytes = 0;
+  bool use_graph = true;
+  int chunk = 256;
+  GraphCache graphs;
+  DevDomain *ddesc() const { return (DevDomain *)(ws + off_desc); }
+  int *dprefix() const { return (int *)(ws + off_prefix); }
+  PItem *ditems() const { return (PItem *)(ws + off_items); }
+};
+
+namespace {
+
+void set_tiles(DevDomain &hd, int tile_w, int rpt) {
+  hd.tile_w = tile_w;
+  hd.rows_per_thread = rpt;
+  hd.tiles_x = (hd.nx + tile_w - 1) / tile_w;
+  const int th = (256 / tile_w) * rpt;
+  hd.tiles_y = (hd.ny + th - 1) / th;
+}
+
+lb_status push_desc(lb_domain *d) {
+  HIPCHK(hipMemcpyAsync(d->ddesc(), &d->hd, sizeof(DevDomain), hipMemcpyHostToDevice, d->stream));
+  int pre[2] = {0, d->ntiles()};
+  HIPCHK(hipMemcpyAsync(d->dprefix(), pre, sizeof(pre), hipMemcpyHostToDevice, d->stream));
+  HIPCHK(hipStreamSynchronize(d->stream));
+  return LB_OK;
+}
+
+lb_status check_health(lb_domain *d) {
+  uint32_t h = 0;
+  HIPCHK(hipMemcpyAsync(&h, &d->dhdr()->health, sizeof(h), hipMemcpyDeviceToHost, d->stream));
+  HIPCHK(hipStreamSynchronize(d->stream));
+  if (h) {
+    std::string m = "device latched:";
+    if (h & HEALTH_NONFINITE) m += " non-finite density;";
+    if (h & HEALTH_FAST_PARTICLE) m += " particle faster than 0.5 nodes/step;";
+    if (h & HEALTH_LINK_OVERFLOW) m += " particle link list overflow;";
+    return fail(LB_EUNSTABLE, m);
+  }
+  return LB_OK;
+}
+
+// Enqueue `n` steps of the launch sequence on stream s (eager or under capture).
+void record_steps(const KernelSet &ks, const DevDomain *doms, const int *prefix, int ndom,
+                  int blocks, const PItem *items, int nitems, int n, hipStream_t s) {
+  for (int k = 0; k < n; ++k) {
+    if (nitems > 0) {
+      ks.link(doms, items, nitems, k, s);
+      launch_pupdate(doms, items, nitems, k, s);
+    }
+    ks.sweep(doms, prefix, ndom, k, blocks, s);
+    if (nitems > 0) {
+      ks.cover(doms, items, nitems, k, s);
+      launch_relabel(doms, items, nitems, k, 1, s);
+    }
+  }
+  launch_advance(doms, ndom, n, s);
+}
+
+lb_status run_chunk(GraphCache &gc, bool use_graph, hipStream_t stream, hipStream_t cap,
+                    const KernelSet &ks, const DevDomain *doms, const int *prefix, int ndom,
+                    int blocks, const PItem *items, int nitems, int n) {
+  if (!use_graph) {
+    record_steps(ks, doms, prefix, ndom, blocks, items, nitems, n, stream);
+    HIPCHK(hipGetLastError());
+    return LB_OK;
+  }
+  auto it = gc.execs.find(n);
+  if (it == gc.execs.end()) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    record_steps(ks, doms, prefix, ndom, blocks, items, nitems, n, cap);
+    hipError_t le = hipGetLastError();
+    HIPCHK(hipStreamEndCapture(cap, &g));
+    if (le != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(LB_EHIP, std::string("kernel launch during capture: ") + hipGetErrorString(le));
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(LB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    it = gc.execs.emplace(n, ex).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, stream));
+  return LB_OK;
+}
+
+lb_status domain_mass_enqueue(lb_domain *d) {
+  d->ks.mass_partial(d->ddesc(), (double *)(d->ws + d->L.partials), NPARTIALS, d->stream);
+  launch_mass_final(d->ddesc(), (double *)(d->ws + d->L.partials), NPARTIALS, &d->dhdr()->mass,
+                    d->stream);
+  HIPCHK(hipGetLastError());
+  return LB_OK;
+}
+
+lb_status upload_labels(lb_domain *d) {
+  HIPCHK(hipMemcpyAsync(d->ws + d->L.label, d->host_labels.data(), d->host_labels.size(),
+                        hipMemcpyHostToDevice, d->stream));
+  HIPCHK(hipStreamSynchronize(d->stream));
+  return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lb_status_string(lb_status s) {
+  switch (s) {
+    case LB_OK: return "ok";
+    case LB_EINVAL: return "invalid argument";
+    case LB_ENOMEM: return "workspace too small";
+    case LB_EHIP: return "HIP runtime error";
+    case LB_ESTATE: return "call not allowed in this state";
+    case LB_EUNSTABLE: return "simulation became unstable";
+    case LB_EUNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+const char *lb_last_error(void) { return g_err.c_str(); }
+
+lb_status lb_workspace_bytes(const lb_domain_desc *desc, size_t *bytes) {
+  if (!bytes) return fail(LB_EINVAL, "bytes is null");
+  lb_status s = validate(desc);
+  if (s != LB_OK) return s;
+  *bytes = layout_of(desc).total;
+  return LB_OK;
+}
+
+lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size_t bytes,
+                           void *hip_stream, lb_domain **out) {
+  if (!out) return fail(LB_EINVAL, "out is null");
+  *out = nullptr;
+  lb_status s = validate(desc);
+  if (s != LB_OK) return s;
+  if (!dev_workspace || ((uintptr_t)dev_workspace & 255)) return fail(LB_EINVAL, "workspace must be non-null and 256-byte aligned");
+  Layout L = layout_of(desc);
+  if (bytes < L.total) return fail(LB_ENOMEM, "workspace smaller than lb_workspace_bytes");
+  const int feat = feat_of(desc);
+  const int plm = desc->power_law ? plm_of(desc->n_index) : PL_GENERIC;
+  KernelSet ks{};
+  if (!get_kernels(desc->storage, feat, plm, &ks)) return fail(LB_EUNSUPPORTED, "no kernel for this feature set");
+
+  lb_domain *d = new lb_domain();
+  d->desc = *desc;
+  d->desc.init_rho = d->desc.init_ux = d->desc.init_uy = nullptr;
+  d->L = L;
+  d->ws = (char *)dev_workspace;
+  d->stream = (hipStream_t)hip_stream;
+  d->feat = feat;
+  d->plm = plm;
+  d->ks = ks;
+  if (hipStreamCreateWithFlags(&d->cap, hipStreamNonBlocking) != hipSuccess) {
+    delete d;
+    return fail(LB_EHIP, "hipStreamCreateWithFlags failed");
+  }
+  DevDomain &h = d->hd;
+  h.f[0] = d->ws + L.f0;
+  h.f[1] = d->ws + L.f1;
+  h.label = needs_labels(desc) ? (uint8_t *)(d->ws + L.label) : nullptr;
+  h.tstep = &d->dhdr()->tstep;
+  h.health = &d->dhdr()->health;
+  h.pstate[0] = (PState *)(d->ws + L.ps0);
+  h.pstate[1] = (PState *)(d->ws + L.ps1);
+  h.pforce = (PForce *)(d->ws + L.pforce);
+  h.nx = desc->nx;
+  h.ny = desc->ny;
+  h.pitch = L.pitch;
+  h.bc_x = desc->bc_x;
+  h.bc_y = desc->bc_y;
+  h.np = 0;
+  set_tiles(h, default_tile_w(desc->nx), 1);
+  h.key0 = (uint32_t)desc->seed;
+  h.key1 = (uint32_t)(desc->seed >> 32) ^ desc->domain_id;
+  h.storage = desc->storage;
+  h.feat = feat;
+  h.rho0 = desc->rho0;
+  h.tau = desc->power_law ? desc->tau_min : desc->tau;
+  h.omega = 1.0 / h.tau;
+  h.gx = desc->gx;
+  h.gy = desc->gy;
+  h.rho_in = desc->rho_in;
+  h.rho_out = desc->rho_out;
+  h.kT = desc->kT;
+  h.pl_n = desc->n_index;
+  h.pl_K = desc->K;
+  h.tau_min = desc->tau_min;
+  h.tau_max = desc->tau_max;
+  h.lj_psi = desc->lj_psi;
+  h.lj_rit = desc->lj_rit;
+  h.lj_floor = desc->lj_floor;
+  h.rho0_f = (float)h.rho0;
+  h.tau_f = (float)h.tau;
+  h.omega_f = (float)h.omega;
+  h.gx_f = (float)h.gx;
+  h.gy_f = (float)h.gy;
+  h.rho_in_f = (float)h.rho_in;
+  h.rho_out_f = (float)h.rho_out;
+  h.kT_f = (float)h.kT;
+  h.pl_n_f = (float)h.pl_n;
+  h.pl_K_f = (float)h.pl_K;
+  h.tau_min_f = (float)h.tau_min;
+  h.tau_max_f = (float)h.tau_max;
+
+  auto bail = [&](lb_status st) {
+    (void)hipStreamDestroy(d->cap);
+    delete d;
+    return st;
+  };
+  Header zero{};
+  if (hipMemcpyAsync(d->dhdr(), &zero, sizeof(zero), hipMemcpyHostToDevice, d->stream) != hipSuccess)
+    return bail(fail(LB_EHIP, "header upload failed"));
+  if ((s = push_desc(d)) != LB_OK) return bail(s);
+  if (h.label) {
+    d->host_labels.assign((size_t)desc->ny * L.pitch, 0);
+    for (int y = 0; y < desc->ny; ++y)
+      for (int x = 0; x < desc->nx; ++x) {
+        const bool wall = (desc->bc_y == LB_WALL && (y == 0 || y == desc->ny - 1)) ||
+                          (desc->bc_x == LB_WALL && (x == 0 || x == desc->nx - 1));
+        d->host_labels[(size_t)y * L.pitch + x] = wall ? LBL_SOLID : LBL_FLUID;
+      }
+    if ((s = upload_labels(d)) != LB_OK) return bail(s);
+  }
+  // initial populations: equilibrium of the fields, then the step-0 collision
+  if (desc->init_kind == LB_INIT_FIELDS) {
+    double *st = (double *)(d->ws + L.stage);
+    const size_t nxs = (size_t)desc->nx;
+    for (int r0 = 0; r0 < desc->ny; r0 += L.band_rows) {
+      const int nr = std::min(L.band_rows, desc->ny - r0);
+      const size_t cnt = (size_t)nr * nxs;
+      if (hipMemcpyAsync(st, desc->init_rho + (size_t)r0 * nxs, cnt * 8, hipMemcpyHostToDevice, d->stream) != hipSuccess ||
+          hipMemcpyAsync(st + cnt, desc->init_ux + (size_t)r0 * nxs, cnt * 8, hipMemcpyHostToDevice, d->stream) != hipSuccess ||
+          hipMemcpyAsync(st + 2 * cnt, desc->init_uy + (size_t)r0 * nxs, cnt * 8, hipMemcpyHostToDevice, d->stream) != hipSuccess)
+        return bail(fail(LB_EHIP, "initial field upload failed"));
+      ks.init(d->ddesc(), st, st + cnt, st + 2 * cnt, r0, nr, L.pitch, d->stream);
+      if (hipStreamSynchronize(d->stream) != hipSuccess) return bail(fail(LB_EHIP, "init kernel failed"));
+    }
+  } else {
+    ks.init(d->ddesc(), nullptr, nullptr, nullptr, 0, desc->ny, L.pitch, d->stream);
+  }
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(d->stream) != hipSuccess)
+    return bail(fail(LB_EHIP, "initialisation failed"));
+  *out = d;
+  return LB_OK;
+}
+
+lb_status lb_set_obstacles(lb_domain *d, const uint8_t *mask, size_t n) {
+  if (!d || !mask) return fail(LB_EINVAL, "null argument");
+  if (!d->hd.label) return fail(LB_ESTATE, "domain was created without obstacles");
+  if (d->np > 0) return fail(LB_ESTATE, "obstacles must be set before particles are added");
+  if (d->in_batches) return fail(LB_ESTATE, "domain is in a batch");
+  if (n != (size_t)d->desc.nx * d->desc.ny) return fail(LB_EINVAL, "mask size must be nx*ny");
+  const int nx = d->desc.nx, ny = d->desc.ny, pitch = d->L.pitch;
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const bool wall = (d->desc.bc_y == LB_WALL && (y == 0 || y == ny - 1)) ||
+                        (d->desc.bc_x == LB_WALL && (x == 0 || x == nx - 1));
+      d->host_labels[(size_t)y * pitch + x] = (wall || mask[(size_t)y * nx + x]) ? LBL_SOLID : LBL_FLUID;
+    }
+  return upload_labels(d);
+}
+
+lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_t *first_id) {
+  if (!d || (!p && n > 0)) return fail(LB_EINVAL, "null argument");
+  if (d->in_batches) return fail(LB_ESTATE, "domain is in a batch");
+  if (n < 0 || d->np + n > d->desc.max_particles) return fail(LB_EINVAL, "exceeds max_particles");
+  if (n == 0) {
+    if (first_id) *first_id = d->np;
+    return LB_OK;
+  }
+  const int nx = d->desc.nx, ny = d->desc.ny, pitch = d->L.pitch;
+  const bool perx = d->desc.bc_x == LB_PERIODIC, pery = d->desc.bc_y == LB_PERIODIC;
+  // current particle states (they move on the device)
+  std::vector<PState> cur(d->np + n);
+  if (d->np > 0) {
+    HIPCHK(hipMemcpyAsync(cur.data(), d->hd.pstate[d->t & 1], d->np * sizeof(PState),
+                          hipMemcpyDeviceToHost, d->stream));
+    HIPCHK(hipStreamSynchronize(d->stream));
+  }
+  auto mimg = [](double v, double len, bool per) { return per ? v - len * std::floor(v / len + 0.5) : v; };
+  for (int k = 0; k < n; ++k) {
+    const lb_particle &q = p[k];
+    if (!(q.radius > 0.0) || !(q.density_ratio > 0.0) || !std::isfinite(q.x) || !std::isfinite(q.y) ||
+        q.x < 0.0 || q.y < 0.0 || q.x >= nx || q.y >= ny)
+      return fail(LB_EINVAL, "particle outside the domain or bad radius/density");
+    const int reach = std::max((int)std::ceil(q.radius + d->desc.lj_rit) + 1, (int)std::ceil(q.radius) + 3);
+    const int W = 2 * reach + 2;
+    if ((perx && W > nx) || (pery && W > ny)) return fail(LB_EINVAL, "particle box wider than a periodic axis");
+    if (d->desc.bc_x == LB_PRESSURE && (q.x - reach < 1.0 || q.x + reach > nx - 2.0))
+      return fail(LB_EINVAL, "particle box touches a pressure face");
+    if ((2 * reach + 2) * (2 * reach + 2) * 8 > 6144 * 8) return fail(LB_EINVAL, "particle radius too large");
+    PState s{};
+    s.x = q.x; s.y = q.y; s.ux = q.ux; s.uy = q.uy; s.omega = q.omega;
+    s.radius = q.radius;
+    s.rho_ratio = q.density_ratio;
+    const double rhop = q.density_ratio * d->desc.rho0;
+    s.mass = rhop * M_PI * q.radius * q.radius;
+    s.inertia = 0.5 * s.mass * q.radius * q.radius;
+    s.flags = q.flags & LB_PARTICLE_FIXED;
+    cur[d->np + k] = s;
+  }
+  // overlap: no node of a new disc may be solid or inside another particle
+  for (int k = 0; k < n; ++k) {
+    const PState &s = cur[d->np + k];
+    const int r = (int)std::ceil(s.radius) + 1;
+    for (int yy = (int)std::floor(s.y) - r; yy <= (int)std::floor(s.y) + r + 1; ++yy)
+      for (int xx = (int)std::floor(s.x) - r; xx <= (int)std::floor(s.x) + r + 1; ++xx) {
+        int x = xx, y = yy;
+        if (x < 0 || x >= nx) { if (!perx) continue; x = (x + nx) % nx; }
+        if (y < 0 || y >= ny) { if (!pery) continue; y = (y + ny) % ny; }
+        const double dx = mimg(x - s.x, nx, perx), dy = mimg(y - s.y, ny, pery);
+        if (!(dx * dx + dy * dy < s.radius * s.radius)) continue;
+        if (d->host_labels[(size_t)y * pitch + x] == LBL_SOLID)
+          return fail(LB_EINVAL, "particle covers a solid node");
+        for (int q = 0; q < d->np + n; ++q) {
+          if (q == d->np + k) continue;
+          const double ex = mimg(x - cur[q].x, nx, perx), ey = mimg(y - cur[q].y, ny, pery);
+          if (ex * ex + ey * ey < cur[q].radius * cur[q].radius)
+            return fail(LB_EINVAL, "particle overlaps another particle");
+        }
+      }
+  }
+  const int first = d->np;
+  HIPCHK(hipMemcpyAsync(d->hd.pstate[d->t & 1] + first, cur.data() + first, n * sizeof(PState),
+                        hipMemcpyHostToDevice, d->stream));
+  std::vector<PForce> zf(n);
+  std::memset(zf.data(), 0, n * sizeof(PForce));
+  HIPCHK(hipMemcpyAsync(d->hd.pforce + first, zf.data(), n * sizeof(PForce), hipMemcpyHostToDevice, d->stream));
+  d->np += n;
+  d->hd.np = d->np;
+  std::vector<PItem> items(d->np);
+  for (int q = 0; q < d->np; ++q) items[q] = PItem{0, q};
+  HIPCHK(hipMemcpyAsync(d->ditems(), items.data(), d->np * sizeof(PItem), hipMemcpyHostToDevice, d->stream));
+  lb_status s = push_desc(d);
+  if (s != LB_OK) return s;
+  launch_relabel(d->ddesc(), d->ditems(), d->np, 0, 0, d->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(d->stream));
+  d->graphs.clear();
+  if (first_id) *first_id = first;
+  return LB_OK;
+}
+
+lb_status lb_step(lb_domain *d, int64_t nsteps) {
+  if (!d) return fail(LB_EINVAL, "null domain");
+  if (nsteps < 0) return fail(LB_EINVAL, "nsteps < 0");
+  int64_t left = nsteps;
+  while (left > 0) {
+    const int c = (int)std::min<int64_t>(left, d->chunk);
+    lb_status s = run_chunk(d->graphs, d->use_graph, d->stream, d->cap, d->ks, d->ddesc(),
+                            d->dprefix(), 1, d->ntiles(), d->ditems(), d->np, c);
+    if (s != LB_OK) return s;
+    left -= c;
+  }
+  d->t += nsteps;
+  if (nsteps > 0) return domain_mass_enqueue(d);
+  return LB_OK;
+}
+
+lb_status lb_moments_device(lb_domain *d, double *rho, double *ux, double *uy) {
+  if (!d || !rho || !ux || !uy) return fail(LB_EINVAL, "null argument");
+  d->ks.moments(d->ddesc(), rho, ux, uy, 0, d->desc.ny, d->desc.nx, d->stream);
+  HIPCHK(hipGetLastError());
+  return LB_OK;
+}
+
+lb_status lb_moments(lb_domain *d, double *rho, double *ux, double *uy) {
+  if (!d || !rho || !ux || !uy) return fail(LB_EINVAL, "null argument");
+  const int nx = d->desc.nx;
+  double *st = (double *)(d->ws + d->L.stage);
+  for (int r0 = 0; r0 < d->desc.ny; r0 += d->L.band_rows) {
+    const int nr = std::min(d->L.band_rows, d->desc.ny - r0);
+    const size_t cnt = (size_t)nr * nx;
+    d->ks.moments(d->ddesc(), st, st + cnt, st + 2 * cnt, r0, nr, nx, d->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(rho + (size_t)r0 * nx, st, cnt * 8, hipMemcpyDeviceToHost, d->stream));
+    HIPCHK(hipMemcpyAsync(ux + (size_t)r0 * nx, st + cnt, cnt * 8, hipMemcpyDeviceToHost, d->stream));
+    HIPCHK(hipMemcpyAsync(uy + (size_t)r0 * nx, st + 2 * cnt, cnt * 8, hipMemcpyDeviceToHost, d->stream));
+    HIPCHK(hipStreamSynchronize(d->stream));
+  }
+  return check_health(d);
+}
+
+lb_status lb_get_particles(lb_domain *d, lb_particle *out, int32_t n) {
+  if (!d || (!out && n > 0)) return fail(LB_EINVAL, "null argument");
+  if (n < 0 || n > d->np) return fail(LB_EINVAL, "n exceeds the particle count");
+  std::vector<PState> cur(std::max(n, 1));
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(cur.data(), d->hd.pstate[d->t & 1], n * sizeof(PState),
+                          hipMemcpyDeviceToHost, d->stream));
+  }
+  HIPCHK(hipStreamSynchronize(d->stream));
+  for (int k = 0; k < n; ++k) {
+    const PState &s = cur[k];
+    lb_particle &q = out[k];
+    q.x = s.x; q.y = s.y; q.radius = s.radius; q.density_ratio = s.rho_ratio;
+    q.ux = s.ux; q.uy = s.uy; q.omega = s.omega;
+    q.fx = s.fx; q.fy = s.fy; q.torque = s.torque;
+    q.flags = s.flags; q.reserved = 0;
+  }
+  return check_health(d);
+}
+
+lb_status lb_mass(lb_domain *d, double *total) {
+  if (!d || !total) return fail(LB_EINVAL, "null argument");
+  lb_status s = domain_mass_enqueue(d);
+  if (s != LB_OK) return s;
+  HIPCHK(hipMemcpyAsync(total, &d->dhdr()->mass, sizeof(double), hipMemcpyDeviceToHost, d->stream));
+  HIPCHK(hipStreamSynchronize(d->stream));
+  return check_health(d);
+}
+
+lb_status lb_time(lb_domain *d, int64_t *t) {
+  if (!d || !t) return fail(LB_EINVAL, "null argument");
+  *t = d->t;
+  return LB_OK;
+}
+
+lb_status lb_get_populations(lb_domain *d, double *hf) {
+  if (!d || !hf) return fail(LB_EINVAL, "null argument");
+  const int nx = d->desc.nx, ny = d->desc.ny;
+  double *st = (double *)(d->ws + d->L.stage);
+  for (int r0 = 0; r0 < ny; r0 += d->L.band_rows) {
+    const int nr = std::min(d->L.band_rows, ny - r0);
+    const size_t cnt = (size_t)nr * nx;
+    d->ks.export_f(d->ddesc(), st, r0, nr, nx, d->stream);
+    HIPCHK(hipGetLastError());
+    for (int i = 0; i < 9; ++i)
+      HIPCHK(hipMemcpyAsync(hf + ((size_t)i * ny + r0) * nx, st + i * cnt, cnt * 8,
+                            hipMemcpyDeviceToHost, d->stream));
+    HIPCHK(hipStreamSynchronize(d->stream));
+  }
+  return check_health(d);
+}
+
+lb_status lb_set_populations(lb_domain *d, const double *hf) {
+  if (!d || !hf) return fail(LB_EINVAL, "null argument");
+  const int nx = d->desc.nx, ny = d->desc.ny;
+  double *st = (double *)(d->ws + d->L.stage);
+  for (int r0 = 0; r0 < ny; r0 += d->L.band_rows) {
+    const int nr = std::min(d->L.band_rows, ny - r0);
+    const size_t cnt = (size_t)nr * nx;
+    for (int i = 0; i < 9; ++i)
+      HIPCHK(hipMemcpyAsync(st + i * cnt, hf + ((size_t)i * ny + r0) * nx, cnt * 8,
+                            hipMemcpyHostToDevice, d->stream));
+    d->ks.import_f(d->ddesc(), st, r0, nr, nx, d->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(d->stream));
+  }
+  return LB_OK;
+}
+
+lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
+  if (!d) return fail(LB_EINVAL, "null domain");
+  if (d->in_batches && (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD))
+    return fail(LB_ESTATE, "tile options are fixed while the domain is in a batch");
+  switch (key) {
+    case LB_OPT_USE_GRAPH: d->use_graph = value != 0; break;
+    case LB_OPT_TILE_WIDTH:
+      if (value != 64 && value != 128 && value != 256) return fail(LB_EINVAL, "tile width must be 64, 128 or 256");
+      set_tiles(d->hd, (int)value, d->hd.rows_per_thread);
+      break;
+    case LB_OPT_ROWS_PER_THREAD:
+      if (value < 1 || value > 16) return fail(LB_EINVAL, "rows per thread must be in [1, 16]");
+      set_tiles(d->hd, d->hd.tile_w, (int)value);
+      break;
+    case LB_OPT_GRAPH_CHUNK:
+      if (value < 1 || value > 4096) return fail(LB_EINVAL, "graph chunk must be in [1, 4096]");
+      d->chunk = (int)value;
+      break;
+    default: return fail(LB_EINVAL, "unknown option");
+  }
+  d->graphs.clear();
+  if (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD) return push_desc(d);
+  return LB_OK;
+}
+
+lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value) {
+  if (!d || !value) return fail(LB_EINVAL, "null argument");
+  switch (key) {
+    case LB_OPT_USE_GRAPH: *value = d->use_graph; return LB_OK;
+    case LB_OPT_TILE_WIDTH: *value = d->hd.tile_w; return LB_OK;
+    case LB_OPT_ROWS_PER_THREAD: *value = d->hd.rows_per_thread; return LB_OK;
+    case LB_OPT_GRAPH_CHUNK: *value = d->chunk; return LB_OK;
+  }
+  return fail(LB_EINVAL, "unknown option");
+}
+
+lb_status lb_autotune(lb_domain *d, int32_t steps, double *best_ms) {
+  if (!d || steps < 1) return fail(LB_EINVAL, "bad argument");
+  if (d->in_batches) return fail(LB_ESTATE, "domain is in a batch");
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int widths[3] = {64, 128, 256};
+  const int rows[4] = {1, 2, 4, 8};
+  double best = 1e300;
+  int bw = d->hd.tile_w, br = d->hd.rows_per_thread;
+  const int saved_chunk = d->chunk;
+  d->chunk = std::max(1, std::min(steps, 4096));
+  lb_status s = LB_OK;
+  for (int w : widths) {
+    if (w > 64 && w / 2 >= d->desc.nx) continue;
+    for (int r : rows) {
+      if ((s = lb_set_option(d, LB_OPT_TILE_WIDTH, w)) != LB_OK) break;
+      if ((s = lb_set_option(d, LB_OPT_ROWS_PER_THREAD, r)) != LB_OK) break;
+      if ((s = lb_step(d, steps)) != LB_OK) break;  // warm-up (and graph capture)
+      if (hipEventRecord(e0, d->stream) != hipSuccess) { s = fail(LB_EHIP, "event"); break; }
+      if ((s = lb_step(d, steps)) != LB_OK) break;
+      if (hipEventRecord(e1, d->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        s = fail(LB_EHIP, "event");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms / steps < best) { best = ms / steps; bw = w; br = r; }
+    }
+    if (s != LB_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  d->chunk = saved_chunk;
+  if (s != LB_OK) return s;
+  if ((s = lb_set_option(d, LB_OPT_TILE_WIDTH, bw)) != LB_OK) return s;
+  if ((s = lb_set_option(d, LB_OPT_ROWS_PER_THREAD, br)) != LB_OK) return s;
+  if (best_ms) *best_ms = best;
+  return check_health(d);
+}
+
+lb_status lb_destroy_domain(lb_domain *d) {
+  if (!d) return fail(LB_EINVAL, "null domain");
+  if (d->in_batches) return fail(LB_ESTATE, "destroy the batches that hold this domain first");
+  (void)hipStreamSynchronize(d->stream);
+  d->graphs.clear();
+  (void)hipStreamDestroy(d->cap);
+  delete d;
+  return LB_OK;
+}
+
+lb_status lb_batch_workspace_bytes(lb_domain *const *domains, int32_t n, size_t *bytes) {
+  if (!domains || n < 1 || !bytes) return fail(LB_EINVAL, "bad argument");
+  size_t items = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!domains[i]) return fail(LB_EINVAL, "null domain");
+    items += domains[i]->np;
+  }
+  *bytes = align256((size_t)n * sizeof(DevDomain)) + align256((size_t)(n + 1) * sizeof(int)) +
+           align256(std::max<size_t>(items, 1) * sizeof(PItem));
+  return LB_OK;
+}
+
+lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_workspace, size_t bytes,
+                          void *hip_stream, lb_batch **out) {
+  if (!out) return fail(LB_EINVAL, "out is null");
+  *out = nullptr;
+  size_t need = 0;
+  lb_status s = lb_batch_workspace_bytes(domains, n, &need);
+  if (s != LB_OK) return s;
+  if (!dev_workspace || ((uintptr_t)dev_workspace & 255)) return fail(LB_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < need) return fail(LB_ENOMEM, "batch workspace too small");
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < i; ++j)
+      if (domains[i] == domains[j]) return fail(LB_EINVAL, "a domain appears twice");
+    if (domains[i]->desc.storage != domains[0]->desc.storage ||
+        (domains[i]->feat & (F_LABELS | F_NOISE | F_POWER)) != (domains[0]->feat & (F_LABELS | F_NOISE | F_POWER)) ||
+        domains[i]->plm != domains[0]->plm)
+      return fail(LB_EUNSUPPORTED, "batched domains must share storage and features");
+  }
+  lb_batch *b = new lb_batch();
+  b->doms.assign(domains, domains + n);
+  b->ws = (char *)dev_workspace;
+  b->stream = (hipStream_t)hip_stream;
+  b->ks = domains[0]->ks;
+  b->off_desc = 0;
+  b->off_prefix = align256((size_t)n * sizeof(DevDomain));
+  b->off_items = b->off_prefix + align256((size_t)(n + 1) * sizeof(int));
+  b->bytes = need;
+  std::vector<DevDomain> descs(n);
+  std::vector<int> prefix(n + 1, 0);
+  std::vector<PItem> items;
+  for (int i = 0; i < n; ++i) {
+    descs[i] = domains[i]->hd;
+    prefix[i + 1] = prefix[i] + domains[i]->ntiles();
+    for (int q = 0; q < domains[i]->np; ++q) items.push_back(PItem{i, q});
+  }
+  b->total_tiles = prefix[n];
+  b->nitems = (int)items.size();
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return fail(LB_EHIP, "hipStreamCreateWithFlags failed");
+  }
+  bool ok = hipMemcpyAsync(b->ddesc(), descs.data(), n * sizeof(DevDomain), hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+            hipMemcpyAsync(b->dprefix(), prefix.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+            (items.empty() || hipMemcpyAsync(b->ditems(), items.data(), items.size() * sizeof(PItem), hipMemcpyHostToDevice, b->stream) == hipSuccess) &&
+            hipStreamSynchronize(b->stream) == hipSuccess;
+  if (!ok) {
+    (void)hipStreamDestroy(b->cap);
+    delete b;
+    return fail(LB_EHIP, "batch upload failed");
+  }
+  for (auto *d : b->doms) {
+    (void)hipStreamSynchronize(d->stream);
+    d->in_batches += 1;
+  }
+  *out = b;
+  return LB_OK;
+}
+
+lb_status lb_batch_step(lb_batch *b, int64_t nsteps) {
+  if (!b) return fail(LB_EINVAL, "null batch");
+  if (nsteps < 0) return fail(LB_EINVAL, "nsteps < 0");
+  int64_t left = nsteps;
+  while (left > 0) {
+    const int c = (int)std::min<int64_t>(left, b->chunk);
+    lb_status s = run_chunk(b->graphs, b->use_graph, b->stream, b->cap, b->ks, b->ddesc(),
+                            b->dprefix(), (int)b->doms.size(), b->total_tiles, b->ditems(),
+                            b->nitems, c);
+    if (s != LB_OK) return s;
+    left -= c;
+  }
+  for (auto *d : b->doms) d->t += nsteps;
+  return LB_OK;
+}
+
+lb_status lb_batch_set_option(lb_batch *b, int32_t key, int64_t value) {
+  if (!b) return fail(LB_EINVAL, "null batch");
+  switch (key) {
+    case LB_OPT_USE_GRAPH: b->use_graph = value != 0; break;
+    case LB_OPT_GRAPH_CHUNK:
+      if (value < 1 || value > 4096) return fail(LB_EINVAL, "graph chunk must be in [1, 4096]");
+      b->chunk = (int)value;
+      break;
+    default: return fail(LB_EINVAL, "option not available on a batch");
+  }
+  b->graphs.clear();
+  return LB_OK;
+}
+
+lb_status lb_batch_destroy(lb_batch *b) {
+  if (!b) return fail(LB_EINVAL, "null batch");
+  (void)hipStreamSynchronize(b->stream);
+  b->graphs.clear();
+  (void)hipStreamDestroy(b->cap);
+  for (auto *d : b->doms) d->in_batches -= 1;
+  delete b;
+  return LB_OK;
+}
+
+lb_status lb_noise_normals(uint64_t seed, uint32_t domain_id, uint32_t step, uint32_t node0,
+                           uint32_t count, float *dev_out, void *hip_stream) {
+  if (!dev_out && count > 0) return fail(LB_EINVAL, "null output");
+  if (count == 0) return LB_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  launch_normals((uint32_t)seed, (uint32_t)(seed >> 32) ^ domain_id, step, node0, count, dev_out, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return LB_OK;
+}
+
+}  // extern "C"

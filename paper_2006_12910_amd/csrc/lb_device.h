@@ -1,0 +1,331 @@
+// lb_device.h -- internal definitions shared by the library's HIP sources:
+// the D2Q9 lattice, the per-domain device descriptor, storage formats and the
+// thermal-noise generator.  gfx950 (CDNA4, wave64) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbk {
+
+// ---------------------------------------------------------------------------
+// D2Q9 (Sec. 2): direction i has velocity (CX[i], CY[i]); rest, the four axis
+// directions at angles (i-1) pi/2, the four diagonals at (2i-9) pi/4.
+constexpr int Q = 9;
+__host__ __device__ constexpr int cx(int i) {
+  return (i == 1 || i == 5 || i == 8) ? 1 : (i == 3 || i == 6 || i == 7) ? -1 : 0;
+}
+__host__ __device__ constexpr int cy(int i) {
+  return (i == 2 || i == 5 || i == 6) ? 1 : (i == 4 || i == 7 || i == 8) ? -1 : 0;
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5); }
+// lattice weights 4/9, 1/9, 1/36
+template <class R> __host__ __device__ constexpr R wgt(int i) {
+  return i == 0 ? R(4) / R(9) : (i <= 4 ? R(1) / R(9) : R(1) / R(36));
+}
+// power-of-two scale of the 16-bit deviation formats: w_i * scale_i = 8/9
+__host__ __device__ constexpr float dscale(int i) { return i == 0 ? 2.0f : (i <= 4 ? 8.0f : 32.0f); }
+
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "axis opposites");
+static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "diagonal opposites");
+
+// Table t1 basis polynomials of the lattice vector, for k = 3..8 (the modes
+// that carry noise): 3e^2-2, 2ex^2-e^2, ex ey, (3e^2-4)ex, (3e^2-4)ey,
+// 9e^4-15e^2+2; their lengths are 4, 4/9, 1/9, 2/3, 2/3, 16.
+__host__ __device__ constexpr int basis_poly(int k, int i) {
+  return k == 3 ? 3 * (cx(i) * cx(i) + cy(i) * cy(i)) - 2
+       : k == 4 ? 2 * cx(i) * cx(i) - (cx(i) * cx(i) + cy(i) * cy(i))
+       : k == 5 ? cx(i) * cy(i)
+       : k == 6 ? (3 * (cx(i) * cx(i) + cy(i) * cy(i)) - 4) * cx(i)
+       : k == 7 ? (3 * (cx(i) * cx(i) + cy(i) * cy(i)) - 4) * cy(i)
+       : 9 * (cx(i) * cx(i) + cy(i) * cy(i)) * (cx(i) * cx(i) + cy(i) * cy(i)) -
+             15 * (cx(i) * cx(i) + cy(i) * cy(i)) + 2;
+}
+
+// ---------------------------------------------------------------------------
+enum : int { BC_PERIODIC = 0, BC_WALL = 1, BC_PRESSURE = 2 };
+enum : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+
+// Feature bits of a sweep instantiation.
+enum : int {
+  F_LABELS = 1,    // label plane (obstacles and/or particles)
+  F_NOISE = 2,     // thermal noise
+  F_POWER = 4,     // power-law tau*
+  F_PRESSURE = 8,  // Zou-He faces on x
+  F_STOCH = 16,    // stochastic rounding of 16-bit storage
+};
+// Power-law exponent specialisations.
+enum : int { PL_GENERIC = 0, PL_HALF = 1, PL_3Q = 2, PL_3H = 3 };
+
+// Labels: 0 fluid, 1 solid, 2 + p inside particle p.
+constexpr uint8_t LBL_FLUID = 0, LBL_SOLID = 1, LBL_PART0 = 2;
+
+// Particle state, FP64 (double-buffered by step parity).
+struct PState {
+  double x, y, ux, uy, omega;
+  double radius, mass, inertia, rho_ratio;
+  double fx, fy, torque;  // total force/torque used in the last update
+  int32_t flags, pad;
+  double pad2[3];
+};
+static_assert(sizeof(PState) == 128, "PState layout");
+
+// Per-particle force accumulators produced each step.
+struct PForce {
+  double fx, fy, torque;  // exterior link momentum exchange (Eq. MP1)
+  double ljx, ljy;        // repulsion from solid nodes (Eq. MP2)
+  double cx_, cy_, ctorque;  // covered/uncovered nodes (Eq. MP3), for the next step
+};
+
+// Device-side descriptor of one domain (lives in the domain's workspace).
+struct alignas(256) DevDomain {
+  void *f[2];          // population buffers (deviations), [9][ny][pitch]
+  uint8_t *label;      // [ny][pitch] or null
+  uint64_t *tstep;     // completed steps
+  uint32_t *health;    // latched error bits
+  PState *pstate[2];
+  PForce *pforce;
+  int nx, ny, pitch;   // pitch in elements, a multiple of 64
+  int bc_x, bc_y;
+  int np;              // particles
+  int tile_w, rows_per_thread, tiles_x, tiles_y;
+  uint32_t key0, key1; // noise generator key
+  int storage, feat;
+  // FP64 parameters
+  double rho0, tau, omega, gx, gy, rho_in, rho_out, kT;
+  double pl_n, pl_K, tau_min, tau_max;
+  double lj_psi, lj_rit, lj_floor;
+  // FP32 copies
+  float rho0_f, tau_f, omega_f, gx_f, gy_f, rho_in_f, rho_out_f, kT_f;
+  float pl_n_f, pl_K_f, tau_min_f, tau_max_f;
+};
+
+// One particle of a batch: owning domain (index into the descriptor array) and
+// particle index within it.
+struct PItem {
+  int dom, p;
+};
+
+constexpr uint32_t HEALTH_NONFINITE = 1u, HEALTH_FAST_PARTICLE = 2u, HEALTH_LINK_OVERFLOW = 4u;
+
+// ---------------------------------------------------------------------------
+// Storage formats.  Value held = (f_i - w_i rho0) * scale.
+template <int ST> struct Store;
+template <> struct Store<ST_F64> {
+  using T = double;
+  using R = double;
+  static __device__ __forceinline__ R load(const T *p, size_t o, int) { return p[o]; }
+  static __device__ __forceinline__ void put(T *p, size_t o, int, R v, uint32_t) { p[o] = v; }
+};
+template <> struct Store<ST_F32> {
+  using T = float;
+  using R = float;
+  static __device__ __forceinline__ R load(const T *p, size_t o, int) { return p[o]; }
+  static __device__ __forceinline__ void put(T *p, size_t o, int, R v, uint32_t) { p[o] = v; }
+};
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rn(float v) {
+  uint32_t b = __float_as_uint(v);
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Stochastic rounding to bf16: add 16 random bits below the kept mantissa
+// and truncate (magnitude arithmetic on the sign-magnitude encoding).
+__device__ __forceinline__ uint16_t f32_to_bf16_sr(float v, uint32_t r) {
+  uint32_t b = __float_as_uint(v);
+  b += (r & 0xffffu);
+  return (uint16_t)(b >> 16);
+}
+
+__device__ __forceinline__ uint16_t f32_to_f16_rn(float v) {
+  _Float16 h = (_Float16)v;
+  return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float f16_to_f32(uint16_t h) {
+  return (float)__builtin_bit_cast(_Float16, h);
+}
+// Stochastic rounding to fp16: the two neighbours of v in fp16 are found from
+// the round-to-nearest result, and the upper one is taken with probability
+// equal to v's fractional position between them (exact for subnormals too).
+__device__ __forceinline__ uint16_t f32_to_f16_sr(float v, uint32_t r) {
+  uint16_t h = f32_to_f16_rn(v);
+  float hv = f16_to_f32(h);
+  float av = fabsf(v), ah = fabsf(hv);
+  uint16_t lo = h, hi = h;
+  if (ah > av) lo = (uint16_t)(h - 1); else hi = (uint16_t)(h + 1);
+  if (av == ah) return h;
+  float l = fabsf(f16_to_f32(lo)), u = fabsf(f16_to_f32(hi));
+  float frac = (av - l) / (u - l);
+  float rnd = (float)(r >> 8) * (1.0f / 16777216.0f);
+  return rnd < frac ? hi : lo;
+}
+
+template <> struct Store<ST_F16> {
+  using T = uint16_t;
+  using R = float;
+  static __device__ __forceinline__ R load(const T *p, size_t o, int i) {
+    return f16_to_f32(p[o]) * (1.0f / dscale(i));
+  }
+  static __device__ __forceinline__ void put(T *p, size_t o, int i, R v, uint32_t rbits) {
+    p[o] = rbits ? f32_to_f16_sr(v * dscale(i), rbits) : f32_to_f16_rn(v * dscale(i));
+  }
+};
+template <> struct Store<ST_BF16> {
+  using T = uint16_t;
+  using R = float;
+  static __device__ __forceinline__ R load(const T *p, size_t o, int i) {
+    return bf16_to_f32(p[o]) * (1.0f / dscale(i));
+  }
+  static __device__ __forceinline__ void put(T *p, size_t o, int i, R v, uint32_t rbits) {
+    p[o] = rbits ? f32_to_bf16_sr(v * dscale(i), rbits) : f32_to_bf16_rn(v * dscale(i));
+  }
+};
+
+// 32-bit integer hash (Wellons' "lowbias32" mixer) for stochastic-rounding bits.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// Thermal noise: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) with
+// counter (node, step, 0, 0) and key (lo32(seed), hi32(seed) ^ domain_id).
+// The 128 output bits give six 21-bit integers -- the top 21 bits of w0..w3
+// and (w0 & 0x7ff) << 10 | (w2 & 0x3ff), (w1 & 0x7ff) << 10 | (w3 & 0x3ff) --
+// turned into uniforms (2k+1) 2^-22 and paired (w0,w1), (w2,w3), (low words)
+// into three Box-Muller transforms (radius, angle) giving Theta_3..Theta_8.
+// Every floating-point operation below is a single correctly rounded IEEE
+// float operation in a fixed order (no contraction), so the host's
+// independent implementation of the same definition reproduces it bit-exactly.
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// ln u for u in (0,1]: u = m 2^e, m folded into [sqrt(1/2), sqrt(2)];
+// ln m = 2 atanh(s), s = (m-1)/(m+1), power series through s^11; ln 2 in two
+// parts (Cody-Waite) so that e * hi is exact.
+__device__ __forceinline__ float noise_log(float u) {
+#pragma clang fp contract(off)
+  uint32_t b = __float_as_uint(u);
+  int e = (int)((b >> 23) & 0xffu) - 127;
+  float m = __uint_as_float((b & 0x007fffffu) | 0x3f800000u);
+  if (m > 1.41421354f) {
+    m = m * 0.5f;
+    e = e + 1;
+  }
+  const float s = (m - 1.0f) / (m + 1.0f);
+  const float s2 = s * s;
+  float p = 1.0f / 11.0f;
+  p = p * s2 + 1.0f / 9.0f;
+  p = p * s2 + 1.0f / 7.0f;
+  p = p * s2 + 1.0f / 5.0f;
+  p = p * s2 + 1.0f / 3.0f;
+  p = p * s2 + 1.0f;
+  const float lnm = (s + s) * p;
+  const float fe = (float)e;
+  return fe * 0.693145751953125f + (fe * 1.42860682030941723e-6f + lnm);
+}
+
+// sin and cos of 2 pi u, u a multiple of 2^-22 in (0,1): exact reduction to a
+// quadrant and r in [-1/8, 1/8]; Taylor series at a = 2 pi r through a^9 (sin)
+// and a^10 (cos).
+__device__ __forceinline__ void noise_sincos2pi(float u, float &sn, float &cs) {
+#pragma clang fp contract(off)
+  int q = (int)(u * 4.0f);
+  float r = u - 0.25f * (float)q;
+  if (r > 0.125f) {
+    r = r - 0.25f;
+    q = q + 1;
+  }
+  const float a = r * 6.28318530717958647692f;
+  const float a2 = a * a;
+  float ps = 1.0f / 362880.0f;
+  ps = ps * a2 + (-1.0f / 5040.0f);
+  ps = ps * a2 + 1.0f / 120.0f;
+  ps = ps * a2 + (-1.0f / 6.0f);
+  const float sa = a + (a * a2) * ps;
+  float pc = -1.0f / 3628800.0f;
+  pc = pc * a2 + 1.0f / 40320.0f;
+  pc = pc * a2 + (-1.0f / 720.0f);
+  pc = pc * a2 + 1.0f / 24.0f;
+  pc = pc * a2 + (-0.5f);
+  const float ca = 1.0f + a2 * pc;
+  switch (q & 3) {
+    case 0: sn = sa; cs = ca; break;
+    case 1: sn = ca; cs = -sa; break;
+    case 2: sn = -sa; cs = -ca; break;
+    default: sn = -ca; cs = sa; break;
+  }
+}
+
+__device__ __forceinline__ void noise_pair(uint32_t kr, uint32_t ka, float &z0, float &z1) {
+#pragma clang fp contract(off)
+  const float ur = (float)(2u * kr + 1u) * (1.0f / 4194304.0f);
+  const float ua = (float)(2u * ka + 1u) * (1.0f / 4194304.0f);
+  const float rad = sqrtf(-2.0f * noise_log(ur));
+  float sn, cs;
+  noise_sincos2pi(ua, sn, cs);
+  z0 = rad * cs;
+  z1 = rad * sn;
+}
+
+// Theta_3..Theta_8 of one node and step.
+__device__ __forceinline__ void noise_normals(uint32_t k0, uint32_t k1, uint32_t node,
+                                              uint32_t step, float th[6]) {
+  uint32_t w[4];
+  philox4x32_10(node, step, 0u, 0u, k0, k1, w);
+  const uint32_t b0 = ((w[0] & 0x7ffu) << 10) | (w[2] & 0x3ffu);
+  const uint32_t b1 = ((w[1] & 0x7ffu) << 10) | (w[3] & 0x3ffu);
+  noise_pair(w[0] >> 11, w[1] >> 11, th[0], th[1]);
+  noise_pair(w[2] >> 11, w[3] >> 11, th[2], th[3]);
+  noise_pair(b0, b1, th[4], th[5]);
+}
+
+// ---------------------------------------------------------------------------
+// XCD-aware block order: consecutive hardware block ids are dealt round-robin
+// to the 8 XCDs; remap so that each XCD walks a contiguous run of tiles and
+// the halo rows it pulls stay in its own L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  constexpr int NX = 8;
+  if (nblocks < 2 * NX) return bid;
+  const int xcd = bid % NX, local = bid / NX;
+  const int per = nblocks / NX, rem = nblocks % NX;
+  return xcd * per + min(xcd, rem) + local;
+}
+
+// Which domain of a batch owns block b: largest d with prefix[d] <= b.
+__device__ __forceinline__ int find_domain(const int *__restrict__ prefix, int ndom, int b) {
+  int lo = 0, hi = ndom - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ double min_image(double d, double len, bool periodic) {
+  return periodic ? d - len * floor(d / len + 0.5) : d;
+}
+
+}  // namespace lbk

@@ -1,0 +1,328 @@
+// particles_impl.h -- particle coupling kernels (Sec. 3).
+//
+// Per step, for the state at time T (post-collision populations f*(T), labels
+// G(T), particle state P(T)):
+//   k_link        one workgroup per particle: enumerate the exterior pulls
+//                 crossing its surface inside its bounding box, compact them
+//                 into an LDS list (deterministic block scan), and reduce the
+//                 momentum exchange of Eq. MP1 and its torque (Eq. MP4) in
+//                 FP64; the same scan sums the repulsion from solid nodes
+//                 (Eq. MP2).
+//   k_pupdate     one lane per particle: particle-particle repulsion and the
+//                 Newton-Euler update of Eqs. MP5-MP6 into P(T+1).
+//   k_cover       after the sweep: covered/uncovered-node force (Eq. MP3) of
+//                 the nodes whose label changes from G(T) to G(T+1).
+//   k_relabel     write G(T+1).
+// All reductions run in a fixed order, so results are bit-reproducible.
+#pragma once
+
+#include "lb_device.h"
+
+namespace lbk {
+
+constexpr int LINK_CAP = 6144;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of NV values over the 256 threads of a block, fixed order; result valid
+// in every thread.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*scratch)[NV]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) scratch[w][k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = (scratch[0][k] + scratch[1][k]) + (scratch[2][k] + scratch[3][k]);
+  __syncthreads();
+}
+
+// Exclusive prefix sum of one int per thread over the block (fixed order).
+__device__ __forceinline__ int block_exscan(int v, int *sh, int &total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) sh[w] = incl;
+  __syncthreads();
+  int base = 0;
+  for (int k = 0; k < w; ++k) base += sh[k];
+  total = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return base + incl - v;
+}
+
+// Map a box coordinate into the domain: any integer on a periodic axis (so a
+// corrupted particle position can never index outside the planes), rejected
+// outside a non-periodic axis.
+__device__ __forceinline__ bool wrap_coord(int &v, int n, bool periodic) {
+  if (v < 0 || v >= n) {
+    if (!periodic) return false;
+    v %= n;
+    if (v < 0) v += n;
+  }
+  return true;
+}
+
+__device__ __forceinline__ double lj_mag(const DevDomain &D, double gap) {
+  const double g = gap < D.lj_floor ? D.lj_floor : gap;
+  return D.lj_psi * pow(g / D.lj_rit, -13.0);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_link(const DevDomain *__restrict__ doms,
+                                              const PItem *__restrict__ items, int kstep) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  __shared__ uint32_t links[LINK_CAP];
+  __shared__ int scan_sh[4];
+  __shared__ double red[4][5];
+  const PItem it = items[blockIdx.x];
+  const DevDomain &D = doms[it.dom];
+  const uint64_t T0 = *D.tstep + (uint64_t)kstep;
+  const PState P = D.pstate[T0 & 1][it.p];
+  const T *src = (const T *)D.f[T0 & 1];
+  const size_t plane = (size_t)D.ny * D.pitch;
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  const uint8_t mine = (uint8_t)(LBL_PART0 + it.p);
+  const int reach = max((int)ceil(P.radius) + 2, (int)ceil(P.radius + D.lj_rit) + 1);
+  const int W = 2 * reach + 2;
+  const int bx0 = (int)floor(P.x) - reach, by0 = (int)floor(P.y) - reach;
+  const int nbox = W * W;
+  const int chunk = (nbox + 255) / 256;
+  const double lim = P.radius + D.lj_rit;
+
+  // pass 1: count crossing exterior pulls of this thread's contiguous nodes,
+  // and sum the repulsion from solid nodes
+  int cnt = 0;
+  double ljx = 0.0, ljy = 0.0;
+  for (int j = threadIdx.x * chunk; j < min(nbox, (threadIdx.x + 1) * chunk); ++j) {
+    int x = bx0 + j % W, y = by0 + j / W;
+    if (!wrap_coord(x, D.nx, perx) || !wrap_coord(y, D.ny, pery)) continue;
+    const uint8_t lx = D.label[(size_t)y * D.pitch + x];
+    if (lx == LBL_SOLID) {
+      const double dx = min_image(P.x - x, D.nx, perx), dy = min_image(P.y - y, D.ny, pery);
+      const double dist = sqrt(dx * dx + dy * dy);
+      if (dist <= lim && dist > 0.0) {
+        const double m = lj_mag(D, dist - P.radius);
+        ljx += m * dx / dist;
+        ljy += m * dy / dist;
+      }
+      continue;
+    }
+    if (lx != LBL_FLUID) continue;
+    for (int i = 1; i < 9; ++i) {
+      int sx = x - cx(i), sy = y - cy(i);
+      if (!wrap_coord(sx, D.nx, perx) || !wrap_coord(sy, D.ny, pery)) continue;
+      if (D.label[(size_t)sy * D.pitch + sx] == mine) ++cnt;
+    }
+  }
+  int total;
+  int pos = block_exscan(cnt, scan_sh, total);
+  // pass 2: write this thread's links in node order into the LDS list
+  for (int j = threadIdx.x * chunk; j < min(nbox, (threadIdx.x + 1) * chunk); ++j) {
+    if (!cnt) break;
+    int x = bx0 + j % W, y = by0 + j / W;
+    if (!wrap_coord(x, D.nx, perx) || !wrap_coord(y, D.ny, pery)) continue;
+    if (D.label[(size_t)y * D.pitch + x] != LBL_FLUID) continue;
+    for (int i = 1; i < 9; ++i) {
+      int sx = x - cx(i), sy = y - cy(i);
+      if (!wrap_coord(sx, D.nx, perx) || !wrap_coord(sy, D.ny, pery)) continue;
+      if (D.label[(size_t)sy * D.pitch + sx] == mine) {
+        if (pos < LINK_CAP) links[pos] = ((uint32_t)j << 4) | (uint32_t)i;
+        ++pos;
+      }
+    }
+  }
+  __syncthreads();
+  if (total > LINK_CAP && threadIdx.x == 0) atomicOr(D.health, HEALTH_LINK_OVERFLOW);
+  const int nl = min(total, LINK_CAP);
+  // pass 3: momentum exchange of each link, FP64
+  double acc[5] = {0.0, 0.0, 0.0, ljx, ljy};
+  for (int e = threadIdx.x; e < nl; e += 256) {
+    const uint32_t rec = links[e];
+    const int j = (int)(rec >> 4), dir = (int)(rec & 15u);
+    int x = bx0 + j % W, y = by0 + j / W;
+    wrap_coord(x, D.nx, perx);
+    wrap_coord(y, D.ny, pery);
+    const int o = opp(dir);
+    const double fopp = wgt<double>(o) * D.rho0 +
+                        (double)S::load(src + o * plane, (uint32_t)y * D.pitch + x, o);
+    const double bxr = x - 0.5 * cx(dir), byr = y - 0.5 * cy(dir);
+    const double rx = min_image(bxr - P.x, D.nx, perx), ry = min_image(byr - P.y, D.ny, pery);
+    const double vx = P.ux - P.omega * ry, vy = P.uy + P.omega * rx;
+    const double ue = vx * cx(dir) + vy * cy(dir);
+    const double mag = 2.0 * fopp + 6.0 * D.rho0 * wgt<double>(dir) * ue;
+    const double dpx = -cx(dir) * mag, dpy = -cy(dir) * mag;
+    acc[0] += dpx;
+    acc[1] += dpy;
+    acc[2] += rx * dpy - ry * dpx;
+  }
+  block_sum<5>(acc, red);
+  if (threadIdx.x == 0) {
+    PForce &F = D.pforce[it.p];
+    F.fx = acc[0];
+    F.fy = acc[1];
+    F.torque = acc[2];
+    F.ljx = acc[3];
+    F.ljy = acc[4];
+  }
+}
+
+#ifdef LBK_COMMON_KERNELS
+__global__ void k_pupdate(const DevDomain *__restrict__ doms, const PItem *__restrict__ items,
+                          int nitems, int kstep) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nitems) return;
+  const PItem it = items[i];
+  const DevDomain &D = doms[it.dom];
+  const uint64_t T0 = *D.tstep + (uint64_t)kstep;
+  const PState *cur = D.pstate[T0 & 1];
+  PState *nxt = D.pstate[(T0 + 1) & 1];
+  const PState P = cur[it.p];
+  const PForce F = D.pforce[it.p];
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  double lx = 0.0, ly = 0.0;
+  if (D.lj_psi > 0.0) {
+    for (int q = 0; q < D.np; ++q) {
+      if (q == it.p) continue;
+      const PState &Q = cur[q];
+      const double dx = min_image(P.x - Q.x, D.nx, perx), dy = min_image(P.y - Q.y, D.ny, pery);
+      const double dist = sqrt(dx * dx + dy * dy);
+      const double gap = dist - P.radius - Q.radius;
+      if (gap > D.lj_rit || !(dist > 0.0)) continue;
+      const double m = lj_mag(D, gap);
+      lx += m * dx / dist;
+      ly += m * dy / dist;
+    }
+  }
+  const double fx = F.fx + F.cx_ + (lx + F.ljx);
+  const double fy = F.fy + F.cy_ + (ly + F.ljy);
+  const double tq = F.torque + F.ctorque;
+  PState N = P;
+  N.fx = fx;
+  N.fy = fy;
+  N.torque = tq;
+  if (!(P.flags & 1)) {
+    const double buoy = 1.0 - D.rho0 / (P.rho_ratio * D.rho0);
+    N.ux = P.ux + fx / P.mass + buoy * D.gx;
+    N.uy = P.uy + fy / P.mass + buoy * D.gy;
+    N.omega = P.omega + tq / P.inertia;
+    N.x = P.x + P.ux;
+    N.y = P.y + P.uy;
+    if (perx) { if (N.x >= D.nx) N.x -= D.nx; if (N.x < 0.0) N.x += D.nx; }
+    if (pery) { if (N.y >= D.ny) N.y -= D.ny; if (N.y < 0.0) N.y += D.ny; }
+    if (!(fabs(N.ux) < 0.5 && fabs(N.uy) < 0.5)) atomicOr(D.health, HEALTH_FAST_PARTICLE);
+  }
+  nxt[it.p] = N;
+}
+#endif  // LBK_COMMON_KERNELS
+
+// Label of node (x, y) from the particle state Pn: first particle (in index
+// order) whose disc strictly contains the node, else fluid.
+__device__ __forceinline__ uint8_t new_label(const DevDomain &D, const PState *Pn, int x, int y) {
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  for (int q = 0; q < D.np; ++q) {
+    const double dx = min_image((double)x - Pn[q].x, D.nx, perx);
+    const double dy = min_image((double)y - Pn[q].y, D.ny, pery);
+    if (dx * dx + dy * dy < Pn[q].radius * Pn[q].radius) return (uint8_t)(LBL_PART0 + q);
+  }
+  return LBL_FLUID;
+}
+
+// Covered/uncovered nodes of particle p between G(T) (the label plane, not yet
+// rewritten) and G(T+1) (from P(T+1)): F = +rho (u - U_p) for a covered node,
+// -rho (u - U_p) for an uncovered one, with rho and u = j/rho + g/2 the
+// moments of f(T+1) (recovered from f*(T+1): j(f*) = j(f) + rho g), applied
+// in the next step (Eq. MP3).
+template <int ST>
+__global__ __launch_bounds__(256) void k_cover(const DevDomain *__restrict__ doms,
+                                               const PItem *__restrict__ items, int kstep) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  __shared__ double red[4][3];
+  const PItem it = items[blockIdx.x];
+  const DevDomain &D = doms[it.dom];
+  const uint64_t T1 = *D.tstep + (uint64_t)kstep + 1;
+  const PState *Pn = D.pstate[T1 & 1];
+  const PState P = Pn[it.p];
+  const T *src = (const T *)D.f[T1 & 1];
+  const size_t plane = (size_t)D.ny * D.pitch;
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  const uint8_t mine = (uint8_t)(LBL_PART0 + it.p);
+  const int reach = (int)ceil(P.radius) + 3;
+  const int W = 2 * reach + 2;
+  const int bx0 = (int)floor(P.x) - reach, by0 = (int)floor(P.y) - reach;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < W * W; j += 256) {
+    int x = bx0 + j % W, y = by0 + j / W;
+    if (!wrap_coord(x, D.nx, perx) || !wrap_coord(y, D.ny, pery)) continue;
+    const uint32_t here = (uint32_t)y * D.pitch + x;
+    const uint8_t l0 = D.label[here];
+    if (l0 == LBL_SOLID) continue;
+    const uint8_t l1 = new_label(D, Pn, x, y);
+    if ((l0 == mine) == (l1 == mine)) continue;
+    const double sign = l1 == mine ? 1.0 : -1.0;
+    double drho = 0.0, jx = 0.0, jy = 0.0;
+    for (int i = 0; i < 9; ++i) {
+      const double v = (double)S::load(src + i * plane, here, i);
+      drho += v;
+      jx += v * cx(i);
+      jy += v * cy(i);
+    }
+    const double rho = D.rho0 + drho;
+    const double ux = jx / rho - 0.5 * D.gx, uy = jy / rho - 0.5 * D.gy;
+    const double fx = sign * rho * (ux - P.ux), fy = sign * rho * (uy - P.uy);
+    const double rx = min_image(x - P.x, D.nx, perx), ry = min_image(y - P.y, D.ny, pery);
+    acc[0] += fx;
+    acc[1] += fy;
+    acc[2] += rx * fy - ry * fx;
+  }
+  block_sum<3>(acc, red);
+  if (threadIdx.x == 0) {
+    PForce &F = D.pforce[it.p];
+    F.cx_ = acc[0];
+    F.cy_ = acc[1];
+    F.ctorque = acc[2];
+  }
+}
+
+#ifdef LBK_COMMON_KERNELS
+// Write G(T+1) inside particle p's box (every changed node lies in the box of
+// the particle it leaves or enters; concurrent boxes write identical values).
+__global__ __launch_bounds__(256) void k_relabel(const DevDomain *__restrict__ doms,
+                                                 const PItem *__restrict__ items, int kstep,
+                                                 int time_offset) {
+  const PItem it = items[blockIdx.x];
+  const DevDomain &D = doms[it.dom];
+  const uint64_t T1 = *D.tstep + (uint64_t)kstep + (uint64_t)time_offset;
+  const PState *Pn = D.pstate[T1 & 1];
+  const PState P = Pn[it.p];
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  const int reach = (int)ceil(P.radius) + 3;
+  const int W = 2 * reach + 2;
+  const int bx0 = (int)floor(P.x) - reach, by0 = (int)floor(P.y) - reach;
+  for (int j = threadIdx.x; j < W * W; j += 256) {
+    int x = bx0 + j % W, y = by0 + j / W;
+    if (!wrap_coord(x, D.nx, perx) || !wrap_coord(y, D.ny, pery)) continue;
+    const size_t here = (size_t)y * D.pitch + x;
+    const uint8_t l0 = D.label[here];
+    if (l0 == LBL_SOLID) continue;
+    const uint8_t l1 = new_label(D, Pn, x, y);
+    if (l1 != l0) D.label[here] = l1;
+  }
+}
+#endif  // LBK_COMMON_KERNELS
+
+}  // namespace lbk

@@ -1,0 +1,358 @@
+// sweep_impl.h -- the fused stream-collide sweep and the initial collision.
+//
+// One launch advances every tile of every domain of a batch by one step:
+//   pull  f_i(x) <- f*_i(x - e_i) from the post-collision buffer of step T,
+//         with halfway bounce-back where the source is solid, moving-wall
+//         bounce-back where the pull crosses a particle surface (Eqs. MP7-MP8),
+//         and Zou-He reconstruction of the unknown populations on density faces;
+//   collide at step T+1: moments, body force through the equilibrium velocity
+//         (Sec. 2), local power-law tau* (Sec. 5), BGK relaxation (Eq. LB1),
+//         thermal noise on the non-conserved modes (Eqs. NP1-NP2);
+//   store f*(T+1) into the other buffer.
+// Arithmetic works on deviations d_i = f_i - w_i rho0 and never forms f_i.
+#pragma once
+
+#include "lb_device.h"
+
+namespace lbk {
+
+template <class R> __device__ __forceinline__ R par(double a, float b);
+template <> __device__ __forceinline__ double par<double>(double a, float) { return a; }
+template <> __device__ __forceinline__ float par<float>(double, float b) { return b; }
+
+template <class R> __device__ __forceinline__ R rsq(R v);
+template <> __device__ __forceinline__ float rsq<float>(float v) { return 1.0f / sqrtf(v); }
+template <> __device__ __forceinline__ double rsq<double>(double v) { return 1.0 / sqrt(v); }
+
+template <class R> __device__ __forceinline__ R powr(R a, R b);
+template <> __device__ __forceinline__ float powr<float>(float a, float b) { return exp2f(b * log2f(a)); }
+template <> __device__ __forceinline__ double powr<double>(double a, double b) { return pow(a, b); }
+
+// Local relaxation time of the power-law fluid (Sec. 5).  The shear rate
+// comes from the non-equilibrium stress Pi = sum e e (f - feq(rho, j/rho + g/2)):
+// gamma_dot = A / tau*, A = 3 |Pi|_F / (sqrt(2) rho).  With nu* = xi gamma_dot^(n-1)
+// (Eq. nn4, kappa = 2^(n-1)) and tau* = 1/2 + 3 nu*, tau* is the root of
+// h(tau) = tau - 1/2 - c tau^(1-n), c = 3 xi A^(n-1), clamped to
+// [tau_min, tau_max].  n = 1/2 has the closed form tau = s^2,
+// s = (c + sqrt(c^2 + 2))/2; otherwise Newton from the bracket end on the side
+// where it converges monotonically (tau_max for n < 1, tau_min for n > 1).
+template <class R, int PLM>
+__device__ __forceinline__ R powerlaw_tau(const DevDomain &D, const R d[9], R drho, R rho, R irho,
+                                          R jx, R jy) {
+  const R gx = par<R>(D.gx, D.gx_f), gy = par<R>(D.gy, D.gy_f);
+  const R ux = jx * irho + R(0.5) * gx, uy = jy * irho + R(0.5) * gy;
+  const R third = drho * (R(1) / R(3));
+  const R sxx = (d[1] + d[3]) + ((d[5] + d[6]) + (d[7] + d[8]));
+  const R syy = (d[2] + d[4]) + ((d[5] + d[6]) + (d[7] + d[8]));
+  const R sxy = (d[5] - d[6]) + (d[7] - d[8]);
+  const R pxx = sxx - rho * ux * ux - third;
+  const R pyy = syy - rho * uy * uy - third;
+  const R pxy = sxy - rho * ux * uy;
+  const R fro = sqrt(pxx * pxx + pyy * pyy + R(2) * pxy * pxy);
+  const R A = R(2.1213203435596424) * fro * irho;  // 3 / sqrt(2)
+  const R tmin = par<R>(D.tau_min, D.tau_min_f), tmax = par<R>(D.tau_max, D.tau_max_f);
+  const R xi = par<R>(D.pl_K, D.pl_K_f);
+  const R n = par<R>(D.pl_n, D.pl_n_f);
+  if (PLM == PL_GENERIC && n == R(1)) {  // Newtonian: tau* = 1/2 + 3 xi
+    const R t = R(0.5) + R(3) * xi;
+    return t < tmin ? tmin : (t > tmax ? tmax : t);
+  }
+  const bool thinning = PLM == PL_HALF || PLM == PL_3Q || (PLM == PL_GENERIC && n < R(1));
+  if (!(A > R(0))) return thinning ? tmax : tmin;
+  R tau;
+  if constexpr (PLM == PL_HALF) {
+    const R c = R(3) * xi * rsq<R>(A);
+    const R s = R(0.5) * (c + sqrt(c * c + R(2)));
+    tau = s * s;
+  } else {
+    R c;
+    if constexpr (PLM == PL_3Q) c = R(3) * xi * sqrt(rsq<R>(A));          // A^(-1/4)
+    else if constexpr (PLM == PL_3H) c = R(3) * xi * sqrt(A);              // A^(1/2)
+    else c = R(3) * xi * powr<R>(A, n - R(1));
+    // h(t) = t - 1/2 - c t^(1-n), h'(t) = 1 - c (1-n) t^(-n)
+    auto tpow = [&](R t, R &tp, R &tpm) {  // t^(1-n), t^(-n)
+      if constexpr (PLM == PL_3Q) { const R q = sqrt(sqrt(t)); tp = q; tpm = q / t; }
+      else if constexpr (PLM == PL_3H) { const R r = rsq<R>(t); tp = r; tpm = r / t; }
+      else { tp = powr<R>(t, R(1) - n); tpm = tp / t; }
+    };
+    R t0 = thinning ? tmax : tmin;
+    R tp, tpm;
+    tpow(t0, tp, tpm);
+    const R h0 = t0 - R(0.5) - c * tp;
+    if (thinning ? !(h0 > R(0)) : !(h0 < R(0))) return t0;
+    constexpr int ITERS = sizeof(R) == 8 ? 40 : 12;
+    const R tol = sizeof(R) == 8 ? R(1e-15) : R(1e-7);
+    R t = t0;
+#pragma unroll 1
+    for (int it = 0; it < ITERS; ++it) {
+      tpow(t, tp, tpm);
+      const R h = t - R(0.5) - c * tp;
+      const R dh = R(1) - c * (R(1) - n) * tpm;
+      const R tn = t - h / dh;
+      const bool done = fabs(tn - t) <= tol * tn;
+      t = tn;
+      if (done) break;
+    }
+    tau = t;
+  }
+  return tau < tmin ? tmin : (tau > tmax ? tmax : tau);
+}
+
+// BGK collision of one node (deviations in, deviations out), step `step`.
+template <int ST, int FEAT, int PLM>
+__device__ __forceinline__ void collide_node(const DevDomain &D, typename Store<ST>::R d[9],
+                                             uint32_t node, uint32_t step) {
+  using R = typename Store<ST>::R;
+  const R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+  const R jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+  const R jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+  const R rho = par<R>(D.rho0, D.rho0_f) + drho;
+  const R irho = R(1) / rho;
+  R tau, om;
+  if constexpr ((FEAT & F_POWER) != 0) {
+    tau = powerlaw_tau<R, PLM>(D, d, drho, rho, irho, jx, jy);
+    om = R(1) / tau;
+  } else {
+    tau = par<R>(D.tau, D.tau_f);
+    om = par<R>(D.omega, D.omega_f);
+  }
+  const R ux = jx * irho + tau * par<R>(D.gx, D.gx_f);
+  const R uy = jy * irho + tau * par<R>(D.gy, D.gy_f);
+  const R A = drho - R(1.5) * rho * (ux * ux + uy * uy);
+  const R w0 = wgt<R>(0), w1 = wgt<R>(1), w5 = wgt<R>(5);
+  R eq[9];
+  eq[0] = w0 * A;
+  {
+    const R a = R(3) * ux, b = R(3) * uy;
+    const R hx = R(0.5) * a * a, hy = R(0.5) * b * b;
+    eq[1] = w1 * (A + rho * (hx + a));
+    eq[3] = w1 * (A + rho * (hx - a));
+    eq[2] = w1 * (A + rho * (hy + b));
+    eq[4] = w1 * (A + rho * (hy - b));
+    const R p = a + b, m = b - a;
+    const R hp = R(0.5) * p * p, hm = R(0.5) * m * m;
+    eq[5] = w5 * (A + rho * (hp + p));
+    eq[7] = w5 * (A + rho * (hp - p));
+    eq[6] = w5 * (A + rho * (hm + m));
+    eq[8] = w5 * (A + rho * (hm - m));
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) d[i] = d[i] + om * (eq[i] - d[i]);
+
+  if constexpr ((FEAT & F_NOISE) != 0) {
+    float th[6];
+    noise_normals(D.key0, D.key1, node, step, th);
+    // Theta_k / sqrt(w_k) with w_k = 4, 4/9, 1/9, 2/3, 2/3, 16 (Table t1)
+    const R t3 = R(th[0]) * R(0.5), t4 = R(th[1]) * R(1.5), t5 = R(th[2]) * R(3);
+    const R t6 = R(th[3]) * R(1.2247448713915890491), t7 = R(th[4]) * R(1.2247448713915890491);
+    const R t8 = R(th[5]) * R(0.25);
+    const R amp = sqrt(rho * par<R>(D.kT, D.kT_f) * om * (R(2) - om) * R(3));
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const R z = R(basis_poly(3, i)) * t3 + R(basis_poly(4, i)) * t4 + R(basis_poly(5, i)) * t5 +
+                  R(basis_poly(6, i)) * t6 + R(basis_poly(7, i)) * t7 + R(basis_poly(8, i)) * t8;
+      d[i] += amp * wgt<R>(i) * z;
+    }
+  }
+}
+
+template <int ST>
+__device__ __forceinline__ void store_node(const DevDomain &D, typename Store<ST>::T *dst,
+                                           size_t plane, uint32_t off,
+                                           const typename Store<ST>::R d[9], uint32_t node,
+                                           uint32_t step) {
+  using S = Store<ST>;
+  if constexpr (ST == ST_F16 || ST == ST_BF16) {
+    if (D.feat & F_STOCH) {
+      const uint32_t h = mix32(node * 0x9E3779B1u ^ mix32(step ^ D.key0) ^ D.key1);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const uint32_t r = mix32(h + (uint32_t)i * 0x632BE5ABu) | 1u;
+        S::put(dst + i * plane, off, i, d[i], r);
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) S::put(dst + i * plane, off, i, d[i], 0u);
+}
+
+// Moving-wall term 6 rho0 w_d (u_b . e_d) of the pull into (x, y) along d
+// crossing the surface of particle p, with u_b = U + Omega z x (r_b - r_c)
+// at the link midpoint r_b = x - e_d / 2 (Eqs. MP7-MP8).
+template <class R>
+__device__ __forceinline__ R moving_wall_term(const DevDomain &D, const PState &P, int x, int y,
+                                              int dir) {
+  const double bx = (double)x - 0.5 * cx(dir), by = (double)y - 0.5 * cy(dir);
+  const double rx = min_image(bx - P.x, (double)D.nx, D.bc_x == BC_PERIODIC);
+  const double ry = min_image(by - P.y, (double)D.ny, D.bc_y == BC_PERIODIC);
+  const double vx = P.ux - P.omega * ry, vy = P.uy + P.omega * rx;
+  const double ue = vx * cx(dir) + vy * cy(dir);
+  return R(6.0 * D.rho0 * wgt<double>(dir) * ue);
+}
+
+template <int ST, int FEAT, int PLM>
+__global__ __launch_bounds__(256) void k_sweep(const DevDomain *__restrict__ doms,
+                                               const int *__restrict__ prefix, int ndom,
+                                               int kstep) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
+  constexpr bool LABELS = (FEAT & F_LABELS) != 0;
+
+  const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int dix = ndom == 1 ? 0 : find_domain(prefix, ndom, b);
+  const DevDomain &D = doms[dix];
+  const int local = b - prefix[dix];
+  const int nx = D.nx, ny = D.ny, pitch = D.pitch;
+  const int tw = D.tile_w, npt = D.rows_per_thread;
+  const int rows_pass = 256 / tw;
+  const int tyi = local / D.tiles_x, txi = local - tyi * D.tiles_x;
+  const int x = txi * tw + (int)threadIdx.x % tw;
+  if (x >= nx) return;
+  const int ybase = tyi * rows_pass * npt + (int)threadIdx.x / tw;
+
+  const uint64_t T0 = *D.tstep + (uint64_t)kstep;  // state time of the source buffer
+  const uint32_t step = (uint32_t)(T0 + 1);
+  const T *__restrict__ src = (const T *)D.f[T0 & 1];
+  T *__restrict__ dst = (T *)D.f[(T0 + 1) & 1];
+  const size_t plane = (size_t)ny * pitch;
+  const PState *P = D.pstate[T0 & 1];
+  const uint8_t *lab = D.label;
+
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  const bool wallx = D.bc_x == BC_WALL, wally = D.bc_y == BC_WALL;
+  const bool pressx = D.bc_x == BC_PRESSURE;
+
+  // columns x-1, x, x+1 (index by 1 - cx)
+  int col[3];
+  bool col_out[3], col_wall[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int c = x + 1 - k;  // k = 0 -> x+1 (source of cx = -1), k = 2 -> x-1 (cx = +1)
+    bool out = false;
+    if (c < 0) { if (perx) c += nx; else out = true; }
+    else if (c >= nx) { if (perx) c -= nx; else out = true; }
+    col[k] = out ? x : c;
+    col_out[k] = out;
+    col_wall[k] = wallx && (c == 0 || c == nx - 1);
+  }
+
+#pragma unroll 1
+  for (int r = 0; r < npt; ++r) {
+    const int y = ybase + r * rows_pass;
+    if (y >= ny) break;
+    const uint32_t here = (uint32_t)y * pitch + x;
+    uint8_t lx = 0;
+    if constexpr (LABELS) {
+      lx = lab[here];
+      if (lx == LBL_SOLID) continue;
+    } else {
+      if ((wally && (y == 0 || y == ny - 1)) || (wallx && (x == 0 || x == nx - 1))) continue;
+    }
+    int row[3];
+    bool row_out[3], row_wall[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      int rr = y + 1 - k;  // k = 0 -> y+1 (source of cy = -1), k = 2 -> y-1
+      bool out = false;
+      if (rr < 0) { if (pery) rr += ny; else out = true; }
+      else if (rr >= ny) { if (pery) rr -= ny; else out = true; }
+      row[k] = (out ? y : rr) * pitch;
+      row_out[k] = out;
+      row_wall[k] = wally && (rr == 0 || rr == ny - 1);
+    }
+
+    R d[9];
+    uint32_t unknown = 0;
+    d[0] = S::load(src, here, 0);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const int kc = 1 + cx(i), kr = 1 + cy(i);
+      if (col_out[kc] || row_out[kr]) {
+        unknown |= 1u << i;
+        d[i] = R(0);
+        continue;
+      }
+      const uint32_t so = (uint32_t)row[kr] + (uint32_t)col[kc];
+      bool solid;
+      uint8_t ls = 0;
+      if constexpr (LABELS) {
+        ls = lab[so];
+        solid = ls == LBL_SOLID;
+      } else {
+        solid = col_wall[kc] || row_wall[kr];
+      }
+      if (solid) {
+        d[i] = S::load(src + opp(i) * plane, here, opp(i));
+      } else if (LABELS && (lx | ls) >= LBL_PART0 && (lx == 0 || ls == 0)) {
+        const int p = (int)(lx | ls) - LBL_PART0;
+        d[i] = S::load(src + opp(i) * plane, here, opp(i)) + moving_wall_term<R>(D, P[p], x, y, i);
+      } else {
+        d[i] = S::load(src + i * plane, so, i);
+      }
+    }
+    if (pressx && unknown) {
+      const R half = R(0.5), third2 = R(2) / R(3), sixth = R(1) / R(6);
+      if (x == 0) {
+        const R s = d[0] + d[2] + d[4] + R(2) * (d[3] + d[6] + d[7]);
+        const R rux = (par<R>(D.rho_in, D.rho_in_f) - par<R>(D.rho0, D.rho0_f)) - s;
+        d[1] = d[3] + third2 * rux;
+        d[5] = d[7] - half * (d[2] - d[4]) + sixth * rux;
+        d[8] = d[6] + half * (d[2] - d[4]) + sixth * rux;
+      } else {
+        const R s = d[0] + d[2] + d[4] + R(2) * (d[1] + d[5] + d[8]);
+        const R rux = s - (par<R>(D.rho_out, D.rho_out_f) - par<R>(D.rho0, D.rho0_f));
+        d[3] = d[1] - third2 * rux;
+        d[7] = d[5] + half * (d[2] - d[4]) - sixth * rux;
+        d[6] = d[8] - half * (d[2] - d[4]) - sixth * rux;
+      }
+    }
+    const uint32_t node = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
+    collide_node<ST, FEAT, PLM>(D, d, node, step);
+    const R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    if (!(fabs(drho) < R(1e30))) atomicOr(D.health, HEALTH_NONFINITE);
+    store_node<ST>(D, dst, plane, here, d, node, step);
+  }
+}
+
+// Initial state: equilibrium of the given fields (or rest), then the
+// collision of the current step, written to the buffer of that step.
+// Rows [row0, row0 + nrows); fields are band-local [nrows][nx] FP64.
+template <int ST, int FEAT, int PLM>
+__global__ __launch_bounds__(256) void k_init(const DevDomain *__restrict__ Dp, const double *rho_f,
+                                              const double *ux_f, const double *uy_f, int row0,
+                                              int nrows) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
+  const DevDomain &D = *Dp;
+  const int x = (int)(blockIdx.x * 256 + threadIdx.x) % D.pitch;
+  const int yl = (int)(blockIdx.x * 256 + threadIdx.x) / D.pitch;
+  if (x >= D.nx || yl >= nrows) return;
+  const int y = row0 + yl;
+  const uint64_t T0 = *D.tstep;
+  T *dst = (T *)D.f[T0 & 1];
+  const size_t plane = (size_t)D.ny * D.pitch;
+  const uint32_t here = (uint32_t)y * D.pitch + x;
+  R d[9];
+  if (rho_f) {
+    const size_t fi = (size_t)yl * D.nx + x;
+    const R rho = R(rho_f[fi]), ux = R(ux_f[fi]), uy = R(uy_f[fi]);
+    const R drho = R(rho_f[fi] - D.rho0);
+    const R A = drho - R(1.5) * rho * (ux * ux + uy * uy);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const R eu = R(3) * (R(cx(i)) * ux + R(cy(i)) * uy);
+      d[i] = wgt<R>(i) * (A + rho * (eu + R(0.5) * eu * eu));
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d[i] = R(0);
+  }
+  const uint32_t node = (uint32_t)y * (uint32_t)D.nx + (uint32_t)x;
+  collide_node<ST, FEAT, PLM>(D, d, node, (uint32_t)T0);
+  store_node<ST>(D, dst, plane, here, d, node, (uint32_t)T0);
+}
+
+}  // namespace lbk

@@ -1,0 +1,333 @@
+"""Python binding of liblb.so (include/lb.h): argument marshalling only.
+
+Every computation runs in the HIP library; torch provides the device
+workspace (a uint8 tensor the library sub-allocates) and the HIP stream.
+Names follow the C ABI: ``Domain.step`` wraps ``lb_step``, ``Domain.moments``
+wraps ``lb_moments`` and so on.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime the library then shares
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblb.so")
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ESTATE, LB_EUNSTABLE, LB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+PERIODIC, WALL, PRESSURE = 0, 1, 2
+F64, F32, F16_DELTA, BF16_DELTA = 0, 1, 2, 3
+ROUND_NEAREST, ROUND_STOCHASTIC = 0, 1
+INIT_REST, INIT_FIELDS = 0, 1
+PARTICLE_FIXED = 1
+OPT_USE_GRAPH, OPT_TILE_WIDTH, OPT_ROWS_PER_THREAD, OPT_GRAPH_CHUNK = 1, 2, 3, 4
+ABI_VERSION = 1
+
+_BC = {"periodic": PERIODIC, "wall": WALL, "pressure": PRESSURE}
+_ST = {"f64": F64, "f32": F32, "f16": F16_DELTA, "bf16": BF16_DELTA}
+_RND = {"nearest": ROUND_NEAREST, "stochastic": ROUND_STOCHASTIC}
+
+EXPORTED = [
+    "lb_workspace_bytes", "lb_create_domain", "lb_set_obstacles", "lb_add_particles", "lb_step",
+    "lb_moments", "lb_moments_device", "lb_get_particles", "lb_mass", "lb_time",
+    "lb_get_populations", "lb_set_populations", "lb_set_option", "lb_get_option",
+    "lb_destroy_domain", "lb_batch_workspace_bytes", "lb_batch_create", "lb_batch_step",
+    "lb_batch_set_option", "lb_batch_destroy", "lb_noise_normals", "lb_autotune",
+    "lb_status_string", "lb_last_error",
+]
+
+
+class DomainDesc(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32),
+        ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("storage", C.c_int32),
+        ("rounding", C.c_int32), ("obstacles", C.c_int32), ("max_particles", C.c_int32),
+        ("power_law", C.c_int32), ("init_kind", C.c_int32), ("domain_id", C.c_uint32),
+        ("seed", C.c_uint64), ("rho0", C.c_double), ("tau", C.c_double),
+        ("gx", C.c_double), ("gy", C.c_double), ("rho_in", C.c_double), ("rho_out", C.c_double),
+        ("kT", C.c_double), ("n_index", C.c_double), ("K", C.c_double),
+        ("tau_min", C.c_double), ("tau_max", C.c_double), ("lj_psi", C.c_double),
+        ("lj_rit", C.c_double), ("lj_floor", C.c_double),
+        ("init_rho", C.POINTER(C.c_double)), ("init_ux", C.POINTER(C.c_double)),
+        ("init_uy", C.POINTER(C.c_double)),
+    ]
+
+
+class Particle(C.Structure):
+    _fields_ = [
+        ("x", C.c_double), ("y", C.c_double), ("radius", C.c_double),
+        ("density_ratio", C.c_double), ("ux", C.c_double), ("uy", C.c_double),
+        ("omega", C.c_double), ("fx", C.c_double), ("fy", C.c_double), ("torque", C.c_double),
+        ("flags", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class LBError(RuntimeError):
+    def __init__(self, status, where, detail):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+
+def library():
+    """Load liblb.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2006_12910_amd.build` (hipcc, gfx950)")
+    lib = C.CDLL(LIB_PATH)
+    P, vp, st = C.POINTER, C.c_void_p, C.c_int32
+    dp = P(C.c_double)
+    sig = {
+        "lb_workspace_bytes": [P(DomainDesc), P(C.c_size_t)],
+        "lb_create_domain": [P(DomainDesc), vp, C.c_size_t, vp, P(vp)],
+        "lb_set_obstacles": [vp, P(C.c_uint8), C.c_size_t],
+        "lb_add_particles": [vp, P(Particle), st, P(st)],
+        "lb_step": [vp, C.c_int64],
+        "lb_moments": [vp, dp, dp, dp],
+        "lb_moments_device": [vp, vp, vp, vp],
+        "lb_get_particles": [vp, P(Particle), st],
+        "lb_mass": [vp, dp],
+        "lb_time": [vp, P(C.c_int64)],
+        "lb_get_populations": [vp, dp],
+        "lb_set_populations": [vp, dp],
+        "lb_set_option": [vp, st, C.c_int64],
+        "lb_get_option": [vp, st, P(C.c_int64)],
+        "lb_destroy_domain": [vp],
+        "lb_batch_workspace_bytes": [P(vp), st, P(C.c_size_t)],
+        "lb_batch_create": [P(vp), st, vp, C.c_size_t, vp, P(vp)],
+        "lb_batch_step": [vp, C.c_int64],
+        "lb_batch_set_option": [vp, st, C.c_int64],
+        "lb_batch_destroy": [vp],
+        "lb_noise_normals": [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, vp, vp],
+        "lb_autotune": [vp, st, dp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = st
+    lib.lb_status_string.restype = C.c_char_p
+    lib.lb_status_string.argtypes = [st]
+    lib.lb_last_error.restype = C.c_char_p
+    lib.lb_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(status, where):
+    if status != LB_OK:
+        lib = library()
+        raise LBError(status, where, lib.lb_last_error().decode() or
+                      lib.lb_status_string(status).decode())
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Domain:
+    """One lattice domain on the GPU (lb_create_domain ... lb_destroy_domain)."""
+
+    def __init__(self, nx, ny, *, tau=1.0, rho0=1.0, g=(0.0, 0.0), bc_x="periodic",
+                 bc_y="periodic", storage="f32", rounding="nearest", rho_in=1.0, rho_out=1.0,
+                 kT=0.0, seed=0, domain_id=0, power_law=None, obstacles=None, max_particles=0,
+                 lj=(20.0, 2.5, 0.1), init=None, device="cuda", stream=None):
+        lib = library()
+        d = DomainDesc()
+        d.abi_version = ABI_VERSION
+        d.nx, d.ny = int(nx), int(ny)
+        d.bc_x, d.bc_y = _BC[bc_x], _BC[bc_y]
+        d.storage = _ST[storage]
+        d.rounding = _RND[rounding]
+        d.obstacles = 1 if obstacles is not None else 0
+        d.max_particles = int(max_particles)
+        d.domain_id = int(domain_id) & 0xFFFFFFFF
+        d.seed = int(seed) & (2 ** 64 - 1)
+        d.rho0, d.tau = float(rho0), float(tau)
+        d.gx, d.gy = float(g[0]), float(g[1])
+        d.rho_in, d.rho_out = float(rho_in), float(rho_out)
+        d.kT = float(kT)
+        if power_law is not None:
+            d.power_law = 1
+            d.n_index = float(power_law["n"])
+            d.K = float(power_law["K"])
+            d.tau_min = float(power_law.get("tau_min", 0.51))
+            d.tau_max = float(power_law.get("tau_max", 2.5))
+        d.lj_psi, d.lj_rit, d.lj_floor = (float(v) for v in lj)
+        self._fields = None
+        if init is not None:
+            shape = (ny, nx)
+            self._fields = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), shape))
+                            for a in init]
+            d.init_kind = INIT_FIELDS
+            d.init_rho, d.init_ux, d.init_uy = (_dptr(a) for a in self._fields)
+        self.desc = d
+        self.nx, self.ny = int(nx), int(ny)
+        self._np = 0
+        nbytes = C.c_size_t()
+        _check(lib.lb_workspace_bytes(C.byref(d), C.byref(nbytes)), "lb_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+        self._stream = stream
+        h = C.c_void_p()
+        _check(lib.lb_create_domain(C.byref(d), C.c_void_p(self.workspace.data_ptr()),
+                                    nbytes.value, _stream_ptr(stream), C.byref(h)),
+               "lb_create_domain")
+        self._h = h
+        self._fields = None
+        d.init_rho = d.init_ux = d.init_uy = None
+        if obstacles is not None:
+            self.set_obstacles(obstacles)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(library().lb_destroy_domain(self._h), "lb_destroy_domain")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_obstacles(self, mask):
+        m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8).reshape(self.ny, self.nx)
+        _check(library().lb_set_obstacles(self._h, m.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                          m.size), "lb_set_obstacles")
+
+    def add_particles(self, particles):
+        """particles: iterable of dicts with x, y, radius and optional
+        density_ratio, ux, uy, omega, fixed."""
+        plist = list(particles)
+        arr = (Particle * max(len(plist), 1))()
+        for k, p in enumerate(plist):
+            arr[k] = Particle(p["x"], p["y"], p["radius"], p.get("density_ratio", 1.0),
+                              p.get("ux", 0.0), p.get("uy", 0.0), p.get("omega", 0.0), 0, 0, 0,
+                              PARTICLE_FIXED if p.get("fixed") else 0, 0)
+        first = C.c_int32()
+        _check(library().lb_add_particles(self._h, arr, len(plist), C.byref(first)),
+               "lb_add_particles")
+        self._np = first.value + len(plist)
+        return first.value
+
+    def step(self, n=1):
+        _check(library().lb_step(self._h, int(n)), "lb_step")
+        return self
+
+    def moments(self):
+        shape = (self.ny, self.nx)
+        r, u, v = (np.empty(shape) for _ in range(3))
+        _check(library().lb_moments(self._h, _dptr(r), _dptr(u), _dptr(v)), "lb_moments")
+        return r, u, v
+
+    def moments_device(self):
+        t = torch.empty((3, self.ny, self.nx), dtype=torch.float64, device=self.workspace.device)
+        _check(library().lb_moments_device(self._h, C.c_void_p(t[0].data_ptr()),
+                                           C.c_void_p(t[1].data_ptr()),
+                                           C.c_void_p(t[2].data_ptr())), "lb_moments_device")
+        return t
+
+    def particles(self, n=None):
+        """[n][10]: x, y, radius, density_ratio, ux, uy, omega, fx, fy, torque."""
+        n = self.num_particles if n is None else n
+        arr = (Particle * max(n, 1))()
+        _check(library().lb_get_particles(self._h, arr, n), "lb_get_particles")
+        keys = ["x", "y", "radius", "density_ratio", "ux", "uy", "omega", "fx", "fy", "torque"]
+        return np.array([[getattr(arr[i], k) for k in keys] for i in range(n)]).reshape(n, 10)
+
+    @property
+    def num_particles(self):
+        return self._np
+
+    def mass(self):
+        m = C.c_double()
+        _check(library().lb_mass(self._h, C.byref(m)), "lb_mass")
+        return m.value
+
+    @property
+    def time(self):
+        t = C.c_int64()
+        _check(library().lb_time(self._h, C.byref(t)), "lb_time")
+        return t.value
+
+    def populations(self):
+        """Post-collision deviations f*_i - w_i rho0, [9][ny][nx] FP64."""
+        f = np.empty((9, self.ny, self.nx))
+        _check(library().lb_get_populations(self._h, _dptr(f)), "lb_get_populations")
+        return f
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, np.float64).reshape(9, self.ny, self.nx)
+        _check(library().lb_set_populations(self._h, _dptr(f)), "lb_set_populations")
+
+    def set_option(self, key, value):
+        _check(library().lb_set_option(self._h, int(key), int(value)), "lb_set_option")
+
+    def get_option(self, key):
+        v = C.c_int64()
+        _check(library().lb_get_option(self._h, int(key), C.byref(v)), "lb_get_option")
+        return v.value
+
+    def autotune(self, steps=20):
+        ms = C.c_double()
+        _check(library().lb_autotune(self._h, int(steps), C.byref(ms)), "lb_autotune")
+        return ms.value
+
+
+class Batch:
+    """Several domains advanced together (lb_batch_create ... lb_batch_destroy)."""
+
+    def __init__(self, domains, stream=None):
+        lib = library()
+        self.domains = list(domains)
+        hs = (C.c_void_p * len(self.domains))(*[d.handle.value for d in self.domains])
+        nbytes = C.c_size_t()
+        _check(lib.lb_batch_workspace_bytes(hs, len(self.domains), C.byref(nbytes)),
+               "lb_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8,
+                                     device=self.domains[0].workspace.device)
+        h = C.c_void_p()
+        _check(lib.lb_batch_create(hs, len(self.domains), C.c_void_p(self.workspace.data_ptr()),
+                                   nbytes.value, _stream_ptr(stream), C.byref(h)),
+               "lb_batch_create")
+        self._h = h
+
+    def step(self, n=1):
+        _check(library().lb_batch_step(self._h, int(n)), "lb_batch_step")
+        return self
+
+    def set_option(self, key, value):
+        _check(library().lb_batch_set_option(self._h, int(key), int(value)), "lb_batch_set_option")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(library().lb_batch_destroy(self._h), "lb_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def noise_normals(seed, domain_id, step, node0, count, device="cuda"):
+    """lb_noise_normals: Theta_3..Theta_8 of nodes node0.. at `step`, [count][6] FP32."""
+    out = torch.empty((count, 6), dtype=torch.float32, device=device)
+    _check(library().lb_noise_normals(int(seed) & (2 ** 64 - 1), int(domain_id) & 0xFFFFFFFF,
+                                      int(step) & 0xFFFFFFFF, int(node0) & 0xFFFFFFFF,
+                                      int(count), C.c_void_p(out.data_ptr()),
+                                      _stream_ptr(None)), "lb_noise_normals")
+    return out

@@ -1,0 +1,75 @@
+"""The C-ABI library loads and exports every entry point include/lb.h
+declares; argument validation needs no GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_entry_points():
+    src = open(os.path.join(ROOT, "include", "lb.h")).read()
+    return sorted(set(re.findall(r"^(?:lb_status|const char \*)\s*(lb_\w+)\(", src, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_entry_points()
+    for required in ("lb_create_domain", "lb_set_obstacles", "lb_add_particles", "lb_step",
+                     "lb_moments", "lb_destroy_domain", "lb_batch_create", "lb_batch_step"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2006_12910_amd import lb
+    lib = lb.library()
+    names = declared_entry_points()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(lb.EXPORTED)
+
+
+def _desc(**kw):
+    from paper_2006_12910_amd import lb
+    d = lb.DomainDesc()
+    d.abi_version, d.nx, d.ny, d.tau, d.rho0 = 1, 64, 32, 0.8, 1.0
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(tau=0.5), "tau"), (dict(nx=2), "nx"), (dict(abi_version=7), "abi"),
+    (dict(bc_y=2), "bc_y"), (dict(storage=9), "storage"), (dict(rounding=1), "stochastic"),
+    (dict(max_particles=251), "max_particles"), (dict(kT=-1.0), "kT"),
+    (dict(power_law=1, n_index=0.5, K=0.01, tau_min=0.4, tau_max=2.5), "power law"),
+    (dict(bc_x=2, rho_in=0.0, rho_out=1.0), "pressure"), (dict(init_kind=1), "INIT_FIELDS"),
+])
+def test_validation_errors(bad, msg):
+    from paper_2006_12910_amd import lb
+    lib = lb.library()
+    n = C.c_size_t()
+    st = lib.lb_workspace_bytes(C.byref(_desc(**bad)), C.byref(n))
+    assert st == lb.LB_EINVAL
+    assert msg.lower() in lib.lb_last_error().decode().lower()
+
+
+def test_workspace_size_covers_both_population_buffers():
+    from paper_2006_12910_amd import lb
+    lib = lb.library()
+    for storage, size in ((0, 8), (1, 4), (2, 2), (3, 2)):
+        n = C.c_size_t()
+        assert lib.lb_workspace_bytes(C.byref(_desc(storage=storage, nx=1000, ny=100)),
+                                      C.byref(n)) == 0
+        assert n.value >= 2 * 9 * 1024 * 100 * size
+
+
+def test_null_arguments_are_rejected():
+    from paper_2006_12910_amd import lb
+    lib = lb.library()
+    assert lib.lb_step(None, 1) == lb.LB_EINVAL
+    assert lib.lb_moments(None, None, None, None) == lb.LB_EINVAL
+    assert lib.lb_destroy_domain(None) == lb.LB_EINVAL
+    assert lib.lb_status_string(lb.LB_EUNSTABLE).decode().startswith("simulation")
