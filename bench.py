@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Throughput of the D2Q9 lattice-Boltzmann hot path on one MI355X.
+
+Workload (precision-and-batching stress): one 8192x8192 periodic domain plus
+200 uneven periodic domains of 64^2..2048^2 (log-uniform sides, RSA disc
+obstacles at 20% solid, tau ~ U[0.55, 1.2]), all started from seeded shear
+waves (u0 = 0.01).  Every step advances all 201 domains with one sweep launch
+(batched, replayed from a hipGraph).  Populations are stored as FP16 deviations
+with stochastic rounding (the reported value), and, for comparison, as plain
+FP32 and as BF16 deviations; arithmetic is FP32.
+
+MLUPS counts every lattice site of every domain (solids included), as the
+paper defines it.  The roofline object reports the sweep kernel's algorithmic
+HBM bytes per launch over its measured duration against 8 TB/s.  The CPU
+baseline is the FP64 oracle on a bounded sample of the smallest domains of the
+same workload; the same sample gives the relative L2 velocity error of each
+storage format against the oracle.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS and % of HBM roofline, FP16-delta batched vs plain FP32 at stated L2 error"
+BIG_N = 8192
+BIG_TAU = 0.8
+N_SMALL = 200
+SHEAR_U0 = 0.01
+STORAGE_BYTES = {"f16": 2, "bf16": 2, "f32": 4}
+ROUNDING = {"f16": "stochastic", "bf16": "stochastic", "f32": "nearest"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+SWEEP_SOURCES = ["paper_2006_12910_amd/csrc/sweep_impl.h", "paper_2006_12910_amd/csrc/lb_device.h",
+                 "paper_2006_12910_amd/csrc/kernels_st.h"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def sweep_source_hash():
+    h = hashlib.sha256()
+    for rel in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload():
+    from paper_2006_12910_amd import inputs
+    specs = [dict(n=BIG_N, tau=BIG_TAU, k=1, phase=0.0, obstacle_seed=None)]
+    specs += inputs.stress_batch(count=N_SMALL, seed=0)
+    return specs
+
+
+def domain_inputs(spec):
+    from paper_2006_12910_amd import inputs
+    n = spec["n"]
+    fields = inputs.shear_wave_field(n, n, SHEAR_U0, spec["k"], spec["phase"])
+    mask = None if spec["obstacle_seed"] is None else inputs.stress_obstacles(n, spec["obstacle_seed"])
+    return fields, mask
+
+
+def build_variant(storage, specs, masks):
+    from paper_2006_12910_amd import lb
+    doms = []
+    for i, spec in enumerate(specs):
+        fields, _ = domain_inputs(dict(spec, obstacle_seed=None))
+        doms.append(lb.Domain(spec["n"], spec["n"], tau=spec["tau"], storage=storage,
+                              rounding=ROUNDING[storage], init=fields, obstacles=masks[i]))
+    return doms
+
+
+def algorithmic_bytes(specs, masks, sbytes):
+    """Bytes the sweep must move per step: 9 loads + 9 stores of each fluid
+    node's populations, plus one label byte per site of domains with obstacles."""
+    total = 0
+    for spec, m in zip(specs, masks):
+        n2 = spec["n"] * spec["n"]
+        fluid = n2 if m is None else n2 - int(m.sum())
+        total += 18 * sbytes * fluid + (0 if m is None else n2)
+    return total
+
+
+def run_variant(storage, specs, masks, steps, warmup):
+    import torch
+    from paper_2006_12910_amd import lb
+    t0 = time.time()
+    doms = build_variant(storage, specs, masks)
+    batch = lb.Batch(doms)
+    torch.cuda.synchronize()
+    log(f"{storage}: built {len(doms)} domains in {time.time() - t0:.1f}s")
+    batch.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    batch.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    log(f"{storage}: {steps} steps in {ms:.1f} ms")
+    return doms, batch, ms
+
+
+def oracle_sample(specs, masks, nsteps, budget_s):
+    """Smallest domains of the workload whose estimated oracle cost fits the
+    budget (about 25 M site-updates per second on the host)."""
+    order = sorted(range(len(specs)), key=lambda i: specs[i]["n"])
+    chosen, cost = [], 0.0
+    for i in order:
+        c = specs[i]["n"] ** 2 * nsteps / 25e6
+        if chosen and cost + c > budget_s:
+            break
+        chosen.append(i)
+        cost += c
+    return chosen
+
+
+def run_oracle(specs, masks, sample, nsteps):
+    from oracle import Oracle, OracleParams
+    results, t_total, sites = {}, 0.0, 0
+    for i in sample:
+        spec = specs[i]
+        n = spec["n"]
+        fields, _ = domain_inputs(dict(spec, obstacle_seed=None))
+        o = Oracle(OracleParams(nx=n, ny=n, tau=spec["tau"]), masks[i], *fields)
+        t0 = time.perf_counter()
+        o.run(nsteps)
+        t_total += time.perf_counter() - t0
+        sites += n * n * nsteps
+        results[i] = o.moments()
+    return results, sites / t_total / 1e6, t_total
+
+
+def l2_errors(doms, ref, specs):
+    errs_t, errs_0 = [], []
+    for i, (r, u, v) in ref.items():
+        rg, ug, vg = doms[i].moments()
+        num = np.sqrt(((ug - u) ** 2 + (vg - v) ** 2).sum())
+        errs_t.append(num / np.sqrt((u ** 2 + v ** 2).sum()))
+        fluid = r > 0
+        errs_0.append(num / (SHEAR_U0 * np.sqrt(0.5 * fluid.sum())))  # |u(0)| over fluid sites
+    return dict(max_vs_u_T=float(np.max(errs_t)), median_vs_u_T=float(np.median(errs_t)),
+                max_vs_u_0=float(np.max(errs_0)), median_vs_u_0=float(np.median(errs_0)))
+
+
+def traffic_entry(bytes_alg):
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    if t.get("sweep_source_hash") != sweep_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--variants", default="f16,f32,bf16",
+                    help="storage formats to run; the first is the reported value")
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of oracle work for the CPU baseline and the L2 sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline and L2 sample")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
+                    help="before the workload, copy a buffer of this size 5 times (a kernel of "
+                         "known traffic for scaling profiler byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the domains of a batch would shard across GPUs with no communication).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs an MI355X"
+    variants = [v.strip() for v in args.variants.split(",") if v.strip()]
+    if args.calibrate_copy > 0:
+        a = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: 5 x {args.calibrate_copy} MiB")
+        del a, b
+        torch.cuda.empty_cache()
+    specs = workload()
+    t0 = time.time()
+    masks = [None if s["obstacle_seed"] is None else domain_inputs(s)[1] for s in specs]
+    log(f"inputs: {len(specs)} domains, {sum(s['n'] ** 2 for s in specs) / 1e6:.1f} M sites "
+        f"({time.time() - t0:.1f}s)")
+    sites = sum(s["n"] ** 2 for s in specs)
+    nsteps_total = args.warmup + args.steps
+
+    sample, ref, cpu = [], {}, None
+    if not args.no_cpu:
+        threads = min(len(os.sched_getaffinity(0)), 16)
+        os.environ["OMP_NUM_THREADS"] = str(threads)
+        sample = oracle_sample(specs, masks, nsteps_total, args.cpu_budget)
+        ref, cpu_mlups, cpu_s = run_oracle(specs, masks, sample, nsteps_total)
+        cpu = {"value": round(cpu_mlups, 2), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+               "sample": f"{len(sample)} smallest domains of the workload "
+                         f"({min(specs[i]['n'] for i in sample)}^2..{max(specs[i]['n'] for i in sample)}^2), "
+                         f"{nsteps_total} steps each, FP64, {cpu_s:.1f}s"}
+        log(f"oracle: {cpu_mlups:.2f} MLUPS on {threads} threads, {len(sample)} domains")
+
+    results = {}
+    for v in variants:
+        doms, batch, ms = run_variant(v, specs, masks, args.steps, args.warmup)
+        mlups = sites * args.steps / (ms * 1e-3) / 1e6
+        bytes_alg = algorithmic_bytes(specs, masks, STORAGE_BYTES[v])
+        gbs = bytes_alg * args.steps / (ms * 1e-3) / 1e9
+        entry = {"mlups": round(mlups, 1), "ms_per_step": round(ms / args.steps, 4),
+                 "sweep_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                 "bytes_per_step": bytes_alg, "rounding": ROUNDING[v]}
+        if ref:
+            entry["l2_vs_oracle"] = l2_errors(doms, ref, specs)
+        results[v] = entry
+        log(f"{v}: {json.dumps(entry)}")
+        batch.close()
+        for d in doms:
+            d.close()
+        del doms, batch
+        torch.cuda.empty_cache()
+
+    head = results[variants[0]]
+    achieved = head["sweep_GBps"]
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_entry(head["bytes_per_step"]),
+                "kernel": f"k_sweep ({variants[0]} storage, batched)",
+                "algorithmic_bytes_per_launch": head["bytes_per_step"]}
+    out = {
+        "metric": METRIC, "value": head["mlups"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "precision-and-batching stress: 8192^2 periodic domain + 200 "
+                               "uneven 64^2..2048^2 obstacle domains (20% solid), batched, "
+                               f"{variants[0]}-delta storage",
+                   "sites": sites, "domains": len(specs), "storage": variants[0],
+                   "rounding": ROUNDING[variants[0]], "arithmetic": "f32"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": results,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

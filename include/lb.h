@@ -61,7 +61,8 @@ typedef int32_t lb_status;
 
 /* population storage.  Arithmetic is FP64 for LB_F64 and FP32 otherwise; the
  * stored value is the deviation f_i - w_i rho0 (scaled by 2, 8, 32 for the
- * rest, axis and diagonal directions in the 16-bit formats). */
+ * rest, axis and diagonal directions in the 16-bit formats); see also
+ * LB_COMPUTE_* below. */
 #define LB_F64 0
 #define LB_F32 1
 #define LB_F16_DELTA 2
@@ -69,6 +70,15 @@ typedef int32_t lb_status;
 
 #define LB_ROUND_NEAREST 0
 #define LB_ROUND_STOCHASTIC 1  /* 16-bit storage only */
+
+/* arithmetic of the collision: the storage's own precision (FP64 for LB_F64,
+ * FP32 otherwise), or FP64 with any storage.  FP32 arithmetic keeps mass and
+ * momentum exact by construction, but its rounding still biases flows whose
+ * state changes by a near-constant amount each step (the plug-flow core of a
+ * channel at tau close to 1/2); FP64 arithmetic with FP32 storage removes that
+ * at no memory cost. */
+#define LB_COMPUTE_NATIVE 0
+#define LB_COMPUTE_F64 1
 
 #define LB_INIT_REST 0        /* rho = rho0, u = 0                               */
 #define LB_INIT_FIELDS 1      /* f = equilibrium of init_rho/init_ux/init_uy     */
@@ -79,6 +89,7 @@ typedef struct lb_domain_desc {
   int32_t bc_x, bc_y;         /* LB_PERIODIC | LB_WALL | LB_PRESSURE (x only)   */
   int32_t storage;            /* LB_F64 | LB_F32 | LB_F16_DELTA | LB_BF16_DELTA */
   int32_t rounding;           /* LB_ROUND_NEAREST | LB_ROUND_STOCHASTIC         */
+  int32_t compute;            /* LB_COMPUTE_NATIVE | LB_COMPUTE_F64             */
   int32_t obstacles;          /* nonzero: reserve a label plane for lb_set_obstacles */
   int32_t max_particles;      /* capacity of lb_add_particles, 0..250            */
   int32_t power_law;          /* nonzero: local tau* of Sec. 5                   */
@@ -172,11 +183,16 @@ lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value);
 /* Destroy the handle (the workspace can then be reused).  Synchronises. */
 lb_status lb_destroy_domain(lb_domain *d);
 
-/* Batching: several independent domains with the same storage and features
- * advance together, one sweep launch per step over the tiles of all of them,
- * replayed from a hipGraph.  Every domain keeps its own parameters, noise key
- * and step counter; a batched run is bit-identical to running each domain
- * alone.  The batch workspace is caller-owned device memory. */
+/* Batching: several independent domains advance together, one sweep launch
+ * per step over the tiles of all of them, replayed from a hipGraph.  The
+ * domains must share storage, arithmetic, noise and power-law settings
+ * (LB_EUNSUPPORTED otherwise); sizes, boundaries, obstacles, particles and all
+ * parameters may differ.  Every domain keeps its own noise key and step
+ * counter; a batched run is bit-identical to running each domain alone.  The
+ * domains may not change (obstacles, particles, tile options) while in a
+ * batch (LB_ESTATE).  The batch runs on its own stream: order it against the
+ * domains' streams (e.g. synchronise) when mixing lb_step and lb_batch_step.
+ * The batch workspace is caller-owned device memory. */
 lb_status lb_batch_workspace_bytes(lb_domain *const *domains, int32_t n, size_t *bytes);
 lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_workspace,
                           size_t bytes, void *hip_stream, lb_batch **out);

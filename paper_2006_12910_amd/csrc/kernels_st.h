@@ -13,17 +13,17 @@ namespace {
 
 constexpr int ST = LBK_ST;
 
-template <int FEAT, int PLM>
+template <int FEAT, int PLM, int WIDE>
 void sweep_l(const DevDomain *doms, const int *prefix, int ndom, int kstep, int blocks,
              hipStream_t s) {
-  hipLaunchKernelGGL((k_sweep<ST, FEAT, PLM>), dim3(blocks), dim3(256), 0, s, doms, prefix, ndom,
-                     kstep);
+  hipLaunchKernelGGL((k_sweep<ST, FEAT, PLM, WIDE>), dim3(blocks), dim3(256), 0, s, doms, prefix,
+                     ndom, kstep);
 }
-template <int FEAT, int PLM>
+template <int FEAT, int PLM, int WIDE>
 void init_l(const DevDomain *dom, const double *rho, const double *ux, const double *uy, int row0,
             int nrows, int pitch, hipStream_t s) {
   const long long n = (long long)nrows * pitch;
-  hipLaunchKernelGGL((k_init<ST, FEAT, PLM>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_init<ST, FEAT, PLM, WIDE>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                      dom, rho, ux, uy, row0, nrows);
 }
 void link_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
@@ -53,9 +53,9 @@ void import_l(const DevDomain *dom, const double *in, int row0, int nrows, int n
                      row0, nrows);
 }
 
-template <int FEAT, int PLM> void fill(KernelSet *k) {
-  k->sweep = sweep_l<FEAT, PLM>;
-  k->init = init_l<FEAT, PLM>;
+template <int FEAT, int PLM, int WIDE> void fill(KernelSet *k) {
+  k->sweep = sweep_l<FEAT, PLM, WIDE>;
+  k->init = init_l<FEAT, PLM, WIDE>;
   k->link = link_l;
   k->cover = cover_l;
   k->mass_partial = mass_l;
@@ -64,27 +64,32 @@ template <int FEAT, int PLM> void fill(KernelSet *k) {
   k->import_f = import_l;
 }
 
-template <int BASE> bool pick_power(int feat, int plm, KernelSet *k) {
-  if (!(feat & F_POWER)) { fill<BASE, PL_GENERIC>(k); return true; }
+template <int BASE, int WIDE> bool pick_power(int feat, int plm, KernelSet *k) {
+  if (!(feat & F_POWER)) { fill<BASE, PL_GENERIC, WIDE>(k); return true; }
   switch (plm) {
-    case PL_GENERIC: fill<BASE | F_POWER, PL_GENERIC>(k); return true;
-    case PL_HALF: fill<BASE | F_POWER, PL_HALF>(k); return true;
-    case PL_3Q: fill<BASE | F_POWER, PL_3Q>(k); return true;
-    case PL_3H: fill<BASE | F_POWER, PL_3H>(k); return true;
+    case PL_GENERIC: fill<BASE | F_POWER, PL_GENERIC, WIDE>(k); return true;
+    case PL_HALF: fill<BASE | F_POWER, PL_HALF, WIDE>(k); return true;
+    case PL_3Q: fill<BASE | F_POWER, PL_3Q, WIDE>(k); return true;
+    case PL_3H: fill<BASE | F_POWER, PL_3H, WIDE>(k); return true;
+  }
+  return false;
+}
+
+template <int WIDE> bool pick(int feat, int plm, KernelSet *k) {
+  switch (feat & (F_LABELS | F_NOISE)) {
+    case 0: return pick_power<0, WIDE>(feat, plm, k);
+    case F_LABELS: return pick_power<F_LABELS, WIDE>(feat, plm, k);
+    case F_NOISE: return pick_power<F_NOISE, WIDE>(feat, plm, k);
+    case F_LABELS | F_NOISE: return pick_power<F_LABELS | F_NOISE, WIDE>(feat, plm, k);
   }
   return false;
 }
 
 }  // namespace
 
-bool LBK_GETTER(int feat, int plm, KernelSet *k) {
-  switch (feat & (F_LABELS | F_NOISE)) {
-    case 0: return pick_power<0>(feat, plm, k);
-    case F_LABELS: return pick_power<F_LABELS>(feat, plm, k);
-    case F_NOISE: return pick_power<F_NOISE>(feat, plm, k);
-    case F_LABELS | F_NOISE: return pick_power<F_LABELS | F_NOISE>(feat, plm, k);
-  }
-  return false;
+bool LBK_GETTER(int feat, int plm, int wide, KernelSet *k) {
+  if (ST == ST_F64 || !wide) return pick<0>(feat, plm, k);
+  return pick<1>(feat, plm, k);
 }
 
 }  // namespace lbk

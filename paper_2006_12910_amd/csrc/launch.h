@@ -20,11 +20,12 @@ struct KernelSet {
                    hipStream_t s);
 };
 
-// Kernel set of a storage format / feature set / power-law specialisation.
-bool kernels_f64(int feat, int plm, KernelSet *k);
-bool kernels_f32(int feat, int plm, KernelSet *k);
-bool kernels_f16(int feat, int plm, KernelSet *k);
-bool kernels_bf16(int feat, int plm, KernelSet *k);
+// Kernel set of a storage format / feature set / power-law specialisation /
+// arithmetic width (wide = FP64 arithmetic with any storage).
+bool kernels_f64(int feat, int plm, int wide, KernelSet *k);
+bool kernels_f32(int feat, int plm, int wide, KernelSet *k);
+bool kernels_f16(int feat, int plm, int wide, KernelSet *k);
+bool kernels_bf16(int feat, int plm, int wide, KernelSet *k);
 
 void launch_pupdate(const DevDomain *doms, const PItem *items, int nitems, int kstep,
                     hipStream_t s);

@@ -94,6 +94,8 @@ lb_status validate(const lb_domain_desc *d) {
     return fail(LB_EINVAL, "bad rounding");
   if (d->rounding == LB_ROUND_STOCHASTIC && d->storage < LB_F16_DELTA)
     return fail(LB_EINVAL, "stochastic rounding needs 16-bit storage");
+  if (d->compute != LB_COMPUTE_NATIVE && d->compute != LB_COMPUTE_F64)
+    return fail(LB_EINVAL, "bad compute");
   if (d->max_particles < 0 || d->max_particles > MAX_PARTICLES)
     return fail(LB_EINVAL, "max_particles must be in [0, 250]");
   if (!(d->rho0 > 0.0) || !std::isfinite(d->rho0)) return fail(LB_EINVAL, "rho0 must be > 0");
@@ -132,12 +134,12 @@ int feat_of(const lb_domain_desc *d) {
   return f;
 }
 
-bool get_kernels(int st, int feat, int plm, KernelSet *k) {
+bool get_kernels(int st, int feat, int plm, int wide, KernelSet *k) {
   switch (st) {
-    case LB_F64: return kernels_f64(feat, plm, k);
-    case LB_F32: return kernels_f32(feat, plm, k);
-    case LB_F16_DELTA: return kernels_f16(feat, plm, k);
-    case LB_BF16_DELTA: return kernels_bf16(feat, plm, k);
+    case LB_F64: return kernels_f64(feat, plm, wide, k);
+    case LB_F32: return kernels_f32(feat, plm, wide, k);
+    case LB_F16_DELTA: return kernels_f16(feat, plm, wide, k);
+    case LB_BF16_DELTA: return kernels_bf16(feat, plm, wide, k);
   }
   return false;
 }
@@ -326,7 +328,8 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   const int feat = feat_of(desc);
   const int plm = desc->power_law ? plm_of(desc->n_index) : PL_GENERIC;
   KernelSet ks{};
-  if (!get_kernels(desc->storage, feat, plm, &ks)) return fail(LB_EUNSUPPORTED, "no kernel for this feature set");
+  if (!get_kernels(desc->storage, feat, plm, desc->compute == LB_COMPUTE_F64, &ks))
+    return fail(LB_EUNSUPPORTED, "no kernel for this feature set");
 
   lb_domain *d = new lb_domain();
   d->desc = *desc;
@@ -356,7 +359,7 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   h.bc_x = desc->bc_x;
   h.bc_y = desc->bc_y;
   h.np = 0;
-  set_tiles(h, default_tile_w(desc->nx), 1);
+  set_tiles(h, default_tile_w(desc->nx), desc->storage >= LB_F16_DELTA ? 4 : 2);
   h.key0 = (uint32_t)desc->seed;
   h.key1 = (uint32_t)(desc->seed >> 32) ^ desc->domain_id;
   h.storage = desc->storage;
@@ -749,15 +752,22 @@ lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_worksp
     for (int j = 0; j < i; ++j)
       if (domains[i] == domains[j]) return fail(LB_EINVAL, "a domain appears twice");
     if (domains[i]->desc.storage != domains[0]->desc.storage ||
-        (domains[i]->feat & (F_LABELS | F_NOISE | F_POWER)) != (domains[0]->feat & (F_LABELS | F_NOISE | F_POWER)) ||
+        domains[i]->desc.compute != domains[0]->desc.compute ||
+        (domains[i]->feat & (F_NOISE | F_POWER)) != (domains[0]->feat & (F_NOISE | F_POWER)) ||
         domains[i]->plm != domains[0]->plm)
-      return fail(LB_EUNSUPPORTED, "batched domains must share storage and features");
+      return fail(LB_EUNSUPPORTED, "batched domains must share storage, arithmetic, noise and power law");
   }
+  // label-plane and label-free domains share one launch: take the kernel set
+  // with label support if any domain has a plane (it reads no labels for the
+  // others)
+  int lab_dom = -1;
+  for (int i = 0; i < n; ++i)
+    if (domains[i]->feat & F_LABELS) lab_dom = i;
   lb_batch *b = new lb_batch();
   b->doms.assign(domains, domains + n);
   b->ws = (char *)dev_workspace;
   b->stream = (hipStream_t)hip_stream;
-  b->ks = domains[0]->ks;
+  b->ks = domains[lab_dom >= 0 ? lab_dom : 0]->ks;
   b->off_desc = 0;
   b->off_prefix = align256((size_t)n * sizeof(DevDomain));
   b->off_items = b->off_prefix + align256((size_t)(n + 1) * sizeof(int));

@@ -12,6 +12,8 @@
 // Arithmetic works on deviations d_i = f_i - w_i rho0 and never forms f_i.
 #pragma once
 
+#include <type_traits>
+
 #include "lb_device.h"
 
 namespace lbk {
@@ -98,11 +100,18 @@ __device__ __forceinline__ R powerlaw_tau(const DevDomain &D, const R d[9], R dr
   return tau < tmin ? tmin : (tau > tmax ? tmax : tau);
 }
 
-// BGK collision of one node (deviations in, deviations out), step `step`.
-template <int ST, int FEAT, int PLM>
-__device__ __forceinline__ void collide_node(const DevDomain &D, typename Store<ST>::R d[9],
-                                             uint32_t node, uint32_t step) {
-  using R = typename Store<ST>::R;
+// BGK collision of one node (deviations in, deviations out), step `step`, in
+// arithmetic type R.  The equilibrium of Eq. LB2 with u = j/rho + tau g is
+// evaluated in a form whose mass and momentum do not depend on how the
+// lattice constants round: the linear term is built from J = j + rho tau g
+// with coefficients L1 ~ 1/3, L5 = (1 - 2 L1)/4 (so 2 L1 + 4 L5 = 1 exactly),
+// opposite directions share one even part c and take c +- (linear term), and
+// the rest population is delta_rho minus the other eight.  Algebraically this
+// is Eq. LB2; in FP32 it removes a systematic O(1e-8) momentum error per step
+// that would otherwise bias slowly accelerating flows.
+template <int ST, int FEAT, int PLM, class R>
+__device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_t node,
+                                             uint32_t step) {
   const R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
   const R jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
   const R jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
@@ -116,26 +125,27 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, typename Store<
     tau = par<R>(D.tau, D.tau_f);
     om = par<R>(D.omega, D.omega_f);
   }
-  const R ux = jx * irho + tau * par<R>(D.gx, D.gx_f);
-  const R uy = jy * irho + tau * par<R>(D.gy, D.gy_f);
-  const R A = drho - R(1.5) * rho * (ux * ux + uy * uy);
-  const R w0 = wgt<R>(0), w1 = wgt<R>(1), w5 = wgt<R>(5);
+  const R Jx = jx + rho * tau * par<R>(D.gx, D.gx_f);
+  const R Jy = jy + rho * tau * par<R>(D.gy, D.gy_f);
+  const R ux = Jx * irho, uy = Jy * irho;
+  const R W1 = R(1) / R(9), W5 = R(0.25) * W1;
+  const R L1 = R(1) / R(3), L5 = (R(1) - R(2) * L1) * R(0.25);
+  const R q = R(1.5) * rho * (ux * ux + uy * uy);
+  const R r45 = R(4.5) * rho;
+  const R sp = ux + uy, sm = uy - ux;
+  const R cxx = W1 * (drho + (r45 * ux * ux - q)), cyy = W1 * (drho + (r45 * uy * uy - q));
+  const R cpp = W5 * (drho + (r45 * sp * sp - q)), cmm = W5 * (drho + (r45 * sm * sm - q));
+  const R lx = L1 * Jx, ly = L1 * Jy, lp = L5 * (Jx + Jy), lm = L5 * (Jy - Jx);
   R eq[9];
-  eq[0] = w0 * A;
-  {
-    const R a = R(3) * ux, b = R(3) * uy;
-    const R hx = R(0.5) * a * a, hy = R(0.5) * b * b;
-    eq[1] = w1 * (A + rho * (hx + a));
-    eq[3] = w1 * (A + rho * (hx - a));
-    eq[2] = w1 * (A + rho * (hy + b));
-    eq[4] = w1 * (A + rho * (hy - b));
-    const R p = a + b, m = b - a;
-    const R hp = R(0.5) * p * p, hm = R(0.5) * m * m;
-    eq[5] = w5 * (A + rho * (hp + p));
-    eq[7] = w5 * (A + rho * (hp - p));
-    eq[6] = w5 * (A + rho * (hm + m));
-    eq[8] = w5 * (A + rho * (hm - m));
-  }
+  eq[0] = drho - R(2) * ((cxx + cyy) + (cpp + cmm));
+  eq[1] = cxx + lx;
+  eq[3] = cxx - lx;
+  eq[2] = cyy + ly;
+  eq[4] = cyy - ly;
+  eq[5] = cpp + lp;
+  eq[7] = cpp - lp;
+  eq[6] = cmm + lm;
+  eq[8] = cmm - lm;
 #pragma unroll
   for (int i = 0; i < 9; ++i) d[i] = d[i] + om * (eq[i] - d[i]);
 
@@ -151,30 +161,31 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, typename Store<
     for (int i = 0; i < 9; ++i) {
       const R z = R(basis_poly(3, i)) * t3 + R(basis_poly(4, i)) * t4 + R(basis_poly(5, i)) * t5 +
                   R(basis_poly(6, i)) * t6 + R(basis_poly(7, i)) * t7 + R(basis_poly(8, i)) * t8;
-      d[i] += amp * wgt<R>(i) * z;
+      const R wi = i == 0 ? R(4) * W1 : (i <= 4 ? W1 : W5);  // exact ratios 4 : 1 : 1/4
+      d[i] += amp * wi * z;
     }
   }
 }
 
-template <int ST>
+template <int ST, class R>
 __device__ __forceinline__ void store_node(const DevDomain &D, typename Store<ST>::T *dst,
-                                           size_t plane, uint32_t off,
-                                           const typename Store<ST>::R d[9], uint32_t node,
-                                           uint32_t step) {
+                                           size_t plane, uint32_t off, const R d[9],
+                                           uint32_t node, uint32_t step) {
   using S = Store<ST>;
+  using RS = typename S::R;
   if constexpr (ST == ST_F16 || ST == ST_BF16) {
     if (D.feat & F_STOCH) {
       const uint32_t h = mix32(node * 0x9E3779B1u ^ mix32(step ^ D.key0) ^ D.key1);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const uint32_t r = mix32(h + (uint32_t)i * 0x632BE5ABu) | 1u;
-        S::put(dst + i * plane, off, i, d[i], r);
+        S::put(dst + i * plane, off, i, (RS)d[i], r);
       }
       return;
     }
   }
 #pragma unroll
-  for (int i = 0; i < 9; ++i) S::put(dst + i * plane, off, i, d[i], 0u);
+  for (int i = 0; i < 9; ++i) S::put(dst + i * plane, off, i, (RS)d[i], 0u);
 }
 
 // Moving-wall term 6 rho0 w_d (u_b . e_d) of the pull into (x, y) along d
@@ -191,14 +202,78 @@ __device__ __forceinline__ R moving_wall_term(const DevDomain &D, const PState &
   return R(6.0 * D.rho0 * wgt<double>(dir) * ue);
 }
 
-template <int ST, int FEAT, int PLM>
+// Arithmetic type: FP64 for FP64 storage or when wide arithmetic is chosen,
+// FP32 otherwise.
+template <int ST, int WIDE>
+using CompT = typename std::conditional<ST == ST_F64 || WIDE != 0, double, float>::type;
+
+// Rows a thread loads before it computes: 16-bit storage moves half the bytes
+// per load, so it keeps more rows in flight to cover memory latency.
+template <int ST> constexpr int rows_in_flight() { return ST == ST_F16 || ST == ST_BF16 ? 4 : 2; }
+
+// Pull of one node: for each direction pick the source plane and offset
+// (the neighbour, or the node's own opposite population when the neighbour is
+// solid or across a particle surface), then one unconditional load; the
+// moving-wall term is added only on the rare surface-crossing links.
+template <int ST, int FEAT, class R>
+__device__ __forceinline__ uint32_t pull_node(const DevDomain &D, const typename Store<ST>::T *src,
+                                              size_t plane, int x, int y, uint32_t here,
+                                              uint8_t lx, bool has_lab, const int (&col)[3],
+                                              const bool (&col_out)[3], const bool (&col_wall)[3],
+                                              const PState *P, R (&d)[9]) {
+  using S = Store<ST>;
+  constexpr bool LABELS = (FEAT & F_LABELS) != 0;
+  const int ny = D.ny, pitch = D.pitch;
+  const bool pery = D.bc_y == BC_PERIODIC, wally = D.bc_y == BC_WALL;
+  int row[3];
+  bool row_out[3], row_wall[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int rr = y + 1 - k;  // k = 0 -> y+1 (source of cy = -1), k = 2 -> y-1
+    bool out = false;
+    if (rr < 0) { if (pery) rr += ny; else out = true; }
+    else if (rr >= ny) { if (pery) rr -= ny; else out = true; }
+    row[k] = (out ? y : rr) * pitch;
+    row_out[k] = out;
+    row_wall[k] = wally && (rr == 0 || rr == ny - 1);
+  }
+  uint32_t unknown = 0;
+  d[0] = (R)S::load(src, here, 0);
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const int kc = 1 + cx(i), kr = 1 + cy(i);
+    const bool out = col_out[kc] || row_out[kr];
+    const uint32_t so = (uint32_t)row[kr] + (uint32_t)col[kc];
+    bool own;  // take this node's opposite population
+    uint8_t ls = 0;
+    if (LABELS && has_lab) {
+      ls = out ? (uint8_t)LBL_FLUID : D.label[so];
+      own = ls == LBL_SOLID || ((lx | ls) >= LBL_PART0 && (lx == 0 || ls == 0));
+    } else {
+      own = col_wall[kc] || row_wall[kr];
+    }
+    own = own || out;
+    const typename Store<ST>::T *pp = src + (own ? opp(i) : i) * plane;
+    R v = (R)S::load(pp, own ? here : so, i);
+    if constexpr (LABELS) {
+      if (!out && ls != LBL_SOLID && (lx | ls) >= LBL_PART0 && (lx == 0 || ls == 0))
+        v += moving_wall_term<R>(D, P[(int)(lx | ls) - LBL_PART0], x, y, i);
+    }
+    if (out) unknown |= 1u << i;
+    d[i] = v;
+  }
+  return unknown;
+}
+
+template <int ST, int FEAT, int PLM, int WIDE>
 __global__ __launch_bounds__(256) void k_sweep(const DevDomain *__restrict__ doms,
                                                const int *__restrict__ prefix, int ndom,
                                                int kstep) {
   using S = Store<ST>;
   using T = typename S::T;
-  using R = typename S::R;
+  using R = CompT<ST, WIDE>;
   constexpr bool LABELS = (FEAT & F_LABELS) != 0;
+  constexpr int U = rows_in_flight<ST>();
 
   const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
   const int dix = ndom == 1 ? 0 : find_domain(prefix, ndom, b);
@@ -218,11 +293,11 @@ __global__ __launch_bounds__(256) void k_sweep(const DevDomain *__restrict__ dom
   T *__restrict__ dst = (T *)D.f[(T0 + 1) & 1];
   const size_t plane = (size_t)ny * pitch;
   const PState *P = D.pstate[T0 & 1];
-  const uint8_t *lab = D.label;
-
-  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
-  const bool wallx = D.bc_x == BC_WALL, wally = D.bc_y == BC_WALL;
+  const bool perx = D.bc_x == BC_PERIODIC, wallx = D.bc_x == BC_WALL;
+  const bool wally = D.bc_y == BC_WALL;
   const bool pressx = D.bc_x == BC_PRESSURE;
+  // a batch may mix domains with and without a label plane
+  const bool has_lab = LABELS && D.label != nullptr;
 
   // columns x-1, x, x+1 (index by 1 - cx)
   int col[3];
@@ -239,93 +314,71 @@ __global__ __launch_bounds__(256) void k_sweep(const DevDomain *__restrict__ dom
   }
 
 #pragma unroll 1
-  for (int r = 0; r < npt; ++r) {
-    const int y = ybase + r * rows_pass;
-    if (y >= ny) break;
-    const uint32_t here = (uint32_t)y * pitch + x;
-    uint8_t lx = 0;
-    if constexpr (LABELS) {
-      lx = lab[here];
-      if (lx == LBL_SOLID) continue;
-    } else {
-      if ((wally && (y == 0 || y == ny - 1)) || (wallx && (x == 0 || x == nx - 1))) continue;
-    }
-    int row[3];
-    bool row_out[3], row_wall[3];
+  for (int r0 = 0; r0 < npt; r0 += U) {
+    R d[U][9];
+    uint32_t unk[U];
+    bool act[U];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      int rr = y + 1 - k;  // k = 0 -> y+1 (source of cy = -1), k = 2 -> y-1
-      bool out = false;
-      if (rr < 0) { if (pery) rr += ny; else out = true; }
-      else if (rr >= ny) { if (pery) rr -= ny; else out = true; }
-      row[k] = (out ? y : rr) * pitch;
-      row_out[k] = out;
-      row_wall[k] = wally && (rr == 0 || rr == ny - 1);
+    for (int u = 0; u < U; ++u) {
+      const int y = ybase + (r0 + u) * rows_pass;
+      act[u] = r0 + u < npt && y < ny;
+      unk[u] = 0;
+      if (!act[u]) continue;
+      const uint32_t here = (uint32_t)y * pitch + x;
+      uint8_t lx = 0;
+      if (LABELS && has_lab) {
+        lx = D.label[here];
+        act[u] = lx != LBL_SOLID;
+      } else {
+        act[u] = !((wally && (y == 0 || y == ny - 1)) || (wallx && (x == 0 || x == nx - 1)));
+      }
+      if (!act[u]) continue;
+      unk[u] = pull_node<ST, FEAT, R>(D, src, plane, x, y, here, lx, has_lab, col, col_out,
+                                      col_wall, P, d[u]);
     }
-
-    R d[9];
-    uint32_t unknown = 0;
-    d[0] = S::load(src, here, 0);
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-      const int kc = 1 + cx(i), kr = 1 + cy(i);
-      if (col_out[kc] || row_out[kr]) {
-        unknown |= 1u << i;
-        d[i] = R(0);
-        continue;
+    for (int u = 0; u < U; ++u) {
+      if (!act[u]) continue;
+      const int y = ybase + (r0 + u) * rows_pass;
+      const uint32_t here = (uint32_t)y * pitch + x;
+      if (pressx && unk[u]) {
+        // 2/3 + 2 (1/6) = 1 exactly in the chosen constants
+        const R half = R(0.5), third2 = R(2) / R(3), sixth = (R(1) - third2) * R(0.5);
+        R *e = d[u];
+        if (x == 0) {
+          const R s = e[0] + e[2] + e[4] + R(2) * (e[3] + e[6] + e[7]);
+          const R rux = (par<R>(D.rho_in, D.rho_in_f) - par<R>(D.rho0, D.rho0_f)) - s;
+          e[1] = e[3] + third2 * rux;
+          e[5] = e[7] - half * (e[2] - e[4]) + sixth * rux;
+          e[8] = e[6] + half * (e[2] - e[4]) + sixth * rux;
+        } else {
+          const R s = e[0] + e[2] + e[4] + R(2) * (e[1] + e[5] + e[8]);
+          const R rux = s - (par<R>(D.rho_out, D.rho_out_f) - par<R>(D.rho0, D.rho0_f));
+          e[3] = e[1] - third2 * rux;
+          e[7] = e[5] + half * (e[2] - e[4]) - sixth * rux;
+          e[6] = e[8] - half * (e[2] - e[4]) - sixth * rux;
+        }
       }
-      const uint32_t so = (uint32_t)row[kr] + (uint32_t)col[kc];
-      bool solid;
-      uint8_t ls = 0;
-      if constexpr (LABELS) {
-        ls = lab[so];
-        solid = ls == LBL_SOLID;
-      } else {
-        solid = col_wall[kc] || row_wall[kr];
-      }
-      if (solid) {
-        d[i] = S::load(src + opp(i) * plane, here, opp(i));
-      } else if (LABELS && (lx | ls) >= LBL_PART0 && (lx == 0 || ls == 0)) {
-        const int p = (int)(lx | ls) - LBL_PART0;
-        d[i] = S::load(src + opp(i) * plane, here, opp(i)) + moving_wall_term<R>(D, P[p], x, y, i);
-      } else {
-        d[i] = S::load(src + i * plane, so, i);
-      }
+      const uint32_t node = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
+      collide_node<ST, FEAT, PLM, R>(D, d[u], node, step);
+      const R drho = ((d[u][0] + d[u][1]) + (d[u][2] + d[u][3])) +
+                     ((d[u][4] + d[u][5]) + (d[u][6] + d[u][7])) + d[u][8];
+      if (!(fabs(drho) < R(1e30))) atomicOr(D.health, HEALTH_NONFINITE);
+      store_node<ST, R>(D, dst, plane, here, d[u], node, step);
     }
-    if (pressx && unknown) {
-      const R half = R(0.5), third2 = R(2) / R(3), sixth = R(1) / R(6);
-      if (x == 0) {
-        const R s = d[0] + d[2] + d[4] + R(2) * (d[3] + d[6] + d[7]);
-        const R rux = (par<R>(D.rho_in, D.rho_in_f) - par<R>(D.rho0, D.rho0_f)) - s;
-        d[1] = d[3] + third2 * rux;
-        d[5] = d[7] - half * (d[2] - d[4]) + sixth * rux;
-        d[8] = d[6] + half * (d[2] - d[4]) + sixth * rux;
-      } else {
-        const R s = d[0] + d[2] + d[4] + R(2) * (d[1] + d[5] + d[8]);
-        const R rux = s - (par<R>(D.rho_out, D.rho_out_f) - par<R>(D.rho0, D.rho0_f));
-        d[3] = d[1] - third2 * rux;
-        d[7] = d[5] + half * (d[2] - d[4]) - sixth * rux;
-        d[6] = d[8] - half * (d[2] - d[4]) - sixth * rux;
-      }
-    }
-    const uint32_t node = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
-    collide_node<ST, FEAT, PLM>(D, d, node, step);
-    const R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
-    if (!(fabs(drho) < R(1e30))) atomicOr(D.health, HEALTH_NONFINITE);
-    store_node<ST>(D, dst, plane, here, d, node, step);
   }
 }
 
 // Initial state: equilibrium of the given fields (or rest), then the
 // collision of the current step, written to the buffer of that step.
 // Rows [row0, row0 + nrows); fields are band-local [nrows][nx] FP64.
-template <int ST, int FEAT, int PLM>
+template <int ST, int FEAT, int PLM, int WIDE>
 __global__ __launch_bounds__(256) void k_init(const DevDomain *__restrict__ Dp, const double *rho_f,
                                               const double *ux_f, const double *uy_f, int row0,
                                               int nrows) {
   using S = Store<ST>;
   using T = typename S::T;
-  using R = typename S::R;
+  using R = CompT<ST, WIDE>;
   const DevDomain &D = *Dp;
   const int x = (int)(blockIdx.x * 256 + threadIdx.x) % D.pitch;
   const int yl = (int)(blockIdx.x * 256 + threadIdx.x) / D.pitch;
@@ -351,8 +404,8 @@ __global__ __launch_bounds__(256) void k_init(const DevDomain *__restrict__ Dp, 
     for (int i = 0; i < 9; ++i) d[i] = R(0);
   }
   const uint32_t node = (uint32_t)y * (uint32_t)D.nx + (uint32_t)x;
-  collide_node<ST, FEAT, PLM>(D, d, node, (uint32_t)T0);
-  store_node<ST>(D, dst, plane, here, d, node, (uint32_t)T0);
+  collide_node<ST, FEAT, PLM, R>(D, d, node, (uint32_t)T0);
+  store_node<ST, R>(D, dst, plane, here, d, node, (uint32_t)T0);
 }
 
 }  // namespace lbk

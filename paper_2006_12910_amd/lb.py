@@ -18,6 +18,7 @@ LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ESTATE, LB_EUNSTABLE, LB_EUNSUPPORTED =
 PERIODIC, WALL, PRESSURE = 0, 1, 2
 F64, F32, F16_DELTA, BF16_DELTA = 0, 1, 2, 3
 ROUND_NEAREST, ROUND_STOCHASTIC = 0, 1
+COMPUTE_NATIVE, COMPUTE_F64 = 0, 1
 INIT_REST, INIT_FIELDS = 0, 1
 PARTICLE_FIXED = 1
 OPT_USE_GRAPH, OPT_TILE_WIDTH, OPT_ROWS_PER_THREAD, OPT_GRAPH_CHUNK = 1, 2, 3, 4
@@ -41,7 +42,8 @@ class DomainDesc(C.Structure):
     _fields_ = [
         ("abi_version", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32),
         ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("storage", C.c_int32),
-        ("rounding", C.c_int32), ("obstacles", C.c_int32), ("max_particles", C.c_int32),
+        ("rounding", C.c_int32), ("compute", C.c_int32), ("obstacles", C.c_int32),
+        ("max_particles", C.c_int32),
         ("power_law", C.c_int32), ("init_kind", C.c_int32), ("domain_id", C.c_uint32),
         ("seed", C.c_uint64), ("rho0", C.c_double), ("tau", C.c_double),
         ("gx", C.c_double), ("gy", C.c_double), ("rho_in", C.c_double), ("rho_out", C.c_double),
@@ -138,7 +140,8 @@ class Domain:
     """One lattice domain on the GPU (lb_create_domain ... lb_destroy_domain)."""
 
     def __init__(self, nx, ny, *, tau=1.0, rho0=1.0, g=(0.0, 0.0), bc_x="periodic",
-                 bc_y="periodic", storage="f32", rounding="nearest", rho_in=1.0, rho_out=1.0,
+                 bc_y="periodic", storage="f32", rounding="nearest", compute="native",
+                 rho_in=1.0, rho_out=1.0,
                  kT=0.0, seed=0, domain_id=0, power_law=None, obstacles=None, max_particles=0,
                  lj=(20.0, 2.5, 0.1), init=None, device="cuda", stream=None):
         lib = library()
@@ -148,6 +151,7 @@ class Domain:
         d.bc_x, d.bc_y = _BC[bc_x], _BC[bc_y]
         d.storage = _ST[storage]
         d.rounding = _RND[rounding]
+        d.compute = {"native": COMPUTE_NATIVE, "f64": COMPUTE_F64}[compute]
         d.obstacles = 1 if obstacles is not None else 0
         d.max_particles = int(max_particles)
         d.domain_id = int(domain_id) & 0xFFFFFFFF

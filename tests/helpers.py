@@ -11,13 +11,13 @@ _BC = {"periodic": PERIODIC, "wall": WALL, "pressure": PRESSURE}
 def make_pair(nx, ny, storage="f64", bc_x="periodic", bc_y="periodic", tau=1.0, g=(0.0, 0.0),
               rho0=1.0, rho_in=1.0, rho_out=1.0, kT=0.0, seed=0, domain_id=0, power_law=None,
               obstacles=None, particles=(), init=None, lj=(20.0, 2.5, 0.1), max_particles=None,
-              rounding="nearest"):
+              rounding="nearest", compute="native"):
     """(gpu Domain, Oracle) with identical parameters and inputs."""
     from paper_2006_12910_amd import lb
     plist = list(particles)
     nmax = len(plist) if max_particles is None else max_particles
     gpu = lb.Domain(nx, ny, tau=tau, rho0=rho0, g=g, bc_x=bc_x, bc_y=bc_y, storage=storage,
-                    rounding=rounding, rho_in=rho_in, rho_out=rho_out, kT=kT, seed=seed,
+                    rounding=rounding, compute=compute, rho_in=rho_in, rho_out=rho_out, kT=kT, seed=seed,
                     domain_id=domain_id, power_law=power_law, obstacles=obstacles,
                     max_particles=nmax, lj=lj, init=init)
     pl = power_law or {}

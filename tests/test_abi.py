@@ -46,6 +46,7 @@ def _desc(**kw):
     (dict(max_particles=251), "max_particles"), (dict(kT=-1.0), "kT"),
     (dict(power_law=1, n_index=0.5, K=0.01, tau_min=0.4, tau_max=2.5), "power law"),
     (dict(bc_x=2, rho_in=0.0, rho_out=1.0), "pressure"), (dict(init_kind=1), "INIT_FIELDS"),
+    (dict(compute=2), "compute"),
 ])
 def test_validation_errors(bad, msg):
     from paper_2006_12910_amd import lb

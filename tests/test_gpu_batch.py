@@ -1,0 +1,82 @@
+"""Batching: many uneven domains advanced by one launch per step (captured in a
+hipGraph).  Each domain of a batch must evolve bit-identically to the same
+domain stepped alone (same kernels, same noise keys), and match the oracle."""
+import numpy as np
+import pytest
+
+from helpers import make_pair, velocity_error
+
+pytestmark = pytest.mark.gpu
+
+
+def _stress_domain(lb, spec, storage, rounding="nearest", with_obstacles=True):
+    from paper_2006_12910_amd import inputs
+    n = spec["n"]
+    init = inputs.shear_wave_field(n, n, 0.01, spec["k"], spec["phase"])
+    mask = inputs.stress_obstacles(n, spec["obstacle_seed"]) if with_obstacles else None
+    return lb.Domain(n, n, tau=spec["tau"], storage=storage, rounding=rounding, init=init,
+                     obstacles=mask)
+
+
+@pytest.mark.parametrize("storage,rounding", [("f32", "nearest"), ("f16", "stochastic"),
+                                              ("bf16", "nearest")])
+def test_batch_equals_solo(storage, rounding):
+    from paper_2006_12910_amd import inputs, lb
+    specs = inputs.stress_batch(count=7, seed=3, smin=40, smax=300)
+    solo = [_stress_domain(lb, s, storage, rounding) for s in specs]
+    solo.append(lb.Domain(96, 80, tau=0.7, storage=storage, rounding=rounding,
+                          init=inputs.shear_wave_field(96, 80, 0.01, 1, 0.5)))  # no label plane
+    grouped = [_stress_domain(lb, s, storage, rounding) for s in specs]
+    grouped.append(lb.Domain(96, 80, tau=0.7, storage=storage, rounding=rounding,
+                             init=inputs.shear_wave_field(96, 80, 0.01, 1, 0.5)))
+    batch = lb.Batch(grouped)
+    batch.set_option(lb.OPT_GRAPH_CHUNK, 16)
+    batch.step(37)
+    for d in solo:
+        d.step(37)
+    import torch
+    torch.cuda.synchronize()
+    for a, b in zip(solo, grouped):
+        assert b.time == 37
+        assert np.array_equal(a.populations(), b.populations())
+    batch.close()
+
+
+def test_batch_with_particles_and_noise_matches_oracle():
+    """Fluctuating ensemble: periodic boxes, one Brownian disc each, own
+    domain ids; FP64 storage against the oracle for every member."""
+    from paper_2006_12910_amd import inputs, lb
+    pairs = []
+    for spec in inputs.fluctuating_batch(count=4, smin=40, smax=90):
+        n = spec["n"]
+        cx, cy, r = spec["disc"]
+        pairs.append(make_pair(n, n, tau=1.0, kT=1e-4, seed=77, domain_id=spec["domain_id"],
+                               particles=[dict(x=cx, y=cy, radius=r)]))
+    batch = lb.Batch([g for g, _ in pairs])
+    batch.step(60)
+    import torch
+    torch.cuda.synchronize()
+    for g, o in pairs:
+        o.run(60)
+        drho, err = velocity_error(g, o)
+        assert drho < 1e-12 and err < 1e-10, (drho, err)
+        assert np.abs(g.particles()[0][:7] - o.particles()[0][:7]).max() < 1e-12
+    batch.close()
+
+
+def test_batch_rejects_mixed_arithmetic_and_duplicates():
+    from paper_2006_12910_amd import lb
+    a = lb.Domain(32, 32, storage="f32")
+    b = lb.Domain(32, 32, storage="f16")
+    with pytest.raises(lb.LBError) as e:
+        lb.Batch([a, b])
+    assert e.value.status == lb.LB_EUNSUPPORTED
+    with pytest.raises(lb.LBError) as e:
+        lb.Batch([a, a])
+    assert e.value.status == lb.LB_EINVAL
+    batch = lb.Batch([a])
+    with pytest.raises(lb.LBError) as e:
+        a.set_option(lb.OPT_TILE_WIDTH, 64)
+    assert e.value.status == lb.LB_ESTATE
+    batch.close()
+    a.set_option(lb.OPT_TILE_WIDTH, 64)
