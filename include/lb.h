@@ -142,8 +142,9 @@ lb_status lb_set_obstacles(lb_domain *d, const uint8_t *host_mask, size_t n);
 
 /* Add n circular particles (Sec. 3).  *first_id receives the index of the
  * first one.  LB_EINVAL if a disc covers a solid node or another particle,
- * exceeds max_particles, or its bounding box (radius + lj_rit + 3 nodes each
- * side) does not fit in a periodic axis; LB_ESTATE if the domain is in a batch. */
+ * exceeds max_particles, or its bounding box (max(radius + lj_rit + 1,
+ * radius + 3) nodes each side) does not fit in a periodic axis or reaches a
+ * pressure face; LB_ESTATE if the domain is in a batch. */
 lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_t *first_id);
 
 /* Enqueue nsteps full time steps (collision, noise, streaming, boundaries,

@@ -89,6 +89,30 @@ __global__ __launch_bounds__(256) void k_moments(const DevDomain *__restrict__ D
   uy_o[n] = jy / rho - 0.5 * D.gy;
 }
 
+// Mirror slots of the current buffer: for every fluid node x and solid source
+// s = x - e_i, slot i of s holds x's own opposite population (what the pull
+// along i bounces back), copied bit for bit.
+template <int ST>
+__global__ __launch_bounds__(256) void k_mirror(const DevDomain *__restrict__ Dp) {
+  using T = typename Store<ST>::T;
+  const DevDomain &D = *Dp;
+  const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (n >= (long long)D.ny * D.nx) return;
+  const int y = (int)(n / D.nx), x = (int)(n - (long long)y * D.nx);
+  const size_t here = (size_t)y * D.pitch + x;
+  const uint16_t w = D.nodew[here];
+  if ((w & NODE_SOLID) || !(w & 0xffu)) return;
+  T *f = (T *)D.f[*D.tstep & 1];
+  const size_t plane = (size_t)D.ny * D.pitch;
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  for (int i = 1; i < 9; ++i) {
+    if (!((w >> (i - 1)) & 1u)) continue;
+    int sx, sy;
+    if (!source_of(D.nx, D.ny, perx, pery, x, y, i, sx, sy)) continue;
+    f[i * plane + (size_t)sy * D.pitch + sx] = f[opp(i) * plane + here];
+  }
+}
+
 // Export / import of the stored deviations as FP64, band layout [9][nrows][nx].
 template <int ST>
 __global__ __launch_bounds__(256) void k_export(const DevDomain *__restrict__ Dp, double *out,
@@ -103,8 +127,9 @@ __global__ __launch_bounds__(256) void k_export(const DevDomain *__restrict__ Dp
   const T *src = (const T *)D.f[T0 & 1];
   const size_t plane = (size_t)D.ny * D.pitch;
   const uint32_t here = (uint32_t)(row0 + yl) * D.pitch + x;
+  const bool solid = node_is_solid(D, x, row0 + yl);  // never written by the sweep
   for (int i = 0; i < 9; ++i)
-    out[(size_t)i * nrows * D.nx + n] = (double)S::load(src + i * plane, here, i);
+    out[(size_t)i * nrows * D.nx + n] = solid ? 0.0 : (double)S::load(src + i * plane, here, i);
 }
 
 template <int ST>
@@ -126,6 +151,17 @@ __global__ __launch_bounds__(256) void k_import(const DevDomain *__restrict__ Dp
 }
 
 #ifdef LBK_COMMON_KERNELS
+// Static node words of every node (after the label plane is written).
+__global__ __launch_bounds__(256) void k_masks_full(const DevDomain *__restrict__ Dp) {
+  const DevDomain &D = *Dp;
+  const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (n >= (long long)D.ny * D.nx) return;
+  const int y = (int)(n / D.nx), x = (int)(n - (long long)y * D.nx);
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  const size_t here = (size_t)y * D.pitch + x;
+  D.nodew[here] = node_word(D.label, D.nx, D.ny, D.pitch, perx, pery, x, y);
+}
+
 __global__ __launch_bounds__(256) void k_normals(uint32_t k0, uint32_t k1, uint32_t step,
                                                  uint32_t node0, uint32_t count, float *out) {
   const uint32_t n = blockIdx.x * 256 + threadIdx.x;

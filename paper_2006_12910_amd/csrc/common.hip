@@ -16,6 +16,10 @@ void launch_relabel(const DevDomain *doms, const PItem *items, int nitems, int k
                     int time_offset, hipStream_t s) {
   hipLaunchKernelGGL(k_relabel, dim3(nitems), dim3(256), 0, s, doms, items, kstep, time_offset);
 }
+void launch_masks_full(const DevDomain *dom, int nx, int ny, hipStream_t s) {
+  const long long n = (long long)nx * ny;
+  hipLaunchKernelGGL(k_masks_full, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dom);
+}
 void launch_mass_final(const DevDomain *dom, const double *partials, int n, double *out,
                        hipStream_t s) {
   hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(64), 0, s, dom, partials, n, out);

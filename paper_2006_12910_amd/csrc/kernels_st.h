@@ -29,6 +29,9 @@ void init_l(const DevDomain *dom, const double *rho, const double *ux, const dou
 void link_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
   hipLaunchKernelGGL((k_link<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
 }
+void swap_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
+  hipLaunchKernelGGL((k_link_swap<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
+}
 void cover_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
   hipLaunchKernelGGL((k_cover<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
 }
@@ -53,15 +56,22 @@ void import_l(const DevDomain *dom, const double *in, int row0, int nrows, int n
                      row0, nrows);
 }
 
+void mirror_l(const DevDomain *dom, int nx, int ny, hipStream_t s) {
+  const long long n = (long long)nx * ny;
+  hipLaunchKernelGGL((k_mirror<ST>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dom);
+}
+
 template <int FEAT, int PLM, int WIDE> void fill(KernelSet *k) {
   k->sweep = sweep_l<FEAT, PLM, WIDE>;
   k->init = init_l<FEAT, PLM, WIDE>;
   k->link = link_l;
   k->cover = cover_l;
+  k->swap = swap_l;
   k->mass_partial = mass_l;
   k->moments = moments_l;
   k->export_f = export_l;
   k->import_f = import_l;
+  k->mirror = mirror_l;
 }
 
 template <int BASE, int WIDE> bool pick_power(int feat, int plm, KernelSet *k) {

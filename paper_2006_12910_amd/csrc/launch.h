@@ -12,12 +12,14 @@ struct KernelSet {
                int row0, int nrows, int pitch, hipStream_t s);
   void (*link)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
   void (*cover)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
+  void (*swap)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
   void (*mass_partial)(const DevDomain *dom, double *partials, int blocks, hipStream_t s);
   void (*moments)(const DevDomain *dom, double *rho, double *ux, double *uy, int row0, int nrows,
                   int nx, hipStream_t s);
   void (*export_f)(const DevDomain *dom, double *out, int row0, int nrows, int nx, hipStream_t s);
   void (*import_f)(const DevDomain *dom, const double *in, int row0, int nrows, int nx,
                    hipStream_t s);
+  void (*mirror)(const DevDomain *dom, int nx, int ny, hipStream_t s);
 };
 
 // Kernel set of a storage format / feature set / power-law specialisation /
@@ -31,6 +33,7 @@ void launch_pupdate(const DevDomain *doms, const PItem *items, int nitems, int k
                     hipStream_t s);
 void launch_relabel(const DevDomain *doms, const PItem *items, int nitems, int kstep,
                     int time_offset, hipStream_t s);
+void launch_masks_full(const DevDomain *dom, int nx, int ny, hipStream_t s);
 void launch_mass_final(const DevDomain *dom, const double *partials, int n, double *out,
                        hipStream_t s);
 void launch_normals(uint32_t k0, uint32_t k1, uint32_t step, uint32_t node0, uint32_t count,

@@ -41,7 +41,8 @@ constexpr size_t STAGE_TARGET = size_t(16) << 20;  // bytes of the host-transfer
 
 struct Layout {
   int pitch = 0, band_rows = 0;
-  size_t desc = 0, hdr = 0, f0 = 0, f1 = 0, label = 0, ps0 = 0, ps1 = 0, pforce = 0, items = 0,
+  size_t desc = 0, hdr = 0, f0 = 0, f1 = 0, label = 0, nodew = 0, ps0 = 0, ps1 = 0, pforce = 0,
+         items = 0,
          partials = 0, stage = 0, prefix = 0, total = 0;
 };
 
@@ -68,6 +69,7 @@ Layout layout_of(const lb_domain_desc *d) {
   L.f0 = o; o += align256(fbytes);
   L.f1 = o; o += align256(fbytes);
   L.label = o; if (needs_labels(d)) o += align256(plane);
+  L.nodew = o; if (needs_labels(d)) o += align256(plane * sizeof(uint16_t));
   const size_t np = (size_t)std::max(d->max_particles, 0);
   L.ps0 = o; o += align256(np * sizeof(PState));
   L.ps1 = o; o += align256(np * sizeof(PState));
@@ -235,6 +237,7 @@ void record_steps(const KernelSet &ks, const DevDomain *doms, const int *prefix,
     if (nitems > 0) {
       ks.link(doms, items, nitems, k, s);
       launch_pupdate(doms, items, nitems, k, s);
+      ks.swap(doms, items, nitems, k, s);
     }
     ks.sweep(doms, prefix, ndom, k, blocks, s);
     if (nitems > 0) {
@@ -282,11 +285,22 @@ lb_status domain_mass_enqueue(lb_domain *d) {
   return LB_OK;
 }
 
+// Mirror slots of stationary solids in the current population buffer.
+lb_status refresh_mirrors(lb_domain *d) {
+  if (!d->hd.label) return LB_OK;
+  d->ks.mirror(d->ddesc(), d->desc.nx, d->desc.ny, d->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(d->stream));
+  return LB_OK;
+}
+
 lb_status upload_labels(lb_domain *d) {
   HIPCHK(hipMemcpyAsync(d->ws + d->L.label, d->host_labels.data(), d->host_labels.size(),
                         hipMemcpyHostToDevice, d->stream));
+  launch_masks_full(d->ddesc(), d->desc.nx, d->desc.ny, d->stream);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(d->stream));
-  return LB_OK;
+  return refresh_mirrors(d);
 }
 
 }  // namespace
@@ -348,6 +362,7 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   h.f[0] = d->ws + L.f0;
   h.f[1] = d->ws + L.f1;
   h.label = needs_labels(desc) ? (uint8_t *)(d->ws + L.label) : nullptr;
+  h.nodew = needs_labels(desc) ? (uint16_t *)(d->ws + L.nodew) : nullptr;
   h.tstep = &d->dhdr()->tstep;
   h.health = &d->dhdr()->health;
   h.pstate[0] = (PState *)(d->ws + L.ps0);
@@ -430,6 +445,7 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   }
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(d->stream) != hipSuccess)
     return bail(fail(LB_EHIP, "initialisation failed"));
+  if ((s = refresh_mirrors(d)) != LB_OK) return bail(s);
   *out = d;
   return LB_OK;
 }
@@ -473,6 +489,7 @@ lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_
     if (!(q.radius > 0.0) || !(q.density_ratio > 0.0) || !std::isfinite(q.x) || !std::isfinite(q.y) ||
         q.x < 0.0 || q.y < 0.0 || q.x >= nx || q.y >= ny)
       return fail(LB_EINVAL, "particle outside the domain or bad radius/density");
+    // widest per-particle box of the kernels: link/repulsion scan, relabelling
     const int reach = std::max((int)std::ceil(q.radius + d->desc.lj_rit) + 1, (int)std::ceil(q.radius) + 3);
     const int W = 2 * reach + 2;
     if ((perx && W > nx) || (pery && W > ny)) return fail(LB_EINVAL, "particle box wider than a periodic axis");
@@ -637,7 +654,7 @@ lb_status lb_set_populations(lb_domain *d, const double *hf) {
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(d->stream));
   }
-  return LB_OK;
+  return refresh_mirrors(d);
 }
 
 lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {

@@ -81,6 +81,8 @@ struct PForce {
 struct alignas(256) DevDomain {
   void *f[2];          // population buffers (deviations), [9][ny][pitch]
   uint8_t *label;      // [ny][pitch] or null
+  uint16_t *nodew;     // [ny][pitch] with the label plane, static: bit 8 = node
+                       // is solid, bit i-1 = the source x - e_i is solid
   uint64_t *tstep;     // completed steps
   uint32_t *health;    // latched error bits
   PState *pstate[2];
@@ -109,19 +111,29 @@ struct PItem {
 constexpr uint32_t HEALTH_NONFINITE = 1u, HEALTH_FAST_PARTICLE = 2u, HEALTH_LINK_OVERFLOW = 4u;
 
 // ---------------------------------------------------------------------------
+// Global-address-space views of device pointers: pointers read from the
+// descriptor are generic to the compiler, which would otherwise emit flat
+// memory instructions.
+#define LBK_GLOBAL __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ const LBK_GLOBAL T *gbl(const T *p) {
+  return (const LBK_GLOBAL T *)p;
+}
+template <class T> __device__ __forceinline__ LBK_GLOBAL T *gbl(T *p) { return (LBK_GLOBAL T *)p; }
+
+// ---------------------------------------------------------------------------
 // Storage formats.  Value held = (f_i - w_i rho0) * scale.
 template <int ST> struct Store;
 template <> struct Store<ST_F64> {
   using T = double;
   using R = double;
-  static __device__ __forceinline__ R load(const T *p, size_t o, int) { return p[o]; }
-  static __device__ __forceinline__ void put(T *p, size_t o, int, R v, uint32_t) { p[o] = v; }
+  static __device__ __forceinline__ R load(const T *p, size_t o, int) { return gbl(p)[o]; }
+  static __device__ __forceinline__ void put(T *p, size_t o, int, R v, uint32_t) { gbl(p)[o] = v; }
 };
 template <> struct Store<ST_F32> {
   using T = float;
   using R = float;
-  static __device__ __forceinline__ R load(const T *p, size_t o, int) { return p[o]; }
-  static __device__ __forceinline__ void put(T *p, size_t o, int, R v, uint32_t) { p[o] = v; }
+  static __device__ __forceinline__ R load(const T *p, size_t o, int) { return gbl(p)[o]; }
+  static __device__ __forceinline__ void put(T *p, size_t o, int, R v, uint32_t) { gbl(p)[o] = v; }
 };
 
 __device__ __forceinline__ uint16_t f32_to_bf16_rn(float v) {
@@ -131,14 +143,6 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rn(float v) {
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// Stochastic rounding to bf16: add 16 random bits below the kept mantissa
-// and truncate (magnitude arithmetic on the sign-magnitude encoding).
-__device__ __forceinline__ uint16_t f32_to_bf16_sr(float v, uint32_t r) {
-  uint32_t b = __float_as_uint(v);
-  b += (r & 0xffffu);
-  return (uint16_t)(b >> 16);
-}
-
 __device__ __forceinline__ uint16_t f32_to_f16_rn(float v) {
   _Float16 h = (_Float16)v;
   return __builtin_bit_cast(uint16_t, h);
@@ -146,42 +150,49 @@ __device__ __forceinline__ uint16_t f32_to_f16_rn(float v) {
 __device__ __forceinline__ float f16_to_f32(uint16_t h) {
   return (float)__builtin_bit_cast(_Float16, h);
 }
-// Stochastic rounding to fp16: the two neighbours of v in fp16 are found from
-// the round-to-nearest result, and the upper one is taken with probability
-// equal to v's fractional position between them (exact for subnormals too).
+// Stochastic rounding with the CDNA4 conversion instructions
+// (v_cvt_sr_f16_f32 / v_cvt_sr_bf16_f32): v rounds to the upper of its two
+// neighbours with probability equal to its fractional position between them,
+// drawing the comparison from the high bits of r.
+typedef _Float16 lbk_half2 __attribute__((ext_vector_type(2)));
+typedef __bf16 lbk_bf16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint16_t f32_to_f16_sr(float v, uint32_t r) {
-  uint16_t h = f32_to_f16_rn(v);
-  float hv = f16_to_f32(h);
-  float av = fabsf(v), ah = fabsf(hv);
-  uint16_t lo = h, hi = h;
-  if (ah > av) lo = (uint16_t)(h - 1); else hi = (uint16_t)(h + 1);
-  if (av == ah) return h;
-  float l = fabsf(f16_to_f32(lo)), u = fabsf(f16_to_f32(hi));
-  float frac = (av - l) / (u - l);
-  float rnd = (float)(r >> 8) * (1.0f / 16777216.0f);
-  return rnd < frac ? hi : lo;
+  lbk_half2 o = {(_Float16)0, (_Float16)0};
+  o = __builtin_amdgcn_cvt_sr_f16_f32(o, v, r, false);
+  return __builtin_bit_cast(uint16_t, o[0]);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16_sr(float v, uint32_t r) {
+  lbk_bf16x2 o = {(__bf16)0.0f, (__bf16)0.0f};
+  o = __builtin_amdgcn_cvt_sr_bf16_f32(o, v, r, false);
+  return __builtin_bit_cast(uint16_t, o[0]);
 }
 
 template <> struct Store<ST_F16> {
   using T = uint16_t;
   using R = float;
   static __device__ __forceinline__ R load(const T *p, size_t o, int i) {
-    return f16_to_f32(p[o]) * (1.0f / dscale(i));
+    return f16_to_f32(gbl(p)[o]) * (1.0f / dscale(i));
   }
   static __device__ __forceinline__ void put(T *p, size_t o, int i, R v, uint32_t rbits) {
-    p[o] = rbits ? f32_to_f16_sr(v * dscale(i), rbits) : f32_to_f16_rn(v * dscale(i));
+    gbl(p)[o] = rbits ? f32_to_f16_sr(v * dscale(i), rbits) : f32_to_f16_rn(v * dscale(i));
   }
 };
 template <> struct Store<ST_BF16> {
   using T = uint16_t;
   using R = float;
   static __device__ __forceinline__ R load(const T *p, size_t o, int i) {
-    return bf16_to_f32(p[o]) * (1.0f / dscale(i));
+    return bf16_to_f32(gbl(p)[o]) * (1.0f / dscale(i));
   }
   static __device__ __forceinline__ void put(T *p, size_t o, int i, R v, uint32_t rbits) {
-    p[o] = rbits ? f32_to_bf16_sr(v * dscale(i), rbits) : f32_to_bf16_rn(v * dscale(i));
+    gbl(p)[o] = rbits ? f32_to_bf16_sr(v * dscale(i), rbits) : f32_to_bf16_rn(v * dscale(i));
   }
 };
+
+// Random bits of direction i at a node with hash h: a multiplicative hash,
+// whose high bits (those the rounding instructions use) are well mixed.
+__device__ __forceinline__ uint32_t sr_bits(uint32_t h, int i) {
+  return (h + (uint32_t)(i + 1) * 0x9E3779B9u) * 0x85EBCA6Bu;
+}
 
 // 32-bit integer hash (Wellons' "lowbias32" mixer) for stochastic-rounding bits.
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
@@ -300,6 +311,33 @@ __device__ __forceinline__ void noise_normals(uint32_t k0, uint32_t k1, uint32_t
   noise_pair(w[0] >> 11, w[1] >> 11, th[0], th[1]);
   noise_pair(w[2] >> 11, w[3] >> 11, th[2], th[3]);
   noise_pair(b0, b1, th[4], th[5]);
+}
+
+constexpr uint16_t NODE_SOLID = 0x100;
+
+__device__ __forceinline__ bool source_of(int nx, int ny, bool perx, bool pery, int x, int y, int i,
+                                          int &sx, int &sy) {
+  sx = x - cx(i);
+  sy = y - cy(i);
+  if (sx < 0 || sx >= nx) { if (!perx) return false; sx = sx < 0 ? sx + nx : sx - nx; }
+  if (sy < 0 || sy >= ny) { if (!pery) return false; sy = sy < 0 ? sy + ny : sy - ny; }
+  return true;
+}
+
+// Static node word from the label plane: NODE_SOLID for a solid node, else bit
+// i-1 set when the source x - e_i of the pull along i is solid.  Sources
+// outside a non-periodic edge are left clear (pressure faces reconstruct them).
+__device__ __forceinline__ uint16_t node_word(const uint8_t *lab, int nx, int ny, int pitch,
+                                              bool perx, bool pery, int x, int y) {
+  if (lab[(size_t)y * pitch + x] == LBL_SOLID) return NODE_SOLID;
+  uint16_t m = 0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    int sx, sy;
+    if (!source_of(nx, ny, perx, pery, x, y, i, sx, sy)) continue;
+    if (lab[(size_t)sy * pitch + sx] == LBL_SOLID) m |= (uint16_t)(1u << (i - 1));
+  }
+  return m;
 }
 
 // ---------------------------------------------------------------------------

@@ -10,6 +10,8 @@
 //                 (Eq. MP2).
 //   k_pupdate     one lane per particle: particle-particle repulsion and the
 //                 Newton-Euler update of Eqs. MP5-MP6 into P(T+1).
+//   k_link_swap   moving-wall bounce-back written into the crossing links'
+//                 pull slots, so the sweep pulls unconditionally.
 //   k_cover       after the sweep: covered/uncovered-node force (Eq. MP3) of
 //                 the nodes whose label changes from G(T) to G(T+1).
 //   k_relabel     write G(T+1).
@@ -180,6 +182,55 @@ __global__ __launch_bounds__(256) void k_link(const DevDomain *__restrict__ doms
   }
 }
 
+// Moving-wall bounce-back as a pre-pass (Eqs. MP7-MP8).  For every link
+// between an exterior fluid node x and an interior node s = x - e_d of particle
+// p, the pull into x along d and the pull into s along -e_d both bounce off the
+// surface point r_b = x - e_d/2 moving at u_b = U + Omega z x (r_b - r_c):
+//   f_d(x)  <- f*_{-d}(x) + M,   f_{-d}(s) <- f*_d(s) - M,   M = 6 rho0 w_d (u_b . e_d).
+// The slots those two pulls read -- (d, s) and (-d, x) -- are read by no other
+// pull, so writing the bounced values into them in place lets the sweep pull
+// every direction unconditionally.  Each link is handled once, by the particle
+// that contains s; runs after k_link has read the unmodified f*.
+template <int ST>
+__global__ __launch_bounds__(256) void k_link_swap(const DevDomain *__restrict__ doms,
+                                                   const PItem *__restrict__ items, int kstep) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using RS = typename S::R;
+  const PItem it = items[blockIdx.x];
+  const DevDomain &D = doms[it.dom];
+  const uint64_t T0 = *D.tstep + (uint64_t)kstep;
+  const PState P = D.pstate[T0 & 1][it.p];
+  T *f = (T *)D.f[T0 & 1];
+  const size_t plane = (size_t)D.ny * D.pitch;
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  const uint8_t mine = (uint8_t)(LBL_PART0 + it.p);
+  const int reach = (int)ceil(P.radius) + 2;
+  const int W = 2 * reach + 2;
+  const int bx0 = (int)floor(P.x) - reach, by0 = (int)floor(P.y) - reach;
+  for (int j = threadIdx.x; j < W * W; j += 256) {
+    int x = bx0 + j % W, y = by0 + j / W;
+    if (!wrap_coord(x, D.nx, perx) || !wrap_coord(y, D.ny, pery)) continue;
+    const uint32_t here = (uint32_t)y * D.pitch + x;
+    if (D.label[here] != LBL_FLUID) continue;
+    for (int d = 1; d < 9; ++d) {
+      int sx = x - cx(d), sy = y - cy(d);
+      if (!wrap_coord(sx, D.nx, perx) || !wrap_coord(sy, D.ny, pery)) continue;
+      const uint32_t so = (uint32_t)sy * D.pitch + sx;
+      if (D.label[so] != mine) continue;
+      const double bxr = x - 0.5 * cx(d), byr = y - 0.5 * cy(d);
+      const double rx = min_image(bxr - P.x, D.nx, perx), ry = min_image(byr - P.y, D.ny, pery);
+      const double ue = (P.ux - P.omega * ry) * cx(d) + (P.uy + P.omega * rx) * cy(d);
+      const double M = 6.0 * D.rho0 * wgt<double>(d) * ue;
+      const int o = opp(d);
+      const double a = (double)S::load(f + o * plane, here, o);
+      const double b = (double)S::load(f + d * plane, so, d);
+      S::put(f + d * plane, so, d, (RS)(a + M), 0u);
+      S::put(f + o * plane, here, o, (RS)(b - M), 0u);
+    }
+  }
+}
+
 #ifdef LBK_COMMON_KERNELS
 __global__ void k_pupdate(const DevDomain *__restrict__ doms, const PItem *__restrict__ items,
                           int nitems, int kstep) {
@@ -323,6 +374,7 @@ __global__ __launch_bounds__(256) void k_relabel(const DevDomain *__restrict__ d
     if (l1 != l0) D.label[here] = l1;
   }
 }
+
 #endif  // LBK_COMMON_KERNELS
 
 }  // namespace lbk

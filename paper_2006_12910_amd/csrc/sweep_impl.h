@@ -177,10 +177,7 @@ __device__ __forceinline__ void store_node(const DevDomain &D, typename Store<ST
     if (D.feat & F_STOCH) {
       const uint32_t h = mix32(node * 0x9E3779B1u ^ mix32(step ^ D.key0) ^ D.key1);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const uint32_t r = mix32(h + (uint32_t)i * 0x632BE5ABu) | 1u;
-        S::put(dst + i * plane, off, i, (RS)d[i], r);
-      }
+      for (int i = 0; i < 9; ++i) S::put(dst + i * plane, off, i, (RS)d[i], sr_bits(h, i) | 1u);
       return;
     }
   }
@@ -188,18 +185,20 @@ __device__ __forceinline__ void store_node(const DevDomain &D, typename Store<ST
   for (int i = 0; i < 9; ++i) S::put(dst + i * plane, off, i, (RS)d[i], 0u);
 }
 
-// Moving-wall term 6 rho0 w_d (u_b . e_d) of the pull into (x, y) along d
-// crossing the surface of particle p, with u_b = U + Omega z x (r_b - r_c)
-// at the link midpoint r_b = x - e_d / 2 (Eqs. MP7-MP8).
-template <class R>
-__device__ __forceinline__ R moving_wall_term(const DevDomain &D, const PState &P, int x, int y,
-                                              int dir) {
-  const double bx = (double)x - 0.5 * cx(dir), by = (double)y - 0.5 * cy(dir);
-  const double rx = min_image(bx - P.x, (double)D.nx, D.bc_x == BC_PERIODIC);
-  const double ry = min_image(by - P.y, (double)D.ny, D.bc_y == BC_PERIODIC);
-  const double vx = P.ux - P.omega * ry, vy = P.uy + P.omega * rx;
-  const double ue = vx * cx(dir) + vy * cy(dir);
-  return R(6.0 * D.rho0 * wgt<double>(dir) * ue);
+// One mirrored value, rounded like the node's own slot of the same direction.
+template <int ST, class R>
+__device__ __forceinline__ void store_one(const DevDomain &D, typename Store<ST>::T *p, uint32_t off,
+                                          int dir, R v, uint32_t node, uint32_t step) {
+  using S = Store<ST>;
+  using RS = typename S::R;
+  if constexpr (ST == ST_F16 || ST == ST_BF16) {
+    if (D.feat & F_STOCH) {
+      const uint32_t h = mix32(node * 0x9E3779B1u ^ mix32(step ^ D.key0) ^ D.key1);
+      S::put(p, off, dir, (RS)v, sr_bits(h, opp(dir)) | 1u);
+      return;
+    }
+  }
+  S::put(p, off, dir, (RS)v, 0u);
 }
 
 // Arithmetic type: FP64 for FP64 storage or when wide arithmetic is chosen,
@@ -211,18 +210,19 @@ using CompT = typename std::conditional<ST == ST_F64 || WIDE != 0, double, float
 // per load, so it keeps more rows in flight to cover memory latency.
 template <int ST> constexpr int rows_in_flight() { return ST == ST_F16 || ST == ST_BF16 ? 4 : 2; }
 
-// Pull of one node: for each direction pick the source plane and offset
-// (the neighbour, or the node's own opposite population when the neighbour is
-// solid or across a particle surface), then one unconditional load; the
-// moving-wall term is added only on the rare surface-crossing links.
+// Pull of one node.  Every direction loads the neighbour's slot at x - e_i:
+// where that neighbour is solid, its slot holds this node's own opposite
+// population, written there by the previous step's store (halfway
+// bounce-back by mirror writes); where the pull crosses a particle surface,
+// the slot holds the moving-wall bounced value, put there by the particle
+// pre-pass (k_link_swap).  So the loads have no data-dependent address.
+// Index walls of label-free domains select the node's own slot directly.
 template <int ST, int FEAT, class R>
 __device__ __forceinline__ uint32_t pull_node(const DevDomain &D, const typename Store<ST>::T *src,
-                                              size_t plane, int x, int y, uint32_t here,
-                                              uint8_t lx, bool has_lab, const int (&col)[3],
-                                              const bool (&col_out)[3], const bool (&col_wall)[3],
-                                              const PState *P, R (&d)[9]) {
+                                              size_t plane, int y, uint32_t here, bool has_lab,
+                                              const int (&col)[3], const bool (&col_out)[3],
+                                              const bool (&col_wall)[3], R (&d)[9]) {
   using S = Store<ST>;
-  constexpr bool LABELS = (FEAT & F_LABELS) != 0;
   const int ny = D.ny, pitch = D.pitch;
   const bool pery = D.bc_y == BC_PERIODIC, wally = D.bc_y == BC_WALL;
   int row[3];
@@ -244,29 +244,22 @@ __device__ __forceinline__ uint32_t pull_node(const DevDomain &D, const typename
     const int kc = 1 + cx(i), kr = 1 + cy(i);
     const bool out = col_out[kc] || row_out[kr];
     const uint32_t so = (uint32_t)row[kr] + (uint32_t)col[kc];
-    bool own;  // take this node's opposite population
-    uint8_t ls = 0;
-    if (LABELS && has_lab) {
-      ls = out ? (uint8_t)LBL_FLUID : D.label[so];
-      own = ls == LBL_SOLID || ((lx | ls) >= LBL_PART0 && (lx == 0 || ls == 0));
-    } else {
-      own = col_wall[kc] || row_wall[kr];
-    }
-    own = own || out;
-    const typename Store<ST>::T *pp = src + (own ? opp(i) : i) * plane;
-    R v = (R)S::load(pp, own ? here : so, i);
-    if constexpr (LABELS) {
-      if (!out && ls != LBL_SOLID && (lx | ls) >= LBL_PART0 && (lx == 0 || ls == 0))
-        v += moving_wall_term<R>(D, P[(int)(lx | ls) - LBL_PART0], x, y, i);
-    }
+    const bool own = out || (!has_lab && (col_wall[kc] || row_wall[kr]));
+    d[i] = (R)S::load(src + (own ? opp(i) : i) * plane, own ? here : so, i);
     if (out) unknown |= 1u << i;
-    d[i] = v;
   }
   return unknown;
 }
 
+// 256 threads.  The plain and obstacle variants are held to at least 5 waves
+// per SIMD (enough loads in flight to cover memory latency, no spills); the
+// noise and power-law variants keep the compiler's register choice.
+template <int FEAT, int WIDE> constexpr int sweep_min_waves() {
+  return (FEAT & (F_NOISE | F_POWER)) == 0 && WIDE == 0 ? 5 : 1;
+}
+
 template <int ST, int FEAT, int PLM, int WIDE>
-__global__ __launch_bounds__(256) void k_sweep(const DevDomain *__restrict__ doms,
+__global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(const DevDomain *__restrict__ doms,
                                                const int *__restrict__ prefix, int ndom,
                                                int kstep) {
   using S = Store<ST>;
@@ -287,12 +280,14 @@ __global__ __launch_bounds__(256) void k_sweep(const DevDomain *__restrict__ dom
   if (x >= nx) return;
   const int ybase = tyi * rows_pass * npt + (int)threadIdx.x / tw;
 
-  const uint64_t T0 = *D.tstep + (uint64_t)kstep;  // state time of the source buffer
+  const uint64_t T0 = *gbl(D.tstep) + (uint64_t)kstep;  // state time of the source buffer
   const uint32_t step = (uint32_t)(T0 + 1);
-  const T *__restrict__ src = (const T *)D.f[T0 & 1];
-  T *__restrict__ dst = (T *)D.f[(T0 + 1) & 1];
+  void *const f0 = D.f[0];
+  void *const f1 = D.f[1];
+  const T *__restrict__ src = (const T *)((T0 & 1) ? f1 : f0);
+  T *__restrict__ dst = (T *)((T0 & 1) ? f0 : f1);
   const size_t plane = (size_t)ny * pitch;
-  const PState *P = D.pstate[T0 & 1];
+  bool bad = false;  // non-finite density seen by this thread
   const bool perx = D.bc_x == BC_PERIODIC, wallx = D.bc_x == BC_WALL;
   const bool wally = D.bc_y == BC_WALL;
   const bool pressx = D.bc_x == BC_PRESSURE;
@@ -317,28 +312,27 @@ __global__ __launch_bounds__(256) void k_sweep(const DevDomain *__restrict__ dom
   for (int r0 = 0; r0 < npt; r0 += U) {
     R d[U][9];
     uint32_t unk[U];
+    uint16_t nw[U];
     bool act[U];
+    // phase 1: every load of the row group, branch-free and none depending on
+    // another, so they are all in flight together; rows past the tile or the
+    // domain load from a clamped valid row and are discarded
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int y = ybase + (r0 + u) * rows_pass;
-      act[u] = r0 + u < npt && y < ny;
-      unk[u] = 0;
-      if (!act[u]) continue;
+      const int yr = ybase + (r0 + u) * rows_pass;
+      const bool valid = r0 + u < npt && yr < ny;
+      const int y = valid ? yr : ny - 1;
       const uint32_t here = (uint32_t)y * pitch + x;
-      uint8_t lx = 0;
-      if (LABELS && has_lab) {
-        lx = D.label[here];
-        act[u] = lx != LBL_SOLID;
-      } else {
-        act[u] = !((wally && (y == 0 || y == ny - 1)) || (wallx && (x == 0 || x == nx - 1)));
-      }
-      if (!act[u]) continue;
-      unk[u] = pull_node<ST, FEAT, R>(D, src, plane, x, y, here, lx, has_lab, col, col_out,
-                                      col_wall, P, d[u]);
+      nw[u] = (LABELS && has_lab) ? gbl(D.nodew)[here] : (uint16_t)0;
+      const bool wall = !(LABELS && has_lab) &&
+                        ((wally && (y == 0 || y == ny - 1)) || (wallx && (x == 0 || x == nx - 1)));
+      act[u] = valid && !wall;
+      unk[u] = pull_node<ST, FEAT, R>(D, src, plane, y, here, LABELS && has_lab, col, col_out,
+                                      col_wall, d[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (!act[u]) continue;
+      if (!act[u] || (nw[u] & NODE_SOLID)) continue;
       const int y = ybase + (r0 + u) * rows_pass;
       const uint32_t here = (uint32_t)y * pitch + x;
       if (pressx && unk[u]) {
@@ -363,10 +357,23 @@ __global__ __launch_bounds__(256) void k_sweep(const DevDomain *__restrict__ dom
       collide_node<ST, FEAT, PLM, R>(D, d[u], node, step);
       const R drho = ((d[u][0] + d[u][1]) + (d[u][2] + d[u][3])) +
                      ((d[u][4] + d[u][5]) + (d[u][6] + d[u][7])) + d[u][8];
-      if (!(fabs(drho) < R(1e30))) atomicOr(D.health, HEALTH_NONFINITE);
+      bad = bad || !(fabs(drho) < R(1e30));
       store_node<ST, R>(D, dst, plane, here, d[u], node, step);
+      if (LABELS && (nw[u] & 0xffu)) {
+        // mirror writes: the pull along i from the solid source x - e_i will
+        // read this node's post-collision opposite population there
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+          if (!((nw[u] >> (i - 1)) & 1u)) continue;
+          int sy = y - cy(i);
+          sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+          const uint32_t so = (uint32_t)sy * pitch + (uint32_t)col[1 + cx(i)];
+          store_one<ST, R>(D, dst + i * plane, so, i, d[u][opp(i)], node, step);
+        }
+      }
     }
   }
+  if (bad) atomicOr(D.health, HEALTH_NONFINITE);
 }
 
 // Initial state: equilibrium of the given fields (or rest), then the
