@@ -308,22 +308,29 @@ static int inside_particle(const lbo_sim *s, const lbo_particle *q, int x, int y
   return dx * dx + dy * dy < q->radius * q->radius;
 }
 
+/* Labels of G(t): solid nodes 1; a non-solid node takes 2 + q for the first
+ * particle q (index order) whose disc strictly contains it, else 0.  Only
+ * nodes in a particle's bounding box can be inside it. */
 static void relabel(lbo_sim *s) {
-  for (int y = 0; y < s->ny; ++y)
-    for (int x = 0; x < s->nx; ++x) {
-      size_t id = (size_t)y * s->nx + x;
-      if (s->solid[id]) {
-        s->label[id] = 1;
-        continue;
+  size_t n = (size_t)s->nx * s->ny;
+  for (size_t id = 0; id < n; ++id) s->label[id] = s->solid[id] ? 1 : 0;
+  int perx = s->p.bc_x == LBO_PERIODIC, pery = s->p.bc_y == LBO_PERIODIC;
+  for (int q = 0; q < s->np; ++q) {
+    const lbo_particle *pq = &s->part[q];
+    int reach = (int)ceil(pq->radius) + 1;
+    int cx = (int)floor(pq->x), cy = (int)floor(pq->y);
+    int *xs = (int *)malloc(sizeof(int) * (s->nx + 2 * reach + 2));
+    int *ys = (int *)malloc(sizeof(int) * (s->ny + 2 * reach + 2));
+    int nxs = axis_window(cx - reach, cx + reach + 1, s->nx, perx, xs);
+    int nys = axis_window(cy - reach, cy + reach + 1, s->ny, pery, ys);
+    for (int b = 0; b < nys; ++b)
+      for (int a = 0; a < nxs; ++a) {
+        size_t id = (size_t)ys[b] * s->nx + xs[a];
+        if (s->label[id] == 0 && inside_particle(s, pq, xs[a], ys[b])) s->label[id] = (uint8_t)(2 + q);
       }
-      uint8_t lab = 0;
-      for (int q = 0; q < s->np; ++q)
-        if (inside_particle(s, &s->part[q], x, y)) {
-          lab = (uint8_t)(2 + q);
-          break;
-        }
-      s->label[id] = lab;
-    }
+    free(xs);
+    free(ys);
+  }
 }
 
 lbo_sim *lbo_create(const lbo_params *p, const uint8_t *mask, const double *rho,
