@@ -7,7 +7,9 @@ obstacles at 20% solid, tau ~ U[0.55, 1.2]), all started from seeded shear
 waves (u0 = 0.01).  Every step advances all 201 domains with one sweep launch
 (batched, replayed from a hipGraph).  Populations are stored as FP16 deviations
 with stochastic rounding (the reported value), and, for comparison, as plain
-FP32 and as BF16 deviations; arithmetic is FP32.
+FP32 and as BF16 deviations; arithmetic is FP32.  Before the timed region the
+library's autotuner (lb_autotune) picks the tile shape of each size class on
+a throwaway copy of its largest member.
 
 MLUPS counts every lattice site of every domain (solids included), as the
 paper defines it.  The roofline object reports the sweep kernel's algorithmic
@@ -70,32 +72,62 @@ def domain_inputs(spec):
     return fields, mask
 
 
-def build_variant(storage, specs, masks):
+def size_bucket(spec):
+    n = spec["n"]
+    return (spec["obstacle_seed"] is not None, 0 if n < 128 else 1 if n < 512 else 2 if n < 2048 else 3)
+
+
+def autotune_tiles(storage, specs, masks):
+    """Tile shape per size class: lb_autotune (every tile width and rows per
+    thread, timed with HIP events) on a throwaway copy of the largest member
+    of each class; the batch members of the class then take its choice."""
+    from paper_2006_12910_amd import lb
+    best = {}
+    for b in sorted({size_bucket(s) for s in specs}):
+        i = max((j for j, s in enumerate(specs) if size_bucket(s) == b), key=lambda j: specs[j]["n"])
+        n = specs[i]["n"]
+        d = lb.Domain(n, n, tau=specs[i]["tau"], storage=storage, rounding=ROUNDING[storage],
+                      obstacles=masks[i])
+        ms = d.autotune(steps=10 if n >= 2048 else 40)
+        best[b] = (d.get_option(lb.OPT_TILE_WIDTH), d.get_option(lb.OPT_ROWS_PER_THREAD))
+        log(f"{storage}: autotune class {b} ({n}^2): tile {best[b][0]}x{best[b][1]}, {ms * 1e3:.1f} us/step")
+        d.close()
+    return best
+
+
+def build_variant(storage, specs, masks, tiles=None):
     from paper_2006_12910_amd import lb
     doms = []
     for i, spec in enumerate(specs):
         fields, _ = domain_inputs(dict(spec, obstacle_seed=None))
-        doms.append(lb.Domain(spec["n"], spec["n"], tau=spec["tau"], storage=storage,
-                              rounding=ROUNDING[storage], init=fields, obstacles=masks[i]))
+        d = lb.Domain(spec["n"], spec["n"], tau=spec["tau"], storage=storage,
+                      rounding=ROUNDING[storage], init=fields, obstacles=masks[i])
+        if tiles:
+            tw, rows = tiles[size_bucket(spec)]
+            d.set_option(lb.OPT_TILE_WIDTH, tw)
+            d.set_option(lb.OPT_ROWS_PER_THREAD, rows)
+        doms.append(d)
     return doms
 
 
 def algorithmic_bytes(specs, masks, sbytes):
     """Bytes the sweep must move per step: 9 loads + 9 stores of each fluid
-    node's populations, plus one label byte per site of domains with obstacles."""
+    node's populations, plus the 2-byte node word (solid flag and solid-source
+    mask) of every site of a domain with obstacles."""
     total = 0
     for spec, m in zip(specs, masks):
         n2 = spec["n"] * spec["n"]
         fluid = n2 if m is None else n2 - int(m.sum())
-        total += 18 * sbytes * fluid + (0 if m is None else n2)
+        total += 18 * sbytes * fluid + (0 if m is None else 2 * n2)
     return total
 
 
-def run_variant(storage, specs, masks, steps, warmup):
+def run_variant(storage, specs, masks, steps, warmup, tune):
     import torch
     from paper_2006_12910_amd import lb
     t0 = time.time()
-    doms = build_variant(storage, specs, masks)
+    tiles = autotune_tiles(storage, specs, masks) if tune else None
+    doms = build_variant(storage, specs, masks, tiles)
     batch = lb.Batch(doms)
     torch.cuda.synchronize()
     log(f"{storage}: built {len(doms)} domains in {time.time() - t0:.1f}s")
@@ -109,7 +141,7 @@ def run_variant(storage, specs, masks, steps, warmup):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     log(f"{storage}: {steps} steps in {ms:.1f} ms")
-    return doms, batch, ms
+    return doms, batch, ms, tiles
 
 
 def oracle_sample(specs, masks, nsteps, budget_s):
@@ -167,13 +199,14 @@ def traffic_entry(bytes_alg):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=900)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--variants", default="f16,f32,bf16",
                     help="storage formats to run; the first is the reported value")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline and the L2 sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline and L2 sample")
+    ap.add_argument("--no-tune", action="store_true", help="default tile shapes instead of the autotuner's")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="before the workload, copy a buffer of this size 5 times (a kernel of "
                          "known traffic for scaling profiler byte counters)")
@@ -218,15 +251,18 @@ def main():
 
     results = {}
     for v in variants:
-        doms, batch, ms = run_variant(v, specs, masks, args.steps, args.warmup)
+        doms, batch, ms, tiles = run_variant(v, specs, masks, args.steps, args.warmup, not args.no_tune)
         mlups = sites * args.steps / (ms * 1e-3) / 1e6
         bytes_alg = algorithmic_bytes(specs, masks, STORAGE_BYTES[v])
         gbs = bytes_alg * args.steps / (ms * 1e-3) / 1e9
         entry = {"mlups": round(mlups, 1), "ms_per_step": round(ms / args.steps, 4),
                  "sweep_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                 "bytes_per_step": bytes_alg, "rounding": ROUNDING[v]}
+                 "bytes_per_step": bytes_alg, "rounding": ROUNDING[v],
+                 "tiles": None if tiles is None else {f"{'obstacles' if k[0] else 'open'}/class{k[1]}": f"{t[0]}x{t[1]}"
+                                                       for k, t in tiles.items()}}
         if ref:
-            entry["l2_vs_oracle"] = l2_errors(doms, ref, specs)
+            entry["l2_vs_oracle"] = dict(l2_errors(doms, ref, specs), after_steps=nsteps_total,
+                                         domains=len(ref))
         results[v] = entry
         log(f"{v}: {json.dumps(entry)}")
         batch.close()

@@ -85,7 +85,9 @@ typedef int32_t lb_status;
 
 typedef struct lb_domain_desc {
   uint32_t abi_version;       /* LB_ABI_VERSION                                  */
-  int32_t nx, ny;             /* lattice size, each in [3, 65536]               */
+  int32_t nx, ny;             /* lattice size, each in [3, 65536], with         
+                               * 9 * ny * (nx rounded up to 64) * (bytes per    
+                               * stored value: 8, 4 or 2) < 2^32                */
   int32_t bc_x, bc_y;         /* LB_PERIODIC | LB_WALL | LB_PRESSURE (x only)   */
   int32_t storage;            /* LB_F64 | LB_F32 | LB_F16_DELTA | LB_BF16_DELTA */
   int32_t rounding;           /* LB_ROUND_NEAREST | LB_ROUND_STOCHASTIC         */

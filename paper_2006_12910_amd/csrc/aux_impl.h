@@ -90,8 +90,9 @@ __global__ __launch_bounds__(256) void k_moments(const DevDomain *__restrict__ D
 }
 
 // Mirror slots of the current buffer: for every fluid node x and solid source
-// s = x - e_i, slot i of s holds x's own opposite population (what the pull
-// along i bounces back), copied bit for bit.
+// s = x - e_i (an obstacle or particle node of the label plane, or a wall row
+// or column of a domain without one), slot i of s holds x's own opposite
+// population (what the pull along i bounces back), copied bit for bit.
 template <int ST>
 __global__ __launch_bounds__(256) void k_mirror(const DevDomain *__restrict__ Dp) {
   using T = typename Store<ST>::T;
@@ -100,11 +101,22 @@ __global__ __launch_bounds__(256) void k_mirror(const DevDomain *__restrict__ Dp
   if (n >= (long long)D.ny * D.nx) return;
   const int y = (int)(n / D.nx), x = (int)(n - (long long)y * D.nx);
   const size_t here = (size_t)y * D.pitch + x;
-  const uint16_t w = D.nodew[here];
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  uint32_t w;
+  if (D.nodew) {
+    w = D.nodew[here];
+  } else {
+    if (node_is_solid(D, x, y)) return;
+    w = 0;
+    for (int i = 1; i < 9; ++i) {
+      int sx, sy;
+      if (source_of(D.nx, D.ny, perx, pery, x, y, i, sx, sy) && node_is_solid(D, sx, sy))
+        w |= 1u << (i - 1);
+    }
+  }
   if ((w & NODE_SOLID) || !(w & 0xffu)) return;
   T *f = (T *)D.f[*D.tstep & 1];
   const size_t plane = (size_t)D.ny * D.pitch;
-  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
   for (int i = 1; i < 9; ++i) {
     if (!((w >> (i - 1)) & 1u)) continue;
     int sx, sy;

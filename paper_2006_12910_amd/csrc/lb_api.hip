@@ -87,8 +87,12 @@ lb_status validate(const lb_domain_desc *d) {
   if (d->abi_version != LB_ABI_VERSION) return fail(LB_EINVAL, "abi_version mismatch");
   if (d->nx < 3 || d->ny < 3 || d->nx > 65536 || d->ny > 65536)
     return fail(LB_EINVAL, "nx, ny must be in [3, 65536]");
-  if ((long long)d->nx * d->ny * 9 >= (1LL << 32) / 2)
-    return fail(LB_EINVAL, "lattice too large for 32-bit plane offsets");
+  if (d->storage < LB_F64 || d->storage > LB_BF16_DELTA) return fail(LB_EINVAL, "bad storage");
+  {
+    const long long vbytes = d->storage == LB_F64 ? 8 : (d->storage == LB_F32 ? 4 : 2);
+    if ((long long)((d->nx + 63) / 64 * 64) * d->ny * 9 * vbytes >= (1LL << 32))
+      return fail(LB_EINVAL, "lattice too large: a population buffer must span fewer than 2^32 bytes");
+  }
   if (d->bc_x < LB_PERIODIC || d->bc_x > LB_PRESSURE) return fail(LB_EINVAL, "bad bc_x");
   if (d->bc_y != LB_PERIODIC && d->bc_y != LB_WALL) return fail(LB_EINVAL, "bad bc_y");
   if (d->storage < LB_F64 || d->storage > LB_BF16_DELTA) return fail(LB_EINVAL, "bad storage");
@@ -285,9 +289,10 @@ lb_status domain_mass_enqueue(lb_domain *d) {
   return LB_OK;
 }
 
-// Mirror slots of stationary solids in the current population buffer.
+// Mirror slots of stationary solids (obstacles, particles, index walls) in
+// the current population buffer.
 lb_status refresh_mirrors(lb_domain *d) {
-  if (!d->hd.label) return LB_OK;
+  if (!d->hd.label && d->desc.bc_x != LB_WALL && d->desc.bc_y != LB_WALL) return LB_OK;
   d->ks.mirror(d->ddesc(), d->desc.nx, d->desc.ny, d->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(d->stream));

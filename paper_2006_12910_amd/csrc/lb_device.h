@@ -122,17 +122,33 @@ template <class T> __device__ __forceinline__ LBK_GLOBAL T *gbl(T *p) { return (
 
 // ---------------------------------------------------------------------------
 // Storage formats.  Value held = (f_i - w_i rho0) * scale.
+// Scale of the stored deviations of direction i: the 16-bit formats store
+// d_i times 2, 8, 32 (rest, axis, diagonal); the others store d_i.
+template <int ST> constexpr float kscale(int i) {
+  return (ST == ST_F16 || ST == ST_BF16) ? dscale(i) : 1.0f;
+}
+
 template <int ST> struct Store;
 template <> struct Store<ST_F64> {
   using T = double;
   using R = double;
   static __device__ __forceinline__ R load(const T *p, size_t o, int) { return gbl(p)[o]; }
+  static __device__ __forceinline__ R dec(T v, int) { return v; }
+  static __device__ __forceinline__ T enc(R v, int, uint32_t) { return v; }
+  static __device__ __forceinline__ R raw_dec(T v) { return v; }
+  static __device__ __forceinline__ T raw_rn(R v) { return v; }
+  static __device__ __forceinline__ T raw_sr(R v, uint32_t) { return v; }
   static __device__ __forceinline__ void put(T *p, size_t o, int, R v, uint32_t) { gbl(p)[o] = v; }
 };
 template <> struct Store<ST_F32> {
   using T = float;
   using R = float;
   static __device__ __forceinline__ R load(const T *p, size_t o, int) { return gbl(p)[o]; }
+  static __device__ __forceinline__ R dec(T v, int) { return v; }
+  static __device__ __forceinline__ T enc(R v, int, uint32_t) { return v; }
+  static __device__ __forceinline__ R raw_dec(T v) { return v; }
+  static __device__ __forceinline__ T raw_rn(R v) { return v; }
+  static __device__ __forceinline__ T raw_sr(R v, uint32_t) { return v; }
   static __device__ __forceinline__ void put(T *p, size_t o, int, R v, uint32_t) { gbl(p)[o] = v; }
 };
 
@@ -170,21 +186,31 @@ __device__ __forceinline__ uint16_t f32_to_bf16_sr(float v, uint32_t r) {
 template <> struct Store<ST_F16> {
   using T = uint16_t;
   using R = float;
-  static __device__ __forceinline__ R load(const T *p, size_t o, int i) {
-    return f16_to_f32(gbl(p)[o]) * (1.0f / dscale(i));
+  static __device__ __forceinline__ R dec(T v, int i) { return f16_to_f32(v) * (1.0f / dscale(i)); }
+  static __device__ __forceinline__ R raw_dec(T v) { return f16_to_f32(v); }
+  static __device__ __forceinline__ T raw_rn(R v) { return f32_to_f16_rn(v); }
+  static __device__ __forceinline__ T raw_sr(R v, uint32_t r) { return f32_to_f16_sr(v, r); }
+  static __device__ __forceinline__ R load(const T *p, size_t o, int i) { return dec(gbl(p)[o], i); }
+  static __device__ __forceinline__ T enc(R v, int i, uint32_t rbits) {
+    return rbits ? f32_to_f16_sr(v * dscale(i), rbits) : f32_to_f16_rn(v * dscale(i));
   }
   static __device__ __forceinline__ void put(T *p, size_t o, int i, R v, uint32_t rbits) {
-    gbl(p)[o] = rbits ? f32_to_f16_sr(v * dscale(i), rbits) : f32_to_f16_rn(v * dscale(i));
+    gbl(p)[o] = enc(v, i, rbits);
   }
 };
 template <> struct Store<ST_BF16> {
   using T = uint16_t;
   using R = float;
-  static __device__ __forceinline__ R load(const T *p, size_t o, int i) {
-    return bf16_to_f32(gbl(p)[o]) * (1.0f / dscale(i));
+  static __device__ __forceinline__ R dec(T v, int i) { return bf16_to_f32(v) * (1.0f / dscale(i)); }
+  static __device__ __forceinline__ R raw_dec(T v) { return bf16_to_f32(v); }
+  static __device__ __forceinline__ T raw_rn(R v) { return f32_to_bf16_rn(v); }
+  static __device__ __forceinline__ T raw_sr(R v, uint32_t r) { return f32_to_bf16_sr(v, r); }
+  static __device__ __forceinline__ R load(const T *p, size_t o, int i) { return dec(gbl(p)[o], i); }
+  static __device__ __forceinline__ T enc(R v, int i, uint32_t rbits) {
+    return rbits ? f32_to_bf16_sr(v * dscale(i), rbits) : f32_to_bf16_rn(v * dscale(i));
   }
   static __device__ __forceinline__ void put(T *p, size_t o, int i, R v, uint32_t rbits) {
-    gbl(p)[o] = rbits ? f32_to_bf16_sr(v * dscale(i), rbits) : f32_to_bf16_rn(v * dscale(i));
+    gbl(p)[o] = enc(v, i, rbits);
   }
 };
 
@@ -324,18 +350,23 @@ __device__ __forceinline__ bool source_of(int nx, int ny, bool perx, bool pery, 
   return true;
 }
 
-// Static node word from the label plane: NODE_SOLID for a solid node, else bit
-// i-1 set when the source x - e_i of the pull along i is solid.  Sources
-// outside a non-periodic edge are left clear (pressure faces reconstruct them).
+// Static node word from the label plane.  A fluid (or particle) node: bit
+// i-1 set when the source x - e_i of its pull along i is solid, so the node
+// mirror-writes that slot; sources outside a non-periodic edge are left clear
+// (pressure faces reconstruct them).  A solid node: NODE_SOLID, and bit i-1
+// set when the node x + e_i that pulls slot i from it is not solid, so that
+// slot is the neighbour's mirror slot; the solid node's own sweep thread
+// fills every other slot, and each slot of the plane is written once a step.
 __device__ __forceinline__ uint16_t node_word(const uint8_t *lab, int nx, int ny, int pitch,
                                               bool perx, bool pery, int x, int y) {
-  if (lab[(size_t)y * pitch + x] == LBL_SOLID) return NODE_SOLID;
-  uint16_t m = 0;
+  const bool solid = lab[(size_t)y * pitch + x] == LBL_SOLID;
+  uint16_t m = solid ? NODE_SOLID : 0;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     int sx, sy;
-    if (!source_of(nx, ny, perx, pery, x, y, i, sx, sy)) continue;
-    if (lab[(size_t)sy * pitch + sx] == LBL_SOLID) m |= (uint16_t)(1u << (i - 1));
+    // the source of the pull along i, or (solid node) the node pulling from here
+    if (!source_of(nx, ny, perx, pery, x, y, solid ? opp(i) : i, sx, sy)) continue;
+    if ((lab[(size_t)sy * pitch + sx] == LBL_SOLID) != solid) m |= (uint16_t)(1u << (i - 1));
   }
   return m;
 }

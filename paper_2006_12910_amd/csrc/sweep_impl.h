@@ -38,15 +38,19 @@ template <> __device__ __forceinline__ double powr<double>(double a, double b) {
 // [tau_min, tau_max].  n = 1/2 has the closed form tau = s^2,
 // s = (c + sqrt(c^2 + 2))/2; otherwise Newton from the bracket end on the side
 // where it converges monotonically (tau_max for n < 1, tau_min for n > 1).
-template <class R, int PLM>
+template <class R, int PLM, int ST>
 __device__ __forceinline__ R powerlaw_tau(const DevDomain &D, const R d[9], R drho, R rho, R irho,
                                           R jx, R jy) {
   const R gx = par<R>(D.gx, D.gx_f), gy = par<R>(D.gy, D.gy_f);
   const R ux = jx * irho + R(0.5) * gx, uy = jy * irho + R(0.5) * gy;
   const R third = drho * (R(1) / R(3));
-  const R sxx = (d[1] + d[3]) + ((d[5] + d[6]) + (d[7] + d[8]));
-  const R syy = (d[2] + d[4]) + ((d[5] + d[6]) + (d[7] + d[8]));
-  const R sxy = (d[5] - d[6]) + (d[7] - d[8]);
+  // d holds the stored scaling (see collide_node): axis values times K1,
+  // diagonal values times K5, both powers of two
+  constexpr R i1 = R(1) / R(kscale<ST>(1)), i5 = R(1) / R(kscale<ST>(5));
+  const R dsum = (d[5] + d[6]) + (d[7] + d[8]);
+  const R sxx = i1 * (d[1] + d[3]) + i5 * dsum;
+  const R syy = i1 * (d[2] + d[4]) + i5 * dsum;
+  const R sxy = i5 * ((d[5] - d[6]) + (d[7] - d[8]));
   const R pxx = sxx - rho * ux * ux - third;
   const R pyy = syy - rho * uy * uy - third;
   const R pxy = sxy - rho * ux * uy;
@@ -100,26 +104,44 @@ __device__ __forceinline__ R powerlaw_tau(const DevDomain &D, const R d[9], R dr
   return tau < tmin ? tmin : (tau > tmax ? tmax : tau);
 }
 
-// BGK collision of one node (deviations in, deviations out), step `step`, in
-// arithmetic type R.  The equilibrium of Eq. LB2 with u = j/rho + tau g is
-// evaluated in a form whose mass and momentum do not depend on how the
-// lattice constants round: the linear term is built from J = j + rho tau g
-// with coefficients L1 ~ 1/3, L5 = (1 - 2 L1)/4 (so 2 L1 + 4 L5 = 1 exactly),
-// opposite directions share one even part c and take c +- (linear term), and
-// the rest population is delta_rho minus the other eight.  Algebraically this
-// is Eq. LB2; in FP32 it removes a systematic O(1e-8) momentum error per step
-// that would otherwise bias slowly accelerating flows.
+// Reciprocal: FP32 takes the hardware estimate and one Newton step (error
+// below one ulp), FP64 the correctly rounded division.
+template <class R> __device__ __forceinline__ R recip(R x);
+template <> __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ float recip<float>(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(fmaf(-x, r, 1.0f), r, r);
+}
+
+// BGK collision of one node, step `step`, in arithmetic type R.  The values
+// are the deviations d_i = f_i - w_i rho0 in the stored scaling: times K0, K1,
+// K5 for rest, axis and diagonal directions (powers of two: 2, 8, 32 for the
+// 16-bit formats, 1 otherwise).  Scaling by a power of two commutes with every
+// rounding, so the result is exactly K_i times the unscaled computation, and
+// the stores and loads need no conversion factor.
+//
+// The equilibrium of Eq. LB2 with u = j/rho + tau g is evaluated in a form
+// whose mass and momentum do not depend on how the lattice constants round:
+// the linear term is built from J = j + rho tau g with coefficients L1 ~ 1/3,
+// L5 = (1 - 2 L1)/4 (so 2 L1 + 4 L5 = 1 exactly), opposite directions share
+// one even part c and take c +- (linear term), and the rest population is
+// delta_rho minus the other eight.  Algebraically this is Eq. LB2; in FP32 it
+// removes a systematic O(1e-8) momentum error per step that would otherwise
+// bias slowly accelerating flows.
 template <int ST, int FEAT, int PLM, class R>
 __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_t node,
                                              uint32_t step) {
-  const R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
-  const R jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
-  const R jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+  constexpr R K0 = R(kscale<ST>(0)), K1 = R(kscale<ST>(1)), K5 = R(kscale<ST>(5));
+  constexpr R i0 = R(1) / K0, i1 = R(1) / K1, i5 = R(1) / K5;
+  const R drho = i0 * d[0] + (i1 * ((d[1] + d[3]) + (d[2] + d[4])) +
+                              i5 * ((d[5] + d[7]) + (d[6] + d[8])));
+  const R jx = i1 * (d[1] - d[3]) + i5 * ((d[5] - d[6]) + (d[8] - d[7]));
+  const R jy = i1 * (d[2] - d[4]) + i5 * ((d[5] + d[6]) - (d[7] + d[8]));
   const R rho = par<R>(D.rho0, D.rho0_f) + drho;
-  const R irho = R(1) / rho;
+  const R irho = recip<R>(rho);
   R tau, om;
   if constexpr ((FEAT & F_POWER) != 0) {
-    tau = powerlaw_tau<R, PLM>(D, d, drho, rho, irho, jx, jy);
+    tau = powerlaw_tau<R, PLM, ST>(D, d, drho, rho, irho, jx, jy);
     om = R(1) / tau;
   } else {
     tau = par<R>(D.tau, D.tau_f);
@@ -133,11 +155,13 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
   const R q = R(1.5) * rho * (ux * ux + uy * uy);
   const R r45 = R(4.5) * rho;
   const R sp = ux + uy, sm = uy - ux;
-  const R cxx = W1 * (drho + (r45 * ux * ux - q)), cyy = W1 * (drho + (r45 * uy * uy - q));
-  const R cpp = W5 * (drho + (r45 * sp * sp - q)), cmm = W5 * (drho + (r45 * sm * sm - q));
-  const R lx = L1 * Jx, ly = L1 * Jy, lp = L5 * (Jx + Jy), lm = L5 * (Jy - Jx);
+  // even parts and linear terms, already in the stored scaling
+  const R cxx = (K1 * W1) * (drho + (r45 * ux * ux - q)), cyy = (K1 * W1) * (drho + (r45 * uy * uy - q));
+  const R cpp = (K5 * W5) * (drho + (r45 * sp * sp - q)), cmm = (K5 * W5) * (drho + (r45 * sm * sm - q));
+  const R lx = (K1 * L1) * Jx, ly = (K1 * L1) * Jy;
+  const R lp = (K5 * L5) * (Jx + Jy), lm = (K5 * L5) * (Jy - Jx);
   R eq[9];
-  eq[0] = drho - R(2) * ((cxx + cyy) + (cpp + cmm));
+  eq[0] = K0 * (drho - R(2) * (i1 * (cxx + cyy) + i5 * (cpp + cmm)));
   eq[1] = cxx + lx;
   eq[3] = cxx - lx;
   eq[2] = cyy + ly;
@@ -161,44 +185,51 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
     for (int i = 0; i < 9; ++i) {
       const R z = R(basis_poly(3, i)) * t3 + R(basis_poly(4, i)) * t4 + R(basis_poly(5, i)) * t5 +
                   R(basis_poly(6, i)) * t6 + R(basis_poly(7, i)) * t7 + R(basis_poly(8, i)) * t8;
-      const R wi = i == 0 ? R(4) * W1 : (i <= 4 ? W1 : W5);  // exact ratios 4 : 1 : 1/4
+      // w_i in exact ratios 4 : 1 : 1/4, times the stored scaling
+      const R wi = i == 0 ? K0 * (R(4) * W1) : (i <= 4 ? K1 * W1 : K5 * W5);
       d[i] += amp * wi * z;
     }
   }
+}
+
+// Stored form of the nine post-collision deviations of one node.  16-bit
+// storage with stochastic rounding takes its rounding bits from one hash of
+// (node, step, key) per node, rotated by 7 i bits for direction i (nine
+// distinct rotations), so every store of the same value at the same node and
+// step rounds the same way.
+template <int ST, class R, bool SR>
+__device__ __forceinline__ void encode_node(const DevDomain &D, const R d[9], uint32_t node,
+                                            uint32_t step, typename Store<ST>::T q[9]) {
+  using S = Store<ST>;
+  using RS = typename S::R;
+  if constexpr (SR && (ST == ST_F16 || ST == ST_BF16)) {
+    const uint32_t h = mix32(node ^ (mix32(step ^ D.key0) ^ D.key1));
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int r = (7 * i) & 31;
+      q[i] = S::raw_sr((RS)d[i], r == 0 ? h : (h << r) | (h >> (32 - r)));
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) q[i] = S::raw_rn((RS)d[i]);
+  }
+}
+
+// delta rho of deviations in the stored scaling
+template <int ST, class R> __device__ __forceinline__ R scaled_drho(const R d[9]) {
+  constexpr R i0 = R(1) / R(kscale<ST>(0)), i1 = R(1) / R(kscale<ST>(1)), i5 = R(1) / R(kscale<ST>(5));
+  return i0 * d[0] + (i1 * ((d[1] + d[3]) + (d[2] + d[4])) + i5 * ((d[5] + d[7]) + (d[6] + d[8])));
 }
 
 template <int ST, class R>
 __device__ __forceinline__ void store_node(const DevDomain &D, typename Store<ST>::T *dst,
                                            size_t plane, uint32_t off, const R d[9],
                                            uint32_t node, uint32_t step) {
-  using S = Store<ST>;
-  using RS = typename S::R;
-  if constexpr (ST == ST_F16 || ST == ST_BF16) {
-    if (D.feat & F_STOCH) {
-      const uint32_t h = mix32(node * 0x9E3779B1u ^ mix32(step ^ D.key0) ^ D.key1);
+  typename Store<ST>::T q[9];
+  if ((ST == ST_F16 || ST == ST_BF16) && (D.feat & F_STOCH)) encode_node<ST, R, true>(D, d, node, step, q);
+  else encode_node<ST, R, false>(D, d, node, step, q);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) S::put(dst + i * plane, off, i, (RS)d[i], sr_bits(h, i) | 1u);
-      return;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 9; ++i) S::put(dst + i * plane, off, i, (RS)d[i], 0u);
-}
-
-// One mirrored value, rounded like the node's own slot of the same direction.
-template <int ST, class R>
-__device__ __forceinline__ void store_one(const DevDomain &D, typename Store<ST>::T *p, uint32_t off,
-                                          int dir, R v, uint32_t node, uint32_t step) {
-  using S = Store<ST>;
-  using RS = typename S::R;
-  if constexpr (ST == ST_F16 || ST == ST_BF16) {
-    if (D.feat & F_STOCH) {
-      const uint32_t h = mix32(node * 0x9E3779B1u ^ mix32(step ^ D.key0) ^ D.key1);
-      S::put(p, off, dir, (RS)v, sr_bits(h, opp(dir)) | 1u);
-      return;
-    }
-  }
-  S::put(p, off, dir, (RS)v, 0u);
+  for (int i = 0; i < 9; ++i) gbl(dst + i * plane)[off] = q[i];
 }
 
 // Arithmetic type: FP64 for FP64 storage or when wide arithmetic is chosen,
@@ -210,45 +241,64 @@ using CompT = typename std::conditional<ST == ST_F64 || WIDE != 0, double, float
 // per load, so it keeps more rows in flight to cover memory latency.
 template <int ST> constexpr int rows_in_flight() { return ST == ST_F16 || ST == ST_BF16 ? 4 : 2; }
 
+// The sweep addresses a population buffer as one base pointer plus a 32-bit
+// byte offset (a domain's nine planes span fewer than 2^32 bytes), which maps
+// to the scalar-base + vector-offset form of the global memory instructions.
+template <class T> __device__ __forceinline__ T ldb(const char LBK_GLOBAL *b, uint32_t off) {
+  return *(const T LBK_GLOBAL *)(b + off);
+}
+template <class T> __device__ __forceinline__ void stb(char LBK_GLOBAL *b, uint32_t off, T v) {
+  *(T LBK_GLOBAL *)(b + off) = v;
+}
+
 // Pull of one node.  Every direction loads the neighbour's slot at x - e_i:
-// where that neighbour is solid, its slot holds this node's own opposite
-// population, written there by the previous step's store (halfway
-// bounce-back by mirror writes); where the pull crosses a particle surface,
-// the slot holds the moving-wall bounced value, put there by the particle
-// pre-pass (k_link_swap).  So the loads have no data-dependent address.
-// Index walls of label-free domains select the node's own slot directly.
-template <int ST, int FEAT, class R>
-__device__ __forceinline__ uint32_t pull_node(const DevDomain &D, const typename Store<ST>::T *src,
-                                              size_t plane, int y, uint32_t here, bool has_lab,
-                                              const int (&col)[3], const bool (&col_out)[3],
-                                              const bool (&col_wall)[3], R (&d)[9]) {
-  using S = Store<ST>;
-  const int ny = D.ny, pitch = D.pitch;
-  const bool pery = D.bc_y == BC_PERIODIC, wally = D.bc_y == BC_WALL;
-  int row[3];
-  bool row_out[3], row_wall[3];
+// where that neighbour is solid (an obstacle, or a wall row or column), its
+// slot holds this node's own opposite population, written there by the
+// previous step's store (halfway bounce-back by mirror writes); where the
+// pull crosses a particle surface, the slot holds the moving-wall bounced
+// value, put there by the particle pre-pass (k_link_swap).  So the loads have
+// no data-dependent address.  A source beyond a density face is read from the
+// node's own column: those populations are unknown and the face
+// reconstruction replaces them.  row[] and col[] are the byte offsets of the
+// (wrapped or clamped) source rows y+1, y, y-1 and columns x+1, x, x-1.
+template <class T, class P>
+__device__ __forceinline__ void pull_node(const char LBK_GLOBAL *src, uint32_t planeB,
+                                          uint32_t hereB, const uint32_t (&row)[3],
+                                          const uint32_t (&col)[3], P &raw) {
+  raw.set(0, ldb<T>(src, hereB));
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    int rr = y + 1 - k;  // k = 0 -> y+1 (source of cy = -1), k = 2 -> y-1
-    bool out = false;
-    if (rr < 0) { if (pery) rr += ny; else out = true; }
-    else if (rr >= ny) { if (pery) rr -= ny; else out = true; }
-    row[k] = (out ? y : rr) * pitch;
-    row_out[k] = out;
-    row_wall[k] = wally && (rr == 0 || rr == ny - 1);
-  }
-  uint32_t unknown = 0;
-  d[0] = (R)S::load(src, here, 0);
-#pragma unroll
-  for (int i = 1; i < 9; ++i) {
-    const int kc = 1 + cx(i), kr = 1 + cy(i);
-    const bool out = col_out[kc] || row_out[kr];
-    const uint32_t so = (uint32_t)row[kr] + (uint32_t)col[kc];
-    const bool own = out || (!has_lab && (col_wall[kc] || row_wall[kr]));
-    d[i] = (R)S::load(src + (own ? opp(i) : i) * plane, own ? here : so, i);
-    if (out) unknown |= 1u << i;
-  }
-  return unknown;
+  for (int i = 1; i < 9; ++i)
+    raw.set(i, ldb<T>(src, (uint32_t)i * planeB + (row[1 + cy(i)] + col[1 + cx(i)])));
+}
+
+// Stored values of one node while its loads are in flight (decoded only
+// when the node is computed).
+template <class T> struct Pulled {
+  T v[9];
+  __device__ __forceinline__ void set(int i, T x) { v[i] = x; }
+  __device__ __forceinline__ T get(int i) const { return v[i]; }
+};
+
+// Byte offsets of the source rows y+1, y, y-1 (index 1 + cy): wrapped on a
+// periodic axis, else a row beyond the edge is clamped to y.
+__device__ __forceinline__ void src_rows(int y, int ny, uint32_t pitchB, uint32_t planeB,
+                                         bool periodic, uint32_t (&row)[3]) {
+  const uint32_t yp = (uint32_t)y * pitchB;
+  row[1] = yp;
+  row[0] = y + 1 < ny ? yp + pitchB : (periodic ? 0u : yp);
+  row[2] = y > 0 ? yp - pitchB : (periodic ? planeB - pitchB : yp);
+}
+
+// Bit i-1 set for the directions i with cx(i) == v (resp. cy(i) == v).
+constexpr uint32_t dirs_cx(int v) {
+  uint32_t m = 0;
+  for (int i = 1; i < 9; ++i) m |= cx(i) == v ? 1u << (i - 1) : 0u;
+  return m;
+}
+constexpr uint32_t dirs_cy(int v) {
+  uint32_t m = 0;
+  for (int i = 1; i < 9; ++i) m |= cy(i) == v ? 1u << (i - 1) : 0u;
+  return m;
 }
 
 // 256 threads.  The plain and obstacle variants are held to at least 5 waves
@@ -259,14 +309,14 @@ template <int FEAT, int WIDE> constexpr int sweep_min_waves() {
 }
 
 template <int ST, int FEAT, int PLM, int WIDE>
-__global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(const DevDomain *__restrict__ doms,
-                                               const int *__restrict__ prefix, int ndom,
-                                               int kstep) {
+__global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
+    const DevDomain *__restrict__ doms, const int *__restrict__ prefix, int ndom, int kstep) {
   using S = Store<ST>;
   using T = typename S::T;
   using R = CompT<ST, WIDE>;
   constexpr bool LABELS = (FEAT & F_LABELS) != 0;
   constexpr int U = rows_in_flight<ST>();
+  constexpr uint32_t B = sizeof(T);
 
   const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
   const int dix = ndom == 1 ? 0 : find_domain(prefix, ndom, b);
@@ -284,34 +334,43 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
   const uint32_t step = (uint32_t)(T0 + 1);
   void *const f0 = D.f[0];
   void *const f1 = D.f[1];
-  const T *__restrict__ src = (const T *)((T0 & 1) ? f1 : f0);
-  T *__restrict__ dst = (T *)((T0 & 1) ? f0 : f1);
-  const size_t plane = (size_t)ny * pitch;
+  const char LBK_GLOBAL *src = (const char LBK_GLOBAL *)((T0 & 1) ? f1 : f0);
+  char LBK_GLOBAL *dst = (char LBK_GLOBAL *)((T0 & 1) ? f0 : f1);
+  const uint32_t pitchB = (uint32_t)pitch * B;
+  const uint32_t planeB = (uint32_t)ny * pitchB;
   bool bad = false;  // non-finite density seen by this thread
   const bool perx = D.bc_x == BC_PERIODIC, wallx = D.bc_x == BC_WALL;
-  const bool wally = D.bc_y == BC_WALL;
+  const bool pery = D.bc_y == BC_PERIODIC, wally = D.bc_y == BC_WALL;
   const bool pressx = D.bc_x == BC_PRESSURE;
   // a batch may mix domains with and without a label plane
   const bool has_lab = LABELS && D.label != nullptr;
+  // index walls of a domain without a label plane
+  const bool walls = !has_lab && (wallx || wally);
+  // nodes on a density face (Zou-He reconstruction)
+  const bool face = pressx && (x == 0 || x == nx - 1);
 
-  // columns x-1, x, x+1 (index by 1 - cx)
-  int col[3];
-  bool col_out[3], col_wall[3];
+  // source columns x+1, x, x-1 (index 1 + cx); a column beyond a
+  // non-periodic edge is clamped to x
+  uint32_t col[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    int c = x + 1 - k;  // k = 0 -> x+1 (source of cx = -1), k = 2 -> x-1 (cx = +1)
-    bool out = false;
-    if (c < 0) { if (perx) c += nx; else out = true; }
-    else if (c >= nx) { if (perx) c -= nx; else out = true; }
-    col[k] = out ? x : c;
-    col_out[k] = out;
-    col_wall[k] = wallx && (c == 0 || c == nx - 1);
+    const int c = x + 1 - k;
+    col[k] = (uint32_t)(c < 0 ? (perx ? c + nx : x) : (c >= nx ? (perx ? c - nx : x) : c)) * B;
   }
+  // index walls: directions whose source is a wall column, and directions
+  // whose source column lies inside the domain
+  const uint32_t wall_cols =
+      wallx ? (x == 1 ? dirs_cx(1) : 0u) | (x == nx - 2 ? dirs_cx(-1) : 0u) : 0u;
+  const uint32_t cols_in = 0xffu & ~(!perx && x == 0 ? dirs_cx(1) : 0u) &
+                           ~(!perx && x == nx - 1 ? dirs_cx(-1) : 0u);
 
 #pragma unroll 1
   for (int r0 = 0; r0 < npt; r0 += U) {
-    R d[U][9];
-    uint32_t unk[U];
+    // first row of this group; hidden from the optimiser so that it does not
+    // turn every address of the group into an induction variable of its own
+    int yg = ybase + r0 * rows_pass;
+    __asm__ volatile("" : "+v"(yg));
+    Pulled<T> raw[U];
     uint16_t nw[U];
     bool act[U];
     // phase 1: every load of the row group, branch-free and none depending on
@@ -319,26 +378,45 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
     // domain load from a clamped valid row and are discarded
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int yr = ybase + (r0 + u) * rows_pass;
+      const int yr = yg + u * rows_pass;
       const bool valid = r0 + u < npt && yr < ny;
       const int y = valid ? yr : ny - 1;
       const uint32_t here = (uint32_t)y * pitch + x;
-      nw[u] = (LABELS && has_lab) ? gbl(D.nodew)[here] : (uint16_t)0;
-      const bool wall = !(LABELS && has_lab) &&
-                        ((wally && (y == 0 || y == ny - 1)) || (wallx && (x == 0 || x == nx - 1)));
+      const uint16_t w = has_lab ? gbl(D.nodew)[here] : (uint16_t)0;
+      nw[u] = valid ? w : (uint16_t)0;  // a clamped row's word must not act
+      const bool wall =
+          walls && ((wally && (y == 0 || y == ny - 1)) || (wallx && (x == 0 || x == nx - 1)));
       act[u] = valid && !wall;
-      unk[u] = pull_node<ST, FEAT, R>(D, src, plane, y, here, LABELS && has_lab, col, col_out,
-                                      col_wall, d[u]);
+      uint32_t row[3];
+      src_rows(y, ny, pitchB, planeB, pery, row);
+      pull_node<T>(src, planeB, row[1] + col[1], row, col, raw[u]);
     }
+    // phase 2: boundary reconstruction, collision, stores
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      const int y = yg + u * rows_pass;
+      if (sizeof(T) >= 4 && has_lab && (nw[u] & NODE_SOLID) && r0 + u < npt && y < ny) {
+        // 32/64-bit storage (bandwidth-bound): a solid node writes zero into
+        // every slot no fluid neighbour mirror-writes, so each slot of the
+        // buffer is written once a step and no cache line is stored in part
+        // (a partial line costs the memory a read-modify-write)
+        const uint32_t keep = nw[u] & 0xffu;  // bit i-1: slot i is a mirror slot
+        const uint32_t hB = (uint32_t)y * pitchB + col[1];
+        stb<T>(dst, hB, T(0));
+#pragma unroll
+        for (int i = 1; i < 9; ++i)
+          if (!((keep >> (i - 1)) & 1u)) stb<T>(dst, (uint32_t)i * planeB + hB, T(0));
+        continue;
+      }
       if (!act[u] || (nw[u] & NODE_SOLID)) continue;
-      const int y = ybase + (r0 + u) * rows_pass;
-      const uint32_t here = (uint32_t)y * pitch + x;
-      if (pressx && unk[u]) {
-        // 2/3 + 2 (1/6) = 1 exactly in the chosen constants
+      R e[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) e[i] = (R)S::raw_dec(raw[u].get(i));
+      if (face) {
+        // 2/3 + 2 (1/6) = 1 exactly in the chosen constants; unscaled values
         const R half = R(0.5), third2 = R(2) / R(3), sixth = (R(1) - third2) * R(0.5);
-        R *e = d[u];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) e[i] *= R(1) / R(kscale<ST>(i));
         if (x == 0) {
           const R s = e[0] + e[2] + e[4] + R(2) * (e[3] + e[6] + e[7]);
           const R rux = (par<R>(D.rho_in, D.rho_in_f) - par<R>(D.rho0, D.rho0_f)) - s;
@@ -352,25 +430,41 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
           e[7] = e[5] + half * (e[2] - e[4]) - sixth * rux;
           e[6] = e[8] - half * (e[2] - e[4]) - sixth * rux;
         }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) e[i] *= R(kscale<ST>(i));
       }
       const uint32_t node = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
-      collide_node<ST, FEAT, PLM, R>(D, d[u], node, step);
-      const R drho = ((d[u][0] + d[u][1]) + (d[u][2] + d[u][3])) +
-                     ((d[u][4] + d[u][5]) + (d[u][6] + d[u][7])) + d[u][8];
-      bad = bad || !(fabs(drho) < R(1e30));
-      store_node<ST, R>(D, dst, plane, here, d[u], node, step);
-      if (LABELS && (nw[u] & 0xffu)) {
-        // mirror writes: the pull along i from the solid source x - e_i will
-        // read this node's post-collision opposite population there
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-          if (!((nw[u] >> (i - 1)) & 1u)) continue;
-          int sy = y - cy(i);
-          sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
-          const uint32_t so = (uint32_t)sy * pitch + (uint32_t)col[1 + cx(i)];
-          store_one<ST, R>(D, dst + i * plane, so, i, d[u][opp(i)], node, step);
-        }
+      collide_node<ST, FEAT, PLM, R>(D, e, node, step);
+      bad = bad || !(fabs(scaled_drho<ST, R>(e)) < R(1e30));
+      uint32_t row[3];  // rows y + 1, y, y - 1; all inside the domain for a computed node
+      src_rows(y, ny, pitchB, planeB, true, row);
+      const uint32_t hereB = row[1] + col[1];
+      uint32_t mb = nw[u] & 0xffu;
+      if (walls) {
+        const uint32_t wall_rows =
+            wally ? (y == 1 ? dirs_cy(1) : 0u) | (y == ny - 2 ? dirs_cy(-1) : 0u) : 0u;
+        mb = (wall_cols | wall_rows) & cols_in;
       }
+      // the rounding mode is uniform: each branch keeps its stores, so neither
+      // conversion is evaluated for the other
+      auto emit = [&](auto sr_tag) {
+        T q[9];
+        encode_node<ST, R, decltype(sr_tag)::value>(D, e, node, step, q);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) stb<T>(dst, (uint32_t)i * planeB + hereB, q[i]);
+        // mirror writes: the pull along i from the solid source x - e_i will
+        // read this node's post-collision opposite population there, stored
+        // exactly as the node's own slot of that direction
+        if (mb) {
+#pragma unroll
+          for (int i = 1; i < 9; ++i) {
+            if (!((mb >> (i - 1)) & 1u)) continue;
+            stb<T>(dst, (uint32_t)i * planeB + (row[1 + cy(i)] + col[1 + cx(i)]), q[opp(i)]);
+          }
+        }
+      };
+      if ((ST == ST_F16 || ST == ST_BF16) && (D.feat & F_STOCH)) emit(std::true_type{});
+      else emit(std::false_type{});
     }
   }
   if (bad) atomicOr(D.health, HEALTH_NONFINITE);
@@ -404,7 +498,7 @@ __global__ __launch_bounds__(256) void k_init(const DevDomain *__restrict__ Dp, 
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const R eu = R(3) * (R(cx(i)) * ux + R(cy(i)) * uy);
-      d[i] = wgt<R>(i) * (A + rho * (eu + R(0.5) * eu * eu));
+      d[i] = R(kscale<ST>(i)) * (wgt<R>(i) * (A + rho * (eu + R(0.5) * eu * eu)));
     }
   } else {
 #pragma unroll

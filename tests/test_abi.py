@@ -47,6 +47,8 @@ def _desc(**kw):
     (dict(power_law=1, n_index=0.5, K=0.01, tau_min=0.4, tau_max=2.5), "power law"),
     (dict(bc_x=2, rho_in=0.0, rho_out=1.0), "pressure"), (dict(init_kind=1), "INIT_FIELDS"),
     (dict(compute=2), "compute"),
+    # a population buffer must span fewer than 2^32 bytes (32-bit sweep offsets)
+    (dict(nx=16384, ny=8192, storage=1), "too large"), (dict(nx=8192, ny=8192, storage=0), "too large"),
 ])
 def test_validation_errors(bad, msg):
     from paper_2006_12910_amd import lb
@@ -55,6 +57,15 @@ def test_validation_errors(bad, msg):
     st = lib.lb_workspace_bytes(C.byref(_desc(**bad)), C.byref(n))
     assert st == lb.LB_EINVAL
     assert msg.lower() in lib.lb_last_error().decode().lower()
+
+
+def test_largest_buffers_within_the_offset_limit_are_accepted():
+    from paper_2006_12910_amd import lb
+    lib = lb.library()
+    n = C.c_size_t()
+    for nx, ny, storage in ((8192, 8192, 2), (8192, 8192, 1), (10880, 10880, 1), (15360, 15360, 3)):
+        assert lib.lb_workspace_bytes(C.byref(_desc(nx=nx, ny=ny, storage=storage)), C.byref(n)) == 0
+        assert n.value > 2 * 9 * nx * ny * (4 if storage == 1 else 2)
 
 
 def test_workspace_size_covers_both_population_buffers():
