@@ -1,4 +1,4 @@
-// Storage-independent kernels: particle update, relabelling, mass total,
+// Storage-independent kernels: initial particle labels, mass total,
 // noise diagnostic, step counter.
 #define LBK_COMMON_KERNELS 1
 #include "aux_impl.h"
@@ -7,14 +7,8 @@
 
 namespace lbk {
 
-void launch_pupdate(const DevDomain *doms, const PItem *items, int nitems, int kstep,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(k_pupdate, dim3((nitems + 63) / 64), dim3(64), 0, s, doms, items, nitems,
-                     kstep);
-}
-void launch_relabel(const DevDomain *doms, const PItem *items, int nitems, int kstep,
-                    int time_offset, hipStream_t s) {
-  hipLaunchKernelGGL(k_relabel, dim3(nitems), dim3(256), 0, s, doms, items, kstep, time_offset);
+void launch_relabel(const DevDomain *doms, const PItem *items, int nitems, hipStream_t s) {
+  hipLaunchKernelGGL(k_relabel, dim3(nitems), dim3(256), 0, s, doms, items);
 }
 void launch_masks_full(const DevDomain *dom, int nx, int ny, hipStream_t s) {
   const long long n = (long long)nx * ny;

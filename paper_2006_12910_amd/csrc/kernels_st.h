@@ -26,14 +26,11 @@ void init_l(const DevDomain *dom, const double *rho, const double *ux, const dou
   hipLaunchKernelGGL((k_init<ST, FEAT, PLM, WIDE>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                      dom, rho, ux, uy, row0, nrows);
 }
-void link_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
-  hipLaunchKernelGGL((k_link<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
+void pre_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
+  hipLaunchKernelGGL((k_pre<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
 }
-void swap_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
-  hipLaunchKernelGGL((k_link_swap<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
-}
-void cover_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
-  hipLaunchKernelGGL((k_cover<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
+void post_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
+  hipLaunchKernelGGL((k_post<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
 }
 void mass_l(const DevDomain *dom, double *partials, int blocks, hipStream_t s) {
   hipLaunchKernelGGL((k_mass_partial<ST>), dim3(blocks), dim3(256), 0, s, dom, partials);
@@ -64,9 +61,8 @@ void mirror_l(const DevDomain *dom, int nx, int ny, hipStream_t s) {
 template <int FEAT, int PLM, int WIDE> void fill(KernelSet *k) {
   k->sweep = sweep_l<FEAT, PLM, WIDE>;
   k->init = init_l<FEAT, PLM, WIDE>;
-  k->link = link_l;
-  k->cover = cover_l;
-  k->swap = swap_l;
+  k->pre = pre_l;
+  k->post = post_l;
   k->mass_partial = mass_l;
   k->moments = moments_l;
   k->export_f = export_l;

@@ -10,9 +10,9 @@ struct KernelSet {
                 hipStream_t s);
   void (*init)(const DevDomain *dom, const double *rho, const double *ux, const double *uy,
                int row0, int nrows, int pitch, hipStream_t s);
-  void (*link)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
-  void (*cover)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
-  void (*swap)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
+  // particle coupling before and after the sweep (one workgroup per particle)
+  void (*pre)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
+  void (*post)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
   void (*mass_partial)(const DevDomain *dom, double *partials, int blocks, hipStream_t s);
   void (*moments)(const DevDomain *dom, double *rho, double *ux, double *uy, int row0, int nrows,
                   int nx, hipStream_t s);
@@ -29,10 +29,7 @@ bool kernels_f32(int feat, int plm, int wide, KernelSet *k);
 bool kernels_f16(int feat, int plm, int wide, KernelSet *k);
 bool kernels_bf16(int feat, int plm, int wide, KernelSet *k);
 
-void launch_pupdate(const DevDomain *doms, const PItem *items, int nitems, int kstep,
-                    hipStream_t s);
-void launch_relabel(const DevDomain *doms, const PItem *items, int nitems, int kstep,
-                    int time_offset, hipStream_t s);
+void launch_relabel(const DevDomain *doms, const PItem *items, int nitems, hipStream_t s);
 void launch_masks_full(const DevDomain *dom, int nx, int ny, hipStream_t s);
 void launch_mass_final(const DevDomain *dom, const double *partials, int n, double *out,
                        hipStream_t s);

@@ -238,16 +238,9 @@ lb_status check_health(lb_domain *d) {
 void record_steps(const KernelSet &ks, const DevDomain *doms, const int *prefix, int ndom,
                   int blocks, const PItem *items, int nitems, int n, hipStream_t s) {
   for (int k = 0; k < n; ++k) {
-    if (nitems > 0) {
-      ks.link(doms, items, nitems, k, s);
-      launch_pupdate(doms, items, nitems, k, s);
-      ks.swap(doms, items, nitems, k, s);
-    }
+    if (nitems > 0) ks.pre(doms, items, nitems, k, s);
     ks.sweep(doms, prefix, ndom, k, blocks, s);
-    if (nitems > 0) {
-      ks.cover(doms, items, nitems, k, s);
-      launch_relabel(doms, items, nitems, k, 1, s);
-    }
+    if (nitems > 0) ks.post(doms, items, nitems, k, s);
   }
   launch_advance(doms, ndom, n, s);
 }
@@ -545,7 +538,7 @@ lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_
   HIPCHK(hipMemcpyAsync(d->ditems(), items.data(), d->np * sizeof(PItem), hipMemcpyHostToDevice, d->stream));
   lb_status s = push_desc(d);
   if (s != LB_OK) return s;
-  launch_relabel(d->ddesc(), d->ditems(), d->np, 0, 0, d->stream);
+  launch_relabel(d->ddesc(), d->ditems(), d->np, d->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(d->stream));
   d->graphs.clear();

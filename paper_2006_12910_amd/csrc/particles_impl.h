@@ -1,20 +1,20 @@
 // particles_impl.h -- particle coupling kernels (Sec. 3).
 //
 // Per step, for the state at time T (post-collision populations f*(T), labels
-// G(T), particle state P(T)):
-//   k_link        one workgroup per particle: enumerate the exterior pulls
-//                 crossing its surface inside its bounding box, compact them
-//                 into an LDS list (deterministic block scan), and reduce the
-//                 momentum exchange of Eq. MP1 and its torque (Eq. MP4) in
-//                 FP64; the same scan sums the repulsion from solid nodes
-//                 (Eq. MP2).
-//   k_pupdate     one lane per particle: particle-particle repulsion and the
-//                 Newton-Euler update of Eqs. MP5-MP6 into P(T+1).
-//   k_link_swap   moving-wall bounce-back written into the crossing links'
-//                 pull slots, so the sweep pulls unconditionally.
-//   k_cover       after the sweep: covered/uncovered-node force (Eq. MP3) of
-//                 the nodes whose label changes from G(T) to G(T+1).
-//   k_relabel     write G(T+1).
+// G(T), particle state P(T)), two kernels with one workgroup per particle
+// bracket the sweep:
+//   k_pre    before the sweep: enumerate the exterior pulls crossing the
+//            particle's surface inside its bounding box, compact them into an
+//            LDS list (deterministic block scan); for each link add the
+//            momentum exchange of Eq. MP1 and its torque (Eq. MP4) in FP64
+//            and write the moving-wall bounce-back (Eqs. MP7-MP8) into the
+//            link's two pull slots, so the sweep pulls unconditionally; sum
+//            the repulsion from solid nodes (Eq. MP2); then one lane adds the
+//            particle-particle repulsion and takes the Newton-Euler step of
+//            Eqs. MP5-MP6 into P(T+1).
+//   k_post   after the sweep: the covered/uncovered-node force (Eq. MP3) of
+//            the nodes whose label changes from G(T) to G(T+1), and G(T+1)
+//            written into the label plane.
 // All reductions run in a fixed order, so results are bit-reproducible.
 #pragma once
 
@@ -82,19 +82,73 @@ __device__ __forceinline__ double lj_mag(const DevDomain &D, double gap) {
   return D.lj_psi * pow(g / D.lj_rit, -13.0);
 }
 
+// Particle-particle repulsion and the Newton-Euler step (Eqs. MP2, MP5-MP6)
+// of particle p from P(T) (all particles, `cur`) and its total force F into
+// P(T+1).
+__device__ __forceinline__ void advance_particle(const DevDomain &D, int p, const PState *cur,
+                                                 PState *nxt, const PForce &F) {
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  const PState P = cur[p];
+  double lx = 0.0, ly = 0.0;
+  if (D.lj_psi > 0.0) {
+    for (int q = 0; q < D.np; ++q) {
+      if (q == p) continue;
+      const PState &Q = cur[q];
+      const double dx = min_image(P.x - Q.x, D.nx, perx), dy = min_image(P.y - Q.y, D.ny, pery);
+      const double dist = sqrt(dx * dx + dy * dy);
+      const double gap = dist - P.radius - Q.radius;
+      if (gap > D.lj_rit || !(dist > 0.0)) continue;
+      const double m = lj_mag(D, gap);
+      lx += m * dx / dist;
+      ly += m * dy / dist;
+    }
+  }
+  const double fx = F.fx + F.cx_ + (lx + F.ljx);
+  const double fy = F.fy + F.cy_ + (ly + F.ljy);
+  const double tq = F.torque + F.ctorque;
+  PState N = P;
+  N.fx = fx;
+  N.fy = fy;
+  N.torque = tq;
+  if (!(P.flags & 1)) {
+    const double buoy = 1.0 - D.rho0 / (P.rho_ratio * D.rho0);
+    N.ux = P.ux + fx / P.mass + buoy * D.gx;
+    N.uy = P.uy + fy / P.mass + buoy * D.gy;
+    N.omega = P.omega + tq / P.inertia;
+    N.x = P.x + P.ux;
+    N.y = P.y + P.uy;
+    if (perx) { if (N.x >= D.nx) N.x -= D.nx; if (N.x < 0.0) N.x += D.nx; }
+    if (pery) { if (N.y >= D.ny) N.y -= D.ny; if (N.y < 0.0) N.y += D.ny; }
+    if (!(fabs(N.ux) < 0.5 && fabs(N.uy) < 0.5)) atomicOr(D.health, HEALTH_FAST_PARTICLE);
+  }
+  nxt[p] = N;
+}
+
+// Before the sweep of step T -> T+1, one workgroup per particle p.
+//
+// Links: an exterior fluid node x and an interior node s = x - e_d of p.  The
+// pull into x along d and the pull into s along -e_d both bounce off the
+// surface point r_b = x - e_d/2 moving at u_b = U + Omega z x (r_b - r_c):
+//   f_d(x)  <- f*_{-d}(x) + M,   f_{-d}(s) <- f*_d(s) - M,   M = 6 rho0 w_d (u_b . e_d).
+// The slots those two pulls read -- (d, s) and (-d, x) -- are read by no other
+// pull and by no other link (s lies inside one particle only), so each link's
+// thread reads f*_{-d}(x) for the force and writes the bounced values there
+// in place, and the sweep pulls every direction unconditionally.
 template <int ST>
-__global__ __launch_bounds__(256) void k_link(const DevDomain *__restrict__ doms,
-                                              const PItem *__restrict__ items, int kstep) {
+__global__ __launch_bounds__(256) void k_pre(const DevDomain *__restrict__ doms,
+                                             const PItem *__restrict__ items, int kstep) {
   using S = Store<ST>;
   using T = typename S::T;
+  using RS = typename S::R;
   __shared__ uint32_t links[LINK_CAP];
   __shared__ int scan_sh[4];
   __shared__ double red[4][5];
   const PItem it = items[blockIdx.x];
   const DevDomain &D = doms[it.dom];
   const uint64_t T0 = *D.tstep + (uint64_t)kstep;
-  const PState P = D.pstate[T0 & 1][it.p];
-  const T *src = (const T *)D.f[T0 & 1];
+  const PState *cur = D.pstate[T0 & 1];
+  const PState P = cur[it.p];
+  T *f = (T *)D.f[T0 & 1];
   const size_t plane = (size_t)D.ny * D.pitch;
   const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
   const uint8_t mine = (uint8_t)(LBL_PART0 + it.p);
@@ -148,9 +202,10 @@ __global__ __launch_bounds__(256) void k_link(const DevDomain *__restrict__ doms
     }
   }
   __syncthreads();
+  // the host admits no radius whose box could hold more links than the list
   if (total > LINK_CAP && threadIdx.x == 0) atomicOr(D.health, HEALTH_LINK_OVERFLOW);
   const int nl = min(total, LINK_CAP);
-  // pass 3: momentum exchange of each link, FP64
+  // pass 3: momentum exchange (FP64) and moving-wall bounce-back of each link
   double acc[5] = {0.0, 0.0, 0.0, ljx, ljy};
   for (int e = threadIdx.x; e < nl; e += 256) {
     const uint32_t rec = links[e];
@@ -158,9 +213,14 @@ __global__ __launch_bounds__(256) void k_link(const DevDomain *__restrict__ doms
     int x = bx0 + j % W, y = by0 + j / W;
     wrap_coord(x, D.nx, perx);
     wrap_coord(y, D.ny, pery);
+    int sx = x - cx(dir), sy = y - cy(dir);
+    wrap_coord(sx, D.nx, perx);
+    wrap_coord(sy, D.ny, pery);
+    const uint32_t here = (uint32_t)y * D.pitch + x, so = (uint32_t)sy * D.pitch + sx;
     const int o = opp(dir);
-    const double fopp = wgt<double>(o) * D.rho0 +
-                        (double)S::load(src + o * plane, (uint32_t)y * D.pitch + x, o);
+    const double a = (double)S::load(f + o * plane, here, o);
+    const double b = (double)S::load(f + dir * plane, so, dir);
+    const double fopp = wgt<double>(o) * D.rho0 + a;
     const double bxr = x - 0.5 * cx(dir), byr = y - 0.5 * cy(dir);
     const double rx = min_image(bxr - P.x, D.nx, perx), ry = min_image(byr - P.y, D.ny, pery);
     const double vx = P.ux - P.omega * ry, vy = P.uy + P.omega * rx;
@@ -170,115 +230,22 @@ __global__ __launch_bounds__(256) void k_link(const DevDomain *__restrict__ doms
     acc[0] += dpx;
     acc[1] += dpy;
     acc[2] += rx * dpy - ry * dpx;
+    const double M = 6.0 * D.rho0 * wgt<double>(dir) * ue;
+    S::put(f + dir * plane, so, dir, (RS)(a + M), 0u);
+    S::put(f + o * plane, here, o, (RS)(b - M), 0u);
   }
   block_sum<5>(acc, red);
   if (threadIdx.x == 0) {
-    PForce &F = D.pforce[it.p];
+    PForce F = D.pforce[it.p];
     F.fx = acc[0];
     F.fy = acc[1];
     F.torque = acc[2];
     F.ljx = acc[3];
     F.ljy = acc[4];
+    D.pforce[it.p] = F;
+    advance_particle(D, it.p, cur, D.pstate[(T0 + 1) & 1], F);
   }
 }
-
-// Moving-wall bounce-back as a pre-pass (Eqs. MP7-MP8).  For every link
-// between an exterior fluid node x and an interior node s = x - e_d of particle
-// p, the pull into x along d and the pull into s along -e_d both bounce off the
-// surface point r_b = x - e_d/2 moving at u_b = U + Omega z x (r_b - r_c):
-//   f_d(x)  <- f*_{-d}(x) + M,   f_{-d}(s) <- f*_d(s) - M,   M = 6 rho0 w_d (u_b . e_d).
-// The slots those two pulls read -- (d, s) and (-d, x) -- are read by no other
-// pull, so writing the bounced values into them in place lets the sweep pull
-// every direction unconditionally.  Each link is handled once, by the particle
-// that contains s; runs after k_link has read the unmodified f*.
-template <int ST>
-__global__ __launch_bounds__(256) void k_link_swap(const DevDomain *__restrict__ doms,
-                                                   const PItem *__restrict__ items, int kstep) {
-  using S = Store<ST>;
-  using T = typename S::T;
-  using RS = typename S::R;
-  const PItem it = items[blockIdx.x];
-  const DevDomain &D = doms[it.dom];
-  const uint64_t T0 = *D.tstep + (uint64_t)kstep;
-  const PState P = D.pstate[T0 & 1][it.p];
-  T *f = (T *)D.f[T0 & 1];
-  const size_t plane = (size_t)D.ny * D.pitch;
-  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
-  const uint8_t mine = (uint8_t)(LBL_PART0 + it.p);
-  const int reach = (int)ceil(P.radius) + 2;
-  const int W = 2 * reach + 2;
-  const int bx0 = (int)floor(P.x) - reach, by0 = (int)floor(P.y) - reach;
-  for (int j = threadIdx.x; j < W * W; j += 256) {
-    int x = bx0 + j % W, y = by0 + j / W;
-    if (!wrap_coord(x, D.nx, perx) || !wrap_coord(y, D.ny, pery)) continue;
-    const uint32_t here = (uint32_t)y * D.pitch + x;
-    if (D.label[here] != LBL_FLUID) continue;
-    for (int d = 1; d < 9; ++d) {
-      int sx = x - cx(d), sy = y - cy(d);
-      if (!wrap_coord(sx, D.nx, perx) || !wrap_coord(sy, D.ny, pery)) continue;
-      const uint32_t so = (uint32_t)sy * D.pitch + sx;
-      if (D.label[so] != mine) continue;
-      const double bxr = x - 0.5 * cx(d), byr = y - 0.5 * cy(d);
-      const double rx = min_image(bxr - P.x, D.nx, perx), ry = min_image(byr - P.y, D.ny, pery);
-      const double ue = (P.ux - P.omega * ry) * cx(d) + (P.uy + P.omega * rx) * cy(d);
-      const double M = 6.0 * D.rho0 * wgt<double>(d) * ue;
-      const int o = opp(d);
-      const double a = (double)S::load(f + o * plane, here, o);
-      const double b = (double)S::load(f + d * plane, so, d);
-      S::put(f + d * plane, so, d, (RS)(a + M), 0u);
-      S::put(f + o * plane, here, o, (RS)(b - M), 0u);
-    }
-  }
-}
-
-#ifdef LBK_COMMON_KERNELS
-__global__ void k_pupdate(const DevDomain *__restrict__ doms, const PItem *__restrict__ items,
-                          int nitems, int kstep) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nitems) return;
-  const PItem it = items[i];
-  const DevDomain &D = doms[it.dom];
-  const uint64_t T0 = *D.tstep + (uint64_t)kstep;
-  const PState *cur = D.pstate[T0 & 1];
-  PState *nxt = D.pstate[(T0 + 1) & 1];
-  const PState P = cur[it.p];
-  const PForce F = D.pforce[it.p];
-  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
-  double lx = 0.0, ly = 0.0;
-  if (D.lj_psi > 0.0) {
-    for (int q = 0; q < D.np; ++q) {
-      if (q == it.p) continue;
-      const PState &Q = cur[q];
-      const double dx = min_image(P.x - Q.x, D.nx, perx), dy = min_image(P.y - Q.y, D.ny, pery);
-      const double dist = sqrt(dx * dx + dy * dy);
-      const double gap = dist - P.radius - Q.radius;
-      if (gap > D.lj_rit || !(dist > 0.0)) continue;
-      const double m = lj_mag(D, gap);
-      lx += m * dx / dist;
-      ly += m * dy / dist;
-    }
-  }
-  const double fx = F.fx + F.cx_ + (lx + F.ljx);
-  const double fy = F.fy + F.cy_ + (ly + F.ljy);
-  const double tq = F.torque + F.ctorque;
-  PState N = P;
-  N.fx = fx;
-  N.fy = fy;
-  N.torque = tq;
-  if (!(P.flags & 1)) {
-    const double buoy = 1.0 - D.rho0 / (P.rho_ratio * D.rho0);
-    N.ux = P.ux + fx / P.mass + buoy * D.gx;
-    N.uy = P.uy + fy / P.mass + buoy * D.gy;
-    N.omega = P.omega + tq / P.inertia;
-    N.x = P.x + P.ux;
-    N.y = P.y + P.uy;
-    if (perx) { if (N.x >= D.nx) N.x -= D.nx; if (N.x < 0.0) N.x += D.nx; }
-    if (pery) { if (N.y >= D.ny) N.y -= D.ny; if (N.y < 0.0) N.y += D.ny; }
-    if (!(fabs(N.ux) < 0.5 && fabs(N.uy) < 0.5)) atomicOr(D.health, HEALTH_FAST_PARTICLE);
-  }
-  nxt[it.p] = N;
-}
-#endif  // LBK_COMMON_KERNELS
 
 // Label of node (x, y) from the particle state Pn: first particle (in index
 // order) whose disc strictly contains the node, else fluid.
@@ -292,14 +259,18 @@ __device__ __forceinline__ uint8_t new_label(const DevDomain &D, const PState *P
   return LBL_FLUID;
 }
 
-// Covered/uncovered nodes of particle p between G(T) (the label plane, not yet
-// rewritten) and G(T+1) (from P(T+1)): F = +rho (u - U_p) for a covered node,
-// -rho (u - U_p) for an uncovered one, with rho and u = j/rho + g/2 the
-// moments of f(T+1) (recovered from f*(T+1): j(f*) = j(f) + rho g), applied
-// in the next step (Eq. MP3).
+// After the sweep of step T -> T+1, one workgroup per particle p, over a box
+// around P(T+1) that holds every node p leaves or enters (particles move less
+// than half a node per step).  G(T) and G(T+1) of a non-solid node are the
+// first-particle rule applied to P(T) and P(T+1), so no workgroup reads the
+// label plane while others rewrite it (overlapping boxes write identical
+// values).  Covered node (enters p): F = +rho (u - U_p); uncovered node:
+// -rho (u - U_p), with rho and u = j/rho + g/2 the moments of f(T+1)
+// (recovered from f*(T+1): j(f*) = j(f) + rho g), applied in the next step
+// (Eq. MP3).
 template <int ST>
-__global__ __launch_bounds__(256) void k_cover(const DevDomain *__restrict__ doms,
-                                               const PItem *__restrict__ items, int kstep) {
+__global__ __launch_bounds__(256) void k_post(const DevDomain *__restrict__ doms,
+                                              const PItem *__restrict__ items, int kstep) {
   using S = Store<ST>;
   using T = typename S::T;
   __shared__ double red[4][3];
@@ -307,6 +278,7 @@ __global__ __launch_bounds__(256) void k_cover(const DevDomain *__restrict__ dom
   const DevDomain &D = doms[it.dom];
   const uint64_t T1 = *D.tstep + (uint64_t)kstep + 1;
   const PState *Pn = D.pstate[T1 & 1];
+  const PState *Po = D.pstate[(T1 - 1) & 1];
   const PState P = Pn[it.p];
   const T *src = (const T *)D.f[T1 & 1];
   const size_t plane = (size_t)D.ny * D.pitch;
@@ -320,9 +292,10 @@ __global__ __launch_bounds__(256) void k_cover(const DevDomain *__restrict__ dom
     int x = bx0 + j % W, y = by0 + j / W;
     if (!wrap_coord(x, D.nx, perx) || !wrap_coord(y, D.ny, pery)) continue;
     const uint32_t here = (uint32_t)y * D.pitch + x;
-    const uint8_t l0 = D.label[here];
-    if (l0 == LBL_SOLID) continue;
+    if (D.nodew[here] & NODE_SOLID) continue;
+    const uint8_t l0 = new_label(D, Po, x, y);
     const uint8_t l1 = new_label(D, Pn, x, y);
+    if (l1 != l0) D.label[here] = l1;
     if ((l0 == mine) == (l1 == mine)) continue;
     const double sign = l1 == mine ? 1.0 : -1.0;
     double drho = 0.0, jx = 0.0, jy = 0.0;
@@ -350,15 +323,13 @@ __global__ __launch_bounds__(256) void k_cover(const DevDomain *__restrict__ dom
 }
 
 #ifdef LBK_COMMON_KERNELS
-// Write G(T+1) inside particle p's box (every changed node lies in the box of
-// the particle it leaves or enters; concurrent boxes write identical values).
+// Labels of the current particle state inside each particle's box, from the
+// label plane's own values (used once the particles are added).
 __global__ __launch_bounds__(256) void k_relabel(const DevDomain *__restrict__ doms,
-                                                 const PItem *__restrict__ items, int kstep,
-                                                 int time_offset) {
+                                                 const PItem *__restrict__ items) {
   const PItem it = items[blockIdx.x];
   const DevDomain &D = doms[it.dom];
-  const uint64_t T1 = *D.tstep + (uint64_t)kstep + (uint64_t)time_offset;
-  const PState *Pn = D.pstate[T1 & 1];
+  const PState *Pn = D.pstate[*D.tstep & 1];
   const PState P = Pn[it.p];
   const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
   const int reach = (int)ceil(P.radius) + 3;
@@ -374,7 +345,6 @@ __global__ __launch_bounds__(256) void k_relabel(const DevDomain *__restrict__ d
     if (l1 != l0) D.label[here] = l1;
   }
 }
-
 #endif  // LBK_COMMON_KERNELS
 
 }  // namespace lbk

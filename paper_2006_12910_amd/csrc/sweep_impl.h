@@ -256,7 +256,7 @@ template <class T> __device__ __forceinline__ void stb(char LBK_GLOBAL *b, uint3
 // slot holds this node's own opposite population, written there by the
 // previous step's store (halfway bounce-back by mirror writes); where the
 // pull crosses a particle surface, the slot holds the moving-wall bounced
-// value, put there by the particle pre-pass (k_link_swap).  So the loads have
+// value, put there by the particle pre-pass (k_pre).  So the loads have
 // no data-dependent address.  A source beyond a density face is read from the
 // node's own column: those populations are unknown and the face
 // reconstruction replaces them.  row[] and col[] are the byte offsets of the
