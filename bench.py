@@ -122,11 +122,22 @@ def algorithmic_bytes(specs, masks, sbytes):
     return total
 
 
-def run_variant(storage, specs, masks, steps, warmup, tune):
+def parse_tiles(text):
+    """{"open/class3": "64x4", ...} (the "tiles" object of a bench line) ->
+    {(False, 3): (64, 4), ...}"""
+    out = {}
+    for k, v in json.loads(text).items():
+        kind, cls = k.split("/class")
+        tw, rows = v.split("x")
+        out[(kind == "obstacles", int(cls))] = (int(tw), int(rows))
+    return out
+
+
+def run_variant(storage, specs, masks, steps, warmup, tune, fixed_tiles=None):
     import torch
     from paper_2006_12910_amd import lb
     t0 = time.time()
-    tiles = autotune_tiles(storage, specs, masks) if tune else None
+    tiles = fixed_tiles if fixed_tiles else (autotune_tiles(storage, specs, masks) if tune else None)
     doms = build_variant(storage, specs, masks, tiles)
     batch = lb.Batch(doms)
     torch.cuda.synchronize()
@@ -207,6 +218,9 @@ def main():
                     help="seconds of oracle work for the CPU baseline and the L2 sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline and L2 sample")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes instead of the autotuner's")
+    ap.add_argument("--tiles", default=None, metavar="JSON",
+                    help='tile shape per size class instead of tuning, e.g. the "tiles" object of an '
+                         'earlier line (to profile the configuration that line measured)')
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="before the workload, copy a buffer of this size 5 times (a kernel of "
                          "known traffic for scaling profiler byte counters)")
@@ -251,7 +265,8 @@ def main():
 
     results = {}
     for v in variants:
-        doms, batch, ms, tiles = run_variant(v, specs, masks, args.steps, args.warmup, not args.no_tune)
+        doms, batch, ms, tiles = run_variant(v, specs, masks, args.steps, args.warmup, not args.no_tune,
+                                             parse_tiles(args.tiles) if args.tiles else None)
         mlups = sites * args.steps / (ms * 1e-3) / 1e6
         bytes_alg = algorithmic_bytes(specs, masks, STORAGE_BYTES[v])
         gbs = bytes_alg * args.steps / (ms * 1e-3) / 1e9

@@ -180,6 +180,13 @@ lb_status lb_set_populations(lb_domain *d, const double *host_dev_f);
 #define LB_OPT_TILE_WIDTH 2    /* threads per tile row: 64, 128 or 256            */
 #define LB_OPT_ROWS_PER_THREAD 3 /* nodes per thread along y: 1..16               */
 #define LB_OPT_GRAPH_CHUNK 4   /* steps per captured graph, 1..4096 (default 256) */
+/* 0 (default): the particle velocity update is Eqs. MP5-MP6 with the force and
+ * torque of the current step, as the paper writes it.  1: with the mean of the
+ * current and the previous step's force and torque (the previous ones of a
+ * newly added particle are zero).  The explicit update lets a period-two
+ * oscillation of neighbouring near-neutral discs grow (e.g. density ratio 1.05
+ * at tau = 0.7); the mean damps it.  Not changeable while in a batch. */
+#define LB_OPT_FORCE_AVERAGE 5
 lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value);
 lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value);
 

@@ -635,7 +635,11 @@ static void node_moments(const lbo_sim *s, const double *f, int x, int y, double
 }
 
 /* Newton-Euler (Eqs. MP5, MP6) with m = rho_p pi R^2, I = m R^2 / 2, then
- * relabelling and the covered/uncovered node terms for the next step. */
+ * relabelling and the covered/uncovered node terms for the next step.  With
+ * force_average the velocity update takes the mean of this step's and the
+ * previous step's total force and torque (the previous ones are the
+ * particle's fx, fy, torque before they are overwritten here): an optional
+ * stabilisation of the explicit update, not part of Eqs. MP5-MP6. */
 static void move_particles(lbo_sim *s, double lj[][2]) {
   const lbo_params *p = &s->p;
   int perx = p->bc_x == LBO_PERIODIC, pery = p->bc_y == LBO_PERIODIC;
@@ -644,6 +648,12 @@ static void move_particles(lbo_sim *s, double lj[][2]) {
     double Fx = s->flink[q][0] + s->fcu[q][0] + lj[q][0];
     double Fy = s->flink[q][1] + s->fcu[q][1] + lj[q][1];
     double T = s->flink[q][2] + s->fcu[q][2];
+    double Fxu = Fx, Fyu = Fy, Tu = T;
+    if (p->force_average) {
+      Fxu = 0.5 * (Fx + pq->fx);
+      Fyu = 0.5 * (Fy + pq->fy);
+      Tu = 0.5 * (T + pq->torque);
+    }
     pq->fx = Fx;
     pq->fy = Fy;
     pq->torque = T;
@@ -652,9 +662,9 @@ static void move_particles(lbo_sim *s, double lj[][2]) {
     double m = rhop * M_PI * pq->radius * pq->radius;
     double I = 0.5 * m * pq->radius * pq->radius;
     double ux0 = pq->ux, uy0 = pq->uy;
-    pq->ux = ux0 + Fx / m + (1.0 - p->rho0 / rhop) * p->gx;
-    pq->uy = uy0 + Fy / m + (1.0 - p->rho0 / rhop) * p->gy;
-    pq->omega = pq->omega + T / I;
+    pq->ux = ux0 + Fxu / m + (1.0 - p->rho0 / rhop) * p->gx;
+    pq->uy = uy0 + Fyu / m + (1.0 - p->rho0 / rhop) * p->gy;
+    pq->omega = pq->omega + Tu / I;
     pq->x += ux0;
     pq->y += uy0;
     if (perx) {

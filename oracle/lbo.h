@@ -52,6 +52,9 @@ typedef struct lbo_params {
   double n_index, K;            /* flow index n and consistency xi (Eq. nn1)         */
   double tau_min, tau_max;      /* clamp of tau*                                     */
   double lj_psi, lj_rit, lj_floor; /* repulsion stiffness, threshold, gap floor      */
+  int32_t force_average;        /* 0: Eqs. MP5-MP6 with F_T(t) (the paper);
+                                   1: with (F_T(t) + F_T(t-1)) / 2, F_T(-1) = 0     */
+  int32_t pad_;
 } lbo_params;
 
 enum { LBO_PARTICLE_FIXED = 1 };   /* position and velocities prescribed */

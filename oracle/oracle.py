@@ -26,6 +26,7 @@ class _Params(C.Structure):
         ("power_law", C.c_int32), ("n_index", C.c_double), ("K", C.c_double),
         ("tau_min", C.c_double), ("tau_max", C.c_double),
         ("lj_psi", C.c_double), ("lj_rit", C.c_double), ("lj_floor", C.c_double),
+        ("force_average", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -109,6 +110,7 @@ class OracleParams:
     lj_psi: float = 20.0
     lj_rit: float = 2.5
     lj_floor: float = 0.1
+    force_average: bool = False  # mean of this and the previous step's force in Eq. MP5
     extra: dict = field(default_factory=dict)
 
 
@@ -122,7 +124,8 @@ class Oracle:
         c = _Params(prm.nx, prm.ny, prm.bc_x, prm.bc_y, prm.rho_in, prm.rho_out, prm.tau,
                     prm.rho0, prm.gx, prm.gy, prm.kT, prm.seed & (2**64 - 1),
                     prm.domain_id & 0xFFFFFFFF, int(prm.power_law), prm.n_index, prm.K,
-                    prm.tau_min, prm.tau_max, prm.lj_psi, prm.lj_rit, prm.lj_floor)
+                    prm.tau_min, prm.tau_max, prm.lj_psi, prm.lj_rit, prm.lj_floor,
+                    int(prm.force_average), 0)
         shape = (prm.ny, prm.nx)
         mask = None
         if obstacles is not None:

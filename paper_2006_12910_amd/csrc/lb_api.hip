@@ -657,8 +657,9 @@ lb_status lb_set_populations(lb_domain *d, const double *hf) {
 
 lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
   if (!d) return fail(LB_EINVAL, "null domain");
-  if (d->in_batches && (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD))
-    return fail(LB_ESTATE, "tile options are fixed while the domain is in a batch");
+  if (d->in_batches && (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD ||
+                        key == LB_OPT_FORCE_AVERAGE))
+    return fail(LB_ESTATE, "tile and force options are fixed while the domain is in a batch");
   switch (key) {
     case LB_OPT_USE_GRAPH: d->use_graph = value != 0; break;
     case LB_OPT_TILE_WIDTH:
@@ -673,10 +674,15 @@ lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
       if (value < 1 || value > 4096) return fail(LB_EINVAL, "graph chunk must be in [1, 4096]");
       d->chunk = (int)value;
       break;
+    case LB_OPT_FORCE_AVERAGE:
+      if (value != 0 && value != 1) return fail(LB_EINVAL, "force averaging is 0 or 1");
+      d->hd.feat = value ? (d->hd.feat | F_FAVG) : (d->hd.feat & ~F_FAVG);
+      break;
     default: return fail(LB_EINVAL, "unknown option");
   }
   d->graphs.clear();
-  if (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD) return push_desc(d);
+  if (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD || key == LB_OPT_FORCE_AVERAGE)
+    return push_desc(d);
   return LB_OK;
 }
 
@@ -687,6 +693,7 @@ lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value) {
     case LB_OPT_TILE_WIDTH: *value = d->hd.tile_w; return LB_OK;
     case LB_OPT_ROWS_PER_THREAD: *value = d->hd.rows_per_thread; return LB_OK;
     case LB_OPT_GRAPH_CHUNK: *value = d->chunk; return LB_OK;
+    case LB_OPT_FORCE_AVERAGE: *value = (d->hd.feat & F_FAVG) ? 1 : 0; return LB_OK;
   }
   return fail(LB_EINVAL, "unknown option");
 }

@@ -53,6 +53,7 @@ enum : int {
   F_POWER = 4,     // power-law tau*
   F_PRESSURE = 8,  // Zou-He faces on x
   F_STOCH = 16,    // stochastic rounding of 16-bit storage
+  F_FAVG = 32,     // particle update with the mean of two steps' forces (runtime only)
 };
 // Power-law exponent specialisations.
 enum : int { PL_GENERIC = 0, PL_HALF = 1, PL_3Q = 2, PL_3H = 3 };

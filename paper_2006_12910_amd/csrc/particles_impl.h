@@ -84,7 +84,8 @@ __device__ __forceinline__ double lj_mag(const DevDomain &D, double gap) {
 
 // Particle-particle repulsion and the Newton-Euler step (Eqs. MP2, MP5-MP6)
 // of particle p from P(T) (all particles, `cur`) and its total force F into
-// P(T+1).
+// P(T+1); with F_FAVG the update takes the mean of this step's total force
+// and torque and the previous step's, which P(T) holds.
 __device__ __forceinline__ void advance_particle(const DevDomain &D, int p, const PState *cur,
                                                  PState *nxt, const PForce &F) {
   const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
@@ -106,15 +107,20 @@ __device__ __forceinline__ void advance_particle(const DevDomain &D, int p, cons
   const double fx = F.fx + F.cx_ + (lx + F.ljx);
   const double fy = F.fy + F.cy_ + (ly + F.ljy);
   const double tq = F.torque + F.ctorque;
+  // optional: the mean of this and the previous step's totals (kept in P)
+  const bool avg = (D.feat & F_FAVG) != 0;
+  const double fxu = avg ? 0.5 * (fx + P.fx) : fx;
+  const double fyu = avg ? 0.5 * (fy + P.fy) : fy;
+  const double tqu = avg ? 0.5 * (tq + P.torque) : tq;
   PState N = P;
   N.fx = fx;
   N.fy = fy;
   N.torque = tq;
   if (!(P.flags & 1)) {
     const double buoy = 1.0 - D.rho0 / (P.rho_ratio * D.rho0);
-    N.ux = P.ux + fx / P.mass + buoy * D.gx;
-    N.uy = P.uy + fy / P.mass + buoy * D.gy;
-    N.omega = P.omega + tq / P.inertia;
+    N.ux = P.ux + fxu / P.mass + buoy * D.gx;
+    N.uy = P.uy + fyu / P.mass + buoy * D.gy;
+    N.omega = P.omega + tqu / P.inertia;
     N.x = P.x + P.ux;
     N.y = P.y + P.uy;
     if (perx) { if (N.x >= D.nx) N.x -= D.nx; if (N.x < 0.0) N.x += D.nx; }

@@ -75,8 +75,14 @@ def test_batch_rejects_mixed_arithmetic_and_duplicates():
         lb.Batch([a, a])
     assert e.value.status == lb.LB_EINVAL
     batch = lb.Batch([a])
-    with pytest.raises(lb.LBError) as e:
-        a.set_option(lb.OPT_TILE_WIDTH, 64)
-    assert e.value.status == lb.LB_ESTATE
+    for key, value in ((lb.OPT_TILE_WIDTH, 64), (lb.OPT_FORCE_AVERAGE, 1)):
+        with pytest.raises(lb.LBError) as e:
+            a.set_option(key, value)
+        assert e.value.status == lb.LB_ESTATE
     batch.close()
     a.set_option(lb.OPT_TILE_WIDTH, 64)
+    a.set_option(lb.OPT_FORCE_AVERAGE, 1)
+    assert a.get_option(lb.OPT_FORCE_AVERAGE) == 1
+    with pytest.raises(lb.LBError) as e:
+        a.set_option(lb.OPT_FORCE_AVERAGE, 2)
+    assert e.value.status == lb.LB_EINVAL

@@ -31,11 +31,12 @@ def test_fixed_particle_prescribed_motion():
     assert state < 1e-14 and force < 1e-11, (state, force)
 
 
-@pytest.mark.parametrize("rho_p", [1.0, 1.3])
-def test_free_particle_crossing_nodes(rho_p):
-    """The disc moves across nodes: relabelling and covered/uncovered forces."""
+@pytest.mark.parametrize("rho_p,avg", [(1.0, False), (1.3, False), (1.0, True)])
+def test_free_particle_crossing_nodes(rho_p, avg):
+    """The disc moves across nodes: relabelling and covered/uncovered forces;
+    also with the two-step force mean in the particle update."""
     nx, ny = 64, 52
-    gpu, ora = make_pair(nx, ny, tau=0.7, g=(2e-5, 0.0), particles=[
+    gpu, ora = make_pair(nx, ny, tau=0.7, g=(2e-5, 0.0), force_average=avg, particles=[
         dict(x=20.2, y=26.3, radius=5.5, density_ratio=rho_p, ux=0.03, uy=0.01, omega=0.003)])
     gpu.step(150)
     ora.run(150)

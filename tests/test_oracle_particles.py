@@ -126,3 +126,44 @@ def test_repulsion_is_antisymmetric_with_cutoff():
     cosang = np.dot(p[0, 7:9], d) / (np.linalg.norm(p[0, 7:9]) * np.linalg.norm(d))
     assert cosang > 1 - 1e-12  # repulsive, along the centre line
     assert np.abs(p[2, 7:10]).max() < 1e-14
+
+
+def _disc_block(force_average):
+    """A 2 x 2 block of near-neutral discs (R = 8, density ratio 1.05, surface
+    gaps 8.5 and 5.5) upstream of a disordered obstacle bed, pressure-driven,
+    tau = 0.7: the coupling in which the explicit update of Eq. MP5 lets a
+    period-two oscillation of the discs grow."""
+    from paper_2006_12910_amd import inputs
+    from oracle.oracle import PRESSURE
+    nx, ny = 400, 160
+    mask = inputs.rsa_discs(nx, ny, 6.0, 14.0, 0.30, 2.0, inputs.rng(77), x_margin=(90, 30),
+                            y_margin=(1, 1))[0]
+    o = Oracle(OracleParams(nx=nx, ny=ny, bc_x=PRESSURE, bc_y=WALL, rho_in=1.001, rho_out=0.999,
+                            tau=0.7, lj_psi=1e-3, lj_rit=2.5, lj_floor=0.5,
+                            force_average=force_average), mask)
+    for i in range(2):
+        for j in range(2):
+            o.add_particle(28.5 + 24.5 * j, 69.75 + 21.5 * i, 8.0, 1.05, 0.0, 0.0, 0.0)
+    return o
+
+
+@pytest.mark.slow
+def test_force_average_damps_the_period_two_oscillation():
+    """The paper's explicit update: the link force of the block grows by two
+    orders of magnitude within 3500 steps, alternating sign from one step to
+    the next.  With the mean of two steps' forces it stays at the level of
+    the hydrodynamic force (~1e-4)."""
+    def run(avg):
+        o = _disc_block(avg)
+        o.run(3500)
+        f1 = o.link_forces()[:, 1].copy()
+        o.run(1)
+        f2 = o.link_forces()[:, 1]
+        return np.abs(f1).max(), f1, f2
+
+    big, f1, f2 = run(False)
+    assert big > 1e-2
+    k = np.argmax(np.abs(f1))
+    assert f1[k] * f2[k] < 0  # period two
+    small, _, _ = run(True)
+    assert small < 1e-3
