@@ -80,12 +80,15 @@ def size_bucket(spec):
 def autotune_tiles(storage, specs, masks):
     """Tile shape per size class: lb_autotune (every tile width and rows per
     thread, timed with HIP events) on a throwaway copy of the largest member
-    of each class; the batch members of the class then take its choice."""
+    of each class with sides of 1024 or more; the batch members of the class
+    then take its choice (smaller classes keep the default shape)."""
     from paper_2006_12910_amd import lb
     best = {}
     for b in sorted({size_bucket(s) for s in specs}):
         i = max((j for j, s in enumerate(specs) if size_bucket(s) == b), key=lambda j: specs[j]["n"])
         n = specs[i]["n"]
+        if n < 1024:
+            continue  # a step of a small domain is too short to time: default shape
         d = lb.Domain(n, n, tau=specs[i]["tau"], storage=storage, rounding=ROUNDING[storage],
                       obstacles=masks[i])
         ms = d.autotune(steps=10 if n >= 2048 else 40)
@@ -102,7 +105,7 @@ def build_variant(storage, specs, masks, tiles=None):
         fields, _ = domain_inputs(dict(spec, obstacle_seed=None))
         d = lb.Domain(spec["n"], spec["n"], tau=spec["tau"], storage=storage,
                       rounding=ROUNDING[storage], init=fields, obstacles=masks[i])
-        if tiles:
+        if tiles and size_bucket(spec) in tiles:
             tw, rows = tiles[size_bucket(spec)]
             d.set_option(lb.OPT_TILE_WIDTH, tw)
             d.set_option(lb.OPT_ROWS_PER_THREAD, rows)

@@ -54,6 +54,7 @@ enum : int {
   F_PRESSURE = 8,  // Zou-He faces on x
   F_STOCH = 16,    // stochastic rounding of 16-bit storage
   F_FAVG = 32,     // particle update with the mean of two steps' forces (runtime only)
+  F_PAIR = 64,     // 16-bit storage swept two nodes per thread along x (runtime only)
 };
 // Power-law exponent specialisations.
 enum : int { PL_GENERIC = 0, PL_HALF = 1, PL_3Q = 2, PL_3H = 3 };
