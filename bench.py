@@ -8,8 +8,9 @@ waves (u0 = 0.01).  Every step advances all 201 domains with one sweep launch
 (batched, replayed from a hipGraph).  Populations are stored as FP16 deviations
 with stochastic rounding (the reported value), and, for comparison, as plain
 FP32 and as BF16 deviations; arithmetic is FP32.  Before the timed region the
-library's autotuner (lb_autotune) picks the tile shape of each size class on
-a throwaway copy of its largest member.
+tile shapes are tuned on a throwaway copy of the batch: the batch step is
+timed for the default shapes, every uniform shape and the per-class shapes
+the library's autotuner (lb_autotune) picks, and the fastest is used.
 
 MLUPS counts every lattice site of every domain (solids included), as the
 paper defines it.  The roofline object reports the sweep kernel's algorithmic
@@ -73,8 +74,11 @@ def domain_inputs(spec):
 
 
 def size_bucket(spec):
+    """(has obstacles, size class); the class edges 128 and 256 are those of
+    the library's default tile widths, so a class shares one default shape."""
     n = spec["n"]
-    return (spec["obstacle_seed"] is not None, 0 if n < 128 else 1 if n < 512 else 2 if n < 2048 else 3)
+    return (spec["obstacle_seed"] is not None,
+            0 if n < 128 else 1 if n < 256 else 2 if n < 1024 else 3 if n < 4096 else 4)
 
 
 def autotune_tiles(storage, specs, masks):
@@ -96,6 +100,46 @@ def autotune_tiles(storage, specs, masks):
         log(f"{storage}: autotune class {b} ({n}^2): tile {best[b][0]}x{best[b][1]}, {ms * 1e3:.1f} us/step")
         d.close()
     return best
+
+
+def tune_batch(storage, specs, masks, steps=20):
+    """Tile shape of every batch member, chosen by timing the batch step itself
+    (HIP events, on a throwaway copy of the batch) for the library's default
+    shapes, for every uniform shape, and for lb_autotune's per-class shapes;
+    returns the fastest assignment {class: (tile_w, rows)}, None = defaults."""
+    import torch
+    from paper_2006_12910_amd import lb
+    classes = sorted({size_bucket(s) for s in specs})
+    cands = [("defaults", None)]
+    cands += [(f"uniform {tw}x{r}", {c: (tw, r) for c in classes}) for tw in (64, 128, 256) for r in (2, 4, 8)]
+    cands.append(("per-class autotune", autotune_tiles(storage, specs, masks)))
+    doms = build_variant(storage, specs, masks)
+    default = [(d.get_option(lb.OPT_TILE_WIDTH), d.get_option(lb.OPT_ROWS_PER_THREAD)) for d in doms]
+    stream = torch.cuda.current_stream()
+    best = None
+    for name, tiles in cands:
+        for d, spec, dflt in zip(doms, specs, default):
+            tw, rows = tiles[size_bucket(spec)] if tiles and size_bucket(spec) in tiles else dflt
+            d.set_option(lb.OPT_TILE_WIDTH, tw)
+            d.set_option(lb.OPT_ROWS_PER_THREAD, rows)
+        batch = lb.Batch(doms)
+        batch.step(3)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        batch.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        batch.close()
+        log(f"{storage}: batch tuning, {name}: {ms:.3f} ms/step")
+        if best is None or ms < best[0]:
+            best = (ms, name, tiles)
+    for d in doms:
+        d.close()
+    torch.cuda.empty_cache()
+    log(f"{storage}: batch tuning chose {best[1]}")
+    return best[2]
 
 
 def build_variant(storage, specs, masks, tiles=None):
@@ -140,8 +184,13 @@ def run_variant(storage, specs, masks, steps, warmup, tune, fixed_tiles=None):
     import torch
     from paper_2006_12910_amd import lb
     t0 = time.time()
-    tiles = fixed_tiles if fixed_tiles else (autotune_tiles(storage, specs, masks) if tune else None)
+    tiles = fixed_tiles if fixed_tiles else (tune_batch(storage, specs, masks) if tune else None)
     doms = build_variant(storage, specs, masks, tiles)
+    # the shapes in use, per class (explicit also where the defaults won)
+    tiles = {}
+    for d, spec in zip(doms, specs):
+        tiles.setdefault(size_bucket(spec), (d.get_option(lb.OPT_TILE_WIDTH),
+                                             d.get_option(lb.OPT_ROWS_PER_THREAD)))
     batch = lb.Batch(doms)
     torch.cuda.synchronize()
     log(f"{storage}: built {len(doms)} domains in {time.time() - t0:.1f}s")
@@ -200,6 +249,113 @@ def l2_errors(doms, ref, specs):
                 max_vs_u_0=float(np.max(errs_0)), median_vs_u_0=float(np.median(errs_0)))
 
 
+def copy_bandwidth(mib=2048, reps=10):
+    """Measured device-to-device copy rate (1:1 read/write, like the sweep)."""
+    import torch
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * a.numel() * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def other_configs(with_oracle):
+    """GPU MLUPS of the other four workloads at their full sizes (timed with
+    HIP events after a warm-up call), each next to the oracle's MLUPS on a
+    few steps of the same lattice."""
+    import torch
+    from paper_2006_12910_amd import inputs, lb
+    from oracle import Oracle, OracleParams
+    from oracle.oracle import PRESSURE, WALL
+    out = {}
+
+    def gpu_rate(name, dom_or_batch, sites, steps):
+        dom_or_batch.step(max(steps // 10, 1))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dom_or_batch.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = {"gpu_mlups": round(sites * steps / (e0.elapsed_time(e1) * 1e-3) / 1e6, 1)}
+
+    def oracle_rate(name, ora, sites, steps):
+        if not with_oracle:
+            return
+        t0 = time.perf_counter()
+        ora.run(steps)
+        out[name]["oracle_mlups"] = round(sites * steps / (time.perf_counter() - t0) / 1e6, 2)
+
+    # channel 128 x 64, FP64
+    kw = dict(bc_y="wall", tau=0.8, g=(1e-6, 0.0))
+    d = lb.Domain(128, 64, storage="f64", **kw)
+    gpu_rate("channel_128x64_f64", d, 128 * 64, 5000)
+    d.close()
+    oracle_rate("channel_128x64_f64", Oracle(OracleParams(nx=128, ny=64, bc_y=WALL, tau=0.8, gx=1e-6)),
+                128 * 64, 2000)
+    # porous 2048 x 1024 with 16 discs, FP32 storage
+    mask, _ = inputs.porous_channel()
+    parts = [dict(x=x, y=y, radius=8.0, density_ratio=1.05) for x, y in inputs.particle_block()]
+    lj = (1e-3, 2.5, 0.5)
+    d = lb.Domain(2048, 1024, storage="f32", bc_x="pressure", bc_y="wall", tau=0.7, rho_in=1.001,
+                  rho_out=0.999, obstacles=mask, max_particles=16, lj=lj)
+    d.set_option(lb.OPT_FORCE_AVERAGE, 1)
+    d.add_particles(parts)
+    gpu_rate("porous_2048x1024_16discs_f32", d, 2048 * 1024, 1000)
+    d.close()
+    if with_oracle:
+        o = Oracle(OracleParams(nx=2048, ny=1024, bc_x=PRESSURE, bc_y=WALL, tau=0.7, rho_in=1.001,
+                                rho_out=0.999, lj_psi=lj[0], lj_rit=lj[1], lj_floor=lj[2],
+                                force_average=True), mask)
+        for p in parts:
+            o.add_particle(p["x"], p["y"], 8.0, 1.05, 0.0, 0.0, 0.0)
+        oracle_rate("porous_2048x1024_16discs_f32", o, 2048 * 1024, 20)
+        del o
+    # fluctuating 512^2 with a Brownian disc, FP32 storage; and the 64-member ensemble
+    d = lb.Domain(512, 512, storage="f32", tau=1.0, kT=1e-4, seed=2006, domain_id=1, max_particles=1)
+    d.add_particles([dict(x=256.5, y=256.5, radius=5.0)])
+    gpu_rate("fluctuating_512_disc_f32", d, 512 * 512, 2000)
+    d.close()
+    if with_oracle:
+        o = Oracle(OracleParams(nx=512, ny=512, tau=1.0, kT=1e-4, seed=2006, domain_id=1))
+        o.add_particle(256.5, 256.5, 5.0, 1.0, 0.0, 0.0, 0.0)
+        oracle_rate("fluctuating_512_disc_f32", o, 512 * 512, 100)
+        del o
+    specs = inputs.fluctuating_batch(count=64)
+    doms = []
+    for sp in specs:
+        dd = lb.Domain(sp["n"], sp["n"], storage="f32", tau=1.0, kT=1e-4, seed=64,
+                       domain_id=sp["domain_id"], max_particles=1)
+        cx, cy, r = sp["disc"]
+        dd.add_particles([dict(x=cx, y=cy, radius=r)])
+        doms.append(dd)
+    b = lb.Batch(doms)
+    gpu_rate("fluctuating_ensemble_64_f32", b, sum(sp["n"] ** 2 for sp in specs), 200)
+    b.close()
+    for dd in doms:
+        dd.close()
+    # power-law channel 4096 x 256, n = 0.5, FP32 storage
+    pl = dict(n=0.5, K=0.01, tau_min=0.51, tau_max=2.5)
+    d = lb.Domain(4096, 256, storage="f32", bc_y="wall", g=(2.648e-6, 0.0), power_law=pl)
+    gpu_rate("powerlaw_4096x256_n0.5_f32", d, 4096 * 256, 2000)
+    d.close()
+    oracle_rate("powerlaw_4096x256_n0.5_f32",
+                Oracle(OracleParams(nx=4096, ny=256, bc_y=WALL, gx=2.648e-6, power_law=True, n_index=0.5,
+                                    K=0.01)), 4096 * 256, 20)
+    torch.cuda.empty_cache()
+    return out
+
+
 def traffic_entry(bytes_alg):
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -221,6 +377,8 @@ def main():
                     help="seconds of oracle work for the CPU baseline and the L2 sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline and L2 sample")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes instead of the autotuner's")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the rates of the other four workloads (reported beside the main line)")
     ap.add_argument("--tiles", default=None, metavar="JSON",
                     help='tile shape per size class instead of tuning, e.g. the "tiles" object of an '
                          'earlier line (to profile the configuration that line measured)')
@@ -252,6 +410,7 @@ def main():
     log(f"inputs: {len(specs)} domains, {sum(s['n'] ** 2 for s in specs) / 1e6:.1f} M sites "
         f"({time.time() - t0:.1f}s)")
     sites = sum(s["n"] ** 2 for s in specs)
+    fluid_sites = sum(s["n"] ** 2 - (0 if m is None else int(m.sum())) for s, m in zip(specs, masks))
     nsteps_total = args.warmup + args.steps
 
     sample, ref, cpu = [], {}, None
@@ -271,9 +430,10 @@ def main():
         doms, batch, ms, tiles = run_variant(v, specs, masks, args.steps, args.warmup, not args.no_tune,
                                              parse_tiles(args.tiles) if args.tiles else None)
         mlups = sites * args.steps / (ms * 1e-3) / 1e6
+        mflups = fluid_sites * args.steps / (ms * 1e-3) / 1e6
         bytes_alg = algorithmic_bytes(specs, masks, STORAGE_BYTES[v])
         gbs = bytes_alg * args.steps / (ms * 1e-3) / 1e9
-        entry = {"mlups": round(mlups, 1), "ms_per_step": round(ms / args.steps, 4),
+        entry = {"mlups": round(mlups, 1), "mflups": round(mflups, 1), "ms_per_step": round(ms / args.steps, 4),
                  "sweep_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                  "bytes_per_step": bytes_alg, "rounding": ROUNDING[v],
                  "tiles": None if tiles is None else {f"{'obstacles' if k[0] else 'open'}/class{k[1]}": f"{t[0]}x{t[1]}"
@@ -291,11 +451,19 @@ def main():
 
     head = results[variants[0]]
     achieved = head["sweep_GBps"]
+    copy_gbs = copy_bandwidth()
+    log(f"device-to-device copy: {copy_gbs:.0f} GB/s")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic_entry(head["bytes_per_step"]),
                 "kernel": f"k_sweep ({variants[0]} storage, batched)",
-                "algorithmic_bytes_per_launch": head["bytes_per_step"]}
+                "algorithmic_bytes_per_launch": head["bytes_per_step"],
+                "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
+    configs = None
+    if not args.no_configs:
+        t0 = time.time()
+        configs = other_configs(with_oracle=not args.no_cpu)
+        log(f"other workloads ({time.time() - t0:.0f}s): {json.dumps(configs)}")
     out = {
         "metric": METRIC, "value": head["mlups"], "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
@@ -309,6 +477,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": results,
+        "other_workloads": configs,
     }
     print(json.dumps(out), flush=True)
 

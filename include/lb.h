@@ -187,12 +187,6 @@ lb_status lb_set_populations(lb_domain *d, const double *host_dev_f);
  * oscillation of neighbouring near-neutral discs grow (e.g. density ratio 1.05
  * at tau = 0.7); the mean damps it.  Not changeable while in a batch. */
 #define LB_OPT_FORCE_AVERAGE 5
-/* Nodes per thread along x: 1 (default) or, with FP16/BF16 storage, 2
- * (4-byte pulls and stores of neighbouring node pairs).  Both give
- * bit-identical results.  A tile row is LB_OPT_TILE_WIDTH threads, that many
- * nodes times this value.  Batched domains must agree; not changeable while
- * in a batch. */
-#define LB_OPT_NODES_PER_THREAD 6
 lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value);
 lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value);
 

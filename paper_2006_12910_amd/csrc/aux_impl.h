@@ -89,10 +89,10 @@ __global__ __launch_bounds__(256) void k_moments(const DevDomain *__restrict__ D
   uy_o[n] = jy / rho - 0.5 * D.gy;
 }
 
-// Mirror slots of the current buffer: for every fluid node x and solid source
-// s = x - e_i (an obstacle or particle node of the label plane, or a wall row
-// or column of a domain without one), slot i of s holds x's own opposite
-// population (what the pull along i bounces back), copied bit for bit.
+// Mirror slots of the index walls of a label-free domain in the current
+// buffer: for every fluid node x whose pull along i comes from a wall node
+// s = x - e_i, slot i of s holds x's own opposite population (what that pull
+// bounces back), copied bit for bit.
 template <int ST>
 __global__ __launch_bounds__(256) void k_mirror(const DevDomain *__restrict__ Dp) {
   using T = typename Store<ST>::T;
@@ -102,25 +102,12 @@ __global__ __launch_bounds__(256) void k_mirror(const DevDomain *__restrict__ Dp
   const int y = (int)(n / D.nx), x = (int)(n - (long long)y * D.nx);
   const size_t here = (size_t)y * D.pitch + x;
   const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
-  uint32_t w;
-  if (D.nodew) {
-    w = D.nodew[here];
-  } else {
-    if (node_is_solid(D, x, y)) return;
-    w = 0;
-    for (int i = 1; i < 9; ++i) {
-      int sx, sy;
-      if (source_of(D.nx, D.ny, perx, pery, x, y, i, sx, sy) && node_is_solid(D, sx, sy))
-        w |= 1u << (i - 1);
-    }
-  }
-  if ((w & NODE_SOLID) || !(w & 0xffu)) return;
+  if (node_is_solid(D, x, y)) return;
   T *f = (T *)D.f[*D.tstep & 1];
   const size_t plane = (size_t)D.ny * D.pitch;
   for (int i = 1; i < 9; ++i) {
-    if (!((w >> (i - 1)) & 1u)) continue;
     int sx, sy;
-    if (!source_of(D.nx, D.ny, perx, pery, x, y, i, sx, sy)) continue;
+    if (!source_of(D.nx, D.ny, perx, pery, x, y, i, sx, sy) || !node_is_solid(D, sx, sy)) continue;
     f[i * plane + (size_t)sy * D.pitch + sx] = f[opp(i) * plane + here];
   }
 }

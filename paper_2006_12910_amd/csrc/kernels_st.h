@@ -7,7 +7,6 @@
 #include "launch.h"
 #include "particles_impl.h"
 #include "sweep_impl.h"
-#include "sweep_pair_impl.h"
 
 namespace lbk {
 namespace {
@@ -17,16 +16,6 @@ constexpr int ST = LBK_ST;
 template <int FEAT, int PLM, int WIDE>
 void sweep_l(const DevDomain *doms, const int *prefix, int ndom, int kstep, int blocks,
              hipStream_t s) {
-  if constexpr (ST == ST_F16 || ST == ST_BF16)
-    hipLaunchKernelGGL((k_sweep_pair<ST, FEAT, PLM, WIDE>), dim3(blocks), dim3(256), 0, s, doms,
-                       prefix, ndom, kstep);
-  else
-    hipLaunchKernelGGL((k_sweep<ST, FEAT, PLM, WIDE>), dim3(blocks), dim3(256), 0, s, doms, prefix,
-                       ndom, kstep);
-}
-template <int FEAT, int PLM, int WIDE>
-void sweep1_l(const DevDomain *doms, const int *prefix, int ndom, int kstep, int blocks,
-              hipStream_t s) {
   hipLaunchKernelGGL((k_sweep<ST, FEAT, PLM, WIDE>), dim3(blocks), dim3(256), 0, s, doms, prefix,
                      ndom, kstep);
 }
@@ -71,7 +60,6 @@ void mirror_l(const DevDomain *dom, int nx, int ny, hipStream_t s) {
 
 template <int FEAT, int PLM, int WIDE> void fill(KernelSet *k) {
   k->sweep = sweep_l<FEAT, PLM, WIDE>;
-  k->sweep1 = sweep1_l<FEAT, PLM, WIDE>;
   k->init = init_l<FEAT, PLM, WIDE>;
   k->pre = pre_l;
   k->post = post_l;

@@ -6,12 +6,8 @@
 namespace lbk {
 
 struct KernelSet {
-  // sweep: two nodes per thread for the 16-bit formats, else one;
-  // sweep1: always one node per thread
   void (*sweep)(const DevDomain *doms, const int *prefix, int ndom, int kstep, int blocks,
                 hipStream_t s);
-  void (*sweep1)(const DevDomain *doms, const int *prefix, int ndom, int kstep, int blocks,
-                 hipStream_t s);
   void (*init)(const DevDomain *dom, const double *rho, const double *ux, const double *uy,
                int row0, int nrows, int pitch, hipStream_t s);
   // particle coupling before and after the sweep (one workgroup per particle)

@@ -204,13 +204,11 @@ struct lb_batch {
 
 namespace {
 
-// A tile is tile_w threads along x (two nodes each for the 16-bit formats)
-// by (256 / tile_w) * rpt rows.
+// A tile is tile_w threads (nodes) along x by (256 / tile_w) * rpt rows.
 void set_tiles(DevDomain &hd, int tile_w, int rpt) {
   hd.tile_w = tile_w;
   hd.rows_per_thread = rpt;
-  const int cols = tile_w * ((hd.feat & F_PAIR) ? 2 : 1);
-  hd.tiles_x = (hd.nx + cols - 1) / cols;
+  hd.tiles_x = (hd.nx + tile_w - 1) / tile_w;
   const int th = (256 / tile_w) * rpt;
   hd.tiles_y = (hd.ny + th - 1) / th;
 }
@@ -238,21 +236,21 @@ lb_status check_health(lb_domain *d) {
 }
 
 // Enqueue `n` steps of the launch sequence on stream s (eager or under capture).
-void record_steps(const KernelSet &ks, bool pairs, const DevDomain *doms, const int *prefix,
-                  int ndom, int blocks, const PItem *items, int nitems, int n, hipStream_t s) {
+void record_steps(const KernelSet &ks, const DevDomain *doms, const int *prefix, int ndom,
+                  int blocks, const PItem *items, int nitems, int n, hipStream_t s) {
   for (int k = 0; k < n; ++k) {
     if (nitems > 0) ks.pre(doms, items, nitems, k, s);
-    (pairs ? ks.sweep : ks.sweep1)(doms, prefix, ndom, k, blocks, s);
+    ks.sweep(doms, prefix, ndom, k, blocks, s);
     if (nitems > 0) ks.post(doms, items, nitems, k, s);
   }
   launch_advance(doms, ndom, n, s);
 }
 
 lb_status run_chunk(GraphCache &gc, bool use_graph, hipStream_t stream, hipStream_t cap,
-                    const KernelSet &ks, bool pairs, const DevDomain *doms, const int *prefix,
-                    int ndom, int blocks, const PItem *items, int nitems, int n) {
+                    const KernelSet &ks, const DevDomain *doms, const int *prefix, int ndom,
+                    int blocks, const PItem *items, int nitems, int n) {
   if (!use_graph) {
-    record_steps(ks, pairs, doms, prefix, ndom, blocks, items, nitems, n, stream);
+    record_steps(ks, doms, prefix, ndom, blocks, items, nitems, n, stream);
     HIPCHK(hipGetLastError());
     return LB_OK;
   }
@@ -260,7 +258,7 @@ lb_status run_chunk(GraphCache &gc, bool use_graph, hipStream_t stream, hipStrea
   if (it == gc.execs.end()) {
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    record_steps(ks, pairs, doms, prefix, ndom, blocks, items, nitems, n, cap);
+    record_steps(ks, doms, prefix, ndom, blocks, items, nitems, n, cap);
     hipError_t le = hipGetLastError();
     HIPCHK(hipStreamEndCapture(cap, &g));
     if (le != hipSuccess) {
@@ -285,10 +283,10 @@ lb_status domain_mass_enqueue(lb_domain *d) {
   return LB_OK;
 }
 
-// Mirror slots of stationary solids (obstacles, particles, index walls) in
-// the current population buffer.
+// Mirror slots of the index walls of a label-free domain in the current
+// population buffer (label domains bounce back on the pulling node's own slot).
 lb_status refresh_mirrors(lb_domain *d) {
-  if (!d->hd.label && d->desc.bc_x != LB_WALL && d->desc.bc_y != LB_WALL) return LB_OK;
+  if (d->hd.label || (d->desc.bc_x != LB_WALL && d->desc.bc_y != LB_WALL)) return LB_OK;
   d->ks.mirror(d->ddesc(), d->desc.nx, d->desc.ny, d->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(d->stream));
@@ -379,8 +377,6 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   h.key0 = (uint32_t)desc->seed;
   h.key1 = (uint32_t)(desc->seed >> 32) ^ desc->domain_id;
   h.feat = feat;
-  // one node per thread by default: on MI355X the two-node sweep of the
-  // 16-bit formats measured no faster (136 vs 141 GLUPS on 8192^2 FP16)
   set_tiles(h, default_tile_w(desc->nx), desc->storage >= LB_F16_DELTA ? 4 : 2);
   h.rho0 = desc->rho0;
   h.tau = desc->power_law ? desc->tau_min : desc->tau;
@@ -557,9 +553,8 @@ lb_status lb_step(lb_domain *d, int64_t nsteps) {
   int64_t left = nsteps;
   while (left > 0) {
     const int c = (int)std::min<int64_t>(left, d->chunk);
-    lb_status s = run_chunk(d->graphs, d->use_graph, d->stream, d->cap, d->ks,
-                            (d->hd.feat & F_PAIR) != 0, d->ddesc(), d->dprefix(), 1, d->ntiles(),
-                            d->ditems(), d->np, c);
+    lb_status s = run_chunk(d->graphs, d->use_graph, d->stream, d->cap, d->ks, d->ddesc(),
+                            d->dprefix(), 1, d->ntiles(), d->ditems(), d->np, c);
     if (s != LB_OK) return s;
     left -= c;
   }
@@ -664,7 +659,7 @@ lb_status lb_set_populations(lb_domain *d, const double *hf) {
 lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
   if (!d) return fail(LB_EINVAL, "null domain");
   if (d->in_batches && (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD ||
-                        key == LB_OPT_FORCE_AVERAGE || key == LB_OPT_NODES_PER_THREAD))
+                        key == LB_OPT_FORCE_AVERAGE))
     return fail(LB_ESTATE, "tile and force options are fixed while the domain is in a batch");
   switch (key) {
     case LB_OPT_USE_GRAPH: d->use_graph = value != 0; break;
@@ -684,17 +679,10 @@ lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
       if (value != 0 && value != 1) return fail(LB_EINVAL, "force averaging is 0 or 1");
       d->hd.feat = value ? (d->hd.feat | F_FAVG) : (d->hd.feat & ~F_FAVG);
       break;
-    case LB_OPT_NODES_PER_THREAD:
-      if (value != 1 && !(value == 2 && d->desc.storage >= LB_F16_DELTA))
-        return fail(LB_EINVAL, "nodes per thread: 1, or 2 with 16-bit storage");
-      d->hd.feat = value == 2 ? (d->hd.feat | F_PAIR) : (d->hd.feat & ~F_PAIR);
-      set_tiles(d->hd, d->hd.tile_w, d->hd.rows_per_thread);
-      break;
     default: return fail(LB_EINVAL, "unknown option");
   }
   d->graphs.clear();
-  if (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD || key == LB_OPT_FORCE_AVERAGE ||
-      key == LB_OPT_NODES_PER_THREAD)
+  if (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD || key == LB_OPT_FORCE_AVERAGE)
     return push_desc(d);
   return LB_OK;
 }
@@ -707,7 +695,6 @@ lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value) {
     case LB_OPT_ROWS_PER_THREAD: *value = d->hd.rows_per_thread; return LB_OK;
     case LB_OPT_GRAPH_CHUNK: *value = d->chunk; return LB_OK;
     case LB_OPT_FORCE_AVERAGE: *value = (d->hd.feat & F_FAVG) ? 1 : 0; return LB_OK;
-    case LB_OPT_NODES_PER_THREAD: *value = (d->hd.feat & F_PAIR) ? 2 : 1; return LB_OK;
   }
   return fail(LB_EINVAL, "unknown option");
 }
@@ -790,10 +777,8 @@ lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_worksp
     if (domains[i]->desc.storage != domains[0]->desc.storage ||
         domains[i]->desc.compute != domains[0]->desc.compute ||
         (domains[i]->feat & (F_NOISE | F_POWER)) != (domains[0]->feat & (F_NOISE | F_POWER)) ||
-        domains[i]->plm != domains[0]->plm ||
-        (domains[i]->hd.feat & F_PAIR) != (domains[0]->hd.feat & F_PAIR))
-      return fail(LB_EUNSUPPORTED,
-                  "batched domains must share storage, arithmetic, noise, power law and nodes per thread");
+        domains[i]->plm != domains[0]->plm)
+      return fail(LB_EUNSUPPORTED, "batched domains must share storage, arithmetic, noise and power law");
   }
   // label-plane and label-free domains share one launch: take the kernel set
   // with label support if any domain has a plane (it reads no labels for the
@@ -847,9 +832,9 @@ lb_status lb_batch_step(lb_batch *b, int64_t nsteps) {
   int64_t left = nsteps;
   while (left > 0) {
     const int c = (int)std::min<int64_t>(left, b->chunk);
-    lb_status s = run_chunk(b->graphs, b->use_graph, b->stream, b->cap, b->ks,
-                            (b->doms[0]->hd.feat & F_PAIR) != 0, b->ddesc(), b->dprefix(),
-                            (int)b->doms.size(), b->total_tiles, b->ditems(), b->nitems, c);
+    lb_status s = run_chunk(b->graphs, b->use_graph, b->stream, b->cap, b->ks, b->ddesc(),
+                            b->dprefix(), (int)b->doms.size(), b->total_tiles, b->ditems(),
+                            b->nitems, c);
     if (s != LB_OK) return s;
     left -= c;
   }

@@ -54,7 +54,6 @@ enum : int {
   F_PRESSURE = 8,  // Zou-He faces on x
   F_STOCH = 16,    // stochastic rounding of 16-bit storage
   F_FAVG = 32,     // particle update with the mean of two steps' forces (runtime only)
-  F_PAIR = 64,     // 16-bit storage swept two nodes per thread along x (runtime only)
 };
 // Power-law exponent specialisations.
 enum : int { PL_GENERIC = 0, PL_HALF = 1, PL_3Q = 2, PL_3H = 3 };
@@ -352,23 +351,19 @@ __device__ __forceinline__ bool source_of(int nx, int ny, bool perx, bool pery, 
   return true;
 }
 
-// Static node word from the label plane.  A fluid (or particle) node: bit
-// i-1 set when the source x - e_i of its pull along i is solid, so the node
-// mirror-writes that slot; sources outside a non-periodic edge are left clear
-// (pressure faces reconstruct them).  A solid node: NODE_SOLID, and bit i-1
-// set when the node x + e_i that pulls slot i from it is not solid, so that
-// slot is the neighbour's mirror slot; the solid node's own sweep thread
-// fills every other slot, and each slot of the plane is written once a step.
+// Static node word from the label plane: NODE_SOLID for a stationary solid
+// node, else bit i-1 set when the source x - e_i of the pull along i is solid
+// (that pull bounces back on the node's own slot).  Sources outside a
+// non-periodic edge are left clear (pressure faces reconstruct them).
 __device__ __forceinline__ uint16_t node_word(const uint8_t *lab, int nx, int ny, int pitch,
                                               bool perx, bool pery, int x, int y) {
-  const bool solid = lab[(size_t)y * pitch + x] == LBL_SOLID;
-  uint16_t m = solid ? NODE_SOLID : 0;
+  if (lab[(size_t)y * pitch + x] == LBL_SOLID) return NODE_SOLID;
+  uint16_t m = 0;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     int sx, sy;
-    // the source of the pull along i, or (solid node) the node pulling from here
-    if (!source_of(nx, ny, perx, pery, x, y, solid ? opp(i) : i, sx, sy)) continue;
-    if ((lab[(size_t)sy * pitch + sx] == LBL_SOLID) != solid) m |= (uint16_t)(1u << (i - 1));
+    if (!source_of(nx, ny, perx, pery, x, y, i, sx, sy)) continue;
+    if (lab[(size_t)sy * pitch + sx] == LBL_SOLID) m |= (uint16_t)(1u << (i - 1));
   }
   return m;
 }

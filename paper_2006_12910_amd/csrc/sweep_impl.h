@@ -251,24 +251,30 @@ template <class T> __device__ __forceinline__ void stb(char LBK_GLOBAL *b, uint3
   *(T LBK_GLOBAL *)(b + off) = v;
 }
 
-// Pull of one node.  Every direction loads the neighbour's slot at x - e_i:
-// where that neighbour is solid (an obstacle, or a wall row or column), its
-// slot holds this node's own opposite population, written there by the
-// previous step's store (halfway bounce-back by mirror writes); where the
-// pull crosses a particle surface, the slot holds the moving-wall bounced
-// value, put there by the particle pre-pass (k_pre).  So the loads have
-// no data-dependent address.  A source beyond a density face is read from the
-// node's own column: those populations are unknown and the face
-// reconstruction replaces them.  row[] and col[] are the byte offsets of the
-// (wrapped or clamped) source rows y+1, y, y-1 and columns x+1, x, x-1.
-template <class T, class P>
+// Pull of one node.  Every direction loads the neighbour's slot at x - e_i,
+// except where that neighbour is a stationary solid node of the label plane
+// (bit i-1 of `solid_src`): then halfway bounce-back loads this node's own
+// slot of the opposite direction.  Index walls of a label-free domain have
+// their slots filled by mirror writes instead (see k_sweep), and where the
+// pull crosses a particle surface the neighbour's slot already holds the
+// moving-wall bounced value, put there by the particle pre-pass (k_pre).  A
+// source beyond a density face is read from the node's own column: those
+// populations are unknown and the face reconstruction replaces them.  row[]
+// and col[] are the byte offsets of the (wrapped or clamped) source rows
+// y+1, y, y-1 and columns x+1, x, x-1.
+template <class T, bool LABELS, class P>
 __device__ __forceinline__ void pull_node(const char LBK_GLOBAL *src, uint32_t planeB,
                                           uint32_t hereB, const uint32_t (&row)[3],
-                                          const uint32_t (&col)[3], P &raw) {
+                                          const uint32_t (&col)[3], uint32_t solid_src, P &raw) {
   raw.set(0, ldb<T>(src, hereB));
 #pragma unroll
-  for (int i = 1; i < 9; ++i)
-    raw.set(i, ldb<T>(src, (uint32_t)i * planeB + (row[1 + cy(i)] + col[1 + cx(i)])));
+  for (int i = 1; i < 9; ++i) {
+    uint32_t o = (uint32_t)i * planeB + (row[1 + cy(i)] + col[1 + cx(i)]);
+    if constexpr (LABELS) {
+      if ((solid_src >> (i - 1)) & 1u) o = (uint32_t)opp(i) * planeB + hereB;
+    }
+    raw.set(i, ldb<T>(src, o));
+  }
 }
 
 // Stored values of one node while its loads are in flight (decoded only
@@ -389,29 +395,23 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
       act[u] = valid && !wall;
       uint32_t row[3];
       src_rows(y, ny, pitchB, planeB, pery, row);
-      pull_node<T>(src, planeB, row[1] + col[1], row, col, raw[u]);
+      pull_node<T, LABELS>(src, planeB, row[1] + col[1], row, col, nw[u] & 0xffu, raw[u]);
     }
     // phase 2: boundary reconstruction, collision, stores
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int y = yg + u * rows_pass;
-      if (sizeof(T) >= 4 && has_lab && (nw[u] & NODE_SOLID) && r0 + u < npt && y < ny) {
-        // 32/64-bit storage (bandwidth-bound): a solid node writes zero into
-        // every slot no fluid neighbour mirror-writes, so each slot of the
-        // buffer is written once a step and no cache line is stored in part
-        // (a partial line costs the memory a read-modify-write)
-        const uint32_t keep = nw[u] & 0xffu;  // bit i-1: slot i is a mirror slot
-        const uint32_t hB = (uint32_t)y * pitchB + col[1];
-        stb<T>(dst, hB, T(0));
-#pragma unroll
-        for (int i = 1; i < 9; ++i)
-          if (!((keep >> (i - 1)) & 1u)) stb<T>(dst, (uint32_t)i * planeB + hB, T(0));
-        continue;
-      }
-      if (!act[u] || (nw[u] & NODE_SOLID)) continue;
+      if (!act[u]) continue;
+      // a stationary solid node of the label plane is swept as a node at rest
+      // (zero deviations): its slots are never pulled (the pulls next to it
+      // bounce back on their own slots), but storing them keeps every slot of
+      // the buffer written once a step, with no cache line written in part
+      // (a partial line costs the memory a read-modify-write), and keeps the
+      // lanes of a wave on one path
+      const bool solid = LABELS && (nw[u] & NODE_SOLID);
       R e[9];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) e[i] = (R)S::raw_dec(raw[u].get(i));
+      for (int i = 0; i < 9; ++i) e[i] = solid ? R(0) : (R)S::raw_dec(raw[u].get(i));
       if (face) {
         // 2/3 + 2 (1/6) = 1 exactly in the chosen constants; unscaled values
         const R half = R(0.5), third2 = R(2) / R(3), sixth = (R(1) - third2) * R(0.5);
@@ -439,7 +439,9 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
       uint32_t row[3];  // rows y + 1, y, y - 1; all inside the domain for a computed node
       src_rows(y, ny, pitchB, planeB, true, row);
       const uint32_t hereB = row[1] + col[1];
-      uint32_t mb = nw[u] & 0xffu;
+      // index walls of a label-free domain: mirror writes (bit i-1: the
+      // source x - e_i is a wall node)
+      uint32_t mb = 0;
       if (walls) {
         const uint32_t wall_rows =
             wally ? (y == 1 ? dirs_cy(1) : 0u) | (y == ny - 2 ? dirs_cy(-1) : 0u) : 0u;
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
         encode_node<ST, R, decltype(sr_tag)::value>(D, e, node, step, q);
 #pragma unroll
         for (int i = 0; i < 9; ++i) stb<T>(dst, (uint32_t)i * planeB + hereB, q[i]);
-        // mirror writes: the pull along i from the solid source x - e_i will
+        // mirror writes: the pull along i from the wall node x - e_i will
         // read this node's post-collision opposite population there, stored
         // exactly as the node's own slot of that direction
         if (mb) {
