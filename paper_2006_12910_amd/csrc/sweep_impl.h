@@ -284,6 +284,14 @@ template <class T> struct Pulled {
   __device__ __forceinline__ void set(int i, T x) { v[i] = x; }
   __device__ __forceinline__ T get(int i) const { return v[i]; }
 };
+// 16-bit values two to a register (loads into the low and high halves), which
+// halves the registers that hold the rows in flight
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+template <> struct Pulled<uint16_t> {
+  u16x2 v[5];
+  __device__ __forceinline__ void set(int i, uint16_t x) { v[i >> 1][i & 1] = x; }
+  __device__ __forceinline__ uint16_t get(int i) const { return v[i >> 1][i & 1]; }
+};
 
 // Byte offsets of the source rows y+1, y, y-1 (index 1 + cy): wrapped on a
 // periodic axis, else a row beyond the edge is clamped to y.
@@ -357,11 +365,11 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
 
   // source columns x+1, x, x-1 (index 1 + cx); a column beyond a
   // non-periodic edge is clamped to x
-  uint32_t col[3];
+  uint32_t colv[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int c = x + 1 - k;
-    col[k] = (uint32_t)(c < 0 ? (perx ? c + nx : x) : (c >= nx ? (perx ? c - nx : x) : c)) * B;
+    colv[k] = (uint32_t)(c < 0 ? (perx ? c + nx : x) : (c >= nx ? (perx ? c - nx : x) : c)) * B;
   }
   // index walls: directions whose source is a wall column, and directions
   // whose source column lies inside the domain
@@ -370,14 +378,40 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
   const uint32_t cols_in = 0xffu & ~(!perx && x == 0 ? dirs_cx(1) : 0u) &
                            ~(!perx && x == nx - 1 ? dirs_cx(-1) : 0u);
 
-#pragma unroll 1
-  for (int r0 = 0; r0 < npt; r0 += U) {
-    // first row of this group; hidden from the optimiser so that it does not
-    // turn every address of the group into an induction variable of its own
+  // node words of a row group; a clamped row's word must not act.  Every pull
+  // address of a labelled node depends on its word, so the words of the next
+  // group are loaded while the current group's pulls are in flight.
+  auto load_words = [&](int r0, uint32_t (&w)[U]) {
     int yg = ybase + r0 * rows_pass;
     __asm__ volatile("" : "+v"(yg));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int yr = yg + u * rows_pass;
+      const bool valid = r0 + u < npt && yr < ny;
+      const int y = valid ? yr : ny - 1;
+      const uint32_t v = gbl(D.nodew)[(uint32_t)y * pitch + x];
+      w[u] = valid ? v : 0u;
+    }
+  };
+  uint32_t nwn[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) nwn[u] = 0;
+  if (has_lab) load_words(0, nwn);
+
+#pragma unroll 1
+  for (int r0 = 0; r0 < npt; r0 += U) {
+    uint32_t nw[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) nw[u] = nwn[u];
+    if (has_lab && r0 + U < npt) load_words(r0 + U, nwn);
+    // first row of this group and the column offsets, hidden from the
+    // optimiser so that it neither turns every address of the group into an
+    // induction variable of its own nor keeps a loop-invariant partial sum
+    // per direction in a register
+    int yg = ybase + r0 * rows_pass;
+    uint32_t col[3] = {colv[0], colv[1], colv[2]};
+    __asm__ volatile("" : "+v"(yg), "+v"(col[0]), "+v"(col[1]), "+v"(col[2]));
     Pulled<T> raw[U];
-    uint16_t nw[U];
     bool act[U];
     // phase 1: every load of the row group, branch-free and none depending on
     // another, so they are all in flight together; rows past the tile or the
@@ -387,9 +421,6 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
       const int yr = yg + u * rows_pass;
       const bool valid = r0 + u < npt && yr < ny;
       const int y = valid ? yr : ny - 1;
-      const uint32_t here = (uint32_t)y * pitch + x;
-      const uint16_t w = has_lab ? gbl(D.nodew)[here] : (uint16_t)0;
-      nw[u] = valid ? w : (uint16_t)0;  // a clamped row's word must not act
       const bool wall =
           walls && ((wally && (y == 0 || y == ny - 1)) || (wallx && (x == 0 || x == nx - 1)));
       act[u] = valid && !wall;
