@@ -207,24 +207,15 @@ def run_variant(storage, specs, masks, steps, warmup, tune, fixed_tiles=None):
     return doms, batch, ms, tiles
 
 
-def oracle_sample(specs, masks, nsteps, budget_s):
-    """Smallest domains of the workload whose estimated oracle cost fits the
-    budget (about 25 M site-updates per second on the host)."""
-    order = sorted(range(len(specs)), key=lambda i: specs[i]["n"])
-    chosen, cost = [], 0.0
-    for i in order:
-        c = specs[i]["n"] ** 2 * nsteps / 25e6
-        if chosen and cost + c > budget_s:
-            break
-        chosen.append(i)
-        cost += c
-    return chosen
-
-
-def run_oracle(specs, masks, sample, nsteps):
+def run_oracle(specs, masks, nsteps, budget_s):
+    """The oracle on the smallest domains of the workload, in order of size,
+    until its stepping time reaches the budget: returns the final moments of
+    each domain it ran, its MLUPS and its stepping time."""
     from oracle import Oracle, OracleParams
     results, t_total, sites = {}, 0.0, 0
-    for i in sample:
+    for i in sorted(range(len(specs)), key=lambda k: specs[k]["n"]):
+        if t_total >= budget_s:
+            break
         spec = specs[i]
         n = spec["n"]
         fields, _ = domain_inputs(dict(spec, obstacle_seed=None))
@@ -417,8 +408,8 @@ def main():
     if not args.no_cpu:
         threads = min(len(os.sched_getaffinity(0)), 16)
         os.environ["OMP_NUM_THREADS"] = str(threads)
-        sample = oracle_sample(specs, masks, nsteps_total, args.cpu_budget)
-        ref, cpu_mlups, cpu_s = run_oracle(specs, masks, sample, nsteps_total)
+        ref, cpu_mlups, cpu_s = run_oracle(specs, masks, nsteps_total, args.cpu_budget)
+        sample = sorted(ref)
         cpu = {"value": round(cpu_mlups, 2), "unit": "MLUPS", "cores": threads, "kind": "oracle",
                "sample": f"{len(sample)} smallest domains of the workload "
                          f"({min(specs[i]['n'] for i in sample)}^2..{max(specs[i]['n'] for i in sample)}^2), "
