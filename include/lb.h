@@ -150,7 +150,10 @@ lb_status lb_set_obstacles(lb_domain *d, const uint8_t *host_mask, size_t n);
 lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_t *first_id);
 
 /* Enqueue nsteps full time steps (collision, noise, streaming, boundaries,
- * particle coupling) on the domain's stream; nsteps >= 0. */
+ * particle coupling) on the domain's stream; nsteps >= 0.  A call with
+ * nsteps > 0 ends with the FP64 density sum of the final state.  A non-finite
+ * density (pulled by a step, or in that final sum) latches a flag that the
+ * next synchronising call reports as LB_EUNSTABLE. */
 lb_status lb_step(lb_domain *d, int64_t nsteps);
 
 /* Density and reported velocity u = j/rho + g/2 at every node (zero on solid
@@ -206,6 +209,8 @@ lb_status lb_destroy_domain(lb_domain *d);
 lb_status lb_batch_workspace_bytes(lb_domain *const *domains, int32_t n, size_t *bytes);
 lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_workspace,
                           size_t bytes, void *hip_stream, lb_batch **out);
+/* As lb_step for every domain of the batch, on the batch's stream (the
+ * final density sums included). */
 lb_status lb_batch_step(lb_batch *b, int64_t nsteps);
 lb_status lb_batch_set_option(lb_batch *b, int32_t key, int64_t value);
 lb_status lb_batch_destroy(lb_batch *b);

@@ -45,13 +45,18 @@ __global__ __launch_bounds__(256) void k_mass_partial(const DevDomain *__restric
 }
 
 #ifdef LBK_COMMON_KERNELS
-__global__ void k_mass_final(const DevDomain *__restrict__ Dp, const double *partials, int n,
-                             double *out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Sum of the n partials by one wave, in a fixed order (lane l sums partials
+// l, l + 64, ...; then a butterfly over the lanes).
+__global__ __launch_bounds__(64) void k_mass_final(const DevDomain *__restrict__ Dp,
+                                                   const double *partials, int n, double *out) {
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += partials[i];
-  *out = s;
-  if (!(fabs(s) < 1e300)) atomicOr(Dp->health, HEALTH_NONFINITE);
+  for (int i = (int)threadIdx.x; i < n; i += 64) s += partials[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (threadIdx.x == 0) {
+    *out = s;
+    if (!(fabs(s) < 1e300)) atomicOr(Dp->health, HEALTH_NONFINITE);
+  }
 }
 #endif  // LBK_COMMON_KERNELS
 

@@ -152,6 +152,15 @@ bool get_kernels(int st, int feat, int plm, int wide, KernelSet *k) {
 
 int default_tile_w(int nx) { return nx >= 256 ? 256 : (nx >= 128 ? 128 : 64); }
 
+// The sweep streams its stores past the caches when the step's working set
+// (both population buffers of every domain in the launch) is at least this
+// large; below it the next step finds the written lines in the 256 MB
+// last-level cache.
+constexpr size_t STREAM_STORE_MIN_BYTES = (size_t)256 << 20;
+size_t sweep_working_set(const DevDomain &h) {
+  return 2 * 9 * (size_t)storage_bytes(h.storage) * (size_t)h.pitch * (size_t)h.ny;
+}
+
 // Graph cache of captured step chunks, keyed by chunk length.
 struct GraphCache {
   std::map<int, hipGraphExec_t> execs;
@@ -275,13 +284,19 @@ lb_status run_chunk(GraphCache &gc, bool use_graph, hipStream_t stream, hipStrea
   return LB_OK;
 }
 
-lb_status domain_mass_enqueue(lb_domain *d) {
-  d->ks.mass_partial(d->ddesc(), (double *)(d->ws + d->L.partials), NPARTIALS, d->stream);
-  launch_mass_final(d->ddesc(), (double *)(d->ws + d->L.partials), NPARTIALS, &d->dhdr()->mass,
-                    d->stream);
+// FP64 density sum of the current state; its final kernel also latches a
+// non-finite state (the sweep checks the densities it pulls, so a blow-up in
+// the last step of a call is caught here).
+lb_status domain_mass_enqueue(lb_domain *d, hipStream_t s) {
+  // about 4 nodes per thread, at most NPARTIALS blocks
+  const long long nodes = (long long)d->desc.nx * d->desc.ny;
+  const int blocks = (int)std::min<long long>(NPARTIALS, std::max<long long>(1, nodes / 1024));
+  d->ks.mass_partial(d->ddesc(), (double *)(d->ws + d->L.partials), blocks, s);
+  launch_mass_final(d->ddesc(), (double *)(d->ws + d->L.partials), blocks, &d->dhdr()->mass, s);
   HIPCHK(hipGetLastError());
   return LB_OK;
 }
+lb_status domain_mass_enqueue(lb_domain *d) { return domain_mass_enqueue(d, d->stream); }
 
 // Mirror slots of the index walls of a label-free domain in the current
 // population buffer (label domains bounce back on the pulling node's own slot).
@@ -378,6 +393,7 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   h.key1 = (uint32_t)(desc->seed >> 32) ^ desc->domain_id;
   h.feat = feat;
   set_tiles(h, default_tile_w(desc->nx), desc->storage >= LB_F16_DELTA ? 4 : 2);
+  h.stream_stores = sweep_working_set(h) >= STREAM_STORE_MIN_BYTES;
   h.rho0 = desc->rho0;
   h.tau = desc->power_law ? desc->tau_min : desc->tau;
   h.omega = 1.0 / h.tau;
@@ -803,6 +819,9 @@ lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_worksp
     prefix[i + 1] = prefix[i] + domains[i]->ntiles();
     for (int q = 0; q < domains[i]->np; ++q) items.push_back(PItem{i, q});
   }
+  size_t working_set = 0;
+  for (int i = 0; i < n; ++i) working_set += sweep_working_set(descs[i]);
+  for (int i = 0; i < n; ++i) descs[i].stream_stores = working_set >= STREAM_STORE_MIN_BYTES;
   b->total_tiles = prefix[n];
   b->nitems = (int)items.size();
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
@@ -839,6 +858,12 @@ lb_status lb_batch_step(lb_batch *b, int64_t nsteps) {
     left -= c;
   }
   for (auto *d : b->doms) d->t += nsteps;
+  if (nsteps > 0) {
+    for (auto *d : b->doms) {
+      lb_status s = domain_mass_enqueue(d, b->stream);
+      if (s != LB_OK) return s;
+    }
+  }
   return LB_OK;
 }
 

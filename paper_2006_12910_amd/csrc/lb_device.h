@@ -94,6 +94,7 @@ struct alignas(256) DevDomain {
   int tile_w, rows_per_thread, tiles_x, tiles_y;
   uint32_t key0, key1; // noise generator key
   int storage, feat;
+  int stream_stores;   // 1: the sweep's stores bypass the caches (see k_sweep)
   // FP64 parameters
   double rho0, tau, omega, gx, gy, rho_in, rho_out, kT;
   double pl_n, pl_K, tau_min, tau_max;

@@ -250,6 +250,12 @@ template <class T> __device__ __forceinline__ T ldb(const char LBK_GLOBAL *b, ui
 template <class T> __device__ __forceinline__ void stb(char LBK_GLOBAL *b, uint32_t off, T v) {
   *(T LBK_GLOBAL *)(b + off) = v;
 }
+// Non-temporal store: a written line is read again only in the next step;
+// once a step's working set exceeds the caches it would be evicted before
+// then, so caching it only displaces the source rows still being pulled.
+template <class T> __device__ __forceinline__ void stb_nt(char LBK_GLOBAL *b, uint32_t off, T v) {
+  __builtin_nontemporal_store(v, (T LBK_GLOBAL *)(b + off));
+}
 
 // Pull of one node.  Every direction loads the neighbour's slot at x - e_i,
 // except where that neighbour is a stationary solid node of the label plane
@@ -342,7 +348,10 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
   const int tyi = local / D.tiles_x, txi = local - tyi * D.tiles_x;
   const int x = txi * tw + (int)threadIdx.x % tw;
   if (x >= nx) return;
-  const int ybase = tyi * rows_pass * npt + (int)threadIdx.x / tw;
+  // tile widths are multiples of 64, so all lanes of a wave share one row:
+  // the row index and everything derived from it (validity, wrapped
+  // neighbour rows, row offsets) is wave-uniform and lives in scalar registers
+  const int ybase = __builtin_amdgcn_readfirstlane(tyi * rows_pass * npt + (int)threadIdx.x / tw);
 
   const uint64_t T0 = *gbl(D.tstep) + (uint64_t)kstep;  // state time of the source buffer
   const uint32_t step = (uint32_t)(T0 + 1);
@@ -383,7 +392,7 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
   // group are loaded while the current group's pulls are in flight.
   auto load_words = [&](int r0, uint32_t (&w)[U]) {
     int yg = ybase + r0 * rows_pass;
-    __asm__ volatile("" : "+v"(yg));
+    __asm__ volatile("" : "+s"(yg));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int yr = yg + u * rows_pass;
@@ -410,7 +419,7 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
     // per direction in a register
     int yg = ybase + r0 * rows_pass;
     uint32_t col[3] = {colv[0], colv[1], colv[2]};
-    __asm__ volatile("" : "+v"(yg), "+v"(col[0]), "+v"(col[1]), "+v"(col[2]));
+    __asm__ volatile("" : "+s"(yg), "+v"(col[0]), "+v"(col[1]), "+v"(col[2]));
     Pulled<T> raw[U];
     bool act[U];
     // phase 1: every load of the row group, branch-free and none depending on
@@ -465,8 +474,11 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
         for (int i = 0; i < 9; ++i) e[i] *= R(kscale<ST>(i));
       }
       const uint32_t node = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
-      collide_node<ST, FEAT, PLM, R>(D, e, node, step);
+      // non-finite check on the pulled density (the collision computes the
+      // same sum): a blow-up is seen one step after it is stored, and the
+      // density reduction after every call covers the final state
       bad = bad || !(fabs(scaled_drho<ST, R>(e)) < R(1e30));
+      collide_node<ST, FEAT, PLM, R>(D, e, node, step);
       uint32_t row[3];  // rows y + 1, y, y - 1; all inside the domain for a computed node
       src_rows(y, ny, pitchB, planeB, true, row);
       const uint32_t hereB = row[1] + col[1];
@@ -483,8 +495,15 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
       auto emit = [&](auto sr_tag) {
         T q[9];
         encode_node<ST, R, decltype(sr_tag)::value>(D, e, node, step, q);
+        // cache-resident working sets keep ordinary stores (the next step
+        // reads them back from the cache); larger ones stream (stb_nt)
+        if (D.stream_stores) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) stb<T>(dst, (uint32_t)i * planeB + hereB, q[i]);
+          for (int i = 0; i < 9; ++i) stb_nt<T>(dst, (uint32_t)i * planeB + hereB, q[i]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) stb<T>(dst, (uint32_t)i * planeB + hereB, q[i]);
+        }
         // mirror writes: the pull along i from the wall node x - e_i will
         // read this node's post-collision opposite population there, stored
         // exactly as the node's own slot of that direction
