@@ -174,15 +174,19 @@ __device__ __forceinline__ float f16_to_f32(uint16_t h) {
 // drawing the comparison from the high bits of r.
 typedef _Float16 lbk_half2 __attribute__((ext_vector_type(2)));
 typedef __bf16 lbk_bf16x2 __attribute__((ext_vector_type(2)));
+// The instruction writes the low half of its destination and keeps the high
+// half.  Only the low half is used, so it is written as an ALU instruction
+// with a fresh output register: the builtin's form ties the destination to a
+// vector operand and costs a register copy or a zeroing move per value.
 __device__ __forceinline__ uint16_t f32_to_f16_sr(float v, uint32_t r) {
-  lbk_half2 o = {(_Float16)0, (_Float16)0};
-  o = __builtin_amdgcn_cvt_sr_f16_f32(o, v, r, false);
-  return __builtin_bit_cast(uint16_t, o[0]);
+  uint32_t o;
+  __asm__("v_cvt_sr_f16_f32 %0, %1, %2" : "=v"(o) : "v"(v), "v"(r));
+  return (uint16_t)o;
 }
 __device__ __forceinline__ uint16_t f32_to_bf16_sr(float v, uint32_t r) {
-  lbk_bf16x2 o = {(__bf16)0.0f, (__bf16)0.0f};
-  o = __builtin_amdgcn_cvt_sr_bf16_f32(o, v, r, false);
-  return __builtin_bit_cast(uint16_t, o[0]);
+  uint32_t o;
+  __asm__("v_cvt_sr_bf16_f32 %0, %1, %2" : "=v"(o) : "v"(v), "v"(r));
+  return (uint16_t)o;
 }
 
 template <> struct Store<ST_F16> {

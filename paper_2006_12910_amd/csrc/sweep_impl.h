@@ -241,20 +241,43 @@ using CompT = typename std::conditional<ST == ST_F64 || WIDE != 0, double, float
 // per load, so it keeps more rows in flight to cover memory latency.
 template <int ST> constexpr int rows_in_flight() { return ST == ST_F16 || ST == ST_BF16 ? 4 : 2; }
 
-// The sweep addresses a population buffer as one base pointer plus a 32-bit
-// byte offset (a domain's nine planes span fewer than 2^32 bytes), which maps
-// to the scalar-base + vector-offset form of the global memory instructions.
-template <class T> __device__ __forceinline__ T ldb(const char LBK_GLOBAL *b, uint32_t off) {
-  return *(const T LBK_GLOBAL *)(b + off);
+// The sweep addresses a population buffer through a raw buffer resource
+// (base, size in bytes; a domain's nine planes span fewer than 2^32 bytes).
+// A buffer access adds a scalar and a vector byte offset in the memory unit:
+// the plane and row part of every offset is wave-uniform (scalar adds) and
+// the vector part is the column, so the pulls and stores of a node need no
+// vector address arithmetic.  Word 3 is the raw-buffer format of the gfx9
+// family.
+typedef __amdgpu_buffer_rsrc_t BufRes;
+__device__ __forceinline__ BufRes pop_buffer(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
 }
-template <class T> __device__ __forceinline__ void stb(char LBK_GLOBAL *b, uint32_t off, T v) {
-  *(T LBK_GLOBAL *)(b + off) = v;
+template <class T> __device__ __forceinline__ T bload(BufRes r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 2) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
+  } else if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+  } else {
+    static_assert(sizeof(T) == 8, "population type");
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+  }
 }
-// Non-temporal store: a written line is read again only in the next step;
-// once a step's working set exceeds the caches it would be evicted before
-// then, so caching it only displaces the source rows still being pulled.
-template <class T> __device__ __forceinline__ void stb_nt(char LBK_GLOBAL *b, uint32_t off, T v) {
-  __builtin_nontemporal_store(v, (T LBK_GLOBAL *)(b + off));
+// NT: non-temporal store.  A written line is read again only in the next
+// step; once a step's working set exceeds the caches it would be evicted
+// before then, so caching it only displaces the source rows still being
+// pulled.
+template <class T, bool NT>
+__device__ __forceinline__ void bstore(BufRes r, uint32_t voff, uint32_t soff, T v) {
+  constexpr int aux = NT ? 2 : 0;  // cache-policy bits: 2 = nt
+  if constexpr (sizeof(T) == 2) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, (int)voff, (int)soff, aux);
+  } else if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, aux);
+  } else {
+    static_assert(sizeof(T) == 8, "population type");
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, aux);
+  }
 }
 
 // Pull of one node.  Every direction loads the neighbour's slot at x - e_i,
@@ -266,20 +289,42 @@ template <class T> __device__ __forceinline__ void stb_nt(char LBK_GLOBAL *b, ui
 // moving-wall bounced value, put there by the particle pre-pass (k_pre).  A
 // source beyond a density face is read from the node's own column: those
 // populations are unknown and the face reconstruction replaces them.  row[]
-// and col[] are the byte offsets of the (wrapped or clamped) source rows
-// y+1, y, y-1 and columns x+1, x, x-1.
+// (wave-uniform) and col[] are the byte offsets of the (wrapped or clamped)
+// source rows y+1, y, y-1 and columns x+1, x, x-1.  With labels, the scalar
+// offset of direction i is the smaller of the two candidates' uniform parts
+// (opposite directions lie two planes apart, so which one is smaller is
+// known at compile time) and the vector offset adds the difference, which is
+// never negative.
 template <class T, bool LABELS, class P>
-__device__ __forceinline__ void pull_node(const char LBK_GLOBAL *src, uint32_t planeB,
-                                          uint32_t hereB, const uint32_t (&row)[3],
+__device__ __forceinline__ void pull_node(BufRes src, uint32_t planeB, const uint32_t (&row)[3],
                                           const uint32_t (&col)[3], uint32_t solid_src, P &raw) {
-  raw.set(0, ldb<T>(src, hereB));
+  raw.set(0, bload<T>(src, col[1], row[1]));
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
-    uint32_t o = (uint32_t)i * planeB + (row[1 + cy(i)] + col[1 + cx(i)]);
-    if constexpr (LABELS) {
-      if ((solid_src >> (i - 1)) & 1u) o = (uint32_t)opp(i) * planeB + hereB;
+    const uint32_t sN = (uint32_t)i * planeB + row[1 + cy(i)];  // neighbour's slot
+    const uint32_t vN = col[1 + cx(i)];
+    if constexpr (!LABELS) {
+      raw.set(i, bload<T>(src, vN, sN));
+    } else {
+      const uint32_t sB = (uint32_t)opp(i) * planeB + row[1];  // own opposite slot
+      // all ones where the pull bounces back, else zero; a ^ ((a ^ b) & m)
+      // picks b under the mask (one three-input bitwise instruction)
+      // (the empty asm operands keep the optimiser from turning the mux back
+      // into a compare and select, and from splitting the scalar delta)
+      uint32_t m = (uint32_t)(-(int32_t)((solid_src >> (i - 1)) & 1u));
+      __asm__("" : "+v"(m));
+      if (opp(i) > i) {  // resolved at compile time once the loop is unrolled
+        uint32_t d = sB - sN;
+        __asm__("" : "+s"(d));
+        const uint32_t vB = col[1] + d;
+        raw.set(i, bload<T>(src, vN ^ ((vN ^ vB) & m), sN));
+      } else {
+        uint32_t d = sN - sB;
+        __asm__("" : "+s"(d));
+        const uint32_t vA = vN + d;
+        raw.set(i, bload<T>(src, vA ^ ((vA ^ col[1]) & m), sB));
+      }
     }
-    raw.set(i, ldb<T>(src, o));
   }
 }
 
@@ -357,8 +402,9 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
   const uint32_t step = (uint32_t)(T0 + 1);
   void *const f0 = D.f[0];
   void *const f1 = D.f[1];
-  const char LBK_GLOBAL *src = (const char LBK_GLOBAL *)((T0 & 1) ? f1 : f0);
-  char LBK_GLOBAL *dst = (char LBK_GLOBAL *)((T0 & 1) ? f0 : f1);
+  const uint32_t nbytes = 9u * (uint32_t)ny * (uint32_t)pitch * (uint32_t)sizeof(T);
+  const BufRes src = pop_buffer((T0 & 1) ? f1 : f0, nbytes);
+  const BufRes dst = pop_buffer((T0 & 1) ? f0 : f1, nbytes);
   const uint32_t pitchB = (uint32_t)pitch * B;
   const uint32_t planeB = (uint32_t)ny * pitchB;
   bool bad = false;  // non-finite density seen by this thread
@@ -435,7 +481,7 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
       act[u] = valid && !wall;
       uint32_t row[3];
       src_rows(y, ny, pitchB, planeB, pery, row);
-      pull_node<T, LABELS>(src, planeB, row[1] + col[1], row, col, nw[u] & 0xffu, raw[u]);
+      pull_node<T, LABELS>(src, planeB, row, col, nw[u] & 0xffu, raw[u]);
     }
     // phase 2: boundary reconstruction, collision, stores
 #pragma unroll
@@ -481,7 +527,6 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
       collide_node<ST, FEAT, PLM, R>(D, e, node, step);
       uint32_t row[3];  // rows y + 1, y, y - 1; all inside the domain for a computed node
       src_rows(y, ny, pitchB, planeB, true, row);
-      const uint32_t hereB = row[1] + col[1];
       // index walls of a label-free domain: mirror writes (bit i-1: the
       // source x - e_i is a wall node)
       uint32_t mb = 0;
@@ -499,10 +544,10 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
         // reads them back from the cache); larger ones stream (stb_nt)
         if (D.stream_stores) {
 #pragma unroll
-          for (int i = 0; i < 9; ++i) stb_nt<T>(dst, (uint32_t)i * planeB + hereB, q[i]);
+          for (int i = 0; i < 9; ++i) bstore<T, true>(dst, col[1], (uint32_t)i * planeB + row[1], q[i]);
         } else {
 #pragma unroll
-          for (int i = 0; i < 9; ++i) stb<T>(dst, (uint32_t)i * planeB + hereB, q[i]);
+          for (int i = 0; i < 9; ++i) bstore<T, false>(dst, col[1], (uint32_t)i * planeB + row[1], q[i]);
         }
         // mirror writes: the pull along i from the wall node x - e_i will
         // read this node's post-collision opposite population there, stored
@@ -511,7 +556,7 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
 #pragma unroll
           for (int i = 1; i < 9; ++i) {
             if (!((mb >> (i - 1)) & 1u)) continue;
-            stb<T>(dst, (uint32_t)i * planeB + (row[1 + cy(i)] + col[1 + cx(i)]), q[opp(i)]);
+            bstore<T, false>(dst, col[1 + cx(i)], (uint32_t)i * planeB + row[1 + cy(i)], q[opp(i)]);
           }
         }
       };
