@@ -347,6 +347,81 @@ def other_configs(with_oracle):
     return out
 
 
+# The paper's best CPU rates of its three timing benchmarks (MLUPS, its table
+# of optimisation stages: OpenMP with thread affinity, 28-core Xeon E5-2697 v3).
+PAPER_BEST_CPU_MLUPS = {"b1": 47.27, "b2": 138.20, "b3": 85.85}
+
+
+def paper_replicas(with_oracle):
+    """GPU MLUPS of stand-ins for the paper's three timing benchmarks on their
+    full lattices (FP32 storage; the set-ups of tests/test_gpu_paper_benchmarks.py),
+    next to the oracle on a few steps of the same set-up and the paper's best
+    CPU figure, which is context only."""
+    import torch
+    from paper_2006_12910_amd import inputs, lb
+    from oracle import Oracle, OracleParams
+    from oracle.oracle import WALL
+    out = {}
+
+    def rate(name, make_gpu, make_oracle, sites, steps, ora_steps):
+        d = make_gpu()
+        d.step(max(steps // 10, 1))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        d.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        d.close()
+        out[name] = {"gpu_mlups": round(sites * steps / (e0.elapsed_time(e1) * 1e-3) / 1e6, 1),
+                     "paper_best_cpu_mlups": PAPER_BEST_CPU_MLUPS[name]}
+        if with_oracle:
+            o = make_oracle()
+            t0 = time.perf_counter()
+            o.run(ora_steps)
+            out[name]["oracle_mlups"] = round(sites * ora_steps / (time.perf_counter() - t0) / 1e6, 2)
+
+    mask, centres = inputs.replica_b1()
+
+    def b1_gpu():
+        d = lb.Domain(1020, 1620, storage="f32", bc_x="wall", tau=0.636, g=(1e-6, -1e-5),
+                      obstacles=mask, max_particles=45, lj=(20.0, 2.5, 0.1))
+        d.set_option(lb.OPT_FORCE_AVERAGE, 1)
+        d.add_particles([dict(x=x, y=y, radius=6.5) for x, y in centres])
+        return d
+
+    def b1_oracle():
+        o = Oracle(OracleParams(nx=1020, ny=1620, bc_x=WALL, tau=0.636, gx=1e-6, gy=-1e-5,
+                                force_average=True), mask)
+        for x, y in centres:
+            o.add_particle(x, y, 6.5, 1.0, 0.0, 0.0, 0.0)
+        return o
+
+    rate("b1", b1_gpu, b1_oracle, 1020 * 1620, 1000, 10)
+    ((bx, by),) = inputs.replica_b2()
+
+    def b2_gpu():
+        d = lb.Domain(3000, 41, storage="f32", bc_y="wall", tau=0.8, kT=5e-5, seed=2020,
+                      domain_id=2, max_particles=1)
+        d.add_particles([dict(x=bx, y=by, radius=7.5)])
+        return d
+
+    def b2_oracle():
+        o = Oracle(OracleParams(nx=3000, ny=41, bc_y=WALL, tau=0.8, kT=5e-5, seed=2020, domain_id=2))
+        o.add_particle(bx, by, 7.5, 1.0, 0.0, 0.0, 0.0)
+        return o
+
+    rate("b2", b2_gpu, b2_oracle, 3000 * 41, 5000, 100)
+    pl = dict(n=0.5, K=1e-3, tau_min=0.50003, tau_max=0.8)
+    rate("b3", lambda: lb.Domain(101, 51, storage="f32", bc_y="wall", tau=0.8, g=(1e-6, 0.0),
+                                 power_law=pl),
+         lambda: Oracle(OracleParams(nx=101, ny=51, bc_y=WALL, tau=0.8, gx=1e-6, power_law=True,
+                                     n_index=0.5, K=1e-3, tau_min=0.50003, tau_max=0.8)),
+         101 * 51, 20000, 2000)
+    torch.cuda.empty_cache()
+    return out
+
+
 def traffic_entry(bytes_alg):
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -369,7 +444,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline and L2 sample")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes instead of the autotuner's")
     ap.add_argument("--no-configs", action="store_true",
-                    help="skip the rates of the other four workloads (reported beside the main line)")
+                    help="skip the rates of the other four workloads and of the paper's three "
+                         "benchmarks (reported beside the main line)")
     ap.add_argument("--tiles", default=None, metavar="JSON",
                     help='tile shape per size class instead of tuning, e.g. the "tiles" object of an '
                          'earlier line (to profile the configuration that line measured)')
@@ -450,11 +526,14 @@ def main():
                 "kernel": f"k_sweep ({variants[0]} storage, batched)",
                 "algorithmic_bytes_per_launch": head["bytes_per_step"],
                 "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
-    configs = None
+    configs = replicas = None
     if not args.no_configs:
         t0 = time.time()
         configs = other_configs(with_oracle=not args.no_cpu)
         log(f"other workloads ({time.time() - t0:.0f}s): {json.dumps(configs)}")
+        t0 = time.time()
+        replicas = paper_replicas(with_oracle=not args.no_cpu)
+        log(f"paper benchmarks ({time.time() - t0:.0f}s): {json.dumps(replicas)}")
     out = {
         "metric": METRIC, "value": head["mlups"], "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
@@ -469,6 +548,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": results,
         "other_workloads": configs,
+        "paper_benchmarks": replicas,
     }
     print(json.dumps(out), flush=True)
 

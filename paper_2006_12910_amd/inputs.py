@@ -129,3 +129,30 @@ def fluctuating_batch(count=64, seed=0, smin=128, smax=1024):
     sizes = log_uniform_sizes(count, smin, smax, 500 + seed)
     return [dict(n=n, domain_id=i + 1, disc=(n / 2 + 0.5, n / 2 + 0.5, 5.0))
             for i, n in enumerate(sizes)]
+
+
+# The paper's three timing benchmarks (its Table of MLUPS), as seeded
+# stand-ins: the lattices and parameters it states, with the geometry it shows
+# only in figures replaced by the layouts below.
+
+def replica_b1(seed=0, nx=1020, ny=1620, band=220, solid_fraction=0.30):
+    """Multi-particle flow in a porous medium: lateral walls on x = 0 and
+    nx-1 (not in the mask), periodic in y, RSA grains r ~ U[6, 24] (gap >= 2)
+    to `solid_fraction` of the lattice outside a grain-free release band of
+    `band` rows at the top, and 45 particles of radius 6.5 in three rows of 15
+    in that band, surface spacings 8.5 horizontally and 5.5 vertically.
+    Returns (mask, particle centres)."""
+    r = rng(600 + seed)
+    mask, _ = rsa_discs(nx, ny, 6.0, 24.0, solid_fraction, 2.0, r, x_margin=(1, 1),
+                        y_margin=(0, band))
+    radius, cols = 6.5, 15
+    width = cols * (2 * radius + 8.5) - 8.5
+    centres = particle_block(rows=3, cols=cols, radius=radius, gap_x=8.5, gap_y=5.5,
+                             x0=0.5 * (nx - width), y_centre=ny - 0.5 * band)
+    return mask, centres
+
+
+def replica_b2(nx=3000, ny=41):
+    """Brownian particle in a smooth channel: one disc of radius 7.5 at the
+    channel centre (half-integer centre, so no node lies on its surface)."""
+    return [(nx / 2 + 0.5, (ny - 1) / 2 + 0.5)]
