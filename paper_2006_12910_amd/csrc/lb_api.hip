@@ -35,7 +35,6 @@ lb_status fail(lb_status s, const std::string &msg) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 int storage_bytes(int st) { return st == LB_F64 ? 8 : (st == LB_F32 ? 4 : 2); }
 
-constexpr int MAX_PARTICLES = 250;
 constexpr int NPARTIALS = 1024;
 constexpr size_t STAGE_TARGET = size_t(16) << 20;  // bytes of the host-transfer staging band
 

@@ -60,6 +60,8 @@ enum : int { PL_GENERIC = 0, PL_HALF = 1, PL_3Q = 2, PL_3H = 3 };
 
 // Labels: 0 fluid, 1 solid, 2 + p inside particle p.
 constexpr uint8_t LBL_FLUID = 0, LBL_SOLID = 1, LBL_PART0 = 2;
+// particles per domain: labels 2 .. 2 + 249 fit the uint8 label plane
+constexpr int MAX_PARTICLES = 250;
 
 // Particle state, FP64 (double-buffered by step parity).
 struct PState {

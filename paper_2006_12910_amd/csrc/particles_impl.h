@@ -9,9 +9,9 @@
 //            momentum exchange of Eq. MP1 and its torque (Eq. MP4) in FP64
 //            and write the moving-wall bounce-back (Eqs. MP7-MP8) into the
 //            link's two pull slots, so the sweep pulls unconditionally; sum
-//            the repulsion from solid nodes (Eq. MP2); then one lane adds the
-//            particle-particle repulsion and takes the Newton-Euler step of
-//            Eqs. MP5-MP6 into P(T+1).
+//            the repulsion from solid nodes and from the other particles
+//            (Eq. MP2, one lane per particle pair); then one lane takes the
+//            Newton-Euler step of Eqs. MP5-MP6 into P(T+1).
 //   k_post   after the sweep: the covered/uncovered-node force (Eq. MP3) of
 //            the nodes whose label changes from G(T) to G(T+1), and G(T+1)
 //            written into the label plane.
@@ -23,6 +23,10 @@
 namespace lbk {
 
 constexpr int LINK_CAP = 6144;
+// The host admits no particle whose box side W = 2 reach + 2 has W^2 above
+// LINK_CAP (W <= 78), so the box with a one-node rim fits 80 x 80 labels.
+constexpr int LAB_BOX = 80 * 80;
+constexpr uint8_t LBL_OUT = 0xff;  // rim or box node outside a non-periodic domain
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -82,28 +86,29 @@ __device__ __forceinline__ double lj_mag(const DevDomain &D, double gap) {
   return D.lj_psi * pow(g / D.lj_rit, -13.0);
 }
 
-// Particle-particle repulsion and the Newton-Euler step (Eqs. MP2, MP5-MP6)
-// of particle p from P(T) (all particles, `cur`) and its total force F into
-// P(T+1); with F_FAVG the update takes the mean of this step's total force
-// and torque and the previous step's, which P(T) holds.
+// Repulsion on particle p from particle q (Eq. MP2), both from P(T): zero
+// for q == p or beyond the interaction range.
+__device__ __forceinline__ void pair_repulsion(const DevDomain &D, const PState &P,
+                                               const PState &Q, double &lx, double &ly) {
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  const double dx = min_image(P.x - Q.x, D.nx, perx), dy = min_image(P.y - Q.y, D.ny, pery);
+  const double dist = sqrt(dx * dx + dy * dy);
+  const double gap = dist - P.radius - Q.radius;
+  if (gap > D.lj_rit || !(dist > 0.0)) return;
+  const double m = lj_mag(D, gap);
+  lx += m * dx / dist;
+  ly += m * dy / dist;
+}
+
+// Newton-Euler step (Eqs. MP5-MP6) of particle p from P(T) (`cur`), its link,
+// cover and solid-repulsion forces F and its particle-particle repulsion
+// (lx, ly), into P(T+1); with F_FAVG the update takes the mean of this step's
+// total force and torque and the previous step's, which P(T) holds.
 __device__ __forceinline__ void advance_particle(const DevDomain &D, int p, const PState *cur,
-                                                 PState *nxt, const PForce &F) {
+                                                 PState *nxt, const PForce &F, double lx,
+                                                 double ly) {
   const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
   const PState P = cur[p];
-  double lx = 0.0, ly = 0.0;
-  if (D.lj_psi > 0.0) {
-    for (int q = 0; q < D.np; ++q) {
-      if (q == p) continue;
-      const PState &Q = cur[q];
-      const double dx = min_image(P.x - Q.x, D.nx, perx), dy = min_image(P.y - Q.y, D.ny, pery);
-      const double dist = sqrt(dx * dx + dy * dy);
-      const double gap = dist - P.radius - Q.radius;
-      if (gap > D.lj_rit || !(dist > 0.0)) continue;
-      const double m = lj_mag(D, gap);
-      lx += m * dx / dist;
-      ly += m * dy / dist;
-    }
-  }
   const double fx = F.fx + F.cx_ + (lx + F.ljx);
   const double fy = F.fy + F.cy_ + (ly + F.ljy);
   const double tq = F.torque + F.ctorque;
@@ -148,7 +153,9 @@ __global__ __launch_bounds__(256) void k_pre(const DevDomain *__restrict__ doms,
   using RS = typename S::R;
   __shared__ uint32_t links[LINK_CAP];
   __shared__ int scan_sh[4];
-  __shared__ double red[4][5];
+  __shared__ double red[4][7];
+  // labels G(T) of the box and a one-node rim (out of the domain: LBL_OUT)
+  __shared__ uint8_t lab[LAB_BOX];
   const PItem it = items[blockIdx.x];
   const DevDomain &D = doms[it.dom];
   const uint64_t T0 = *D.tstep + (uint64_t)kstep;
@@ -165,15 +172,28 @@ __global__ __launch_bounds__(256) void k_pre(const DevDomain *__restrict__ doms,
   const int chunk = (nbox + 255) / 256;
   const double lim = P.radius + D.lj_rit;
 
+  // stage the labels: box position (i, k) -> lab[(k + 1) * WR + i + 1]
+  const int WR = W + 2;
+  for (int j = threadIdx.x; j < WR * WR; j += 256) {
+    int x = bx0 - 1 + j % WR, y = by0 - 1 + j / WR;
+    const bool in = wrap_coord(x, D.nx, perx) && wrap_coord(y, D.ny, pery);
+    lab[j] = in ? D.label[(size_t)y * D.pitch + x] : LBL_OUT;
+  }
+  __syncthreads();
+  auto lab_at = [&](int i, int k) { return lab[(k + 1) * WR + i + 1]; };
+
   // pass 1: count crossing exterior pulls of this thread's contiguous nodes,
   // and sum the repulsion from solid nodes
   int cnt = 0;
   double ljx = 0.0, ljy = 0.0;
   for (int j = threadIdx.x * chunk; j < min(nbox, (threadIdx.x + 1) * chunk); ++j) {
-    int x = bx0 + j % W, y = by0 + j / W;
-    if (!wrap_coord(x, D.nx, perx) || !wrap_coord(y, D.ny, pery)) continue;
-    const uint8_t lx = D.label[(size_t)y * D.pitch + x];
+    const int bi = j % W, bk = j / W;
+    const uint8_t lx = lab_at(bi, bk);
+    if (lx == LBL_OUT) continue;
     if (lx == LBL_SOLID) {
+      int x = bx0 + bi, y = by0 + bk;
+      wrap_coord(x, D.nx, perx);
+      wrap_coord(y, D.ny, pery);
       const double dx = min_image(P.x - x, D.nx, perx), dy = min_image(P.y - y, D.ny, pery);
       const double dist = sqrt(dx * dx + dy * dy);
       if (dist <= lim && dist > 0.0) {
@@ -184,24 +204,18 @@ __global__ __launch_bounds__(256) void k_pre(const DevDomain *__restrict__ doms,
       continue;
     }
     if (lx != LBL_FLUID) continue;
-    for (int i = 1; i < 9; ++i) {
-      int sx = x - cx(i), sy = y - cy(i);
-      if (!wrap_coord(sx, D.nx, perx) || !wrap_coord(sy, D.ny, pery)) continue;
-      if (D.label[(size_t)sy * D.pitch + sx] == mine) ++cnt;
-    }
+    for (int i = 1; i < 9; ++i)
+      if (lab_at(bi - cx(i), bk - cy(i)) == mine) ++cnt;
   }
   int total;
   int pos = block_exscan(cnt, scan_sh, total);
   // pass 2: write this thread's links in node order into the LDS list
   for (int j = threadIdx.x * chunk; j < min(nbox, (threadIdx.x + 1) * chunk); ++j) {
     if (!cnt) break;
-    int x = bx0 + j % W, y = by0 + j / W;
-    if (!wrap_coord(x, D.nx, perx) || !wrap_coord(y, D.ny, pery)) continue;
-    if (D.label[(size_t)y * D.pitch + x] != LBL_FLUID) continue;
+    const int bi = j % W, bk = j / W;
+    if (lab_at(bi, bk) != LBL_FLUID) continue;
     for (int i = 1; i < 9; ++i) {
-      int sx = x - cx(i), sy = y - cy(i);
-      if (!wrap_coord(sx, D.nx, perx) || !wrap_coord(sy, D.ny, pery)) continue;
-      if (D.label[(size_t)sy * D.pitch + sx] == mine) {
+      if (lab_at(bi - cx(i), bk - cy(i)) == mine) {
         if (pos < LINK_CAP) links[pos] = ((uint32_t)j << 4) | (uint32_t)i;
         ++pos;
       }
@@ -212,7 +226,13 @@ __global__ __launch_bounds__(256) void k_pre(const DevDomain *__restrict__ doms,
   if (total > LINK_CAP && threadIdx.x == 0) atomicOr(D.health, HEALTH_LINK_OVERFLOW);
   const int nl = min(total, LINK_CAP);
   // pass 3: momentum exchange (FP64) and moving-wall bounce-back of each link
-  double acc[5] = {0.0, 0.0, 0.0, ljx, ljy};
+  // repulsion from the other particles, one lane per pair
+  double plx = 0.0, ply = 0.0;
+  if (D.lj_psi > 0.0) {
+    for (int q = threadIdx.x; q < D.np; q += 256)
+      if (q != it.p) pair_repulsion(D, P, cur[q], plx, ply);
+  }
+  double acc[7] = {0.0, 0.0, 0.0, ljx, ljy, plx, ply};
   for (int e = threadIdx.x; e < nl; e += 256) {
     const uint32_t rec = links[e];
     const int j = (int)(rec >> 4), dir = (int)(rec & 15u);
@@ -240,7 +260,7 @@ __global__ __launch_bounds__(256) void k_pre(const DevDomain *__restrict__ doms,
     S::put(f + dir * plane, so, dir, (RS)(a + M), 0u);
     S::put(f + o * plane, here, o, (RS)(b - M), 0u);
   }
-  block_sum<5>(acc, red);
+  block_sum<7>(acc, red);
   if (threadIdx.x == 0) {
     PForce F = D.pforce[it.p];
     F.fx = acc[0];
@@ -249,13 +269,15 @@ __global__ __launch_bounds__(256) void k_pre(const DevDomain *__restrict__ doms,
     F.ljx = acc[3];
     F.ljy = acc[4];
     D.pforce[it.p] = F;
-    advance_particle(D, it.p, cur, D.pstate[(T0 + 1) & 1], F);
+    advance_particle(D, it.p, cur, D.pstate[(T0 + 1) & 1], F, acc[5], acc[6]);
   }
 }
 
-// Label of node (x, y) from the particle state Pn: first particle (in index
-// order) whose disc strictly contains the node, else fluid.
-__device__ __forceinline__ uint8_t new_label(const DevDomain &D, const PState *Pn, int x, int y) {
+// Label of node (x, y) from the particle discs Pn (PState, or PDisc staged in
+// LDS): first particle (in index order) whose disc strictly contains the
+// node, else fluid.
+template <class Disc>
+__device__ __forceinline__ uint8_t new_label(const DevDomain &D, const Disc *Pn, int x, int y) {
   const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
   for (int q = 0; q < D.np; ++q) {
     const double dx = min_image((double)x - Pn[q].x, D.nx, perx);
@@ -264,6 +286,9 @@ __device__ __forceinline__ uint8_t new_label(const DevDomain &D, const PState *P
   }
   return LBL_FLUID;
 }
+struct PDisc {
+  double x, y, radius;
+};
 
 // After the sweep of step T -> T+1, one workgroup per particle p, over a box
 // around P(T+1) that holds every node p leaves or enters (particles move less
@@ -280,11 +305,18 @@ __global__ __launch_bounds__(256) void k_post(const DevDomain *__restrict__ doms
   using S = Store<ST>;
   using T = typename S::T;
   __shared__ double red[4][3];
+  // discs of P(T) and P(T+1), read by every node's label rule
+  __shared__ PDisc disc0[MAX_PARTICLES], disc1[MAX_PARTICLES];
   const PItem it = items[blockIdx.x];
   const DevDomain &D = doms[it.dom];
   const uint64_t T1 = *D.tstep + (uint64_t)kstep + 1;
   const PState *Pn = D.pstate[T1 & 1];
   const PState *Po = D.pstate[(T1 - 1) & 1];
+  for (int q = threadIdx.x; q < D.np; q += 256) {
+    disc0[q] = PDisc{Po[q].x, Po[q].y, Po[q].radius};
+    disc1[q] = PDisc{Pn[q].x, Pn[q].y, Pn[q].radius};
+  }
+  __syncthreads();
   const PState P = Pn[it.p];
   const T *src = (const T *)D.f[T1 & 1];
   const size_t plane = (size_t)D.ny * D.pitch;
@@ -299,8 +331,8 @@ __global__ __launch_bounds__(256) void k_post(const DevDomain *__restrict__ doms
     if (!wrap_coord(x, D.nx, perx) || !wrap_coord(y, D.ny, pery)) continue;
     const uint32_t here = (uint32_t)y * D.pitch + x;
     if (D.nodew[here] & NODE_SOLID) continue;
-    const uint8_t l0 = new_label(D, Po, x, y);
-    const uint8_t l1 = new_label(D, Pn, x, y);
+    const uint8_t l0 = new_label(D, disc0, x, y);
+    const uint8_t l1 = new_label(D, disc1, x, y);
     if (l1 != l0) D.label[here] = l1;
     if ((l0 == mine) == (l1 == mine)) continue;
     const double sign = l1 == mine ? 1.0 : -1.0;
