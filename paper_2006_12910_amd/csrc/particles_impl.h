@@ -289,6 +289,19 @@ __device__ __forceinline__ uint8_t new_label(const DevDomain &D, const Disc *Pn,
 struct PDisc {
   double x, y, radius;
 };
+// The same rule over the candidate discs cand[0 .. n) (ascending indices):
+// the particles that can hold a node of the caller's box.
+__device__ __forceinline__ uint8_t label_among(const DevDomain &D, const PDisc *Pn, const int *cand,
+                                               int n, int x, int y) {
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  for (int k = 0; k < n; ++k) {
+    const int q = cand[k];
+    const double dx = min_image((double)x - Pn[q].x, D.nx, perx);
+    const double dy = min_image((double)y - Pn[q].y, D.ny, pery);
+    if (dx * dx + dy * dy < Pn[q].radius * Pn[q].radius) return (uint8_t)(LBL_PART0 + q);
+  }
+  return LBL_FLUID;
+}
 
 // After the sweep of step T -> T+1, one workgroup per particle p, over a box
 // around P(T+1) that holds every node p leaves or enters (particles move less
@@ -305,18 +318,16 @@ __global__ __launch_bounds__(256) void k_post(const DevDomain *__restrict__ doms
   using S = Store<ST>;
   using T = typename S::T;
   __shared__ double red[4][3];
-  // discs of P(T) and P(T+1), read by every node's label rule
+  __shared__ int scan_sh[4];
+  // discs of P(T) and P(T+1) that can reach a node of this box, in index
+  // order (so the first-particle rule is unchanged)
   __shared__ PDisc disc0[MAX_PARTICLES], disc1[MAX_PARTICLES];
+  __shared__ int cand[MAX_PARTICLES];
   const PItem it = items[blockIdx.x];
   const DevDomain &D = doms[it.dom];
   const uint64_t T1 = *D.tstep + (uint64_t)kstep + 1;
   const PState *Pn = D.pstate[T1 & 1];
   const PState *Po = D.pstate[(T1 - 1) & 1];
-  for (int q = threadIdx.x; q < D.np; q += 256) {
-    disc0[q] = PDisc{Po[q].x, Po[q].y, Po[q].radius};
-    disc1[q] = PDisc{Pn[q].x, Pn[q].y, Pn[q].radius};
-  }
-  __syncthreads();
   const PState P = Pn[it.p];
   const T *src = (const T *)D.f[T1 & 1];
   const size_t plane = (size_t)D.ny * D.pitch;
@@ -325,14 +336,35 @@ __global__ __launch_bounds__(256) void k_post(const DevDomain *__restrict__ doms
   const int reach = (int)ceil(P.radius) + 3;
   const int W = 2 * reach + 2;
   const int bx0 = (int)floor(P.x) - reach, by0 = (int)floor(P.y) - reach;
+  int ncand;
+  {
+    static_assert(MAX_PARTICLES <= 256, "one candidate test per lane");
+    // a node of the box lies within (W - 1) / 2 of the box centre on each
+    // axis, so a disc holding one has its centre within r + W / 2 + 1
+    const int q = (int)threadIdx.x;  // MAX_PARTICLES <= 256: one disc per lane
+    int hit = 0;
+    if (q < D.np) {
+      const double bcx = bx0 + 0.5 * (W - 1), bcy = by0 + 0.5 * (W - 1), h = 0.5 * W + 1.0;
+      const PState &A = Po[q], &B = Pn[q];
+      disc0[q] = PDisc{A.x, A.y, A.radius};
+      disc1[q] = PDisc{B.x, B.y, B.radius};
+      hit = (fabs(min_image(A.x - bcx, D.nx, perx)) < h + A.radius &&
+             fabs(min_image(A.y - bcy, D.ny, pery)) < h + A.radius) ||
+            (fabs(min_image(B.x - bcx, D.nx, perx)) < h + B.radius &&
+             fabs(min_image(B.y - bcy, D.ny, pery)) < h + B.radius);
+    }
+    const int pos = block_exscan(hit, scan_sh, ncand);
+    if (hit) cand[pos] = q;
+    __syncthreads();
+  }
   double acc[3] = {0.0, 0.0, 0.0};
   for (int j = threadIdx.x; j < W * W; j += 256) {
     int x = bx0 + j % W, y = by0 + j / W;
     if (!wrap_coord(x, D.nx, perx) || !wrap_coord(y, D.ny, pery)) continue;
     const uint32_t here = (uint32_t)y * D.pitch + x;
     if (D.nodew[here] & NODE_SOLID) continue;
-    const uint8_t l0 = new_label(D, disc0, x, y);
-    const uint8_t l1 = new_label(D, disc1, x, y);
+    const uint8_t l0 = label_among(D, disc0, cand, ncand, x, y);
+    const uint8_t l1 = label_among(D, disc1, cand, ncand, x, y);
     if (l1 != l0) D.label[here] = l1;
     if ((l0 == mine) == (l1 == mine)) continue;
     const double sign = l1 == mine ? 1.0 : -1.0;
