@@ -454,7 +454,7 @@ def main():
                          "known traffic for scaling profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the domains of a batch would shard across GPUs with no communication).",
               file=sys.stderr)
         sys.exit(2)
