@@ -190,6 +190,13 @@ lb_status lb_set_populations(lb_domain *d, const double *host_dev_f);
  * oscillation of neighbouring near-neutral discs grow (e.g. density ratio 1.05
  * at tau = 0.7); the mean damps it.  Not changeable while in a batch. */
 #define LB_OPT_FORCE_AVERAGE 5
+/* 1 (default): a domain that is periodic on both axes, has no particles and
+ * no noise or power law, with native arithmetic, advances two time steps per
+ * pass over memory (each four steps as two such launches; the first step is
+ * kept in on-chip memory) -- bit-identical to single steps, with half the
+ * memory traffic per step.  0: single steps only.  A batch takes it when all
+ * its domains do.  Not changeable while in a batch. */
+#define LB_OPT_TWO_STEP 6
 lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value);
 lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value);
 

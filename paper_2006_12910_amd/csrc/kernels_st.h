@@ -6,6 +6,7 @@
 #include "aux_impl.h"
 #include "launch.h"
 #include "particles_impl.h"
+#include "sweep2_impl.h"
 #include "sweep_impl.h"
 
 namespace lbk {
@@ -18,6 +19,12 @@ void sweep_l(const DevDomain *doms, const int *prefix, int ndom, int kstep, int 
              hipStream_t s) {
   hipLaunchKernelGGL((k_sweep<ST, FEAT, PLM, WIDE>), dim3(blocks), dim3(256), 0, s, doms, prefix,
                      ndom, kstep);
+}
+template <int FEAT>
+void sweep2_l(const DevDomain *doms, const int *prefix2, int ndom, int kstep, int which, int blocks,
+              hipStream_t s) {
+  hipLaunchKernelGGL((k_sweep2<ST, FEAT>), dim3(blocks), dim3(256), 0, s, doms, prefix2, ndom,
+                     kstep, which);
 }
 template <int FEAT, int PLM, int WIDE>
 void init_l(const DevDomain *dom, const double *rho, const double *ux, const double *uy, int row0,
@@ -60,6 +67,8 @@ void mirror_l(const DevDomain *dom, int nx, int ny, hipStream_t s) {
 
 template <int FEAT, int PLM, int WIDE> void fill(KernelSet *k) {
   k->sweep = sweep_l<FEAT, PLM, WIDE>;
+  if constexpr ((FEAT & (F_NOISE | F_POWER)) == 0 && WIDE == 0) k->sweep2 = sweep2_l<FEAT>;
+  else k->sweep2 = nullptr;
   k->init = init_l<FEAT, PLM, WIDE>;
   k->pre = pre_l;
   k->post = post_l;

@@ -76,7 +76,7 @@ Layout layout_of(const lb_domain_desc *d) {
   L.items = o; o += align256(np * sizeof(PItem));
   L.partials = o; o += align256(NPARTIALS * sizeof(double));
   L.stage = o; o += align256((size_t)L.band_rows * row_stage);
-  L.prefix = o; o += align256(2 * sizeof(int));
+  L.prefix = o; o += align256(4 * sizeof(int));
   L.total = o;
   return L;
 }
@@ -184,6 +184,7 @@ struct lb_domain {
   int64_t t = 0;
   bool use_graph = true;
   int chunk = 256;
+  bool two_step = true;  // LB_OPT_TWO_STEP
   GraphCache graphs;
   int in_batches = 0;
   std::vector<uint8_t> host_labels;  // walls + obstacles, [ny][pitch]
@@ -191,8 +192,10 @@ struct lb_domain {
   DevDomain *ddesc() const { return (DevDomain *)(ws + L.desc); }
   Header *dhdr() const { return (Header *)(ws + L.hdr); }
   int *dprefix() const { return (int *)(ws + L.prefix); }
+  int *dprefix2() const { return dprefix() + 2; }  // tiles of the two-step sweep
   PItem *ditems() const { return (PItem *)(ws + L.items); }
   int ntiles() const { return hd.tiles_x * hd.tiles_y; }
+  int ntiles2() const { return hd.tiles2_x * hd.tiles2_y; }
 };
 
 struct lb_batch {
@@ -200,13 +203,15 @@ struct lb_batch {
   char *ws = nullptr;
   hipStream_t stream = nullptr, cap = nullptr;
   KernelSet ks{};
-  int total_tiles = 0, nitems = 0;
+  int total_tiles = 0, total_tiles2 = 0, nitems = 0;
+  bool two_step = false;  // every domain takes the two-step sweep
   size_t off_desc = 0, off_prefix = 0, off_items = 0, bytes = 0;
   bool use_graph = true;
   int chunk = 256;
   GraphCache graphs;
   DevDomain *ddesc() const { return (DevDomain *)(ws + off_desc); }
   int *dprefix() const { return (int *)(ws + off_prefix); }
+  int *dprefix2() const { return dprefix() + doms.size() + 1; }
   PItem *ditems() const { return (PItem *)(ws + off_items); }
 };
 
@@ -223,7 +228,7 @@ void set_tiles(DevDomain &hd, int tile_w, int rpt) {
 
 lb_status push_desc(lb_domain *d) {
   HIPCHK(hipMemcpyAsync(d->ddesc(), &d->hd, sizeof(DevDomain), hipMemcpyHostToDevice, d->stream));
-  int pre[2] = {0, d->ntiles()};
+  int pre[4] = {0, d->ntiles(), 0, d->ntiles2()};
   HIPCHK(hipMemcpyAsync(d->dprefix(), pre, sizeof(pre), hipMemcpyHostToDevice, d->stream));
   HIPCHK(hipStreamSynchronize(d->stream));
   return LB_OK;
@@ -243,22 +248,43 @@ lb_status check_health(lb_domain *d) {
   return LB_OK;
 }
 
-// Enqueue `n` steps of the launch sequence on stream s (eager or under capture).
-void record_steps(const KernelSet &ks, const DevDomain *doms, const int *prefix, int ndom,
-                  int blocks, const PItem *items, int nitems, int n, hipStream_t s) {
-  for (int k = 0; k < n; ++k) {
-    if (nitems > 0) ks.pre(doms, items, nitems, k, s);
-    ks.sweep(doms, prefix, ndom, k, blocks, s);
-    if (nitems > 0) ks.post(doms, items, nitems, k, s);
+// What one step (or step pair) of a domain or batch launches.
+struct StepPlan {
+  const KernelSet *ks;
+  const DevDomain *doms;
+  const int *prefix;   // single-step tiles per domain
+  const int *prefix2;  // two-step tiles per domain
+  int ndom, blocks, blocks2;
+  const PItem *items;
+  int nitems;
+  bool two;  // two-step sweep (no particles, so no pre/post passes)
+};
+
+// Enqueue `n` steps of the launch sequence on stream s (eager or under
+// capture).  With the two-step sweep, each four steps are a pair of two-step
+// launches (the first leaves the state in the buffer of the other parity, the
+// second brings it back, so the state is where single steps expect it after
+// every pair); the n mod 4 remaining steps are single steps.
+void record_steps(const StepPlan &p, int n, hipStream_t s) {
+  int k = 0;
+  if (p.two) {
+    for (; k + 4 <= n; k += 4) {
+      p.ks->sweep2(p.doms, p.prefix2, p.ndom, k, 0, p.blocks2, s);
+      p.ks->sweep2(p.doms, p.prefix2, p.ndom, k + 2, 1, p.blocks2, s);
+    }
   }
-  launch_advance(doms, ndom, n, s);
+  for (; k < n; ++k) {
+    if (p.nitems > 0) p.ks->pre(p.doms, p.items, p.nitems, k, s);
+    p.ks->sweep(p.doms, p.prefix, p.ndom, k, p.blocks, s);
+    if (p.nitems > 0) p.ks->post(p.doms, p.items, p.nitems, k, s);
+  }
+  launch_advance(p.doms, p.ndom, n, s);
 }
 
 lb_status run_chunk(GraphCache &gc, bool use_graph, hipStream_t stream, hipStream_t cap,
-                    const KernelSet &ks, const DevDomain *doms, const int *prefix, int ndom,
-                    int blocks, const PItem *items, int nitems, int n) {
+                    const StepPlan &p, int n) {
   if (!use_graph) {
-    record_steps(ks, doms, prefix, ndom, blocks, items, nitems, n, stream);
+    record_steps(p, n, stream);
     HIPCHK(hipGetLastError());
     return LB_OK;
   }
@@ -266,7 +292,7 @@ lb_status run_chunk(GraphCache &gc, bool use_graph, hipStream_t stream, hipStrea
   if (it == gc.execs.end()) {
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    record_steps(ks, doms, prefix, ndom, blocks, items, nitems, n, cap);
+    record_steps(p, n, cap);
     hipError_t le = hipGetLastError();
     HIPCHK(hipStreamEndCapture(cap, &g));
     if (le != hipSuccess) {
@@ -281,6 +307,14 @@ lb_status run_chunk(GraphCache &gc, bool use_graph, hipStream_t stream, hipStrea
   }
   HIPCHK(hipGraphLaunch(it->second, stream));
   return LB_OK;
+}
+
+// The two-step sweep serves periodic domains without particles whose kernel
+// set has one (no noise, no power law, native arithmetic), unless switched
+// off with LB_OPT_TWO_STEP.
+bool two_step_ok(const lb_domain *d) {
+  return d->two_step && d->ks.sweep2 != nullptr && d->np == 0 && d->desc.max_particles == 0 &&
+         d->desc.bc_x == LB_PERIODIC && d->desc.bc_y == LB_PERIODIC;
 }
 
 // FP64 density sum of the current state; its final kernel also latches a
@@ -393,6 +427,8 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   h.feat = feat;
   set_tiles(h, default_tile_w(desc->nx), desc->storage >= LB_F16_DELTA ? 4 : 2);
   h.stream_stores = sweep_working_set(h) >= STREAM_STORE_MIN_BYTES;
+  h.tiles2_x = (h.nx + TS_COLS - 1) / TS_COLS;
+  h.tiles2_y = (h.ny + two_step_rows(h.storage) - 1) / two_step_rows(h.storage);
   h.rho0 = desc->rho0;
   h.tau = desc->power_law ? desc->tau_min : desc->tau;
   h.omega = 1.0 / h.tau;
@@ -568,8 +604,9 @@ lb_status lb_step(lb_domain *d, int64_t nsteps) {
   int64_t left = nsteps;
   while (left > 0) {
     const int c = (int)std::min<int64_t>(left, d->chunk);
-    lb_status s = run_chunk(d->graphs, d->use_graph, d->stream, d->cap, d->ks, d->ddesc(),
-                            d->dprefix(), 1, d->ntiles(), d->ditems(), d->np, c);
+    const StepPlan p{&d->ks, d->ddesc(), d->dprefix(), d->dprefix2(), 1, d->ntiles(),
+                     d->ntiles2(), d->ditems(), d->np, two_step_ok(d)};
+    lb_status s = run_chunk(d->graphs, d->use_graph, d->stream, d->cap, p, c);
     if (s != LB_OK) return s;
     left -= c;
   }
@@ -674,8 +711,8 @@ lb_status lb_set_populations(lb_domain *d, const double *hf) {
 lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
   if (!d) return fail(LB_EINVAL, "null domain");
   if (d->in_batches && (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD ||
-                        key == LB_OPT_FORCE_AVERAGE))
-    return fail(LB_ESTATE, "tile and force options are fixed while the domain is in a batch");
+                        key == LB_OPT_FORCE_AVERAGE || key == LB_OPT_TWO_STEP))
+    return fail(LB_ESTATE, "tile, force and two-step options are fixed while the domain is in a batch");
   switch (key) {
     case LB_OPT_USE_GRAPH: d->use_graph = value != 0; break;
     case LB_OPT_TILE_WIDTH:
@@ -694,6 +731,10 @@ lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
       if (value != 0 && value != 1) return fail(LB_EINVAL, "force averaging is 0 or 1");
       d->hd.feat = value ? (d->hd.feat | F_FAVG) : (d->hd.feat & ~F_FAVG);
       break;
+    case LB_OPT_TWO_STEP:
+      if (value != 0 && value != 1) return fail(LB_EINVAL, "two-step sweep is 0 or 1");
+      d->two_step = value != 0;
+      break;
     default: return fail(LB_EINVAL, "unknown option");
   }
   d->graphs.clear();
@@ -710,6 +751,7 @@ lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value) {
     case LB_OPT_ROWS_PER_THREAD: *value = d->hd.rows_per_thread; return LB_OK;
     case LB_OPT_GRAPH_CHUNK: *value = d->chunk; return LB_OK;
     case LB_OPT_FORCE_AVERAGE: *value = (d->hd.feat & F_FAVG) ? 1 : 0; return LB_OK;
+    case LB_OPT_TWO_STEP: *value = d->two_step ? 1 : 0; return LB_OK;
   }
   return fail(LB_EINVAL, "unknown option");
 }
@@ -772,7 +814,7 @@ lb_status lb_batch_workspace_bytes(lb_domain *const *domains, int32_t n, size_t 
     if (!domains[i]) return fail(LB_EINVAL, "null domain");
     items += domains[i]->np;
   }
-  *bytes = align256((size_t)n * sizeof(DevDomain)) + align256((size_t)(n + 1) * sizeof(int)) +
+  *bytes = align256((size_t)n * sizeof(DevDomain)) + align256((size_t)2 * (n + 1) * sizeof(int)) +
            align256(std::max<size_t>(items, 1) * sizeof(PItem));
   return LB_OK;
 }
@@ -808,16 +850,22 @@ lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_worksp
   b->ks = domains[lab_dom >= 0 ? lab_dom : 0]->ks;
   b->off_desc = 0;
   b->off_prefix = align256((size_t)n * sizeof(DevDomain));
-  b->off_items = b->off_prefix + align256((size_t)(n + 1) * sizeof(int));
+  b->off_items = b->off_prefix + align256((size_t)2 * (n + 1) * sizeof(int));
   b->bytes = need;
   std::vector<DevDomain> descs(n);
-  std::vector<int> prefix(n + 1, 0);
+  // single-step tile prefix [0, n], then the two-step one [n + 1, 2n + 1]
+  std::vector<int> prefix(2 * (n + 1), 0);
   std::vector<PItem> items;
+  bool two = b->ks.sweep2 != nullptr;
   for (int i = 0; i < n; ++i) {
     descs[i] = domains[i]->hd;
     prefix[i + 1] = prefix[i] + domains[i]->ntiles();
+    prefix[n + 2 + i] = prefix[n + 1 + i] + domains[i]->ntiles2();
     for (int q = 0; q < domains[i]->np; ++q) items.push_back(PItem{i, q});
+    two = two && two_step_ok(domains[i]);
   }
+  b->two_step = two;
+  b->total_tiles2 = prefix[2 * n + 1];
   size_t working_set = 0;
   for (int i = 0; i < n; ++i) working_set += sweep_working_set(descs[i]);
   for (int i = 0; i < n; ++i) descs[i].stream_stores = working_set >= STREAM_STORE_MIN_BYTES;
@@ -828,7 +876,7 @@ lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_worksp
     return fail(LB_EHIP, "hipStreamCreateWithFlags failed");
   }
   bool ok = hipMemcpyAsync(b->ddesc(), descs.data(), n * sizeof(DevDomain), hipMemcpyHostToDevice, b->stream) == hipSuccess &&
-            hipMemcpyAsync(b->dprefix(), prefix.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+            hipMemcpyAsync(b->dprefix(), prefix.data(), prefix.size() * sizeof(int), hipMemcpyHostToDevice, b->stream) == hipSuccess &&
             (items.empty() || hipMemcpyAsync(b->ditems(), items.data(), items.size() * sizeof(PItem), hipMemcpyHostToDevice, b->stream) == hipSuccess) &&
             hipStreamSynchronize(b->stream) == hipSuccess;
   if (!ok) {
@@ -850,9 +898,9 @@ lb_status lb_batch_step(lb_batch *b, int64_t nsteps) {
   int64_t left = nsteps;
   while (left > 0) {
     const int c = (int)std::min<int64_t>(left, b->chunk);
-    lb_status s = run_chunk(b->graphs, b->use_graph, b->stream, b->cap, b->ks, b->ddesc(),
-                            b->dprefix(), (int)b->doms.size(), b->total_tiles, b->ditems(),
-                            b->nitems, c);
+    const StepPlan p{&b->ks, b->ddesc(), b->dprefix(), b->dprefix2(), (int)b->doms.size(),
+                     b->total_tiles, b->total_tiles2, b->ditems(), b->nitems, b->two_step};
+    lb_status s = run_chunk(b->graphs, b->use_graph, b->stream, b->cap, p, c);
     if (s != LB_OK) return s;
     left -= c;
   }

@@ -58,6 +58,14 @@ enum : int {
 // Power-law exponent specialisations.
 enum : int { PL_GENERIC = 0, PL_HALF = 1, PL_3Q = 2, PL_3H = 3 };
 
+// Tiles of the two-step sweep (k_sweep2): TS_COLS output columns (the 64
+// lanes of a wave less a one-node rim) by two_step_rows output rows (its LDS
+// holds rows + 2 rows of 64 columns x 9 values).
+constexpr int TS_COLS = 62;
+constexpr int two_step_rows(int storage) {
+  return storage == ST_F64 ? 6 : (storage == ST_F32 ? 12 : 16);
+}
+
 // Labels: 0 fluid, 1 solid, 2 + p inside particle p.
 constexpr uint8_t LBL_FLUID = 0, LBL_SOLID = 1, LBL_PART0 = 2;
 // particles per domain: labels 2 .. 2 + 249 fit the uint8 label plane
@@ -94,6 +102,7 @@ struct alignas(256) DevDomain {
   int bc_x, bc_y;
   int np;              // particles
   int tile_w, rows_per_thread, tiles_x, tiles_y;
+  int tiles2_x, tiles2_y;  // tiles of the two-step sweep (k_sweep2)
   uint32_t key0, key1; // noise generator key
   int storage, feat;
   int stream_stores;   // 1: the sweep's stores bypass the caches (see k_sweep)

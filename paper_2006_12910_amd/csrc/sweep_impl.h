@@ -113,6 +113,19 @@ template <> __device__ __forceinline__ float recip<float>(float x) {
   return fmaf(fmaf(-x, r, 1.0f), r, r);
 }
 
+// Fused multiply-add in the arithmetic type.  The library is compiled without
+// floating-point contraction (so every kernel rounds a node's arithmetic the
+// same way); the products that should fuse are written with fmar.
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// delta rho of deviations in the stored scaling (the factors are powers of
+// two, so the fused form rounds as the sum of the scaled values)
+template <int ST, class R> __device__ __forceinline__ R scaled_drho(const R d[9]) {
+  constexpr R i0 = R(1) / R(kscale<ST>(0)), i1 = R(1) / R(kscale<ST>(1)), i5 = R(1) / R(kscale<ST>(5));
+  return fmar(i0, d[0], fmar(i1, (d[1] + d[3]) + (d[2] + d[4]), i5 * ((d[5] + d[7]) + (d[6] + d[8]))));
+}
+
 // BGK collision of one node, step `step`, in arithmetic type R.  The values
 // are the deviations d_i = f_i - w_i rho0 in the stored scaling: times K0, K1,
 // K5 for rest, axis and diagonal directions (powers of two: 2, 8, 32 for the
@@ -133,10 +146,9 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
                                              uint32_t step) {
   constexpr R K0 = R(kscale<ST>(0)), K1 = R(kscale<ST>(1)), K5 = R(kscale<ST>(5));
   constexpr R i0 = R(1) / K0, i1 = R(1) / K1, i5 = R(1) / K5;
-  const R drho = i0 * d[0] + (i1 * ((d[1] + d[3]) + (d[2] + d[4])) +
-                              i5 * ((d[5] + d[7]) + (d[6] + d[8])));
-  const R jx = i1 * (d[1] - d[3]) + i5 * ((d[5] - d[6]) + (d[8] - d[7]));
-  const R jy = i1 * (d[2] - d[4]) + i5 * ((d[5] + d[6]) - (d[7] + d[8]));
+  const R drho = scaled_drho<ST, R>(d);
+  const R jx = fmar(i1, d[1] - d[3], i5 * ((d[5] - d[6]) + (d[8] - d[7])));
+  const R jy = fmar(i1, d[2] - d[4], i5 * ((d[5] + d[6]) - (d[7] + d[8])));
   const R rho = par<R>(D.rho0, D.rho0_f) + drho;
   const R irho = recip<R>(rho);
   R tau, om;
@@ -147,21 +159,24 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
     tau = par<R>(D.tau, D.tau_f);
     om = par<R>(D.omega, D.omega_f);
   }
-  const R Jx = jx + rho * tau * par<R>(D.gx, D.gx_f);
-  const R Jy = jy + rho * tau * par<R>(D.gy, D.gy_f);
+  const R rt = rho * tau;
+  const R Jx = fmar(rt, par<R>(D.gx, D.gx_f), jx);
+  const R Jy = fmar(rt, par<R>(D.gy, D.gy_f), jy);
   const R ux = Jx * irho, uy = Jy * irho;
   const R W1 = R(1) / R(9), W5 = R(0.25) * W1;
   const R L1 = R(1) / R(3), L5 = (R(1) - R(2) * L1) * R(0.25);
-  const R q = R(1.5) * rho * (ux * ux + uy * uy);
+  const R q = (R(1.5) * rho) * fmar(ux, ux, uy * uy);
   const R r45 = R(4.5) * rho;
   const R sp = ux + uy, sm = uy - ux;
   // even parts and linear terms, already in the stored scaling
-  const R cxx = (K1 * W1) * (drho + (r45 * ux * ux - q)), cyy = (K1 * W1) * (drho + (r45 * uy * uy - q));
-  const R cpp = (K5 * W5) * (drho + (r45 * sp * sp - q)), cmm = (K5 * W5) * (drho + (r45 * sm * sm - q));
+  const R cxx = (K1 * W1) * (drho + fmar(r45 * ux, ux, -q));
+  const R cyy = (K1 * W1) * (drho + fmar(r45 * uy, uy, -q));
+  const R cpp = (K5 * W5) * (drho + fmar(r45 * sp, sp, -q));
+  const R cmm = (K5 * W5) * (drho + fmar(r45 * sm, sm, -q));
   const R lx = (K1 * L1) * Jx, ly = (K1 * L1) * Jy;
   const R lp = (K5 * L5) * (Jx + Jy), lm = (K5 * L5) * (Jy - Jx);
   R eq[9];
-  eq[0] = K0 * (drho - R(2) * (i1 * (cxx + cyy) + i5 * (cpp + cmm)));
+  eq[0] = K0 * fmar(R(-2), fmar(i1, cxx + cyy, i5 * (cpp + cmm)), drho);
   eq[1] = cxx + lx;
   eq[3] = cxx - lx;
   eq[2] = cyy + ly;
@@ -171,7 +186,7 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
   eq[6] = cmm + lm;
   eq[8] = cmm - lm;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) d[i] = d[i] + om * (eq[i] - d[i]);
+  for (int i = 0; i < 9; ++i) d[i] = fmar(om, eq[i] - d[i], d[i]);
 
   if constexpr ((FEAT & F_NOISE) != 0) {
     float th[6];
@@ -215,11 +230,6 @@ __device__ __forceinline__ void encode_node(const DevDomain &D, const R d[9], ui
   }
 }
 
-// delta rho of deviations in the stored scaling
-template <int ST, class R> __device__ __forceinline__ R scaled_drho(const R d[9]) {
-  constexpr R i0 = R(1) / R(kscale<ST>(0)), i1 = R(1) / R(kscale<ST>(1)), i5 = R(1) / R(kscale<ST>(5));
-  return i0 * d[0] + (i1 * ((d[1] + d[3]) + (d[2] + d[4])) + i5 * ((d[5] + d[7]) + (d[6] + d[8])));
-}
 
 template <int ST, class R>
 __device__ __forceinline__ void store_node(const DevDomain &D, typename Store<ST>::T *dst,

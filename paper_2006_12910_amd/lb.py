@@ -22,6 +22,7 @@ COMPUTE_NATIVE, COMPUTE_F64 = 0, 1
 INIT_REST, INIT_FIELDS = 0, 1
 PARTICLE_FIXED = 1
 OPT_USE_GRAPH, OPT_TILE_WIDTH, OPT_ROWS_PER_THREAD, OPT_GRAPH_CHUNK, OPT_FORCE_AVERAGE = 1, 2, 3, 4, 5
+OPT_TWO_STEP = 6
 ABI_VERSION = 1
 
 _BC = {"periodic": PERIODIC, "wall": WALL, "pressure": PRESSURE}
