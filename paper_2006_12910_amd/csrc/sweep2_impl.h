@@ -138,14 +138,14 @@ __global__ __launch_bounds__(256) void k_sweep2(const DevDomain *__restrict__ do
     T q[9];
     if (sr) encode_node<ST, R, true>(D, e, node, step2, q);
     else encode_node<ST, R, false>(D, e, node, step2, q);
+    // Ordinary (cached) stores: a tile row is 62 values, so most 128-byte
+    // lines are written in two parts by neighbouring workgroups, and the
+    // cache merges the parts into one line write.  Streaming stores sent the
+    // parts out separately (37 % more bytes written; 8192^2 FP16 0.50 ms
+    // against 0.37 ms per two steps).
     const uint32_t colB = (uint32_t)x * B, rowB = (uint32_t)y * pitchB;
-    if (D.stream_stores) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) bstore<T, true>(dst, colB, (uint32_t)i * planeB + rowB, q[i]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) bstore<T, false>(dst, colB, (uint32_t)i * planeB + rowB, q[i]);
-    }
+    for (int i = 0; i < 9; ++i) bstore<T, false>(dst, colB, (uint32_t)i * planeB + rowB, q[i]);
   }
   if (bad) atomicOr(D.health, HEALTH_NONFINITE);
 }
