@@ -181,17 +181,27 @@ def parse_tiles(text):
     return out
 
 
-def run_variant(storage, specs, masks, steps, warmup, tune, fixed_tiles=None):
+def run_variant(storage, specs, masks, steps, warmup, tune, fixed_tiles=None, two_step=True):
+    """The batch of the workload in one storage format, timed over `steps`
+    steps after `warmup`.  With the two-step sweep (every domain qualifies:
+    periodic, no particles) the tile shapes are fixed and not tuned; with
+    single steps the autotuner picks them."""
     import torch
     from paper_2006_12910_amd import lb
     t0 = time.time()
+    tune = tune and not two_step
     tiles = fixed_tiles if fixed_tiles else (tune_batch(storage, specs, masks) if tune else None)
     doms = build_variant(storage, specs, masks, tiles)
-    # the shapes in use, per class (explicit also where the defaults won)
-    tiles = {}
-    for d, spec in zip(doms, specs):
-        tiles.setdefault(size_bucket(spec), (d.get_option(lb.OPT_TILE_WIDTH),
-                                             d.get_option(lb.OPT_ROWS_PER_THREAD)))
+    for d in doms:
+        d.set_option(lb.OPT_TWO_STEP, 1 if two_step else 0)
+    # the single-step shapes in use, per class (explicit also where the
+    # defaults won); the two-step sweep's tiles are fixed
+    tiles = None
+    if not two_step:
+        tiles = {}
+        for d, spec in zip(doms, specs):
+            tiles.setdefault(size_bucket(spec), (d.get_option(lb.OPT_TILE_WIDTH),
+                                                 d.get_option(lb.OPT_ROWS_PER_THREAD)))
     batch = lb.Batch(doms)
     torch.cuda.synchronize()
     log(f"{storage}: built {len(doms)} domains in {time.time() - t0:.1f}s")
@@ -449,6 +459,8 @@ def main():
                     help="seconds of oracle work for the CPU baseline and the L2 sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline and L2 sample")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes instead of the autotuner's")
+    ap.add_argument("--single-step", action="store_true",
+                    help="one step per launch (two-step sweep off), tile shapes autotuned")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the rates of the other four workloads and of the paper's three "
                          "benchmarks (reported beside the main line)")
@@ -502,7 +514,8 @@ def main():
     results = {}
     for v in variants:
         doms, batch, ms, tiles = run_variant(v, specs, masks, args.steps, args.warmup, not args.no_tune,
-                                             parse_tiles(args.tiles) if args.tiles else None)
+                                             parse_tiles(args.tiles) if args.tiles else None,
+                                             two_step=not args.single_step)
         mlups = sites * args.steps / (ms * 1e-3) / 1e6
         mflups = fluid_sites * args.steps / (ms * 1e-3) / 1e6
         bytes_alg = algorithmic_bytes(specs, masks, STORAGE_BYTES[v])
@@ -511,7 +524,7 @@ def main():
                  "sweep_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                  "bytes_per_step": bytes_alg, "rounding": ROUNDING[v],
                  "two_step": all(d.get_option(lb.OPT_TWO_STEP) == 1 for d in doms),
-                 "tiles": None if tiles is None else {f"{'obstacles' if k[0] else 'open'}/class{k[1]}": f"{t[0]}x{t[1]}"
+                 "tiles": "two-step: 62 columns x 16/12/6 rows (16-bit/FP32/FP64) per tile" if tiles is None else {f"{'obstacles' if k[0] else 'open'}/class{k[1]}": f"{t[0]}x{t[1]}"
                                                        for k, t in tiles.items()}}
         if ref:
             entry["l2_vs_oracle"] = dict(l2_errors(doms, ref, specs), after_steps=nsteps_total,
