@@ -85,3 +85,14 @@ def test_null_arguments_are_rejected():
     assert lib.lb_moments(None, None, None, None) == lb.LB_EINVAL
     assert lib.lb_destroy_domain(None) == lb.LB_EINVAL
     assert lib.lb_status_string(lb.LB_EUNSTABLE).decode().startswith("simulation")
+
+
+def test_binding_constants_match_the_header():
+    """Every LB_* integer constant of include/lb.h has the same value in the
+    Python binding (options, storage formats, boundaries, status codes)."""
+    from paper_2006_12910_amd import lb
+    src = open(os.path.join(ROOT, "include", "lb.h")).read()
+    consts = dict((k, int(v)) for k, v in re.findall(r"^#define (LB_OPT_\w+) (\d+)", src, re.M))
+    assert "LB_OPT_TWO_STEP" in consts
+    for name, value in consts.items():
+        assert getattr(lb, name[len("LB_"):]) == value, name
