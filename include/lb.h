@@ -228,9 +228,10 @@ lb_status lb_batch_destroy(lb_batch *b);
 lb_status lb_noise_normals(uint64_t seed, uint32_t domain_id, uint32_t step, uint32_t node0,
                            uint32_t count, float *dev_out, void *hip_stream);
 
-/* Autotune the sweep tile for this domain: times each candidate tile width /
- * rows-per-thread pair over `steps` steps (the state advances) and keeps the
- * fastest.  *best_ms receives its time per step. */
+/* Autotune the single-step sweep's tile for this domain: times each candidate
+ * tile width / rows-per-thread pair over `steps` single steps (the state
+ * advances; the two-step sweep, whose tiles are fixed, is off while timing)
+ * and keeps the fastest.  *best_ms receives its time per step. */
 lb_status lb_autotune(lb_domain *d, int32_t steps, double *best_ms);
 
 const char *lb_status_string(lb_status s);

@@ -767,7 +767,10 @@ lb_status lb_autotune(lb_domain *d, int32_t steps, double *best_ms) {
   double best = 1e300;
   int bw = d->hd.tile_w, br = d->hd.rows_per_thread;
   const int saved_chunk = d->chunk;
+  const bool saved_two = d->two_step;
   d->chunk = std::max(1, std::min(steps, 4096));
+  d->two_step = false;  // the shapes tuned are the single-step sweep's
+  d->graphs.clear();
   lb_status s = LB_OK;
   for (int w : widths) {
     if (w > 64 && w / 2 >= d->desc.nx) continue;
@@ -790,6 +793,8 @@ lb_status lb_autotune(lb_domain *d, int32_t steps, double *best_ms) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   d->chunk = saved_chunk;
+  d->two_step = saved_two;
+  d->graphs.clear();
   if (s != LB_OK) return s;
   if ((s = lb_set_option(d, LB_OPT_TILE_WIDTH, bw)) != LB_OK) return s;
   if ((s = lb_set_option(d, LB_OPT_ROWS_PER_THREAD, br)) != LB_OK) return s;

@@ -83,3 +83,24 @@ def test_two_step_not_taken_where_not_supported():
         assert np.array_equal(doms[0].populations(), doms[1].populations())
         for d in doms:
             d.close()
+
+
+def test_autotune_times_single_steps_and_keeps_the_option():
+    """The autotuner tunes the single-step tiles with the two-step sweep off,
+    then restores it; the steps it timed advance the state exactly as plain
+    steps do (tiles do not change results)."""
+    a = _domain(300, 140, "f16", "stochastic", True, 1)
+    b = _domain(300, 140, "f16", "stochastic", True, 1)
+    ms = a.autotune(steps=4)
+    assert ms > 0
+    assert a.get_option(lb.OPT_TWO_STEP) == 1
+    assert a.get_option(lb.OPT_TILE_WIDTH) in (64, 128, 256)
+    assert a.get_option(lb.OPT_ROWS_PER_THREAD) in (2, 4, 8)
+    t = a.time
+    assert t > 0 and t % 8 == 0  # warm-up and timed runs of 4 steps per shape
+    b.step(t)
+    a.step(6)
+    b.step(6)
+    assert np.array_equal(a.populations(), b.populations())
+    a.close()
+    b.close()
