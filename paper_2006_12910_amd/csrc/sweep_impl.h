@@ -145,7 +145,7 @@ template <int ST, int FEAT, int PLM, class R>
 __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_t node,
                                              uint32_t step) {
   constexpr R K0 = R(kscale<ST>(0)), K1 = R(kscale<ST>(1)), K5 = R(kscale<ST>(5));
-  constexpr R i0 = R(1) / K0, i1 = R(1) / K1, i5 = R(1) / K5;
+  constexpr R i1 = R(1) / K1, i5 = R(1) / K5;
   const R drho = scaled_drho<ST, R>(d);
   const R jx = fmar(i1, d[1] - d[3], i5 * ((d[5] - d[6]) + (d[8] - d[7])));
   const R jy = fmar(i1, d[2] - d[4], i5 * ((d[5] + d[6]) - (d[7] + d[8])));
