@@ -363,6 +363,67 @@ def other_configs(with_oracle):
 PAPER_BEST_CPU_MLUPS = {"b1": 47.27, "b2": 138.20, "b3": 85.85}
 
 
+def reporting_offload(steps=600, intervals=(10, 100)):
+    """Steps with the moments reported to the host every `interval` steps, on
+    the porous 2048 x 1024 workload with 16 discs (FP32): no reporting; the
+    synchronous call (lb_moments into pageable host arrays); the offloaded one
+    (lb_moments_async on a copy stream into pinned host arrays, two staging
+    sets used in turn, each report consumed on the host after its wait while
+    later steps run).  Wall-clock ms per step, whole loop synchronised."""
+    import numpy as np
+    import torch
+    from paper_2006_12910_amd import inputs, lb
+    mask, _ = inputs.porous_channel()
+    parts = [dict(x=x, y=y, radius=8.0, density_ratio=1.05) for x, y in inputs.particle_block()]
+    d = lb.Domain(2048, 1024, storage="f32", bc_x="pressure", bc_y="wall", tau=0.7, rho_in=1.001,
+                  rho_out=0.999, obstacles=mask, max_particles=16, lj=(1e-3, 2.5, 0.5))
+    d.set_option(lb.OPT_FORCE_AVERAGE, 1)
+    d.add_particles(parts)
+    n = d.nx * d.ny
+    copy = torch.cuda.Stream()
+    stages = [torch.empty(3 * n, dtype=torch.float64, device="cuda") for _ in range(2)]
+    hosts = [[torch.empty((d.ny, d.nx), dtype=torch.float64, pin_memory=True) for _ in range(3)]
+             for _ in range(2)]
+    sink = []
+
+    def timed(body):
+        d.step(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        body()
+        torch.cuda.synchronize()
+        return round((time.perf_counter() - t0) * 1e3 / steps, 4)
+
+    def plain():
+        d.step(steps)
+
+    out = {"workload": "porous 2048x1024, 16 discs, FP32", "steps": steps,
+           "ms_per_step_no_reporting": timed(plain)}
+    for every in intervals:
+        def sync():
+            for _ in range(steps // every):
+                d.step(every)
+                r, u, v = d.moments()
+                sink.append(float(u[::64, ::64].sum()))
+
+        def offload():
+            k = 0
+            for _ in range(steps // every):
+                d.step(every)
+                d.moments_wait()  # the report before last has landed: consume it
+                if k >= 1:
+                    sink.append(float(hosts[(k - 1) % 2][1].numpy()[::64, ::64].sum()))
+                d.moments_async(stages[k % 2], *hosts[k % 2], copy)
+                k += 1
+            d.moments_wait()
+            sink.append(float(hosts[(k - 1) % 2][1].numpy()[::64, ::64].sum()))
+
+        out[f"every_{every}"] = {"sync_ms_per_step": timed(sync),
+                                 "offload_ms_per_step": timed(offload)}
+    d.close()
+    return out
+
+
 def paper_replicas(with_oracle):
     """GPU MLUPS of stand-ins for the paper's three timing benchmarks on their
     full lattices (FP32 storage; the set-ups of tests/test_gpu_paper_benchmarks.py),
@@ -553,7 +614,7 @@ def main():
                 "steps_per_launch": spl,
                 "algorithmic_bytes_per_launch": spl * head["bytes_per_step"],
                 "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
-    configs = replicas = None
+    configs = replicas = offload = None
     if not args.no_configs:
         t0 = time.time()
         configs = other_configs(with_oracle=not args.no_cpu)
@@ -561,6 +622,9 @@ def main():
         t0 = time.time()
         replicas = paper_replicas(with_oracle=not args.no_cpu)
         log(f"paper benchmarks ({time.time() - t0:.0f}s): {json.dumps(replicas)}")
+        t0 = time.time()
+        offload = reporting_offload()
+        log(f"reporting offload ({time.time() - t0:.0f}s): {json.dumps(offload)}")
     out = {
         "metric": METRIC, "value": head["mlups"], "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
@@ -576,6 +640,7 @@ def main():
         "variants": results,
         "other_workloads": configs,
         "paper_benchmarks": replicas,
+        "reporting_offload": offload,
     }
     print(json.dumps(out), flush=True)
 

@@ -163,6 +163,26 @@ lb_status lb_moments(lb_domain *d, double *rho, double *ux, double *uy);
 /* Same, into device FP64 arrays [ny][nx] (no synchronisation). */
 lb_status lb_moments_device(lb_domain *d, double *dev_rho, double *dev_ux, double *dev_uy);
 
+/* Reporting offload (the analogue of the paper's output offloading from the
+ * simulation threads, Sec. 7, task-level pipelining): enqueue on the domain's stream the moments of the
+ * current state (as lb_moments) into dev_stage, caller-owned device memory of
+ * 3 nx ny doubles ([rho][ux][uy], each [ny][nx]), then copy them on
+ * copy_stream (another stream of the same device, not the domain's) into the
+ * host arrays rho, ux, uy ([ny][nx] each), which should be pinned memory
+ * (hipHostMalloc; torch pin_memory) for the copy to run asynchronously.
+ * Returns without waiting: steps enqueued afterwards run while the copy
+ * proceeds.  dev_stage and the host arrays must stay untouched until
+ * lb_moments_wait returns; a later call waits on the device for an earlier
+ * call's copy before it writes dev_stage again.  Errors: LB_EINVAL for a null
+ * pointer or copy_stream equal to the domain's stream; the state's health is
+ * reported by the next synchronising call, as for lb_step. */
+lb_status lb_moments_async(lb_domain *d, double *dev_stage, double *rho, double *ux, double *uy,
+                           void *copy_stream);
+/* Block until the copy of the last lb_moments_async call has landed in host
+ * memory (returns at once if none is pending).  Does not wait for the
+ * domain's stream. */
+lb_status lb_moments_wait(lb_domain *d);
+
 /* Copy out the first n particles' state (n <= count).  Synchronises. */
 lb_status lb_get_particles(lb_domain *d, lb_particle *out, int32_t n);
 

@@ -188,6 +188,10 @@ struct lb_domain {
   GraphCache graphs;
   int in_batches = 0;
   std::vector<uint8_t> host_labels;  // walls + obstacles, [ny][pitch]
+  // asynchronous moment output: moments computed (on stream), copied out
+  // (on the caller's copy stream); a copy in flight until lb_moments_wait
+  hipEvent_t rep_ready = nullptr, rep_copied = nullptr;
+  bool rep_pending = false;
 
   DevDomain *ddesc() const { return (DevDomain *)(ws + L.desc); }
   Header *dhdr() const { return (Header *)(ws + L.hdr); }
@@ -622,6 +626,40 @@ lb_status lb_moments_device(lb_domain *d, double *rho, double *ux, double *uy) {
   return LB_OK;
 }
 
+lb_status lb_moments_async(lb_domain *d, double *dev_stage, double *rho, double *ux, double *uy,
+                           void *copy_stream) {
+  if (!d || !dev_stage || !rho || !ux || !uy) return fail(LB_EINVAL, "null argument");
+  hipStream_t cs = (hipStream_t)copy_stream;
+  if (cs == d->stream) return fail(LB_EINVAL, "the copy stream must differ from the domain's stream");
+  if (!d->rep_ready) {
+    HIPCHK(hipEventCreateWithFlags(&d->rep_ready, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&d->rep_copied, hipEventDisableTiming));
+  }
+  const int nx = d->desc.nx, ny = d->desc.ny;
+  const size_t cnt = (size_t)nx * ny;
+  // the staging memory of an earlier call may still be being copied out
+  if (d->rep_pending) HIPCHK(hipStreamWaitEvent(d->stream, d->rep_copied, 0));
+  d->ks.moments(d->ddesc(), dev_stage, dev_stage + cnt, dev_stage + 2 * cnt, 0, ny, nx, d->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(d->rep_ready, d->stream));
+  HIPCHK(hipStreamWaitEvent(cs, d->rep_ready, 0));
+  HIPCHK(hipMemcpyAsync(rho, dev_stage, cnt * 8, hipMemcpyDeviceToHost, cs));
+  HIPCHK(hipMemcpyAsync(ux, dev_stage + cnt, cnt * 8, hipMemcpyDeviceToHost, cs));
+  HIPCHK(hipMemcpyAsync(uy, dev_stage + 2 * cnt, cnt * 8, hipMemcpyDeviceToHost, cs));
+  HIPCHK(hipEventRecord(d->rep_copied, cs));
+  d->rep_pending = true;
+  return LB_OK;
+}
+
+lb_status lb_moments_wait(lb_domain *d) {
+  if (!d) return fail(LB_EINVAL, "null domain");
+  if (d->rep_pending) {
+    HIPCHK(hipEventSynchronize(d->rep_copied));
+    d->rep_pending = false;
+  }
+  return LB_OK;
+}
+
 lb_status lb_moments(lb_domain *d, double *rho, double *ux, double *uy) {
   if (!d || !rho || !ux || !uy) return fail(LB_EINVAL, "null argument");
   const int nx = d->desc.nx;
@@ -806,6 +844,11 @@ lb_status lb_destroy_domain(lb_domain *d) {
   if (!d) return fail(LB_EINVAL, "null domain");
   if (d->in_batches) return fail(LB_ESTATE, "destroy the batches that hold this domain first");
   (void)hipStreamSynchronize(d->stream);
+  if (d->rep_ready) {
+    (void)hipEventSynchronize(d->rep_copied);
+    (void)hipEventDestroy(d->rep_ready);
+    (void)hipEventDestroy(d->rep_copied);
+  }
   d->graphs.clear();
   (void)hipStreamDestroy(d->cap);
   delete d;

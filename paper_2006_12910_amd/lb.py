@@ -31,7 +31,8 @@ _RND = {"nearest": ROUND_NEAREST, "stochastic": ROUND_STOCHASTIC}
 
 EXPORTED = [
     "lb_workspace_bytes", "lb_create_domain", "lb_set_obstacles", "lb_add_particles", "lb_step",
-    "lb_moments", "lb_moments_device", "lb_get_particles", "lb_mass", "lb_time",
+    "lb_moments", "lb_moments_device", "lb_moments_async", "lb_moments_wait", "lb_get_particles",
+    "lb_mass", "lb_time",
     "lb_get_populations", "lb_set_populations", "lb_set_option", "lb_get_option",
     "lb_destroy_domain", "lb_batch_workspace_bytes", "lb_batch_create", "lb_batch_step",
     "lb_batch_set_option", "lb_batch_destroy", "lb_noise_normals", "lb_autotune",
@@ -93,6 +94,8 @@ def library():
         "lb_step": [vp, C.c_int64],
         "lb_moments": [vp, dp, dp, dp],
         "lb_moments_device": [vp, vp, vp, vp],
+        "lb_moments_async": [vp, vp, vp, vp, vp, vp],
+        "lb_moments_wait": [vp],
         "lb_get_particles": [vp, P(Particle), st],
         "lb_mass": [vp, dp],
         "lb_time": [vp, P(C.c_int64)],
@@ -178,6 +181,7 @@ class Domain:
         self.desc = d
         self.nx, self.ny = int(nx), int(ny)
         self._np = 0
+        self._report_refs = []  # buffers of an asynchronous moment copy in flight
         nbytes = C.c_size_t()
         _check(lib.lb_workspace_bytes(C.byref(d), C.byref(nbytes)), "lb_workspace_bytes")
         self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
@@ -200,6 +204,7 @@ class Domain:
         if getattr(self, "_h", None):
             _check(library().lb_destroy_domain(self._h), "lb_destroy_domain")
             self._h = None
+            self._report_refs = []
 
     def __del__(self):
         try:
@@ -243,6 +248,31 @@ class Domain:
                                            C.c_void_p(t[1].data_ptr()),
                                            C.c_void_p(t[2].data_ptr())), "lb_moments_device")
         return t
+
+    def moments_async(self, stage, rho, ux, uy, copy_stream):
+        """Moments of the current state into ``stage`` (device float64, at least
+        3 ny nx elements) on the domain's stream, copied on ``copy_stream`` (a
+        torch.cuda.Stream other than the domain's) into the pinned host float64
+        tensors ``rho``, ``ux``, ``uy`` of shape (ny, nx).  Returns at once;
+        ``moments_wait()`` blocks until the copy has landed.  The tensors are
+        held until then."""
+        n = self.ny * self.nx
+        if not (stage.is_cuda and stage.dtype == torch.float64 and stage.is_contiguous()
+                and stage.numel() >= 3 * n):
+            raise ValueError("stage: contiguous device float64 tensor of >= 3 ny nx elements")
+        for h in (rho, ux, uy):
+            if (h.is_cuda or h.dtype != torch.float64 or tuple(h.shape) != (self.ny, self.nx)
+                    or not h.is_contiguous() or not h.is_pinned()):
+                raise ValueError("host arrays: pinned contiguous float64 tensors of shape (ny, nx)")
+        _check(library().lb_moments_async(
+            self._h, C.c_void_p(stage.data_ptr()), C.c_void_p(rho.data_ptr()),
+            C.c_void_p(ux.data_ptr()), C.c_void_p(uy.data_ptr()),
+            C.c_void_p(copy_stream.cuda_stream)), "lb_moments_async")
+        self._report_refs.append((stage, rho, ux, uy, copy_stream))
+
+    def moments_wait(self):
+        _check(library().lb_moments_wait(self._h), "lb_moments_wait")
+        self._report_refs = []
 
     def particles(self, n=None):
         """[n][10]: x, y, radius, density_ratio, ux, uy, omega, fx, fy, torque."""

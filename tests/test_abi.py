@@ -83,6 +83,8 @@ def test_null_arguments_are_rejected():
     lib = lb.library()
     assert lib.lb_step(None, 1) == lb.LB_EINVAL
     assert lib.lb_moments(None, None, None, None) == lb.LB_EINVAL
+    assert lib.lb_moments_async(None, None, None, None, None, None) == lb.LB_EINVAL
+    assert lib.lb_moments_wait(None) == lb.LB_EINVAL
     assert lib.lb_destroy_domain(None) == lb.LB_EINVAL
     assert lib.lb_status_string(lb.LB_EUNSTABLE).decode().startswith("simulation")
 

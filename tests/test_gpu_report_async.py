@@ -1,0 +1,70 @@
+"""Reporting offload: moments copied out on a second stream while the next
+steps run (lb_moments_async / lb_moments_wait) equal the synchronous moments of
+the same state, bit for bit, and leave the state exactly as plain steps do."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2006_12910_amd import lb
+
+pytestmark = pytest.mark.gpu
+
+
+def _domain(storage="f32"):
+    nx, ny = 300, 140
+    y = np.arange(ny)[:, None] + np.zeros((1, nx))
+    ux = 0.02 * np.sin(2 * np.pi * y / ny)
+    d = lb.Domain(nx, ny, tau=0.7, g=(2e-6, -1e-6), storage=storage,
+                  rounding="stochastic" if storage in ("f16", "bf16") else "nearest",
+                  init=(1.0, ux, 0.0 * ux), seed=5, domain_id=2)
+    d.add_particles([dict(x=150.5, y=70.5, radius=8.0, density_ratio=1.5, ux=0.01)])
+    return d
+
+
+def _host(d):
+    return [torch.empty((d.ny, d.nx), dtype=torch.float64, pin_memory=True) for _ in range(3)]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_async_moments_equal_sync_and_overlap_steps(storage):
+    a, b = _domain(storage), _domain(storage)
+    copy = torch.cuda.Stream()
+    stage = torch.empty(3 * a.ny * a.nx, dtype=torch.float64, device="cuda")
+    h1, h2 = _host(a), _host(a)
+    a.step(20)
+    a.moments_async(stage, *h1, copy)
+    a.step(15)  # overlaps the copy
+    # same staging memory again before waiting: the device waits for the
+    # first copy before the moments overwrite it
+    a.moments_async(stage, *h2, copy)
+    a.step(5)
+    a.moments_wait()
+    b.step(20)
+    r20 = b.moments()
+    b.step(15)
+    r35 = b.moments()
+    for h, ref in ((h1, r20), (h2, r35)):
+        for x, y in zip(h, ref):
+            assert np.array_equal(x.numpy(), y)
+    b.step(5)
+    assert np.array_equal(a.populations(), b.populations())
+    assert np.array_equal(a.particles(), b.particles())
+    a.moments_wait()  # nothing pending: returns at once
+    a.close()
+    b.close()
+
+
+def test_async_moments_reject_bad_arguments():
+    d = _domain()
+    stage = torch.empty(3 * d.ny * d.nx, dtype=torch.float64, device="cuda")
+    h = _host(d)
+    same = torch.cuda.current_stream()
+    with pytest.raises(lb.LBError) as e:
+        d.moments_async(stage, *h, same)
+    assert e.value.status == lb.LB_EINVAL
+    with pytest.raises(ValueError):
+        d.moments_async(stage[:10], *h, torch.cuda.Stream())
+    with pytest.raises(ValueError):
+        d.moments_async(stage, torch.empty((d.ny, d.nx), dtype=torch.float64), h[1], h[2],
+                        torch.cuda.Stream())
+    d.close()
