@@ -314,6 +314,9 @@ def other_configs(with_oracle):
     d.set_option(lb.OPT_FORCE_AVERAGE, 1)
     d.add_particles(parts)
     gpu_rate("porous_2048x1024_16discs_f32", d, 2048 * 1024, 1000)
+    # the same with the particle coupling overlapping the bulk sweep
+    d.set_option(lb.OPT_OVERLAP, 1)
+    gpu_rate("porous_2048x1024_16discs_f32_overlapped", d, 2048 * 1024, 1000)
     d.close()
     if with_oracle:
         o = Oracle(OracleParams(nx=2048, ny=1024, bc_x=PRESSURE, bc_y=WALL, tau=0.7, rho_in=1.001,

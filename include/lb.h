@@ -217,6 +217,12 @@ lb_status lb_set_populations(lb_domain *d, const double *host_dev_f);
  * memory traffic per step.  0: single steps only.  A batch takes it when all
  * its domains do.  Not changeable while in a batch. */
 #define LB_OPT_TWO_STEP 6
+/* 0 (default) or 1: lb_step of a domain with particles runs the particle
+ * coupling (k_post of the previous step, k_pre, then the sweep of the tiles
+ * within its reach) on a second stream beside the sweep of all other tiles --
+ * the paper's pipelining of particle interaction with streaming (Sec. 7).
+ * Bit-identical to the serial order.  Batches keep the serial order. */
+#define LB_OPT_OVERLAP 7
 lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value);
 lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value);
 

@@ -10,6 +10,10 @@ namespace lbk {
 void launch_relabel(const DevDomain *doms, const PItem *items, int nitems, hipStream_t s) {
   hipLaunchKernelGGL(k_relabel, dim3(nitems), dim3(256), 0, s, doms, items);
 }
+void launch_near_tiles(const DevDomain *dom, int ntiles, int kstep, hipStream_t s) {
+  hipLaunchKernelGGL(k_near_tiles, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, dom,
+                     kstep);
+}
 void launch_masks_full(const DevDomain *dom, int nx, int ny, hipStream_t s) {
   const long long n = (long long)nx * ny;
   hipLaunchKernelGGL(k_masks_full, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dom);

@@ -15,10 +15,10 @@ namespace {
 constexpr int ST = LBK_ST;
 
 template <int FEAT, int PLM, int WIDE>
-void sweep_l(const DevDomain *doms, const int *prefix, int ndom, int kstep, int blocks,
+void sweep_l(const DevDomain *doms, const int *prefix, int ndom, int kstep, int blocks, int part,
              hipStream_t s) {
   hipLaunchKernelGGL((k_sweep<ST, FEAT, PLM, WIDE>), dim3(blocks), dim3(256), 0, s, doms, prefix,
-                     ndom, kstep);
+                     ndom, kstep, part);
 }
 template <int FEAT>
 void sweep2_l(const DevDomain *doms, const int *prefix2, int ndom, int kstep, int which, int blocks,

@@ -6,7 +6,9 @@
 namespace lbk {
 
 struct KernelSet {
-  void (*sweep)(const DevDomain *doms, const int *prefix, int ndom, int kstep, int blocks,
+  // part: 0 every tile; 1 / 2 the tiles outside / inside the particle
+  // coupling's reach (near_tiles of the step)
+  void (*sweep)(const DevDomain *doms, const int *prefix, int ndom, int kstep, int blocks, int part,
                 hipStream_t s);
   // two steps per launch (periodic plain/obstacle domains); null where the
   // feature set has no two-step kernel
@@ -34,6 +36,7 @@ bool kernels_f16(int feat, int plm, int wide, KernelSet *k);
 bool kernels_bf16(int feat, int plm, int wide, KernelSet *k);
 
 void launch_relabel(const DevDomain *doms, const PItem *items, int nitems, hipStream_t s);
+void launch_near_tiles(const DevDomain *dom, int ntiles, int kstep, hipStream_t s);
 void launch_masks_full(const DevDomain *dom, int nx, int ny, hipStream_t s);
 void launch_mass_final(const DevDomain *dom, const double *partials, int n, double *out,
                        hipStream_t s);

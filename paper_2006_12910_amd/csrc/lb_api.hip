@@ -41,7 +41,7 @@ constexpr size_t STAGE_TARGET = size_t(16) << 20;  // bytes of the host-transfer
 struct Layout {
   int pitch = 0, band_rows = 0;
   size_t desc = 0, hdr = 0, f0 = 0, f1 = 0, label = 0, nodew = 0, ps0 = 0, ps1 = 0, pforce = 0,
-         items = 0,
+         items = 0, near = 0, near_bytes = 0,
          partials = 0, stage = 0, prefix = 0, total = 0;
 };
 
@@ -74,6 +74,10 @@ Layout layout_of(const lb_domain_desc *d) {
   L.ps1 = o; o += align256(np * sizeof(PState));
   L.pforce = o; o += align256(np * sizeof(PForce));
   L.items = o; o += align256(np * sizeof(PItem));
+  // tile flags of the overlapped particle step: two sets, sized for the
+  // smallest tiles (64 x 4 nodes)
+  L.near_bytes = np ? (size_t)((d->nx + 63) / 64) * (size_t)((d->ny + 3) / 4) : 0;
+  L.near = o; o += 2 * align256(L.near_bytes);
   L.partials = o; o += align256(NPARTIALS * sizeof(double));
   L.stage = o; o += align256((size_t)L.band_rows * row_stage);
   L.prefix = o; o += align256(4 * sizeof(int));
@@ -185,6 +189,9 @@ struct lb_domain {
   bool use_graph = true;
   int chunk = 256;
   bool two_step = true;  // LB_OPT_TWO_STEP
+  bool overlap = false;  // LB_OPT_OVERLAP
+  hipStream_t side = nullptr;  // particle chain of an overlapped step
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   GraphCache graphs;
   int in_batches = 0;
   std::vector<uint8_t> host_labels;  // walls + obstacles, [ny][pitch]
@@ -262,7 +269,41 @@ struct StepPlan {
   const PItem *items;
   int nitems;
   bool two;  // two-step sweep (no particles, so no pre/post passes)
+  // overlapped particle steps (one domain): the particle chain on `side`
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int ntiles = 0;
 };
+
+// Steps of one domain with particles, the particle coupling overlapping the
+// bulk of the sweep (the analogue of the paper's pipelining of the particle
+// interaction of one step with the streaming of the next, Sec. 7).  Step k
+// forks: stream s sweeps the tiles no coupling of the step touches, while
+// `side` runs k_post of step k - 1, k_pre of step k, the tile flags of step
+// k + 1 (from P(T + 1), which k_pre has just computed) and then the sweep of
+// the flagged tiles; the branches join before the next step.  The two
+// branches touch disjoint memory: the flagged tiles cover, with the sweep's
+// halo and a margin, every node whose label or link slot the coupling reads
+// or writes; the flags of a step and of the next one live in the two halves
+// of near_tiles.  Every node is still computed by the same kernel code from
+// the same inputs, so the result is bit-identical to the serial order.  The
+// last step's k_post runs after the join, so a call ends in the same state.
+void record_overlapped(const StepPlan &p, int n, hipStream_t s) {
+  launch_near_tiles(p.doms, p.ntiles, 0, s);
+  for (int k = 0; k < n; ++k) {
+    (void)hipEventRecord(p.ev_fork, s);
+    (void)hipStreamWaitEvent(p.side, p.ev_fork, 0);
+    if (k > 0) p.ks->post(p.doms, p.items, p.nitems, k - 1, p.side);
+    p.ks->pre(p.doms, p.items, p.nitems, k, p.side);
+    launch_near_tiles(p.doms, p.ntiles, k + 1, p.side);
+    p.ks->sweep(p.doms, p.prefix, p.ndom, k, p.blocks, 2, p.side);
+    p.ks->sweep(p.doms, p.prefix, p.ndom, k, p.blocks, 1, s);
+    (void)hipEventRecord(p.ev_join, p.side);
+    (void)hipStreamWaitEvent(s, p.ev_join, 0);
+  }
+  p.ks->post(p.doms, p.items, p.nitems, n - 1, s);
+  launch_advance(p.doms, p.ndom, n, s);
+}
 
 // Enqueue `n` steps of the launch sequence on stream s (eager or under
 // capture).  With the two-step sweep, each four steps are a pair of two-step
@@ -277,9 +318,13 @@ void record_steps(const StepPlan &p, int n, hipStream_t s) {
       p.ks->sweep2(p.doms, p.prefix2, p.ndom, k + 2, 1, p.blocks2, s);
     }
   }
+  if (p.side != nullptr && p.nitems > 0 && n > 0) {
+    record_overlapped(p, n, s);
+    return;
+  }
   for (; k < n; ++k) {
     if (p.nitems > 0) p.ks->pre(p.doms, p.items, p.nitems, k, s);
-    p.ks->sweep(p.doms, p.prefix, p.ndom, k, p.blocks, s);
+    p.ks->sweep(p.doms, p.prefix, p.ndom, k, p.blocks, 0, s);
     if (p.nitems > 0) p.ks->post(p.doms, p.items, p.nitems, k, s);
   }
   launch_advance(p.doms, p.ndom, n, s);
@@ -419,6 +464,8 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   h.pstate[0] = (PState *)(d->ws + L.ps0);
   h.pstate[1] = (PState *)(d->ws + L.ps1);
   h.pforce = (PForce *)(d->ws + L.pforce);
+  h.near_tiles[0] = L.near_bytes ? (uint8_t *)(d->ws + L.near) : nullptr;
+  h.near_tiles[1] = L.near_bytes ? (uint8_t *)(d->ws + L.near + align256(L.near_bytes)) : nullptr;
   h.nx = desc->nx;
   h.ny = desc->ny;
   h.pitch = L.pitch;
@@ -608,8 +655,19 @@ lb_status lb_step(lb_domain *d, int64_t nsteps) {
   int64_t left = nsteps;
   while (left > 0) {
     const int c = (int)std::min<int64_t>(left, d->chunk);
-    const StepPlan p{&d->ks, d->ddesc(), d->dprefix(), d->dprefix2(), 1, d->ntiles(),
-                     d->ntiles2(), d->ditems(), d->np, two_step_ok(d)};
+    StepPlan p{&d->ks, d->ddesc(), d->dprefix(), d->dprefix2(), 1, d->ntiles(),
+               d->ntiles2(), d->ditems(), d->np, two_step_ok(d)};
+    if (d->overlap && d->np > 0 && !p.two) {
+      if (!d->side) {
+        HIPCHK(hipStreamCreateWithFlags(&d->side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&d->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&d->ev_join, hipEventDisableTiming));
+      }
+      p.side = d->side;
+      p.ev_fork = d->ev_fork;
+      p.ev_join = d->ev_join;
+      p.ntiles = d->ntiles();
+    }
     lb_status s = run_chunk(d->graphs, d->use_graph, d->stream, d->cap, p, c);
     if (s != LB_OK) return s;
     left -= c;
@@ -773,6 +831,10 @@ lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
       if (value != 0 && value != 1) return fail(LB_EINVAL, "two-step sweep is 0 or 1");
       d->two_step = value != 0;
       break;
+    case LB_OPT_OVERLAP:
+      if (value != 0 && value != 1) return fail(LB_EINVAL, "overlap is 0 or 1");
+      d->overlap = value != 0;
+      break;
     default: return fail(LB_EINVAL, "unknown option");
   }
   d->graphs.clear();
@@ -790,6 +852,7 @@ lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value) {
     case LB_OPT_GRAPH_CHUNK: *value = d->chunk; return LB_OK;
     case LB_OPT_FORCE_AVERAGE: *value = (d->hd.feat & F_FAVG) ? 1 : 0; return LB_OK;
     case LB_OPT_TWO_STEP: *value = d->two_step ? 1 : 0; return LB_OK;
+    case LB_OPT_OVERLAP: *value = d->overlap ? 1 : 0; return LB_OK;
   }
   return fail(LB_EINVAL, "unknown option");
 }
@@ -848,6 +911,12 @@ lb_status lb_destroy_domain(lb_domain *d) {
     (void)hipEventSynchronize(d->rep_copied);
     (void)hipEventDestroy(d->rep_ready);
     (void)hipEventDestroy(d->rep_copied);
+  }
+  if (d->side) {
+    (void)hipStreamSynchronize(d->side);
+    (void)hipEventDestroy(d->ev_fork);
+    (void)hipEventDestroy(d->ev_join);
+    (void)hipStreamDestroy(d->side);
   }
   d->graphs.clear();
   (void)hipStreamDestroy(d->cap);

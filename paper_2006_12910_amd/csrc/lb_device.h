@@ -98,6 +98,10 @@ struct alignas(256) DevDomain {
   uint32_t *health;    // latched error bits
   PState *pstate[2];
   PForce *pforce;
+  // per sweep tile: 1 where the particle coupling of the step from state T
+  // touches the tile or its halo, in near_tiles[T & 1] (null without
+  // particles; written by k_near_tiles)
+  uint8_t *near_tiles[2];
   int nx, ny, pitch;   // pitch in elements, a multiple of 64
   int bc_x, bc_y;
   int np;              // particles

@@ -415,6 +415,43 @@ __global__ __launch_bounds__(256) void k_relabel(const DevDomain *__restrict__ d
     if (l1 != l0) D.label[here] = l1;
   }
 }
+
+// [a0, a1] meets [b0, b1] (inclusive node ranges; b may reach past the
+// domain, whose periodic images count on a periodic axis)
+__device__ __forceinline__ bool ranges_meet(int a0, int a1, int b0, int b1, int n, bool periodic) {
+  if (b0 <= a1 && a0 <= b1) return true;
+  if (!periodic) return false;
+  return (b0 - n <= a1 && a0 <= b1 - n) || (b0 + n <= a1 && a0 <= b1 + n);
+}
+
+// Sweep tiles that the particle coupling around the state T = tstep + kstep
+// touches: k_post of the step before (labels in a box of reach ceil(R) + 3
+// around P(T)) and k_pre (link slots within one node of a box of reach
+// max(ceil(R) + 2, ceil(R + r_it) + 1) around P(T)).  A tile is flagged when
+// its nodes or the nodes its pulls read (one-node halo) come within two nodes
+// of the larger box, into near_tiles[T & 1].  One thread per tile.
+__global__ __launch_bounds__(256) void k_near_tiles(const DevDomain *__restrict__ Dp, int kstep) {
+  const DevDomain &D = *Dp;
+  const int t = (int)(blockIdx.x * 256 + threadIdx.x);
+  if (t >= D.tiles_x * D.tiles_y) return;
+  const uint64_t T = *D.tstep + (uint64_t)kstep;
+  const PState *P = D.pstate[T & 1];
+  const int th = (256 / D.tile_w) * D.rows_per_thread;
+  const int ty = t / D.tiles_x, tx = t - ty * D.tiles_x;
+  const int x0 = tx * D.tile_w - 1, x1 = min((tx + 1) * D.tile_w, D.nx);
+  const int y0 = ty * th - 1, y1 = min((ty + 1) * th, D.ny);
+  const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
+  uint8_t hit = 0;
+  for (int p = 0; p < D.np && !hit; ++p) {
+    const PState &Q = P[p];
+    const int reach =
+        max((int)ceil(Q.radius) + 3, (int)ceil(Q.radius + D.lj_rit) + 1) + 2;
+    const int cx0 = (int)floor(Q.x), cy0 = (int)floor(Q.y);
+    hit = ranges_meet(x0, x1, cx0 - reach, cx0 + reach + 1, D.nx, perx) &&
+          ranges_meet(y0, y1, cy0 - reach, cy0 + reach + 1, D.ny, pery);
+  }
+  D.near_tiles[T & 1][t] = hit;
+}
 #endif  // LBK_COMMON_KERNELS
 
 }  // namespace lbk

@@ -385,7 +385,8 @@ template <int FEAT, int WIDE> constexpr int sweep_min_waves() {
 
 template <int ST, int FEAT, int PLM, int WIDE>
 __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
-    const DevDomain *__restrict__ doms, const int *__restrict__ prefix, int ndom, int kstep) {
+    const DevDomain *__restrict__ doms, const int *__restrict__ prefix, int ndom, int kstep,
+    int part) {
   using S = Store<ST>;
   using T = typename S::T;
   using R = CompT<ST, WIDE>;
@@ -409,6 +410,13 @@ __global__ __launch_bounds__(256, (sweep_min_waves<FEAT, WIDE>())) void k_sweep(
   const int ybase = __builtin_amdgcn_readfirstlane(tyi * rows_pass * npt + (int)threadIdx.x / tw);
 
   const uint64_t T0 = *gbl(D.tstep) + (uint64_t)kstep;  // state time of the source buffer
+  // part 1: only the tiles that no particle coupling of this step touches;
+  // part 2: only those it touches (the two launches of an overlapped step);
+  // 0: every tile.  Uniform over the workgroup, and k_sweep has no barrier.
+  if (part != 0) {
+    const bool near = gbl(D.near_tiles[T0 & 1])[local] != 0;
+    if (near != (part == 2)) return;
+  }
   const uint32_t step = (uint32_t)(T0 + 1);
   void *const f0 = D.f[0];
   void *const f1 = D.f[1];

@@ -23,6 +23,7 @@ INIT_REST, INIT_FIELDS = 0, 1
 PARTICLE_FIXED = 1
 OPT_USE_GRAPH, OPT_TILE_WIDTH, OPT_ROWS_PER_THREAD, OPT_GRAPH_CHUNK, OPT_FORCE_AVERAGE = 1, 2, 3, 4, 5
 OPT_TWO_STEP = 6
+OPT_OVERLAP = 7
 ABI_VERSION = 1
 
 _BC = {"periodic": PERIODIC, "wall": WALL, "pressure": PRESSURE}

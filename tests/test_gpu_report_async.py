@@ -16,7 +16,7 @@ def _domain(storage="f32"):
     ux = 0.02 * np.sin(2 * np.pi * y / ny)
     d = lb.Domain(nx, ny, tau=0.7, g=(2e-6, -1e-6), storage=storage,
                   rounding="stochastic" if storage in ("f16", "bf16") else "nearest",
-                  init=(1.0, ux, 0.0 * ux), seed=5, domain_id=2)
+                  init=(1.0, ux, 0.0 * ux), seed=5, domain_id=2, max_particles=1)
     d.add_particles([dict(x=150.5, y=70.5, radius=8.0, density_ratio=1.5, ux=0.01)])
     return d
 
