@@ -221,7 +221,9 @@ lb_status lb_set_populations(lb_domain *d, const double *host_dev_f);
  * coupling (k_post of the previous step, k_pre, then the sweep of the tiles
  * within its reach) on a second stream beside the sweep of all other tiles --
  * the paper's pipelining of particle interaction with streaming (Sec. 7).
- * Bit-identical to the serial order.  Batches keep the serial order. */
+ * Bit-identical to the serial order.  Batches keep the serial order.  It
+ * pays only where the runtime runs the two branches of a step graph
+ * concurrently; where it serialises them the extra launches make it slower. */
 #define LB_OPT_OVERLAP 7
 lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value);
 lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value);
