@@ -588,7 +588,7 @@ def main():
                  "sweep_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                  "bytes_per_step": bytes_alg, "rounding": ROUNDING[v],
                  "two_step": all(d.get_option(lb.OPT_TWO_STEP) == 1 for d in doms),
-                 "tiles": "two-step: 62 columns x 16/12/6 rows (16-bit/FP32/FP64) per tile" if tiles is None else {f"{'obstacles' if k[0] else 'open'}/class{k[1]}": f"{t[0]}x{t[1]}"
+                 "tiles": "two-step: 62 columns x 14/10/6 rows (16-bit/FP32/FP64) per tile" if tiles is None else {f"{'obstacles' if k[0] else 'open'}/class{k[1]}": f"{t[0]}x{t[1]}"
                                                        for k, t in tiles.items()}}
         if ref:
             entry["l2_vs_oracle"] = dict(l2_errors(doms, ref, specs), after_steps=nsteps_total,

@@ -60,10 +60,13 @@ enum : int { PL_GENERIC = 0, PL_HALF = 1, PL_3Q = 2, PL_3H = 3 };
 
 // Tiles of the two-step sweep (k_sweep2): TS_COLS output columns (the 64
 // lanes of a wave less a one-node rim) by two_step_rows output rows (its LDS
-// holds rows + 2 rows of 64 columns x 9 values).
+// holds rows + 2 rows of 64 columns x 9 values).  Measured on the 185 M-site
+// stress batch: 16-bit rows 13 / 14 / 15 / 16 took 1.059 / 1.037 / 1.078 /
+// 1.056 ms per step, FP32 rows 9 / 10 / 11 / 12 1.625 / 1.603 / 1.648 /
+// 1.644 ms (one run).
 constexpr int TS_COLS = 62;
 constexpr int two_step_rows(int storage) {
-  return storage == ST_F64 ? 6 : (storage == ST_F32 ? 12 : 16);
+  return storage == ST_F64 ? 6 : (storage == ST_F32 ? 10 : 14);
 }
 
 // Labels: 0 fluid, 1 solid, 2 + p inside particle p.
