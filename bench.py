@@ -497,10 +497,9 @@ def paper_replicas(with_oracle):
     return out
 
 
-def traffic_entry(steps_per_launch):
-    """Measured HBM bytes per launch of the dominant sweep kernel (profiles/),
-    or None if the sweep sources changed since or the profile covers another
-    kernel."""
+def profile_entry(steps_per_launch):
+    """The dominant sweep kernel's profile (profiles/), or None if the sweep
+    sources changed since or the profile covers another kernel."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
@@ -509,7 +508,13 @@ def traffic_entry(steps_per_launch):
         return None
     if t.get("steps_per_launch", 1) != steps_per_launch:
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t
+
+
+def traffic_entry(steps_per_launch):
+    """Measured HBM bytes per launch of the dominant sweep kernel, or None."""
+    t = profile_entry(steps_per_launch)
+    return None if t is None else t.get("hbm_bytes_per_launch")
 
 
 def main():
@@ -617,6 +622,12 @@ def main():
                 "steps_per_launch": spl,
                 "algorithmic_bytes_per_launch": spl * head["bytes_per_step"],
                 "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
+    # the 16-bit two-step sweep is bound by vector issue as much as by memory:
+    # the profile's VALU lane-instructions per site update and issue fraction
+    prof = profile_entry(spl)
+    if prof is not None and prof.get("valu"):
+        roofline["valu_per_site_update"] = round(prof["valu"]["valu_per_site_update"], 1)
+        roofline["valu_issue_frac"] = round(prof["valu"]["valu_issue_util"], 3)
     configs = replicas = offload = None
     if not args.no_configs:
         t0 = time.time()
