@@ -1,10 +1,13 @@
 """Pins of the oracle's particle module (Sec. 3, Eqs. MP1-MP8).
 
 Link momentum exchange and moving-wall bounce-back are pinned by exact
-momentum identities, lattice symmetry and two closed-form flows (rotating disc
-torque, periodic-array drag).  The covered/uncovered-node force (Eq. MP3) and
-the LJ repulsion (Eq. MP2) are parity unpinned: only their antisymmetry and
-cut-off are checked here.
+momentum identities, lattice symmetry, Galilean invariance and two closed-form
+flows (rotating disc torque, periodic-array drag).  The force of covered and
+uncovered nodes (Eq. MP3) is pinned by Galilean invariance (it vanishes for
+fluid that moves with the disc) and by the momentum balance of the exterior
+fluid and the particle, which fixes its sign, the fluid velocity it uses and
+the time level of the particle velocity.  The LJ repulsion (Eq. MP2) is parity
+unpinned: only its antisymmetry, direction and cut-off are checked here.
 """
 import numpy as np
 import pytest
@@ -12,6 +15,9 @@ import pytest
 import closed_forms as cf
 from oracle import Oracle, OracleParams
 from oracle.oracle import WALL
+
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
 
 
 def test_labels_match_disc_definition_across_periodic_corner():
@@ -43,6 +49,116 @@ def test_link_force_equals_fluid_momentum_loss():
         assert np.abs(F[:2]).max() > 1e-3 and np.abs(F[3:5]).max() > 1e-3
         assert np.array_equal(o.particles()[0][7:10], F[0:3])  # no LJ, no covering
         j0 = j1
+
+
+def test_galilean_invariance_of_a_co_moving_disc():
+    """A neutral disc moving with a uniform flow on a periodic lattice (Sec. 3,
+    Eqs. MP1, MP3, MP7, MP8): the moving-wall bounce-back returns every
+    population the uniform equilibrium would have streamed, so the fluid,
+    inside and outside the disc, stays uniform; the link forces cancel on the
+    closed surface, and covered and uncovered nodes carry fluid at the disc's
+    own velocity, so force and torque stay at round-off while the disc crosses
+    lattice nodes."""
+    nx, ny, U = 40, 36, (0.04, 0.015)
+    o = Oracle(OracleParams(nx=nx, ny=ny, tau=0.8, lj_psi=0.0), None, np.ones((ny, nx)),
+               np.full((ny, nx), U[0]), np.full((ny, nx), U[1]))
+    o.add_particle(17.3, 18.6, 6.2, 1.0, U[0], U[1], 0.0)
+    relabelled = 0
+    for _ in range(120):
+        lab = o.labels()
+        o.run(1)
+        relabelled += int((o.labels() != lab).sum())
+        p = o.particles()[0]
+        assert np.abs(p[7:10]).max() < 1e-13
+    assert relabelled > 50  # the disc crossed nodes: ~5 columns, 2 rows
+    r, u, v = o.moments()
+    assert np.abs(r - 1).max() < 1e-13
+    assert np.abs(u - U[0]).max() < 1e-13 and np.abs(v - U[1]).max() < 1e-13
+    p = o.particles()[0]
+    np.testing.assert_allclose(p[4:6], U, rtol=0, atol=1e-14)
+    assert abs(p[6]) < 1e-14
+    np.testing.assert_allclose(p[0:2], (17.3 + 120 * U[0], 18.6 + 120 * U[1]), rtol=0, atol=1e-11)
+
+
+def _exterior_record(o):
+    f = o.populations()
+    lab = o.labels()
+    rho = f.sum(0)
+    jx = np.tensordot(EX, f, 1)
+    jy = np.tensordot(EY, f, 1)
+    ext = lab == 0
+    p = o.particles()[0]
+    return dict(P=np.array([jx[ext].sum(), jy[ext].sum()]), M=rho[ext].sum(), rho=rho, lab=lab,
+                U=p[4:6].copy(), F=p[7:9].copy(), Flink=o.link_forces()[0][0:2].copy())
+
+
+def test_covered_uncovered_force_balances_exterior_momentum():
+    """Momentum of the exterior fluid plus the particle (Sec. 3, Eqs. MP1,
+    MP3, MP5).  No population crosses the disc surface, so the exterior fluid
+    exchanges momentum with the particle only through the link force and
+    through the nodes the disc covers or uncovers.  With the covered/uncovered
+    force of Eq. MP3 (+ for covered nodes, - for uncovered ones, rho (u - U_p)
+    with the node's post-step moments, u = j/rho + g/2, and U_p the particle
+    velocity after the update) the sum Q = P_ext + m U_p + (force pending for
+    the next update) changes per step by exactly the external body force on
+    the exterior fluid and the particle, plus (g/2 - U_p) dM, the momentum the
+    covered mass dM leaves behind as it joins the disc interior.  A sign
+    error, j/rho instead of j/rho + g/2, or U_p before the update leaves a
+    residual of 1e-6 to 1e-2 here; the identity holds to round-off."""
+    g = np.array([3e-6, -1e-6])
+    R, ratio = 6.3, 1.3
+    o = Oracle(OracleParams(nx=64, ny=48, tau=0.7, gx=g[0], gy=g[1], lj_psi=0.0))
+    o.add_particle(20.3, 23.7, R, ratio, 0.05, 0.02, 0.003)
+    m = ratio * np.pi * R * R
+    rec = []
+    for _ in range(60):
+        o.run(1)
+        rec.append(_exterior_record(o))
+    covered = 0
+    for k in range(len(rec) - 2):
+        a, b = rec[k], rec[k + 1]
+        # the covered/uncovered force computed at the end of a step is applied
+        # by the next update: it is that update's force less its link force
+        pend_a = rec[k + 1]["F"] - rec[k + 1]["Flink"]
+        pend_b = rec[k + 2]["F"] - rec[k + 2]["Flink"]
+        dQ = (b["P"] + m * b["U"] + pend_b) - (a["P"] + m * a["U"] + pend_a)
+        cov = (a["lab"] == 0) & (b["lab"] >= 2)
+        unc = (a["lab"] >= 2) & (b["lab"] == 0)
+        dM = b["rho"][cov].sum() - b["rho"][unc].sum()
+        covered += int(cov.sum() + unc.sum())
+        expect = g * a["M"] + m * (1.0 - 1.0 / ratio) * g + (0.5 * g - b["U"]) * dM
+        assert np.abs(dQ - expect).max() < 1e-12, (k, dQ - expect)
+    assert covered > 20
+
+
+def test_covering_force_opposes_the_motion():
+    """A heavy disc moving into fluid at rest, its interior fluid moving with
+    it (Sec. 3, Eq. MP3): the nodes it covers hold fluid slower than the disc,
+    so the covered-node term +rho (u - U_p) points against the motion, while
+    the nodes it uncovers hold interior fluid moving with the disc and add
+    little.  Summed over the run the force is anti-parallel to the motion, and
+    so is most single step's term on steps that only cover nodes."""
+    U = np.array([0.03, 0.01])
+    nx, ny, cx, cy, R = 72, 40, 18.4, 20.3, 5.6
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    inside = (xx - cx) ** 2 + (yy - cy) ** 2 < R * R
+    o = Oracle(OracleParams(nx=nx, ny=ny, tau=0.8, lj_psi=0.0), None, np.ones((ny, nx)),
+               np.where(inside, U[0], 0.0), np.where(inside, U[1], 0.0))
+    o.add_particle(cx, cy, R, 20.0, U[0], U[1], 0.0)
+    total, only_cover, against, prev = np.zeros(2), 0, 0, None
+    for _ in range(150):
+        lab = o.labels()
+        o.run(1)
+        nlab = o.labels()
+        # the force of the nodes relabelled by the step before is applied now
+        fcu = o.particles()[0][7:9] - o.link_forces()[0][0:2]
+        total += fcu
+        if prev is not None and prev[0] > 0 and prev[1] == 0:
+            only_cover += 1
+            against += int(np.dot(fcu, U) < 0)
+        prev = (int(((lab == 0) & (nlab >= 2)).sum()), int(((lab >= 2) & (nlab == 0)).sum()))
+    assert np.dot(total, U) / (np.linalg.norm(total) * np.linalg.norm(U)) < -0.99
+    assert only_cover >= 20 and against >= 0.8 * only_cover
 
 
 def test_free_particle_momentum_balance():
