@@ -69,7 +69,13 @@ typedef int32_t lb_status;
 #define LB_BF16_DELTA 3
 
 #define LB_ROUND_NEAREST 0
-#define LB_ROUND_STOCHASTIC 1  /* 16-bit storage only */
+/* stochastic rounding: FP32 storage (with FP32 arithmetic) and the 16-bit
+ * formats.  Each stored value rounds to one of its two neighbours with
+ * probability proportional to closeness, the random bits hashed from (node,
+ * step, seed, domain_id): unbiased, so slow flows whose per-step change is
+ * below half the spacing of the stored values do not stagnate, and
+ * reproducible run to run. */
+#define LB_ROUND_STOCHASTIC 1
 
 /* arithmetic of the collision: the storage's own precision (FP64 for LB_F64,
  * FP32 otherwise), or FP64 with any storage.  FP32 arithmetic keeps mass and
@@ -150,14 +156,20 @@ lb_status lb_set_obstacles(lb_domain *d, const uint8_t *host_mask, size_t n);
 lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_t *first_id);
 
 /* Enqueue nsteps full time steps (collision, noise, streaming, boundaries,
- * particle coupling) on the domain's stream; nsteps >= 0.  A call with
- * nsteps > 0 ends with the FP64 density sum of the final state.  A non-finite
- * density (pulled by a step, or in that final sum) latches a flag that the
- * next synchronising call reports as LB_EUNSTABLE. */
+ * particle coupling; Sec. 2-5) on the domain's stream; nsteps >= 0.  Every
+ * step checks the densities it pulls; a call during which the step counter
+ * passes a multiple of LB_OPT_MASS_INTERVAL (default 256) ends with the FP64
+ * density sum of the final state (see lb_mass, lb_set_mass_check).  A
+ * non-finite density, or a sum beyond the drift threshold, latches a flag
+ * that the next synchronising call reports as LB_EUNSTABLE.  Steps replay
+ * captured hipGraphs of fixed sizes (LB_OPT_GRAPH_CHUNK and the powers of
+ * four below it), all captured by the first call with nsteps > 0. */
 lb_status lb_step(lb_domain *d, int64_t nsteps);
 
-/* Density and reported velocity u = j/rho + g/2 at every node (zero on solid
- * nodes), host FP64 [ny][nx] each.  Synchronises. */
+/* Moments of Sec. 2: density rho = sum_i f_i and velocity u = j/rho + g/2
+ * (j = sum_i f_i e_i; the half-step force shift makes u the fluid velocity of
+ * the velocity-shift forcing, exact for the steady channel) at every node
+ * (zero on solid nodes), host FP64 [ny][nx] each.  Synchronises. */
 lb_status lb_moments(lb_domain *d, double *rho, double *ux, double *uy);
 
 /* Same, into device FP64 arrays [ny][nx] (no synchronisation). */
@@ -183,20 +195,68 @@ lb_status lb_moments_async(lb_domain *d, double *dev_stage, double *rho, double 
  * domain's stream. */
 lb_status lb_moments_wait(lb_domain *d);
 
-/* Copy out the first n particles' state (n <= count).  Synchronises. */
+/* Copy out the first n particles' state (n <= count): centre, velocities
+ * after the last Newton-Euler update (Sec. 3, Eqs. MP5-MP6) and the total
+ * force and torque that update used (Eqs. MP1-MP4).  Synchronises. */
 lb_status lb_get_particles(lb_domain *d, lb_particle *out, int32_t n);
 
-/* FP64 sum of rho over non-solid nodes.  Synchronises. */
+/* Global mass check (the FP64 density sum with its non-finite latch): FP64
+ * sum of rho = sum_i f_i (Sec. 2) over the non-solid nodes of the current
+ * state, computed on the device in a fixed order (bit-reproducible).  The same
+ * sum ends the lb_step / lb_batch_step calls that LB_OPT_MASS_INTERVAL
+ * selects.
+ * Synchronises; LB_EUNSTABLE if the device latched an error (see above). */
 lb_status lb_mass(lb_domain *d, double *total);
+
+/* Mass-drift threshold for the density sums of lb_mass and of lb_step /
+ * lb_batch_step (LB_OPT_MASS_INTERVAL): with rel_tol > 0, a sum M that leaves
+ * |M - M_ref| <= rel_tol |M_ref| latches LB_EUNSTABLE, where M_ref is the
+ * density sum at the time of this call (computed here, as lb_mass does).
+ * Collision and streaming conserve mass exactly on periodic, wall, obstacle
+ * and particle domains (Sec. 2-3), so the threshold measures accumulated
+ * rounding and catches a blow-up before it turns non-finite; density faces
+ * (LB_PRESSURE) exchange mass with the outside and are better left at 0 (the
+ * default: no drift check).  Synchronises.  LB_EINVAL for a negative or
+ * non-finite rel_tol. */
+lb_status lb_set_mass_check(lb_domain *d, double rel_tol);
 
 /* Completed step count. */
 lb_status lb_time(lb_domain *d, int64_t *t);
 
 /* Post-collision state as deviations f*_i - w_i rho0, host FP64 [9][ny][nx]
- * (get synchronises; set rounds to the storage format).  Together with
- * lb_time this checkpoints a particle-free domain bit-exactly. */
+ * (get synchronises; set rounds to the storage format, exactly for values
+ * that get returned).  With lb_time / lb_set_time and, for particles,
+ * lb_get_particle_state / lb_set_particle_state this checkpoints a domain
+ * bit-exactly (the paper's dumps for restarts, Sec. 7): a domain created
+ * with the same description and obstacles, given the time, the populations
+ * and the particle state in that order, continues exactly as the original,
+ * noise included (the generator is keyed by node and step). */
 lb_status lb_get_populations(lb_domain *d, double *host_dev_f);
 lb_status lb_set_populations(lb_domain *d, const double *host_dev_f);
+
+/* Set the completed step count (>= 0), keeping the current state: the state
+ * of step t lives in population buffer t mod 2, so a change of parity moves
+ * it.  Not allowed in a batch (LB_ESTATE).  Synchronises. */
+lb_status lb_set_time(lb_domain *d, int64_t t);
+
+/* Particle state of a checkpoint (Sec. 3): the lb_particle record (centre,
+ * velocities, and fx, fy, torque, the totals of the last update, which the
+ * two-step force mean of LB_OPT_FORCE_AVERAGE reuses) and the force and
+ * torque of the nodes covered or uncovered by the last step (Eq. MP3),
+ * pending for the next update. */
+typedef struct lb_particle_state {
+  lb_particle p;
+  double cover_fx, cover_fy, cover_torque;
+} lb_particle_state;
+
+/* Copy out the state of all n particles (n == count).  Synchronises. */
+lb_status lb_get_particle_state(lb_domain *d, lb_particle_state *out, int32_t n);
+/* Replace every particle by the n given states (n <= max_particles; n = 0
+ * removes them all), relabelling the nodes they cover.  Same checks as
+ * lb_add_particles (LB_EINVAL), except that overlaps between the given
+ * particles are accepted as they are (a checkpoint restores whatever state
+ * it holds); LB_ESTATE in a batch.  Synchronises. */
+lb_status lb_set_particle_state(lb_domain *d, const lb_particle_state *in, int32_t n);
 
 /* Options (see LB_OPT_*).  Changing one drops the cached step graphs. */
 #define LB_OPT_USE_GRAPH 1     /* 1 (default): lb_step replays a captured hipGraph */
@@ -225,6 +285,10 @@ lb_status lb_set_populations(lb_domain *d, const double *host_dev_f);
  * pays only where the runtime runs the two branches of a step graph
  * concurrently; where it serialises them the extra launches make it slower. */
 #define LB_OPT_OVERLAP 7
+/* Steps between the FP64 density sums that lb_step / lb_batch_step run
+ * (>= 1, default 256; 1: after every call).  On a batch it counts the batch's
+ * own steps. */
+#define LB_OPT_MASS_INTERVAL 8
 lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value);
 lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value);
 
@@ -244,9 +308,12 @@ lb_status lb_destroy_domain(lb_domain *d);
 lb_status lb_batch_workspace_bytes(lb_domain *const *domains, int32_t n, size_t *bytes);
 lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_workspace,
                           size_t bytes, void *hip_stream, lb_batch **out);
-/* As lb_step for every domain of the batch, on the batch's stream (the
- * final density sums included). */
+/* As lb_step for every domain of the batch, on the batch's stream (Sec. 2-5
+ * for each member).  The density sums that LB_OPT_MASS_INTERVAL selects
+ * (counted in the batch's own steps) cover every member in two launches. */
 lb_status lb_batch_step(lb_batch *b, int64_t nsteps);
+/* Batch options: LB_OPT_USE_GRAPH, LB_OPT_GRAPH_CHUNK, LB_OPT_MASS_INTERVAL
+ * (LB_EINVAL for the others). */
 lb_status lb_batch_set_option(lb_batch *b, int32_t key, int64_t value);
 lb_status lb_batch_destroy(lb_batch *b);
 

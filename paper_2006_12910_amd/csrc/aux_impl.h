@@ -13,49 +13,57 @@ __device__ __forceinline__ bool node_is_solid(const DevDomain &D, int x, int y) 
          (D.bc_x == BC_WALL && (x == 0 || x == D.nx - 1));
 }
 
-// Partial FP64 sums of rho over non-solid nodes, one per block (grid-stride
-// over rows, fixed order inside the block).
+// Partial FP64 sums of rho over the non-solid nodes of every domain of a
+// launch: domain d owns blocks prefix[d] .. prefix[d+1]-1 (its mass_blocks);
+// local block k sums rows k, k + mass_blocks, ..., each row with the 256
+// threads striding along x, in a fixed order into the domain's partials[k].
 template <int ST>
-__global__ __launch_bounds__(256) void k_mass_partial(const DevDomain *__restrict__ Dp,
-                                                      double *partials) {
+__global__ __launch_bounds__(256) void k_mass_partial(const DevDomain *__restrict__ doms,
+                                                      const int *__restrict__ prefix, int ndom) {
   using S = Store<ST>;
   using T = typename S::T;
   __shared__ double red[4];
-  const DevDomain &D = *Dp;
+  const int b = (int)blockIdx.x;
+  const int dix = ndom == 1 ? 0 : find_domain(prefix, ndom, b);
+  const DevDomain &D = doms[dix];
+  const int local = b - prefix[dix];
   const uint64_t T0 = *D.tstep;
   const T *src = (const T *)D.f[T0 & 1];
   const size_t plane = (size_t)D.ny * D.pitch;
   double acc = 0.0;
-  const long long total = (long long)D.ny * D.nx;
-  for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < total;
-       n += (long long)gridDim.x * 256) {
-    const int y = (int)(n / D.nx), x = (int)(n - (long long)y * D.nx);
-    if (node_is_solid(D, x, y)) continue;
-    const uint32_t here = (uint32_t)y * D.pitch + x;
-    double r = 0.0;
+  for (int y = local; y < D.ny; y += D.mass_blocks) {
+    for (int x = (int)threadIdx.x; x < D.nx; x += 256) {
+      if (node_is_solid(D, x, y)) continue;
+      const size_t here = (size_t)y * D.pitch + x;
+      double r = 0.0;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) r += (double)S::load(src + i * plane, here, i);
-    acc += D.rho0 + r;
+      for (int i = 0; i < 9; ++i) r += (double)S::load(src + i * plane, here, i);
+      acc += D.rho0 + r;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) D.partials[local] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 #ifdef LBK_COMMON_KERNELS
-// Sum of the n partials by one wave, in a fixed order (lane l sums partials
-// l, l + 64, ...; then a butterfly over the lanes).
-__global__ __launch_bounds__(64) void k_mass_final(const DevDomain *__restrict__ Dp,
-                                                   const double *partials, int n, double *out) {
+// Total of each domain's partials, one wave per domain in a fixed order (lane
+// l sums partials l, l + 64, ...; then a butterfly over the lanes).  Latches a
+// non-finite total, and a total that drifts from the reference by more than
+// the relative tolerance when one is set.
+__global__ __launch_bounds__(64) void k_mass_final(const DevDomain *__restrict__ doms) {
+  const DevDomain &D = doms[blockIdx.x];
   double s = 0.0;
-  for (int i = (int)threadIdx.x; i < n; i += 64) s += partials[i];
+  for (int i = (int)threadIdx.x; i < D.mass_blocks; i += 64) s += D.partials[i];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if (threadIdx.x == 0) {
-    *out = s;
-    if (!(fabs(s) < 1e300)) atomicOr(Dp->health, HEALTH_NONFINITE);
+    *D.mass_out = s;
+    if (!(fabs(s) < 1e300)) atomicOr(D.health, HEALTH_NONFINITE);
+    const double ref = D.mass_ctl[0], tol = D.mass_ctl[1];
+    if (tol > 0.0 && !(fabs(s - ref) <= tol * fabs(ref))) atomicOr(D.health, HEALTH_MASS_DRIFT);
   }
 }
 #endif  // LBK_COMMON_KERNELS

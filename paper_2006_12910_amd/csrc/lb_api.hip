@@ -45,13 +45,22 @@ struct Layout {
          partials = 0, stage = 0, prefix = 0, total = 0;
 };
 
-// header block: step counter, health word, mass result
+// header block: step counter, health word, density sum, drift control
 struct Header {
   uint64_t tstep;
   uint32_t health;
   uint32_t pad;
   double mass;
+  double mass_ctl[2];  // reference density sum, relative tolerance (0: off)
 };
+
+// FP64 density sum: one block per ~4 rows of 256 nodes (rows are summed
+// whole), at most one per row and at most NPARTIALS blocks
+int mass_blocks_of(int nx, int ny) {
+  const long long nodes = (long long)nx * ny;
+  return (int)std::min<long long>({(long long)NPARTIALS, (long long)ny,
+                                   std::max<long long>(1, nodes / 1024)});
+}
 
 bool needs_labels(const lb_domain_desc *d) { return d->obstacles != 0 || d->max_particles > 0; }
 
@@ -80,7 +89,7 @@ Layout layout_of(const lb_domain_desc *d) {
   L.near = o; o += 2 * align256(L.near_bytes);
   L.partials = o; o += align256(NPARTIALS * sizeof(double));
   L.stage = o; o += align256((size_t)L.band_rows * row_stage);
-  L.prefix = o; o += align256(4 * sizeof(int));
+  L.prefix = o; o += align256(8 * sizeof(int));
   L.total = o;
   return L;
 }
@@ -101,8 +110,10 @@ lb_status validate(const lb_domain_desc *d) {
   if (d->storage < LB_F64 || d->storage > LB_BF16_DELTA) return fail(LB_EINVAL, "bad storage");
   if (d->rounding != LB_ROUND_NEAREST && d->rounding != LB_ROUND_STOCHASTIC)
     return fail(LB_EINVAL, "bad rounding");
-  if (d->rounding == LB_ROUND_STOCHASTIC && d->storage < LB_F16_DELTA)
-    return fail(LB_EINVAL, "stochastic rounding needs 16-bit storage");
+  if (d->rounding == LB_ROUND_STOCHASTIC && d->storage == LB_F64)
+    return fail(LB_EINVAL, "stochastic rounding needs FP32 or 16-bit storage");
+  if (d->rounding == LB_ROUND_STOCHASTIC && d->storage == LB_F32 && d->compute == LB_COMPUTE_F64)
+    return fail(LB_EINVAL, "stochastic rounding of FP32 storage needs FP32 arithmetic");
   if (d->compute != LB_COMPUTE_NATIVE && d->compute != LB_COMPUTE_F64)
     return fail(LB_EINVAL, "bad compute");
   if (d->max_particles < 0 || d->max_particles > MAX_PARTICLES)
@@ -190,6 +201,7 @@ struct lb_domain {
   int chunk = 256;
   bool two_step = true;  // LB_OPT_TWO_STEP
   bool overlap = false;  // LB_OPT_OVERLAP
+  int64_t mass_interval = 256;  // LB_OPT_MASS_INTERVAL
   hipStream_t side = nullptr;  // particle chain of an overlapped step
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   GraphCache graphs;
@@ -204,6 +216,7 @@ struct lb_domain {
   Header *dhdr() const { return (Header *)(ws + L.hdr); }
   int *dprefix() const { return (int *)(ws + L.prefix); }
   int *dprefix2() const { return dprefix() + 2; }  // tiles of the two-step sweep
+  int *dprefixm() const { return dprefix() + 4; }  // blocks of the density sum
   PItem *ditems() const { return (PItem *)(ws + L.items); }
   int ntiles() const { return hd.tiles_x * hd.tiles_y; }
   int ntiles2() const { return hd.tiles2_x * hd.tiles2_y; }
@@ -214,15 +227,18 @@ struct lb_batch {
   char *ws = nullptr;
   hipStream_t stream = nullptr, cap = nullptr;
   KernelSet ks{};
-  int total_tiles = 0, total_tiles2 = 0, nitems = 0;
+  int total_tiles = 0, total_tiles2 = 0, total_mass_blocks = 0, nitems = 0;
   bool two_step = false;  // every domain takes the two-step sweep
   size_t off_desc = 0, off_prefix = 0, off_items = 0, bytes = 0;
   bool use_graph = true;
   int chunk = 256;
+  int64_t t = 0;                // steps since creation
+  int64_t mass_interval = 256;  // LB_OPT_MASS_INTERVAL
   GraphCache graphs;
   DevDomain *ddesc() const { return (DevDomain *)(ws + off_desc); }
   int *dprefix() const { return (int *)(ws + off_prefix); }
   int *dprefix2() const { return dprefix() + doms.size() + 1; }
+  int *dprefixm() const { return dprefix() + 2 * (doms.size() + 1); }  // density-sum blocks
   PItem *ditems() const { return (PItem *)(ws + off_items); }
 };
 
@@ -239,7 +255,7 @@ void set_tiles(DevDomain &hd, int tile_w, int rpt) {
 
 lb_status push_desc(lb_domain *d) {
   HIPCHK(hipMemcpyAsync(d->ddesc(), &d->hd, sizeof(DevDomain), hipMemcpyHostToDevice, d->stream));
-  int pre[4] = {0, d->ntiles(), 0, d->ntiles2()};
+  int pre[6] = {0, d->ntiles(), 0, d->ntiles2(), 0, d->hd.mass_blocks};
   HIPCHK(hipMemcpyAsync(d->dprefix(), pre, sizeof(pre), hipMemcpyHostToDevice, d->stream));
   HIPCHK(hipStreamSynchronize(d->stream));
   return LB_OK;
@@ -254,6 +270,7 @@ lb_status check_health(lb_domain *d) {
     if (h & HEALTH_NONFINITE) m += " non-finite density;";
     if (h & HEALTH_FAST_PARTICLE) m += " particle faster than 0.5 nodes/step;";
     if (h & HEALTH_LINK_OVERFLOW) m += " particle link list overflow;";
+    if (h & HEALTH_MASS_DRIFT) m += " density sum drifted beyond the set tolerance;";
     return fail(LB_EUNSTABLE, m);
   }
   return LB_OK;
@@ -330,31 +347,62 @@ void record_steps(const StepPlan &p, int n, hipStream_t s) {
   launch_advance(p.doms, p.ndom, n, s);
 }
 
-lb_status run_chunk(GraphCache &gc, bool use_graph, hipStream_t stream, hipStream_t cap,
-                    const StepPlan &p, int n) {
+// Step counts of the captured graphs: the chunk length and every power of
+// four below it.  A call of n steps replays them largest first, so a handle
+// holds at most a handful of graphs, and all of them are captured by the
+// first call: no later call captures or instantiates anything, whatever its
+// step count.  Every size but 1 is a multiple of four, so the two-step sweep
+// runs in launch pairs and only the n mod 4 last steps are single steps.
+std::vector<int> graph_sizes(int chunk) {
+  std::vector<int> v{chunk};
+  int p = 1;
+  while (p * 4 < chunk) p *= 4;
+  for (; p >= 1; p /= 4)
+    if (p < chunk) v.push_back(p);
+  return v;
+}
+
+lb_status capture(GraphCache &gc, hipStream_t cap, const StepPlan &p, int n) {
+  if (gc.execs.count(n)) return LB_OK;
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  record_steps(p, n, cap);
+  hipError_t le = hipGetLastError();
+  HIPCHK(hipStreamEndCapture(cap, &g));
+  if (le != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(LB_EHIP, std::string("kernel launch during capture: ") + hipGetErrorString(le));
+  }
+  hipGraphExec_t ex = nullptr;
+  hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) return fail(LB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+  gc.execs.emplace(n, ex);
+  return LB_OK;
+}
+
+// Enqueue n steps on `stream`: eager launches, or replays of the captured
+// step graphs.
+lb_status run_steps(GraphCache &gc, bool use_graph, int chunk, hipStream_t stream, hipStream_t cap,
+                    const StepPlan &p, int64_t n) {
   if (!use_graph) {
-    record_steps(p, n, stream);
-    HIPCHK(hipGetLastError());
+    while (n > 0) {
+      const int c = (int)std::min<int64_t>(n, chunk);
+      record_steps(p, c, stream);
+      HIPCHK(hipGetLastError());
+      n -= c;
+    }
     return LB_OK;
   }
-  auto it = gc.execs.find(n);
-  if (it == gc.execs.end()) {
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    record_steps(p, n, cap);
-    hipError_t le = hipGetLastError();
-    HIPCHK(hipStreamEndCapture(cap, &g));
-    if (le != hipSuccess) {
-      (void)hipGraphDestroy(g);
-      return fail(LB_EHIP, std::string("kernel launch during capture: ") + hipGetErrorString(le));
-    }
-    hipGraphExec_t ex = nullptr;
-    hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ie != hipSuccess) return fail(LB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-    it = gc.execs.emplace(n, ex).first;
+  const std::vector<int> sizes = graph_sizes(chunk);
+  for (int c : sizes) {
+    lb_status s = capture(gc, cap, p, c);
+    if (s != LB_OK) return s;
   }
-  HIPCHK(hipGraphLaunch(it->second, stream));
+  for (int c : sizes) {
+    const hipGraphExec_t ex = gc.execs.at(c);
+    for (; n >= c; n -= c) HIPCHK(hipGraphLaunch(ex, stream));
+  }
   return LB_OK;
 }
 
@@ -369,16 +417,18 @@ bool two_step_ok(const lb_domain *d) {
 // FP64 density sum of the current state; its final kernel also latches a
 // non-finite state (the sweep checks the densities it pulls, so a blow-up in
 // the last step of a call is caught here).
-lb_status domain_mass_enqueue(lb_domain *d, hipStream_t s) {
-  // about 4 nodes per thread, at most NPARTIALS blocks
-  const long long nodes = (long long)d->desc.nx * d->desc.ny;
-  const int blocks = (int)std::min<long long>(NPARTIALS, std::max<long long>(1, nodes / 1024));
-  d->ks.mass_partial(d->ddesc(), (double *)(d->ws + d->L.partials), blocks, s);
-  launch_mass_final(d->ddesc(), (double *)(d->ws + d->L.partials), blocks, &d->dhdr()->mass, s);
+// Does a call that advances the step counter from t0 by n steps pass a
+// multiple of the density-check interval?
+bool check_due(int64_t t0, int64_t n, int64_t interval) {
+  return n > 0 && (t0 + n) / interval != t0 / interval;
+}
+
+lb_status domain_mass_enqueue(lb_domain *d) {
+  d->ks.mass_partial(d->ddesc(), d->dprefixm(), 1, d->hd.mass_blocks, d->stream);
+  launch_mass_final(d->ddesc(), 1, d->stream);
   HIPCHK(hipGetLastError());
   return LB_OK;
 }
-lb_status domain_mass_enqueue(lb_domain *d) { return domain_mass_enqueue(d, d->stream); }
 
 // Mirror slots of the index walls of a label-free domain in the current
 // population buffer (label domains bounce back on the pulling node's own slot).
@@ -461,6 +511,10 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   h.nodew = needs_labels(desc) ? (uint16_t *)(d->ws + L.nodew) : nullptr;
   h.tstep = &d->dhdr()->tstep;
   h.health = &d->dhdr()->health;
+  h.partials = (double *)(d->ws + L.partials);
+  h.mass_out = &d->dhdr()->mass;
+  h.mass_ctl = d->dhdr()->mass_ctl;
+  h.mass_blocks = mass_blocks_of(desc->nx, desc->ny);
   h.pstate[0] = (PState *)(d->ws + L.ps0);
   h.pstate[1] = (PState *)(d->ws + L.ps1);
   h.pforce = (PForce *)(d->ws + L.pforce);
@@ -485,8 +539,8 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   h.omega = 1.0 / h.tau;
   h.gx = desc->gx;
   h.gy = desc->gy;
-  h.rho_in = desc->rho_in;
-  h.rho_out = desc->rho_out;
+  h.drho_in = desc->rho_in - desc->rho0;
+  h.drho_out = desc->rho_out - desc->rho0;
   h.kT = desc->kT;
   h.pl_n = desc->n_index;
   h.pl_K = desc->K;
@@ -500,8 +554,8 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   h.omega_f = (float)h.omega;
   h.gx_f = (float)h.gx;
   h.gy_f = (float)h.gy;
-  h.rho_in_f = (float)h.rho_in;
-  h.rho_out_f = (float)h.rho_out;
+  h.drho_in_f = (float)h.drho_in;
+  h.drho_out_f = (float)h.drho_out;
   h.kT_f = (float)h.kT;
   h.pl_n_f = (float)h.pl_n;
   h.pl_K_f = (float)h.pl_K;
@@ -567,6 +621,89 @@ lb_status lb_set_obstacles(lb_domain *d, const uint8_t *mask, size_t n) {
   return upload_labels(d);
 }
 
+namespace {
+
+double mimg(double v, double len, bool per) { return per ? v - len * std::floor(v / len + 0.5) : v; }
+
+// Validated device state of one particle description (Sec. 3: m = rho_p pi R^2,
+// I = m R^2 / 2).
+lb_status particle_state_of(const lb_domain *d, const lb_particle &q, PState *out) {
+  const int nx = d->desc.nx, ny = d->desc.ny;
+  const bool perx = d->desc.bc_x == LB_PERIODIC, pery = d->desc.bc_y == LB_PERIODIC;
+  if (!(q.radius > 0.0) || !(q.density_ratio > 0.0) || !std::isfinite(q.x) || !std::isfinite(q.y) ||
+      q.x < 0.0 || q.y < 0.0 || q.x >= nx || q.y >= ny)
+    return fail(LB_EINVAL, "particle outside the domain or bad radius/density");
+  if (!std::isfinite(q.ux) || !std::isfinite(q.uy) || !std::isfinite(q.omega))
+    return fail(LB_EINVAL, "particle velocity not finite");
+  // widest per-particle box of the kernels: link/repulsion scan, relabelling
+  const int reach = std::max((int)std::ceil(q.radius + d->desc.lj_rit) + 1, (int)std::ceil(q.radius) + 3);
+  const int W = 2 * reach + 2;
+  if ((perx && W > nx) || (pery && W > ny)) return fail(LB_EINVAL, "particle box wider than a periodic axis");
+  if (d->desc.bc_x == LB_PRESSURE && (q.x - reach < 1.0 || q.x + reach > nx - 2.0))
+    return fail(LB_EINVAL, "particle box touches a pressure face");
+  if ((2 * reach + 2) * (2 * reach + 2) * 8 > 6144 * 8) return fail(LB_EINVAL, "particle radius too large");
+  PState s{};
+  s.x = q.x; s.y = q.y; s.ux = q.ux; s.uy = q.uy; s.omega = q.omega;
+  s.radius = q.radius;
+  s.rho_ratio = q.density_ratio;
+  const double rhop = q.density_ratio * d->desc.rho0;
+  s.mass = rhop * M_PI * q.radius * q.radius;
+  s.inertia = 0.5 * s.mass * q.radius * q.radius;
+  s.flags = q.flags & LB_PARTICLE_FIXED;
+  *out = s;
+  return LB_OK;
+}
+
+// No node of particle k of `all` may be solid; with check_others, none may lie
+// inside another particle of `all` either.
+lb_status check_cover(const lb_domain *d, const std::vector<PState> &all, int k, bool check_others) {
+  const int nx = d->desc.nx, ny = d->desc.ny, pitch = d->L.pitch;
+  const bool perx = d->desc.bc_x == LB_PERIODIC, pery = d->desc.bc_y == LB_PERIODIC;
+  const PState &s = all[k];
+  const int r = (int)std::ceil(s.radius) + 1;
+  for (int yy = (int)std::floor(s.y) - r; yy <= (int)std::floor(s.y) + r + 1; ++yy)
+    for (int xx = (int)std::floor(s.x) - r; xx <= (int)std::floor(s.x) + r + 1; ++xx) {
+      int x = xx, y = yy;
+      if (x < 0 || x >= nx) { if (!perx) continue; x = (x + nx) % nx; }
+      if (y < 0 || y >= ny) { if (!pery) continue; y = (y + ny) % ny; }
+      const double dx = mimg(x - s.x, nx, perx), dy = mimg(y - s.y, ny, pery);
+      if (!(dx * dx + dy * dy < s.radius * s.radius)) continue;
+      if (d->host_labels[(size_t)y * pitch + x] == LBL_SOLID)
+        return fail(LB_EINVAL, "particle covers a solid node");
+      if (!check_others) continue;
+      for (int q = 0; q < (int)all.size(); ++q) {
+        if (q == k) continue;
+        const double ex = mimg(x - all[q].x, nx, perx), ey = mimg(y - all[q].y, ny, pery);
+        if (ex * ex + ey * ey < all[q].radius * all[q].radius)
+          return fail(LB_EINVAL, "particle overlaps another particle");
+      }
+    }
+  return LB_OK;
+}
+
+// Work items (one per particle), descriptor upload, labels of the current
+// particle state; drops the step graphs (the launch sequence changes).
+lb_status particles_changed(lb_domain *d) {
+  d->hd.np = d->np;
+  if (d->np > 0) {
+    std::vector<PItem> items(d->np);
+    for (int q = 0; q < d->np; ++q) items[q] = PItem{0, q};
+    HIPCHK(hipMemcpyAsync(d->ditems(), items.data(), d->np * sizeof(PItem), hipMemcpyHostToDevice,
+                          d->stream));
+  }
+  lb_status s = push_desc(d);
+  if (s != LB_OK) return s;
+  if (d->np > 0) {
+    launch_relabel(d->ddesc(), d->ditems(), d->np, d->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(d->stream));
+  }
+  d->graphs.clear();
+  return LB_OK;
+}
+
+}  // namespace
+
 lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_t *first_id) {
   if (!d || (!p && n > 0)) return fail(LB_EINVAL, "null argument");
   if (d->in_batches) return fail(LB_ESTATE, "domain is in a batch");
@@ -575,8 +712,6 @@ lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_
     if (first_id) *first_id = d->np;
     return LB_OK;
   }
-  const int nx = d->desc.nx, ny = d->desc.ny, pitch = d->L.pitch;
-  const bool perx = d->desc.bc_x == LB_PERIODIC, pery = d->desc.bc_y == LB_PERIODIC;
   // current particle states (they move on the device)
   std::vector<PState> cur(d->np + n);
   if (d->np > 0) {
@@ -584,50 +719,12 @@ lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_
                           hipMemcpyDeviceToHost, d->stream));
     HIPCHK(hipStreamSynchronize(d->stream));
   }
-  auto mimg = [](double v, double len, bool per) { return per ? v - len * std::floor(v / len + 0.5) : v; };
-  for (int k = 0; k < n; ++k) {
-    const lb_particle &q = p[k];
-    if (!(q.radius > 0.0) || !(q.density_ratio > 0.0) || !std::isfinite(q.x) || !std::isfinite(q.y) ||
-        q.x < 0.0 || q.y < 0.0 || q.x >= nx || q.y >= ny)
-      return fail(LB_EINVAL, "particle outside the domain or bad radius/density");
-    // widest per-particle box of the kernels: link/repulsion scan, relabelling
-    const int reach = std::max((int)std::ceil(q.radius + d->desc.lj_rit) + 1, (int)std::ceil(q.radius) + 3);
-    const int W = 2 * reach + 2;
-    if ((perx && W > nx) || (pery && W > ny)) return fail(LB_EINVAL, "particle box wider than a periodic axis");
-    if (d->desc.bc_x == LB_PRESSURE && (q.x - reach < 1.0 || q.x + reach > nx - 2.0))
-      return fail(LB_EINVAL, "particle box touches a pressure face");
-    if ((2 * reach + 2) * (2 * reach + 2) * 8 > 6144 * 8) return fail(LB_EINVAL, "particle radius too large");
-    PState s{};
-    s.x = q.x; s.y = q.y; s.ux = q.ux; s.uy = q.uy; s.omega = q.omega;
-    s.radius = q.radius;
-    s.rho_ratio = q.density_ratio;
-    const double rhop = q.density_ratio * d->desc.rho0;
-    s.mass = rhop * M_PI * q.radius * q.radius;
-    s.inertia = 0.5 * s.mass * q.radius * q.radius;
-    s.flags = q.flags & LB_PARTICLE_FIXED;
-    cur[d->np + k] = s;
-  }
+  lb_status st;
+  for (int k = 0; k < n; ++k)
+    if ((st = particle_state_of(d, p[k], &cur[d->np + k])) != LB_OK) return st;
   // overlap: no node of a new disc may be solid or inside another particle
-  for (int k = 0; k < n; ++k) {
-    const PState &s = cur[d->np + k];
-    const int r = (int)std::ceil(s.radius) + 1;
-    for (int yy = (int)std::floor(s.y) - r; yy <= (int)std::floor(s.y) + r + 1; ++yy)
-      for (int xx = (int)std::floor(s.x) - r; xx <= (int)std::floor(s.x) + r + 1; ++xx) {
-        int x = xx, y = yy;
-        if (x < 0 || x >= nx) { if (!perx) continue; x = (x + nx) % nx; }
-        if (y < 0 || y >= ny) { if (!pery) continue; y = (y + ny) % ny; }
-        const double dx = mimg(x - s.x, nx, perx), dy = mimg(y - s.y, ny, pery);
-        if (!(dx * dx + dy * dy < s.radius * s.radius)) continue;
-        if (d->host_labels[(size_t)y * pitch + x] == LBL_SOLID)
-          return fail(LB_EINVAL, "particle covers a solid node");
-        for (int q = 0; q < d->np + n; ++q) {
-          if (q == d->np + k) continue;
-          const double ex = mimg(x - cur[q].x, nx, perx), ey = mimg(y - cur[q].y, ny, pery);
-          if (ex * ex + ey * ey < cur[q].radius * cur[q].radius)
-            return fail(LB_EINVAL, "particle overlaps another particle");
-        }
-      }
-  }
+  for (int k = 0; k < n; ++k)
+    if ((st = check_cover(d, cur, d->np + k, true)) != LB_OK) return st;
   const int first = d->np;
   HIPCHK(hipMemcpyAsync(d->hd.pstate[d->t & 1] + first, cur.data() + first, n * sizeof(PState),
                         hipMemcpyHostToDevice, d->stream));
@@ -635,26 +732,96 @@ lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_
   std::memset(zf.data(), 0, n * sizeof(PForce));
   HIPCHK(hipMemcpyAsync(d->hd.pforce + first, zf.data(), n * sizeof(PForce), hipMemcpyHostToDevice, d->stream));
   d->np += n;
-  d->hd.np = d->np;
-  std::vector<PItem> items(d->np);
-  for (int q = 0; q < d->np; ++q) items[q] = PItem{0, q};
-  HIPCHK(hipMemcpyAsync(d->ditems(), items.data(), d->np * sizeof(PItem), hipMemcpyHostToDevice, d->stream));
-  lb_status s = push_desc(d);
-  if (s != LB_OK) return s;
-  launch_relabel(d->ddesc(), d->ditems(), d->np, d->stream);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(d->stream));
-  d->graphs.clear();
+  if ((st = particles_changed(d)) != LB_OK) return st;
   if (first_id) *first_id = first;
   return LB_OK;
+}
+
+lb_status lb_get_particle_state(lb_domain *d, lb_particle_state *out, int32_t n) {
+  if (!d || (!out && n > 0)) return fail(LB_EINVAL, "null argument");
+  if (n != d->np) return fail(LB_EINVAL, "n must equal the particle count");
+  std::vector<PState> cur(std::max(n, 1));
+  std::vector<PForce> frc(std::max(n, 1));
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(cur.data(), d->hd.pstate[d->t & 1], n * sizeof(PState),
+                          hipMemcpyDeviceToHost, d->stream));
+    HIPCHK(hipMemcpyAsync(frc.data(), d->hd.pforce, n * sizeof(PForce), hipMemcpyDeviceToHost,
+                          d->stream));
+  }
+  HIPCHK(hipStreamSynchronize(d->stream));
+  for (int k = 0; k < n; ++k) {
+    const PState &s = cur[k];
+    lb_particle_state &o = out[k];
+    o.p.x = s.x; o.p.y = s.y; o.p.radius = s.radius; o.p.density_ratio = s.rho_ratio;
+    o.p.ux = s.ux; o.p.uy = s.uy; o.p.omega = s.omega;
+    o.p.fx = s.fx; o.p.fy = s.fy; o.p.torque = s.torque;
+    o.p.flags = s.flags; o.p.reserved = 0;
+    o.cover_fx = frc[k].cx_; o.cover_fy = frc[k].cy_; o.cover_torque = frc[k].ctorque;
+  }
+  return check_health(d);
+}
+
+lb_status lb_set_particle_state(lb_domain *d, const lb_particle_state *in, int32_t n) {
+  if (!d || (!in && n > 0)) return fail(LB_EINVAL, "null argument");
+  if (d->in_batches) return fail(LB_ESTATE, "domain is in a batch");
+  if (n < 0 || n > d->desc.max_particles) return fail(LB_EINVAL, "exceeds max_particles");
+  std::vector<PState> cur(n);
+  std::vector<PForce> frc(n);
+  lb_status st;
+  for (int k = 0; k < n; ++k) {
+    if ((st = particle_state_of(d, in[k].p, &cur[k])) != LB_OK) return st;
+    if (!std::isfinite(in[k].p.fx) || !std::isfinite(in[k].p.fy) || !std::isfinite(in[k].p.torque) ||
+        !std::isfinite(in[k].cover_fx) || !std::isfinite(in[k].cover_fy) ||
+        !std::isfinite(in[k].cover_torque))
+      return fail(LB_EINVAL, "particle force not finite");
+    cur[k].fx = in[k].p.fx;
+    cur[k].fy = in[k].p.fy;
+    cur[k].torque = in[k].p.torque;
+    std::memset(&frc[k], 0, sizeof(PForce));
+    frc[k].cx_ = in[k].cover_fx;
+    frc[k].cy_ = in[k].cover_fy;
+    frc[k].ctorque = in[k].cover_torque;
+  }
+  for (int k = 0; k < n; ++k)
+    if ((st = check_cover(d, cur, k, false)) != LB_OK) return st;
+  if (d->hd.label) {
+    // labels of walls and obstacles only; the new particles relabel below
+    if ((st = upload_labels(d)) != LB_OK) return st;
+  }
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(d->hd.pstate[d->t & 1], cur.data(), n * sizeof(PState),
+                          hipMemcpyHostToDevice, d->stream));
+    HIPCHK(hipMemcpyAsync(d->hd.pforce, frc.data(), n * sizeof(PForce), hipMemcpyHostToDevice,
+                          d->stream));
+  }
+  d->np = n;
+  return particles_changed(d);
+}
+
+lb_status lb_set_time(lb_domain *d, int64_t t) {
+  if (!d) return fail(LB_EINVAL, "null domain");
+  if (t < 0) return fail(LB_EINVAL, "t < 0");
+  if (d->in_batches) return fail(LB_ESTATE, "domain is in a batch");
+  if ((t & 1) != (d->t & 1)) {
+    // the state moves to the buffer of the new parity (populations, and the
+    // particle state, double-buffered the same way)
+    const size_t fbytes = (size_t)9 * d->desc.ny * d->L.pitch * storage_bytes(d->desc.storage);
+    HIPCHK(hipMemcpyAsync(d->hd.f[t & 1], d->hd.f[d->t & 1], fbytes, hipMemcpyDeviceToDevice, d->stream));
+    if (d->np > 0)
+      HIPCHK(hipMemcpyAsync(d->hd.pstate[t & 1], d->hd.pstate[d->t & 1], d->np * sizeof(PState),
+                            hipMemcpyDeviceToDevice, d->stream));
+  }
+  const uint64_t tt = (uint64_t)t;
+  HIPCHK(hipMemcpyAsync(&d->dhdr()->tstep, &tt, sizeof(tt), hipMemcpyHostToDevice, d->stream));
+  HIPCHK(hipStreamSynchronize(d->stream));
+  d->t = t;
+  return refresh_mirrors(d);
 }
 
 lb_status lb_step(lb_domain *d, int64_t nsteps) {
   if (!d) return fail(LB_EINVAL, "null domain");
   if (nsteps < 0) return fail(LB_EINVAL, "nsteps < 0");
-  int64_t left = nsteps;
-  while (left > 0) {
-    const int c = (int)std::min<int64_t>(left, d->chunk);
+  if (nsteps > 0) {
     StepPlan p{&d->ks, d->ddesc(), d->dprefix(), d->dprefix2(), 1, d->ntiles(),
                d->ntiles2(), d->ditems(), d->np, two_step_ok(d)};
     if (d->overlap && d->np > 0 && !p.two) {
@@ -668,12 +835,11 @@ lb_status lb_step(lb_domain *d, int64_t nsteps) {
       p.ev_join = d->ev_join;
       p.ntiles = d->ntiles();
     }
-    lb_status s = run_chunk(d->graphs, d->use_graph, d->stream, d->cap, p, c);
+    lb_status s = run_steps(d->graphs, d->use_graph, d->chunk, d->stream, d->cap, p, nsteps);
     if (s != LB_OK) return s;
-    left -= c;
   }
   d->t += nsteps;
-  if (nsteps > 0) return domain_mass_enqueue(d);
+  if (check_due(d->t - nsteps, nsteps, d->mass_interval)) return domain_mass_enqueue(d);
   return LB_OK;
 }
 
@@ -764,6 +930,18 @@ lb_status lb_mass(lb_domain *d, double *total) {
   return check_health(d);
 }
 
+lb_status lb_set_mass_check(lb_domain *d, double rel_tol) {
+  if (!d) return fail(LB_EINVAL, "null domain");
+  if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return fail(LB_EINVAL, "rel_tol must be finite and >= 0");
+  double ref = 0.0;
+  lb_status s = lb_mass(d, &ref);
+  if (s != LB_OK) return s;
+  const double ctl[2] = {ref, rel_tol};
+  HIPCHK(hipMemcpyAsync(d->dhdr()->mass_ctl, ctl, sizeof(ctl), hipMemcpyHostToDevice, d->stream));
+  HIPCHK(hipStreamSynchronize(d->stream));
+  return LB_OK;
+}
+
 lb_status lb_time(lb_domain *d, int64_t *t) {
   if (!d || !t) return fail(LB_EINVAL, "null argument");
   *t = d->t;
@@ -835,6 +1013,10 @@ lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
       if (value != 0 && value != 1) return fail(LB_EINVAL, "overlap is 0 or 1");
       d->overlap = value != 0;
       break;
+    case LB_OPT_MASS_INTERVAL:
+      if (value < 1) return fail(LB_EINVAL, "mass check interval must be >= 1");
+      d->mass_interval = value;
+      return LB_OK;  // no effect on the captured graphs
     default: return fail(LB_EINVAL, "unknown option");
   }
   d->graphs.clear();
@@ -853,6 +1035,7 @@ lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value) {
     case LB_OPT_FORCE_AVERAGE: *value = (d->hd.feat & F_FAVG) ? 1 : 0; return LB_OK;
     case LB_OPT_TWO_STEP: *value = d->two_step ? 1 : 0; return LB_OK;
     case LB_OPT_OVERLAP: *value = d->overlap ? 1 : 0; return LB_OK;
+    case LB_OPT_MASS_INTERVAL: *value = d->mass_interval; return LB_OK;
   }
   return fail(LB_EINVAL, "unknown option");
 }
@@ -931,7 +1114,7 @@ lb_status lb_batch_workspace_bytes(lb_domain *const *domains, int32_t n, size_t 
     if (!domains[i]) return fail(LB_EINVAL, "null domain");
     items += domains[i]->np;
   }
-  *bytes = align256((size_t)n * sizeof(DevDomain)) + align256((size_t)2 * (n + 1) * sizeof(int)) +
+  *bytes = align256((size_t)n * sizeof(DevDomain)) + align256((size_t)3 * (n + 1) * sizeof(int)) +
            align256(std::max<size_t>(items, 1) * sizeof(PItem));
   return LB_OK;
 }
@@ -967,22 +1150,25 @@ lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_worksp
   b->ks = domains[lab_dom >= 0 ? lab_dom : 0]->ks;
   b->off_desc = 0;
   b->off_prefix = align256((size_t)n * sizeof(DevDomain));
-  b->off_items = b->off_prefix + align256((size_t)2 * (n + 1) * sizeof(int));
+  b->off_items = b->off_prefix + align256((size_t)3 * (n + 1) * sizeof(int));
   b->bytes = need;
   std::vector<DevDomain> descs(n);
-  // single-step tile prefix [0, n], then the two-step one [n + 1, 2n + 1]
-  std::vector<int> prefix(2 * (n + 1), 0);
+  // single-step tile prefix [0, n], the two-step one [n + 1, 2n + 1], the
+  // density-sum blocks [2n + 2, 3n + 2]
+  std::vector<int> prefix(3 * (n + 1), 0);
   std::vector<PItem> items;
   bool two = b->ks.sweep2 != nullptr;
   for (int i = 0; i < n; ++i) {
     descs[i] = domains[i]->hd;
     prefix[i + 1] = prefix[i] + domains[i]->ntiles();
     prefix[n + 2 + i] = prefix[n + 1 + i] + domains[i]->ntiles2();
+    prefix[2 * n + 3 + i] = prefix[2 * n + 2 + i] + domains[i]->hd.mass_blocks;
     for (int q = 0; q < domains[i]->np; ++q) items.push_back(PItem{i, q});
     two = two && two_step_ok(domains[i]);
   }
   b->two_step = two;
   b->total_tiles2 = prefix[2 * n + 1];
+  b->total_mass_blocks = prefix[3 * n + 2];
   size_t working_set = 0;
   for (int i = 0; i < n; ++i) working_set += sweep_working_set(descs[i]);
   for (int i = 0; i < n; ++i) descs[i].stream_stores = working_set >= STREAM_STORE_MIN_BYTES;
@@ -1012,21 +1198,20 @@ lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_worksp
 lb_status lb_batch_step(lb_batch *b, int64_t nsteps) {
   if (!b) return fail(LB_EINVAL, "null batch");
   if (nsteps < 0) return fail(LB_EINVAL, "nsteps < 0");
-  int64_t left = nsteps;
-  while (left > 0) {
-    const int c = (int)std::min<int64_t>(left, b->chunk);
+  if (nsteps > 0) {
     const StepPlan p{&b->ks, b->ddesc(), b->dprefix(), b->dprefix2(), (int)b->doms.size(),
                      b->total_tiles, b->total_tiles2, b->ditems(), b->nitems, b->two_step};
-    lb_status s = run_chunk(b->graphs, b->use_graph, b->stream, b->cap, p, c);
+    lb_status s = run_steps(b->graphs, b->use_graph, b->chunk, b->stream, b->cap, p, nsteps);
     if (s != LB_OK) return s;
-    left -= c;
   }
   for (auto *d : b->doms) d->t += nsteps;
-  if (nsteps > 0) {
-    for (auto *d : b->doms) {
-      lb_status s = domain_mass_enqueue(d, b->stream);
-      if (s != LB_OK) return s;
-    }
+  b->t += nsteps;
+  if (check_due(b->t - nsteps, nsteps, b->mass_interval)) {
+    // the FP64 density sums of every domain: two launches for the batch
+    b->ks.mass_partial(b->ddesc(), b->dprefixm(), (int)b->doms.size(), b->total_mass_blocks,
+                       b->stream);
+    launch_mass_final(b->ddesc(), (int)b->doms.size(), b->stream);
+    HIPCHK(hipGetLastError());
   }
   return LB_OK;
 }
@@ -1039,6 +1224,10 @@ lb_status lb_batch_set_option(lb_batch *b, int32_t key, int64_t value) {
       if (value < 1 || value > 4096) return fail(LB_EINVAL, "graph chunk must be in [1, 4096]");
       b->chunk = (int)value;
       break;
+    case LB_OPT_MASS_INTERVAL:
+      if (value < 1) return fail(LB_EINVAL, "mass check interval must be >= 1");
+      b->mass_interval = value;
+      return LB_OK;
     default: return fail(LB_EINVAL, "option not available on a batch");
   }
   b->graphs.clear();

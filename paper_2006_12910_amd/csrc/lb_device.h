@@ -52,7 +52,7 @@ enum : int {
   F_NOISE = 2,     // thermal noise
   F_POWER = 4,     // power-law tau*
   F_PRESSURE = 8,  // Zou-He faces on x
-  F_STOCH = 16,    // stochastic rounding of 16-bit storage
+  F_STOCH = 16,    // stochastic rounding of the stored values (FP32 or 16-bit)
   F_FAVG = 32,     // particle update with the mean of two steps' forces (runtime only)
 };
 // Power-law exponent specialisations.
@@ -99,6 +99,13 @@ struct alignas(256) DevDomain {
                        // is solid, bit i-1 = the source x - e_i is solid
   uint64_t *tstep;     // completed steps
   uint32_t *health;    // latched error bits
+  // FP64 density check: per-block partial sums (mass_blocks of them), the
+  // total, and the drift control {reference, relative tolerance} (tolerance
+  // 0: no drift check)
+  double *partials;
+  double *mass_out;
+  const double *mass_ctl;
+  int mass_blocks;
   PState *pstate[2];
   PForce *pforce;
   // per sweep tile: 1 where the particle coupling of the step from state T
@@ -113,12 +120,15 @@ struct alignas(256) DevDomain {
   uint32_t key0, key1; // noise generator key
   int storage, feat;
   int stream_stores;   // 1: the sweep's stores bypass the caches (see k_sweep)
-  // FP64 parameters
-  double rho0, tau, omega, gx, gy, rho_in, rho_out, kT;
+  // FP64 parameters; the face densities as deviations rho_in - rho0 and
+  // rho_out - rho0, formed in FP64 so that the FP32 copies carry them to
+  // FP32 precision (a difference of two FP32-rounded densities near 1 would
+  // err by ~5e-8, i.e. 5e-5 of a 1e-3 pressure difference)
+  double rho0, tau, omega, gx, gy, drho_in, drho_out, kT;
   double pl_n, pl_K, tau_min, tau_max;
   double lj_psi, lj_rit, lj_floor;
   // FP32 copies
-  float rho0_f, tau_f, omega_f, gx_f, gy_f, rho_in_f, rho_out_f, kT_f;
+  float rho0_f, tau_f, omega_f, gx_f, gy_f, drho_in_f, drho_out_f, kT_f;
   float pl_n_f, pl_K_f, tau_min_f, tau_max_f;
 };
 
@@ -128,7 +138,8 @@ struct PItem {
   int dom, p;
 };
 
-constexpr uint32_t HEALTH_NONFINITE = 1u, HEALTH_FAST_PARTICLE = 2u, HEALTH_LINK_OVERFLOW = 4u;
+constexpr uint32_t HEALTH_NONFINITE = 1u, HEALTH_FAST_PARTICLE = 2u, HEALTH_LINK_OVERFLOW = 4u,
+                   HEALTH_MASS_DRIFT = 8u;
 
 // ---------------------------------------------------------------------------
 // Global-address-space views of device pointers: pointers read from the

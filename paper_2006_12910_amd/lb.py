@@ -24,6 +24,7 @@ PARTICLE_FIXED = 1
 OPT_USE_GRAPH, OPT_TILE_WIDTH, OPT_ROWS_PER_THREAD, OPT_GRAPH_CHUNK, OPT_FORCE_AVERAGE = 1, 2, 3, 4, 5
 OPT_TWO_STEP = 6
 OPT_OVERLAP = 7
+OPT_MASS_INTERVAL = 8
 ABI_VERSION = 1
 
 _BC = {"periodic": PERIODIC, "wall": WALL, "pressure": PRESSURE}
@@ -33,8 +34,9 @@ _RND = {"nearest": ROUND_NEAREST, "stochastic": ROUND_STOCHASTIC}
 EXPORTED = [
     "lb_workspace_bytes", "lb_create_domain", "lb_set_obstacles", "lb_add_particles", "lb_step",
     "lb_moments", "lb_moments_device", "lb_moments_async", "lb_moments_wait", "lb_get_particles",
-    "lb_mass", "lb_time",
-    "lb_get_populations", "lb_set_populations", "lb_set_option", "lb_get_option",
+    "lb_mass", "lb_set_mass_check", "lb_time",
+    "lb_get_populations", "lb_set_populations", "lb_set_time", "lb_get_particle_state",
+    "lb_set_particle_state", "lb_set_option", "lb_get_option",
     "lb_destroy_domain", "lb_batch_workspace_bytes", "lb_batch_create", "lb_batch_step",
     "lb_batch_set_option", "lb_batch_destroy", "lb_noise_normals", "lb_autotune",
     "lb_status_string", "lb_last_error",
@@ -65,6 +67,11 @@ class Particle(C.Structure):
         ("omega", C.c_double), ("fx", C.c_double), ("fy", C.c_double), ("torque", C.c_double),
         ("flags", C.c_int32), ("reserved", C.c_int32),
     ]
+
+
+class ParticleState(C.Structure):
+    _fields_ = [("p", Particle), ("cover_fx", C.c_double), ("cover_fy", C.c_double),
+                ("cover_torque", C.c_double)]
 
 
 class LBError(RuntimeError):
@@ -99,9 +106,13 @@ def library():
         "lb_moments_wait": [vp],
         "lb_get_particles": [vp, P(Particle), st],
         "lb_mass": [vp, dp],
+        "lb_set_mass_check": [vp, C.c_double],
         "lb_time": [vp, P(C.c_int64)],
         "lb_get_populations": [vp, dp],
         "lb_set_populations": [vp, dp],
+        "lb_set_time": [vp, C.c_int64],
+        "lb_get_particle_state": [vp, P(ParticleState), st],
+        "lb_set_particle_state": [vp, P(ParticleState), st],
         "lb_set_option": [vp, st, C.c_int64],
         "lb_get_option": [vp, st, P(C.c_int64)],
         "lb_destroy_domain": [vp],
@@ -292,6 +303,11 @@ class Domain:
         _check(library().lb_mass(self._h, C.byref(m)), "lb_mass")
         return m.value
 
+    def set_mass_check(self, rel_tol):
+        """Latch LB_EUNSTABLE when a call's final density sum drifts from the
+        current one by more than rel_tol (relative); 0 switches it off."""
+        _check(library().lb_set_mass_check(self._h, float(rel_tol)), "lb_set_mass_check")
+
     @property
     def time(self):
         t = C.c_int64()
@@ -307,6 +323,22 @@ class Domain:
     def set_populations(self, f):
         f = np.ascontiguousarray(f, np.float64).reshape(9, self.ny, self.nx)
         _check(library().lb_set_populations(self._h, _dptr(f)), "lb_set_populations")
+
+    def set_time(self, t):
+        _check(library().lb_set_time(self._h, int(t)), "lb_set_time")
+
+    def particle_state(self):
+        """Checkpoint record of every particle (a ctypes array of
+        ParticleState, for set_particle_state)."""
+        n = self.num_particles
+        arr = (ParticleState * max(n, 1))()
+        _check(library().lb_get_particle_state(self._h, arr, n), "lb_get_particle_state")
+        return arr, n
+
+    def set_particle_state(self, state):
+        arr, n = state
+        _check(library().lb_set_particle_state(self._h, arr, int(n)), "lb_set_particle_state")
+        self._np = int(n)
 
     def set_option(self, key, value):
         _check(library().lb_set_option(self._h, int(key), int(value)), "lb_set_option")

@@ -47,12 +47,11 @@ def _porous(storage, compute="native"):
 
 @pytest.mark.parametrize("storage,compute,tol,ptol", [("f64", "native", 1e-10, 1e-11),
                                                       ("f32", "f64", 1e-5, 1e-6),
-                                                      ("f32", "native", 6e-5, 1e-5)])
+                                                      ("f32", "native", 1e-5, 1e-5)])
 def test_porous_full_lattice_against_oracle(storage, compute, tol, ptol):
-    """FP32 storage meets the 1e-5 target with FP64 arithmetic.  With FP32
-    arithmetic the deviations carry the imposed density difference
-    (|delta rho| ~ 1e-3) next to a momentum part of ~1e-5, so each rounding
-    costs ~1e-5 of the velocity; the run stays within 6e-5."""
+    """FP32 storage meets the 1e-5 target with FP32 and with FP64 arithmetic.
+    The density faces hold rho_in - rho0 = 1e-3 as one FP32 number (the
+    difference of the two FP32-rounded densities erred by 5e-5 of it)."""
     gpu, ora = _porous(storage, compute)
     gpu.step(200)
     ora.run(200)
@@ -231,32 +230,42 @@ def _pl_init(n, nx, ny):
 
 
 @pytest.mark.parametrize("n", [0.5, 0.75, 1.5])
-@pytest.mark.parametrize("storage,compute,tol", [("f64", "native", 1e-10), ("f32", "native", 1e-4),
-                                                 ("f32", "f64", 5e-5)])
-def test_powerlaw_full_lattice_columns_match_oracle(n, storage, compute, tol):
-    """Started x-uniform, every column of the full lattice stays identical
-    (bit for bit) and equals the oracle's column of a narrow channel.
+@pytest.mark.parametrize("storage,compute,rounding,tol", [("f64", "native", "nearest", 1e-10),
+                                                          ("f32", "native", "stochastic", 1e-5),
+                                                          ("f32", "native", "nearest", 2e-5),
+                                                          ("f32", "f64", "nearest", 2e-5)])
+def test_powerlaw_full_lattice_columns_match_oracle(n, storage, compute, rounding, tol):
+    """Started x-uniform, every column of the full lattice equals the
+    oracle's column of a narrow channel; with round-to-nearest storage the
+    columns stay identical bit for bit (stochastic rounding draws different
+    bits per node, so there each column is compared).
 
-    FP32 storage: the flow starts from its steady profile and changes by
-    less per step than the spacing of the stored FP32 values (where tau* is
-    clamped at 2.5 the populations relax by 40 % of a tiny non-equilibrium
-    part), so round-to-nearest storage settles up to a few 1e-5 away
-    (measured 0.2-4.6e-5 with FP32 arithmetic, 0.02-1.3e-5 with FP64)."""
+    FP32 storage meets the 1e-5 target with stochastic rounding.  With
+    round-to-nearest storage the flow, started from its steady closed-form
+    profile, changes by less per step than half the spacing of the stored
+    FP32 values where tau* sits at its upper clamp (n = 0.5: the populations
+    relax by 40 % of a tiny non-equilibrium part), so those values stagnate,
+    in FP32 and FP64 arithmetic alike: bound 2e-5 (measured about 1.3e-5 for
+    n = 0.5, below 2e-6 for the other two)."""
     from paper_2006_12910_amd import lb
     nx, ny = 4096, 256
     pl = dict(n=n, K=0.01, tau_min=0.51, tau_max=2.5)
     rho, ux, uy, _ = _pl_init(n, nx, ny)
-    gpu = lb.Domain(nx, ny, storage=storage, compute=compute, bc_y="wall", g=(_PL_G[n], 0.0),
-                    power_law=pl, init=(rho, ux, uy))
+    gpu = lb.Domain(nx, ny, storage=storage, compute=compute, rounding=rounding, bc_y="wall",
+                    g=(_PL_G[n], 0.0), power_law=pl, init=(rho, ux, uy))
     _, ora = make_pair(4, ny, bc_y="wall", g=(_PL_G[n], 0.0), power_law=pl,
                        init=(rho[:, :4], ux[:, :4], uy[:, :4]))
     gpu.step(1500)
     ora.run(1500)
     rg, ug, vg = gpu.moments()
-    assert (ug == ug[:, :1]).all() and (vg == vg[:, :1]).all() and (rg == rg[:, :1]).all()
     ro, uo, vo = ora.moments()
-    err = rel_l2(ug[:, 0], uo[:, 0])
-    print(f"power law n={n} {storage}/{compute}: column vs oracle {err:.2e}")
+    if rounding == "nearest":
+        assert (ug == ug[:, :1]).all() and (vg == vg[:, :1]).all() and (rg == rg[:, :1]).all()
+        err = rel_l2(ug[:, 0], uo[:, 0])
+    else:
+        cols = np.sqrt(((ug - uo[:, :1]) ** 2).sum(0) / (uo[:, 0] ** 2).sum())
+        err = float(cols.max())
+    print(f"power law n={n} {storage}/{compute}/{rounding}: column vs oracle {err:.2e}")
     assert err < tol, err
 
 

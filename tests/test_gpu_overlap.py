@@ -64,3 +64,26 @@ def test_overlap_option_values():
     with pytest.raises(lb.LBError):
         d.set_option(lb.OPT_OVERLAP, 2)
     d.close()
+
+
+def test_overlapped_steps_match_the_oracle():
+    """FP64 storage: the overlapped order against the FP64 oracle (walls,
+    obstacles, three moving particles)."""
+    from helpers import make_pair, velocity_error
+    nx, ny = 320, 160
+    mask, _ = inputs.rsa_discs(nx, ny, 4.0, 9.0, 0.12, 1.0, inputs.rng(8), periodic=False)
+    mask[:, :40] = 0
+    mask[0, :] = mask[-1, :] = 1
+    parts = [dict(x=12.5, y=40.5, radius=6.0, density_ratio=1.2, ux=0.02),
+             dict(x=20.0, y=80.0, radius=7.5, density_ratio=1.5, uy=0.01, omega=0.001),
+             dict(x=14.0, y=118.0, radius=5.0, density_ratio=1.1)]
+    gpu, ora = make_pair(nx, ny, tau=0.7, g=(3e-5, 0.0), obstacles=mask, particles=parts,
+                         lj=(1e-3, 2.5, 0.5), max_particles=4)
+    gpu.set_option(lb.OPT_OVERLAP, 1)
+    for n in (1, 6, 33):
+        gpu.step(n)
+        ora.run(n)
+        drho, err = velocity_error(gpu, ora)
+        pd = np.abs(gpu.particles()[:, :7] - ora.particles()[:, :7]).max()
+        assert drho < 1e-13 and err < 1e-11 and pd < 1e-13, (n, drho, err, pd)
+    gpu.close()

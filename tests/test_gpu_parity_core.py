@@ -129,19 +129,23 @@ def test_power_law(n):
     assert drho < 1e-12 and err < 1e-9, (drho, err)
 
 
-@pytest.mark.parametrize("n,compute,tol", [(0.5, "native", 1e-5), (0.75, "native", 1e-5),
-                                           (1.5, "f64", 1e-5), (1.5, "native", 3e-4)])
-def test_power_law_fp32(n, compute, tol):
-    """FP32 storage.  n = 1.5 relaxes at tau_min = 0.51 everywhere; its plug-flow
-    core accumulates a rounding bias under FP32 arithmetic (documented bound
-    3e-4), removed by FP64 arithmetic on the same FP32 storage."""
+@pytest.mark.parametrize("n,compute,rounding", [(0.5, "native", "nearest"), (0.75, "native", "nearest"),
+                                               (1.5, "f64", "nearest"), (1.5, "native", "nearest"),
+                                               (1.5, "native", "stochastic")])
+def test_power_law_fp32(n, compute, rounding):
+    """FP32 storage, 1e-5 target.  n = 1.5 relaxes at tau_min = 0.51 everywhere
+    with a body force of a few ulps of the stored momentum per step: FP32
+    arithmetic meets the target because the collision's increment carries
+    exactly the method's mass and momentum change (Sec. 2)."""
     nx, ny = 64, 66
-    gpu, ora = make_pair(nx, ny, storage="f32", compute=compute, bc_y="wall",
+    tol = 1e-5
+    gpu, ora = make_pair(nx, ny, storage="f32", compute=compute, rounding=rounding, bc_y="wall",
                          g=(1.66e-5 if n == 0.5 else 3e-6, 0),
                          power_law=dict(n=n, K=0.01, tau_min=0.51, tau_max=2.5))
     gpu.step(3000)
     ora.run(3000)
     _, err = velocity_error(gpu, ora)
+    print(f"power law n={n} f32/{compute}/{rounding}: {err:.2e}", flush=True)
     assert err < tol, err
 
 

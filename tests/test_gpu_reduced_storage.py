@@ -15,7 +15,8 @@ from helpers import make_pair, velocity_error
 pytestmark = pytest.mark.gpu
 
 BOUNDS = {("f16", "stochastic"): 1e-3, ("f16", "nearest"): 5e-2,
-          ("bf16", "stochastic"): 1e-2, ("bf16", "nearest"): 5e-1, ("f32", "nearest"): 1e-5}
+          ("bf16", "stochastic"): 1e-2, ("bf16", "nearest"): 5e-1, ("f32", "nearest"): 1e-5,
+          ("f32", "stochastic"): 1e-5}
 
 
 @pytest.mark.parametrize("tau", [0.55, 1.2])

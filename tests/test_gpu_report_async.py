@@ -68,3 +68,28 @@ def test_async_moments_reject_bad_arguments():
         d.moments_async(stage, torch.empty((d.ny, d.nx), dtype=torch.float64), h[1], h[2],
                         torch.cuda.Stream())
     d.close()
+
+
+def test_async_moments_match_the_oracle():
+    """FP64 storage: the moments reported by the offloaded copy equal the
+    FP64 oracle's at the same step, while later steps run."""
+    from helpers import make_pair
+    nx, ny = 300, 140
+    y = np.arange(ny)[:, None] + np.zeros((1, nx))
+    ux = 0.02 * np.sin(2 * np.pi * y / ny)
+    gpu, ora = make_pair(nx, ny, tau=0.7, g=(2e-6, -1e-6), init=(1.0, ux, 0.0 * ux), seed=5,
+                         domain_id=2, kT=1e-5,
+                         particles=[dict(x=150.5, y=70.5, radius=8.0, density_ratio=1.5, ux=0.01)])
+    copy = torch.cuda.Stream()
+    stage = torch.empty(3 * ny * nx, dtype=torch.float64, device="cuda")
+    h = _host(gpu)
+    gpu.step(25)
+    gpu.moments_async(stage, *h, copy)
+    gpu.step(10)
+    gpu.moments_wait()
+    ora.run(25)
+    ro, uo, vo = ora.moments()
+    assert np.abs(h[0].numpy() - ro).max() < 1e-13
+    num = np.sqrt(((h[1].numpy() - uo) ** 2 + (h[2].numpy() - vo) ** 2).sum())
+    assert num / np.sqrt((uo ** 2 + vo ** 2).sum()) < 1e-11
+    gpu.close()

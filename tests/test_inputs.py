@@ -9,7 +9,7 @@ from paper_2006_12910_amd import inputs
 
 
 def test_replica_b1_layout():
-    """Sec. 5, first benchmark: 1020 x 1620 lattice, 45 particles of radius
+    """Sec. 6, first benchmark: 1020 x 1620 lattice, 45 particles of radius
     6.5 with surface spacings 8.5 and 5.5, released into a grain-free band of
     a disordered porous medium between lateral walls."""
     mask, centres = inputs.replica_b1()
@@ -33,7 +33,7 @@ def test_replica_b1_layout():
 
 
 def test_replica_b2_disc_sits_in_the_channel():
-    """Sec. 5, second benchmark: 3000 x 41 channel, one disc of radius 7.5."""
+    """Sec. 6, second benchmark: 3000 x 41 channel, one disc of radius 7.5."""
     ((cx, cy),) = inputs.replica_b2()
     r = 7.5
     assert r + 2 < cy < 40 - r - 2 and 0 < cx < 3000
