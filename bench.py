@@ -416,6 +416,50 @@ def other_configs(with_oracle):
     return out
 
 
+def fluct_ensemble(storage="f32"):
+    """The batched fluctuating workload: 64 realisations of 128^2..1024^2,
+    each with a Brownian disc of radius 5, kT = 1e-4, tau = 1."""
+    from paper_2006_12910_amd import inputs, lb
+    specs = inputs.fluctuating_batch(count=64)
+    doms = []
+    for sp in specs:
+        dd = lb.Domain(sp["n"], sp["n"], storage=storage, tau=1.0, kT=1e-4, seed=64,
+                       domain_id=sp["domain_id"], max_particles=1)
+        cx, cy, r = sp["disc"]
+        dd.add_particles([dict(x=cx, y=cy, radius=r)])
+        doms.append(dd)
+    return lb.Batch(doms), doms, sum(sp["n"] ** 2 for sp in specs)
+
+
+def porous_discs(storage="f32"):
+    """Porous 2048 x 1024 (35 % discs, density faces) with 16 mobile discs."""
+    from paper_2006_12910_amd import inputs, lb
+    mask, _ = inputs.porous_channel()
+    parts = [dict(x=x, y=y, radius=8.0, density_ratio=1.05) for x, y in inputs.particle_block()]
+    d = lb.Domain(2048, 1024, storage=storage, bc_x="pressure", bc_y="wall", tau=0.7, rho_in=1.001,
+                  rho_out=0.999, obstacles=mask, max_particles=16, lj=(1e-3, 2.5, 0.5))
+    d.set_option(lb.OPT_FORCE_AVERAGE, 1)
+    d.add_particles(parts)
+    return d, [d], 2048 * 1024
+
+
+def only_workload(name, steps, warmup):
+    """One workload alone (for profiling): warm-up, then `steps` timed steps;
+    prints one JSON line."""
+    import torch
+    make = {"fluct-ensemble": fluct_ensemble, "porous": porous_discs}[name]
+    runner, doms, sites = make()
+    runner.step(max(warmup, 1))
+    torch.cuda.synchronize()
+    ms = timed_call(runner, steps)
+    print(json.dumps({"workload": name, "steps": steps, "ms_per_step": round(ms / steps, 5),
+                      "mlups": round(sites * steps / (ms * 1e-3) / 1e6, 1)}), flush=True)
+    if runner is not doms[0]:
+        runner.close()
+    for d in doms:
+        d.close()
+
+
 # The paper's best CPU rates of its three timing benchmarks (MLUPS, its table
 # of optimisation stages: OpenMP with thread affinity, 28-core Xeon E5-2697 v3).
 PAPER_BEST_CPU_MLUPS = {"b1": 47.27, "b2": 138.20, "b3": 85.85}
@@ -591,6 +635,8 @@ def main():
     ap.add_argument("--tiles", default=None, metavar="JSON",
                     help='tile shape per size class instead of tuning, e.g. the "tiles" object of an '
                          'earlier line (to profile the configuration that line measured)')
+    ap.add_argument("--only", default=None, choices=["fluct-ensemble", "porous"],
+                    help="time one other workload alone (GPU only; for profiling) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="before the workload, copy a buffer of this size 5 times (a kernel of "
                          "known traffic for scaling profiler byte counters)")
@@ -614,6 +660,9 @@ def main():
         log(f"calibration copy: 5 x {args.calibrate_copy} MiB")
         del a, b
         torch.cuda.empty_cache()
+    if args.only:
+        only_workload(args.only, args.steps, args.warmup)
+        return
     specs = workload()
     t0 = time.time()
     masks = [None if s["obstacle_seed"] is None else domain_inputs(s)[1] for s in specs]

@@ -362,7 +362,7 @@ std::vector<int> graph_sizes(int chunk) {
   return v;
 }
 
-lb_status capture(GraphCache &gc, hipStream_t cap, const StepPlan &p, int n) {
+lb_status capture(GraphCache &gc, hipStream_t stream, hipStream_t cap, const StepPlan &p, int n) {
   if (gc.execs.count(n)) return LB_OK;
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
@@ -378,6 +378,8 @@ lb_status capture(GraphCache &gc, hipStream_t cap, const StepPlan &p, int n) {
   (void)hipGraphDestroy(g);
   if (ie != hipSuccess) return fail(LB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
   gc.execs.emplace(n, ex);
+  // upload now, so that the first replay carries no set-up cost
+  HIPCHK(hipGraphUpload(ex, stream));
   return LB_OK;
 }
 
@@ -396,7 +398,7 @@ lb_status run_steps(GraphCache &gc, bool use_graph, int chunk, hipStream_t strea
   }
   const std::vector<int> sizes = graph_sizes(chunk);
   for (int c : sizes) {
-    lb_status s = capture(gc, cap, p, c);
+    lb_status s = capture(gc, stream, cap, p, c);
     if (s != LB_OK) return s;
   }
   for (int c : sizes) {
