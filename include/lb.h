@@ -208,6 +208,21 @@ lb_status lb_get_particles(lb_domain *d, lb_particle *out, int32_t n);
  * Synchronises; LB_EUNSTABLE if the device latched an error (see above). */
 lb_status lb_mass(lb_domain *d, double *total);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): lb_mass
+ * without the domain's reduction area.  The FP64 density sum of the current
+ * state (same blocks, same order, so bit-identical to lb_mass) is written to
+ * dev_total, caller-owned device memory of one double, enqueued on the
+ * domain's stream without synchronising; it latches a non-finite or drifting
+ * sum as lb_mass does.  Its partial sums go to a fixed device array of the
+ * library (1024 doubles, 8 KiB, on each GPU used, held until the process
+ * ends; every block overwrites its own entry, so nothing needs clearing).
+ * Calls on one GPU share that array: calls that may overlap on one GPU (on
+ * different streams) race.  LB_EINVAL for a null argument or a domain whose
+ * sum needs more partial sums than the array holds (none does: at most 1024);
+ * allocates nothing (no hipMalloc, hipFree or allocating library call). */
+lb_status lb_mass_static(lb_domain *d, double *dev_total);
+
 /* Mass-drift threshold for the density sums of lb_mass and of lb_step /
  * lb_batch_step (LB_OPT_MASS_INTERVAL): with rel_tol > 0, a sum M that leaves
  * |M - M_ref| <= rel_tol |M_ref| latches LB_EUNSTABLE, where M_ref is the

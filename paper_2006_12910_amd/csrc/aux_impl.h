@@ -16,10 +16,12 @@ __device__ __forceinline__ bool node_is_solid(const DevDomain &D, int x, int y) 
 // Partial FP64 sums of rho over the non-solid nodes of every domain of a
 // launch: domain d owns blocks prefix[d] .. prefix[d+1]-1 (its mass_blocks);
 // local block k sums rows k, k + mass_blocks, ..., each row with the 256
-// threads striding along x, in a fixed order into the domain's partials[k].
+// threads striding along x, in a fixed order into the domain's partials[k]
+// (or into alt[k] when alt is given: one domain, ndom == 1).
 template <int ST>
 __global__ __launch_bounds__(256) void k_mass_partial(const DevDomain *__restrict__ doms,
-                                                      const int *__restrict__ prefix, int ndom) {
+                                                      const int *__restrict__ prefix, int ndom,
+                                                      double *alt) {
   using S = Store<ST>;
   using T = typename S::T;
   __shared__ double red[4];
@@ -45,22 +47,26 @@ __global__ __launch_bounds__(256) void k_mass_partial(const DevDomain *__restric
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) D.partials[local] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) (alt ? alt : D.partials)[local] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 #ifdef LBK_COMMON_KERNELS
 // Total of each domain's partials, one wave per domain in a fixed order (lane
 // l sums partials l, l + 64, ...; then a butterfly over the lanes).  Latches a
 // non-finite total, and a total that drifts from the reference by more than
-// the relative tolerance when one is set.
-__global__ __launch_bounds__(64) void k_mass_final(const DevDomain *__restrict__ doms) {
+// the relative tolerance when one is set.  With alt (one domain) the
+// partials are read from alt and the total is also written to *alt_out.
+__global__ __launch_bounds__(64) void k_mass_final(const DevDomain *__restrict__ doms,
+                                                   const double *alt, double *alt_out) {
   const DevDomain &D = doms[blockIdx.x];
+  const double *part = alt ? alt : D.partials;
   double s = 0.0;
-  for (int i = (int)threadIdx.x; i < D.mass_blocks; i += 64) s += D.partials[i];
+  for (int i = (int)threadIdx.x; i < D.mass_blocks; i += 64) s += part[i];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if (threadIdx.x == 0) {
     *D.mass_out = s;
+    if (alt_out) *alt_out = s;
     if (!(fabs(s) < 1e300)) atomicOr(D.health, HEALTH_NONFINITE);
     const double ref = D.mass_ctl[0], tol = D.mass_ctl[1];
     if (tol > 0.0 && !(fabs(s - ref) <= tol * fabs(ref))) atomicOr(D.health, HEALTH_MASS_DRIFT);

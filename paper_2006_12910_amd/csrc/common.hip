@@ -18,8 +18,9 @@ void launch_masks_full(const DevDomain *dom, int nx, int ny, hipStream_t s) {
   const long long n = (long long)nx * ny;
   hipLaunchKernelGGL(k_masks_full, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dom);
 }
-void launch_mass_final(const DevDomain *doms, int ndom, hipStream_t s) {
-  hipLaunchKernelGGL(k_mass_final, dim3(ndom), dim3(64), 0, s, doms);
+void launch_mass_final(const DevDomain *doms, int ndom, const double *alt, double *alt_out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_mass_final, dim3(ndom), dim3(64), 0, s, doms, alt, alt_out);
 }
 void launch_normals(uint32_t k0, uint32_t k1, uint32_t step, uint32_t node0, uint32_t count,
                     float *out, hipStream_t s) {

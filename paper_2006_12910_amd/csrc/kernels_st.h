@@ -39,8 +39,9 @@ void pre_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hip
 void post_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
   hipLaunchKernelGGL((k_post<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
 }
-void mass_l(const DevDomain *doms, const int *prefix, int ndom, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_mass_partial<ST>), dim3(blocks), dim3(256), 0, s, doms, prefix, ndom);
+void mass_l(const DevDomain *doms, const int *prefix, int ndom, int blocks, double *alt,
+            hipStream_t s) {
+  hipLaunchKernelGGL((k_mass_partial<ST>), dim3(blocks), dim3(256), 0, s, doms, prefix, ndom, alt);
 }
 void moments_l(const DevDomain *dom, double *rho, double *ux, double *uy, int row0, int nrows,
                int nx, hipStream_t s) {

@@ -19,9 +19,10 @@ struct KernelSet {
   // particle coupling before and after the sweep (one workgroup per particle)
   void (*pre)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
   void (*post)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
-  // FP64 density partial sums of ndom domains (mass block prefix per domain)
+  // FP64 density partial sums of ndom domains (mass block prefix per domain),
+  // into each domain's partials, or into alt (one domain)
   void (*mass_partial)(const DevDomain *doms, const int *prefix, int ndom, int blocks,
-                       hipStream_t s);
+                       double *alt, hipStream_t s);
   void (*moments)(const DevDomain *dom, double *rho, double *ux, double *uy, int row0, int nrows,
                   int nx, hipStream_t s);
   void (*export_f)(const DevDomain *dom, double *out, int row0, int nrows, int nx, hipStream_t s);
@@ -40,7 +41,8 @@ bool kernels_bf16(int feat, int plm, int wide, KernelSet *k);
 void launch_relabel(const DevDomain *doms, const PItem *items, int nitems, hipStream_t s);
 void launch_near_tiles(const DevDomain *dom, int ntiles, int kstep, hipStream_t s);
 void launch_masks_full(const DevDomain *dom, int nx, int ny, hipStream_t s);
-void launch_mass_final(const DevDomain *doms, int ndom, hipStream_t s);
+void launch_mass_final(const DevDomain *doms, int ndom, const double *alt, double *alt_out,
+                       hipStream_t s);
 void launch_normals(uint32_t k0, uint32_t k1, uint32_t step, uint32_t node0, uint32_t count,
                     float *out, hipStream_t s);
 void launch_advance(const DevDomain *doms, int ndom, int n, hipStream_t s);

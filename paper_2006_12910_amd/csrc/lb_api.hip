@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -189,6 +190,7 @@ struct GraphCache {
 struct lb_domain {
   lb_domain_desc desc{};
   Layout L;
+  int device = 0;  // the device current at creation (the workspace's)
   char *ws = nullptr;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
@@ -426,8 +428,8 @@ bool check_due(int64_t t0, int64_t n, int64_t interval) {
 }
 
 lb_status domain_mass_enqueue(lb_domain *d) {
-  d->ks.mass_partial(d->ddesc(), d->dprefixm(), 1, d->hd.mass_blocks, d->stream);
-  launch_mass_final(d->ddesc(), 1, d->stream);
+  d->ks.mass_partial(d->ddesc(), d->dprefixm(), 1, d->hd.mass_blocks, nullptr, d->stream);
+  launch_mass_final(d->ddesc(), 1, nullptr, nullptr, d->stream);
   HIPCHK(hipGetLastError());
   return LB_OK;
 }
@@ -493,7 +495,10 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   if (!get_kernels(desc->storage, feat, plm, desc->compute == LB_COMPUTE_F64, &ks))
     return fail(LB_EUNSUPPORTED, "no kernel for this feature set");
 
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(LB_EHIP, "hipGetDevice failed");
   lb_domain *d = new lb_domain();
+  d->device = dev;
   d->desc = *desc;
   d->desc.init_rho = d->desc.init_ux = d->desc.init_uy = nullptr;
   d->L = L;
@@ -932,6 +937,51 @@ lb_status lb_mass(lb_domain *d, double *total) {
   return check_health(d);
 }
 
+// Partial sums of lb_mass_static: one fixed array per GPU, for callers that
+// cannot allocate.  Its host-side name is not a device address: kernels get
+// the address hipGetSymbolAddress returns for each device (kept per device).
+constexpr int STATIC_MASS_PARTIALS = NPARTIALS;
+static __device__ __align__(256) double scratch[STATIC_MASS_PARTIALS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[MAX_DEVICES] = {};
+
+// scratch's address on device dev (resolved once per device, dev current)
+lb_status scratch_on(int dev, double **out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(LB_EUNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    int cur = 0;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != dev) HIPCHK(hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) HIPCHK(hipSetDevice(cur));
+    if (e != hipSuccess || !p)
+      return fail(LB_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = (double *)p;
+  }
+  *out = g_scratch[dev];
+  return LB_OK;
+}
+}  // namespace
+
+lb_status lb_mass_static(lb_domain *d, double *dev_total) {
+  if (!d || !dev_total) return fail(LB_EINVAL, "null argument");
+  if (d->hd.mass_blocks > STATIC_MASS_PARTIALS)
+    return fail(LB_EINVAL, "density sum needs more partial sums than the static array holds (" +
+                               std::to_string(STATIC_MASS_PARTIALS) + ")");
+  double *part = nullptr;
+  lb_status s = scratch_on(d->device, &part);
+  if (s != LB_OK) return s;
+  d->ks.mass_partial(d->ddesc(), d->dprefixm(), 1, d->hd.mass_blocks, part, d->stream);
+  launch_mass_final(d->ddesc(), 1, part, dev_total, d->stream);
+  HIPCHK(hipGetLastError());
+  return LB_OK;
+}
+
 lb_status lb_set_mass_check(lb_domain *d, double rel_tol) {
   if (!d) return fail(LB_EINVAL, "null domain");
   if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return fail(LB_EINVAL, "rel_tol must be finite and >= 0");
@@ -1211,8 +1261,8 @@ lb_status lb_batch_step(lb_batch *b, int64_t nsteps) {
   if (check_due(b->t - nsteps, nsteps, b->mass_interval)) {
     // the FP64 density sums of every domain: two launches for the batch
     b->ks.mass_partial(b->ddesc(), b->dprefixm(), (int)b->doms.size(), b->total_mass_blocks,
-                       b->stream);
-    launch_mass_final(b->ddesc(), (int)b->doms.size(), b->stream);
+                       nullptr, b->stream);
+    launch_mass_final(b->ddesc(), (int)b->doms.size(), nullptr, nullptr, b->stream);
     HIPCHK(hipGetLastError());
   }
   return LB_OK;

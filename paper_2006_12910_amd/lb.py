@@ -34,7 +34,7 @@ _RND = {"nearest": ROUND_NEAREST, "stochastic": ROUND_STOCHASTIC}
 EXPORTED = [
     "lb_workspace_bytes", "lb_create_domain", "lb_set_obstacles", "lb_add_particles", "lb_step",
     "lb_moments", "lb_moments_device", "lb_moments_async", "lb_moments_wait", "lb_get_particles",
-    "lb_mass", "lb_set_mass_check", "lb_time",
+    "lb_mass", "lb_mass_static", "lb_set_mass_check", "lb_time",
     "lb_get_populations", "lb_set_populations", "lb_set_time", "lb_get_particle_state",
     "lb_set_particle_state", "lb_set_option", "lb_get_option",
     "lb_destroy_domain", "lb_batch_workspace_bytes", "lb_batch_create", "lb_batch_step",
@@ -107,6 +107,7 @@ def library():
         "lb_get_particles": [vp, P(Particle), st],
         "lb_mass": [vp, dp],
         "lb_set_mass_check": [vp, C.c_double],
+        "lb_mass_static": [vp, vp],
         "lb_time": [vp, P(C.c_int64)],
         "lb_get_populations": [vp, dp],
         "lb_set_populations": [vp, dp],
