@@ -1,4 +1,5 @@
-"""Build the CPU oracle (test infrastructure): oracle/liblbo.so from lbo.c.
+"""Build the CPU oracle (test infrastructure): oracle/liblbo.so from lbo.c
+(D2Q9) and lbo3.c (D3Q19).
 
 Plain gcc, FP64, no fast-math and no floating-point contraction, so that the
 oracle's single-precision noise routines round every operation separately.
@@ -10,12 +11,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liblbo.so")
 
 
+SOURCES = [os.path.join(HERE, "lbo.c"), os.path.join(HERE, "lbo3.c")]
+
+
 def build(verbose: bool = False) -> str:
-    src = os.path.join(HERE, "lbo.c")
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
            "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
-           "-D_DEFAULT_SOURCE", src, "-o", tmp, "-lm"]
+           "-D_DEFAULT_SOURCE", *SOURCES, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

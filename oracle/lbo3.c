@@ -1,0 +1,203 @@
+/*
+ * lbo3.c -- CPU oracle (FP64) of the three-dimensional D3Q19 variant of the
+ * lattice-Boltzmann step (the 3D lattices the paper names as its next step,
+ * Sec. 8): BGK collision with the velocity-shift body force of Sec. 2
+ * (u_eq = j/rho + tau g), pull streaming, halfway bounce-back on solid
+ * nodes.  TEST INFRASTRUCTURE ONLY: used by the tests and the benchmark's
+ * CPU-baseline leg, never by the library.
+ *
+ * Plain on purpose: full populations f (not deviations), two arrays, one
+ * loop per step of the method.  Build flags: -O2 -fno-fast-math
+ * -ffp-contract=off.
+ */
+#include "lbo3.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* D3Q19: the rest velocity, the six axis velocities and the twelve edge
+ * velocities (two unit components); opposite velocities sit at (i, i + 1)
+ * for odd i.  Weights 1/3, 1/18, 1/36 (c_s^2 = 1/3). */
+static const int EX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static const int EY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+static const int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+static double weight(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+static int opposite(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+struct lbo3_sim {
+  lbo3_params p;
+  int64_t t;
+  double *f, *fs; /* pre-collision f(t) and post-collision f*(t), [19][nz][ny][nx] */
+  uint8_t *solid; /* [nz][ny][nx] */
+};
+
+#define NODE(s, x, y, z) (((size_t)(z) * (s)->p.ny + (y)) * (s)->p.nx + (x))
+#define IDX(s, i, x, y, z) ((size_t)(i) * (size_t)(s)->p.nx * (s)->p.ny * (s)->p.nz + NODE(s, x, y, z))
+
+void lbo3_lattice(int *ex, int *ey, int *ez, double *w) {
+  for (int i = 0; i < 19; ++i) {
+    ex[i] = EX[i];
+    ey[i] = EY[i];
+    ez[i] = EZ[i];
+    w[i] = weight(i);
+  }
+}
+
+/* Equilibrium of Eq. LB2 on D3Q19 (c_s^2 = 1/3). */
+static double feq(int i, double rho, double ux, double uy, double uz) {
+  double eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
+  double uu = ux * ux + uy * uy + uz * uz;
+  return weight(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+}
+
+lbo3_sim *lbo3_create(const lbo3_params *p, const uint8_t *mask, const double *rho,
+                      const double *ux, const double *uy, const double *uz) {
+  if (p->nx < 3 || p->ny < 3 || p->nz < 3 || !(p->tau > 0.5)) return NULL;
+  lbo3_sim *s = (lbo3_sim *)calloc(1, sizeof(lbo3_sim));
+  s->p = *p;
+  size_t n = (size_t)p->nx * p->ny * p->nz;
+  s->f = (double *)calloc(19 * n, sizeof(double));
+  s->fs = (double *)calloc(19 * n, sizeof(double));
+  s->solid = (uint8_t *)calloc(n, 1);
+  for (int z = 0; z < p->nz; ++z)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        size_t id = NODE(s, x, y, z);
+        int sol = mask ? (mask[id] != 0) : 0;
+        if (p->wall_x && (x == 0 || x == p->nx - 1)) sol = 1;
+        if (p->wall_y && (y == 0 || y == p->ny - 1)) sol = 1;
+        if (p->wall_z && (z == 0 || z == p->nz - 1)) sol = 1;
+        s->solid[id] = (uint8_t)sol;
+        double r = rho ? rho[id] : p->rho0;
+        double vx = ux ? ux[id] : 0.0, vy = uy ? uy[id] : 0.0, vz = uz ? uz[id] : 0.0;
+        for (int i = 0; i < 19; ++i) s->f[IDX(s, i, x, y, z)] = sol ? 0.0 : feq(i, r, vx, vy, vz);
+      }
+  return s;
+}
+
+void lbo3_destroy(lbo3_sim *s) {
+  if (!s) return;
+  free(s->f);
+  free(s->fs);
+  free(s->solid);
+  free(s);
+}
+
+static int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+/* collide every fluid node into fs */
+static void collide(lbo3_sim *s) {
+  const lbo3_params *p = &s->p;
+#pragma omp parallel for schedule(static)
+  for (int z = 0; z < p->nz; ++z)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        if (s->solid[NODE(s, x, y, z)]) continue;
+        double fl[19], rho = 0, jx = 0, jy = 0, jz = 0;
+        for (int i = 0; i < 19; ++i) {
+          fl[i] = s->f[IDX(s, i, x, y, z)];
+          rho += fl[i];
+          jx += fl[i] * EX[i];
+          jy += fl[i] * EY[i];
+          jz += fl[i] * EZ[i];
+        }
+        double ux = jx / rho + p->tau * p->gx;
+        double uy = jy / rho + p->tau * p->gy;
+        double uz = jz / rho + p->tau * p->gz;
+        for (int i = 0; i < 19; ++i)
+          s->fs[IDX(s, i, x, y, z)] = fl[i] - (fl[i] - feq(i, rho, ux, uy, uz)) / p->tau;
+      }
+}
+
+/* pull: f_i(x, t+1) = f*_i(x - e_i) with periodic wrap; halfway bounce-back
+ * f*_{opp i}(x) where the source is solid */
+static void stream(lbo3_sim *s) {
+  const lbo3_params *p = &s->p;
+#pragma omp parallel for schedule(static)
+  for (int z = 0; z < p->nz; ++z)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        if (s->solid[NODE(s, x, y, z)]) {
+          for (int i = 0; i < 19; ++i) s->f[IDX(s, i, x, y, z)] = 0.0;
+          continue;
+        }
+        for (int i = 0; i < 19; ++i) {
+          int sx = wrap(x - EX[i], p->nx), sy = wrap(y - EY[i], p->ny), sz = wrap(z - EZ[i], p->nz);
+          s->f[IDX(s, i, x, y, z)] = s->solid[NODE(s, sx, sy, sz)]
+                                         ? s->fs[IDX(s, opposite(i), x, y, z)]
+                                         : s->fs[IDX(s, i, sx, sy, sz)];
+        }
+      }
+}
+
+void lbo3_run(lbo3_sim *s, int64_t nsteps) {
+  for (int64_t k = 0; k < nsteps; ++k) {
+    collide(s);
+    stream(s);
+    s->t += 1;
+  }
+}
+
+int64_t lbo3_time(const lbo3_sim *s) { return s->t; }
+
+void lbo3_moments(const lbo3_sim *s, double *rho, double *ux, double *uy, double *uz) {
+  const lbo3_params *p = &s->p;
+  for (int z = 0; z < p->nz; ++z)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        size_t id = NODE(s, x, y, z);
+        if (s->solid[id]) {
+          rho[id] = ux[id] = uy[id] = uz[id] = 0.0;
+          continue;
+        }
+        double r = 0, jx = 0, jy = 0, jz = 0;
+        for (int i = 0; i < 19; ++i) {
+          double v = s->f[IDX(s, i, x, y, z)];
+          r += v;
+          jx += v * EX[i];
+          jy += v * EY[i];
+          jz += v * EZ[i];
+        }
+        rho[id] = r;
+        ux[id] = jx / r + 0.5 * p->gx;
+        uy[id] = jy / r + 0.5 * p->gy;
+        uz[id] = jz / r + 0.5 * p->gz;
+      }
+}
+
+void lbo3_populations(const lbo3_sim *s, double *f) {
+  memcpy(f, s->f, 19 * (size_t)s->p.nx * s->p.ny * s->p.nz * sizeof(double));
+}
+
+double lbo3_mass(const lbo3_sim *s) {
+  const lbo3_params *p = &s->p;
+  double m = 0.0;
+  for (int z = 0; z < p->nz; ++z)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        if (s->solid[NODE(s, x, y, z)]) continue;
+        for (int i = 0; i < 19; ++i) m += s->f[IDX(s, i, x, y, z)];
+      }
+  return m;
+}
+
+void lbo3_momentum(const lbo3_sim *s, double *j) {
+  const lbo3_params *p = &s->p;
+  double a[3] = {0, 0, 0};
+  for (int z = 0; z < p->nz; ++z)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        if (s->solid[NODE(s, x, y, z)]) continue;
+        for (int i = 0; i < 19; ++i) {
+          double v = s->f[IDX(s, i, x, y, z)];
+          a[0] += v * EX[i];
+          a[1] += v * EY[i];
+          a[2] += v * EZ[i];
+        }
+      }
+  j[0] = a[0];
+  j[1] = a[1];
+  j[2] = a[2];
+}

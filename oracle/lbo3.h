@@ -1,0 +1,35 @@
+/*
+ * lbo3.h -- CPU oracle (FP64) of the D3Q19 lattice-Boltzmann step: BGK with
+ * the velocity-shift body force (Sec. 2), pull streaming with periodic wrap,
+ * halfway bounce-back on solid nodes.  TEST INFRASTRUCTURE ONLY.
+ *
+ * Arrays: nodes [nz][ny][nx] (x fastest), populations [19][nz][ny][nx].
+ * Step order: collide every fluid node, then pull-stream.  The reported
+ * velocity is u = j/rho + g/2.
+ */
+#ifndef LBO3_H
+#define LBO3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t wall_x, wall_y, wall_z; /* nonzero: the outermost planes are solid */
+  double tau, rho0, gx, gy, gz;
+} lbo3_params;
+
+typedef struct lbo3_sim lbo3_sim;
+
+lbo3_sim *lbo3_create(const lbo3_params *p, const uint8_t *mask, const double *rho,
+                      const double *ux, const double *uy, const double *uz);
+void lbo3_destroy(lbo3_sim *s);
+void lbo3_run(lbo3_sim *s, int64_t nsteps);
+int64_t lbo3_time(const lbo3_sim *s);
+void lbo3_moments(const lbo3_sim *s, double *rho, double *ux, double *uy, double *uz);
+void lbo3_populations(const lbo3_sim *s, double *f);
+double lbo3_mass(const lbo3_sim *s);
+void lbo3_momentum(const lbo3_sim *s, double *j);
+void lbo3_lattice(int *ex, int *ey, int *ez, double *w);
+
+#endif

@@ -39,6 +39,15 @@ class _Particle(C.Structure):
     ]
 
 
+class _Params3(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("wall_x", C.c_int32), ("wall_y", C.c_int32), ("wall_z", C.c_int32),
+        ("tau", C.c_double), ("rho0", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
+        ("gz", C.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -47,8 +56,8 @@ def _load():
     if _lib is not None:
         return _lib
     path = _build.LIB
-    src = os.path.join(os.path.dirname(path), "lbo.c")
-    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+    if not os.path.exists(path) or any(os.path.getmtime(path) < os.path.getmtime(src)
+                                       for src in _build.SOURCES):
         _build.build()
     lib = C.CDLL(path)
     P = C.POINTER
@@ -79,6 +88,18 @@ def _load():
     lib.lbo_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, P(C.c_float)]
     lib.lbo_normals_bulk.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                      P(C.c_float)]
+    lib.lbo3_create.restype = C.c_void_p
+    lib.lbo3_create.argtypes = [P(_Params3), P(C.c_uint8), dptr, dptr, dptr, dptr]
+    lib.lbo3_destroy.argtypes = [C.c_void_p]
+    lib.lbo3_run.argtypes = [C.c_void_p, C.c_int64]
+    lib.lbo3_time.restype = C.c_int64
+    lib.lbo3_time.argtypes = [C.c_void_p]
+    lib.lbo3_moments.argtypes = [C.c_void_p, dptr, dptr, dptr, dptr]
+    lib.lbo3_populations.argtypes = [C.c_void_p, dptr]
+    lib.lbo3_mass.restype = C.c_double
+    lib.lbo3_mass.argtypes = [C.c_void_p]
+    lib.lbo3_momentum.argtypes = [C.c_void_p, dptr]
+    lib.lbo3_lattice.argtypes = [P(C.c_int), P(C.c_int), P(C.c_int), dptr]
     _lib = lib
     return lib
 
@@ -242,3 +263,74 @@ def own_sincos2pi(u):
     s, c = C.c_float(), C.c_float()
     _load().lbo_sincos2pi(float(u), C.byref(s), C.byref(c))
     return np.float32(s.value), np.float32(c.value)
+
+
+class Oracle3:
+    """One D3Q19 domain of the FP64 CPU oracle (lbo3.c).  Node arrays are
+    [nz][ny][nx]; populations [19][nz][ny][nx]."""
+
+    def __init__(self, nx, ny, nz, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0), walls=(False, False, False),
+                 obstacles=None, init=None):
+        lib = _load()
+        self.nx, self.ny, self.nz = nx, ny, nz
+        c = _Params3(nx, ny, nz, int(walls[0]), int(walls[1]), int(walls[2]), tau, rho0, *g)
+        shape = (nz, ny, nx)
+        mask = None
+        if obstacles is not None:
+            self._mask = np.ascontiguousarray(obstacles, dtype=np.uint8).reshape(shape)
+            mask = self._mask.ctypes.data_as(C.POINTER(C.c_uint8))
+        fields = [None] * 4
+        if init is not None:
+            fields = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), shape))
+                      for a in init]
+        self._h = lib.lbo3_create(C.byref(c), mask, *[_dp(a) for a in fields])
+        if not self._h:
+            raise ValueError("oracle rejected parameters")
+        self._lib = lib
+
+    def close(self):
+        if self._h:
+            self._lib.lbo3_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, nsteps):
+        self._lib.lbo3_run(self._h, int(nsteps))
+        return self
+
+    @property
+    def t(self):
+        return self._lib.lbo3_time(self._h)
+
+    def moments(self):
+        shape = (self.nz, self.ny, self.nx)
+        out = [np.zeros(shape) for _ in range(4)]
+        self._lib.lbo3_moments(self._h, *[_dp(a) for a in out])
+        return tuple(out)
+
+    def populations(self):
+        f = np.zeros((19, self.nz, self.ny, self.nx))
+        self._lib.lbo3_populations(self._h, _dp(f))
+        return f
+
+    def mass(self):
+        return self._lib.lbo3_mass(self._h)
+
+    def momentum(self):
+        j = np.zeros(3)
+        self._lib.lbo3_momentum(self._h, _dp(j))
+        return j
+
+
+def lattice3():
+    """(ex, ey, ez, w) of the oracle's D3Q19 velocity set."""
+    lib = _load()
+    ex, ey, ez = (C.c_int * 19)(), (C.c_int * 19)(), (C.c_int * 19)()
+    w = np.zeros(19)
+    lib.lbo3_lattice(ex, ey, ez, _dp(w))
+    return np.array(ex[:]), np.array(ey[:]), np.array(ez[:]), w

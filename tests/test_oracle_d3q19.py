@@ -1,0 +1,130 @@
+"""Pins of the oracle's D3Q19 variant (the three-dimensional lattice the
+paper names as its next step, Sec. 8, with the BGK collision and the
+velocity-shift forcing of Sec. 2): lattice isotropy, equilibrium moments,
+exact conservation, the exact discrete steady solution of plane Poiseuille
+flow, shear-wave decay at the BGK viscosity and the series solution of
+square-duct flow with second-order convergence."""
+import numpy as np
+
+from oracle.oracle import Oracle3, lattice3
+
+
+def test_d3q19_lattice_isotropy():
+    ex, ey, ez, w = lattice3()
+    e = np.stack([ex, ey, ez], 1)
+    assert len({tuple(v) for v in e}) == 19
+    assert sorted((e ** 2).sum(1).tolist()) == [0] + [1] * 6 + [2] * 12
+    for i in range(1, 19):  # opposites pair as (i, i + 1), i odd
+        j = i + 1 if i % 2 else i - 1
+        assert np.array_equal(e[j], -e[i])
+    assert abs(w.sum() - 1) < 1e-15
+    d = np.eye(3)
+    m2 = np.einsum("i,ia,ib->ab", w, e, e)
+    np.testing.assert_allclose(m2, d / 3, atol=1e-15)
+    assert np.abs(np.einsum("i,ia->a", w, e)).max() < 1e-15
+    assert np.abs(np.einsum("i,ia,ib,ic->abc", w, e, e, e)).max() < 1e-15
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, e, e, e, e)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d)) / 9
+    np.testing.assert_allclose(m4, iso, atol=1e-15)
+
+
+def test_equilibrium_moments():
+    """Populations of the initial state (equilibria) have density rho,
+    momentum rho u and momentum flux rho/3 I + rho u u."""
+    rng = np.random.default_rng(3)
+    shape = (5, 4, 6)
+    rho = 1 + 0.01 * rng.standard_normal(shape)
+    u = 0.05 * rng.standard_normal((3,) + shape)
+    o = Oracle3(6, 4, 5, init=(rho, u[0], u[1], u[2]))
+    f = o.populations()
+    ex, ey, ez, _ = lattice3()
+    e = np.stack([ex, ey, ez], 1).astype(float)
+    np.testing.assert_allclose(f.sum(0), rho, rtol=1e-14)
+    j = np.einsum("ia,i...->a...", e, f)
+    np.testing.assert_allclose(j, rho * u, atol=1e-15)
+    pi = np.einsum("ia,ib,i...->ab...", e, e, f)
+    ref = np.einsum("ab,...->ab...", np.eye(3), rho / 3) + rho * np.einsum("a...,b...->ab...", u, u)
+    np.testing.assert_allclose(pi, ref, atol=1e-14)
+
+
+def test_mass_and_momentum_balance():
+    """Periodic box with an obstacle: mass is conserved and the momentum
+    grows by g times the fluid mass each step, less what the solid takes."""
+    rng = np.random.default_rng(4)
+    n = (10, 9, 8)
+    o = Oracle3(*n, tau=0.7, g=(2e-5, -1e-5, 3e-6),
+                init=(1 + 0.01 * rng.standard_normal(n[::-1]), 0.01 * rng.standard_normal(n[::-1]),
+                      0.0, 0.0))
+    m0 = o.mass()
+    o.run(40)
+    assert abs(o.mass() - m0) / m0 < 1e-13
+    free = Oracle3(*n, tau=0.7, g=(2e-5, -1e-5, 3e-6))
+    for _ in range(5):
+        j0 = free.momentum()
+        free.run(1)
+        np.testing.assert_allclose(free.momentum() - j0, np.array([2e-5, -1e-5, 3e-6]) * free.mass(),
+                                   rtol=1e-12, atol=1e-13)
+
+
+def test_plane_poiseuille_exact_discrete_steady_state():
+    """Walls at z = 0 and nz - 1 (halfway bounce-back), body force along x:
+    the steady u = j/rho + g/2 is the exact discrete solution
+    g/(2 nu) (z - 1/2)(nz - 3/2 - z) + g (16 (tau - 1/2)^2 - 3) / (24 nu),
+    the same as on D2Q9 (the flow involves only the populations with
+    e_z != 0, which bounce back alike)."""
+    nz, g, tau = 34, 1e-6, 0.8
+    o = Oracle3(4, 4, nz, tau=tau, g=(g, 0.0, 0.0), walls=(False, False, True))
+    o.run(30000)
+    _, ux, uy, uz = o.moments()
+    nu = (tau - 0.5) / 3
+    z = np.arange(1, nz - 1)
+    exact = g / (2 * nu) * (z - 0.5) * (nz - 1.5 - z) + g * (16 * (tau - 0.5) ** 2 - 3) / (24 * nu)
+    u = ux[1:-1, :, :]
+    assert np.abs(u - exact[:, None, None]).max() / exact.max() < 1e-10
+    assert max(np.abs(uy).max(), np.abs(uz).max()) < 1e-10 * exact.max()
+
+
+def test_shear_wave_decays_at_the_bgk_viscosity():
+    """u_x = u0 sin(k z) in a periodic box decays as exp(-nu k^2 t) with
+    nu = (tau - 1/2)/3, up to O(k^2) lattice corrections."""
+    nz, u0, t = 64, 1e-3, 600
+    k = 2 * np.pi / nz
+    for tau in (0.6, 1.1):
+        z = np.arange(nz)[:, None, None] + np.zeros((nz, 3, 4))
+        o = Oracle3(4, 3, nz, tau=tau, init=(1.0, u0 * np.sin(k * z), 0.0, 0.0))
+        o.run(t)
+        _, ux, _, _ = o.moments()
+        amp = 2 * (ux[:, 0, 0] * np.sin(k * np.arange(nz))).mean()
+        ref = u0 * np.exp(-(tau - 0.5) / 3 * k * k * t)
+        assert abs(amp / ref - 1) < 2e-3, (tau, amp, ref)
+
+
+def _duct_series(n, g, nu, terms=200):
+    """Square duct, walls halfway between the solid planes: half width
+    a = (n - 2)/2; u = 16 a^2 g/(nu pi^3) sum_(m odd) (-1)^((m-1)/2) m^-3
+    [1 - cosh(m pi z/(2a)) / cosh(m pi/2)] cos(m pi y/(2a))."""
+    a = (n - 2) / 2.0
+    c = np.arange(n) - (n - 1) / 2.0
+    Z, Y = np.meshgrid(c, c, indexing="ij")
+    u = np.zeros_like(Y)
+    for q in range(terms):
+        m = 2 * q + 1
+        u += (-1) ** q / m ** 3 * (1 - np.cosh(m * np.pi * Z / (2 * a)) / np.cosh(m * np.pi / 2)) \
+            * np.cos(m * np.pi * Y / (2 * a))
+    return 16 * a * a * g / (nu * np.pi ** 3) * u
+
+
+def test_square_duct_flow_converges_to_the_series_solution():
+    g, tau = 1e-6, 0.8
+    nu = (tau - 0.5) / 3
+    errs = []
+    for n in (18, 34):
+        o = Oracle3(4, n, n, tau=tau, g=(g, 0.0, 0.0), walls=(False, True, True))
+        o.run(int(4 * n * n / nu))
+        _, ux, _, _ = o.moments()
+        u = ux[1:-1, 1:-1, 0]
+        ref = _duct_series(n, g, nu)[1:-1, 1:-1]
+        errs.append(np.sqrt(((u - ref) ** 2).sum() / (ref ** 2).sum()))
+    assert errs[1] < 1.5e-3
+    assert errs[0] / errs[1] > 3.0  # second order in the lattice spacing
