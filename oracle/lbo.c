@@ -94,8 +94,9 @@ static uint32_t float_to_bits(float f) {
 
 /* Natural log of a normal float in (0, 1]: exponent split u = m 2^e with
  * m in [sqrt(1/2), sqrt(2)], then ln m = 2 atanh(s), s = (m-1)/(m+1), by its
- * power series to s^11; ln 2 is split hi + lo (Cody & Waite) so that e*hi is
- * exact.  Every operation is a single IEEE float operation in a fixed order. */
+ * power series to s^11 (Horner steps as fused multiply-adds); ln 2 is split
+ * hi + lo (Cody & Waite) so that e*hi is exact.  Every operation is a single
+ * IEEE float operation (fmaf: one rounding) in a fixed order. */
 float lbo_logf(float u) {
   uint32_t b = float_to_bits(u);
   int e = (int)((b >> 23) & 0xffu) - 127;
@@ -107,21 +108,22 @@ float lbo_logf(float u) {
   float s = (m - 1.0f) / (m + 1.0f);
   float s2 = s * s;
   float poly = 1.0f / 11.0f;
-  poly = poly * s2 + 1.0f / 9.0f;
-  poly = poly * s2 + 1.0f / 7.0f;
-  poly = poly * s2 + 1.0f / 5.0f;
-  poly = poly * s2 + 1.0f / 3.0f;
-  poly = poly * s2 + 1.0f;
+  poly = fmaf(poly, s2, 1.0f / 9.0f);
+  poly = fmaf(poly, s2, 1.0f / 7.0f);
+  poly = fmaf(poly, s2, 1.0f / 5.0f);
+  poly = fmaf(poly, s2, 1.0f / 3.0f);
+  poly = fmaf(poly, s2, 1.0f);
   float lnm = (s + s) * poly;
   const float LN2_HI = 0.693145751953125f;      /* 45426 / 65536              */
   const float LN2_LO = 1.42860682030941723e-6f; /* ln 2 - LN2_HI, rounded     */
   float fe = (float)e;
-  return fe * LN2_HI + (fe * LN2_LO + lnm);
+  return fmaf(fe, LN2_HI, fmaf(fe, LN2_LO, lnm));
 }
 
 /* sin and cos of 2 pi u for u a multiple of 2^-22 in (0, 1): exact reduction
  * to a quadrant q and a remainder r in [-1/8, 1/8], then Taylor series of sin
- * (to a^9) and cos (to a^10) at a = 2 pi r, |a| <= pi/4. */
+ * (to a^9) and cos (to a^10) at a = 2 pi r, |a| <= pi/4, Horner steps as
+ * fused multiply-adds. */
 void lbo_sincos2pi(float u, float *sn, float *cs) {
   int q = (int)(u * 4.0f);
   float r = u - 0.25f * (float)q;
@@ -133,16 +135,16 @@ void lbo_sincos2pi(float u, float *sn, float *cs) {
   float a = r * TWO_PI;
   float a2 = a * a;
   float ps = 1.0f / 362880.0f;
-  ps = ps * a2 + (-1.0f / 5040.0f);
-  ps = ps * a2 + 1.0f / 120.0f;
-  ps = ps * a2 + (-1.0f / 6.0f);
-  float sa = a + (a * a2) * ps;
+  ps = fmaf(ps, a2, -1.0f / 5040.0f);
+  ps = fmaf(ps, a2, 1.0f / 120.0f);
+  ps = fmaf(ps, a2, -1.0f / 6.0f);
+  float sa = fmaf(a * a2, ps, a);
   float pc = -1.0f / 3628800.0f;
-  pc = pc * a2 + 1.0f / 40320.0f;
-  pc = pc * a2 + (-1.0f / 720.0f);
-  pc = pc * a2 + 1.0f / 24.0f;
-  pc = pc * a2 + (-0.5f);
-  float ca = 1.0f + a2 * pc;
+  pc = fmaf(pc, a2, 1.0f / 40320.0f);
+  pc = fmaf(pc, a2, -1.0f / 720.0f);
+  pc = fmaf(pc, a2, 1.0f / 24.0f);
+  pc = fmaf(pc, a2, -0.5f);
+  float ca = fmaf(a2, pc, 1.0f);
   switch (q & 3) {
     case 0: *sn = sa;  *cs = ca;  break;
     case 1: *sn = ca;  *cs = -sa; break;

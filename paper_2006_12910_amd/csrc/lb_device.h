@@ -273,8 +273,9 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 // turned into uniforms (2k+1) 2^-22 and paired (w0,w1), (w2,w3), (low words)
 // into three Box-Muller transforms (radius, angle) giving Theta_3..Theta_8.
 // Every floating-point operation below is a single correctly rounded IEEE
-// float operation in a fixed order (no contraction), so the host's
-// independent implementation of the same definition reproduces it bit-exactly.
+// float operation (the Horner steps fused multiply-adds, nothing else
+// contracted) in a fixed order, so the host's independent implementation of
+// the same definition reproduces it bit-exactly.
 
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t out[4]) {
@@ -295,8 +296,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 }
 
 // ln u for u in (0,1]: u = m 2^e, m folded into [sqrt(1/2), sqrt(2)];
-// ln m = 2 atanh(s), s = (m-1)/(m+1), power series through s^11; ln 2 in two
-// parts (Cody-Waite) so that e * hi is exact.
+// ln m = 2 atanh(s), s = (m-1)/(m+1), power series through s^11 (Horner with
+// fused multiply-adds); ln 2 in two parts (Cody-Waite) so that e * hi is exact.
 __device__ __forceinline__ float noise_log(float u) {
 #pragma clang fp contract(off)
   uint32_t b = __float_as_uint(u);
@@ -309,19 +310,19 @@ __device__ __forceinline__ float noise_log(float u) {
   const float s = (m - 1.0f) / (m + 1.0f);
   const float s2 = s * s;
   float p = 1.0f / 11.0f;
-  p = p * s2 + 1.0f / 9.0f;
-  p = p * s2 + 1.0f / 7.0f;
-  p = p * s2 + 1.0f / 5.0f;
-  p = p * s2 + 1.0f / 3.0f;
-  p = p * s2 + 1.0f;
+  p = __builtin_fmaf(p, s2, 1.0f / 9.0f);
+  p = __builtin_fmaf(p, s2, 1.0f / 7.0f);
+  p = __builtin_fmaf(p, s2, 1.0f / 5.0f);
+  p = __builtin_fmaf(p, s2, 1.0f / 3.0f);
+  p = __builtin_fmaf(p, s2, 1.0f);
   const float lnm = (s + s) * p;
   const float fe = (float)e;
-  return fe * 0.693145751953125f + (fe * 1.42860682030941723e-6f + lnm);
+  return __builtin_fmaf(fe, 0.693145751953125f, __builtin_fmaf(fe, 1.42860682030941723e-6f, lnm));
 }
 
 // sin and cos of 2 pi u, u a multiple of 2^-22 in (0,1): exact reduction to a
 // quadrant and r in [-1/8, 1/8]; Taylor series at a = 2 pi r through a^9 (sin)
-// and a^10 (cos).
+// and a^10 (cos), Horner with fused multiply-adds.
 __device__ __forceinline__ void noise_sincos2pi(float u, float &sn, float &cs) {
 #pragma clang fp contract(off)
   int q = (int)(u * 4.0f);
@@ -333,16 +334,16 @@ __device__ __forceinline__ void noise_sincos2pi(float u, float &sn, float &cs) {
   const float a = r * 6.28318530717958647692f;
   const float a2 = a * a;
   float ps = 1.0f / 362880.0f;
-  ps = ps * a2 + (-1.0f / 5040.0f);
-  ps = ps * a2 + 1.0f / 120.0f;
-  ps = ps * a2 + (-1.0f / 6.0f);
-  const float sa = a + (a * a2) * ps;
+  ps = __builtin_fmaf(ps, a2, -1.0f / 5040.0f);
+  ps = __builtin_fmaf(ps, a2, 1.0f / 120.0f);
+  ps = __builtin_fmaf(ps, a2, -1.0f / 6.0f);
+  const float sa = __builtin_fmaf(a * a2, ps, a);
   float pc = -1.0f / 3628800.0f;
-  pc = pc * a2 + 1.0f / 40320.0f;
-  pc = pc * a2 + (-1.0f / 720.0f);
-  pc = pc * a2 + 1.0f / 24.0f;
-  pc = pc * a2 + (-0.5f);
-  const float ca = 1.0f + a2 * pc;
+  pc = __builtin_fmaf(pc, a2, 1.0f / 40320.0f);
+  pc = __builtin_fmaf(pc, a2, -1.0f / 720.0f);
+  pc = __builtin_fmaf(pc, a2, 1.0f / 24.0f);
+  pc = __builtin_fmaf(pc, a2, -0.5f);
+  const float ca = __builtin_fmaf(a2, pc, 1.0f);
   switch (q & 3) {
     case 0: sn = sa; cs = ca; break;
     case 1: sn = ca; cs = -sa; break;
