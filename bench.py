@@ -205,20 +205,21 @@ def timed_call(batch, steps):
 def run_variant(storage, specs, masks, steps, warmup, tune, fixed_tiles=None, two_step=True):
     """The batch of the workload in one storage format, timed over `steps`
     steps after `warmup` (the first call captures every step graph the batch
-    uses, so nothing is captured inside the timed call).  With the two-step
-    sweep (every domain qualifies: periodic, no particles) the tile shapes are
-    fixed and not tuned; with single steps the autotuner picks them.  Also
-    returns the ms of a following call of 2 * steps steps."""
+    uses, so nothing is captured inside the timed call).  With single steps
+    the autotuner picks the members' tile shapes.  Also
+    returns the ms of a following call of 2 * steps steps.  An untimed call
+    of `steps` steps precedes the timed one.  With the two-step sweep the
+    batch's tile height comes from lb_batch_autotune (unless --no-tune)."""
     import torch
     from paper_2006_12910_amd import lb
     t0 = time.time()
-    tune = tune and not two_step
-    tiles = fixed_tiles if fixed_tiles else (tune_batch(storage, specs, masks) if tune else None)
+    tiles = fixed_tiles if fixed_tiles else (
+        tune_batch(storage, specs, masks) if tune and not two_step else None)
     doms = build_variant(storage, specs, masks, tiles)
     for d in doms:
         d.set_option(lb.OPT_TWO_STEP, 1 if two_step else 0)
     # the single-step shapes in use, per class (explicit also where the
-    # defaults won); the two-step sweep's tiles are fixed
+    # defaults won)
     tiles = None
     if not two_step:
         tiles = {}
@@ -228,12 +229,23 @@ def run_variant(storage, specs, masks, steps, warmup, tune, fixed_tiles=None, tw
     batch = lb.Batch(doms)
     torch.cuda.synchronize()
     log(f"{storage}: built {len(doms)} domains in {time.time() - t0:.1f}s")
+    if two_step and tune:
+        # the two-step tile height: lb_batch_autotune (timed, or from its cache)
+        ms_t = batch.autotune(steps=16)
+        log(f"{storage}: batch two-step tile height {batch.get_option(lb.OPT_TWO_STEP_ROWS)} "
+            f"({'timed, ' + format(ms_t, '.3f') + ' ms/step' if ms_t > 0 else 'cached'})")
     batch.step(max(warmup, 1))
+    # one untimed call of the timed length first (a 20-step call timed right
+    # after a 5-step warm-up took ~3 ms more than its share of a 40-step call)
+    batch.step(steps)
     torch.cuda.synchronize()
     ms = timed_call(batch, steps)
     log(f"{storage}: {steps} steps in {ms:.1f} ms")
     ms2 = timed_call(batch, 2 * steps)
     log(f"{storage}: {2 * steps} steps in {ms2:.1f} ms")
+    if two_step:
+        tiles = f"two-step: 62 columns x {batch.get_option(lb.OPT_TWO_STEP_ROWS)} rows per tile" + (
+            " (lb_batch_autotune)" if tune else " (default)")
     return doms, batch, ms, ms2, tiles
 
 
@@ -412,6 +424,23 @@ def other_configs(with_oracle):
     oracle_rate("powerlaw_4096x256_n0.5_f32",
                 Oracle(OracleParams(nx=4096, ny=256, bc_y=WALL, gx=2.648e-6, power_law=True, n_index=0.5,
                                     K=0.01)), 4096 * 256, 20)
+    # the D3Q19 lattice: 256^3 periodic, FP32 storage, one sweep per step;
+    # algorithmic bytes 2 x 19 x 4 per node update; the oracle on 64^3
+    from oracle.oracle import Oracle3
+    n3 = 256
+    d = lb.Domain3(n3, n3, n3, tau=0.8, storage="f32")
+    gpu_rate("d3q19_256cube_f32", d, n3 ** 3, 200)
+    d.close()
+    r = out["d3q19_256cube_f32"]
+    r["sweep_GBps"] = round(r["gpu_mlups"] * 1e6 * 152 / 1e9, 1)
+    r["hbm_frac"] = round(r["sweep_GBps"] / HBM_PEAK_GBS, 4)
+    if with_oracle:
+        o3 = Oracle3(64, 64, 64, tau=0.8)
+        t0 = time.perf_counter()
+        o3.run(10)
+        r["oracle_mlups"] = round(64 ** 3 * 10 / (time.perf_counter() - t0) / 1e6, 2)
+        r["oracle_lattice"] = "64^3"
+        del o3
     torch.cuda.empty_cache()
     return out
 
@@ -711,7 +740,7 @@ def main():
                  "hbm_frac": round(spl * bytes_alg / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                  "bytes_per_step": bytes_alg, "rounding": ROUNDING[v],
                  "two_step": two,
-                 "tiles": "two-step: 62 columns x 14/10/6 rows (16-bit/FP32/FP64) per tile" if tiles is None else {f"{'obstacles' if k[0] else 'open'}/class{k[1]}": f"{t[0]}x{t[1]}"
+                 "tiles": tiles if isinstance(tiles, str) or tiles is None else {f"{'obstacles' if k[0] else 'open'}/class{k[1]}": f"{t[0]}x{t[1]}"
                                                        for k, t in tiles.items()}}
         results[v] = entry
         batch.close()

@@ -304,6 +304,11 @@ lb_status lb_set_particle_state(lb_domain *d, const lb_particle_state *in, int32
  * (>= 1, default 256; 1: after every call).  On a batch it counts the batch's
  * own steps. */
 #define LB_OPT_MASS_INTERVAL 8
+/* Output rows of the two-step sweep's tiles (62 columns each): one of 10, 14,
+ * 18 (16-bit storage; default 14), 6, 10, 14 (FP32; default 10), 4, 6, 8
+ * (FP64; default 6); results do not depend on it.  On a batch: the height of
+ * its launch (at creation the members' common height, else the default). */
+#define LB_OPT_TWO_STEP_ROWS 10
 lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value);
 lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value);
 
@@ -327,9 +332,10 @@ lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_worksp
  * for each member).  The density sums that LB_OPT_MASS_INTERVAL selects
  * (counted in the batch's own steps) cover every member in two launches. */
 lb_status lb_batch_step(lb_batch *b, int64_t nsteps);
-/* Batch options: LB_OPT_USE_GRAPH, LB_OPT_GRAPH_CHUNK, LB_OPT_MASS_INTERVAL
- * (LB_EINVAL for the others). */
+/* Batch options: LB_OPT_USE_GRAPH, LB_OPT_GRAPH_CHUNK, LB_OPT_MASS_INTERVAL,
+ * LB_OPT_TWO_STEP_ROWS (LB_EINVAL for the others). */
 lb_status lb_batch_set_option(lb_batch *b, int32_t key, int64_t value);
+lb_status lb_batch_get_option(lb_batch *b, int32_t key, int64_t *value);
 lb_status lb_batch_destroy(lb_batch *b);
 
 /* Diagnostic: the six standard normals Theta_3..Theta_8 that the collision of
@@ -338,11 +344,69 @@ lb_status lb_batch_destroy(lb_batch *b);
 lb_status lb_noise_normals(uint64_t seed, uint32_t domain_id, uint32_t step, uint32_t node0,
                            uint32_t count, float *dev_out, void *hip_stream);
 
-/* Autotune the single-step sweep's tile for this domain: times each candidate
- * tile width / rows-per-thread pair over `steps` single steps (the state
- * advances; the two-step sweep, whose tiles are fixed, is off while timing)
- * and keeps the fastest.  *best_ms receives its time per step. */
+/* Autotune this domain's sweep tiles: times each candidate single-step tile
+ * width / rows-per-thread pair over `steps` single steps (the two-step sweep
+ * off while timing) and keeps the fastest; where the two-step sweep applies,
+ * then also its tile height (LB_OPT_TWO_STEP_ROWS), timed over `steps`
+ * rounded up to a multiple of four.  The height chosen is cached for the
+ * process per (storage, label plane, rounding, size class floor(log2(nx ny)))
+ * and later domains of a cached class take it without timing.  The state
+ * advances by the steps timed.  *best_ms receives the best time per step. */
 lb_status lb_autotune(lb_domain *d, int32_t steps, double *best_ms);
+
+/* Autotune a batch's two-step tile height (LB_OPT_TWO_STEP_ROWS of the
+ * batch): each instantiated height is timed over `steps` steps (rounded up to
+ * a multiple of four, after an untimed call of as many), the fastest kept
+ * and cached for the process per (storage, label plane in any member,
+ * rounding, size class of the batch's total sites); a cached class is applied
+ * without timing (*best_ms = 0).  A batch that runs single steps is left as
+ * it is.  The members' states advance by the steps timed. */
+lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms);
+
+/* ---------------------------------------------------------------------------
+ * D3Q19 domains: the three-dimensional lattice the paper names as its next
+ * step (Sec. 8), with the same BGK collision and velocity-shift body force
+ * (Sec. 2, Eqs. LB1-LB2 on D3Q19: weights 1/3, 1/18, 1/36, c_s^2 = 1/3), pull
+ * streaming with periodic wrap and halfway bounce-back on solid nodes.  The
+ * velocity set: rest; (+-1,0,0), (0,+-1,0), (0,0,+-1); then (1,1,0),
+ * (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1),
+ * (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1) (opposites in consecutive pairs).
+ * Host node arrays are [nz][ny][nx] (x fastest), populations
+ * [19][nz][ny][nx].  Storage: LB_F64 or LB_F32 deviations f_i - w_i rho0
+ * (FP32 arithmetic with FP32 storage, its increment holding exactly the
+ * collision's mass and momentum change).  Same conventions as above:
+ * caller-owned 256-byte aligned workspace, stream-ordered calls, errors
+ * through lb_last_error.  No particles, noise or power law. */
+typedef struct lb3_domain_desc {
+  uint32_t abi_version;        /* LB_ABI_VERSION                                  */
+  int32_t nx, ny, nz;          /* each in [3, 4096]                               */
+  int32_t wall_x, wall_y, wall_z;  /* nonzero: the outermost planes are solid    */
+  int32_t storage;             /* LB_F64 | LB_F32                                 */
+  int32_t obstacles;           /* nonzero: lb3_set_obstacles may be called        */
+  int32_t init_kind;           /* LB_INIT_REST | LB_INIT_FIELDS                   */
+  double rho0, tau;            /* reference density (> 0), relaxation time (> 1/2) */
+  double gx, gy, gz;           /* body acceleration                               */
+  const double *init_rho, *init_ux, *init_uy, *init_uz;  /* host [nz][ny][nx], copied */
+} lb3_domain_desc;
+typedef struct lb3_domain lb3_domain;
+
+lb_status lb3_workspace_bytes(const lb3_domain_desc *desc, size_t *bytes);
+/* Create and initialise (equilibrium of the fields, then one collision). */
+lb_status lb3_create_domain(const lb3_domain_desc *desc, void *dev_workspace, size_t bytes,
+                            void *hip_stream, lb3_domain **out);
+/* Solid nodes: host mask [nz][ny][nx], nonzero = solid (walls stay solid). */
+lb_status lb3_set_obstacles(lb3_domain *d, const uint8_t *host_mask, size_t n);
+/* Enqueue nsteps steps (one sweep launch per step); nsteps >= 0. */
+lb_status lb3_step(lb3_domain *d, int64_t nsteps);
+/* rho and u = j/rho + g/2 at every node (zero on solids), host FP64
+ * [nz][ny][nx] each.  Synchronises; LB_EUNSTABLE after a non-finite state. */
+lb_status lb3_moments(lb3_domain *d, double *rho, double *ux, double *uy, double *uz);
+/* Post-collision deviations, host FP64 [19][nz][ny][nx].  Synchronises. */
+lb_status lb3_get_populations(lb3_domain *d, double *host_dev_f);
+/* FP64 sum of rho over the non-solid nodes (fixed order).  Synchronises. */
+lb_status lb3_mass(lb3_domain *d, double *total);
+lb_status lb3_time(lb3_domain *d, int64_t *t);
+lb_status lb3_destroy_domain(lb3_domain *d);
 
 const char *lb_status_string(lb_status s);
 const char *lb_last_error(void);

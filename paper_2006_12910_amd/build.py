@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblb.so")
 SOURCES = ["lb_api.hip", "common.hip", "kern_f64.hip", "kern_f32.hip", "kern_f16.hip",
-           "kern_bf16.hip"]
+           "kern_bf16.hip", "lb3_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # No floating-point contraction: a node's arithmetic then compiles to the same

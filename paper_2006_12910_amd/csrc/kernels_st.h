@@ -22,9 +22,18 @@ void sweep_l(const DevDomain *doms, const int *prefix, int ndom, int kstep, int 
 }
 template <int FEAT>
 void sweep2_l(const DevDomain *doms, const int *prefix2, int ndom, int kstep, int which, int blocks,
-              hipStream_t s) {
-  hipLaunchKernelGGL((k_sweep2<ST, FEAT>), dim3(blocks), dim3(256), 0, s, doms, prefix2, ndom,
-                     kstep, which);
+              int rows, hipStream_t s) {
+  constexpr int H0 = two_step_rows_of(ST, 0), H1 = two_step_rows_of(ST, 1),
+                H2 = two_step_rows_of(ST, 2);
+  if (rows == H0)
+    hipLaunchKernelGGL((k_sweep2<ST, FEAT, H0>), dim3(blocks), dim3(256), 0, s, doms, prefix2,
+                       ndom, kstep, which);
+  else if (rows == H2)
+    hipLaunchKernelGGL((k_sweep2<ST, FEAT, H2>), dim3(blocks), dim3(256), 0, s, doms, prefix2,
+                       ndom, kstep, which);
+  else
+    hipLaunchKernelGGL((k_sweep2<ST, FEAT, H1>), dim3(blocks), dim3(256), 0, s, doms, prefix2,
+                       ndom, kstep, which);
 }
 template <int FEAT, int PLM, int WIDE>
 void init_l(const DevDomain *dom, const double *rho, const double *ux, const double *uy, int row0,

@@ -10,10 +10,11 @@ struct KernelSet {
   // coupling's reach (near_tiles of the step)
   void (*sweep)(const DevDomain *doms, const int *prefix, int ndom, int kstep, int blocks, int part,
                 hipStream_t s);
-  // two steps per launch (periodic plain/obstacle domains); null where the
-  // feature set has no two-step kernel
+  // two steps per launch (periodic plain/obstacle domains), tiles of `rows`
+  // output rows (one of two_step_rows_of); null where the feature set has no
+  // two-step kernel
   void (*sweep2)(const DevDomain *doms, const int *prefix2, int ndom, int kstep, int which,
-                 int blocks, hipStream_t s);
+                 int blocks, int rows, hipStream_t s);
   void (*init)(const DevDomain *dom, const double *rho, const double *ux, const double *uy,
                int row0, int nrows, int pitch, hipStream_t s);
   // particle coupling before and after the sweep (one workgroup per particle)

@@ -1,0 +1,348 @@
+// lb3_api.hip -- C ABI of the D3Q19 domains (declared in include/lb.h):
+// validation, workspace layout, launch sequence, host transfers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lb.h"
+#include "sweep3_impl.h"
+
+using namespace lbk3;
+
+namespace lbk {
+// records msg as lb_last_error() and returns s (lb_api.hip)
+lb_status lb_fail(lb_status s, const std::string &msg);
+}
+
+namespace {
+
+lb_status fail3(lb_status s, const std::string &msg) { return lbk::lb_fail(s, msg); }
+
+#define HIPCHK3(call)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail3(LB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// nodes per host-transfer band (initial fields, moments, populations)
+constexpr long long BAND = 262144;
+
+struct Header3 {
+  uint64_t tstep;
+  uint32_t health, pad;
+  double mass;
+};
+
+struct Layout3 {
+  int pitch = 0;
+  size_t desc = 0, hdr = 0, f0 = 0, f1 = 0, nodew = 0, mask = 0, partials = 0, stage = 0, total = 0;
+  bool solids = false;
+};
+
+Layout3 layout3(const lb3_domain_desc *d) {
+  Layout3 L;
+  L.pitch = (d->nx + 63) / 64 * 64;
+  const size_t nodes = (size_t)d->nz * d->ny * L.pitch;
+  const size_t fbytes = 19 * nodes * (d->storage == LB_F64 ? 8 : 4);
+  L.solids = d->obstacles || d->wall_x || d->wall_y || d->wall_z;
+  size_t o = 0;
+  L.desc = o; o += al256(sizeof(Dom3));
+  L.hdr = o; o += al256(sizeof(Header3));
+  L.f0 = o; o += al256(fbytes);
+  L.f1 = o; o += al256(fbytes);
+  L.nodew = o; if (L.solids) o += al256(nodes * 4);
+  L.mask = o; if (L.solids) o += al256(nodes);
+  L.partials = o; o += al256((size_t)d->nz * 8);
+  L.stage = o; o += al256((size_t)19 * BAND * 8);
+  L.total = o;
+  return L;
+}
+
+lb_status validate3(const lb3_domain_desc *d) {
+  if (!d) return fail3(LB_EINVAL, "desc is null");
+  if (d->abi_version != LB_ABI_VERSION) return fail3(LB_EINVAL, "abi_version mismatch");
+  if (d->nx < 3 || d->ny < 3 || d->nz < 3 || d->nx > 4096 || d->ny > 4096 || d->nz > 4096)
+    return fail3(LB_EINVAL, "nx, ny, nz must be in [3, 4096]");
+  if (d->storage != LB_F64 && d->storage != LB_F32)
+    return fail3(LB_EINVAL, "storage must be LB_F64 or LB_F32");
+  if (!(d->tau > 0.5)) return fail3(LB_EINVAL, "tau must be > 1/2");
+  if (!(d->rho0 > 0.0) || !std::isfinite(d->rho0)) return fail3(LB_EINVAL, "rho0 must be > 0");
+  if (!std::isfinite(d->gx) || !std::isfinite(d->gy) || !std::isfinite(d->gz))
+    return fail3(LB_EINVAL, "g not finite");
+  if (d->init_kind != LB_INIT_REST && d->init_kind != LB_INIT_FIELDS)
+    return fail3(LB_EINVAL, "bad init_kind");
+  if (d->init_kind == LB_INIT_FIELDS && (!d->init_rho || !d->init_ux || !d->init_uy || !d->init_uz))
+    return fail3(LB_EINVAL, "LB_INIT_FIELDS needs init_rho, init_ux, init_uy, init_uz");
+  return LB_OK;
+}
+
+unsigned blocks_of(long long n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+struct lb3_domain {
+  lb3_domain_desc desc{};
+  Layout3 L;
+  char *ws = nullptr;
+  hipStream_t stream = nullptr;
+  Dom3 hd{};
+  int64_t t = 0;
+  std::vector<uint8_t> host_mask;  // [nz][ny][pitch]: walls and obstacles
+  Dom3 *ddesc() const { return (Dom3 *)(ws + L.desc); }
+  Header3 *dhdr() const { return (Header3 *)(ws + L.hdr); }
+  long long nodes() const { return (long long)desc.nx * desc.ny * desc.nz; }
+};
+
+namespace {
+
+lb_status check_health3(lb3_domain *d) {
+  uint32_t h = 0;
+  HIPCHK3(hipMemcpyAsync(&h, &d->dhdr()->health, sizeof(h), hipMemcpyDeviceToHost, d->stream));
+  HIPCHK3(hipStreamSynchronize(d->stream));
+  if (h) return fail3(LB_EUNSTABLE, "device latched: non-finite density");
+  return LB_OK;
+}
+
+// mask of walls and obstacles to the device, and the node words from it
+lb_status upload_solids(lb3_domain *d) {
+  HIPCHK3(hipMemcpyAsync(d->ws + d->L.mask, d->host_mask.data(), d->host_mask.size(),
+                         hipMemcpyHostToDevice, d->stream));
+  hipLaunchKernelGGL(k_words3, dim3(blocks_of(d->nodes())), dim3(256), 0, d->stream, d->ddesc(),
+                     (const uint8_t *)(d->ws + d->L.mask));
+  HIPCHK3(hipGetLastError());
+  HIPCHK3(hipStreamSynchronize(d->stream));
+  return LB_OK;
+}
+
+// initial state from host fields (null: rest), band by band through the
+// staging area
+lb_status init3(lb3_domain *d, const double *rho, const double *ux, const double *uy,
+                const double *uz) {
+  const long long n = d->nodes();
+  double *st = (double *)(d->ws + d->L.stage);
+  for (long long n0 = 0; n0 < n; n0 += BAND) {
+    const long long cnt = std::min(BAND, n - n0);
+    const double *a[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (rho) {
+      const double *h[4] = {rho, ux, uy, uz};
+      for (int k = 0; k < 4; ++k) {
+        HIPCHK3(hipMemcpyAsync(st + k * BAND, h[k] + n0, cnt * 8, hipMemcpyHostToDevice, d->stream));
+        a[k] = st + k * BAND;
+      }
+    }
+    if (d->desc.storage == LB_F64)
+      hipLaunchKernelGGL(k_init3<0>, dim3(blocks_of(cnt)), dim3(256), 0, d->stream, d->ddesc(), a[0],
+                         a[1], a[2], a[3], n0, cnt);
+    else
+      hipLaunchKernelGGL(k_init3<1>, dim3(blocks_of(cnt)), dim3(256), 0, d->stream, d->ddesc(), a[0],
+                         a[1], a[2], a[3], n0, cnt);
+    HIPCHK3(hipGetLastError());
+    HIPCHK3(hipStreamSynchronize(d->stream));
+  }
+  return LB_OK;
+}
+
+lb_status push_desc3(lb3_domain *d) {
+  HIPCHK3(hipMemcpyAsync(d->ddesc(), &d->hd, sizeof(Dom3), hipMemcpyHostToDevice, d->stream));
+  HIPCHK3(hipStreamSynchronize(d->stream));
+  return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb3_workspace_bytes(const lb3_domain_desc *desc, size_t *bytes) {
+  if (!bytes) return fail3(LB_EINVAL, "bytes is null");
+  lb_status s = validate3(desc);
+  if (s != LB_OK) return s;
+  *bytes = layout3(desc).total;
+  return LB_OK;
+}
+
+lb_status lb3_create_domain(const lb3_domain_desc *desc, void *dev_workspace, size_t bytes,
+                            void *hip_stream, lb3_domain **out) {
+  if (!out) return fail3(LB_EINVAL, "out is null");
+  *out = nullptr;
+  lb_status s = validate3(desc);
+  if (s != LB_OK) return s;
+  if (!dev_workspace || ((uintptr_t)dev_workspace & 255))
+    return fail3(LB_EINVAL, "workspace must be non-null and 256-byte aligned");
+  const Layout3 L = layout3(desc);
+  if (bytes < L.total) return fail3(LB_ENOMEM, "workspace smaller than lb3_workspace_bytes");
+  lb3_domain *d = new lb3_domain();
+  d->desc = *desc;
+  d->desc.init_rho = d->desc.init_ux = d->desc.init_uy = d->desc.init_uz = nullptr;
+  d->L = L;
+  d->ws = (char *)dev_workspace;
+  d->stream = (hipStream_t)hip_stream;
+  Dom3 &h = d->hd;
+  h.f[0] = d->ws + L.f0;
+  h.f[1] = d->ws + L.f1;
+  h.nodew = L.solids ? (uint32_t *)(d->ws + L.nodew) : nullptr;
+  h.tstep = &d->dhdr()->tstep;
+  h.health = &d->dhdr()->health;
+  h.partials = (double *)(d->ws + L.partials);
+  h.mass = &d->dhdr()->mass;
+  h.nx = desc->nx;
+  h.ny = desc->ny;
+  h.nz = desc->nz;
+  h.pitch = L.pitch;
+  h.storage = desc->storage == LB_F64 ? 0 : 1;
+  h.tiles_x = (desc->nx + 63) / 64;
+  h.tiles_y = (desc->ny + 3) / 4;
+  h.rho0 = desc->rho0;
+  h.tau = desc->tau;
+  h.omega = 1.0 / desc->tau;
+  h.gx = desc->gx;
+  h.gy = desc->gy;
+  h.gz = desc->gz;
+  h.rho0_f = (float)h.rho0;
+  h.tau_f = (float)h.tau;
+  h.omega_f = (float)h.omega;
+  h.gx_f = (float)h.gx;
+  h.gy_f = (float)h.gy;
+  h.gz_f = (float)h.gz;
+  auto bail = [&](lb_status st) {
+    delete d;
+    return st;
+  };
+  Header3 zero{};
+  if (hipMemcpyAsync(d->dhdr(), &zero, sizeof(zero), hipMemcpyHostToDevice, d->stream) != hipSuccess)
+    return bail(fail3(LB_EHIP, "header upload failed"));
+  if ((s = push_desc3(d)) != LB_OK) return bail(s);
+  if (L.solids) {
+    d->host_mask.assign((size_t)desc->nz * desc->ny * L.pitch, 0);
+    for (int z = 0; z < desc->nz; ++z)
+      for (int y = 0; y < desc->ny; ++y)
+        for (int x = 0; x < desc->nx; ++x) {
+          const bool wall = (desc->wall_x && (x == 0 || x == desc->nx - 1)) ||
+                            (desc->wall_y && (y == 0 || y == desc->ny - 1)) ||
+                            (desc->wall_z && (z == 0 || z == desc->nz - 1));
+          d->host_mask[((size_t)z * desc->ny + y) * L.pitch + x] = wall ? 1 : 0;
+        }
+    if ((s = upload_solids(d)) != LB_OK) return bail(s);
+  }
+  if ((s = init3(d, desc->init_kind == LB_INIT_FIELDS ? desc->init_rho : nullptr, desc->init_ux,
+                 desc->init_uy, desc->init_uz)) != LB_OK)
+    return bail(s);
+  *out = d;
+  return LB_OK;
+}
+
+lb_status lb3_set_obstacles(lb3_domain *d, const uint8_t *mask, size_t n) {
+  if (!d || !mask) return fail3(LB_EINVAL, "null argument");
+  if (!d->desc.obstacles) return fail3(LB_ESTATE, "domain was created without obstacles");
+  if (n != (size_t)d->nodes()) return fail3(LB_EINVAL, "mask size must be nx*ny*nz");
+  const lb3_domain_desc &c = d->desc;
+  const int pitch = d->L.pitch;
+  for (int z = 0; z < c.nz; ++z)
+    for (int y = 0; y < c.ny; ++y)
+      for (int x = 0; x < c.nx; ++x) {
+        const bool wall = (c.wall_x && (x == 0 || x == c.nx - 1)) ||
+                          (c.wall_y && (y == 0 || y == c.ny - 1)) ||
+                          (c.wall_z && (z == 0 || z == c.nz - 1));
+        d->host_mask[((size_t)z * c.ny + y) * pitch + x] =
+            (wall || mask[((size_t)z * c.ny + y) * c.nx + x]) ? 1 : 0;
+      }
+  lb_status s = upload_solids(d);
+  if (s != LB_OK) return s;
+  // solid nodes hold zero deviations in the current state
+  return LB_OK;
+}
+
+lb_status lb3_step(lb3_domain *d, int64_t nsteps) {
+  if (!d) return fail3(LB_EINVAL, "null domain");
+  if (nsteps < 0) return fail3(LB_EINVAL, "nsteps < 0");
+  const unsigned blocks = (unsigned)(d->hd.tiles_x * d->hd.tiles_y * d->desc.nz);
+  for (int64_t k0 = 0; k0 < nsteps; k0 += 1024) {
+    const int c = (int)std::min<int64_t>(1024, nsteps - k0);
+    for (int k = 0; k < c; ++k) {
+      if (d->desc.storage == LB_F64)
+        hipLaunchKernelGGL(k_sweep3<0>, dim3(blocks), dim3(256), 0, d->stream, d->ddesc(), k);
+      else
+        hipLaunchKernelGGL(k_sweep3<1>, dim3(blocks), dim3(256), 0, d->stream, d->ddesc(), k);
+    }
+    hipLaunchKernelGGL(k_advance3, dim3(1), dim3(1), 0, d->stream, d->ddesc(), c);
+    HIPCHK3(hipGetLastError());
+  }
+  d->t += nsteps;
+  return LB_OK;
+}
+
+lb_status lb3_moments(lb3_domain *d, double *rho, double *ux, double *uy, double *uz) {
+  if (!d || !rho || !ux || !uy || !uz) return fail3(LB_EINVAL, "null argument");
+  const long long n = d->nodes();
+  double *st = (double *)(d->ws + d->L.stage);
+  double *h[4] = {rho, ux, uy, uz};
+  for (long long n0 = 0; n0 < n; n0 += BAND) {
+    const long long cnt = std::min(BAND, n - n0);
+    if (d->desc.storage == LB_F64)
+      hipLaunchKernelGGL(k_moments3<0>, dim3(blocks_of(cnt)), dim3(256), 0, d->stream, d->ddesc(),
+                         st, n0, cnt);
+    else
+      hipLaunchKernelGGL(k_moments3<1>, dim3(blocks_of(cnt)), dim3(256), 0, d->stream, d->ddesc(),
+                         st, n0, cnt);
+    HIPCHK3(hipGetLastError());
+    for (int k = 0; k < 4; ++k)
+      HIPCHK3(hipMemcpyAsync(h[k] + n0, st + k * cnt, cnt * 8, hipMemcpyDeviceToHost, d->stream));
+    HIPCHK3(hipStreamSynchronize(d->stream));
+  }
+  return check_health3(d);
+}
+
+lb_status lb3_get_populations(lb3_domain *d, double *f) {
+  if (!d || !f) return fail3(LB_EINVAL, "null argument");
+  const long long n = d->nodes();
+  double *st = (double *)(d->ws + d->L.stage);
+  for (long long n0 = 0; n0 < n; n0 += BAND) {
+    const long long cnt = std::min(BAND, n - n0);
+    if (d->desc.storage == LB_F64)
+      hipLaunchKernelGGL(k_export3<0>, dim3(blocks_of(cnt)), dim3(256), 0, d->stream, d->ddesc(),
+                         st, n0, cnt);
+    else
+      hipLaunchKernelGGL(k_export3<1>, dim3(blocks_of(cnt)), dim3(256), 0, d->stream, d->ddesc(),
+                         st, n0, cnt);
+    HIPCHK3(hipGetLastError());
+    for (int i = 0; i < 19; ++i)
+      HIPCHK3(hipMemcpyAsync(f + (size_t)i * n + n0, st + (size_t)i * cnt, cnt * 8,
+                             hipMemcpyDeviceToHost, d->stream));
+    HIPCHK3(hipStreamSynchronize(d->stream));
+  }
+  return check_health3(d);
+}
+
+lb_status lb3_mass(lb3_domain *d, double *total) {
+  if (!d || !total) return fail3(LB_EINVAL, "null argument");
+  if (d->desc.storage == LB_F64)
+    hipLaunchKernelGGL(k_mass3_partial<0>, dim3(d->desc.nz), dim3(256), 0, d->stream, d->ddesc());
+  else
+    hipLaunchKernelGGL(k_mass3_partial<1>, dim3(d->desc.nz), dim3(256), 0, d->stream, d->ddesc());
+  hipLaunchKernelGGL(k_mass3_final, dim3(1), dim3(64), 0, d->stream, d->ddesc());
+  HIPCHK3(hipGetLastError());
+  HIPCHK3(hipMemcpyAsync(total, &d->dhdr()->mass, 8, hipMemcpyDeviceToHost, d->stream));
+  HIPCHK3(hipStreamSynchronize(d->stream));
+  return check_health3(d);
+}
+
+lb_status lb3_time(lb3_domain *d, int64_t *t) {
+  if (!d || !t) return fail3(LB_EINVAL, "null argument");
+  *t = d->t;
+  return LB_OK;
+}
+
+lb_status lb3_destroy_domain(lb3_domain *d) {
+  if (!d) return fail3(LB_EINVAL, "null domain");
+  (void)hipStreamSynchronize(d->stream);
+  delete d;
+  return LB_OK;
+}
+
+}  // extern "C"

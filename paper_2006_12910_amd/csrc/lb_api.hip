@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "lb.h"
@@ -187,6 +188,12 @@ struct GraphCache {
 
 }  // namespace
 
+namespace lbk {
+// the error record of the D3Q19 entry points (lb3_api.hip): the same
+// thread-local text lb_last_error returns
+lb_status lb_fail(lb_status s, const std::string &msg) { return fail(s, msg); }
+}  // namespace lbk
+
 struct lb_domain {
   lb_domain_desc desc{};
   Layout L;
@@ -231,6 +238,9 @@ struct lb_batch {
   KernelSet ks{};
   int total_tiles = 0, total_tiles2 = 0, total_mass_blocks = 0, nitems = 0;
   bool two_step = false;  // every domain takes the two-step sweep
+  int rows2 = 0;          // its tile height, shared by the launch
+  std::vector<DevDomain> hdescs;  // host copies of the descriptors
+  std::vector<int> hprefix;       // and of the prefix tables
   size_t off_desc = 0, off_prefix = 0, off_items = 0, bytes = 0;
   bool use_graph = true;
   int chunk = 256;
@@ -245,6 +255,28 @@ struct lb_batch {
 };
 
 namespace {
+
+// Two-step sweep tiles: TS_COLS columns by `rows` rows.
+void set_two_step_rows(DevDomain &hd, int rows) {
+  hd.rows2 = rows;
+  hd.tiles2_x = (hd.nx + TS_COLS - 1) / TS_COLS;
+  hd.tiles2_y = (hd.ny + rows - 1) / rows;
+}
+bool valid_two_step_rows(int storage, int64_t rows) {
+  for (int k = 0; k < 3; ++k)
+    if (rows == two_step_rows_of(storage, k)) return true;
+  return false;
+}
+
+// Tile heights the autotuner chose, per (storage, label plane, stochastic
+// rounding, size class = floor(log2(sites))), for this process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_rows2_cache;
+std::tuple<int, int, int, int> tune_key(int storage, int feat, long long sites) {
+  int cls = 0;
+  while ((1LL << (cls + 1)) <= sites) ++cls;
+  return {storage, (feat & F_LABELS) ? 1 : 0, (feat & F_STOCH) ? 1 : 0, cls};
+}
 
 // A tile is tile_w threads (nodes) along x by (256 / tile_w) * rpt rows.
 void set_tiles(DevDomain &hd, int tile_w, int rpt) {
@@ -288,6 +320,7 @@ struct StepPlan {
   const PItem *items;
   int nitems;
   bool two;  // two-step sweep (no particles, so no pre/post passes)
+  int rows2 = 0;  // its tile height (every domain of the launch shares it)
   // overlapped particle steps (one domain): the particle chain on `side`
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -333,8 +366,8 @@ void record_steps(const StepPlan &p, int n, hipStream_t s) {
   int k = 0;
   if (p.two) {
     for (; k + 4 <= n; k += 4) {
-      p.ks->sweep2(p.doms, p.prefix2, p.ndom, k, 0, p.blocks2, s);
-      p.ks->sweep2(p.doms, p.prefix2, p.ndom, k + 2, 1, p.blocks2, s);
+      p.ks->sweep2(p.doms, p.prefix2, p.ndom, k, 0, p.blocks2, p.rows2, s);
+      p.ks->sweep2(p.doms, p.prefix2, p.ndom, k + 2, 1, p.blocks2, p.rows2, s);
     }
   }
   if (p.side != nullptr && p.nitems > 0 && n > 0) {
@@ -453,6 +486,24 @@ lb_status upload_labels(lb_domain *d) {
   return refresh_mirrors(d);
 }
 
+// ms per step of `n` steps run by step(n) on stream s, after one untimed
+// call of the same length (which also captures its graphs).
+template <class F> lb_status time_steps(F &&step, hipStream_t s, int n, double *ms_per_step) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  lb_status st = step(n);
+  if (st == LB_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(LB_EHIP, "event");
+  if (st == LB_OK) st = step(n);
+  if (st == LB_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+    st = fail(LB_EHIP, "event");
+  float ms = 0.f;
+  if (st == LB_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_per_step = ms / n;
+  return st;
+}
 }  // namespace
 
 extern "C" {
@@ -539,8 +590,7 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   h.feat = feat;
   set_tiles(h, default_tile_w(desc->nx), desc->storage >= LB_F16_DELTA ? 4 : 2);
   h.stream_stores = sweep_working_set(h) >= STREAM_STORE_MIN_BYTES;
-  h.tiles2_x = (h.nx + TS_COLS - 1) / TS_COLS;
-  h.tiles2_y = (h.ny + two_step_rows(h.storage) - 1) / two_step_rows(h.storage);
+  set_two_step_rows(h, two_step_rows(h.storage));
   h.rho0 = desc->rho0;
   h.tau = desc->power_law ? desc->tau_min : desc->tau;
   h.omega = 1.0 / h.tau;
@@ -831,6 +881,7 @@ lb_status lb_step(lb_domain *d, int64_t nsteps) {
   if (nsteps > 0) {
     StepPlan p{&d->ks, d->ddesc(), d->dprefix(), d->dprefix2(), 1, d->ntiles(),
                d->ntiles2(), d->ditems(), d->np, two_step_ok(d)};
+    p.rows2 = d->hd.rows2;
     if (d->overlap && d->np > 0 && !p.two) {
       if (!d->side) {
         HIPCHK(hipStreamCreateWithFlags(&d->side, hipStreamNonBlocking));
@@ -1037,7 +1088,8 @@ lb_status lb_set_populations(lb_domain *d, const double *hf) {
 lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
   if (!d) return fail(LB_EINVAL, "null domain");
   if (d->in_batches && (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD ||
-                        key == LB_OPT_FORCE_AVERAGE || key == LB_OPT_TWO_STEP))
+                        key == LB_OPT_FORCE_AVERAGE || key == LB_OPT_TWO_STEP ||
+                        key == LB_OPT_TWO_STEP_ROWS))
     return fail(LB_ESTATE, "tile, force and two-step options are fixed while the domain is in a batch");
   switch (key) {
     case LB_OPT_USE_GRAPH: d->use_graph = value != 0; break;
@@ -1065,6 +1117,11 @@ lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
       if (value != 0 && value != 1) return fail(LB_EINVAL, "overlap is 0 or 1");
       d->overlap = value != 0;
       break;
+    case LB_OPT_TWO_STEP_ROWS:
+      if (!valid_two_step_rows(d->desc.storage, value))
+        return fail(LB_EINVAL, "two-step tile rows: not an instantiated height for this storage");
+      set_two_step_rows(d->hd, (int)value);
+      break;
     case LB_OPT_MASS_INTERVAL:
       if (value < 1) return fail(LB_EINVAL, "mass check interval must be >= 1");
       d->mass_interval = value;
@@ -1072,7 +1129,8 @@ lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
     default: return fail(LB_EINVAL, "unknown option");
   }
   d->graphs.clear();
-  if (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD || key == LB_OPT_FORCE_AVERAGE)
+  if (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD || key == LB_OPT_FORCE_AVERAGE ||
+      key == LB_OPT_TWO_STEP_ROWS)
     return push_desc(d);
   return LB_OK;
 }
@@ -1087,6 +1145,7 @@ lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value) {
     case LB_OPT_FORCE_AVERAGE: *value = (d->hd.feat & F_FAVG) ? 1 : 0; return LB_OK;
     case LB_OPT_TWO_STEP: *value = d->two_step ? 1 : 0; return LB_OK;
     case LB_OPT_OVERLAP: *value = d->overlap ? 1 : 0; return LB_OK;
+    case LB_OPT_TWO_STEP_ROWS: *value = d->hd.rows2; return LB_OK;
     case LB_OPT_MASS_INTERVAL: *value = d->mass_interval; return LB_OK;
   }
   return fail(LB_EINVAL, "unknown option");
@@ -1134,8 +1193,71 @@ lb_status lb_autotune(lb_domain *d, int32_t steps, double *best_ms) {
   if (s != LB_OK) return s;
   if ((s = lb_set_option(d, LB_OPT_TILE_WIDTH, bw)) != LB_OK) return s;
   if ((s = lb_set_option(d, LB_OPT_ROWS_PER_THREAD, br)) != LB_OK) return s;
+  if (two_step_ok(d)) {
+    // the two-step sweep's tile height: cached for the class, else timed
+    const auto key = tune_key(d->desc.storage, d->feat, (long long)d->desc.nx * d->desc.ny);
+    int rows = 0;
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      auto it = g_rows2_cache.find(key);
+      if (it != g_rows2_cache.end()) rows = it->second;
+    }
+    if (rows == 0) {
+      double best2 = 1e300;
+      const int n4 = std::max(4, (steps + 3) / 4 * 4);
+      for (int k = 0; k < 3 && s == LB_OK; ++k) {
+        const int h = two_step_rows_of(d->desc.storage, k);
+        double ms = 0.0;
+        if ((s = lb_set_option(d, LB_OPT_TWO_STEP_ROWS, h)) != LB_OK) break;
+        if ((s = time_steps([&](int64_t n) { return lb_step(d, n); }, d->stream, n4, &ms)) != LB_OK)
+          break;
+        if (ms < best2) { best2 = ms; rows = h; }
+      }
+      if (s != LB_OK) return s;
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      g_rows2_cache[key] = rows;
+      best = std::min(best, best2);
+    }
+    if ((s = lb_set_option(d, LB_OPT_TWO_STEP_ROWS, rows)) != LB_OK) return s;
+  }
   if (best_ms) *best_ms = best;
   return check_health(d);
+}
+
+lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms) {
+  if (!b || steps < 1) return fail(LB_EINVAL, "bad argument");
+  if (best_ms) *best_ms = 0.0;
+  if (!b->two_step) return LB_OK;  // single steps: the members' own tiles
+  long long sites = 0;
+  int feat = 0;
+  for (auto *d : b->doms) {
+    sites += (long long)d->desc.nx * d->desc.ny;
+    feat |= d->feat;
+  }
+  const auto key = tune_key(b->doms[0]->desc.storage, feat, sites);
+  int rows = 0;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_rows2_cache.find(key);
+    if (it != g_rows2_cache.end()) rows = it->second;
+  }
+  lb_status s = LB_OK;
+  if (rows == 0) {
+    double best = 1e300;
+    const int n4 = std::max(4, (steps + 3) / 4 * 4);
+    for (int k = 0; k < 3; ++k) {
+      const int h = two_step_rows_of(b->doms[0]->desc.storage, k);
+      double ms = 0.0;
+      if ((s = lb_batch_set_option(b, LB_OPT_TWO_STEP_ROWS, h)) != LB_OK) return s;
+      if ((s = time_steps([&](int64_t n) { return lb_batch_step(b, n); }, b->stream, n4, &ms)) != LB_OK)
+        return s;
+      if (ms < best) { best = ms; rows = h; }
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_rows2_cache[key] = rows;
+    if (best_ms) *best_ms = best;
+  }
+  return lb_batch_set_option(b, LB_OPT_TWO_STEP_ROWS, rows);
 }
 
 lb_status lb_destroy_domain(lb_domain *d) {
@@ -1218,6 +1340,15 @@ lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_worksp
     for (int q = 0; q < domains[i]->np; ++q) items.push_back(PItem{i, q});
     two = two && two_step_ok(domains[i]);
   }
+  // one tile height per launch: the members' own if they agree, else the
+  // storage format's default (the batch's descriptor copies carry it)
+  int rows2 = domains[0]->hd.rows2;
+  for (int i = 1; i < n; ++i)
+    if (domains[i]->hd.rows2 != rows2) rows2 = two_step_rows(domains[0]->desc.storage);
+  for (int i = 0; i < n; ++i) set_two_step_rows(descs[i], rows2);
+  for (int i = 0; i < n; ++i)
+    prefix[n + 2 + i] = prefix[n + 1 + i] + descs[i].tiles2_x * descs[i].tiles2_y;
+  b->rows2 = rows2;
   b->two_step = two;
   b->total_tiles2 = prefix[2 * n + 1];
   b->total_mass_blocks = prefix[3 * n + 2];
@@ -1226,6 +1357,8 @@ lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_worksp
   for (int i = 0; i < n; ++i) descs[i].stream_stores = working_set >= STREAM_STORE_MIN_BYTES;
   b->total_tiles = prefix[n];
   b->nitems = (int)items.size();
+  b->hdescs = descs;
+  b->hprefix = prefix;
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
     delete b;
     return fail(LB_EHIP, "hipStreamCreateWithFlags failed");
@@ -1251,8 +1384,9 @@ lb_status lb_batch_step(lb_batch *b, int64_t nsteps) {
   if (!b) return fail(LB_EINVAL, "null batch");
   if (nsteps < 0) return fail(LB_EINVAL, "nsteps < 0");
   if (nsteps > 0) {
-    const StepPlan p{&b->ks, b->ddesc(), b->dprefix(), b->dprefix2(), (int)b->doms.size(),
-                     b->total_tiles, b->total_tiles2, b->ditems(), b->nitems, b->two_step};
+    StepPlan p{&b->ks, b->ddesc(), b->dprefix(), b->dprefix2(), (int)b->doms.size(),
+               b->total_tiles, b->total_tiles2, b->ditems(), b->nitems, b->two_step};
+    p.rows2 = b->rows2;
     lb_status s = run_steps(b->graphs, b->use_graph, b->chunk, b->stream, b->cap, p, nsteps);
     if (s != LB_OK) return s;
   }
@@ -1280,10 +1414,38 @@ lb_status lb_batch_set_option(lb_batch *b, int32_t key, int64_t value) {
       if (value < 1) return fail(LB_EINVAL, "mass check interval must be >= 1");
       b->mass_interval = value;
       return LB_OK;
+    case LB_OPT_TWO_STEP_ROWS: {
+      if (!valid_two_step_rows(b->doms[0]->desc.storage, value))
+        return fail(LB_EINVAL, "two-step tile rows: not an instantiated height for this storage");
+      const int n = (int)b->doms.size();
+      b->rows2 = (int)value;
+      for (int i = 0; i < n; ++i) {
+        set_two_step_rows(b->hdescs[i], b->rows2);
+        b->hprefix[n + 2 + i] = b->hprefix[n + 1 + i] + b->hdescs[i].tiles2_x * b->hdescs[i].tiles2_y;
+      }
+      b->total_tiles2 = b->hprefix[2 * n + 1];
+      HIPCHK(hipMemcpyAsync(b->ddesc(), b->hdescs.data(), n * sizeof(DevDomain),
+                            hipMemcpyHostToDevice, b->stream));
+      HIPCHK(hipMemcpyAsync(b->dprefix(), b->hprefix.data(), b->hprefix.size() * sizeof(int),
+                            hipMemcpyHostToDevice, b->stream));
+      HIPCHK(hipStreamSynchronize(b->stream));
+      break;
+    }
     default: return fail(LB_EINVAL, "option not available on a batch");
   }
   b->graphs.clear();
   return LB_OK;
+}
+
+lb_status lb_batch_get_option(lb_batch *b, int32_t key, int64_t *value) {
+  if (!b || !value) return fail(LB_EINVAL, "null argument");
+  switch (key) {
+    case LB_OPT_USE_GRAPH: *value = b->use_graph ? 1 : 0; return LB_OK;
+    case LB_OPT_GRAPH_CHUNK: *value = b->chunk; return LB_OK;
+    case LB_OPT_MASS_INTERVAL: *value = b->mass_interval; return LB_OK;
+    case LB_OPT_TWO_STEP_ROWS: *value = b->rows2; return LB_OK;
+  }
+  return fail(LB_EINVAL, "option not available on a batch");
 }
 
 lb_status lb_batch_destroy(lb_batch *b) {

@@ -59,15 +59,17 @@ enum : int {
 enum : int { PL_GENERIC = 0, PL_HALF = 1, PL_3Q = 2, PL_3H = 3 };
 
 // Tiles of the two-step sweep (k_sweep2): TS_COLS output columns (the 64
-// lanes of a wave less a one-node rim) by two_step_rows output rows (its LDS
-// holds rows + 2 rows of 64 columns x 9 values).  Measured on the 185 M-site
+// lanes of a wave less a one-node rim) by H output rows (its LDS holds H + 2
+// rows of 64 columns x 9 values).  Three tile heights are instantiated per
+// storage format; the default is the middle one (measured on the 185 M-site
 // stress batch: 16-bit rows 13 / 14 / 15 / 16 took 1.059 / 1.037 / 1.078 /
 // 1.056 ms per step, FP32 rows 9 / 10 / 11 / 12 1.625 / 1.603 / 1.648 /
-// 1.644 ms (one run).
+// 1.644 ms, one run), and the autotuner picks among the three.
 constexpr int TS_COLS = 62;
-constexpr int two_step_rows(int storage) {
-  return storage == ST_F64 ? 6 : (storage == ST_F32 ? 10 : 14);
+constexpr int two_step_rows_of(int storage, int k) {  // k = 0, 1, 2
+  return storage == ST_F64 ? 4 + 2 * k : (storage == ST_F32 ? 6 + 4 * k : 10 + 4 * k);
 }
+constexpr int two_step_rows(int storage) { return two_step_rows_of(storage, 1); }
 
 // Labels: 0 fluid, 1 solid, 2 + p inside particle p.
 constexpr uint8_t LBL_FLUID = 0, LBL_SOLID = 1, LBL_PART0 = 2;
@@ -117,6 +119,7 @@ struct alignas(256) DevDomain {
   int np;              // particles
   int tile_w, rows_per_thread, tiles_x, tiles_y;
   int tiles2_x, tiles2_y;  // tiles of the two-step sweep (k_sweep2)
+  int rows2;               // their output rows (one of two_step_rows_of)
   uint32_t key0, key1; // noise generator key
   int storage, feat;
   int stream_stores;   // 1: the sweep's stores bypass the caches (see k_sweep)

@@ -32,7 +32,7 @@ __device__ __forceinline__ uint32_t sel_keep(uint32_t a, uint32_t b, uint32_t m,
   return __builtin_amdgcn_bitop3_b32(m, b, a, 0xCA) & keep;
 }
 
-template <int ST, int FEAT>
+template <int ST, int FEAT, int H>
 __global__ __launch_bounds__(256) void k_sweep2(const DevDomain *__restrict__ doms,
                                                 const int *__restrict__ prefix, int ndom,
                                                 int kstep, int which) {
@@ -40,7 +40,6 @@ __global__ __launch_bounds__(256) void k_sweep2(const DevDomain *__restrict__ do
   using T = typename S::T;
   using R = CompT<ST, 0>;
   constexpr bool LABELS = (FEAT & F_LABELS) != 0;
-  constexpr int H = two_step_rows(ST);
   constexpr int RS = H + 2;  // rows of the first step
   constexpr uint32_t B = sizeof(T);
   __shared__ T lds[9][RS][64];

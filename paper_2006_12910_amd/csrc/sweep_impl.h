@@ -205,7 +205,11 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
   eq[6] = cmm + lm;
   eq[8] = cmm - lm;
 
-  // thermal noise zeta_i of Eqs. NP1-NP2 (zero mass and momentum)
+  // thermal noise zeta_i of Eqs. NP1-NP2 (zero mass and momentum):
+  // zeta_i = amp w_i z_i, z_i = sum_k e_ki t_k over the Table t1 basis
+  // polynomials of the six non-conserved modes, t_k = Theta_k / sqrt(w_k).
+  // Opposite directions share the even part of z and take +- the odd part;
+  // add(i, c, z) receives the coefficient amp w_i (stored scaling) and z_i.
   auto noise = [&](auto &&add) {
     float th[6];
     noise_normals(D.key0, D.key1, node, step, th);
@@ -214,14 +218,23 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
     const R t6 = R(th[3]) * R(1.2247448713915890491), t7 = R(th[4]) * R(1.2247448713915890491);
     const R t8 = R(th[5]) * R(0.25);
     const R amp = sqrt(rho * par<R>(D.kT, D.kT_f) * om * (R(2) - om) * R(3));
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const R z = R(basis_poly(3, i)) * t3 + R(basis_poly(4, i)) * t4 + R(basis_poly(5, i)) * t5 +
-                  R(basis_poly(6, i)) * t6 + R(basis_poly(7, i)) * t7 + R(basis_poly(8, i)) * t8;
-      // w_i in exact ratios 4 : 1 : 1/4, times the stored scaling
-      const R wi = i == 0 ? K0 * (R(4) * W1) : (i <= 4 ? K1 * W1 : K5 * W5);
-      add(i, amp * wi * z);
-    }
+    // e_k of rest: (-2, 0, 0, 0, 0, 2); axis (1, 0): (1, 1, 0, -1, 0, -4);
+    // diagonal (1, 1): (4, 0, 1, 2, 2, 8), the others by symmetry
+    const R a0 = fmar(R(-4), t8, t3);      // t3 - 4 t8
+    const R ax = a0 + t4, ay = a0 - t4;     // even parts, x and y axis
+    const R d0 = fmar(R(4), t3, R(8) * t8);  // 4 t3 + 8 t8
+    const R dp = d0 + t5, dm = d0 - t5;     // even parts, diagonals 5/7 and 6/8
+    const R op = R(2) * (t6 + t7), om2 = R(2) * (t7 - t6);
+    const R c0 = amp * (K0 * (R(4) * W1)), c1 = amp * (K1 * W1), c5 = amp * (K5 * W5);
+    add(0, c0, R(2) * (t8 - t3));
+    add(1, c1, ax - t6);
+    add(3, c1, ax + t6);
+    add(2, c1, ay - t7);
+    add(4, c1, ay + t7);
+    add(5, c5, dp + op);
+    add(7, c5, dp - op);
+    add(6, c5, dm + om2);
+    add(8, c5, dm - om2);
   };
 
   if constexpr (ST == ST_F32 && sizeof(R) == 4) {
@@ -241,7 +254,8 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
     R inc[9];
 #pragma unroll
     for (int i = 1; i < 9; ++i) inc[i] = om * (eq[i] - d[i]);
-    if constexpr ((FEAT & F_NOISE) != 0) noise([&](int i, R z) { if (i > 0) inc[i] += z; });
+    if constexpr ((FEAT & F_NOISE) != 0)
+      noise([&](int i, R c, R z) { if (i > 0) inc[i] = fmar(c, z, inc[i]); });
     const R sx = ((inc[1] - inc[3]) + (inc[5] - inc[6])) + (inc[8] - inc[7]);
     const R sy = ((inc[2] - inc[4]) + (inc[5] + inc[6])) - (inc[7] + inc[8]);
     const R hx = R(0.5) * fmar(rho, par<R>(D.gx, D.gx_f), -sx);
@@ -268,7 +282,7 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) d[i] = fmar(om, eq[i] - d[i], d[i]);
-    if constexpr ((FEAT & F_NOISE) != 0) noise([&](int i, R z) { d[i] += z; });
+    if constexpr ((FEAT & F_NOISE) != 0) noise([&](int i, R c, R z) { d[i] = fmar(c, z, d[i]); });
   }
 }
 

@@ -25,6 +25,7 @@ OPT_USE_GRAPH, OPT_TILE_WIDTH, OPT_ROWS_PER_THREAD, OPT_GRAPH_CHUNK, OPT_FORCE_A
 OPT_TWO_STEP = 6
 OPT_OVERLAP = 7
 OPT_MASS_INTERVAL = 8
+OPT_TWO_STEP_ROWS = 10
 ABI_VERSION = 1
 
 _BC = {"periodic": PERIODIC, "wall": WALL, "pressure": PRESSURE}
@@ -39,6 +40,9 @@ EXPORTED = [
     "lb_set_particle_state", "lb_set_option", "lb_get_option",
     "lb_destroy_domain", "lb_batch_workspace_bytes", "lb_batch_create", "lb_batch_step",
     "lb_batch_set_option", "lb_batch_destroy", "lb_noise_normals", "lb_autotune",
+    "lb_batch_autotune", "lb_batch_get_option",
+    "lb3_workspace_bytes", "lb3_create_domain", "lb3_set_obstacles", "lb3_step", "lb3_moments",
+    "lb3_get_populations", "lb3_mass", "lb3_time", "lb3_destroy_domain",
     "lb_status_string", "lb_last_error",
 ]
 
@@ -57,6 +61,18 @@ class DomainDesc(C.Structure):
         ("lj_rit", C.c_double), ("lj_floor", C.c_double),
         ("init_rho", C.POINTER(C.c_double)), ("init_ux", C.POINTER(C.c_double)),
         ("init_uy", C.POINTER(C.c_double)),
+    ]
+
+
+class Domain3Desc(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("wall_x", C.c_int32), ("wall_y", C.c_int32), ("wall_z", C.c_int32),
+        ("storage", C.c_int32), ("obstacles", C.c_int32), ("init_kind", C.c_int32),
+        ("rho0", C.c_double), ("tau", C.c_double),
+        ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double),
+        ("init_rho", C.POINTER(C.c_double)), ("init_ux", C.POINTER(C.c_double)),
+        ("init_uy", C.POINTER(C.c_double)), ("init_uz", C.POINTER(C.c_double)),
     ]
 
 
@@ -124,6 +140,17 @@ def library():
         "lb_batch_destroy": [vp],
         "lb_noise_normals": [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, vp, vp],
         "lb_autotune": [vp, st, dp],
+        "lb_batch_autotune": [vp, st, dp],
+        "lb_batch_get_option": [vp, st, P(C.c_int64)],
+        "lb3_workspace_bytes": [P(Domain3Desc), P(C.c_size_t)],
+        "lb3_create_domain": [P(Domain3Desc), vp, C.c_size_t, vp, P(vp)],
+        "lb3_set_obstacles": [vp, P(C.c_uint8), C.c_size_t],
+        "lb3_step": [vp, C.c_int64],
+        "lb3_moments": [vp, dp, dp, dp, dp],
+        "lb3_get_populations": [vp, dp],
+        "lb3_mass": [vp, dp],
+        "lb3_time": [vp, P(C.c_int64)],
+        "lb3_destroy_domain": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -380,6 +407,18 @@ class Batch:
     def set_option(self, key, value):
         _check(library().lb_batch_set_option(self._h, int(key), int(value)), "lb_batch_set_option")
 
+    def get_option(self, key):
+        v = C.c_int64()
+        _check(library().lb_batch_get_option(self._h, int(key), C.byref(v)), "lb_batch_get_option")
+        return v.value
+
+    def autotune(self, steps=8):
+        """lb_batch_autotune: the two-step tile height (0.0 when cached or
+        not applicable, else the best ms per step)."""
+        ms = C.c_double()
+        _check(library().lb_batch_autotune(self._h, int(steps), C.byref(ms)), "lb_batch_autotune")
+        return ms.value
+
     def close(self):
         if getattr(self, "_h", None):
             _check(library().lb_batch_destroy(self._h), "lb_batch_destroy")
@@ -400,3 +439,78 @@ def noise_normals(seed, domain_id, step, node0, count, device="cuda"):
                                       int(count), C.c_void_p(out.data_ptr()),
                                       _stream_ptr(None)), "lb_noise_normals")
     return out
+
+
+class Domain3:
+    """One D3Q19 domain on the GPU (lb3_create_domain ... lb3_destroy_domain).
+    Node arrays are [nz][ny][nx]; populations [19][nz][ny][nx]."""
+
+    def __init__(self, nx, ny, nz, *, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0),
+                 walls=(False, False, False), storage="f32", obstacles=None, init=None,
+                 device="cuda", stream=None):
+        lib = library()
+        d = Domain3Desc()
+        d.abi_version = ABI_VERSION
+        d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
+        d.wall_x, d.wall_y, d.wall_z = (int(bool(w)) for w in walls)
+        d.storage = {"f64": F64, "f32": F32}[storage]
+        d.obstacles = 1 if obstacles is not None else 0
+        d.rho0, d.tau = float(rho0), float(tau)
+        d.gx, d.gy, d.gz = (float(v) for v in g)
+        shape = (nz, ny, nx)
+        fields = None
+        if init is not None:
+            fields = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), shape))
+                      for a in init]
+            d.init_kind = INIT_FIELDS
+            d.init_rho, d.init_ux, d.init_uy, d.init_uz = (_dptr(a) for a in fields)
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        nbytes = C.c_size_t()
+        _check(lib.lb3_workspace_bytes(C.byref(d), C.byref(nbytes)), "lb3_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        _check(lib.lb3_create_domain(C.byref(d), C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                     _stream_ptr(stream), C.byref(h)), "lb3_create_domain")
+        self._h = h
+        del fields
+        if obstacles is not None:
+            m = np.ascontiguousarray(np.asarray(obstacles) != 0, dtype=np.uint8).reshape(shape)
+            _check(lib.lb3_set_obstacles(self._h, m.ctypes.data_as(C.POINTER(C.c_uint8)), m.size),
+                   "lb3_set_obstacles")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(library().lb3_destroy_domain(self._h), "lb3_destroy_domain")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        _check(library().lb3_step(self._h, int(n)), "lb3_step")
+        return self
+
+    def moments(self):
+        shape = (self.nz, self.ny, self.nx)
+        out = [np.empty(shape) for _ in range(4)]
+        _check(library().lb3_moments(self._h, *[_dptr(a) for a in out]), "lb3_moments")
+        return tuple(out)
+
+    def populations(self):
+        f = np.empty((19, self.nz, self.ny, self.nx))
+        _check(library().lb3_get_populations(self._h, _dptr(f)), "lb3_get_populations")
+        return f
+
+    def mass(self):
+        m = C.c_double()
+        _check(library().lb3_mass(self._h, C.byref(m)), "lb3_mass")
+        return m.value
+
+    @property
+    def time(self):
+        t = C.c_int64()
+        _check(library().lb3_time(self._h, C.byref(t)), "lb3_time")
+        return t.value

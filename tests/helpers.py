@@ -59,3 +59,15 @@ def random_fields(nx, ny, seed, du=0.03, drho=0.01):
     rng = np.random.default_rng(seed)
     return (1.0 + drho * rng.standard_normal((ny, nx)), du * rng.standard_normal((ny, nx)),
             du * rng.standard_normal((ny, nx)))
+
+
+def velocity_max_error(gpu, ora):
+    """Element-wise velocity error relative to the oracle's largest speed:
+    max_x |u_gpu - u_oracle| / max_x |u_oracle|.  A relative L2 over millions
+    of nodes can hide an error confined to a few nodes (near a particle, say);
+    this cannot."""
+    _, ug, vg = gpu.moments()
+    _, uo, vo = ora.moments()
+    d = np.sqrt((ug - uo) ** 2 + (vg - vo) ** 2).max()
+    s = np.sqrt(uo ** 2 + vo ** 2).max()
+    return d / (s if s > 0 else 1.0)

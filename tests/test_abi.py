@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_entry_points():
     src = open(os.path.join(ROOT, "include", "lb.h")).read()
-    return sorted(set(re.findall(r"^(?:lb_status|const char \*)\s*(lb_\w+)\(", src, re.M)))
+    return sorted(set(re.findall(r"^(?:lb_status|const char \*)\s*(lb3?_\w+)\(", src, re.M)))
 
 
 def test_header_declares_the_boundary():
@@ -98,3 +98,36 @@ def test_binding_constants_match_the_header():
     assert "LB_OPT_TWO_STEP" in consts
     for name, value in consts.items():
         assert getattr(lb, name[len("LB_"):]) == value, name
+
+
+def _desc3(**kw):
+    from paper_2006_12910_amd import lb
+    d = lb.Domain3Desc()
+    d.abi_version, d.nx, d.ny, d.nz, d.tau, d.rho0, d.storage = 1, 32, 16, 8, 0.8, 1.0, 1
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(tau=0.5), "tau"), (dict(nz=2), "nz"), (dict(abi_version=3), "abi"),
+    (dict(storage=2), "storage"), (dict(init_kind=1), "INIT_FIELDS"), (dict(rho0=0.0), "rho0"),
+])
+def test_d3q19_validation_errors(bad, msg):
+    from paper_2006_12910_amd import lb
+    lib = lb.library()
+    n = C.c_size_t()
+    assert lib.lb3_workspace_bytes(C.byref(_desc3(**bad)), C.byref(n)) == lb.LB_EINVAL
+    assert msg.lower() in lib.lb_last_error().decode().lower()
+
+
+def test_d3q19_workspace_covers_both_population_buffers():
+    from paper_2006_12910_amd import lb
+    lib = lb.library()
+    for storage, size in ((0, 8), (1, 4)):
+        n = C.c_size_t()
+        assert lib.lb3_workspace_bytes(C.byref(_desc3(storage=storage, nx=100, ny=30, nz=20)),
+                                       C.byref(n)) == 0
+        assert n.value >= 2 * 19 * 128 * 30 * 20 * size
+    assert lib.lb3_step(None, 1) == lb.LB_EINVAL
+    assert lib.lb3_destroy_domain(None) == lb.LB_EINVAL

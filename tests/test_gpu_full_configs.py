@@ -11,7 +11,7 @@ FP32 against FP64 runs of the same lattice, and batched against solo runs.
 import numpy as np
 import pytest
 
-from helpers import make_pair, rel_l2, velocity_error
+from helpers import make_pair, rel_l2, velocity_error, velocity_max_error
 import closed_forms as cf
 
 pytestmark = pytest.mark.gpu
@@ -56,9 +56,11 @@ def test_porous_full_lattice_against_oracle(storage, compute, tol, ptol):
     gpu.step(200)
     ora.run(200)
     drho, err = velocity_error(gpu, ora)
+    emax = velocity_max_error(gpu, ora)
     state = _particle_state_diff(gpu, ora)
-    print(f"porous {storage}/{compute}: drho {drho:.2e} err {err:.2e} particle state {state:.2e}")
-    assert err < tol, err
+    print(f"porous {storage}/{compute}: drho {drho:.2e} err {err:.2e} max {emax:.2e} "
+          f"particle state {state:.2e}")
+    assert err < tol and emax < tol, (err, emax)
     assert state < ptol, state
 
 
@@ -133,9 +135,11 @@ def test_fluctuating_full_lattice_against_oracle(storage, tol):
     gpu.step(100)
     ora.run(100)
     drho, err = velocity_error(gpu, ora)
+    emax = velocity_max_error(gpu, ora)
     state = _particle_state_diff(gpu, ora)
-    print(f"fluctuating {storage}: drho {drho:.2e} err {err:.2e} particle state {state:.2e}")
-    assert err < tol and state < (1e-11 if storage == "f64" else 1e-6), (err, state)
+    print(f"fluctuating {storage}: drho {drho:.2e} err {err:.2e} max {emax:.2e} "
+          f"particle state {state:.2e}")
+    assert err < tol and emax < tol and state < (1e-11 if storage == "f64" else 1e-6), (err, state)
 
 
 def test_fluctuating_100000_steps_equipartition():

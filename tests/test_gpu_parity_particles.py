@@ -5,7 +5,7 @@ accumulated rounding; FP32 storage to the 1e-5 velocity target."""
 import numpy as np
 import pytest
 
-from helpers import make_pair, random_fields, velocity_error
+from helpers import make_pair, random_fields, velocity_error, velocity_max_error
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +42,7 @@ def test_free_particle_crossing_nodes(rho_p, avg):
     ora.run(150)
     drho, err = velocity_error(gpu, ora)
     state, force = particle_diff(gpu, ora)
-    assert drho < 1e-12 and err < 1e-10, (drho, err)
+    assert drho < 1e-12 and err < 1e-10 and velocity_max_error(gpu, ora) < 1e-10, (drho, err)
     assert state < 1e-11 and force < 1e-9, (state, force)
 
 

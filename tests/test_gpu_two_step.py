@@ -53,6 +53,60 @@ def test_two_step_equals_single_steps(storage, rounding, obstacles):
             b.close()
 
 
+HEIGHTS = {"f64": (4, 6, 8), "f32": (6, 10, 14), "f16": (10, 14, 18), "bf16": (10, 14, 18)}
+
+
+@pytest.mark.parametrize("storage,rounding", FORMATS)
+def test_every_tile_height_equals_single_steps(storage, rounding):
+    """Each instantiated two-step tile height (LB_OPT_TWO_STEP_ROWS) gives
+    the single-step result bit for bit."""
+    for nx, ny in ((130, 77), (300, 33)):
+        b = _domain(nx, ny, storage, rounding, True, 0)
+        b.step(23)
+        ref = b.populations()
+        b.close()
+        for h in HEIGHTS[storage]:
+            a = _domain(nx, ny, storage, rounding, True, 1)
+            a.set_option(lb.OPT_TWO_STEP_ROWS, h)
+            assert a.get_option(lb.OPT_TWO_STEP_ROWS) == h
+            a.step(23)
+            assert np.array_equal(a.populations(), ref), (storage, nx, ny, h)
+            a.close()
+    d = _domain(64, 64, storage, rounding, False, 1)
+    with pytest.raises(lb.LBError):
+        d.set_option(lb.OPT_TWO_STEP_ROWS, 12)
+    d.close()
+
+
+def test_batch_tile_height_and_autotune():
+    """The batch's own tile height (option and autotuner, with its cache):
+    the members still evolve exactly as under single steps."""
+    shapes = [(130, 77, False), (64, 64, True), (300, 33, True), (257, 129, True)]
+    ref = None
+    for mode in ("single", "rows10", "tuned", "tuned-again"):
+        doms = [_domain(nx, ny, "f16", "stochastic", obs, 0 if mode == "single" else 1, seed=20 + i)
+                for i, (nx, ny, obs) in enumerate(shapes)]
+        batch = lb.Batch(doms)
+        if mode == "rows10":
+            batch.set_option(lb.OPT_TWO_STEP_ROWS, 10)
+        elif mode.startswith("tuned"):
+            ms = batch.autotune(steps=8)
+            assert ms >= 0 and (mode == "tuned" or ms == 0)  # the second time from the cache
+        done = doms[0].time
+        batch.step(64 - done)
+        pops = [d.populations() for d in doms]
+        if ref is None:
+            ref = pops
+        else:
+            for f, g in zip(pops, ref):
+                assert np.array_equal(f, g), mode
+        with pytest.raises(lb.LBError):
+            batch.set_option(lb.OPT_TWO_STEP_ROWS, 7)
+        batch.close()
+        for d in doms:
+            d.close()
+
+
 def test_two_step_batch_equals_single_steps():
     shapes = [(130, 77, False), (64, 64, True), (300, 33, True), (40, 50, False), (257, 129, True)]
     for two in (1, 0):
@@ -96,6 +150,7 @@ def test_autotune_times_single_steps_and_keeps_the_option():
     assert a.get_option(lb.OPT_TWO_STEP) == 1
     assert a.get_option(lb.OPT_TILE_WIDTH) in (64, 128, 256)
     assert a.get_option(lb.OPT_ROWS_PER_THREAD) in (2, 4, 8)
+    assert a.get_option(lb.OPT_TWO_STEP_ROWS) in HEIGHTS["f16"]
     t = a.time
     assert t > 0 and t % 8 == 0  # warm-up and timed runs of 4 steps per shape
     b.step(t)
