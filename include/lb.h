@@ -338,11 +338,21 @@ lb_status lb_batch_set_option(lb_batch *b, int32_t key, int64_t value);
 lb_status lb_batch_get_option(lb_batch *b, int32_t key, int64_t *value);
 lb_status lb_batch_destroy(lb_batch *b);
 
-/* Diagnostic: the six standard normals Theta_3..Theta_8 that the collision of
- * step `step` adds at nodes node0 .. node0+count-1 of a domain with this seed
- * and domain_id; device FP32 output [count][6].  Synchronises the stream. */
+/* Diagnostic: the six standard normals Theta_3..Theta_8 (Sec. 4, Eq. NP2)
+ * that the collision of step `step` adds at nodes node0 .. node0+count-1 of a
+ * domain with this seed and domain_id; device FP32 output [count][6]
+ * (count <= 2^28).  Both transforms start from the same Philox4x32-10 block
+ * and uniforms.  fp32_arithmetic = 0: the transform of collisions in FP64
+ * arithmetic (FP64 storage, LB_COMPUTE_F64), every operation a correctly
+ * rounded IEEE float operation in a fixed order (an independent
+ * implementation of the definition reproduces it bit for bit).  1: the
+ * transform of collisions in FP32 arithmetic (FP32 and 16-bit storage),
+ * through the hardware's log2, square root, sine and cosine instructions,
+ * within ~1e-6 absolute of the former.  Synchronises the stream; LB_EINVAL
+ * for a null output, another fp32_arithmetic or a larger count. */
 lb_status lb_noise_normals(uint64_t seed, uint32_t domain_id, uint32_t step, uint32_t node0,
-                           uint32_t count, float *dev_out, void *hip_stream);
+                           uint32_t count, int32_t fp32_arithmetic, float *dev_out,
+                           void *hip_stream);
 
 /* Autotune this domain's sweep tiles: times each candidate single-step tile
  * width / rows-per-thread pair over `steps` single steps (the two-step sweep

@@ -180,12 +180,13 @@ __global__ __launch_bounds__(256) void k_masks_full(const DevDomain *__restrict_
   D.nodew[here] = node_word(D.label, D.nx, D.ny, D.pitch, perx, pery, x, y);
 }
 
+template <bool HW>
 __global__ __launch_bounds__(256) void k_normals(uint32_t k0, uint32_t k1, uint32_t step,
                                                  uint32_t node0, uint32_t count, float *out) {
   const uint32_t n = blockIdx.x * 256 + threadIdx.x;
   if (n >= count) return;
   float th[6];
-  noise_normals(k0, k1, node0 + n, step, th);
+  noise_normals<HW>(k0, k1, node0 + n, step, th);
 #pragma unroll
   for (int k = 0; k < 6; ++k) out[(size_t)n * 6 + k] = th[k];
 }

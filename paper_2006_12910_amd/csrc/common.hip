@@ -23,9 +23,13 @@ void launch_mass_final(const DevDomain *doms, int ndom, const double *alt, doubl
   hipLaunchKernelGGL(k_mass_final, dim3(ndom), dim3(64), 0, s, doms, alt, alt_out);
 }
 void launch_normals(uint32_t k0, uint32_t k1, uint32_t step, uint32_t node0, uint32_t count,
-                    float *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_normals, dim3((count + 255) / 256), dim3(256), 0, s, k0, k1, step, node0,
-                     count, out);
+                    bool hw, float *out, hipStream_t s) {
+  if (hw)
+    hipLaunchKernelGGL(k_normals<true>, dim3((count + 255) / 256), dim3(256), 0, s, k0, k1, step,
+                       node0, count, out);
+  else
+    hipLaunchKernelGGL(k_normals<false>, dim3((count + 255) / 256), dim3(256), 0, s, k0, k1, step,
+                       node0, count, out);
 }
 void launch_advance(const DevDomain *doms, int ndom, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3((ndom + 63) / 64), dim3(64), 0, s, doms, ndom, n);

@@ -45,7 +45,7 @@ void launch_masks_full(const DevDomain *dom, int nx, int ny, hipStream_t s);
 void launch_mass_final(const DevDomain *doms, int ndom, const double *alt, double *alt_out,
                        hipStream_t s);
 void launch_normals(uint32_t k0, uint32_t k1, uint32_t step, uint32_t node0, uint32_t count,
-                    float *out, hipStream_t s);
+                    bool hw, float *out, hipStream_t s);
 void launch_advance(const DevDomain *doms, int ndom, int n, hipStream_t s);
 
 }  // namespace lbk

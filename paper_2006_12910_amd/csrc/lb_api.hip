@@ -1459,11 +1459,15 @@ lb_status lb_batch_destroy(lb_batch *b) {
 }
 
 lb_status lb_noise_normals(uint64_t seed, uint32_t domain_id, uint32_t step, uint32_t node0,
-                           uint32_t count, float *dev_out, void *hip_stream) {
+                           uint32_t count, int32_t fp32_arithmetic, float *dev_out,
+                           void *hip_stream) {
   if (!dev_out && count > 0) return fail(LB_EINVAL, "null output");
+  if (fp32_arithmetic != 0 && fp32_arithmetic != 1) return fail(LB_EINVAL, "fp32_arithmetic must be 0 or 1");
+  if (count > (1u << 28)) return fail(LB_EINVAL, "count above 2^28");
   if (count == 0) return LB_OK;
   hipStream_t s = (hipStream_t)hip_stream;
-  launch_normals((uint32_t)seed, (uint32_t)(seed >> 32) ^ domain_id, step, node0, count, dev_out, s);
+  launch_normals((uint32_t)seed, (uint32_t)(seed >> 32) ^ domain_id, step, node0, count,
+                 fp32_arithmetic == 1, dev_out, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   return LB_OK;

@@ -212,7 +212,7 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
   // add(i, c, z) receives the coefficient amp w_i (stored scaling) and z_i.
   auto noise = [&](auto &&add) {
     float th[6];
-    noise_normals(D.key0, D.key1, node, step, th);
+    noise_normals<sizeof(R) == 4>(D.key0, D.key1, node, step, th);
     // Theta_k / sqrt(w_k) with w_k = 4, 4/9, 1/9, 2/3, 2/3, 16 (Table t1)
     const R t3 = R(th[0]) * R(0.5), t4 = R(th[1]) * R(1.5), t5 = R(th[2]) * R(3);
     const R t6 = R(th[3]) * R(1.2247448713915890491), t7 = R(th[4]) * R(1.2247448713915890491);

@@ -138,7 +138,8 @@ def library():
         "lb_batch_step": [vp, C.c_int64],
         "lb_batch_set_option": [vp, st, C.c_int64],
         "lb_batch_destroy": [vp],
-        "lb_noise_normals": [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, vp, vp],
+        "lb_noise_normals": [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, st, vp,
+                             vp],
         "lb_autotune": [vp, st, dp],
         "lb_batch_autotune": [vp, st, dp],
         "lb_batch_get_option": [vp, st, P(C.c_int64)],
@@ -431,12 +432,14 @@ class Batch:
             pass
 
 
-def noise_normals(seed, domain_id, step, node0, count, device="cuda"):
-    """lb_noise_normals: Theta_3..Theta_8 of nodes node0.. at `step`, [count][6] FP32."""
+def noise_normals(seed, domain_id, step, node0, count, fp32_arithmetic=False, device="cuda"):
+    """lb_noise_normals: Theta_3..Theta_8 of nodes node0.. at `step`, [count][6]
+    FP32; fp32_arithmetic selects the transform of FP32-arithmetic collisions."""
     out = torch.empty((count, 6), dtype=torch.float32, device=device)
     _check(library().lb_noise_normals(int(seed) & (2 ** 64 - 1), int(domain_id) & 0xFFFFFFFF,
                                       int(step) & 0xFFFFFFFF, int(node0) & 0xFFFFFFFF,
-                                      int(count), C.c_void_p(out.data_ptr()),
+                                      int(count), int(bool(fp32_arithmetic)),
+                                      C.c_void_p(out.data_ptr()),
                                       _stream_ptr(None)), "lb_noise_normals")
     return out
 

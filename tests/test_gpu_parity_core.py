@@ -4,7 +4,8 @@ Tolerances: FP64 storage runs the same arithmetic in a different order
 (deviations instead of full populations, fused loops), so results agree to
 rounding accumulated over the run (<= 1e-10 relative on velocities that are
 1e-3..1e-6 of the populations).  FP32 storage is held to the 1e-5 relative-L2
-velocity target.  The noise normals must match bit for bit.
+velocity target.  The noise normals of FP64 arithmetic must match bit for
+bit; those of FP32 arithmetic (hardware transcendentals) to float precision.
 """
 import numpy as np
 import pytest
@@ -30,6 +31,30 @@ def test_noise_normals_bit_exact():
         assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (seed, dom, step)
         total += got.size
     assert total >= 2_000_000
+
+
+def test_noise_normals_of_fp32_arithmetic():
+    """The hardware transform of FP32-arithmetic collisions (log2, square
+    root, sine and cosine instructions) against the oracle's correctly rounded
+    definition: the same deviates within float precision.  Bound: the radius
+    carries ~1.4e-7 relative (log2 within 1 ulp, then the square root), the
+    sine and cosine ~1.3e-7 absolute at radius <= 5.5 (21-bit uniforms), plus
+    the two implementations' own roundings: |dz| <= 1e-6 + 2e-7 |z|.  Any
+    mispairing of the Philox words or a swapped sine and cosine fails it by
+    orders of magnitude."""
+    from paper_2006_12910_amd import lb
+    worst = 0.0
+    for seed, dom, step, node0, count in ((0, 0, 0, 0, 200000),
+                                          (20061291, 7, 123456, 5000, 200000),
+                                          ((1 << 63) + 12345, 0xFFFFFFFF, 0xFFFFFFF0, 0xFFFF0000, 65536)):
+        got = lb.noise_normals(seed, dom, step, node0, count, fp32_arithmetic=True).cpu().numpy()
+        ref = normals_bulk(seed, dom, step, node0, count)
+        dz = np.abs(got.astype(np.float64) - ref.astype(np.float64))
+        bound = 1e-6 + 2e-7 * np.abs(ref.astype(np.float64))
+        assert (dz <= bound).all(), (seed, float(dz.max()), float((dz / bound).max()))
+        worst = max(worst, float(dz.max()))
+    print(f"hardware transform: max |dz| {worst:.3e}")
+    assert worst > 0.0  # a different transform, not the exact one
 
 
 @pytest.mark.parametrize("storage,compute,tol", [("f64", "native", 1e-10), ("f32", "native", 1e-5),
