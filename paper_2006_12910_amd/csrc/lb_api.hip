@@ -618,6 +618,7 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   h.pl_K_f = (float)h.pl_K;
   h.tau_min_f = (float)h.tau_min;
   h.tau_max_f = (float)h.tau_max;
+  set_collision_coefficients(h);
 
   auto bail = [&](lb_status st) {
     (void)hipStreamDestroy(d->cap);

@@ -187,15 +187,30 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
   const R q = (R(1.5) * rho) * fmar(ux, ux, uy * uy);
   const R r45 = R(4.5) * rho;
   const R sp = ux + uy, sm = uy - ux;
-  // even parts and linear terms, already in the stored scaling
-  const R cxx = (K1 * W1) * (drho + fmar(r45 * ux, ux, -q));
-  const R cyy = (K1 * W1) * (drho + fmar(r45 * uy, uy, -q));
-  const R cpp = (K5 * W5) * (drho + fmar(r45 * sp, sp, -q));
-  const R cmm = (K5 * W5) * (drho + fmar(r45 * sm, sm, -q));
-  const R lx = (K1 * L1) * Jx, ly = (K1 * L1) * Jy;
-  const R lp = (K5 * L5) * (Jx + Jy), lm = (K5 * L5) * (Jy - Jx);
-  R eq[9];
-  eq[0] = K0 * fmar(R(-2), fmar(i1, cxx + cyy, i5 * (cpp + cmm)), drho);
+  // even parts and linear terms of omega feq, already in the stored scaling:
+  // omega rides on the class coefficients (uniform unless the relaxation
+  // time is local), so the relaxation below is one fused multiply-add a
+  // direction, d (1 - omega) + omega feq, instead of a subtraction and one
+  R aw1, aw5, al1, al5;
+  if constexpr ((FEAT & F_POWER) != 0) {
+    aw1 = om * (K1 * W1);
+    aw5 = om * (K5 * W5);
+    al1 = om * (K1 * L1);
+    al5 = om * (K5 * L5);
+  } else {  // the same products, formed once on the host
+    aw1 = par<R>(D.cw1, D.cw1_f);
+    aw5 = par<R>(D.cw5, D.cw5_f);
+    al1 = par<R>(D.cl1, D.cl1_f);
+    al5 = par<R>(D.cl5, D.cl5_f);
+  }
+  const R cxx = aw1 * (drho + fmar(r45 * ux, ux, -q));
+  const R cyy = aw1 * (drho + fmar(r45 * uy, uy, -q));
+  const R cpp = aw5 * (drho + fmar(r45 * sp, sp, -q));
+  const R cmm = aw5 * (drho + fmar(r45 * sm, sm, -q));
+  const R lx = al1 * Jx, ly = al1 * Jy;
+  const R lp = al5 * (Jx + Jy), lm = al5 * (Jy - Jx);
+  R eq[9];  // omega feq_i
+  eq[0] = K0 * fmar(R(-2), fmar(i1, cxx + cyy, i5 * (cpp + cmm)), om * drho);
   eq[1] = cxx + lx;
   eq[3] = cxx - lx;
   eq[2] = cyy + ly;
@@ -253,7 +268,7 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
     // takes the mass balance, so its equilibrium value is not needed.
     R inc[9];
 #pragma unroll
-    for (int i = 1; i < 9; ++i) inc[i] = om * (eq[i] - d[i]);
+    for (int i = 1; i < 9; ++i) inc[i] = fmar(-om, d[i], eq[i]);
     if constexpr ((FEAT & F_NOISE) != 0)
       noise([&](int i, R c, R z) { if (i > 0) inc[i] = fmar(c, z, inc[i]); });
     const R sx = ((inc[1] - inc[3]) + (inc[5] - inc[6])) + (inc[8] - inc[7]);
@@ -280,8 +295,9 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
       for (int i = 0; i < 9; ++i) d[i] = d[i] + inc[i];
     }
   } else {
+    const R keep = R(1) - om;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = fmar(om, eq[i] - d[i], d[i]);
+    for (int i = 0; i < 9; ++i) d[i] = fmar(keep, d[i], eq[i]);
     if constexpr ((FEAT & F_NOISE) != 0) noise([&](int i, R c, R z) { d[i] = fmar(c, z, d[i]); });
   }
 }

@@ -53,6 +53,7 @@ def test_d3q19_against_oracle(storage, tol, shape):
         gpu.step(n)
         ora.run(n)
         drho, err, emax = _velocity_error(gpu, ora)
+        print(f"D3Q19 {storage} {shape} step {gpu.time}: drho {drho:.2e} err {err:.2e} max {emax:.2e}")
         assert drho < (1e-13 if storage == "f64" else 1e-6) and err < tol and emax < 10 * tol, \
             (n, drho, err, emax)
     assert gpu.time == 60
@@ -72,7 +73,9 @@ def test_d3q19_plane_poiseuille_exact_steady_state():
     nu = (tau - 0.5) / 3
     z = np.arange(1, nz - 1)
     exact = g / (2 * nu) * (z - 0.5) * (nz - 1.5 - z) + g * (16 * (tau - 0.5) ** 2 - 3) / (24 * nu)
-    assert np.abs(ux[1:-1] - exact[:, None, None]).max() / exact.max() < 1e-10
+    dev = np.abs(ux[1:-1] - exact[:, None, None]).max() / exact.max()
+    print(f"D3Q19 plane Poiseuille: max deviation from the exact profile {dev:.2e}")
+    assert dev < 1e-10
     gpu.close()
 
 
@@ -90,6 +93,8 @@ def test_d3q19_256_cube_shear_wave_and_mass():
     prof = ux.mean(axis=(1, 2))
     amp = 2 * (prof * np.sin(k * np.arange(n))).mean()
     ref = u0 * np.exp(-(tau - 0.5) / 3 * k * k * steps)
+    print(f"D3Q19 256^3 shear wave: amplitude / closed form - 1 = {amp / ref - 1:.2e}, "
+          f"mass drift {gpu.mass() / m0 - 1:.2e}")
     assert abs(amp / ref - 1) < 1e-3, (amp, ref)
     assert np.abs(uy).max() < 1e-7 and np.abs(uz).max() < 1e-7
     assert abs(gpu.mass() / m0 - 1) < 1e-9
