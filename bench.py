@@ -7,10 +7,12 @@ obstacles at 20% solid, tau ~ U[0.55, 1.2]), all started from seeded shear
 waves (u0 = 0.01).  Every step advances all 201 domains with one sweep launch
 (batched, replayed from a hipGraph).  Populations are stored as FP16 deviations
 with stochastic rounding (the reported value), and, for comparison, as plain
-FP32 and as BF16 deviations; arithmetic is FP32.  Before the timed region the
-tile shapes are tuned on a throwaway copy of the batch: the batch step is
-timed for the default shapes, every uniform shape and the per-class shapes
-the library's autotuner (lb_autotune) picks, and the fastest is used.
+FP32 and as BF16 deviations; arithmetic is FP32.  Each launch of the
+two-step sweep advances every domain by two steps; before the timed region
+lb_batch_autotune picks its tile height (timed once per process, then
+cached).  With --single-step (one step per launch) the single-step tile
+shapes are tuned instead, on a throwaway copy of the batch.  The first call
+captures every step graph the timed calls replay.
 
 MLUPS counts every lattice site of every domain (solids included), as the
 paper defines it.  The roofline object reports the sweep kernel's algorithmic
@@ -19,10 +21,10 @@ HBM bytes per launch over its measured average launch duration against 8 TB/s
 call of 2K steps and the timed call of K steps, which removes each call's
 fixed cost, the FP64 density sums).  The CPU baseline is the FP64 oracle on a
 bounded sample of the smallest domains of the same workload, 1000 steps each,
-on all host threads the process may use (at most 16) and on one thread; the
-same sample, run on the GPU for 1000 steps in each storage format, gives the
-relative L2 velocity error against the oracle (the workload's stated horizon),
-whatever --steps is.
+on all host threads the process may use (at most 16) and on one thread, and on
+a few steps of each other workload's lattice; the same sample, run on the GPU
+for 1000 steps in each storage format, gives the relative L2 velocity error
+against the oracle (the workload's stated horizon), whatever --steps is.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -122,6 +124,8 @@ def tune_batch(storage, specs, masks, steps=20):
     cands += [(f"uniform {tw}x{r}", {c: (tw, r) for c in classes}) for tw in (64, 128, 256) for r in (2, 4, 8)]
     cands.append(("per-class autotune", autotune_tiles(storage, specs, masks)))
     doms = build_variant(storage, specs, masks)
+    for d in doms:
+        d.set_option(lb.OPT_TWO_STEP, 0)  # the shapes tuned are the single-step sweep's
     default = [(d.get_option(lb.OPT_TILE_WIDTH), d.get_option(lb.OPT_ROWS_PER_THREAD)) for d in doms]
     stream = torch.cuda.current_stream()
     best = None
@@ -270,6 +274,34 @@ def run_oracle(specs, masks, nsteps, budget_s):
     return results, sites / t_total / 1e6, t_total
 
 
+def cpu_baseline_leg(specs, masks, args):
+    """The CPU baseline: the oracle on the smallest domains of the workload
+    (all host threads up to 16, then one thread), and, unless the other
+    workloads are skipped, on each of them.  Returns the cpu_baseline entry
+    and the sample's final moments (the reference of the accuracy leg)."""
+    threads = min(len(os.sched_getaffinity(0)), 16)
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    ref, cpu_mlups, cpu_s = run_oracle(specs, masks, ACC_STEPS, args.cpu_budget)
+    sample = sorted(ref)
+    set_omp_threads(1)
+    _, cpu1_mlups, cpu1_s = run_oracle(specs, masks, ACC_STEPS, args.cpu_budget / 3)
+    set_omp_threads(threads)
+    cpu = {"value": round(cpu_mlups, 2), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{len(sample)} smallest domains of the workload "
+                     f"({min(specs[i]['n'] for i in sample)}^2..{max(specs[i]['n'] for i in sample)}^2), "
+                     f"{ACC_STEPS} steps each, FP64, {cpu_s:.1f}s",
+           "cpu_model": cpu_model(), "host_threads_visible": len(os.sched_getaffinity(0)),
+           "one_thread_value": round(cpu1_mlups, 2),
+           "one_thread_sample": f"smallest domains in order, {ACC_STEPS} steps each, {cpu1_s:.1f}s"}
+    log(f"oracle: {cpu_mlups:.2f} MLUPS on {threads} threads, {len(sample)} domains; "
+        f"{cpu1_mlups:.2f} MLUPS on one thread ({cpu_model()})")
+    if not args.no_configs:
+        t0 = time.time()
+        cpu["other_workloads"] = cpu_baseline_other_workloads()
+        log(f"oracle on the other workloads ({time.time() - t0:.0f}s): {json.dumps(cpu['other_workloads'])}")
+    return cpu, ref
+
+
 def set_omp_threads(n):
     """Thread count of the oracle's OpenMP loops (process-wide libgomp)."""
     import ctypes
@@ -338,14 +370,12 @@ def copy_bandwidth(mib=2048, reps=10):
     return gbs
 
 
-def other_configs(with_oracle):
-    """GPU MLUPS of the other four workloads at their full sizes (timed with
-    HIP events after a warm-up call), each next to the oracle's MLUPS on a
-    few steps of the same lattice."""
+def other_configs():
+    """GPU MLUPS of the other four workloads and of the D3Q19 lattice at their
+    full sizes (timed with HIP events after a warm-up call); the oracle's
+    rates on the same lattices are part of the CPU baseline."""
     import torch
     from paper_2006_12910_amd import inputs, lb
-    from oracle import Oracle, OracleParams
-    from oracle.oracle import PRESSURE, WALL
     out = {}
 
     def gpu_rate(name, dom_or_batch, sites, steps):
@@ -358,20 +388,11 @@ def other_configs(with_oracle):
         torch.cuda.synchronize()
         out[name] = {"gpu_mlups": round(sites * steps / (e0.elapsed_time(e1) * 1e-3) / 1e6, 1)}
 
-    def oracle_rate(name, ora, sites, steps):
-        if not with_oracle:
-            return
-        t0 = time.perf_counter()
-        ora.run(steps)
-        out[name]["oracle_mlups"] = round(sites * steps / (time.perf_counter() - t0) / 1e6, 2)
-
     # channel 128 x 64, FP64
     kw = dict(bc_y="wall", tau=0.8, g=(1e-6, 0.0))
     d = lb.Domain(128, 64, storage="f64", **kw)
     gpu_rate("channel_128x64_f64", d, 128 * 64, 5000)
     d.close()
-    oracle_rate("channel_128x64_f64", Oracle(OracleParams(nx=128, ny=64, bc_y=WALL, tau=0.8, gx=1e-6)),
-                128 * 64, 2000)
     # porous 2048 x 1024 with 16 discs, FP32 storage
     mask, _ = inputs.porous_channel()
     parts = [dict(x=x, y=y, radius=8.0, density_ratio=1.05) for x, y in inputs.particle_block()]
@@ -385,24 +406,11 @@ def other_configs(with_oracle):
     d.set_option(lb.OPT_OVERLAP, 1)
     gpu_rate("porous_2048x1024_16discs_f32_overlapped", d, 2048 * 1024, 1000)
     d.close()
-    if with_oracle:
-        o = Oracle(OracleParams(nx=2048, ny=1024, bc_x=PRESSURE, bc_y=WALL, tau=0.7, rho_in=1.001,
-                                rho_out=0.999, lj_psi=lj[0], lj_rit=lj[1], lj_floor=lj[2],
-                                force_average=True), mask)
-        for p in parts:
-            o.add_particle(p["x"], p["y"], 8.0, 1.05, 0.0, 0.0, 0.0)
-        oracle_rate("porous_2048x1024_16discs_f32", o, 2048 * 1024, 20)
-        del o
     # fluctuating 512^2 with a Brownian disc, FP32 storage; and the 64-member ensemble
     d = lb.Domain(512, 512, storage="f32", tau=1.0, kT=1e-4, seed=2006, domain_id=1, max_particles=1)
     d.add_particles([dict(x=256.5, y=256.5, radius=5.0)])
     gpu_rate("fluctuating_512_disc_f32", d, 512 * 512, 2000)
     d.close()
-    if with_oracle:
-        o = Oracle(OracleParams(nx=512, ny=512, tau=1.0, kT=1e-4, seed=2006, domain_id=1))
-        o.add_particle(256.5, 256.5, 5.0, 1.0, 0.0, 0.0, 0.0)
-        oracle_rate("fluctuating_512_disc_f32", o, 512 * 512, 100)
-        del o
     specs = inputs.fluctuating_batch(count=64)
     doms = []
     for sp in specs:
@@ -417,30 +425,18 @@ def other_configs(with_oracle):
     for dd in doms:
         dd.close()
     # power-law channel 4096 x 256, n = 0.5, FP32 storage
-    pl = dict(n=0.5, K=0.01, tau_min=0.51, tau_max=2.5)
-    d = lb.Domain(4096, 256, storage="f32", bc_y="wall", g=(2.648e-6, 0.0), power_law=pl)
+    d, _, _ = powerlaw_channel("f32")
     gpu_rate("powerlaw_4096x256_n0.5_f32", d, 4096 * 256, 2000)
     d.close()
-    oracle_rate("powerlaw_4096x256_n0.5_f32",
-                Oracle(OracleParams(nx=4096, ny=256, bc_y=WALL, gx=2.648e-6, power_law=True, n_index=0.5,
-                                    K=0.01)), 4096 * 256, 20)
     # the D3Q19 lattice: 256^3 periodic, FP32 storage, one sweep per step;
-    # algorithmic bytes 2 x 19 x 4 per node update; the oracle on 64^3
-    from oracle.oracle import Oracle3
+    # algorithmic bytes 2 x 19 x 4 per node update
     n3 = 256
-    d = lb.Domain3(n3, n3, n3, tau=0.8, storage="f32")
+    d, _, _ = d3q19_cube("f32", n3)
     gpu_rate("d3q19_256cube_f32", d, n3 ** 3, 200)
     d.close()
     r = out["d3q19_256cube_f32"]
     r["sweep_GBps"] = round(r["gpu_mlups"] * 1e6 * 152 / 1e9, 1)
     r["hbm_frac"] = round(r["sweep_GBps"] / HBM_PEAK_GBS, 4)
-    if with_oracle:
-        o3 = Oracle3(64, 64, 64, tau=0.8)
-        t0 = time.perf_counter()
-        o3.run(10)
-        r["oracle_mlups"] = round(64 ** 3 * 10 / (time.perf_counter() - t0) / 1e6, 2)
-        r["oracle_lattice"] = "64^3"
-        del o3
     torch.cuda.empty_cache()
     return out
 
@@ -472,11 +468,27 @@ def porous_discs(storage="f32"):
     return d, [d], 2048 * 1024
 
 
+def powerlaw_channel(storage="f32"):
+    """Power-law channel 4096 x 256, n = 0.5, K = 0.01, tau* in [0.51, 2.5]."""
+    from paper_2006_12910_amd import lb
+    pl = dict(n=0.5, K=0.01, tau_min=0.51, tau_max=2.5)
+    d = lb.Domain(4096, 256, storage=storage, bc_y="wall", g=(2.648e-6, 0.0), power_law=pl)
+    return d, [d], 4096 * 256
+
+
+def d3q19_cube(storage="f32", n=256):
+    """The D3Q19 lattice: 256^3 periodic, tau = 0.8, at rest."""
+    from paper_2006_12910_amd import lb
+    d = lb.Domain3(n, n, n, tau=0.8, storage=storage)
+    return d, [d], n ** 3
+
+
 def only_workload(name, steps, warmup):
     """One workload alone (for profiling): warm-up, then `steps` timed steps;
     prints one JSON line."""
     import torch
-    make = {"fluct-ensemble": fluct_ensemble, "porous": porous_discs}[name]
+    make = {"fluct-ensemble": fluct_ensemble, "porous": porous_discs, "powerlaw": powerlaw_channel,
+            "d3q19": d3q19_cube}[name]
     runner, doms, sites = make()
     runner.step(max(warmup, 1))
     torch.cuda.synchronize()
@@ -555,18 +567,16 @@ def reporting_offload(steps=600, intervals=(10, 100)):
     return out
 
 
-def paper_replicas(with_oracle):
+def paper_replicas():
     """GPU MLUPS of stand-ins for the paper's three timing benchmarks on their
     full lattices (FP32 storage; the set-ups of tests/test_gpu_paper_benchmarks.py),
-    next to the oracle on a few steps of the same set-up and the paper's best
-    CPU figure, which is context only."""
+    next to the paper's best CPU figure, which is context only (the oracle's
+    rates on the same set-ups are part of the CPU baseline)."""
     import torch
     from paper_2006_12910_amd import inputs, lb
-    from oracle import Oracle, OracleParams
-    from oracle.oracle import WALL
     out = {}
 
-    def rate(name, make_gpu, make_oracle, sites, steps, ora_steps):
+    def rate(name, make_gpu, sites, steps):
         d = make_gpu()
         d.step(max(steps // 10, 1))
         torch.cuda.synchronize()
@@ -578,11 +588,6 @@ def paper_replicas(with_oracle):
         d.close()
         out[name] = {"gpu_mlups": round(sites * steps / (e0.elapsed_time(e1) * 1e-3) / 1e6, 1),
                      "paper_best_cpu_mlups": PAPER_BEST_CPU_MLUPS[name]}
-        if with_oracle:
-            o = make_oracle()
-            t0 = time.perf_counter()
-            o.run(ora_steps)
-            out[name]["oracle_mlups"] = round(sites * ora_steps / (time.perf_counter() - t0) / 1e6, 2)
 
     mask, centres = inputs.replica_b1()
 
@@ -593,14 +598,7 @@ def paper_replicas(with_oracle):
         d.add_particles([dict(x=x, y=y, radius=6.5) for x, y in centres])
         return d
 
-    def b1_oracle():
-        o = Oracle(OracleParams(nx=1020, ny=1620, bc_x=WALL, tau=0.636, gx=1e-6, gy=-1e-5,
-                                force_average=True), mask)
-        for x, y in centres:
-            o.add_particle(x, y, 6.5, 1.0, 0.0, 0.0, 0.0)
-        return o
-
-    rate("b1", b1_gpu, b1_oracle, 1020 * 1620, 1000, 10)
+    rate("b1", b1_gpu, 1020 * 1620, 1000)
     ((bx, by),) = inputs.replica_b2()
 
     def b2_gpu():
@@ -609,19 +607,58 @@ def paper_replicas(with_oracle):
         d.add_particles([dict(x=bx, y=by, radius=7.5)])
         return d
 
-    def b2_oracle():
-        o = Oracle(OracleParams(nx=3000, ny=41, bc_y=WALL, tau=0.8, kT=5e-5, seed=2020, domain_id=2))
-        o.add_particle(bx, by, 7.5, 1.0, 0.0, 0.0, 0.0)
-        return o
-
-    rate("b2", b2_gpu, b2_oracle, 3000 * 41, 5000, 100)
+    rate("b2", b2_gpu, 3000 * 41, 5000)
     pl = dict(n=0.5, K=1e-3, tau_min=0.50003, tau_max=0.8)
     rate("b3", lambda: lb.Domain(101, 51, storage="f32", bc_y="wall", tau=0.8, g=(1e-6, 0.0),
                                  power_law=pl),
-         lambda: Oracle(OracleParams(nx=101, ny=51, bc_y=WALL, tau=0.8, gx=1e-6, power_law=True,
-                                     n_index=0.5, K=1e-3, tau_min=0.50003, tau_max=0.8)),
-         101 * 51, 20000, 2000)
+         101 * 51, 20000)
     torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_other_workloads():
+    """CPU-baseline leg for the other workloads: the oracle's MLUPS (all
+    host threads up to 16) on a few steps of each lattice that other_configs
+    and paper_replicas time on the GPU (D3Q19 on 64^3 instead of 256^3)."""
+    from paper_2006_12910_amd import inputs
+    from oracle import Oracle, OracleParams
+    from oracle.oracle import PRESSURE, WALL, Oracle3
+    out = {}
+
+    def rate(name, ora, sites, steps, **extra):
+        t0 = time.perf_counter()
+        ora.run(steps)
+        out[name] = dict(oracle_mlups=round(sites * steps / (time.perf_counter() - t0) / 1e6, 2), **extra)
+
+    rate("channel_128x64_f64", Oracle(OracleParams(nx=128, ny=64, bc_y=WALL, tau=0.8, gx=1e-6)),
+         128 * 64, 2000)
+    mask, _ = inputs.porous_channel()
+    o = Oracle(OracleParams(nx=2048, ny=1024, bc_x=PRESSURE, bc_y=WALL, tau=0.7, rho_in=1.001,
+                            rho_out=0.999, lj_psi=1e-3, lj_rit=2.5, lj_floor=0.5,
+                            force_average=True), mask)
+    for x, y in inputs.particle_block():
+        o.add_particle(x, y, 8.0, 1.05, 0.0, 0.0, 0.0)
+    rate("porous_2048x1024_16discs_f32", o, 2048 * 1024, 20)
+    o = Oracle(OracleParams(nx=512, ny=512, tau=1.0, kT=1e-4, seed=2006, domain_id=1))
+    o.add_particle(256.5, 256.5, 5.0, 1.0, 0.0, 0.0, 0.0)
+    rate("fluctuating_512_disc_f32", o, 512 * 512, 100)
+    rate("powerlaw_4096x256_n0.5_f32",
+         Oracle(OracleParams(nx=4096, ny=256, bc_y=WALL, gx=2.648e-6, power_law=True, n_index=0.5,
+                             K=0.01)), 4096 * 256, 20)
+    rate("d3q19_256cube_f32", Oracle3(64, 64, 64, tau=0.8), 64 ** 3, 10, oracle_lattice="64^3")
+    mask, centres = inputs.replica_b1()
+    o = Oracle(OracleParams(nx=1020, ny=1620, bc_x=WALL, tau=0.636, gx=1e-6, gy=-1e-5,
+                            force_average=True), mask)
+    for x, y in centres:
+        o.add_particle(x, y, 6.5, 1.0, 0.0, 0.0, 0.0)
+    rate("b1", o, 1020 * 1620, 10)
+    ((bx, by),) = inputs.replica_b2()
+    o = Oracle(OracleParams(nx=3000, ny=41, bc_y=WALL, tau=0.8, kT=5e-5, seed=2020, domain_id=2))
+    o.add_particle(bx, by, 7.5, 1.0, 0.0, 0.0, 0.0)
+    rate("b2", o, 3000 * 41, 100)
+    rate("b3", Oracle(OracleParams(nx=101, ny=51, bc_y=WALL, tau=0.8, gx=1e-6, power_law=True,
+                                   n_index=0.5, K=1e-3, tau_min=0.50003, tau_max=0.8)),
+         101 * 51, 2000)
     return out
 
 
@@ -664,7 +701,7 @@ def main():
     ap.add_argument("--tiles", default=None, metavar="JSON",
                     help='tile shape per size class instead of tuning, e.g. the "tiles" object of an '
                          'earlier line (to profile the configuration that line measured)')
-    ap.add_argument("--only", default=None, choices=["fluct-ensemble", "porous"],
+    ap.add_argument("--only", default=None, choices=["fluct-ensemble", "porous", "powerlaw", "d3q19"],
                     help="time one other workload alone (GPU only; for profiling) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="before the workload, copy a buffer of this size 5 times (a kernel of "
@@ -700,24 +737,9 @@ def main():
     sites = sum(s["n"] ** 2 for s in specs)
     fluid_sites = sum(s["n"] ** 2 - (0 if m is None else int(m.sum())) for s, m in zip(specs, masks))
 
-    sample, ref, cpu = [], {}, None
+    ref, cpu = {}, None
     if not args.no_cpu:
-        threads = min(len(os.sched_getaffinity(0)), 16)
-        os.environ["OMP_NUM_THREADS"] = str(threads)
-        ref, cpu_mlups, cpu_s = run_oracle(specs, masks, ACC_STEPS, args.cpu_budget)
-        sample = sorted(ref)
-        set_omp_threads(1)
-        _, cpu1_mlups, cpu1_s = run_oracle(specs, masks, ACC_STEPS, args.cpu_budget / 3)
-        set_omp_threads(threads)
-        cpu = {"value": round(cpu_mlups, 2), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-               "sample": f"{len(sample)} smallest domains of the workload "
-                         f"({min(specs[i]['n'] for i in sample)}^2..{max(specs[i]['n'] for i in sample)}^2), "
-                         f"{ACC_STEPS} steps each, FP64, {cpu_s:.1f}s",
-               "cpu_model": cpu_model(), "host_threads_visible": len(os.sched_getaffinity(0)),
-               "one_thread_value": round(cpu1_mlups, 2),
-               "one_thread_sample": f"smallest domains in order, {ACC_STEPS} steps each, {cpu1_s:.1f}s"}
-        log(f"oracle: {cpu_mlups:.2f} MLUPS on {threads} threads, {len(sample)} domains; "
-            f"{cpu1_mlups:.2f} MLUPS on one thread ({cpu_model()})")
+        cpu, ref = cpu_baseline_leg(specs, masks, args)
 
     results = {}
     for v in variants:
@@ -784,10 +806,10 @@ def main():
     configs = replicas = offload = None
     if not args.no_configs:
         t0 = time.time()
-        configs = other_configs(with_oracle=not args.no_cpu)
+        configs = other_configs()
         log(f"other workloads ({time.time() - t0:.0f}s): {json.dumps(configs)}")
         t0 = time.time()
-        replicas = paper_replicas(with_oracle=not args.no_cpu)
+        replicas = paper_replicas()
         log(f"paper benchmarks ({time.time() - t0:.0f}s): {json.dumps(replicas)}")
         t0 = time.time()
         offload = reporting_offload()
