@@ -72,6 +72,9 @@ lb_status validate3(const lb3_domain_desc *d) {
     return fail3(LB_EINVAL, "nx, ny, nz must be in [3, 4096]");
   if (d->storage != LB_F64 && d->storage != LB_F32)
     return fail3(LB_EINVAL, "storage must be LB_F64 or LB_F32");
+  // the sweep indexes a population buffer with 32-bit element offsets
+  if (19.0 * d->nz * d->ny * ((d->nx + 63) / 64 * 64) >= 2147483648.0)
+    return fail3(LB_EINVAL, "lattice too large: 19 nz ny pitch must stay below 2^31");
   if (!(d->tau > 0.5)) return fail3(LB_EINVAL, "tau must be > 1/2");
   if (!(d->rho0 > 0.0) || !std::isfinite(d->rho0)) return fail3(LB_EINVAL, "rho0 must be > 0");
   if (!std::isfinite(d->gx) || !std::isfinite(d->gy) || !std::isfinite(d->gz))

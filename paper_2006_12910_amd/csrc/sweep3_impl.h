@@ -132,10 +132,24 @@ template <class R> __device__ __forceinline__ void collide3(const Dom3 &D, R d[1
   }
 }
 
+// XCD-aware block order: the hardware deals consecutive block ids to the 8
+// XCDs in turn; remapped, each XCD walks a contiguous run of tiles, so the
+// 128-byte lines that an x-shifted pull shares with the neighbouring tile
+// are found in the same L2 (without it the FP32 256^3 sweep read 1.26 x its
+// populations).
+__device__ __forceinline__ int xcd_order(int bid, int nblocks) {
+  constexpr int NX = 8;
+  if (nblocks < 2 * NX) return bid;
+  const int xcd = bid % NX, local = bid / NX;
+  const int per = nblocks / NX, rem = nblocks % NX;
+  return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
 // One step of every node: 256 threads = a tile of 64 (x) by 4 (y) nodes of
 // one z plane; each wave reads 64 consecutive x of a row per population
 // plane.  A solid node stores zero deviations (every slot is written each
-// step and never pulled).
+// step and never pulled).  Element offsets are 32-bit (the host admits no
+// buffer of 2^31 elements or more).
 template <int ST>
 __global__ __launch_bounds__(256) void k_sweep3(const Dom3 *__restrict__ Dp, int kstep) {
   using T = typename std::conditional<ST == 0, double, float>::type;
@@ -143,8 +157,9 @@ __global__ __launch_bounds__(256) void k_sweep3(const Dom3 *__restrict__ Dp, int
   const Dom3 &D = *Dp;
   const int nx = D.nx, ny = D.ny, nz = D.nz, pitch = D.pitch;
   const int per_plane = D.tiles_x * D.tiles_y;
-  const int z = (int)blockIdx.x / per_plane;
-  const int t = (int)blockIdx.x - z * per_plane;
+  const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
+  const int z = b / per_plane;
+  const int t = b - z * per_plane;
   const int ty = t / D.tiles_x, tx = t - ty * D.tiles_x;
   const int x = tx * 64 + (int)(threadIdx.x & 63);
   const int y = ty * 4 + (int)(threadIdx.x >> 6);
@@ -152,8 +167,8 @@ __global__ __launch_bounds__(256) void k_sweep3(const Dom3 *__restrict__ Dp, int
   const uint64_t T0 = *D.tstep + (uint64_t)kstep;  // state time of the source buffer
   const T *src = (const T *)D.f[T0 & 1];
   T *dst = (T *)D.f[(T0 + 1) & 1];
-  const size_t plane = (size_t)nz * ny * pitch;
-  const size_t here = ((size_t)z * ny + y) * pitch + x;
+  const uint32_t plane = (uint32_t)nz * (uint32_t)ny * (uint32_t)pitch;
+  const uint32_t here = ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)pitch + (uint32_t)x;
   const uint32_t w = D.nodew ? D.nodew[here] : 0u;
   R d[19];
   if (w & NODE_SOLID3) {
@@ -170,16 +185,18 @@ __global__ __launch_bounds__(256) void k_sweep3(const Dom3 *__restrict__ Dp, int
       const int sx = ex(i) > 0 ? xm : (ex(i) < 0 ? xp : x);
       const int sy = ey(i) > 0 ? ym : (ey(i) < 0 ? yp : y);
       const int sz = ez(i) > 0 ? zm : (ez(i) < 0 ? zp : z);
-      const size_t from = ((w >> (i - 1)) & 1u)
-                              ? (size_t)opp(i) * plane + here  // halfway bounce-back
-                              : (size_t)i * plane + ((size_t)sz * ny + sy) * pitch + sx;
+      const uint32_t from =
+          ((w >> (i - 1)) & 1u)
+              ? (uint32_t)opp(i) * plane + here  // halfway bounce-back
+              : (uint32_t)i * plane + ((uint32_t)sz * (uint32_t)ny + (uint32_t)sy) * (uint32_t)pitch +
+                    (uint32_t)sx;
       d[i] = src[from];
     }
     collide3<R>(D, d);
     if (!(fabs((double)d[0]) < 1e30)) atomicOr(D.health, 1u);
   }
 #pragma unroll
-  for (int i = 0; i < 19; ++i) dst[(size_t)i * plane + here] = d[i];
+  for (int i = 0; i < 19; ++i) dst[(uint32_t)i * plane + here] = d[i];
 }
 
 // Node words from the solid mask ([nz][ny][pitch] bytes, 1 = solid).
