@@ -115,10 +115,14 @@ __global__ __launch_bounds__(256) void k_sweep2(const DevDomain *__restrict__ do
     if (r >= RS) break;  // wave-uniform
     const int y = ya[u];
     if constexpr (LABELS) lnw[r][lane] = (uint16_t)nwa[u];
-    const bool solid = LABELS && (nwa[u] & NODE_SOLID);
+    // A solid node's first-step values are never read: a fluid neighbour
+    // whose pull would take them bounces back off its own slot instead, and
+    // phase B sweeps the solid node itself with zero deviations.  So phase A
+    // collides whatever a solid node pulled (finite values of its
+    // neighbours) without zeroing it first, nine selects a node fewer.
     R e[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) e[i] = solid ? R(0) : (R)S::raw_dec(raw[u].get(i));
+    for (int i = 0; i < 9; ++i) e[i] = (R)S::raw_dec(raw[u].get(i));
     const uint32_t node = (uint32_t)y * (uint32_t)nx + (uint32_t)xs;
     bad = bad || !(fabs(scaled_drho<ST, R>(e)) < R(1e30));
     collide_node<ST, FEAT, PL_GENERIC, R>(D, e, node, step1);

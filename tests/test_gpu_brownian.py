@@ -80,8 +80,15 @@ def test_brownian_disc_msd_follows_the_regression_of_fluctuations():
         d.close()
     c0 = (vel ** 2).mean() / 1.0  # <U_x^2> = <U_y^2>: per component
     m = np.pi * R * R
-    print(f"disc translation energy m <U_x^2> / kT = {m * c0 / KT:.3f}")
-    assert 0.7 < m * c0 / KT < 1.3
+    # sampling error from the spread of the 16 independent realisations
+    per_member = m * (vel ** 2).mean(axis=(1, 2)) / KT
+    se = per_member.std(ddof=1) / np.sqrt(members)
+    print(f"disc translation energy m <U_x^2> / kT = {m * c0 / KT:.3f} +- {se:.3f} (16 realisations)")
+    # the disc runs ~10 % hot (measured 1.10-1.13, far outside the sampling
+    # error): a systematic excess of the particle coupling, not of the noise,
+    # whose fluid equipartition holds to 0.2 %
+    assert se < 0.05
+    assert 0.95 < m * c0 / KT < 1.25
     D_per = KT * (-0.5 * np.log(np.pi * R * R / N ** 2) - 0.738 + np.pi * R * R / N ** 2) / (
         4 * np.pi * cf.nu_of_tau(TAU))
     for lag in LAGS:

@@ -181,7 +181,10 @@ def test_fluctuating_100000_steps_equipartition():
     print(f"equipartition: fluid u {ex:.4f} v {ey:.4f} rho {er:.4f}; disc translation {et:.3f} "
           f"rotation {erot:.3f}")
     assert abs(ex - 1) < 0.02 and abs(ey - 1) < 0.02 and abs(er - 1) < 0.02
-    assert 0.7 < et < 1.3 and 0.5 < erot < 1.5
+    # one disc, 800 correlated samples: the disc's temperature is checked
+    # loosely here (measured 1.10 / 1.22); the 16-realisation ensemble of the
+    # MSD test bounds the translational one with its sampling error
+    assert 0.9 < et < 1.35 and 0.9 < erot < 1.5
 
 
 def test_fluctuating_ensemble_batch():
@@ -275,6 +278,38 @@ def test_powerlaw_full_lattice_columns_match_oracle(n, storage, compute, roundin
         err = float(cols.max())
     print(f"power law n={n} {storage}/{compute}/{rounding}: column vs oracle {err:.2e}")
     assert err < tol, err
+
+
+@pytest.mark.parametrize("n", [0.5, 0.75, 1.5])
+@pytest.mark.parametrize("storage,rounding,tol", [("f64", "nearest", 1e-10),
+                                                  ("f32", "stochastic", 1e-5)])
+def test_powerlaw_full_lattice_perturbed_against_oracle(n, storage, rounding, tol):
+    """The whole 4096 x 256 lattice started from the closed-form profile with
+    a seeded perturbation that varies along x (a few long waves in both
+    velocity components plus small random noise), so every column differs:
+    the GPU against the oracle on the full lattice, node by node."""
+    from paper_2006_12910_amd import lb
+    nx, ny = 4096, 256
+    pl = dict(n=n, K=0.01, tau_min=0.51, tau_max=2.5)
+    rho, ux, uy, u = _pl_init(n, nx, ny)
+    rng = np.random.default_rng(4096 + int(100 * n))
+    x = np.arange(nx)[None, :]
+    y = np.arange(ny)[:, None]
+    umax = np.abs(u).max()
+    wall = np.zeros((ny, 1))
+    wall[1:-1] = 1.0
+    ux = ux * (1.0 + 0.05 * np.sin(2 * np.pi * 3 * x / nx)) + wall * 1e-3 * umax * rng.standard_normal((ny, nx))
+    uy = wall * 0.02 * umax * np.sin(2 * np.pi * 5 * x / nx) * np.sin(np.pi * y / (ny - 1))
+    rho = rho + wall * 1e-4 * np.cos(2 * np.pi * 2 * x / nx)
+    gpu, ora = make_pair(nx, ny, storage=storage, rounding=rounding, bc_y="wall", g=(_PL_G[n], 0.0),
+                         power_law=pl, init=(rho, ux, uy))
+    gpu.step(300)
+    ora.run(300)
+    drho, err = velocity_error(gpu, ora)
+    emax = velocity_max_error(gpu, ora)
+    print(f"power law n={n} {storage}/{rounding} perturbed 4096x256: drho {drho:.2e} err {err:.2e} "
+          f"max {emax:.2e}", flush=True)
+    assert err < tol and emax < 10 * tol, (err, emax)
 
 
 @pytest.mark.parametrize("n,tol", [(0.5, 2e-3), (0.75, 6e-4), (1.5, 1e-4)])
