@@ -411,19 +411,13 @@ def other_configs():
     d.add_particles([dict(x=256.5, y=256.5, radius=5.0)])
     gpu_rate("fluctuating_512_disc_f32", d, 512 * 512, 2000)
     d.close()
-    specs = inputs.fluctuating_batch(count=64)
-    doms = []
-    for sp in specs:
-        dd = lb.Domain(sp["n"], sp["n"], storage="f32", tau=1.0, kT=1e-4, seed=64,
-                       domain_id=sp["domain_id"], max_particles=1)
-        cx, cy, r = sp["disc"]
-        dd.add_particles([dict(x=cx, y=cy, radius=r)])
-        doms.append(dd)
-    b = lb.Batch(doms)
-    gpu_rate("fluctuating_ensemble_64_f32", b, sum(sp["n"] ** 2 for sp in specs), 200)
-    b.close()
-    for dd in doms:
-        dd.close()
+    # the 64-member ensemble in FP32 and in FP16 deviations (stochastic rounding)
+    for storage in ("f32", "f16"):
+        b, doms, sites = fluct_ensemble(storage)
+        gpu_rate(f"fluctuating_ensemble_64_{storage}", b, sites, 200)
+        b.close()
+        for dd in doms:
+            dd.close()
     # power-law channel 4096 x 256, n = 0.5, FP32 storage
     d, _, _ = powerlaw_channel("f32")
     gpu_rate("powerlaw_4096x256_n0.5_f32", d, 4096 * 256, 2000)
@@ -443,13 +437,14 @@ def other_configs():
 
 def fluct_ensemble(storage="f32"):
     """The batched fluctuating workload: 64 realisations of 128^2..1024^2,
-    each with a Brownian disc of radius 5, kT = 1e-4, tau = 1."""
+    each with a Brownian disc of radius 5, kT = 1e-4, tau = 1 (16-bit
+    storage with stochastic rounding)."""
     from paper_2006_12910_amd import inputs, lb
     specs = inputs.fluctuating_batch(count=64)
     doms = []
     for sp in specs:
         dd = lb.Domain(sp["n"], sp["n"], storage=storage, tau=1.0, kT=1e-4, seed=64,
-                       domain_id=sp["domain_id"], max_particles=1)
+                       domain_id=sp["domain_id"], max_particles=1, rounding=ROUNDING[storage])
         cx, cy, r = sp["disc"]
         dd.add_particles([dict(x=cx, y=cy, radius=r)])
         doms.append(dd)
@@ -487,8 +482,8 @@ def only_workload(name, steps, warmup):
     """One workload alone (for profiling): warm-up, then `steps` timed steps;
     prints one JSON line."""
     import torch
-    make = {"fluct-ensemble": fluct_ensemble, "porous": porous_discs, "powerlaw": powerlaw_channel,
-            "d3q19": d3q19_cube}[name]
+    make = {"fluct-ensemble": fluct_ensemble, "fluct-ensemble-f16": lambda: fluct_ensemble("f16"),
+            "porous": porous_discs, "powerlaw": powerlaw_channel, "d3q19": d3q19_cube}[name]
     runner, doms, sites = make()
     runner.step(max(warmup, 1))
     torch.cuda.synchronize()
@@ -701,7 +696,8 @@ def main():
     ap.add_argument("--tiles", default=None, metavar="JSON",
                     help='tile shape per size class instead of tuning, e.g. the "tiles" object of an '
                          'earlier line (to profile the configuration that line measured)')
-    ap.add_argument("--only", default=None, choices=["fluct-ensemble", "porous", "powerlaw", "d3q19"],
+    ap.add_argument("--only", default=None,
+                    choices=["fluct-ensemble", "fluct-ensemble-f16", "porous", "powerlaw", "d3q19"],
                     help="time one other workload alone (GPU only; for profiling) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="before the workload, copy a buffer of this size 5 times (a kernel of "

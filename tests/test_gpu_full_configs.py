@@ -187,6 +187,32 @@ def test_fluctuating_100000_steps_equipartition():
     assert 0.9 < et < 1.35 and 0.9 < erot < 1.5
 
 
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_fluctuating_reduced_storage_equipartition(storage):
+    """Thermal noise on 16-bit deviation storage with stochastic rounding
+    (FP32 arithmetic): the fluid's velocity and density variances still
+    equal kT and 3 kT (Eqs. NP1-NP2; linear fluctuating hydrodynamics).  The
+    unbiased rounding adds a variance far below the noise's per step, so the
+    bound is the sampling error of 200 snapshots of 256^2 nodes (~0.3 %)
+    plus margin; round-to-nearest would damp or stall the fluctuations."""
+    from paper_2006_12910_amd import lb
+    kT, n = 1e-4, 256
+    d = lb.Domain(n, n, tau=1.0, storage=storage, rounding="stochastic", kT=kT, seed=16,
+                  domain_id=3)
+    d.step(4000)
+    fu, fv, fr = [], [], []
+    for _ in range(200):
+        d.step(50)
+        r, ux, uy = d.moments()
+        fu.append((r * ux ** 2).mean())
+        fv.append((r * uy ** 2).mean())
+        fr.append(((r - 1.0) ** 2).mean())
+    ex, ey, er = np.mean(fu) / kT, np.mean(fv) / kT, np.mean(fr) / (3 * kT)
+    print(f"{storage} equipartition: fluid u {ex:.4f} v {ey:.4f} rho {er:.4f}")
+    assert abs(ex - 1) < 0.02 and abs(ey - 1) < 0.02 and abs(er - 1) < 0.02
+    d.close()
+
+
 def test_fluctuating_ensemble_batch():
     """64 realisations of 128^2..1024^2 in one batch: FP64 members match the
     oracle (the five smallest and the largest), FP32 members match their solo
