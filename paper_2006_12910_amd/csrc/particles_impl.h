@@ -86,10 +86,36 @@ __device__ __forceinline__ double lj_mag(const DevDomain &D, double gap) {
   return D.lj_psi * pow(g / D.lj_rit, -13.0);
 }
 
+struct PDisc {
+  double x, y, radius;
+};
+
+// One of two particle records, chosen field by field (a select of the whole
+// record by a runtime condition would go through private memory).
+__device__ __forceinline__ PState pick_state(bool second, const PState &a, const PState &b) {
+  PState r;
+  r.x = second ? b.x : a.x;
+  r.y = second ? b.y : a.y;
+  r.ux = second ? b.ux : a.ux;
+  r.uy = second ? b.uy : a.uy;
+  r.omega = second ? b.omega : a.omega;
+  r.radius = second ? b.radius : a.radius;
+  r.mass = second ? b.mass : a.mass;
+  r.inertia = second ? b.inertia : a.inertia;
+  r.rho_ratio = second ? b.rho_ratio : a.rho_ratio;
+  r.fx = second ? b.fx : a.fx;
+  r.fy = second ? b.fy : a.fy;
+  r.torque = second ? b.torque : a.torque;
+  r.flags = second ? b.flags : a.flags;
+  r.pad = 0;
+  r.pad2[0] = r.pad2[1] = r.pad2[2] = 0.0;
+  return r;
+}
+
 // Repulsion on particle p from particle q (Eq. MP2), both from P(T): zero
 // for q == p or beyond the interaction range.
 __device__ __forceinline__ void pair_repulsion(const DevDomain &D, const PState &P,
-                                               const PState &Q, double &lx, double &ly) {
+                                               const PDisc &Q, double &lx, double &ly) {
   const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
   const double dx = min_image(P.x - Q.x, D.nx, perx), dy = min_image(P.y - Q.y, D.ny, pery);
   const double dist = sqrt(dx * dx + dy * dy);
@@ -100,15 +126,15 @@ __device__ __forceinline__ void pair_repulsion(const DevDomain &D, const PState 
   ly += m * dy / dist;
 }
 
-// Newton-Euler step (Eqs. MP5-MP6) of particle p from P(T) (`cur`), its link,
-// cover and solid-repulsion forces F and its particle-particle repulsion
-// (lx, ly), into P(T+1); with F_FAVG the update takes the mean of this step's
-// total force and torque and the previous step's, which P(T) holds.
-__device__ __forceinline__ void advance_particle(const DevDomain &D, int p, const PState *cur,
+// Newton-Euler step (Eqs. MP5-MP6) of particle p from its state P = P(T),
+// its link, cover and solid-repulsion forces F and its particle-particle
+// repulsion (lx, ly), into P(T+1); with F_FAVG the update takes the mean of
+// this step's total force and torque and the previous step's, which P(T)
+// holds.
+__device__ __forceinline__ void advance_particle(const DevDomain &D, int p, const PState &P,
                                                  PState *nxt, const PForce &F, double lx,
                                                  double ly) {
   const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
-  const PState P = cur[p];
   const double fx = F.fx + F.cx_ + (lx + F.ljx);
   const double fy = F.fy + F.cy_ + (ly + F.ljy);
   const double tq = F.torque + F.ctorque;
@@ -158,9 +184,24 @@ __global__ __launch_bounds__(256) void k_pre(const DevDomain *__restrict__ doms,
   __shared__ uint8_t lab[LAB_BOX];
   const PItem it = items[blockIdx.x];
   const DevDomain &D = doms[it.dom];
+  // The step counter, this particle's record in both state buffers, its force
+  // record (read by the update at the end) and, one per lane, the other
+  // particles' records in both buffers are requested together: none depends
+  // on another, so choosing the buffer by the step's parity afterwards costs
+  // no extra round trip through memory (this kernel is a latency chain).
   const uint64_t T0 = *D.tstep + (uint64_t)kstep;
-  const PState *cur = D.pstate[T0 & 1];
-  const PState P = cur[it.p];
+  const PState Pa = D.pstate[0][it.p], Pb = D.pstate[1][it.p];
+  const PForce Fpre = D.pforce[it.p];
+  const int qme = (int)threadIdx.x;  // np <= MAX_PARTICLES <= 256: one particle per lane
+  const bool pair_lane = D.lj_psi > 0.0 && qme < D.np && qme != it.p;
+  PDisc qa{0.0, 0.0, 0.0}, qb{0.0, 0.0, 0.0};
+  if (pair_lane) {
+    const PState &A = D.pstate[0][qme], &B = D.pstate[1][qme];
+    qa = PDisc{A.x, A.y, A.radius};
+    qb = PDisc{B.x, B.y, B.radius};
+  }
+  static_assert(MAX_PARTICLES <= 256, "one particle per lane");
+  const PState P = pick_state((T0 & 1) != 0, Pa, Pb);
   T *f = (T *)D.f[T0 & 1];
   const size_t plane = (size_t)D.ny * D.pitch;
   const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
@@ -228,9 +269,10 @@ __global__ __launch_bounds__(256) void k_pre(const DevDomain *__restrict__ doms,
   // pass 3: momentum exchange (FP64) and moving-wall bounce-back of each link
   // repulsion from the other particles, one lane per pair
   double plx = 0.0, ply = 0.0;
-  if (D.lj_psi > 0.0) {
-    for (int q = threadIdx.x; q < D.np; q += 256)
-      if (q != it.p) pair_repulsion(D, P, cur[q], plx, ply);
+  if (pair_lane) {
+    const bool odd = (T0 & 1) != 0;
+    const PDisc Q{odd ? qb.x : qa.x, odd ? qb.y : qa.y, odd ? qb.radius : qa.radius};
+    pair_repulsion(D, P, Q, plx, ply);
   }
   double acc[7] = {0.0, 0.0, 0.0, ljx, ljy, plx, ply};
   for (int e = threadIdx.x; e < nl; e += 256) {
@@ -262,14 +304,14 @@ __global__ __launch_bounds__(256) void k_pre(const DevDomain *__restrict__ doms,
   }
   block_sum<7>(acc, red);
   if (threadIdx.x == 0) {
-    PForce F = D.pforce[it.p];
+    PForce F = Fpre;
     F.fx = acc[0];
     F.fy = acc[1];
     F.torque = acc[2];
     F.ljx = acc[3];
     F.ljy = acc[4];
     D.pforce[it.p] = F;
-    advance_particle(D, it.p, cur, D.pstate[(T0 + 1) & 1], F, acc[5], acc[6]);
+    advance_particle(D, it.p, P, D.pstate[(T0 + 1) & 1], F, acc[5], acc[6]);
   }
 }
 
@@ -286,9 +328,6 @@ __device__ __forceinline__ uint8_t new_label(const DevDomain &D, const Disc *Pn,
   }
   return LBL_FLUID;
 }
-struct PDisc {
-  double x, y, radius;
-};
 // The same rule over the candidate discs cand[0 .. n) (ascending indices):
 // the particles that can hold a node of the caller's box.
 __device__ __forceinline__ uint8_t label_among(const DevDomain &D, const PDisc *Pn, const int *cand,
@@ -325,10 +364,20 @@ __global__ __launch_bounds__(256) void k_post(const DevDomain *__restrict__ doms
   __shared__ int cand[MAX_PARTICLES];
   const PItem it = items[blockIdx.x];
   const DevDomain &D = doms[it.dom];
+  // the step counter and the discs in both state buffers (this particle's
+  // record, and one other particle per lane) are requested together, then
+  // sorted into old and new by the step's parity: no dependent round trip
   const uint64_t T1 = *D.tstep + (uint64_t)kstep + 1;
-  const PState *Pn = D.pstate[T1 & 1];
-  const PState *Po = D.pstate[(T1 - 1) & 1];
-  const PState P = Pn[it.p];
+  const PState Pa = D.pstate[0][it.p], Pb = D.pstate[1][it.p];
+  const int qme = (int)threadIdx.x;  // MAX_PARTICLES <= 256: one disc per lane
+  PDisc qa{0.0, 0.0, 0.0}, qb{0.0, 0.0, 0.0};
+  if (qme < D.np) {
+    const PState &A = D.pstate[0][qme], &B = D.pstate[1][qme];
+    qa = PDisc{A.x, A.y, A.radius};
+    qb = PDisc{B.x, B.y, B.radius};
+  }
+  const bool odd = (T1 & 1) != 0;
+  const PState P = pick_state(odd, Pa, Pb);  // P(T+1)
   const T *src = (const T *)D.f[T1 & 1];
   const size_t plane = (size_t)D.ny * D.pitch;
   const bool perx = D.bc_x == BC_PERIODIC, pery = D.bc_y == BC_PERIODIC;
@@ -341,13 +390,14 @@ __global__ __launch_bounds__(256) void k_post(const DevDomain *__restrict__ doms
     static_assert(MAX_PARTICLES <= 256, "one candidate test per lane");
     // a node of the box lies within (W - 1) / 2 of the box centre on each
     // axis, so a disc holding one has its centre within r + W / 2 + 1
-    const int q = (int)threadIdx.x;  // MAX_PARTICLES <= 256: one disc per lane
+    const int q = qme;
     int hit = 0;
     if (q < D.np) {
       const double bcx = bx0 + 0.5 * (W - 1), bcy = by0 + 0.5 * (W - 1), h = 0.5 * W + 1.0;
-      const PState &A = Po[q], &B = Pn[q];
-      disc0[q] = PDisc{A.x, A.y, A.radius};
-      disc1[q] = PDisc{B.x, B.y, B.radius};
+      const PDisc A{odd ? qa.x : qb.x, odd ? qa.y : qb.y, odd ? qa.radius : qb.radius};  // P(T)
+      const PDisc B{odd ? qb.x : qa.x, odd ? qb.y : qa.y, odd ? qb.radius : qa.radius};  // P(T+1)
+      disc0[q] = A;
+      disc1[q] = B;
       hit = (fabs(min_image(A.x - bcx, D.nx, perx)) < h + A.radius &&
              fabs(min_image(A.y - bcy, D.ny, pery)) < h + A.radius) ||
             (fabs(min_image(B.x - bcx, D.nx, perx)) < h + B.radius &&
