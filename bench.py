@@ -371,9 +371,10 @@ def copy_bandwidth(mib=2048, reps=10):
 
 
 def other_configs():
-    """GPU MLUPS of the other four workloads and of the D3Q19 lattice at their
-    full sizes (timed with HIP events after a warm-up call); the oracle's
-    rates on the same lattices are part of the CPU baseline."""
+    """GPU MLUPS of the other four workloads, of the 8192^2 member alone and
+    of the D3Q19 lattice at their full sizes (timed with HIP events after a
+    warm-up call); the oracle's rates on the same lattices are part of the
+    CPU baseline."""
     import torch
     from paper_2006_12910_amd import inputs, lb
     out = {}
@@ -388,6 +389,18 @@ def other_configs():
         torch.cuda.synchronize()
         out[name] = {"gpu_mlups": round(sites * steps / (e0.elapsed_time(e1) * 1e-3) / 1e6, 1)}
 
+    # a single-domain probe above 1 GB: the 8192^2 periodic shear wave alone,
+    # FP16 deviations with stochastic rounding, two steps per launch
+    # (algorithmic bytes 36 per site update; the A-B buffers take 2.4 GB)
+    fields = inputs.shear_wave_field(8192, 8192, SHEAR_U0, 1, 0.0)
+    d = lb.Domain(8192, 8192, tau=BIG_TAU, storage="f16", rounding="stochastic", init=fields)
+    del fields
+    gpu_rate("single_8192_f16", d, 8192 * 8192, 200)
+    d.close()
+    r = out["single_8192_f16"]
+    r["sweep_GBps"] = round(r["gpu_mlups"] * 1e6 * 36 / 1e9, 1)
+    r["hbm_frac"] = round(r["sweep_GBps"] / HBM_PEAK_GBS, 4)
+    torch.cuda.empty_cache()
     # channel 128 x 64, FP64
     kw = dict(bc_y="wall", tau=0.8, g=(1e-6, 0.0))
     d = lb.Domain(128, 64, storage="f64", **kw)

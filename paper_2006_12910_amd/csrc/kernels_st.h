@@ -48,6 +48,9 @@ void pre_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hip
 void post_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
   hipLaunchKernelGGL((k_post<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
 }
+void post_pre_l(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s) {
+  hipLaunchKernelGGL((k_post_pre<ST>), dim3(nitems), dim3(256), 0, s, doms, items, kstep);
+}
 void mass_l(const DevDomain *doms, const int *prefix, int ndom, int blocks, double *alt,
             hipStream_t s) {
   hipLaunchKernelGGL((k_mass_partial<ST>), dim3(blocks), dim3(256), 0, s, doms, prefix, ndom, alt);
@@ -82,6 +85,7 @@ template <int FEAT, int PLM, int WIDE> void fill(KernelSet *k) {
   k->init = init_l<FEAT, PLM, WIDE>;
   k->pre = pre_l;
   k->post = post_l;
+  k->post_pre = post_pre_l;
   k->mass_partial = mass_l;
   k->moments = moments_l;
   k->export_f = export_l;

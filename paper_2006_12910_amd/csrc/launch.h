@@ -20,6 +20,10 @@ struct KernelSet {
   // particle coupling before and after the sweep (one workgroup per particle)
   void (*pre)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
   void (*post)(const DevDomain *doms, const PItem *items, int nitems, int kstep, hipStream_t s);
+  // post of step kstep and pre of step kstep + 1 in one launch (launches in
+  // which no domain holds more than one particle)
+  void (*post_pre)(const DevDomain *doms, const PItem *items, int nitems, int kstep,
+                   hipStream_t s);
   // FP64 density partial sums of ndom domains (mass block prefix per domain),
   // into each domain's partials, or into alt (one domain)
   void (*mass_partial)(const DevDomain *doms, const int *prefix, int ndom, int blocks,

@@ -321,6 +321,9 @@ struct StepPlan {
   int nitems;
   bool two;  // two-step sweep (no particles, so no pre/post passes)
   int rows2 = 0;  // its tile height (every domain of the launch shares it)
+  // no domain of the launch holds more than one particle: the post pass of a
+  // step and the pre pass of the next run as one launch (k_post_pre)
+  bool fuse_pp = false;
   // overlapped particle steps (one domain): the particle chain on `side`
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -375,9 +378,15 @@ void record_steps(const StepPlan &p, int n, hipStream_t s) {
     return;
   }
   for (; k < n; ++k) {
-    if (p.nitems > 0) p.ks->pre(p.doms, p.items, p.nitems, k, s);
+    // with fuse_pp, the pre pass of step k > 0 ran in the launch before
+    if (p.nitems > 0 && !(p.fuse_pp && k > 0)) p.ks->pre(p.doms, p.items, p.nitems, k, s);
     p.ks->sweep(p.doms, p.prefix, p.ndom, k, p.blocks, 0, s);
-    if (p.nitems > 0) p.ks->post(p.doms, p.items, p.nitems, k, s);
+    if (p.nitems > 0) {
+      if (p.fuse_pp && k + 1 < n)
+        p.ks->post_pre(p.doms, p.items, p.nitems, k, s);
+      else
+        p.ks->post(p.doms, p.items, p.nitems, k, s);  // a call ends after a post pass
+    }
   }
   launch_advance(p.doms, p.ndom, n, s);
 }
@@ -883,6 +892,7 @@ lb_status lb_step(lb_domain *d, int64_t nsteps) {
     StepPlan p{&d->ks, d->ddesc(), d->dprefix(), d->dprefix2(), 1, d->ntiles(),
                d->ntiles2(), d->ditems(), d->np, two_step_ok(d)};
     p.rows2 = d->hd.rows2;
+    p.fuse_pp = d->np == 1;
     if (d->overlap && d->np > 0 && !p.two) {
       if (!d->side) {
         HIPCHK(hipStreamCreateWithFlags(&d->side, hipStreamNonBlocking));
@@ -1388,6 +1398,8 @@ lb_status lb_batch_step(lb_batch *b, int64_t nsteps) {
     StepPlan p{&b->ks, b->ddesc(), b->dprefix(), b->dprefix2(), (int)b->doms.size(),
                b->total_tiles, b->total_tiles2, b->ditems(), b->nitems, b->two_step};
     p.rows2 = b->rows2;
+    p.fuse_pp = true;
+    for (auto *m : b->doms) p.fuse_pp = p.fuse_pp && m->np <= 1;
     lb_status s = run_steps(b->graphs, b->use_graph, b->chunk, b->stream, b->cap, p, nsteps);
     if (s != LB_OK) return s;
   }

@@ -172,8 +172,8 @@ __device__ __forceinline__ void advance_particle(const DevDomain &D, int p, cons
 // thread reads f*_{-d}(x) for the force and writes the bounced values there
 // in place, and the sweep pulls every direction unconditionally.
 template <int ST>
-__global__ __launch_bounds__(256) void k_pre(const DevDomain *__restrict__ doms,
-                                             const PItem *__restrict__ items, int kstep) {
+__device__ __forceinline__ void pre_body(const DevDomain *__restrict__ doms,
+                                         const PItem *__restrict__ items, int kstep) {
   using S = Store<ST>;
   using T = typename S::T;
   using RS = typename S::R;
@@ -352,8 +352,8 @@ __device__ __forceinline__ uint8_t label_among(const DevDomain &D, const PDisc *
 // (recovered from f*(T+1): j(f*) = j(f) + rho g), applied in the next step
 // (Eq. MP3).
 template <int ST>
-__global__ __launch_bounds__(256) void k_post(const DevDomain *__restrict__ doms,
-                                              const PItem *__restrict__ items, int kstep) {
+__device__ __forceinline__ void post_body(const DevDomain *__restrict__ doms,
+                                          const PItem *__restrict__ items, int kstep) {
   using S = Store<ST>;
   using T = typename S::T;
   __shared__ double red[4][3];
@@ -440,6 +440,36 @@ __global__ __launch_bounds__(256) void k_post(const DevDomain *__restrict__ doms
     F.cy_ = acc[1];
     F.ctorque = acc[2];
   }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_pre(const DevDomain *__restrict__ doms,
+                                             const PItem *__restrict__ items, int kstep) {
+  pre_body<ST>(doms, items, kstep);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_post(const DevDomain *__restrict__ doms,
+                                              const PItem *__restrict__ items, int kstep) {
+  post_body<ST>(doms, items, kstep);
+}
+
+// k_post of step kstep and k_pre of step kstep + 1 in one launch, for
+// launches in which no domain holds more than one particle.  Then each
+// workgroup's particle is alone in its domain: no other workgroup touches
+// its labels, populations or records, and the barrier between the two
+// halves orders everything the second half reads (the labels and the cover
+// force just written, the populations the first half read before the
+// bounce-back writes).  One launch less per step, the same results.  With
+// two or more particles in a domain the halves of different workgroups
+// would race (a disc's bounce-back writes can reach nodes a neighbour's
+// cover force still reads), so those launches keep the two kernels.
+template <int ST>
+__global__ __launch_bounds__(256) void k_post_pre(const DevDomain *__restrict__ doms,
+                                                  const PItem *__restrict__ items, int kstep) {
+  post_body<ST>(doms, items, kstep);
+  __syncthreads();
+  pre_body<ST>(doms, items, kstep + 1);
 }
 
 #ifdef LBK_COMMON_KERNELS
