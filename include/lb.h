@@ -389,7 +389,8 @@ lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms);
  * through lb_last_error.  No particles, noise or power law. */
 typedef struct lb3_domain_desc {
   uint32_t abi_version;        /* LB_ABI_VERSION                                  */
-  int32_t nx, ny, nz;          /* each in [3, 4096]                               */
+  int32_t nx, ny, nz;          /* each in [3, 4096], with 19 nz ny pitch < 2^31   */
+                               /* (pitch = nx rounded up to 64; 460^3 fits)       */
   int32_t wall_x, wall_y, wall_z;  /* nonzero: the outermost planes are solid    */
   int32_t storage;             /* LB_F64 | LB_F32                                 */
   int32_t obstacles;           /* nonzero: lb3_set_obstacles may be called        */
