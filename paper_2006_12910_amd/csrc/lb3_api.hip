@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -16,6 +17,8 @@ using namespace lbk3;
 namespace lbk {
 // records msg as lb_last_error() and returns s (lb_api.hip)
 lb_status lb_fail(lb_status s, const std::string &msg);
+// the same without throwing (lb_api.hip)
+lb_status lb_fail_nothrow(lb_status s, const char *msg) noexcept;
 }
 
 namespace {
@@ -160,9 +163,20 @@ lb_status push_desc3(lb3_domain *d) {
 
 }  // namespace
 
+// Every entry point runs its body through LB_GUARDED, so that no C++
+// exception (a failed host allocation, say) crosses the C ABI.
+#define LB_GUARDED(call)                                                           \
+  try {                                                                            \
+    return call;                                                                   \
+  } catch (const std::bad_alloc &) {                                               \
+    return lbk::lb_fail_nothrow(LB_ENOMEM, "host memory allocation failed");       \
+  } catch (...) {                                                                  \
+    return lbk::lb_fail_nothrow(LB_EHIP, "unexpected internal error");             \
+  }
+
 extern "C" {
 
-lb_status lb3_workspace_bytes(const lb3_domain_desc *desc, size_t *bytes) {
+static lb_status lb3_workspace_bytes_impl(const lb3_domain_desc *desc, size_t *bytes) {
   if (!bytes) return fail3(LB_EINVAL, "bytes is null");
   lb_status s = validate3(desc);
   if (s != LB_OK) return s;
@@ -170,8 +184,12 @@ lb_status lb3_workspace_bytes(const lb3_domain_desc *desc, size_t *bytes) {
   return LB_OK;
 }
 
-lb_status lb3_create_domain(const lb3_domain_desc *desc, void *dev_workspace, size_t bytes,
-                            void *hip_stream, lb3_domain **out) {
+lb_status lb3_workspace_bytes(const lb3_domain_desc *desc, size_t *bytes) {
+  LB_GUARDED(lb3_workspace_bytes_impl(desc, bytes));
+}
+
+static lb_status lb3_create_domain_impl(const lb3_domain_desc *desc, void *dev_workspace, size_t bytes,
+                                        void *hip_stream, lb3_domain **out) {
   if (!out) return fail3(LB_EINVAL, "out is null");
   *out = nullptr;
   lb_status s = validate3(desc);
@@ -240,7 +258,12 @@ lb_status lb3_create_domain(const lb3_domain_desc *desc, void *dev_workspace, si
   return LB_OK;
 }
 
-lb_status lb3_set_obstacles(lb3_domain *d, const uint8_t *mask, size_t n) {
+lb_status lb3_create_domain(const lb3_domain_desc *desc, void *dev_workspace, size_t bytes,
+                            void *hip_stream, lb3_domain **out) {
+  LB_GUARDED(lb3_create_domain_impl(desc, dev_workspace, bytes, hip_stream, out));
+}
+
+static lb_status lb3_set_obstacles_impl(lb3_domain *d, const uint8_t *mask, size_t n) {
   if (!d || !mask) return fail3(LB_EINVAL, "null argument");
   if (!d->desc.obstacles) return fail3(LB_ESTATE, "domain was created without obstacles");
   if (n != (size_t)d->nodes()) return fail3(LB_EINVAL, "mask size must be nx*ny*nz");
@@ -261,7 +284,11 @@ lb_status lb3_set_obstacles(lb3_domain *d, const uint8_t *mask, size_t n) {
   return LB_OK;
 }
 
-lb_status lb3_step(lb3_domain *d, int64_t nsteps) {
+lb_status lb3_set_obstacles(lb3_domain *d, const uint8_t *mask, size_t n) {
+  LB_GUARDED(lb3_set_obstacles_impl(d, mask, n));
+}
+
+static lb_status lb3_step_impl(lb3_domain *d, int64_t nsteps) {
   if (!d) return fail3(LB_EINVAL, "null domain");
   if (nsteps < 0) return fail3(LB_EINVAL, "nsteps < 0");
   const unsigned blocks = (unsigned)(d->hd.tiles_x * d->hd.tiles_y * d->desc.nz);
@@ -280,7 +307,11 @@ lb_status lb3_step(lb3_domain *d, int64_t nsteps) {
   return LB_OK;
 }
 
-lb_status lb3_moments(lb3_domain *d, double *rho, double *ux, double *uy, double *uz) {
+lb_status lb3_step(lb3_domain *d, int64_t nsteps) {
+  LB_GUARDED(lb3_step_impl(d, nsteps));
+}
+
+static lb_status lb3_moments_impl(lb3_domain *d, double *rho, double *ux, double *uy, double *uz) {
   if (!d || !rho || !ux || !uy || !uz) return fail3(LB_EINVAL, "null argument");
   const long long n = d->nodes();
   double *st = (double *)(d->ws + d->L.stage);
@@ -301,7 +332,11 @@ lb_status lb3_moments(lb3_domain *d, double *rho, double *ux, double *uy, double
   return check_health3(d);
 }
 
-lb_status lb3_get_populations(lb3_domain *d, double *f) {
+lb_status lb3_moments(lb3_domain *d, double *rho, double *ux, double *uy, double *uz) {
+  LB_GUARDED(lb3_moments_impl(d, rho, ux, uy, uz));
+}
+
+static lb_status lb3_get_populations_impl(lb3_domain *d, double *f) {
   if (!d || !f) return fail3(LB_EINVAL, "null argument");
   const long long n = d->nodes();
   double *st = (double *)(d->ws + d->L.stage);
@@ -322,7 +357,11 @@ lb_status lb3_get_populations(lb3_domain *d, double *f) {
   return check_health3(d);
 }
 
-lb_status lb3_mass(lb3_domain *d, double *total) {
+lb_status lb3_get_populations(lb3_domain *d, double *f) {
+  LB_GUARDED(lb3_get_populations_impl(d, f));
+}
+
+static lb_status lb3_mass_impl(lb3_domain *d, double *total) {
   if (!d || !total) return fail3(LB_EINVAL, "null argument");
   if (d->desc.storage == LB_F64)
     hipLaunchKernelGGL(k_mass3_partial<0>, dim3(d->desc.nz), dim3(256), 0, d->stream, d->ddesc());
@@ -335,17 +374,29 @@ lb_status lb3_mass(lb3_domain *d, double *total) {
   return check_health3(d);
 }
 
-lb_status lb3_time(lb3_domain *d, int64_t *t) {
+lb_status lb3_mass(lb3_domain *d, double *total) {
+  LB_GUARDED(lb3_mass_impl(d, total));
+}
+
+static lb_status lb3_time_impl(lb3_domain *d, int64_t *t) {
   if (!d || !t) return fail3(LB_EINVAL, "null argument");
   *t = d->t;
   return LB_OK;
 }
 
-lb_status lb3_destroy_domain(lb3_domain *d) {
+lb_status lb3_time(lb3_domain *d, int64_t *t) {
+  LB_GUARDED(lb3_time_impl(d, t));
+}
+
+static lb_status lb3_destroy_domain_impl(lb3_domain *d) {
   if (!d) return fail3(LB_EINVAL, "null domain");
   (void)hipStreamSynchronize(d->stream);
   delete d;
   return LB_OK;
+}
+
+lb_status lb3_destroy_domain(lb3_domain *d) {
+  LB_GUARDED(lb3_destroy_domain_impl(d));
 }
 
 }  // extern "C"

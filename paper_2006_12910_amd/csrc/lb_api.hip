@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -192,6 +193,15 @@ namespace lbk {
 // the error record of the D3Q19 entry points (lb3_api.hip): the same
 // thread-local text lb_last_error returns
 lb_status lb_fail(lb_status s, const std::string &msg) { return fail(s, msg); }
+// The error record where an allocation has just failed: the message is kept
+// if it can be, and nothing is thrown.
+lb_status lb_fail_nothrow(lb_status s, const char *msg) noexcept {
+  try {
+    g_err = msg;
+  } catch (...) {
+  }
+  return s;
+}
 }  // namespace lbk
 
 struct lb_domain {
@@ -515,6 +525,17 @@ template <class F> lb_status time_steps(F &&step, hipStream_t s, int n, double *
 }
 }  // namespace
 
+// Every entry point runs its body through LB_GUARDED, so that no C++
+// exception (a failed host allocation, say) crosses the C ABI.
+#define LB_GUARDED(call)                                                           \
+  try {                                                                            \
+    return call;                                                                   \
+  } catch (const std::bad_alloc &) {                                               \
+    return lbk::lb_fail_nothrow(LB_ENOMEM, "host memory allocation failed");       \
+  } catch (...) {                                                                  \
+    return lbk::lb_fail_nothrow(LB_EHIP, "unexpected internal error");             \
+  }
+
 extern "C" {
 
 const char *lb_status_string(lb_status s) {
@@ -532,7 +553,7 @@ const char *lb_status_string(lb_status s) {
 
 const char *lb_last_error(void) { return g_err.c_str(); }
 
-lb_status lb_workspace_bytes(const lb_domain_desc *desc, size_t *bytes) {
+static lb_status lb_workspace_bytes_impl(const lb_domain_desc *desc, size_t *bytes) {
   if (!bytes) return fail(LB_EINVAL, "bytes is null");
   lb_status s = validate(desc);
   if (s != LB_OK) return s;
@@ -540,8 +561,12 @@ lb_status lb_workspace_bytes(const lb_domain_desc *desc, size_t *bytes) {
   return LB_OK;
 }
 
-lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size_t bytes,
-                           void *hip_stream, lb_domain **out) {
+lb_status lb_workspace_bytes(const lb_domain_desc *desc, size_t *bytes) {
+  LB_GUARDED(lb_workspace_bytes_impl(desc, bytes));
+}
+
+static lb_status lb_create_domain_impl(const lb_domain_desc *desc, void *dev_workspace, size_t bytes,
+                                       void *hip_stream, lb_domain **out) {
   if (!out) return fail(LB_EINVAL, "out is null");
   *out = nullptr;
   lb_status s = validate(desc);
@@ -672,7 +697,12 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
   return LB_OK;
 }
 
-lb_status lb_set_obstacles(lb_domain *d, const uint8_t *mask, size_t n) {
+lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size_t bytes,
+                           void *hip_stream, lb_domain **out) {
+  LB_GUARDED(lb_create_domain_impl(desc, dev_workspace, bytes, hip_stream, out));
+}
+
+static lb_status lb_set_obstacles_impl(lb_domain *d, const uint8_t *mask, size_t n) {
   if (!d || !mask) return fail(LB_EINVAL, "null argument");
   if (!d->hd.label) return fail(LB_ESTATE, "domain was created without obstacles");
   if (d->np > 0) return fail(LB_ESTATE, "obstacles must be set before particles are added");
@@ -686,6 +716,10 @@ lb_status lb_set_obstacles(lb_domain *d, const uint8_t *mask, size_t n) {
       d->host_labels[(size_t)y * pitch + x] = (wall || mask[(size_t)y * nx + x]) ? LBL_SOLID : LBL_FLUID;
     }
   return upload_labels(d);
+}
+
+lb_status lb_set_obstacles(lb_domain *d, const uint8_t *mask, size_t n) {
+  LB_GUARDED(lb_set_obstacles_impl(d, mask, n));
 }
 
 namespace {
@@ -771,7 +805,7 @@ lb_status particles_changed(lb_domain *d) {
 
 }  // namespace
 
-lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_t *first_id) {
+static lb_status lb_add_particles_impl(lb_domain *d, const lb_particle *p, int32_t n, int32_t *first_id) {
   if (!d || (!p && n > 0)) return fail(LB_EINVAL, "null argument");
   if (d->in_batches) return fail(LB_ESTATE, "domain is in a batch");
   if (n < 0 || d->np + n > d->desc.max_particles) return fail(LB_EINVAL, "exceeds max_particles");
@@ -804,7 +838,11 @@ lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_
   return LB_OK;
 }
 
-lb_status lb_get_particle_state(lb_domain *d, lb_particle_state *out, int32_t n) {
+lb_status lb_add_particles(lb_domain *d, const lb_particle *p, int32_t n, int32_t *first_id) {
+  LB_GUARDED(lb_add_particles_impl(d, p, n, first_id));
+}
+
+static lb_status lb_get_particle_state_impl(lb_domain *d, lb_particle_state *out, int32_t n) {
   if (!d || (!out && n > 0)) return fail(LB_EINVAL, "null argument");
   if (n != d->np) return fail(LB_EINVAL, "n must equal the particle count");
   std::vector<PState> cur(std::max(n, 1));
@@ -828,7 +866,11 @@ lb_status lb_get_particle_state(lb_domain *d, lb_particle_state *out, int32_t n)
   return check_health(d);
 }
 
-lb_status lb_set_particle_state(lb_domain *d, const lb_particle_state *in, int32_t n) {
+lb_status lb_get_particle_state(lb_domain *d, lb_particle_state *out, int32_t n) {
+  LB_GUARDED(lb_get_particle_state_impl(d, out, n));
+}
+
+static lb_status lb_set_particle_state_impl(lb_domain *d, const lb_particle_state *in, int32_t n) {
   if (!d || (!in && n > 0)) return fail(LB_EINVAL, "null argument");
   if (d->in_batches) return fail(LB_ESTATE, "domain is in a batch");
   if (n < 0 || n > d->desc.max_particles) return fail(LB_EINVAL, "exceeds max_particles");
@@ -865,7 +907,11 @@ lb_status lb_set_particle_state(lb_domain *d, const lb_particle_state *in, int32
   return particles_changed(d);
 }
 
-lb_status lb_set_time(lb_domain *d, int64_t t) {
+lb_status lb_set_particle_state(lb_domain *d, const lb_particle_state *in, int32_t n) {
+  LB_GUARDED(lb_set_particle_state_impl(d, in, n));
+}
+
+static lb_status lb_set_time_impl(lb_domain *d, int64_t t) {
   if (!d) return fail(LB_EINVAL, "null domain");
   if (t < 0) return fail(LB_EINVAL, "t < 0");
   if (d->in_batches) return fail(LB_ESTATE, "domain is in a batch");
@@ -885,7 +931,11 @@ lb_status lb_set_time(lb_domain *d, int64_t t) {
   return refresh_mirrors(d);
 }
 
-lb_status lb_step(lb_domain *d, int64_t nsteps) {
+lb_status lb_set_time(lb_domain *d, int64_t t) {
+  LB_GUARDED(lb_set_time_impl(d, t));
+}
+
+static lb_status lb_step_impl(lb_domain *d, int64_t nsteps) {
   if (!d) return fail(LB_EINVAL, "null domain");
   if (nsteps < 0) return fail(LB_EINVAL, "nsteps < 0");
   if (nsteps > 0) {
@@ -912,15 +962,23 @@ lb_status lb_step(lb_domain *d, int64_t nsteps) {
   return LB_OK;
 }
 
-lb_status lb_moments_device(lb_domain *d, double *rho, double *ux, double *uy) {
+lb_status lb_step(lb_domain *d, int64_t nsteps) {
+  LB_GUARDED(lb_step_impl(d, nsteps));
+}
+
+static lb_status lb_moments_device_impl(lb_domain *d, double *rho, double *ux, double *uy) {
   if (!d || !rho || !ux || !uy) return fail(LB_EINVAL, "null argument");
   d->ks.moments(d->ddesc(), rho, ux, uy, 0, d->desc.ny, d->desc.nx, d->stream);
   HIPCHK(hipGetLastError());
   return LB_OK;
 }
 
-lb_status lb_moments_async(lb_domain *d, double *dev_stage, double *rho, double *ux, double *uy,
-                           void *copy_stream) {
+lb_status lb_moments_device(lb_domain *d, double *rho, double *ux, double *uy) {
+  LB_GUARDED(lb_moments_device_impl(d, rho, ux, uy));
+}
+
+static lb_status lb_moments_async_impl(lb_domain *d, double *dev_stage, double *rho, double *ux, double *uy,
+                                       void *copy_stream) {
   if (!d || !dev_stage || !rho || !ux || !uy) return fail(LB_EINVAL, "null argument");
   hipStream_t cs = (hipStream_t)copy_stream;
   if (cs == d->stream) return fail(LB_EINVAL, "the copy stream must differ from the domain's stream");
@@ -944,7 +1002,12 @@ lb_status lb_moments_async(lb_domain *d, double *dev_stage, double *rho, double 
   return LB_OK;
 }
 
-lb_status lb_moments_wait(lb_domain *d) {
+lb_status lb_moments_async(lb_domain *d, double *dev_stage, double *rho, double *ux, double *uy,
+                           void *copy_stream) {
+  LB_GUARDED(lb_moments_async_impl(d, dev_stage, rho, ux, uy, copy_stream));
+}
+
+static lb_status lb_moments_wait_impl(lb_domain *d) {
   if (!d) return fail(LB_EINVAL, "null domain");
   if (d->rep_pending) {
     HIPCHK(hipEventSynchronize(d->rep_copied));
@@ -953,7 +1016,11 @@ lb_status lb_moments_wait(lb_domain *d) {
   return LB_OK;
 }
 
-lb_status lb_moments(lb_domain *d, double *rho, double *ux, double *uy) {
+lb_status lb_moments_wait(lb_domain *d) {
+  LB_GUARDED(lb_moments_wait_impl(d));
+}
+
+static lb_status lb_moments_impl(lb_domain *d, double *rho, double *ux, double *uy) {
   if (!d || !rho || !ux || !uy) return fail(LB_EINVAL, "null argument");
   const int nx = d->desc.nx;
   double *st = (double *)(d->ws + d->L.stage);
@@ -970,7 +1037,11 @@ lb_status lb_moments(lb_domain *d, double *rho, double *ux, double *uy) {
   return check_health(d);
 }
 
-lb_status lb_get_particles(lb_domain *d, lb_particle *out, int32_t n) {
+lb_status lb_moments(lb_domain *d, double *rho, double *ux, double *uy) {
+  LB_GUARDED(lb_moments_impl(d, rho, ux, uy));
+}
+
+static lb_status lb_get_particles_impl(lb_domain *d, lb_particle *out, int32_t n) {
   if (!d || (!out && n > 0)) return fail(LB_EINVAL, "null argument");
   if (n < 0 || n > d->np) return fail(LB_EINVAL, "n exceeds the particle count");
   std::vector<PState> cur(std::max(n, 1));
@@ -990,13 +1061,21 @@ lb_status lb_get_particles(lb_domain *d, lb_particle *out, int32_t n) {
   return check_health(d);
 }
 
-lb_status lb_mass(lb_domain *d, double *total) {
+lb_status lb_get_particles(lb_domain *d, lb_particle *out, int32_t n) {
+  LB_GUARDED(lb_get_particles_impl(d, out, n));
+}
+
+static lb_status lb_mass_impl(lb_domain *d, double *total) {
   if (!d || !total) return fail(LB_EINVAL, "null argument");
   lb_status s = domain_mass_enqueue(d);
   if (s != LB_OK) return s;
   HIPCHK(hipMemcpyAsync(total, &d->dhdr()->mass, sizeof(double), hipMemcpyDeviceToHost, d->stream));
   HIPCHK(hipStreamSynchronize(d->stream));
   return check_health(d);
+}
+
+lb_status lb_mass(lb_domain *d, double *total) {
+  LB_GUARDED(lb_mass_impl(d, total));
 }
 
 // Partial sums of lb_mass_static: one fixed array per GPU, for callers that
@@ -1030,7 +1109,7 @@ lb_status scratch_on(int dev, double **out) {
 }
 }  // namespace
 
-lb_status lb_mass_static(lb_domain *d, double *dev_total) {
+static lb_status lb_mass_static_impl(lb_domain *d, double *dev_total) {
   if (!d || !dev_total) return fail(LB_EINVAL, "null argument");
   if (d->hd.mass_blocks > STATIC_MASS_PARTIALS)
     return fail(LB_EINVAL, "density sum needs more partial sums than the static array holds (" +
@@ -1044,7 +1123,11 @@ lb_status lb_mass_static(lb_domain *d, double *dev_total) {
   return LB_OK;
 }
 
-lb_status lb_set_mass_check(lb_domain *d, double rel_tol) {
+lb_status lb_mass_static(lb_domain *d, double *dev_total) {
+  LB_GUARDED(lb_mass_static_impl(d, dev_total));
+}
+
+static lb_status lb_set_mass_check_impl(lb_domain *d, double rel_tol) {
   if (!d) return fail(LB_EINVAL, "null domain");
   if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return fail(LB_EINVAL, "rel_tol must be finite and >= 0");
   double ref = 0.0;
@@ -1056,13 +1139,21 @@ lb_status lb_set_mass_check(lb_domain *d, double rel_tol) {
   return LB_OK;
 }
 
-lb_status lb_time(lb_domain *d, int64_t *t) {
+lb_status lb_set_mass_check(lb_domain *d, double rel_tol) {
+  LB_GUARDED(lb_set_mass_check_impl(d, rel_tol));
+}
+
+static lb_status lb_time_impl(lb_domain *d, int64_t *t) {
   if (!d || !t) return fail(LB_EINVAL, "null argument");
   *t = d->t;
   return LB_OK;
 }
 
-lb_status lb_get_populations(lb_domain *d, double *hf) {
+lb_status lb_time(lb_domain *d, int64_t *t) {
+  LB_GUARDED(lb_time_impl(d, t));
+}
+
+static lb_status lb_get_populations_impl(lb_domain *d, double *hf) {
   if (!d || !hf) return fail(LB_EINVAL, "null argument");
   const int nx = d->desc.nx, ny = d->desc.ny;
   double *st = (double *)(d->ws + d->L.stage);
@@ -1079,7 +1170,11 @@ lb_status lb_get_populations(lb_domain *d, double *hf) {
   return check_health(d);
 }
 
-lb_status lb_set_populations(lb_domain *d, const double *hf) {
+lb_status lb_get_populations(lb_domain *d, double *hf) {
+  LB_GUARDED(lb_get_populations_impl(d, hf));
+}
+
+static lb_status lb_set_populations_impl(lb_domain *d, const double *hf) {
   if (!d || !hf) return fail(LB_EINVAL, "null argument");
   const int nx = d->desc.nx, ny = d->desc.ny;
   double *st = (double *)(d->ws + d->L.stage);
@@ -1096,7 +1191,11 @@ lb_status lb_set_populations(lb_domain *d, const double *hf) {
   return refresh_mirrors(d);
 }
 
-lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
+lb_status lb_set_populations(lb_domain *d, const double *hf) {
+  LB_GUARDED(lb_set_populations_impl(d, hf));
+}
+
+static lb_status lb_set_option_impl(lb_domain *d, int32_t key, int64_t value) {
   if (!d) return fail(LB_EINVAL, "null domain");
   if (d->in_batches && (key == LB_OPT_TILE_WIDTH || key == LB_OPT_ROWS_PER_THREAD ||
                         key == LB_OPT_FORCE_AVERAGE || key == LB_OPT_TWO_STEP ||
@@ -1146,7 +1245,11 @@ lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
   return LB_OK;
 }
 
-lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value) {
+lb_status lb_set_option(lb_domain *d, int32_t key, int64_t value) {
+  LB_GUARDED(lb_set_option_impl(d, key, value));
+}
+
+static lb_status lb_get_option_impl(lb_domain *d, int32_t key, int64_t *value) {
   if (!d || !value) return fail(LB_EINVAL, "null argument");
   switch (key) {
     case LB_OPT_USE_GRAPH: *value = d->use_graph; return LB_OK;
@@ -1162,7 +1265,11 @@ lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value) {
   return fail(LB_EINVAL, "unknown option");
 }
 
-lb_status lb_autotune(lb_domain *d, int32_t steps, double *best_ms) {
+lb_status lb_get_option(lb_domain *d, int32_t key, int64_t *value) {
+  LB_GUARDED(lb_get_option_impl(d, key, value));
+}
+
+static lb_status lb_autotune_impl(lb_domain *d, int32_t steps, double *best_ms) {
   if (!d || steps < 1) return fail(LB_EINVAL, "bad argument");
   if (d->in_batches) return fail(LB_ESTATE, "domain is in a batch");
   hipEvent_t e0, e1;
@@ -1235,7 +1342,11 @@ lb_status lb_autotune(lb_domain *d, int32_t steps, double *best_ms) {
   return check_health(d);
 }
 
-lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms) {
+lb_status lb_autotune(lb_domain *d, int32_t steps, double *best_ms) {
+  LB_GUARDED(lb_autotune_impl(d, steps, best_ms));
+}
+
+static lb_status lb_batch_autotune_impl(lb_batch *b, int32_t steps, double *best_ms) {
   if (!b || steps < 1) return fail(LB_EINVAL, "bad argument");
   if (best_ms) *best_ms = 0.0;
   if (!b->two_step) return LB_OK;  // single steps: the members' own tiles
@@ -1271,7 +1382,11 @@ lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms) {
   return lb_batch_set_option(b, LB_OPT_TWO_STEP_ROWS, rows);
 }
 
-lb_status lb_destroy_domain(lb_domain *d) {
+lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms) {
+  LB_GUARDED(lb_batch_autotune_impl(b, steps, best_ms));
+}
+
+static lb_status lb_destroy_domain_impl(lb_domain *d) {
   if (!d) return fail(LB_EINVAL, "null domain");
   if (d->in_batches) return fail(LB_ESTATE, "destroy the batches that hold this domain first");
   (void)hipStreamSynchronize(d->stream);
@@ -1292,7 +1407,11 @@ lb_status lb_destroy_domain(lb_domain *d) {
   return LB_OK;
 }
 
-lb_status lb_batch_workspace_bytes(lb_domain *const *domains, int32_t n, size_t *bytes) {
+lb_status lb_destroy_domain(lb_domain *d) {
+  LB_GUARDED(lb_destroy_domain_impl(d));
+}
+
+static lb_status lb_batch_workspace_bytes_impl(lb_domain *const *domains, int32_t n, size_t *bytes) {
   if (!domains || n < 1 || !bytes) return fail(LB_EINVAL, "bad argument");
   size_t items = 0;
   for (int i = 0; i < n; ++i) {
@@ -1304,8 +1423,12 @@ lb_status lb_batch_workspace_bytes(lb_domain *const *domains, int32_t n, size_t 
   return LB_OK;
 }
 
-lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_workspace, size_t bytes,
-                          void *hip_stream, lb_batch **out) {
+lb_status lb_batch_workspace_bytes(lb_domain *const *domains, int32_t n, size_t *bytes) {
+  LB_GUARDED(lb_batch_workspace_bytes_impl(domains, n, bytes));
+}
+
+static lb_status lb_batch_create_impl(lb_domain *const *domains, int32_t n, void *dev_workspace, size_t bytes,
+                                      void *hip_stream, lb_batch **out) {
   if (!out) return fail(LB_EINVAL, "out is null");
   *out = nullptr;
   size_t need = 0;
@@ -1391,7 +1514,12 @@ lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_worksp
   return LB_OK;
 }
 
-lb_status lb_batch_step(lb_batch *b, int64_t nsteps) {
+lb_status lb_batch_create(lb_domain *const *domains, int32_t n, void *dev_workspace, size_t bytes,
+                          void *hip_stream, lb_batch **out) {
+  LB_GUARDED(lb_batch_create_impl(domains, n, dev_workspace, bytes, hip_stream, out));
+}
+
+static lb_status lb_batch_step_impl(lb_batch *b, int64_t nsteps) {
   if (!b) return fail(LB_EINVAL, "null batch");
   if (nsteps < 0) return fail(LB_EINVAL, "nsteps < 0");
   if (nsteps > 0) {
@@ -1415,7 +1543,11 @@ lb_status lb_batch_step(lb_batch *b, int64_t nsteps) {
   return LB_OK;
 }
 
-lb_status lb_batch_set_option(lb_batch *b, int32_t key, int64_t value) {
+lb_status lb_batch_step(lb_batch *b, int64_t nsteps) {
+  LB_GUARDED(lb_batch_step_impl(b, nsteps));
+}
+
+static lb_status lb_batch_set_option_impl(lb_batch *b, int32_t key, int64_t value) {
   if (!b) return fail(LB_EINVAL, "null batch");
   switch (key) {
     case LB_OPT_USE_GRAPH: b->use_graph = value != 0; break;
@@ -1450,7 +1582,11 @@ lb_status lb_batch_set_option(lb_batch *b, int32_t key, int64_t value) {
   return LB_OK;
 }
 
-lb_status lb_batch_get_option(lb_batch *b, int32_t key, int64_t *value) {
+lb_status lb_batch_set_option(lb_batch *b, int32_t key, int64_t value) {
+  LB_GUARDED(lb_batch_set_option_impl(b, key, value));
+}
+
+static lb_status lb_batch_get_option_impl(lb_batch *b, int32_t key, int64_t *value) {
   if (!b || !value) return fail(LB_EINVAL, "null argument");
   switch (key) {
     case LB_OPT_USE_GRAPH: *value = b->use_graph ? 1 : 0; return LB_OK;
@@ -1461,7 +1597,11 @@ lb_status lb_batch_get_option(lb_batch *b, int32_t key, int64_t *value) {
   return fail(LB_EINVAL, "option not available on a batch");
 }
 
-lb_status lb_batch_destroy(lb_batch *b) {
+lb_status lb_batch_get_option(lb_batch *b, int32_t key, int64_t *value) {
+  LB_GUARDED(lb_batch_get_option_impl(b, key, value));
+}
+
+static lb_status lb_batch_destroy_impl(lb_batch *b) {
   if (!b) return fail(LB_EINVAL, "null batch");
   (void)hipStreamSynchronize(b->stream);
   b->graphs.clear();
@@ -1471,9 +1611,13 @@ lb_status lb_batch_destroy(lb_batch *b) {
   return LB_OK;
 }
 
-lb_status lb_noise_normals(uint64_t seed, uint32_t domain_id, uint32_t step, uint32_t node0,
-                           uint32_t count, int32_t fp32_arithmetic, float *dev_out,
-                           void *hip_stream) {
+lb_status lb_batch_destroy(lb_batch *b) {
+  LB_GUARDED(lb_batch_destroy_impl(b));
+}
+
+static lb_status lb_noise_normals_impl(uint64_t seed, uint32_t domain_id, uint32_t step, uint32_t node0,
+                                       uint32_t count, int32_t fp32_arithmetic, float *dev_out,
+                                       void *hip_stream) {
   if (!dev_out && count > 0) return fail(LB_EINVAL, "null output");
   if (fp32_arithmetic != 0 && fp32_arithmetic != 1) return fail(LB_EINVAL, "fp32_arithmetic must be 0 or 1");
   if (count > (1u << 28)) return fail(LB_EINVAL, "count above 2^28");
@@ -1484,6 +1628,12 @@ lb_status lb_noise_normals(uint64_t seed, uint32_t domain_id, uint32_t step, uin
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   return LB_OK;
+}
+
+lb_status lb_noise_normals(uint64_t seed, uint32_t domain_id, uint32_t step, uint32_t node0,
+                           uint32_t count, int32_t fp32_arithmetic, float *dev_out,
+                           void *hip_stream) {
+  LB_GUARDED(lb_noise_normals_impl(seed, domain_id, step, node0, count, fp32_arithmetic, dev_out, hip_stream));
 }
 
 }  // extern "C"
