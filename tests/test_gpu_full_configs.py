@@ -360,7 +360,7 @@ def test_powerlaw_full_lattice_holds_the_closed_form(n, tol):
 
 # --- precision-and-batching stress: 8192^2 shear wave and the uneven batch
 
-@pytest.mark.parametrize("storage,rounding,tol", [("f32", "nearest", 1e-4), ("f16", "stochastic", 1e-4),
+@pytest.mark.parametrize("storage,rounding,tol", [("f32", "nearest", 1e-5), ("f16", "stochastic", 1e-4),
                                                   ("bf16", "stochastic", 1e-3)])
 def test_shear_wave_8192_decays_as_closed_form(storage, rounding, tol):
     """u_x = u0 sin(2 pi y / N) decays as exp(-nu k^2 t), nu = (tau - 1/2)/3;
@@ -368,9 +368,11 @@ def test_shear_wave_8192_decays_as_closed_form(storage, rounding, tol):
 
     The wave loses only 6e-5 of its amplitude in 1000 steps, 6e-10 per step,
     less than the spacing of the FP32 values that carry it (half an ulp of
-    |d_i| ~ 3e-3 is 1.2e-10, ~7e-10 in u): round-to-nearest storage repeats the
-    same rounding every step and can lag by up to 1000 x 7e-10 / 0.01 = 7e-5.
-    Stochastic rounding is unbiased, and its errors average out along x."""
+    |d_i| ~ 3e-3 is 1.2e-10, ~7e-10 in u).  FP32 storage with FP32 arithmetic
+    forms the small increment omega (feq - d) first and rounds d + increment
+    once, so the decay is carried (measured 1.9e-7; relaxing the stored value
+    directly lagged by 4.7e-5).  The 16-bit formats round stochastically:
+    unbiased, and the errors average out along x (FP16 1.5e-5, BF16 7.7e-5)."""
     from paper_2006_12910_amd import inputs, lb
     n, tau, u0, steps = 8192, 0.8, 0.01, 1000
     gpu = lb.Domain(n, n, tau=tau, storage=storage, rounding=rounding,
