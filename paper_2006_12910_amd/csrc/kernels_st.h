@@ -20,19 +20,19 @@ void sweep_l(const DevDomain *doms, const int *prefix, int ndom, int kstep, int 
   hipLaunchKernelGGL((k_sweep<ST, FEAT, PLM, WIDE>), dim3(blocks), dim3(256), 0, s, doms, prefix,
                      ndom, kstep, part);
 }
-template <int FEAT>
+template <int FEAT, int PLM>
 void sweep2_l(const DevDomain *doms, const int *prefix2, int ndom, int kstep, int which, int blocks,
               int rows, hipStream_t s) {
   constexpr int H0 = two_step_rows_of(ST, 0), H1 = two_step_rows_of(ST, 1),
                 H2 = two_step_rows_of(ST, 2);
   if (rows == H0)
-    hipLaunchKernelGGL((k_sweep2<ST, FEAT, H0>), dim3(blocks), dim3(256), 0, s, doms, prefix2,
+    hipLaunchKernelGGL((k_sweep2<ST, FEAT, H0, PLM>), dim3(blocks), dim3(256), 0, s, doms, prefix2,
                        ndom, kstep, which);
   else if (rows == H2)
-    hipLaunchKernelGGL((k_sweep2<ST, FEAT, H2>), dim3(blocks), dim3(256), 0, s, doms, prefix2,
+    hipLaunchKernelGGL((k_sweep2<ST, FEAT, H2, PLM>), dim3(blocks), dim3(256), 0, s, doms, prefix2,
                        ndom, kstep, which);
   else
-    hipLaunchKernelGGL((k_sweep2<ST, FEAT, H1>), dim3(blocks), dim3(256), 0, s, doms, prefix2,
+    hipLaunchKernelGGL((k_sweep2<ST, FEAT, H1, PLM>), dim3(blocks), dim3(256), 0, s, doms, prefix2,
                        ndom, kstep, which);
 }
 template <int FEAT, int PLM, int WIDE>
@@ -80,8 +80,13 @@ void mirror_l(const DevDomain *dom, int nx, int ny, hipStream_t s) {
 
 template <int FEAT, int PLM, int WIDE> void fill(KernelSet *k) {
   k->sweep = sweep_l<FEAT, PLM, WIDE>;
-  if constexpr ((FEAT & (F_NOISE | F_POWER)) == 0 && WIDE == 0) k->sweep2 = sweep2_l<FEAT>;
-  else k->sweep2 = nullptr;
+  // the two-step sweep: plain and obstacle (label) sweeps, and the power-law
+  // sweep of label domains (walls as solid label rows); not with noise
+  if constexpr ((FEAT & F_NOISE) == 0 && WIDE == 0 &&
+                ((FEAT & F_POWER) == 0 || (FEAT & F_LABELS) != 0))
+    k->sweep2 = sweep2_l<FEAT, PLM>;
+  else
+    k->sweep2 = nullptr;
   k->init = init_l<FEAT, PLM, WIDE>;
   k->pre = pre_l;
   k->post = post_l;

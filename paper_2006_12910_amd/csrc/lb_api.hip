@@ -65,7 +65,14 @@ int mass_blocks_of(int nx, int ny) {
                                    std::max<long long>(1, nodes / 1024)});
 }
 
-bool needs_labels(const lb_domain_desc *d) { return d->obstacles != 0 || d->max_particles > 0; }
+// A label plane holds obstacles, particles and walls.  Walls of a domain
+// without obstacles or particles could also be index walls (mirror writes, no
+// plane), but as solid label rows they let the two-step sweep run on
+// channels; only domains with a pressure face keep index walls.
+bool needs_labels(const lb_domain_desc *d) {
+  return d->obstacles != 0 || d->max_particles > 0 ||
+         ((d->bc_x == LB_WALL || d->bc_y == LB_WALL) && d->bc_x != LB_PRESSURE);
+}
 
 Layout layout_of(const lb_domain_desc *d) {
   Layout L;
@@ -465,9 +472,12 @@ lb_status run_steps(GraphCache &gc, bool use_graph, int chunk, hipStream_t strea
 // The two-step sweep serves periodic domains without particles whose kernel
 // set has one (no noise, no power law, native arithmetic), unless switched
 // off with LB_OPT_TWO_STEP.
+// The two-step sweep needs periodic edges or walls held as solid label rows
+// (its tiles wrap around the domain), and no particle or pressure face.
 bool two_step_ok(const lb_domain *d) {
-  return d->two_step && d->ks.sweep2 != nullptr && d->np == 0 && d->desc.max_particles == 0 &&
-         d->desc.bc_x == LB_PERIODIC && d->desc.bc_y == LB_PERIODIC;
+  const bool edges = (d->desc.bc_x == LB_PERIODIC && d->desc.bc_y == LB_PERIODIC) ||
+                     (d->hd.label != nullptr && d->desc.bc_x != LB_PRESSURE);
+  return d->two_step && d->ks.sweep2 != nullptr && d->np == 0 && d->desc.max_particles == 0 && edges;
 }
 
 // FP64 density sum of the current state; its final kernel also latches a
@@ -704,7 +714,7 @@ lb_status lb_create_domain(const lb_domain_desc *desc, void *dev_workspace, size
 
 static lb_status lb_set_obstacles_impl(lb_domain *d, const uint8_t *mask, size_t n) {
   if (!d || !mask) return fail(LB_EINVAL, "null argument");
-  if (!d->hd.label) return fail(LB_ESTATE, "domain was created without obstacles");
+  if (!d->desc.obstacles) return fail(LB_ESTATE, "domain was created without obstacles");
   if (d->np > 0) return fail(LB_ESTATE, "obstacles must be set before particles are added");
   if (d->in_batches) return fail(LB_ESTATE, "domain is in a batch");
   if (n != (size_t)d->desc.nx * d->desc.ny) return fail(LB_EINVAL, "mask size must be nx*ny");

@@ -32,7 +32,7 @@ __device__ __forceinline__ uint32_t sel_keep(uint32_t a, uint32_t b, uint32_t m,
   return __builtin_amdgcn_bitop3_b32(m, b, a, 0xCA) & keep;
 }
 
-template <int ST, int FEAT, int H>
+template <int ST, int FEAT, int H, int PLM = PL_GENERIC>
 __global__ __launch_bounds__(256) void k_sweep2(const DevDomain *__restrict__ doms,
                                                 const int *__restrict__ prefix, int ndom,
                                                 int kstep, int which) {
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_sweep2(const DevDomain *__restrict__ do
     for (int i = 0; i < 9; ++i) e[i] = (R)S::raw_dec(raw[u].get(i));
     const uint32_t node = (uint32_t)y * (uint32_t)nx + (uint32_t)xs;
     bad = bad || !(fabs(scaled_drho<ST, R>(e)) < R(1e30));
-    collide_node<ST, FEAT, PL_GENERIC, R>(D, e, node, step1);
+    collide_node<ST, FEAT, PLM, R>(D, e, node, step1);
     // the rounding mode is uniform: each branch keeps its own writes, so no
     // merged (packed) copy of the encoded values is formed
     auto emit = [&](auto sr_tag) {
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void k_sweep2(const DevDomain *__restrict__ do
     }
     const uint32_t node = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
     bad = bad || !(fabs(scaled_drho<ST, R>(e)) < R(1e30));
-    collide_node<ST, FEAT, PL_GENERIC, R>(D, e, node, step2);
+    collide_node<ST, FEAT, PLM, R>(D, e, node, step2);
     // Ordinary (cached) stores: a tile row is 62 values, so most 128-byte
     // lines are written in two parts by neighbouring workgroups, and the
     // cache merges the parts into one line write.  Streaming stores sent the

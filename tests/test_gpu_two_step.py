@@ -124,10 +124,30 @@ def test_two_step_batch_equals_single_steps():
             d.close()
 
 
+@pytest.mark.parametrize("storage,rounding", FORMATS)
+@pytest.mark.parametrize("power_law", [None, 0.5, 0.75, 1.5, 1.3])
+def test_two_step_with_walls_and_power_law_equals_single_steps(storage, rounding, power_law):
+    """Channels: walls held as solid label rows (walls in y, and in x too),
+    Newtonian or with the power-law relaxation time (every closed-form
+    specialisation and the generic Newton solve): two-step launches equal
+    single steps bit for bit."""
+    pl = None if power_law is None else dict(n=power_law, K=0.01, tau_min=0.51, tau_max=2.5)
+    for (nx, ny), walls in (((130, 77), dict(bc_y="wall")), ((64, 40), dict(bc_x="wall", bc_y="wall"))):
+        out = []
+        for two in (1, 0):
+            d = lb.Domain(nx, ny, tau=0.7, g=(3e-6, 0.0), storage=storage, rounding=rounding,
+                          power_law=pl, init=_fields(nx, ny, 9), seed=5, domain_id=2, **walls)
+            d.set_option(lb.OPT_TWO_STEP, two)
+            d.step(27)
+            out.append(d.populations())
+            d.close()
+        assert np.array_equal(out[0], out[1]), (storage, rounding, power_law, nx, ny)
+
+
 def test_two_step_not_taken_where_not_supported():
-    """Walls, particles or noise keep single steps: the option is accepted and
-    the results still equal the single-step ones."""
-    for kw in (dict(bc_y="wall"), dict(kT=1e-5)):
+    """Pressure faces, particles or noise keep single steps: the option is
+    accepted and the results still equal the single-step ones."""
+    for kw in (dict(bc_x="pressure", bc_y="wall", rho_in=1.001, rho_out=0.999), dict(kT=1e-5)):
         doms = []
         for two in (1, 0):
             d = lb.Domain(96, 40, tau=0.8, storage="f32", init=_fields(96, 40, 5), **kw)
