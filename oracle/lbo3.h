@@ -1,7 +1,8 @@
 /*
  * lbo3.h -- CPU oracle (FP64) of the D3Q19 lattice-Boltzmann step: BGK with
- * the velocity-shift body force (Sec. 2), pull streaming with periodic wrap,
- * halfway bounce-back on solid nodes.  TEST INFRASTRUCTURE ONLY.
+ * the velocity-shift body force (Sec. 2), or its two-relaxation-time (TRT)
+ * variant, pull streaming with periodic wrap, halfway bounce-back on solid
+ * nodes.  TEST INFRASTRUCTURE ONLY.
  *
  * Arrays: nodes [nz][ny][nx] (x fastest), populations [19][nz][ny][nx].
  * Step order: collide every fluid node, then pull-stream.  The reported
@@ -17,6 +18,11 @@ typedef struct {
   int32_t nx, ny, nz;
   int32_t wall_x, wall_y, wall_z; /* nonzero: the outermost planes are solid */
   double tau, rho0, gx, gy, gz;
+  /* trt nonzero: the symmetric part of each population pair relaxes with
+   * 1/tau, the antisymmetric part with 1/tau_minus, where
+   * (tau - 1/2)(tau_minus - 1/2) = magic */
+  int32_t trt;
+  double magic;
 } lbo3_params;
 
 typedef struct lbo3_sim lbo3_sim;

@@ -44,7 +44,7 @@ class _Params3(C.Structure):
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("wall_x", C.c_int32), ("wall_y", C.c_int32), ("wall_z", C.c_int32),
         ("tau", C.c_double), ("rho0", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
-        ("gz", C.c_double),
+        ("gz", C.c_double), ("trt", C.c_int32), ("magic", C.c_double),
     ]
 
 
@@ -270,10 +270,12 @@ class Oracle3:
     [nz][ny][nx]; populations [19][nz][ny][nx]."""
 
     def __init__(self, nx, ny, nz, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0), walls=(False, False, False),
-                 obstacles=None, init=None):
+                 obstacles=None, init=None, collision="bgk", magic=3.0 / 16.0):
+        """collision "trt": two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic."""
         lib = _load()
         self.nx, self.ny, self.nz = nx, ny, nz
-        c = _Params3(nx, ny, nz, int(walls[0]), int(walls[1]), int(walls[2]), tau, rho0, *g)
+        c = _Params3(nx, ny, nz, int(walls[0]), int(walls[1]), int(walls[2]), tau, rho0, *g,
+                     int(collision == "trt"), magic)
         shape = (nz, ny, nx)
         mask = None
         if obstacles is not None:

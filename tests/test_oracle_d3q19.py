@@ -3,7 +3,9 @@ paper names as its next step, Sec. 8, with the BGK collision and the
 velocity-shift forcing of Sec. 2): lattice isotropy, equilibrium moments,
 exact conservation, the exact discrete steady solution of plane Poiseuille
 flow, shear-wave decay at the BGK viscosity and the series solution of
-square-duct flow with second-order convergence."""
+square-duct flow with second-order convergence; for the two-relaxation-time
+variant, its reduction to BGK, its conservation and the walls exactly
+halfway at the magic number 3/16."""
 import numpy as np
 
 from oracle.oracle import Oracle3, lattice3
@@ -128,3 +130,67 @@ def test_square_duct_flow_converges_to_the_series_solution():
         errs.append(np.sqrt(((u - ref) ** 2).sum() / (ref ** 2).sum()))
     assert errs[1] < 1.5e-3
     assert errs[0] / errs[1] > 3.0  # second order in the lattice spacing
+
+
+# --- two-relaxation-time (TRT) collision ----------------------------------
+
+def test_trt_with_the_bgk_magic_number_is_bgk():
+    """With magic = (tau - 1/2)^2 the antisymmetric parts relax at 1/tau too:
+    the TRT collision is the BGK one (only the rounding order differs)."""
+    rng = np.random.default_rng(11)
+    n = (9, 7, 6)
+    init = (1 + 0.01 * rng.standard_normal(n[::-1]), 0.02 * rng.standard_normal(n[::-1]),
+            0.01 * rng.standard_normal(n[::-1]), 0.0)
+    tau = 0.83
+    a = Oracle3(*n, tau=tau, g=(1e-5, 0.0, -2e-6), walls=(False, True, False), init=init)
+    b = Oracle3(*n, tau=tau, g=(1e-5, 0.0, -2e-6), walls=(False, True, False), init=init,
+                collision="trt", magic=(tau - 0.5) ** 2)
+    a.run(50)
+    b.run(50)
+    assert np.abs(a.populations() - b.populations()).max() < 1e-15
+
+
+def test_trt_conserves_mass_and_adds_the_body_force():
+    """The TRT step conserves mass and adds g times the fluid mass to the
+    momentum each step (the force shifts u_eq by tau_minus g, and only the
+    antisymmetric parts carry momentum)."""
+    rng = np.random.default_rng(12)
+    n = (10, 9, 8)
+    g = np.array([2e-5, -1e-5, 3e-6])
+    o = Oracle3(*n, tau=0.62, g=tuple(g), collision="trt", magic=0.25,
+                init=(1 + 0.01 * rng.standard_normal(n[::-1]), 0.01 * rng.standard_normal(n[::-1]),
+                      0.005 * rng.standard_normal(n[::-1]), 0.0))
+    m0 = o.mass()
+    for _ in range(5):
+        j0 = o.momentum()
+        o.run(1)
+        np.testing.assert_allclose(o.momentum() - j0, g * o.mass(), rtol=1e-11, atol=1e-14)
+    assert abs(o.mass() - m0) / m0 < 1e-14
+
+
+def test_trt_magic_3_16_puts_the_poiseuille_walls_exactly_halfway():
+    """TRT with magic = 3/16 and halfway bounce-back gives plane Poiseuille
+    flow with the walls exactly halfway between the solid and the first fluid
+    plane, whatever tau (Ginzburg and d'Humieres' result for the TRT
+    bounce-back): the steady profile is the parabola
+    g/(2 nu) (z - 1/2)(nz - 3/2 - z), nu = (tau - 1/2)/3, with no slip term.
+    BGK (magic = (tau - 1/2)^2) keeps a tau-dependent slip, which this
+    check also sees."""
+    nz, g = 34, 1e-6
+    z = np.arange(1, nz - 1)
+    for tau in (0.7, 0.9, 1.8):
+        nu = (tau - 0.5) / 3
+        parabola = g / (2 * nu) * (z - 0.5) * (nz - 1.5 - z)
+        o = Oracle3(4, 4, nz, tau=tau, g=(g, 0.0, 0.0), walls=(False, False, True),
+                    collision="trt", magic=3.0 / 16.0)
+        o.run(50000 if tau < 0.8 else 30000)  # to steady state: ~ nz^2 / (pi^2 nu) per e-fold
+        _, ux, _, _ = o.moments()
+        dev = np.abs(ux[1:-1] - parabola[:, None, None]).max() / parabola.max()
+        assert dev < 1e-10, (tau, dev)
+    # BGK at tau = 1.8: slip g (16 (tau - 1/2)^2 - 3)/(24 nu) ~ 1e-2 of the peak
+    o = Oracle3(4, 4, nz, tau=1.8, g=(g, 0.0, 0.0), walls=(False, False, True))
+    o.run(30000)
+    _, ux, _, _ = o.moments()
+    nu = 1.3 / 3
+    parabola = g / (2 * nu) * (z - 0.5) * (nz - 1.5 - z)
+    assert np.abs(ux[1:-1] - parabola[:, None, None]).max() / parabola.max() > 1e-3
