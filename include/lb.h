@@ -384,9 +384,18 @@ lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms);
  * Host node arrays are [nz][ny][nx] (x fastest), populations
  * [19][nz][ny][nx].  Storage: LB_F64 or LB_F32 deviations f_i - w_i rho0
  * (FP32 arithmetic with FP32 storage, its increment holding exactly the
- * collision's mass and momentum change).  Same conventions as above:
- * caller-owned 256-byte aligned workspace, stream-ordered calls, errors
- * through lb_last_error.  No particles, noise or power law. */
+ * collision's mass and momentum change).  Collision: BGK, or the
+ * two-relaxation-time (TRT) variant, in which the parts of each population
+ * pair symmetric and antisymmetric under e -> -e relax with 1/tau and
+ * 1/tau_minus, (tau - 1/2)(tau_minus - 1/2) = magic, and the body force
+ * shifts the equilibrium velocity by tau_minus g (the antisymmetric parts
+ * carry the momentum); magic = 3/16 puts halfway bounce-back walls of a
+ * channel exactly halfway whatever tau, magic = (tau - 1/2)^2 is BGK.  Same
+ * conventions as above: caller-owned 256-byte aligned workspace,
+ * stream-ordered calls, errors through lb_last_error.  No particles, noise
+ * or power law. */
+#define LB3_BGK 0
+#define LB3_TRT 1
 typedef struct lb3_domain_desc {
   uint32_t abi_version;        /* LB_ABI_VERSION                                  */
   int32_t nx, ny, nz;          /* each in [3, 4096], with 19 nz ny pitch < 2^31   */
@@ -398,6 +407,8 @@ typedef struct lb3_domain_desc {
   double rho0, tau;            /* reference density (> 0), relaxation time (> 1/2) */
   double gx, gy, gz;           /* body acceleration                               */
   const double *init_rho, *init_ux, *init_uy, *init_uz;  /* host [nz][ny][nx], copied */
+  int32_t collision;           /* LB3_BGK | LB3_TRT                               */
+  double magic;                /* TRT: (tau - 1/2)(tau_minus - 1/2), > 0          */
 } lb3_domain_desc;
 typedef struct lb3_domain lb3_domain;
 

@@ -79,6 +79,10 @@ lb_status validate3(const lb3_domain_desc *d) {
   if (19.0 * d->nz * d->ny * ((d->nx + 63) / 64 * 64) >= 2147483648.0)
     return fail3(LB_EINVAL, "lattice too large: 19 nz ny pitch must stay below 2^31");
   if (!(d->tau > 0.5)) return fail3(LB_EINVAL, "tau must be > 1/2");
+  if (d->collision != LB3_BGK && d->collision != LB3_TRT)
+    return fail3(LB_EINVAL, "collision must be LB3_BGK or LB3_TRT");
+  if (d->collision == LB3_TRT && !(d->magic > 0.0 && std::isfinite(d->magic)))
+    return fail3(LB_EINVAL, "TRT magic number must be finite and > 0");
   if (!(d->rho0 > 0.0) || !std::isfinite(d->rho0)) return fail3(LB_EINVAL, "rho0 must be > 0");
   if (!std::isfinite(d->gx) || !std::isfinite(d->gy) || !std::isfinite(d->gz))
     return fail3(LB_EINVAL, "g not finite");
@@ -222,6 +226,11 @@ static lb_status lb3_create_domain_impl(const lb3_domain_desc *desc, void *dev_w
   h.rho0 = desc->rho0;
   h.tau = desc->tau;
   h.omega = 1.0 / desc->tau;
+  h.trt = desc->collision == LB3_TRT ? 1 : 0;
+  h.tau_m = h.trt ? 0.5 + desc->magic / (desc->tau - 0.5) : desc->tau;
+  h.omega_m = 1.0 / h.tau_m;
+  h.tau_m_f = (float)h.tau_m;
+  h.omega_m_f = (float)h.omega_m;
   h.gx = desc->gx;
   h.gy = desc->gy;
   h.gz = desc->gz;

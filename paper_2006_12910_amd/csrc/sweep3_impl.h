@@ -46,8 +46,11 @@ struct Dom3 {
   int nx, ny, nz, pitch;
   int storage;         // 0 FP64, 1 FP32
   int tiles_x, tiles_y;  // 64 x 4 node tiles of one z plane
+  int trt;               // two relaxation times (else BGK: tau_m = tau)
   double rho0, tau, omega, gx, gy, gz;
+  double tau_m, omega_m;  // relaxation of the antisymmetric parts
   float rho0_f, tau_f, omega_f, gx_f, gy_f, gz_f;
+  float tau_m_f, omega_m_f;
 };
 
 template <class R> __device__ __forceinline__ R par3(double a, float b);
@@ -56,14 +59,17 @@ template <> __device__ __forceinline__ float par3<float>(double, float b) { retu
 __device__ __forceinline__ float fmr(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmr(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// BGK collision of one node in deviation form.  The equilibrium of Eq. LB2
-// with u = J / rho, J = j + rho tau g: opposite velocities share the even
-// part c and take c +- 3 w (e.J); the rest population is delta rho less the
-// other eighteen.  FP32 arithmetic forms the increment omega (feq - d) and
-// gives it exactly the method's mass (zero) and momentum (rho g) from sums
-// of the small increments before the one final rounding, as the D2Q9 sweep
-// does (the momentum term of the stored values would otherwise round the
-// body force of slow flows with a bias).
+// BGK or TRT collision of one node in deviation form.  The equilibrium of
+// Eq. LB2 with u = J / rho, J = j + rho tau_m g (tau_m = tau for BGK):
+// opposite velocities share the even part c and take c +- 3 w (e.J); the
+// rest population is delta rho less the other eighteen.  BGK relaxes every
+// d_i with omega; TRT relaxes the part of (feq - d) symmetric over a pair
+// with omega and the antisymmetric part with omega_m (the rest population is
+// symmetric).  FP32 arithmetic forms the increment and gives it exactly the
+// method's mass (zero) and momentum (rho g) from sums of the small
+// increments before the one final rounding, as the D2Q9 sweep does (the
+// momentum term of the stored values would otherwise round the body force
+// of slow flows with a bias).
 template <class R> __device__ __forceinline__ void collide3(const Dom3 &D, R d[19]) {
   R drho = d[0];
 #pragma unroll
@@ -78,7 +84,8 @@ template <class R> __device__ __forceinline__ void collide3(const Dom3 &D, R d[1
   }
   const R rho = par3<R>(D.rho0, D.rho0_f) + drho;
   const R irho = R(1) / rho;
-  const R tau = par3<R>(D.tau, D.tau_f), om = par3<R>(D.omega, D.omega_f);
+  const R tau = par3<R>(D.tau_m, D.tau_m_f), om = par3<R>(D.omega, D.omega_f);
+  const R omm = par3<R>(D.omega_m, D.omega_m_f);
   const R gx = par3<R>(D.gx, D.gx_f), gy = par3<R>(D.gy, D.gy_f), gz = par3<R>(D.gz, D.gz_f);
   const R rt = rho * tau;
   const R Jx = fmr(rt, gx, jx), Jy = fmr(rt, gy, jy), Jz = fmr(rt, gz, jz);
@@ -98,8 +105,18 @@ template <class R> __device__ __forceinline__ void collide3(const Dom3 &D, R d[1
   }
   if constexpr (sizeof(R) == 4) {
     R inc[19];
+    if (D.trt) {
 #pragma unroll
-    for (int i = 1; i < 19; ++i) inc[i] = om * (eq[i] - d[i]);
+      for (int i = 1; i < 19; i += 2) {
+        const R a = eq[i] - d[i], b = eq[i + 1] - d[i + 1];
+        const R sym = R(0.5) * (a + b), anti = R(0.5) * (a - b);
+        inc[i] = fmr(om, sym, omm * anti);
+        inc[i + 1] = fmr(om, sym, -(omm * anti));
+      }
+    } else {
+#pragma unroll
+      for (int i = 1; i < 19; ++i) inc[i] = om * (eq[i] - d[i]);
+    }
     R sx = R(0), sy = R(0), sz = R(0);
 #pragma unroll
     for (int i = 1; i < 19; i += 2) {
@@ -127,8 +144,19 @@ template <class R> __device__ __forceinline__ void collide3(const Dom3 &D, R d[1
 #pragma unroll
     for (int i = 1; i < 19; i += 2) s += eq[i] + eq[i + 1];
     eq[0] = drho - s;
+    if (D.trt) {
+      d[0] = fmr(om, eq[0] - d[0], d[0]);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = fmr(om, eq[i] - d[i], d[i]);
+      for (int i = 1; i < 19; i += 2) {
+        const R a = eq[i] - d[i], b = eq[i + 1] - d[i + 1];
+        const R sym = R(0.5) * (a + b), anti = R(0.5) * (a - b);
+        d[i] += fmr(om, sym, omm * anti);
+        d[i + 1] += fmr(om, sym, -(omm * anti));
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 19; ++i) d[i] = fmr(om, eq[i] - d[i], d[i]);
+    }
   }
 }
 

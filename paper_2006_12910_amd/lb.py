@@ -20,6 +20,7 @@ F64, F32, F16_DELTA, BF16_DELTA = 0, 1, 2, 3
 ROUND_NEAREST, ROUND_STOCHASTIC = 0, 1
 COMPUTE_NATIVE, COMPUTE_F64 = 0, 1
 INIT_REST, INIT_FIELDS = 0, 1
+LB3_BGK, LB3_TRT = 0, 1  # D3Q19 collisions
 PARTICLE_FIXED = 1
 OPT_USE_GRAPH, OPT_TILE_WIDTH, OPT_ROWS_PER_THREAD, OPT_GRAPH_CHUNK, OPT_FORCE_AVERAGE = 1, 2, 3, 4, 5
 OPT_TWO_STEP = 6
@@ -73,6 +74,7 @@ class Domain3Desc(C.Structure):
         ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double),
         ("init_rho", C.POINTER(C.c_double)), ("init_ux", C.POINTER(C.c_double)),
         ("init_uy", C.POINTER(C.c_double)), ("init_uz", C.POINTER(C.c_double)),
+        ("collision", C.c_int32), ("magic", C.c_double),
     ]
 
 
@@ -450,10 +452,13 @@ class Domain3:
 
     def __init__(self, nx, ny, nz, *, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0),
                  walls=(False, False, False), storage="f32", obstacles=None, init=None,
-                 device="cuda", stream=None):
+                 collision="bgk", magic=3.0 / 16.0, device="cuda", stream=None):
+        """collision "trt": two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic."""
         lib = library()
         d = Domain3Desc()
         d.abi_version = ABI_VERSION
+        d.collision = {"bgk": LB3_BGK, "trt": LB3_TRT}[collision]
+        d.magic = float(magic)
         d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
         d.wall_x, d.wall_y, d.wall_z = (int(bool(w)) for w in walls)
         d.storage = {"f64": F64, "f32": F32}[storage]

@@ -114,6 +114,7 @@ def _desc3(**kw):
     (dict(storage=2), "storage"), (dict(init_kind=1), "INIT_FIELDS"), (dict(rho0=0.0), "rho0"),
     # 32-bit element offsets in the sweep: 19 nz ny pitch below 2^31
     (dict(nx=1024, ny=1024, nz=128), "too large"),
+    (dict(collision=2), "collision"), (dict(collision=1, magic=0.0), "magic"),
 ])
 def test_d3q19_validation_errors(bad, msg):
     from paper_2006_12910_amd import lb

@@ -1,9 +1,10 @@
 """GPU vs oracle parity of the D3Q19 sweep (the 3D lattice of Sec. 8 with the
-BGK collision and velocity-shift forcing of Sec. 2): FP64 storage to
-accumulated rounding, FP32 to the 1e-5 target, on ragged lattices with walls
-and spherical obstacles; the exact discrete plane Poiseuille state; the
-closed-form shear-wave decay and exact mass conservation at the benchmark
-size (256^3)."""
+BGK collision and velocity-shift forcing of Sec. 2, and the two-relaxation-
+time variant): FP64 storage to accumulated rounding, FP32 to the 1e-5
+target, on ragged lattices with walls and spherical obstacles; the exact
+discrete plane Poiseuille state (BGK) and the walls exactly halfway (TRT,
+magic 3/16); the closed-form shear-wave decay and exact mass conservation
+at the benchmark size (256^3)."""
 import numpy as np
 import pytest
 
@@ -41,19 +42,23 @@ def _velocity_error(gpu, ora):
 
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-5)])
 @pytest.mark.parametrize("shape", [(70, 33, 21), (64, 16, 9), (130, 7, 5)])
-def test_d3q19_against_oracle(storage, tol, shape):
+@pytest.mark.parametrize("collision", [dict(), dict(collision="trt", magic=3.0 / 16.0),
+                                       dict(collision="trt", magic=0.4)])
+def test_d3q19_against_oracle(storage, tol, shape, collision):
+    """BGK and the two-relaxation-time collision (magic 3/16, and 0.4)."""
     from paper_2006_12910_amd import lb
     nx, ny, nz = shape
     mask = _spheres(nx, ny, nz, nx + ny)
     init = _fields(nx, ny, nz, nz)
-    kw = dict(tau=0.7, g=(2e-5, -1e-5, 5e-6), walls=(False, False, True))
+    kw = dict(tau=0.7, g=(2e-5, -1e-5, 5e-6), walls=(False, False, True), **collision)
     gpu = lb.Domain3(nx, ny, nz, storage=storage, obstacles=mask, init=init, **kw)
     ora = Oracle3(nx, ny, nz, obstacles=mask, init=init, **kw)
     for n in (1, 7, 52):
         gpu.step(n)
         ora.run(n)
         drho, err, emax = _velocity_error(gpu, ora)
-        print(f"D3Q19 {storage} {shape} step {gpu.time}: drho {drho:.2e} err {err:.2e} max {emax:.2e}")
+        print(f"D3Q19 {storage} {shape} {collision} step {gpu.time}: drho {drho:.2e} err {err:.2e} "
+              f"max {emax:.2e}")
         assert drho < (1e-13 if storage == "f64" else 1e-6) and err < tol and emax < 10 * tol, \
             (n, drho, err, emax)
     assert gpu.time == 60
@@ -77,6 +82,26 @@ def test_d3q19_plane_poiseuille_exact_steady_state():
     print(f"D3Q19 plane Poiseuille: max deviation from the exact profile {dev:.2e}")
     assert dev < 1e-10
     gpu.close()
+
+
+def test_d3q19_trt_poiseuille_walls_exactly_halfway():
+    """TRT with magic 3/16 (FP64 storage): the steady channel profile is the
+    parabola with the walls exactly halfway, without the BGK slip term,
+    for two relaxation times (the oracle's pin, on the GPU)."""
+    from paper_2006_12910_amd import lb
+    nz, g = 34, 1e-6
+    z = np.arange(1, nz - 1)
+    for tau in (0.9, 1.8):
+        gpu = lb.Domain3(64, 4, nz, tau=tau, g=(g, 0.0, 0.0), walls=(False, False, True),
+                         storage="f64", collision="trt", magic=3.0 / 16.0)
+        gpu.step(30000)
+        _, ux, _, _ = gpu.moments()
+        nu = (tau - 0.5) / 3
+        parabola = g / (2 * nu) * (z - 0.5) * (nz - 1.5 - z)
+        dev = np.abs(ux[1:-1] - parabola[:, None, None]).max() / parabola.max()
+        print(f"D3Q19 TRT plane Poiseuille tau {tau}: max deviation from the parabola {dev:.2e}")
+        assert dev < 1e-10
+        gpu.close()
 
 
 def test_d3q19_256_cube_shear_wave_and_mass():
