@@ -435,15 +435,18 @@ def other_configs():
     d, _, _ = powerlaw_channel("f32")
     gpu_rate("powerlaw_4096x256_n0.5_f32", d, 4096 * 256, 2000)
     d.close()
-    # the D3Q19 lattice: 256^3 periodic, FP32 storage, one sweep per step;
-    # algorithmic bytes 2 x 19 x 4 per node update
+    # the D3Q19 lattice: 256^3 periodic, one sweep per step, FP32 storage and
+    # FP16 deviations (stochastic rounding); algorithmic bytes 2 x 19 x 4 and
+    # 2 x 19 x 2 per node update
     n3 = 256
-    d, _, _ = d3q19_cube("f32", n3)
-    gpu_rate("d3q19_256cube_f32", d, n3 ** 3, 200)
-    d.close()
-    r = out["d3q19_256cube_f32"]
-    r["sweep_GBps"] = round(r["gpu_mlups"] * 1e6 * 152 / 1e9, 1)
-    r["hbm_frac"] = round(r["sweep_GBps"] / HBM_PEAK_GBS, 4)
+    for storage, per_node in (("f32", 152), ("f16", 76)):
+        d, _, _ = d3q19_cube(storage, n3)
+        name = f"d3q19_256cube_{storage}"
+        gpu_rate(name, d, n3 ** 3, 200)
+        d.close()
+        r = out[name]
+        r["sweep_GBps"] = round(r["gpu_mlups"] * 1e6 * per_node / 1e9, 1)
+        r["hbm_frac"] = round(r["sweep_GBps"] / HBM_PEAK_GBS, 4)
     torch.cuda.empty_cache()
     return out
 
@@ -485,9 +488,10 @@ def powerlaw_channel(storage="f32"):
 
 
 def d3q19_cube(storage="f32", n=256):
-    """The D3Q19 lattice: 256^3 periodic, tau = 0.8, at rest."""
+    """The D3Q19 lattice: 256^3 periodic, tau = 0.8, at rest (16-bit storage
+    with stochastic rounding)."""
     from paper_2006_12910_amd import lb
-    d = lb.Domain3(n, n, n, tau=0.8, storage=storage)
+    d = lb.Domain3(n, n, n, tau=0.8, storage=storage, seed=3)
     return d, [d], n ** 3
 
 
@@ -496,7 +500,8 @@ def only_workload(name, steps, warmup):
     prints one JSON line."""
     import torch
     make = {"fluct-ensemble": fluct_ensemble, "fluct-ensemble-f16": lambda: fluct_ensemble("f16"),
-            "porous": porous_discs, "powerlaw": powerlaw_channel, "d3q19": d3q19_cube}[name]
+            "porous": porous_discs, "powerlaw": powerlaw_channel, "d3q19": d3q19_cube,
+            "d3q19-f16": lambda: d3q19_cube("f16")}[name]
     runner, doms, sites = make()
     runner.step(max(warmup, 1))
     torch.cuda.synchronize()
@@ -710,7 +715,8 @@ def main():
                     help='tile shape per size class instead of tuning, e.g. the "tiles" object of an '
                          'earlier line (to profile the configuration that line measured)')
     ap.add_argument("--only", default=None,
-                    choices=["fluct-ensemble", "fluct-ensemble-f16", "porous", "powerlaw", "d3q19"],
+                    choices=["fluct-ensemble", "fluct-ensemble-f16", "porous", "powerlaw", "d3q19",
+                             "d3q19-f16"],
                     help="time one other workload alone (GPU only; for profiling) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="before the workload, copy a buffer of this size 5 times (a kernel of "

@@ -382,9 +382,13 @@ lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms);
  * (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1),
  * (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1) (opposites in consecutive pairs).
  * Host node arrays are [nz][ny][nx] (x fastest), populations
- * [19][nz][ny][nx].  Storage: LB_F64 or LB_F32 deviations f_i - w_i rho0
- * (FP32 arithmetic with FP32 storage, its increment holding exactly the
- * collision's mass and momentum change).  Collision: BGK, or the
+ * [19][nz][ny][nx].  Storage: deviations f_i - w_i rho0 as LB_F64, LB_F32,
+ * or the 16-bit LB_F16_DELTA / LB_BF16_DELTA (Sec. 3's reduced-precision
+ * storage carried to D3Q19: the stored value is the deviation times 2, 16,
+ * 32 for the rest, axis and edge directions, rounded to nearest or
+ * stochastically with bits hashed from (node, step, seed)); arithmetic FP64
+ * for LB_F64 and FP32 otherwise, the FP32 increment holding exactly the
+ * collision's mass and momentum change before the one rounding to storage.  Collision: BGK, or the
  * two-relaxation-time (TRT) variant, in which the parts of each population
  * pair symmetric and antisymmetric under e -> -e relax with 1/tau and
  * 1/tau_minus, (tau - 1/2)(tau_minus - 1/2) = magic, and the body force
@@ -398,10 +402,10 @@ lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms);
 #define LB3_TRT 1
 typedef struct lb3_domain_desc {
   uint32_t abi_version;        /* LB_ABI_VERSION                                  */
-  int32_t nx, ny, nz;          /* each in [3, 4096], with 19 nz ny pitch < 2^31   */
-                               /* (pitch = nx rounded up to 64; 460^3 fits)       */
+  int32_t nx, ny, nz;          /* each in [3, 4096]; rows padded to a pitch of nx */
+                               /* rounded up to 64 nodes                          */
   int32_t wall_x, wall_y, wall_z;  /* nonzero: the outermost planes are solid    */
-  int32_t storage;             /* LB_F64 | LB_F32                                 */
+  int32_t storage;             /* LB_F64 | LB_F32 | LB_F16_DELTA | LB_BF16_DELTA  */
   int32_t obstacles;           /* nonzero: lb3_set_obstacles may be called        */
   int32_t init_kind;           /* LB_INIT_REST | LB_INIT_FIELDS                   */
   double rho0, tau;            /* reference density (> 0), relaxation time (> 1/2) */
@@ -409,6 +413,8 @@ typedef struct lb3_domain_desc {
   const double *init_rho, *init_ux, *init_uy, *init_uz;  /* host [nz][ny][nx], copied */
   int32_t collision;           /* LB3_BGK | LB3_TRT                               */
   double magic;                /* TRT: (tau - 1/2)(tau_minus - 1/2), > 0          */
+  int32_t rounding;            /* LB_ROUND_NEAREST | LB_ROUND_STOCHASTIC (16-bit) */
+  uint64_t seed;               /* stochastic-rounding key                         */
 } lb3_domain_desc;
 typedef struct lb3_domain lb3_domain;
 
@@ -428,6 +434,13 @@ lb_status lb3_get_populations(lb3_domain *d, double *host_dev_f);
 /* FP64 sum of rho over the non-solid nodes (fixed order).  Synchronises. */
 lb_status lb3_mass(lb3_domain *d, double *total);
 lb_status lb3_time(lb3_domain *d, int64_t *t);
+/* The sweep addresses populations with 32-bit byte offsets while the 19
+ * population planes of one buffer stay below 2^32 bytes, with 64-bit offsets
+ * above.  value 1 forces the 64-bit form on any lattice (the two give
+ * identical states; for testing), 0 restores the 32-bit form where it
+ * applies (LB_EINVAL where the buffer is too large for it). */
+#define LB3_OPT_WIDE_OFFSETS 1
+lb_status lb3_set_option(lb3_domain *d, int32_t option, int64_t value);
 lb_status lb3_destroy_domain(lb3_domain *d);
 
 const char *lb_status_string(lb_status s);

@@ -53,7 +53,7 @@ Layout3 layout3(const lb3_domain_desc *d) {
   Layout3 L;
   L.pitch = (d->nx + 63) / 64 * 64;
   const size_t nodes = (size_t)d->nz * d->ny * L.pitch;
-  const size_t fbytes = 19 * nodes * (d->storage == LB_F64 ? 8 : 4);
+  const size_t fbytes = 19 * nodes * (d->storage == LB_F64 ? 8 : d->storage == LB_F32 ? 4 : 2);
   L.solids = d->obstacles || d->wall_x || d->wall_y || d->wall_z;
   size_t o = 0;
   L.desc = o; o += al256(sizeof(Dom3));
@@ -73,11 +73,14 @@ lb_status validate3(const lb3_domain_desc *d) {
   if (d->abi_version != LB_ABI_VERSION) return fail3(LB_EINVAL, "abi_version mismatch");
   if (d->nx < 3 || d->ny < 3 || d->nz < 3 || d->nx > 4096 || d->ny > 4096 || d->nz > 4096)
     return fail3(LB_EINVAL, "nx, ny, nz must be in [3, 4096]");
-  if (d->storage != LB_F64 && d->storage != LB_F32)
-    return fail3(LB_EINVAL, "storage must be LB_F64 or LB_F32");
-  // the sweep indexes a population buffer with 32-bit element offsets
-  if (19.0 * d->nz * d->ny * ((d->nx + 63) / 64 * 64) >= 2147483648.0)
-    return fail3(LB_EINVAL, "lattice too large: 19 nz ny pitch must stay below 2^31");
+  if (d->storage != LB_F64 && d->storage != LB_F32 && d->storage != LB_F16_DELTA &&
+      d->storage != LB_BF16_DELTA)
+    return fail3(LB_EINVAL, "storage must be LB_F64, LB_F32, LB_F16_DELTA or LB_BF16_DELTA");
+  if (d->rounding != LB_ROUND_NEAREST && d->rounding != LB_ROUND_STOCHASTIC)
+    return fail3(LB_EINVAL, "rounding must be LB_ROUND_NEAREST or LB_ROUND_STOCHASTIC");
+  if (d->rounding == LB_ROUND_STOCHASTIC && d->storage != LB_F16_DELTA &&
+      d->storage != LB_BF16_DELTA)
+    return fail3(LB_EINVAL, "stochastic rounding needs LB_F16_DELTA or LB_BF16_DELTA storage");
   if (!(d->tau > 0.5)) return fail3(LB_EINVAL, "tau must be > 1/2");
   if (d->collision != LB3_BGK && d->collision != LB3_TRT)
     return fail3(LB_EINVAL, "collision must be LB3_BGK or LB3_TRT");
@@ -95,6 +98,17 @@ lb_status validate3(const lb3_domain_desc *d) {
 
 unsigned blocks_of(long long n) { return (unsigned)((n + 255) / 256); }
 
+// launches kernel template K instantiated for storage format st (validated)
+#define LB3_DISPATCH(st, K, ...)                                                  \
+  do {                                                                            \
+    switch (st) {                                                                 \
+      case LB_F64: hipLaunchKernelGGL(K<0>, __VA_ARGS__); break;                  \
+      case LB_F32: hipLaunchKernelGGL(K<1>, __VA_ARGS__); break;                  \
+      case LB_F16_DELTA: hipLaunchKernelGGL(K<2>, __VA_ARGS__); break;            \
+      default: hipLaunchKernelGGL(K<3>, __VA_ARGS__); break;                      \
+    }                                                                             \
+  } while (0)
+
 }  // namespace
 
 struct lb3_domain {
@@ -104,6 +118,7 @@ struct lb3_domain {
   hipStream_t stream = nullptr;
   Dom3 hd{};
   int64_t t = 0;
+  bool wide = false;               // the sweep takes 64-bit byte offsets
   std::vector<uint8_t> host_mask;  // [nz][ny][pitch]: walls and obstacles
   Dom3 *ddesc() const { return (Dom3 *)(ws + L.desc); }
   Header3 *dhdr() const { return (Header3 *)(ws + L.hdr); }
@@ -147,12 +162,8 @@ lb_status init3(lb3_domain *d, const double *rho, const double *ux, const double
         a[k] = st + k * BAND;
       }
     }
-    if (d->desc.storage == LB_F64)
-      hipLaunchKernelGGL(k_init3<0>, dim3(blocks_of(cnt)), dim3(256), 0, d->stream, d->ddesc(), a[0],
-                         a[1], a[2], a[3], n0, cnt);
-    else
-      hipLaunchKernelGGL(k_init3<1>, dim3(blocks_of(cnt)), dim3(256), 0, d->stream, d->ddesc(), a[0],
-                         a[1], a[2], a[3], n0, cnt);
+    LB3_DISPATCH(d->desc.storage, k_init3, dim3(blocks_of(cnt)), dim3(256), 0, d->stream,
+                 d->ddesc(), a[0], a[1], a[2], a[3], n0, cnt);
     HIPCHK3(hipGetLastError());
     HIPCHK3(hipStreamSynchronize(d->stream));
   }
@@ -177,6 +188,34 @@ lb_status push_desc3(lb3_domain *d) {
   } catch (...) {                                                                  \
     return lbk::lb_fail_nothrow(LB_EHIP, "unexpected internal error");             \
   }
+
+namespace {
+
+template <int ST> void launch_sweep3_st(const lb3_domain *d, unsigned blocks, int k) {
+  const dim3 g(blocks), b(256);
+  if (d->L.solids) {
+    if (d->wide)
+      hipLaunchKernelGGL((k_sweep3<ST, true, true>), g, b, 0, d->stream, d->ddesc(), k);
+    else
+      hipLaunchKernelGGL((k_sweep3<ST, true, false>), g, b, 0, d->stream, d->ddesc(), k);
+  } else {
+    if (d->wide)
+      hipLaunchKernelGGL((k_sweep3<ST, false, true>), g, b, 0, d->stream, d->ddesc(), k);
+    else
+      hipLaunchKernelGGL((k_sweep3<ST, false, false>), g, b, 0, d->stream, d->ddesc(), k);
+  }
+}
+
+void launch_sweep3(const lb3_domain *d, unsigned blocks, int k) {
+  switch (d->desc.storage) {
+    case LB_F64: launch_sweep3_st<0>(d, blocks, k); break;
+    case LB_F32: launch_sweep3_st<1>(d, blocks, k); break;
+    case LB_F16_DELTA: launch_sweep3_st<2>(d, blocks, k); break;
+    default: launch_sweep3_st<3>(d, blocks, k); break;
+  }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -220,7 +259,14 @@ static lb_status lb3_create_domain_impl(const lb3_domain_desc *desc, void *dev_w
   h.ny = desc->ny;
   h.nz = desc->nz;
   h.pitch = L.pitch;
-  h.storage = desc->storage == LB_F64 ? 0 : 1;
+  h.storage = desc->storage;
+  // 32-bit byte offsets while the 19 population planes stay below 2^32 bytes
+  d->wide = 19.0 * (double)d->desc.nz * d->desc.ny * L.pitch *
+                (desc->storage == LB_F64 ? 8 : desc->storage == LB_F32 ? 4 : 2) >=
+            4294967296.0;
+  h.sr = desc->rounding == LB_ROUND_STOCHASTIC ? 1 : 0;
+  h.key0 = (uint32_t)desc->seed;
+  h.key1 = (uint32_t)(desc->seed >> 32);
   h.tiles_x = (desc->nx + 63) / 64;
   h.tiles_y = (desc->ny + 3) / 4;
   h.rho0 = desc->rho0;
@@ -304,10 +350,7 @@ static lb_status lb3_step_impl(lb3_domain *d, int64_t nsteps) {
   for (int64_t k0 = 0; k0 < nsteps; k0 += 1024) {
     const int c = (int)std::min<int64_t>(1024, nsteps - k0);
     for (int k = 0; k < c; ++k) {
-      if (d->desc.storage == LB_F64)
-        hipLaunchKernelGGL(k_sweep3<0>, dim3(blocks), dim3(256), 0, d->stream, d->ddesc(), k);
-      else
-        hipLaunchKernelGGL(k_sweep3<1>, dim3(blocks), dim3(256), 0, d->stream, d->ddesc(), k);
+      launch_sweep3(d, blocks, k);
     }
     hipLaunchKernelGGL(k_advance3, dim3(1), dim3(1), 0, d->stream, d->ddesc(), c);
     HIPCHK3(hipGetLastError());
@@ -327,12 +370,8 @@ static lb_status lb3_moments_impl(lb3_domain *d, double *rho, double *ux, double
   double *h[4] = {rho, ux, uy, uz};
   for (long long n0 = 0; n0 < n; n0 += BAND) {
     const long long cnt = std::min(BAND, n - n0);
-    if (d->desc.storage == LB_F64)
-      hipLaunchKernelGGL(k_moments3<0>, dim3(blocks_of(cnt)), dim3(256), 0, d->stream, d->ddesc(),
-                         st, n0, cnt);
-    else
-      hipLaunchKernelGGL(k_moments3<1>, dim3(blocks_of(cnt)), dim3(256), 0, d->stream, d->ddesc(),
-                         st, n0, cnt);
+    LB3_DISPATCH(d->desc.storage, k_moments3, dim3(blocks_of(cnt)), dim3(256), 0, d->stream,
+                 d->ddesc(), st, n0, cnt);
     HIPCHK3(hipGetLastError());
     for (int k = 0; k < 4; ++k)
       HIPCHK3(hipMemcpyAsync(h[k] + n0, st + k * cnt, cnt * 8, hipMemcpyDeviceToHost, d->stream));
@@ -351,12 +390,8 @@ static lb_status lb3_get_populations_impl(lb3_domain *d, double *f) {
   double *st = (double *)(d->ws + d->L.stage);
   for (long long n0 = 0; n0 < n; n0 += BAND) {
     const long long cnt = std::min(BAND, n - n0);
-    if (d->desc.storage == LB_F64)
-      hipLaunchKernelGGL(k_export3<0>, dim3(blocks_of(cnt)), dim3(256), 0, d->stream, d->ddesc(),
-                         st, n0, cnt);
-    else
-      hipLaunchKernelGGL(k_export3<1>, dim3(blocks_of(cnt)), dim3(256), 0, d->stream, d->ddesc(),
-                         st, n0, cnt);
+    LB3_DISPATCH(d->desc.storage, k_export3, dim3(blocks_of(cnt)), dim3(256), 0, d->stream,
+                 d->ddesc(), st, n0, cnt);
     HIPCHK3(hipGetLastError());
     for (int i = 0; i < 19; ++i)
       HIPCHK3(hipMemcpyAsync(f + (size_t)i * n + n0, st + (size_t)i * cnt, cnt * 8,
@@ -372,10 +407,8 @@ lb_status lb3_get_populations(lb3_domain *d, double *f) {
 
 static lb_status lb3_mass_impl(lb3_domain *d, double *total) {
   if (!d || !total) return fail3(LB_EINVAL, "null argument");
-  if (d->desc.storage == LB_F64)
-    hipLaunchKernelGGL(k_mass3_partial<0>, dim3(d->desc.nz), dim3(256), 0, d->stream, d->ddesc());
-  else
-    hipLaunchKernelGGL(k_mass3_partial<1>, dim3(d->desc.nz), dim3(256), 0, d->stream, d->ddesc());
+  LB3_DISPATCH(d->desc.storage, k_mass3_partial, dim3(d->desc.nz), dim3(256), 0, d->stream,
+               d->ddesc());
   hipLaunchKernelGGL(k_mass3_final, dim3(1), dim3(64), 0, d->stream, d->ddesc());
   HIPCHK3(hipGetLastError());
   HIPCHK3(hipMemcpyAsync(total, &d->dhdr()->mass, 8, hipMemcpyDeviceToHost, d->stream));
@@ -395,6 +428,27 @@ static lb_status lb3_time_impl(lb3_domain *d, int64_t *t) {
 
 lb_status lb3_time(lb3_domain *d, int64_t *t) {
   LB_GUARDED(lb3_time_impl(d, t));
+}
+
+static lb_status lb3_set_option_impl(lb3_domain *d, int32_t option, int64_t value) {
+  if (!d) return fail3(LB_EINVAL, "null domain");
+  switch (option) {
+    case LB3_OPT_WIDE_OFFSETS: {
+      if (value != 0 && value != 1) return fail3(LB_EINVAL, "LB3_OPT_WIDE_OFFSETS takes 0 or 1");
+      const Layout3 &L = d->L;
+      const size_t e = d->desc.storage == LB_F64 ? 8 : d->desc.storage == LB_F32 ? 4 : 2;
+      const bool need = 19.0 * (double)d->desc.nz * d->desc.ny * L.pitch * e >= 4294967296.0;
+      if (!value && need)
+        return fail3(LB_EINVAL, "population buffer reaches 2^32 bytes: offsets must stay 64-bit");
+      d->wide = value != 0;
+      return LB_OK;
+    }
+  }
+  return fail3(LB_EINVAL, "unknown D3Q19 option");
+}
+
+lb_status lb3_set_option(lb3_domain *d, int32_t option, int64_t value) {
+  LB_GUARDED(lb3_set_option_impl(d, option, value));
 }
 
 static lb_status lb3_destroy_domain_impl(lb3_domain *d) {

@@ -1,14 +1,17 @@
 // sweep3_impl.h -- the D3Q19 variant of the fused stream-collide sweep (the
 // three-dimensional lattice the paper names as its next step, Sec. 8): BGK
-// collision with the velocity-shift body force of Sec. 2, pull streaming
-// with periodic wrap and halfway bounce-back on solid nodes, FP64 or FP32
-// storage of the deviations d_i = f_i - w_i rho0.
+// or two-relaxation-time collision with the velocity-shift body force of
+// Sec. 2, pull streaming with periodic wrap and halfway bounce-back on solid
+// nodes, FP64, FP32, FP16 or BF16 storage of the deviations
+// d_i = f_i - w_i rho0.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <type_traits>
+
+#include "lb_device.h"  // 16-bit conversions and the rounding-bit hash
 
 namespace lbk3 {
 
@@ -44,7 +47,9 @@ struct Dom3 {
   double *partials;    // FP64 density partial sums, one per z plane
   double *mass;
   int nx, ny, nz, pitch;
-  int storage;         // 0 FP64, 1 FP32
+  int storage;         // 0 FP64, 1 FP32, 2 FP16, 3 BF16
+  int sr;              // 16-bit storage rounds stochastically
+  uint32_t key0, key1; // rounding-bit key
   int tiles_x, tiles_y;  // 64 x 4 node tiles of one z plane
   int trt;               // two relaxation times (else BGK: tau_m = tau)
   double rho0, tau, omega, gx, gy, gz;
@@ -58,6 +63,48 @@ template <> __device__ __forceinline__ double par3<double>(double a, float) { re
 template <> __device__ __forceinline__ float par3<float>(double, float b) { return b; }
 __device__ __forceinline__ float fmr(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmr(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Storage of the deviations: FP64 and FP32 as they are; the 16-bit formats
+// hold d_i K_i with K = 2 (rest), 16 (axis), 32 (edge) -- powers of two, so
+// scaling is exact and w_i K_i is 2/3, 8/9, 8/9: the small edge deviations
+// keep clear of the FP16 subnormal range -- converted with round to nearest
+// or the hardware's stochastic rounding.
+__host__ __device__ constexpr float scale3(int i) { return i == 0 ? 2.0f : (i <= 6 ? 16.0f : 32.0f); }
+template <int ST> struct S3;
+template <> struct S3<0> {
+  using T = double;
+  using R = double;
+  static __device__ __forceinline__ R dec(T v, int) { return v; }
+  static __device__ __forceinline__ T enc(R v, int, bool, uint32_t) { return v; }
+};
+template <> struct S3<1> {
+  using T = float;
+  using R = float;
+  static __device__ __forceinline__ R dec(T v, int) { return v; }
+  static __device__ __forceinline__ T enc(R v, int, bool, uint32_t) { return v; }
+};
+template <> struct S3<2> {
+  using T = uint16_t;
+  using R = float;
+  static __device__ __forceinline__ R dec(T v, int i) { return lbk::f16_to_f32(v) * (1.0f / scale3(i)); }
+  static __device__ __forceinline__ T enc(R v, int i, bool sr, uint32_t r) {
+    return sr ? lbk::f32_to_f16_sr(v * scale3(i), r) : lbk::f32_to_f16_rn(v * scale3(i));
+  }
+};
+template <> struct S3<3> {
+  using T = uint16_t;
+  using R = float;
+  static __device__ __forceinline__ R dec(T v, int i) { return lbk::bf16_to_f32(v) * (1.0f / scale3(i)); }
+  static __device__ __forceinline__ T enc(R v, int i, bool sr, uint32_t r) {
+    return sr ? lbk::f32_to_bf16_sr(v * scale3(i), r) : lbk::f32_to_bf16_rn(v * scale3(i));
+  }
+};
+
+// Rounding bits of a node and step: one hash of (node, step, key), spread
+// over the directions by the multiplicative hash the D2Q9 sweep uses.
+__device__ __forceinline__ uint32_t round_bits3(const Dom3 &D, uint32_t node, uint32_t step) {
+  return lbk::mix32(node ^ (lbk::mix32(step ^ D.key0) ^ D.key1));
+}
 
 // BGK or TRT collision of one node in deviation form.  The equilibrium of
 // Eq. LB2 with u = J / rho, J = j + rho tau_m g (tau_m = tau for BGK):
@@ -173,15 +220,51 @@ __device__ __forceinline__ int xcd_order(int bid, int nblocks) {
   return xcd * per + (xcd < rem ? xcd : rem) + local;
 }
 
+// Raw buffer access: the memory unit adds a wave-uniform (scalar) and a
+// per-lane byte offset to the buffer's base, so the plane part of every
+// address costs no vector instruction.  Word 3 is the raw-buffer format of
+// the gfx9 family.
+typedef __amdgpu_buffer_rsrc_t Res3;
+__device__ __forceinline__ Res3 res3(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+template <class T> __device__ __forceinline__ T ld3(Res3 r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 2)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
+  else if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <class T> __device__ __forceinline__ void st3(Res3 r, uint32_t voff, uint32_t soff, T v) {
+  if constexpr (sizeof(T) == 2) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, (int)voff, (int)soff, 0);
+  } else if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+  } else {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+  }
+}
+
 // One step of every node: 256 threads = a tile of 64 (x) by 4 (y) nodes of
 // one z plane; each wave reads 64 consecutive x of a row per population
 // plane.  A solid node stores zero deviations (every slot is written each
-// step and never pulled).  Element offsets are 32-bit (the host admits no
-// buffer of 2^31 elements or more).
-template <int ST>
+// step and never pulled).  Addressing: each direction pair (i odd, i + 1)
+// loads at the pair's first population plane (a wave-uniform offset) plus a
+// per-lane byte offset, and stores at its own plane plus the node's offset;
+// with WIDE false (19 population planes below 2^32 bytes) these are raw
+// buffer accesses, and a pulled population costs one vector add for its
+// address.  A bounced link reads the opposite population of the node itself,
+// from the same pair base.  SOLIDS false: no node words (no walls or
+// obstacles).
+template <int ST, bool SOLIDS, bool WIDE>
 __global__ __launch_bounds__(256) void k_sweep3(const Dom3 *__restrict__ Dp, int kstep) {
-  using T = typename std::conditional<ST == 0, double, float>::type;
-  using R = T;
+  using S = S3<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
+  using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+  constexpr Off E = sizeof(T);
   const Dom3 &D = *Dp;
   const int nx = D.nx, ny = D.ny, nz = D.nz, pitch = D.pitch;
   const int per_plane = D.tiles_x * D.tiles_y;
@@ -192,39 +275,67 @@ __global__ __launch_bounds__(256) void k_sweep3(const Dom3 *__restrict__ Dp, int
   const int x = tx * 64 + (int)(threadIdx.x & 63);
   const int y = ty * 4 + (int)(threadIdx.x >> 6);
   if (x >= nx || y >= ny) return;
-  const uint64_t T0 = *D.tstep + (uint64_t)kstep;  // state time of the source buffer
-  const T *src = (const T *)D.f[T0 & 1];
-  T *dst = (T *)D.f[(T0 + 1) & 1];
-  const uint32_t plane = (uint32_t)nz * (uint32_t)ny * (uint32_t)pitch;
-  const uint32_t here = ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)pitch + (uint32_t)x;
-  const uint32_t w = D.nodew ? D.nodew[here] : 0u;
+  // state time of the source buffer, made wave-uniform so that the buffer
+  // bases stay in scalar registers
+  const uint64_t ts = *lbk::gbl(D.tstep);
+  const uint64_t T0 =
+      (((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(ts >> 32)) << 32) |
+       __builtin_amdgcn_readfirstlane((uint32_t)ts)) + (uint64_t)kstep;
+  const bool odd = (T0 & 1) != 0;
+  const LBK_GLOBAL char *src = lbk::gbl((const char *)(odd ? D.f[1] : D.f[0]));
+  LBK_GLOBAL char *dst = lbk::gbl((char *)(odd ? D.f[0] : D.f[1]));
+  const Off rowb = (Off)pitch * E, zb = (Off)ny * rowb, popb = (Off)nz * zb;
+  const Off node = ((Off)z * (Off)ny + (Off)y) * (Off)pitch + (Off)x;
+  const Off here = node * E;
+  const Res3 rs = res3((const void *)src, (uint32_t)(19 * popb));
+  const Res3 rd = res3((const void *)dst, (uint32_t)(19 * popb));
+  uint32_t w = 0u;
+  if constexpr (SOLIDS) w = lbk::gbl(D.nodew)[node];
   R d[19];
-  if (w & NODE_SOLID3) {
+  if (SOLIDS && (w & NODE_SOLID3)) {
 #pragma unroll
     for (int i = 0; i < 19; ++i) d[i] = R(0);
   } else {
-    const int xp = x + 1 < nx ? x + 1 : 0, xm = x > 0 ? x - 1 : nx - 1;
-    const int yp = y + 1 < ny ? y + 1 : 0, ym = y > 0 ? y - 1 : ny - 1;
-    const int zp = z + 1 < nz ? z + 1 : 0, zm = z > 0 ? z - 1 : nz - 1;
-    d[0] = src[here];
+    // byte offsets of the source rows and columns x - e_i
+    const Off xo_m = (Off)(x > 0 ? x - 1 : nx - 1) * E, xo_0 = (Off)x * E,
+              xo_p = (Off)(x + 1 < nx ? x + 1 : 0) * E;
+    const Off yo_m = (Off)(y > 0 ? y - 1 : ny - 1) * rowb, yo_0 = (Off)y * rowb,
+              yo_p = (Off)(y + 1 < ny ? y + 1 : 0) * rowb;
+    const Off zo_m = (Off)(z > 0 ? z - 1 : nz - 1) * zb, zo_0 = (Off)z * zb,
+              zo_p = (Off)(z + 1 < nz ? z + 1 : 0) * zb;
+    if constexpr (WIDE)
+      d[0] = S::dec(*(const LBK_GLOBAL T *)(src + here), 0);
+    else
+      d[0] = S::dec(ld3<T>(rs, here, 0u), 0);
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
-      // source x - e_i
-      const int sx = ex(i) > 0 ? xm : (ex(i) < 0 ? xp : x);
-      const int sy = ey(i) > 0 ? ym : (ey(i) < 0 ? yp : y);
-      const int sz = ez(i) > 0 ? zm : (ez(i) < 0 ? zp : z);
-      const uint32_t from =
-          ((w >> (i - 1)) & 1u)
-              ? (uint32_t)opp(i) * plane + here  // halfway bounce-back
-              : (uint32_t)i * plane + ((uint32_t)sz * (uint32_t)ny + (uint32_t)sy) * (uint32_t)pitch +
-                    (uint32_t)sx;
-      d[i] = src[from];
+      const int lo = (i - 1) | 1;  // the pair's first direction: i odd, or i - 1
+      const Off zo = ez(i) > 0 ? zo_m : (ez(i) < 0 ? zo_p : zo_0);
+      const Off yo = ey(i) > 0 ? yo_m : (ey(i) < 0 ? yo_p : yo_0);
+      const Off xo = ex(i) > 0 ? xo_m : (ex(i) < 0 ? xo_p : xo_0);
+      Off off = zo + yo + xo + ((i & 1) ? (Off)0 : popb);
+      if constexpr (SOLIDS) {
+        // halfway bounce-back: population opp(i) of this node
+        const Off bb = (i & 1) ? here + popb : here;
+        off = ((w >> (i - 1)) & 1u) ? bb : off;
+      }
+      if constexpr (WIDE)
+        d[i] = S::dec(*(const LBK_GLOBAL T *)(src + (Off)lo * popb + off), i);
+      else
+        d[i] = S::dec(ld3<T>(rs, off, __builtin_amdgcn_readfirstlane((uint32_t)lo * popb)), i);
     }
     collide3<R>(D, d);
     if (!(fabs((double)d[0]) < 1e30)) atomicOr(D.health, 1u);
   }
+  const uint32_t h = sizeof(T) == 2 && D.sr ? round_bits3(D, (uint32_t)node, (uint32_t)T0) : 0u;
 #pragma unroll
-  for (int i = 0; i < 19; ++i) dst[(uint32_t)i * plane + here] = d[i];
+  for (int i = 0; i < 19; ++i) {
+    const T v = S::enc(d[i], i, sizeof(T) == 2 && D.sr, lbk::sr_bits(h, i));
+    if constexpr (WIDE)
+      *(LBK_GLOBAL T *)(dst + (Off)i * popb + here) = v;
+    else
+      st3<T>(rd, here, __builtin_amdgcn_readfirstlane((uint32_t)i * popb), v);
+  }
 }
 
 // Node words from the solid mask ([nz][ny][pitch] bytes, 1 = solid).
@@ -258,8 +369,9 @@ template <int ST>
 __global__ __launch_bounds__(256) void k_init3(const Dom3 *__restrict__ Dp, const double *rho_f,
                                                const double *ux_f, const double *uy_f,
                                                const double *uz_f, long long n0, long long cnt) {
-  using T = typename std::conditional<ST == 0, double, float>::type;
-  using R = T;
+  using S = S3<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
   const Dom3 &D = *Dp;
   const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
   if (k >= cnt) return;
@@ -284,7 +396,7 @@ __global__ __launch_bounds__(256) void k_init3(const Dom3 *__restrict__ Dp, cons
   }
   if (!solid) collide3<R>(D, d);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) dst[(size_t)i * plane + here] = d[i];
+  for (int i = 0; i < 19; ++i) dst[(size_t)i * plane + here] = S::enc(d[i], i, false, 0u);
 }
 
 // rho and u = j/rho + g/2 of the pre-collision state, recovered from f*:
@@ -293,7 +405,8 @@ __global__ __launch_bounds__(256) void k_init3(const Dom3 *__restrict__ Dp, cons
 template <int ST>
 __global__ __launch_bounds__(256) void k_moments3(const Dom3 *__restrict__ Dp, double *out,
                                                   long long n0, long long cnt) {
-  using T = typename std::conditional<ST == 0, double, float>::type;
+  using S = S3<ST>;
+  using T = typename S::T;
   const Dom3 &D = *Dp;
   const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
   if (k >= cnt) return;
@@ -309,7 +422,7 @@ __global__ __launch_bounds__(256) void k_moments3(const Dom3 *__restrict__ Dp, d
   double dr = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    const double v = (double)src[(size_t)i * plane + here];
+    const double v = (double)S::dec(src[(size_t)i * plane + here], i);
     dr += v;
     jx += ex(i) * v;
     jy += ey(i) * v;
@@ -326,7 +439,8 @@ __global__ __launch_bounds__(256) void k_moments3(const Dom3 *__restrict__ Dp, d
 template <int ST>
 __global__ __launch_bounds__(256) void k_export3(const Dom3 *__restrict__ Dp, double *out,
                                                  long long n0, long long cnt) {
-  using T = typename std::conditional<ST == 0, double, float>::type;
+  using S = S3<ST>;
+  using T = typename S::T;
   const Dom3 &D = *Dp;
   const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
   if (k >= cnt) return;
@@ -336,14 +450,15 @@ __global__ __launch_bounds__(256) void k_export3(const Dom3 *__restrict__ Dp, do
   const size_t here = ((size_t)z * D.ny + y) * D.pitch + x;
   const T *src = (const T *)D.f[*D.tstep & 1];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) out[(size_t)i * cnt + k] = (double)src[(size_t)i * plane + here];
+  for (int i = 0; i < 19; ++i) out[(size_t)i * cnt + k] = (double)S::dec(src[(size_t)i * plane + here], i);
 }
 
 // FP64 density sum: block z sums plane z in a fixed order; one wave adds the
 // planes.  Latches a non-finite total.
 template <int ST>
 __global__ __launch_bounds__(256) void k_mass3_partial(const Dom3 *__restrict__ Dp) {
-  using T = typename std::conditional<ST == 0, double, float>::type;
+  using S = S3<ST>;
+  using T = typename S::T;
   __shared__ double red[4];
   const Dom3 &D = *Dp;
   const int z = (int)blockIdx.x;
@@ -356,7 +471,7 @@ __global__ __launch_bounds__(256) void k_mass3_partial(const Dom3 *__restrict__ 
       if (D.nodew && (D.nodew[here] & NODE_SOLID3)) continue;
       double r = 0.0;
 #pragma unroll
-      for (int i = 0; i < 19; ++i) r += (double)src[(size_t)i * plane + here];
+      for (int i = 0; i < 19; ++i) r += (double)S::dec(src[(size_t)i * plane + here], i);
       acc += D.rho0 + r;
     }
 #pragma unroll

@@ -21,6 +21,7 @@ ROUND_NEAREST, ROUND_STOCHASTIC = 0, 1
 COMPUTE_NATIVE, COMPUTE_F64 = 0, 1
 INIT_REST, INIT_FIELDS = 0, 1
 LB3_BGK, LB3_TRT = 0, 1  # D3Q19 collisions
+LB3_OPT_WIDE_OFFSETS = 1
 PARTICLE_FIXED = 1
 OPT_USE_GRAPH, OPT_TILE_WIDTH, OPT_ROWS_PER_THREAD, OPT_GRAPH_CHUNK, OPT_FORCE_AVERAGE = 1, 2, 3, 4, 5
 OPT_TWO_STEP = 6
@@ -43,7 +44,7 @@ EXPORTED = [
     "lb_batch_set_option", "lb_batch_destroy", "lb_noise_normals", "lb_autotune",
     "lb_batch_autotune", "lb_batch_get_option",
     "lb3_workspace_bytes", "lb3_create_domain", "lb3_set_obstacles", "lb3_step", "lb3_moments",
-    "lb3_get_populations", "lb3_mass", "lb3_time", "lb3_destroy_domain",
+    "lb3_get_populations", "lb3_mass", "lb3_time", "lb3_set_option", "lb3_destroy_domain",
     "lb_status_string", "lb_last_error",
 ]
 
@@ -75,6 +76,7 @@ class Domain3Desc(C.Structure):
         ("init_rho", C.POINTER(C.c_double)), ("init_ux", C.POINTER(C.c_double)),
         ("init_uy", C.POINTER(C.c_double)), ("init_uz", C.POINTER(C.c_double)),
         ("collision", C.c_int32), ("magic", C.c_double),
+        ("rounding", C.c_int32), ("seed", C.c_uint64),
     ]
 
 
@@ -153,6 +155,7 @@ def library():
         "lb3_get_populations": [vp, dp],
         "lb3_mass": [vp, dp],
         "lb3_time": [vp, P(C.c_int64)],
+        "lb3_set_option": [vp, C.c_int32, C.c_int64],
         "lb3_destroy_domain": [vp],
     }
     for name, args in sig.items():
@@ -452,8 +455,11 @@ class Domain3:
 
     def __init__(self, nx, ny, nz, *, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0),
                  walls=(False, False, False), storage="f32", obstacles=None, init=None,
-                 collision="bgk", magic=3.0 / 16.0, device="cuda", stream=None):
-        """collision "trt": two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic."""
+                 collision="bgk", magic=3.0 / 16.0, rounding=None, seed=0, device="cuda",
+                 stream=None):
+        """collision "trt": two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic.
+        storage "f64" | "f32" | "f16" | "bf16"; rounding "nearest" | "stochastic"
+        (16-bit storage only; its default there)."""
         lib = library()
         d = Domain3Desc()
         d.abi_version = ABI_VERSION
@@ -461,7 +467,11 @@ class Domain3:
         d.magic = float(magic)
         d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
         d.wall_x, d.wall_y, d.wall_z = (int(bool(w)) for w in walls)
-        d.storage = {"f64": F64, "f32": F32}[storage]
+        d.storage = _ST[storage]
+        if rounding is None:
+            rounding = "stochastic" if storage in ("f16", "bf16") else "nearest"
+        d.rounding = _RND[rounding]
+        d.seed = int(seed) & (2**64 - 1)
         d.obstacles = 1 if obstacles is not None else 0
         d.rho0, d.tau = float(rho0), float(tau)
         d.gx, d.gy, d.gz = (float(v) for v in g)
@@ -522,3 +532,7 @@ class Domain3:
         t = C.c_int64()
         _check(library().lb3_time(self._h, C.byref(t)), "lb3_time")
         return t.value
+
+    def set_option(self, option, value):
+        _check(library().lb3_set_option(self._h, int(option), int(value)), "lb3_set_option")
+        return self

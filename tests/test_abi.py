@@ -111,9 +111,8 @@ def _desc3(**kw):
 
 @pytest.mark.parametrize("bad,msg", [
     (dict(tau=0.5), "tau"), (dict(nz=2), "nz"), (dict(abi_version=3), "abi"),
-    (dict(storage=2), "storage"), (dict(init_kind=1), "INIT_FIELDS"), (dict(rho0=0.0), "rho0"),
-    # 32-bit element offsets in the sweep: 19 nz ny pitch below 2^31
-    (dict(nx=1024, ny=1024, nz=128), "too large"),
+    (dict(storage=4), "storage"), (dict(init_kind=1), "INIT_FIELDS"), (dict(rho0=0.0), "rho0"),
+    (dict(rounding=2), "rounding"), (dict(rounding=1), "stochastic rounding needs"),
     (dict(collision=2), "collision"), (dict(collision=1, magic=0.0), "magic"),
 ])
 def test_d3q19_validation_errors(bad, msg):
@@ -127,10 +126,28 @@ def test_d3q19_validation_errors(bad, msg):
 def test_d3q19_workspace_covers_both_population_buffers():
     from paper_2006_12910_amd import lb
     lib = lb.library()
-    for storage, size in ((0, 8), (1, 4)):
+    for storage, size in ((0, 8), (1, 4), (2, 2), (3, 2)):
         n = C.c_size_t()
         assert lib.lb3_workspace_bytes(C.byref(_desc3(storage=storage, nx=100, ny=30, nz=20)),
                                        C.byref(n)) == 0
         assert n.value >= 2 * 19 * 128 * 30 * 20 * size
     assert lib.lb3_step(None, 1) == lb.LB_EINVAL
+    assert lib.lb3_set_option(None, lb.LB3_OPT_WIDE_OFFSETS, 1) == lb.LB_EINVAL
     assert lib.lb3_destroy_domain(None) == lb.LB_EINVAL
+
+
+def test_d3q19_lattices_beyond_32_bit_offsets_are_sized():
+    """A lattice whose population buffer passes 2^32 bytes is admitted (the
+    sweep then takes 64-bit offsets): the workspace holds both buffers."""
+    from paper_2006_12910_amd import lb
+    lib = lb.library()
+    n = C.c_size_t()
+    assert lib.lb3_workspace_bytes(C.byref(_desc3(nx=1024, ny=1024, nz=128)), C.byref(n)) == 0
+    assert n.value >= 2 * 19 * 1024 * 1024 * 128 * 4 > 2 * 2 ** 32
+
+
+def test_d3q19_option_constant_matches_the_header():
+    from paper_2006_12910_amd import lb
+    src = open(os.path.join(ROOT, "include", "lb.h")).read()
+    assert int(re.search(r"^#define LB3_OPT_WIDE_OFFSETS (\d+)", src, re.M).group(1)) == \
+        lb.LB3_OPT_WIDE_OFFSETS

@@ -1,7 +1,9 @@
 """GPU vs oracle parity of the D3Q19 sweep (the 3D lattice of Sec. 8 with the
 BGK collision and velocity-shift forcing of Sec. 2, and the two-relaxation-
 time variant): FP64 storage to accumulated rounding, FP32 to the 1e-5
-target, on ragged lattices with walls and spherical obstacles; the exact
+target, on ragged lattices with walls and spherical obstacles; FP16 / BF16
+deviation storage (Sec. 3 carried to D3Q19) to the reduced-storage
+targets, with and without stochastic rounding; the exact
 discrete plane Poiseuille state (BGK) and the walls exactly halfway (TRT,
 magic 3/16); the closed-form shear-wave decay and exact mass conservation
 at the benchmark size (256^3)."""
@@ -67,6 +69,98 @@ def test_d3q19_against_oracle(storage, tol, shape, collision):
     gpu.close()
 
 
+# Relative L2 bounds of the velocity for 16-bit storage (FP32 arithmetic): the
+# reduced-storage targets of the D2Q9 path (FP16 with stochastic rounding
+# 1e-3, BF16 1e-2); round to nearest is held to the measured error with margin.
+BOUNDS16 = {("f16", "stochastic"): 1e-3, ("bf16", "stochastic"): 1e-2,
+            ("f16", "nearest"): 2e-2}
+
+
+@pytest.mark.parametrize("storage,rounding", list(BOUNDS16))
+@pytest.mark.parametrize("shape", [(70, 33, 21), (130, 7, 5)])
+@pytest.mark.parametrize("collision", [dict(), dict(collision="trt", magic=3.0 / 16.0)])
+def test_d3q19_16bit_against_oracle(storage, rounding, shape, collision):
+    """Ragged lattices, walls, spheres, body force: velocity and density
+    against the FP64 oracle, and the FP64 mass of the 16-bit state."""
+    from paper_2006_12910_amd import lb
+    nx, ny, nz = shape
+    mask = _spheres(nx, ny, nz, nx + ny)
+    init = _fields(nx, ny, nz, nz)
+    kw = dict(tau=0.7, g=(2e-5, -1e-5, 5e-6), walls=(False, False, True), **collision)
+    gpu = lb.Domain3(nx, ny, nz, storage=storage, rounding=rounding, seed=11, obstacles=mask,
+                     init=init, **kw)
+    ora = Oracle3(nx, ny, nz, obstacles=mask, init=init, **kw)
+    tol = BOUNDS16[(storage, rounding)]
+    for n in (1, 7, 52):
+        gpu.step(n)
+        ora.run(n)
+        drho, err, emax = _velocity_error(gpu, ora)
+        print(f"D3Q19 {storage}/{rounding} {shape} {collision} step {gpu.time}: drho {drho:.2e} "
+              f"err {err:.2e} max {emax:.2e}")
+        assert drho < (2e-4 if storage == "f16" else 2e-3) and err < tol, (n, drho, err, emax)
+    m_gpu, m_ora = gpu.mass(), ora.mass()
+    assert abs(m_gpu - m_ora) / m_ora < 1e-6
+    gpu.close()
+
+
+@pytest.mark.parametrize("storage,rounding", list(BOUNDS16))
+def test_d3q19_16bit_shear_wave_1000_steps(storage, rounding):
+    """A decaying shear wave (u0 = 0.01, along z) over 1000 steps against the
+    oracle: stochastic rounding keeps the slow decay that round to nearest
+    partly loses (updates below half a spacing of the stored values)."""
+    from paper_2006_12910_amd import lb
+    nx, ny, nz, tau = 8, 6, 96, 0.8
+    z = np.arange(nz)[:, None, None] + np.zeros((1, ny, nx))
+    init = (1.0, 0.01 * np.sin(2 * np.pi * 2 * z / nz + 0.3), 0.0, 0.0)
+    gpu = lb.Domain3(nx, ny, nz, tau=tau, storage=storage, rounding=rounding, seed=5, init=init)
+    ora = Oracle3(nx, ny, nz, tau=tau, init=init)
+    gpu.step(1000)
+    ora.run(1000)
+    drho, err, emax = _velocity_error(gpu, ora)
+    print(f"D3Q19 shear wave {storage}/{rounding} 1000 steps: rel L2 {err:.3e} drho {drho:.2e}")
+    assert err < BOUNDS16[(storage, rounding)], err
+    gpu.close()
+
+
+def test_d3q19_rounding_seed_reproducible():
+    """Stochastic rounding is a function of (node, step, seed): two domains
+    with one seed give identical states, another seed a different one."""
+    from paper_2006_12910_amd import lb
+    init = _fields(40, 9, 7, 3)
+    runs = []
+    for seed in (1, 1, 2):
+        g = lb.Domain3(40, 9, 7, tau=0.7, storage="f16", seed=seed, init=init)
+        g.step(20)
+        runs.append(g.populations())
+        g.close()
+    assert np.array_equal(runs[0], runs[1])
+    assert not np.array_equal(runs[0], runs[2])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("solids", [False, True])
+def test_d3q19_wide_offsets_give_identical_states(storage, solids):
+    """The 64-bit-offset sweep (taken by itself for lattices whose population
+    buffer passes 2^32 bytes) and the 32-bit buffer-offset sweep are the same
+    arithmetic: bit-identical states on a ragged lattice."""
+    from paper_2006_12910_amd import lb
+    nx, ny, nz = 70, 33, 21
+    kw = dict(tau=0.7, g=(2e-5, -1e-5, 5e-6), storage=storage, seed=4, init=_fields(nx, ny, nz, 8))
+    if solids:
+        kw.update(walls=(False, True, False), obstacles=_spheres(nx, ny, nz, 5))
+    a = lb.Domain3(nx, ny, nz, **kw)
+    b = lb.Domain3(nx, ny, nz, **kw).set_option(lb.LB3_OPT_WIDE_OFFSETS, 1)
+    a.step(9)
+    b.step(9)
+    assert np.array_equal(a.populations(), b.populations())
+    b.set_option(lb.LB3_OPT_WIDE_OFFSETS, 0)
+    a.step(3)
+    b.step(3)
+    assert np.array_equal(a.populations(), b.populations())
+    a.close()
+    b.close()
+
+
 def test_d3q19_plane_poiseuille_exact_steady_state():
     """FP64 storage reaches the exact discrete steady solution of the
     walled channel (the oracle's pin)."""
@@ -123,4 +217,32 @@ def test_d3q19_256_cube_shear_wave_and_mass():
     assert abs(amp / ref - 1) < 1e-3, (amp, ref)
     assert np.abs(uy).max() < 1e-7 and np.abs(uz).max() < 1e-7
     assert abs(gpu.mass() / m0 - 1) < 1e-9
+    gpu.close()
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_d3q19_256_cube_shear_wave_16bit(storage):
+    """The benchmark lattice with 16-bit deviation storage and stochastic
+    rounding: the closed-form decay, no spurious cross flow beyond the
+    storage's quantization, and an FP64 mass that drifts only by the
+    rounding's random walk."""
+    from paper_2006_12910_amd import lb
+    n, u0, tau, steps = 256, 0.01, 0.8, 300
+    k = 2 * np.pi / n
+    z = np.arange(n)[:, None, None] + np.zeros((1, n, n))
+    gpu = lb.Domain3(n, n, n, tau=tau, storage=storage, seed=9,
+                     init=(1.0, u0 * np.sin(k * z), 0.0, 0.0))
+    m0 = gpu.mass()
+    gpu.step(steps)
+    _, ux, uy, uz = gpu.moments()
+    prof = ux.mean(axis=(1, 2))
+    amp = 2 * (prof * np.sin(k * np.arange(n))).mean()
+    ref = u0 * np.exp(-(tau - 0.5) / 3 * k * k * steps)
+    cross = max(np.abs(uy).max(), np.abs(uz).max())
+    drift = gpu.mass() / m0 - 1
+    print(f"D3Q19 256^3 {storage} shear wave: amplitude / closed form - 1 = {amp / ref - 1:.2e}, "
+          f"max cross flow {cross:.2e}, mass drift {drift:.2e}")
+    assert abs(amp / ref - 1) < (1e-3 if storage == "f16" else 5e-3), (amp, ref)
+    assert cross < (2e-5 if storage == "f16" else 2e-4)
+    assert abs(drift) < 1e-7
     gpu.close()
