@@ -132,34 +132,38 @@ struct alignas(256) DevDomain {
   double lj_psi, lj_rit, lj_floor;
   // omega times the equilibrium's class coefficients in the stored scaling:
   // K_1 w_1, K_5 w_5 (even parts) and K_1 l_1, K_5 l_5 (linear terms), with
-  // w_1 = 1/9, w_5 = w_1/4, l_1 = 1/3, l_5 = (1 - 2 l_1)/4 (see collide_node);
+  // w_1 = 1/9, w_5 = w_1/4, l_1 = 1/3, l_5 = (1 - 2 l_1)/4 (see collide_node),
+  // and 9/2 times the even-part ones (the second-order term's factor);
   // set by set_collision_coefficients for a fixed relaxation time
-  double cw1, cw5, cl1, cl5;
+  double cw1, cw5, cl1, cl5, cq1, cq5;
   // FP32 copies
   float rho0_f, tau_f, omega_f, gx_f, gy_f, drho_in_f, drho_out_f, kT_f;
   float pl_n_f, pl_K_f, tau_min_f, tau_max_f;
-  float cw1_f, cw5_f, cl1_f, cl5_f;
+  float cw1_f, cw5_f, cl1_f, cl5_f, cq1_f, cq5_f;
 };
 
 // omega-scaled equilibrium coefficients of a domain with a fixed relaxation
 // time, in each arithmetic's own rounding (the collision's formula with its
 // constants rounded to R).
-template <class R> inline void collision_coefficients(R omega, R K1, R K5, R c[4]) {
+template <class R> inline void collision_coefficients(R omega, R K1, R K5, R c[6]) {
   const R W1 = R(1) / R(9), W5 = R(0.25) * W1;
   const R L1 = R(1) / R(3), L5 = (R(1) - R(2) * L1) * R(0.25);
   c[0] = omega * (K1 * W1);
   c[1] = omega * (K5 * W5);
   c[2] = omega * (K1 * L1);
   c[3] = omega * (K5 * L5);
+  c[4] = R(4.5) * c[0];
+  c[5] = R(4.5) * c[1];
 }
 inline void set_collision_coefficients(DevDomain &h) {
   const bool k16 = h.storage == ST_F16 || h.storage == ST_BF16;
-  double c[4];
+  double c[6];
   collision_coefficients<double>(h.omega, k16 ? dscale(1) : 1.0, k16 ? dscale(5) : 1.0, c);
-  h.cw1 = c[0]; h.cw5 = c[1]; h.cl1 = c[2]; h.cl5 = c[3];
-  float cf[4];
+  h.cw1 = c[0]; h.cw5 = c[1]; h.cl1 = c[2]; h.cl5 = c[3]; h.cq1 = c[4]; h.cq5 = c[5];
+  float cf[6];
   collision_coefficients<float>(h.omega_f, k16 ? dscale(1) : 1.0f, k16 ? dscale(5) : 1.0f, cf);
   h.cw1_f = cf[0]; h.cw5_f = cf[1]; h.cl1_f = cf[2]; h.cl5_f = cf[3];
+  h.cq1_f = cf[4]; h.cq5_f = cf[5];
 }
 
 // One particle of a batch: owning domain (index into the descriptor array) and

@@ -123,7 +123,8 @@ __device__ __forceinline__ double fmar(double a, double b, double c) { return __
 // two, so the fused form rounds as the sum of the scaled values)
 template <int ST, class R> __device__ __forceinline__ R scaled_drho(const R d[9]) {
   constexpr R i0 = R(1) / R(kscale<ST>(0)), i1 = R(1) / R(kscale<ST>(1)), i5 = R(1) / R(kscale<ST>(5));
-  return fmar(i0, d[0], fmar(i1, (d[1] + d[3]) + (d[2] + d[4]), i5 * ((d[5] + d[7]) + (d[6] + d[8]))));
+  // the diagonal pairs (5, 6) and (7, 8) are the ones the y momentum sums
+  return fmar(i0, d[0], fmar(i1, (d[1] + d[3]) + (d[2] + d[4]), i5 * ((d[5] + d[6]) + (d[7] + d[8]))));
 }
 
 // a + b in FP32 rounded stochastically: the exact sum s + e (s = fl(a + b),
@@ -185,28 +186,35 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
   const R W1 = R(1) / R(9), W5 = R(0.25) * W1;
   const R L1 = R(1) / R(3), L5 = (R(1) - R(2) * L1) * R(0.25);
   const R q = (R(1.5) * rho) * fmar(ux, ux, uy * uy);
-  const R r45 = R(4.5) * rho;
   const R sp = ux + uy, sm = uy - ux;
   // even parts and linear terms of omega feq, already in the stored scaling:
   // omega rides on the class coefficients (uniform unless the relaxation
   // time is local), so the relaxation below is one fused multiply-add a
   // direction, d (1 - omega) + omega feq, instead of a subtraction and one
-  R aw1, aw5, al1, al5;
+  R aw1, aw5, al1, al5, aq1, aq5;
   if constexpr ((FEAT & F_POWER) != 0) {
     aw1 = om * (K1 * W1);
     aw5 = om * (K5 * W5);
     al1 = om * (K1 * L1);
     al5 = om * (K5 * L5);
+    aq1 = R(4.5) * aw1;
+    aq5 = R(4.5) * aw5;
   } else {  // the same products, formed once on the host
     aw1 = par<R>(D.cw1, D.cw1_f);
     aw5 = par<R>(D.cw5, D.cw5_f);
     al1 = par<R>(D.cl1, D.cl1_f);
     al5 = par<R>(D.cl5, D.cl5_f);
+    aq1 = par<R>(D.cq1, D.cq1_f);
+    aq5 = par<R>(D.cq5, D.cq5_f);
   }
-  const R cxx = aw1 * (drho + fmar(r45 * ux, ux, -q));
-  const R cyy = aw1 * (drho + fmar(r45 * uy, uy, -q));
-  const R cpp = aw5 * (drho + fmar(r45 * sp, sp, -q));
-  const R cmm = aw5 * (drho + fmar(r45 * sm, sm, -q));
+  // even part of class k: aw_k (drho - q) + aw_k (9/2) rho (e.u)^2
+  const R t0 = drho - q;
+  const R b1 = aw1 * t0, b5 = aw5 * t0;
+  const R a1 = aq1 * rho, a5 = aq5 * rho;
+  const R cxx = fmar(a1 * ux, ux, b1);
+  const R cyy = fmar(a1 * uy, uy, b1);
+  const R cpp = fmar(a5 * sp, sp, b5);
+  const R cmm = fmar(a5 * sm, sm, b5);
   const R lx = al1 * Jx, ly = al1 * Jy;
   const R lp = al5 * (Jx + Jy), lm = al5 * (Jy - Jx);
   R eq[9];  // omega feq_i
