@@ -277,6 +277,15 @@ static lb_status lb3_create_domain_impl(const lb3_domain_desc *desc, void *dev_w
   h.omega_m = 1.0 / h.tau_m;
   h.tau_m_f = (float)h.tau_m;
   h.omega_m_f = (float)h.omega_m;
+  {
+    // 16-bit storage: coefficients in the stored scaling (K w = 8/9)
+    const double f = h.trt ? 1.0 : h.omega;
+    h.s_cw = (float)(f * 8.0 / 9.0);
+    h.s_cq = (float)(f * 4.0);
+    h.s_cl = (float)(f * 8.0 / 3.0);
+    h.s_om0 = (float)f;
+    h.keep_f = (float)(1.0 - h.omega);
+  }
   h.gx = desc->gx;
   h.gy = desc->gy;
   h.gz = desc->gz;

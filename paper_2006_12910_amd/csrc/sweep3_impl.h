@@ -56,6 +56,11 @@ struct Dom3 {
   double tau_m, omega_m;  // relaxation of the antisymmetric parts
   float rho0_f, tau_f, omega_f, gx_f, gy_f, gz_f;
   float tau_m_f, omega_m_f;
+  // 16-bit storage (collision in the stored scaling): the even-part,
+  // second-order and linear coefficients K w, (9/2) K w, 3 K w of the moving
+  // directions (K w = 8/9 for all of them), times omega for BGK; the rest
+  // population's relaxation factor (omega for BGK, 1 for TRT) and 1 - omega
+  float s_cw, s_cq, s_cl, s_om0, keep_f;
 };
 
 template <class R> __device__ __forceinline__ R par3(double a, float b);
@@ -87,6 +92,10 @@ template <> struct S3<2> {
   using T = uint16_t;
   using R = float;
   static __device__ __forceinline__ R dec(T v, int i) { return lbk::f16_to_f32(v) * (1.0f / scale3(i)); }
+  static __device__ __forceinline__ R raw(T v) { return lbk::f16_to_f32(v); }
+  static __device__ __forceinline__ T enc_raw(R v, bool sr, uint32_t r) {
+    return sr ? lbk::f32_to_f16_sr(v, r) : lbk::f32_to_f16_rn(v);
+  }
   static __device__ __forceinline__ T enc(R v, int i, bool sr, uint32_t r) {
     return sr ? lbk::f32_to_f16_sr(v * scale3(i), r) : lbk::f32_to_f16_rn(v * scale3(i));
   }
@@ -95,6 +104,10 @@ template <> struct S3<3> {
   using T = uint16_t;
   using R = float;
   static __device__ __forceinline__ R dec(T v, int i) { return lbk::bf16_to_f32(v) * (1.0f / scale3(i)); }
+  static __device__ __forceinline__ R raw(T v) { return lbk::bf16_to_f32(v); }
+  static __device__ __forceinline__ T enc_raw(R v, bool sr, uint32_t r) {
+    return sr ? lbk::f32_to_bf16_sr(v, r) : lbk::f32_to_bf16_rn(v);
+  }
   static __device__ __forceinline__ T enc(R v, int i, bool sr, uint32_t r) {
     return sr ? lbk::f32_to_bf16_sr(v * scale3(i), r) : lbk::f32_to_bf16_rn(v * scale3(i));
   }
@@ -207,6 +220,83 @@ template <class R> __device__ __forceinline__ void collide3(const Dom3 &D, R d[1
   }
 }
 
+// The same collision for the 16-bit formats, on the stored values d_i K_i
+// (K = 2, 16, 32) in FP32.  In that scaling every moving direction has
+// K_i w_i = 8/9, so its even part is cw (drho - q) + cq rho (e.u)^2 and its
+// linear part cl (e.J), one coefficient triple per domain (times omega for
+// BGK, so that the relaxation is one fma a direction); the rest population
+// takes the mass balance, K_0 (omega drho - sum of the others / K_i).  The
+// pair sums and differences of the stored values give drho and j and, for
+// TRT, the symmetric and antisymmetric parts.  Relaxation is applied to the
+// stored values directly (no increment form: the rounding to 16 bits is
+// far coarser than the FP32 arithmetic).
+__device__ __forceinline__ void collide3_scaled(const Dom3 &D, float d[19]) {
+  float ps[10], pd[10];  // pair k: directions 2k - 1 and 2k
+#pragma unroll
+  for (int k = 1; k <= 9; ++k) {
+    ps[k] = d[2 * k - 1] + d[2 * k];
+    pd[k] = d[2 * k - 1] - d[2 * k];
+  }
+  const float sa = (ps[1] + ps[2]) + ps[3];
+  const float se = ((ps[4] + ps[5]) + (ps[6] + ps[7])) + (ps[8] + ps[9]);
+  const float drho = fmr(0.5f, d[0], fmr(1.0f / 16.0f, sa, (1.0f / 32.0f) * se));
+  float ex2 = 0.0f, ey2 = 0.0f, ez2 = 0.0f;  // edge parts of j, times 32
+#pragma unroll
+  for (int k = 4; k <= 9; ++k) {
+    const int i = 2 * k - 1;
+    if (ex(i)) ex2 += float(ex(i)) * pd[k];
+    if (ey(i)) ey2 += float(ey(i)) * pd[k];
+    if (ez(i)) ez2 += float(ez(i)) * pd[k];
+  }
+  const float jx = fmr(1.0f / 16.0f, pd[1], (1.0f / 32.0f) * ex2);
+  const float jy = fmr(1.0f / 16.0f, pd[2], (1.0f / 32.0f) * ey2);
+  const float jz = fmr(1.0f / 16.0f, pd[3], (1.0f / 32.0f) * ez2);
+  const float rho = D.rho0_f + drho;
+  const float irho = __builtin_amdgcn_rcpf(rho);  // 1 ulp: enters only the second-order term
+  const float rt = rho * D.tau_m_f;
+  const float Jx = fmr(rt, D.gx_f, jx), Jy = fmr(rt, D.gy_f, jy), Jz = fmr(rt, D.gz_f, jz);
+  const float ux = Jx * irho, uy = Jy * irho, uz = Jz * irho;
+  const float q = (1.5f * rho) * fmr(ux, ux, fmr(uy, uy, uz * uz));
+  const float b = D.s_cw * (drho - q);
+  const float a = D.s_cq * rho;
+  const float ax = a * ux, ay = a * uy, az = a * uz;
+  const float lx = D.s_cl * Jx, ly = D.s_cl * Jy, lz = D.s_cl * Jz;
+  float c[10], l[10];
+#pragma unroll
+  for (int k = 1; k <= 9; ++k) {
+    const int i = 2 * k - 1;
+    float eu = 0.0f, aeu = 0.0f, lin = 0.0f;
+    if (ex(i)) { eu += float(ex(i)) * ux; aeu += float(ex(i)) * ax; lin += float(ex(i)) * lx; }
+    if (ey(i)) { eu += float(ey(i)) * uy; aeu += float(ey(i)) * ay; lin += float(ey(i)) * ly; }
+    if (ez(i)) { eu += float(ez(i)) * uz; aeu += float(ez(i)) * az; lin += float(ez(i)) * lz; }
+    c[k] = fmr(aeu, eu, b);
+    l[k] = lin;
+  }
+  const float ca = (c[1] + c[2]) + c[3];
+  const float ce = ((c[4] + c[5]) + (c[6] + c[7])) + (c[8] + c[9]);
+  // pair k contributes 2 c_k / K: rest = 2 om0 drho - ca / 4 - ce / 8
+  const float eq0 = fmr(2.0f * D.s_om0, drho, -fmr(0.25f, ca, 0.125f * ce));
+  if (!D.trt) {
+    const float keep = D.keep_f;
+    d[0] = fmr(keep, d[0], eq0);
+#pragma unroll
+    for (int k = 1; k <= 9; ++k) {
+      d[2 * k - 1] = fmr(keep, d[2 * k - 1], c[k] + l[k]);
+      d[2 * k] = fmr(keep, d[2 * k], c[k] - l[k]);
+    }
+  } else {
+    const float om = D.omega_f, omm = D.omega_m_f;
+    d[0] = fmr(om, eq0 - d[0], d[0]);
+#pragma unroll
+    for (int k = 1; k <= 9; ++k) {
+      const float sym = fmr(-0.5f, ps[k], c[k]), anti = fmr(-0.5f, pd[k], l[k]);
+      const float t = omm * anti;
+      d[2 * k - 1] += fmr(om, sym, t);
+      d[2 * k] += fmr(om, sym, -t);
+    }
+  }
+}
+
 // XCD-aware block order: the hardware deals consecutive block ids to the 8
 // XCDs in turn; remapped, each XCD walks a contiguous run of tiles, so the
 // 128-byte lines that an x-shifted pull shares with the neighbouring tile
@@ -249,7 +339,8 @@ template <class T> __device__ __forceinline__ void st3(Res3 r, uint32_t voff, ui
 
 // One step of every node: 256 threads = a tile of 64 (x) by 4 (y) nodes of
 // one z plane; each wave reads 64 consecutive x of a row per population
-// plane.  A solid node stores zero deviations (every slot is written each
+// plane.  Eight waves per SIMD for the FP32 and 16-bit formats (at most 64
+// registers), four for FP64.  A solid node stores zero deviations (every slot is written each
 // step and never pulled).  Addressing: each direction pair (i odd, i + 1)
 // loads at the pair's first population plane (a wave-uniform offset) plus a
 // per-lane byte offset, and stores at its own plane plus the node's offset;
@@ -259,7 +350,7 @@ template <class T> __device__ __forceinline__ void st3(Res3 r, uint32_t voff, ui
 // from the same pair base.  SOLIDS false: no node words (no walls or
 // obstacles).
 template <int ST, bool SOLIDS, bool WIDE>
-__global__ __launch_bounds__(256) void k_sweep3(const Dom3 *__restrict__ Dp, int kstep) {
+__global__ __launch_bounds__(256, ST == 0 ? 4 : 8) void k_sweep3(const Dom3 *__restrict__ Dp, int kstep) {
   using S = S3<ST>;
   using T = typename S::T;
   using R = typename S::R;
@@ -285,10 +376,20 @@ __global__ __launch_bounds__(256) void k_sweep3(const Dom3 *__restrict__ Dp, int
   const LBK_GLOBAL char *src = lbk::gbl((const char *)(odd ? D.f[1] : D.f[0]));
   LBK_GLOBAL char *dst = lbk::gbl((char *)(odd ? D.f[0] : D.f[1]));
   const Off rowb = (Off)pitch * E, zb = (Off)ny * rowb, popb = (Off)nz * zb;
-  const Off node = ((Off)z * (Off)ny + (Off)y) * (Off)pitch + (Off)x;
-  const Off here = node * E;
   const Res3 rs = res3((const void *)src, (uint32_t)(19 * popb));
   const Res3 rd = res3((const void *)dst, (uint32_t)(19 * popb));
+  // byte offsets of the source columns and planes x - e_i (rows below)
+  const Off xo_m = (Off)(x > 0 ? x - 1 : nx - 1) * E, xo_0 = (Off)x * E,
+            xo_p = (Off)(x + 1 < nx ? x + 1 : 0) * E;
+  const Off zo_m = (Off)(z > 0 ? z - 1 : nz - 1) * zb, zo_0 = (Off)z * zb,
+            zo_p = (Off)(z + 1 < nz ? z + 1 : 0) * zb;
+  // 16-bit formats: the stored scaling throughout (collide3_scaled)
+  auto in = [](T v, int i) -> R {
+    if constexpr (sizeof(T) == 2) return S::raw(v);
+    else return S::dec(v, i);
+  };
+  const Off node = ((Off)z * (Off)ny + (Off)y) * (Off)pitch + (Off)x;
+  const Off here = node * E;
   uint32_t w = 0u;
   if constexpr (SOLIDS) w = lbk::gbl(D.nodew)[node];
   R d[19];
@@ -296,17 +397,12 @@ __global__ __launch_bounds__(256) void k_sweep3(const Dom3 *__restrict__ Dp, int
 #pragma unroll
     for (int i = 0; i < 19; ++i) d[i] = R(0);
   } else {
-    // byte offsets of the source rows and columns x - e_i
-    const Off xo_m = (Off)(x > 0 ? x - 1 : nx - 1) * E, xo_0 = (Off)x * E,
-              xo_p = (Off)(x + 1 < nx ? x + 1 : 0) * E;
     const Off yo_m = (Off)(y > 0 ? y - 1 : ny - 1) * rowb, yo_0 = (Off)y * rowb,
               yo_p = (Off)(y + 1 < ny ? y + 1 : 0) * rowb;
-    const Off zo_m = (Off)(z > 0 ? z - 1 : nz - 1) * zb, zo_0 = (Off)z * zb,
-              zo_p = (Off)(z + 1 < nz ? z + 1 : 0) * zb;
     if constexpr (WIDE)
-      d[0] = S::dec(*(const LBK_GLOBAL T *)(src + here), 0);
+      d[0] = in(*(const LBK_GLOBAL T *)(src + here), 0);
     else
-      d[0] = S::dec(ld3<T>(rs, here, 0u), 0);
+      d[0] = in(ld3<T>(rs, here, 0u), 0);
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
       const int lo = (i - 1) | 1;  // the pair's first direction: i odd, or i - 1
@@ -320,17 +416,20 @@ __global__ __launch_bounds__(256) void k_sweep3(const Dom3 *__restrict__ Dp, int
         off = ((w >> (i - 1)) & 1u) ? bb : off;
       }
       if constexpr (WIDE)
-        d[i] = S::dec(*(const LBK_GLOBAL T *)(src + (Off)lo * popb + off), i);
+        d[i] = in(*(const LBK_GLOBAL T *)(src + (Off)lo * popb + off), i);
       else
-        d[i] = S::dec(ld3<T>(rs, off, __builtin_amdgcn_readfirstlane((uint32_t)lo * popb)), i);
+        d[i] = in(ld3<T>(rs, off, __builtin_amdgcn_readfirstlane((uint32_t)lo * popb)), i);
     }
-    collide3<R>(D, d);
+    if constexpr (sizeof(T) == 2) collide3_scaled(D, d);
+    else collide3<R>(D, d);
     if (!(fabs((double)d[0]) < 1e30)) atomicOr(D.health, 1u);
   }
   const uint32_t h = sizeof(T) == 2 && D.sr ? round_bits3(D, (uint32_t)node, (uint32_t)T0) : 0u;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    const T v = S::enc(d[i], i, sizeof(T) == 2 && D.sr, lbk::sr_bits(h, i));
+    T v;
+    if constexpr (sizeof(T) == 2) v = S::enc_raw(d[i], D.sr, lbk::sr_bits(h, i));
+    else v = S::enc(d[i], i, false, 0u);
     if constexpr (WIDE)
       *(LBK_GLOBAL T *)(dst + (Off)i * popb + here) = v;
     else

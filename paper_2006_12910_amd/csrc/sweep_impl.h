@@ -104,13 +104,20 @@ __device__ __forceinline__ R powerlaw_tau(const DevDomain &D, const R d[9], R dr
   return tau < tmin ? tmin : (tau > tmax ? tmax : tau);
 }
 
-// Reciprocal: FP32 takes the hardware estimate and one Newton step (error
-// below one ulp), FP64 the correctly rounded division.
-template <class R> __device__ __forceinline__ R recip(R x);
-template <> __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
-template <> __device__ __forceinline__ float recip<float>(float x) {
-  const float r = __builtin_amdgcn_rcpf(x);
-  return fmaf(fmaf(-x, r, 1.0f), r, r);
+// Reciprocal of the density: FP32 takes the hardware estimate (1 ulp) and,
+// for FP32 storage, one Newton step (error below one ulp); with 16-bit
+// storage the estimate alone, whose error is four orders below the stored
+// values' spacing.  FP64: the correctly rounded division.  The reciprocal
+// enters only the second-order term of the equilibrium (the momentum part
+// is built from J itself), so it does not touch mass or momentum.
+template <int ST, class R> __device__ __forceinline__ R recip(R x) {
+  if constexpr (sizeof(R) == 8) {
+    return R(1) / x;
+  } else {
+    const float r = __builtin_amdgcn_rcpf(x);
+    if constexpr (ST == ST_F16 || ST == ST_BF16) return r;
+    else return fmaf(fmaf(-x, r, 1.0f), r, r);
+  }
 }
 
 // Fused multiply-add in the arithmetic type.  The library is compiled without
@@ -170,7 +177,7 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
   const R jx = fmar(i1, d[1] - d[3], i5 * ((d[5] - d[6]) + (d[8] - d[7])));
   const R jy = fmar(i1, d[2] - d[4], i5 * ((d[5] + d[6]) - (d[7] + d[8])));
   const R rho = par<R>(D.rho0, D.rho0_f) + drho;
-  const R irho = recip<R>(rho);
+  const R irho = recip<ST, R>(rho);
   R tau, om;
   if constexpr ((FEAT & F_POWER) != 0) {
     tau = powerlaw_tau<R, PLM, ST>(D, d, drho, rho, irho, jx, jy);
