@@ -1,5 +1,5 @@
 """Build the CPU oracle (test infrastructure): oracle/liblbo.so from lbo.c
-(D2Q9) and lbo3.c (D3Q19).
+(D2Q9) and lbo3.c (D3Q19, D3Q27).
 
 Plain gcc, FP64, no fast-math and no floating-point contraction, so that the
 oracle's single-precision noise routines round every operation separately.

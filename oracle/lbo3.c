@@ -1,7 +1,8 @@
 /*
- * lbo3.c -- CPU oracle (FP64) of the three-dimensional D3Q19 variant of the
- * lattice-Boltzmann step (the 3D lattices the paper names as its next step,
- * Sec. 8): BGK collision with the velocity-shift body force of Sec. 2
+ * lbo3.c -- CPU oracle (FP64) of the three-dimensional D3Q19 and D3Q27
+ * variants of the lattice-Boltzmann step (the 3D lattices the paper names as
+ * its next step, Sec. 8): BGK collision with the velocity-shift body force of
+ * Sec. 2
  * (u_eq = j/rho + tau g), pull streaming, halfway bounce-back on solid
  * nodes.  Optionally the two-relaxation-time (TRT) collision: populations
  * split into parts symmetric and antisymmetric under e -> -e, relaxed with
@@ -21,51 +22,66 @@
 #include <stdlib.h>
 #include <string.h>
 
-/* D3Q19: the rest velocity, the six axis velocities and the twelve edge
- * velocities (two unit components); opposite velocities sit at (i, i + 1)
- * for odd i.  Weights 1/3, 1/18, 1/36 (c_s^2 = 1/3). */
-static const int EX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-static const int EY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-static const int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+/* The rest velocity, the six axis velocities, the twelve edge velocities (two
+ * unit components) and, for D3Q27 only, the eight corner velocities (three
+ * unit components); opposite velocities sit at (i, i + 1) for odd i.
+ * D3Q19 weights 1/3, 1/18, 1/36; D3Q27 weights the products of the
+ * one-dimensional three-velocity weights 2/3 (component 0) and 1/6
+ * (component +-1): 8/27, 2/27, 1/54, 1/216.  c_s^2 = 1/3 on both. */
+static const int EX[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                           1, -1, 1, -1, 1, -1, -1, 1};
+static const int EY[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                           1, -1, 1, -1, -1, 1, 1, -1};
+static const int EZ[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                           1, -1, -1, 1, 1, -1, 1, -1};
 
-static double weight(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+static double w1d(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+static double weight(int q, int i) {
+  if (q == 27) return w1d(EX[i]) * w1d(EY[i]) * w1d(EZ[i]);
+  return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
 static int opposite(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
 struct lbo3_sim {
   lbo3_params p;
   int64_t t;
-  double *f, *fs; /* pre-collision f(t) and post-collision f*(t), [19][nz][ny][nx] */
+  int q;
+  double w[27];
+  double *f, *fs; /* pre-collision f(t) and post-collision f*(t), [q][nz][ny][nx] */
   uint8_t *solid; /* [nz][ny][nx] */
 };
 
 #define NODE(s, x, y, z) (((size_t)(z) * (s)->p.ny + (y)) * (s)->p.nx + (x))
 #define IDX(s, i, x, y, z) ((size_t)(i) * (size_t)(s)->p.nx * (s)->p.ny * (s)->p.nz + NODE(s, x, y, z))
 
-void lbo3_lattice(int *ex, int *ey, int *ez, double *w) {
-  for (int i = 0; i < 19; ++i) {
+void lbo3_lattice(int q, int *ex, int *ey, int *ez, double *w) {
+  for (int i = 0; i < q; ++i) {
     ex[i] = EX[i];
     ey[i] = EY[i];
     ez[i] = EZ[i];
-    w[i] = weight(i);
+    w[i] = weight(q, i);
   }
 }
 
-/* Equilibrium of Eq. LB2 on D3Q19 (c_s^2 = 1/3). */
-static double feq(int i, double rho, double ux, double uy, double uz) {
+/* Equilibrium of Eq. LB2 (c_s^2 = 1/3) with weight w. */
+static double feq(int i, double w, double rho, double ux, double uy, double uz) {
   double eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
   double uu = ux * ux + uy * uy + uz * uz;
-  return weight(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+  return w * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
 }
 
 lbo3_sim *lbo3_create(const lbo3_params *p, const uint8_t *mask, const double *rho,
                       const double *ux, const double *uy, const double *uz) {
   if (p->nx < 3 || p->ny < 3 || p->nz < 3 || !(p->tau > 0.5)) return NULL;
   if (p->trt && !(p->magic > 0.0)) return NULL;
+  if (p->q != 19 && p->q != 27) return NULL;
   lbo3_sim *s = (lbo3_sim *)calloc(1, sizeof(lbo3_sim));
   s->p = *p;
+  s->q = p->q;
+  for (int i = 0; i < s->q; ++i) s->w[i] = weight(s->q, i);
   size_t n = (size_t)p->nx * p->ny * p->nz;
-  s->f = (double *)calloc(19 * n, sizeof(double));
-  s->fs = (double *)calloc(19 * n, sizeof(double));
+  s->f = (double *)calloc((size_t)s->q * n, sizeof(double));
+  s->fs = (double *)calloc((size_t)s->q * n, sizeof(double));
   s->solid = (uint8_t *)calloc(n, 1);
   for (int z = 0; z < p->nz; ++z)
     for (int y = 0; y < p->ny; ++y)
@@ -78,7 +94,8 @@ lbo3_sim *lbo3_create(const lbo3_params *p, const uint8_t *mask, const double *r
         s->solid[id] = (uint8_t)sol;
         double r = rho ? rho[id] : p->rho0;
         double vx = ux ? ux[id] : 0.0, vy = uy ? uy[id] : 0.0, vz = uz ? uz[id] : 0.0;
-        for (int i = 0; i < 19; ++i) s->f[IDX(s, i, x, y, z)] = sol ? 0.0 : feq(i, r, vx, vy, vz);
+        for (int i = 0; i < s->q; ++i)
+          s->f[IDX(s, i, x, y, z)] = sol ? 0.0 : feq(i, s->w[i], r, vx, vy, vz);
       }
   return s;
 }
@@ -108,8 +125,8 @@ static void collide(lbo3_sim *s) {
     for (int y = 0; y < p->ny; ++y)
       for (int x = 0; x < p->nx; ++x) {
         if (s->solid[NODE(s, x, y, z)]) continue;
-        double fl[19], rho = 0, jx = 0, jy = 0, jz = 0;
-        for (int i = 0; i < 19; ++i) {
+        double fl[27], rho = 0, jx = 0, jy = 0, jz = 0;
+        for (int i = 0; i < s->q; ++i) {
           fl[i] = s->f[IDX(s, i, x, y, z)];
           rho += fl[i];
           jx += fl[i] * EX[i];
@@ -120,14 +137,15 @@ static void collide(lbo3_sim *s) {
         double uy = jy / rho + tm * p->gy;
         double uz = jz / rho + tm * p->gz;
         if (!p->trt) {
-          for (int i = 0; i < 19; ++i)
-            s->fs[IDX(s, i, x, y, z)] = fl[i] - (fl[i] - feq(i, rho, ux, uy, uz)) / p->tau;
+          for (int i = 0; i < s->q; ++i)
+            s->fs[IDX(s, i, x, y, z)] =
+                fl[i] - (fl[i] - feq(i, s->w[i], rho, ux, uy, uz)) / p->tau;
           continue;
         }
-        for (int i = 0; i < 19; ++i) {
+        for (int i = 0; i < s->q; ++i) {
           const int o = opposite(i);
           const double fsym = 0.5 * (fl[i] + fl[o]), fanti = 0.5 * (fl[i] - fl[o]);
-          const double ei = feq(i, rho, ux, uy, uz), eo = feq(o, rho, ux, uy, uz);
+          const double ei = feq(i, s->w[i], rho, ux, uy, uz), eo = feq(o, s->w[o], rho, ux, uy, uz);
           const double esym = 0.5 * (ei + eo), eanti = 0.5 * (ei - eo);
           s->fs[IDX(s, i, x, y, z)] = fl[i] - (fsym - esym) / p->tau - (fanti - eanti) / tm;
         }
@@ -143,10 +161,10 @@ static void stream(lbo3_sim *s) {
     for (int y = 0; y < p->ny; ++y)
       for (int x = 0; x < p->nx; ++x) {
         if (s->solid[NODE(s, x, y, z)]) {
-          for (int i = 0; i < 19; ++i) s->f[IDX(s, i, x, y, z)] = 0.0;
+          for (int i = 0; i < s->q; ++i) s->f[IDX(s, i, x, y, z)] = 0.0;
           continue;
         }
-        for (int i = 0; i < 19; ++i) {
+        for (int i = 0; i < s->q; ++i) {
           int sx = wrap(x - EX[i], p->nx), sy = wrap(y - EY[i], p->ny), sz = wrap(z - EZ[i], p->nz);
           s->f[IDX(s, i, x, y, z)] = s->solid[NODE(s, sx, sy, sz)]
                                          ? s->fs[IDX(s, opposite(i), x, y, z)]
@@ -176,7 +194,7 @@ void lbo3_moments(const lbo3_sim *s, double *rho, double *ux, double *uy, double
           continue;
         }
         double r = 0, jx = 0, jy = 0, jz = 0;
-        for (int i = 0; i < 19; ++i) {
+        for (int i = 0; i < s->q; ++i) {
           double v = s->f[IDX(s, i, x, y, z)];
           r += v;
           jx += v * EX[i];
@@ -191,7 +209,7 @@ void lbo3_moments(const lbo3_sim *s, double *rho, double *ux, double *uy, double
 }
 
 void lbo3_populations(const lbo3_sim *s, double *f) {
-  memcpy(f, s->f, 19 * (size_t)s->p.nx * s->p.ny * s->p.nz * sizeof(double));
+  memcpy(f, s->f, (size_t)s->q * s->p.nx * s->p.ny * s->p.nz * sizeof(double));
 }
 
 double lbo3_mass(const lbo3_sim *s) {
@@ -201,7 +219,7 @@ double lbo3_mass(const lbo3_sim *s) {
     for (int y = 0; y < p->ny; ++y)
       for (int x = 0; x < p->nx; ++x) {
         if (s->solid[NODE(s, x, y, z)]) continue;
-        for (int i = 0; i < 19; ++i) m += s->f[IDX(s, i, x, y, z)];
+        for (int i = 0; i < s->q; ++i) m += s->f[IDX(s, i, x, y, z)];
       }
   return m;
 }
@@ -213,7 +231,7 @@ void lbo3_momentum(const lbo3_sim *s, double *j) {
     for (int y = 0; y < p->ny; ++y)
       for (int x = 0; x < p->nx; ++x) {
         if (s->solid[NODE(s, x, y, z)]) continue;
-        for (int i = 0; i < 19; ++i) {
+        for (int i = 0; i < s->q; ++i) {
           double v = s->f[IDX(s, i, x, y, z)];
           a[0] += v * EX[i];
           a[1] += v * EY[i];

@@ -1,10 +1,10 @@
 /*
- * lbo3.h -- CPU oracle (FP64) of the D3Q19 lattice-Boltzmann step: BGK with
- * the velocity-shift body force (Sec. 2), or its two-relaxation-time (TRT)
- * variant, pull streaming with periodic wrap, halfway bounce-back on solid
- * nodes.  TEST INFRASTRUCTURE ONLY.
+ * lbo3.h -- CPU oracle (FP64) of the three-dimensional lattice-Boltzmann step
+ * on D3Q19 or D3Q27: BGK with the velocity-shift body force (Sec. 2), or its
+ * two-relaxation-time (TRT) variant, pull streaming with periodic wrap,
+ * halfway bounce-back on solid nodes.  TEST INFRASTRUCTURE ONLY.
  *
- * Arrays: nodes [nz][ny][nx] (x fastest), populations [19][nz][ny][nx].
+ * Arrays: nodes [nz][ny][nx] (x fastest), populations [q][nz][ny][nx].
  * Step order: collide every fluid node, then pull-stream.  The reported
  * velocity is u = j/rho + g/2.
  */
@@ -23,6 +23,7 @@ typedef struct {
    * (tau - 1/2)(tau_minus - 1/2) = magic */
   int32_t trt;
   double magic;
+  int32_t q; /* 19 (D3Q19) or 27 (D3Q27) */
 } lbo3_params;
 
 typedef struct lbo3_sim lbo3_sim;
@@ -36,6 +37,7 @@ void lbo3_moments(const lbo3_sim *s, double *rho, double *ux, double *uy, double
 void lbo3_populations(const lbo3_sim *s, double *f);
 double lbo3_mass(const lbo3_sim *s);
 void lbo3_momentum(const lbo3_sim *s, double *j);
-void lbo3_lattice(int *ex, int *ey, int *ez, double *w);
+/* the velocity set and weights of the q-velocity lattice (q = 19 or 27) */
+void lbo3_lattice(int q, int *ex, int *ey, int *ez, double *w);
 
 #endif

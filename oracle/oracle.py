@@ -44,7 +44,7 @@ class _Params3(C.Structure):
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("wall_x", C.c_int32), ("wall_y", C.c_int32), ("wall_z", C.c_int32),
         ("tau", C.c_double), ("rho0", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
-        ("gz", C.c_double), ("trt", C.c_int32), ("magic", C.c_double),
+        ("gz", C.c_double), ("trt", C.c_int32), ("magic", C.c_double), ("q", C.c_int32),
     ]
 
 
@@ -99,7 +99,7 @@ def _load():
     lib.lbo3_mass.restype = C.c_double
     lib.lbo3_mass.argtypes = [C.c_void_p]
     lib.lbo3_momentum.argtypes = [C.c_void_p, dptr]
-    lib.lbo3_lattice.argtypes = [P(C.c_int), P(C.c_int), P(C.c_int), dptr]
+    lib.lbo3_lattice.argtypes = [C.c_int, P(C.c_int), P(C.c_int), P(C.c_int), dptr]
     _lib = lib
     return lib
 
@@ -266,16 +266,18 @@ def own_sincos2pi(u):
 
 
 class Oracle3:
-    """One D3Q19 domain of the FP64 CPU oracle (lbo3.c).  Node arrays are
-    [nz][ny][nx]; populations [19][nz][ny][nx]."""
+    """One D3Q19 or D3Q27 domain of the FP64 CPU oracle (lbo3.c).  Node arrays
+    are [nz][ny][nx]; populations [q][nz][ny][nx]."""
 
     def __init__(self, nx, ny, nz, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0), walls=(False, False, False),
-                 obstacles=None, init=None, collision="bgk", magic=3.0 / 16.0):
-        """collision "trt": two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic."""
+                 obstacles=None, init=None, collision="bgk", magic=3.0 / 16.0, lattice="d3q19"):
+        """collision "trt": two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic;
+        lattice "d3q19" or "d3q27"."""
         lib = _load()
         self.nx, self.ny, self.nz = nx, ny, nz
+        self.q = {"d3q19": 19, "d3q27": 27}[lattice]
         c = _Params3(nx, ny, nz, int(walls[0]), int(walls[1]), int(walls[2]), tau, rho0, *g,
-                     int(collision == "trt"), magic)
+                     int(collision == "trt"), magic, self.q)
         shape = (nz, ny, nx)
         mask = None
         if obstacles is not None:
@@ -316,7 +318,7 @@ class Oracle3:
         return tuple(out)
 
     def populations(self):
-        f = np.zeros((19, self.nz, self.ny, self.nx))
+        f = np.zeros((self.q, self.nz, self.ny, self.nx))
         self._lib.lbo3_populations(self._h, _dp(f))
         return f
 
@@ -329,10 +331,10 @@ class Oracle3:
         return j
 
 
-def lattice3():
-    """(ex, ey, ez, w) of the oracle's D3Q19 velocity set."""
+def lattice3(q=19):
+    """(ex, ey, ez, w) of the oracle's D3Q19 or D3Q27 velocity set."""
     lib = _load()
-    ex, ey, ez = (C.c_int * 19)(), (C.c_int * 19)(), (C.c_int * 19)()
-    w = np.zeros(19)
-    lib.lbo3_lattice(ex, ey, ez, _dp(w))
+    ex, ey, ez = (C.c_int * q)(), (C.c_int * q)(), (C.c_int * q)()
+    w = np.zeros(q)
+    lib.lbo3_lattice(q, ex, ey, ez, _dp(w))
     return np.array(ex[:]), np.array(ey[:]), np.array(ez[:]), w
