@@ -435,18 +435,19 @@ def other_configs():
     d, _, _ = powerlaw_channel("f32")
     gpu_rate("powerlaw_4096x256_n0.5_f32", d, 4096 * 256, 2000)
     d.close()
-    # the D3Q19 lattice: 256^3 periodic, one sweep per step, FP32 storage and
-    # FP16 deviations (stochastic rounding); algorithmic bytes 2 x 19 x 4 and
-    # 2 x 19 x 2 per node update
+    # the 3D lattices: 256^3 periodic, one sweep per step, FP32 storage and
+    # FP16 deviations (stochastic rounding); algorithmic bytes 2 q s per node
+    # update (q = 19 or 27, s = 4 or 2)
     n3 = 256
-    for storage, per_node in (("f32", 152), ("f16", 76)):
-        d, _, _ = d3q19_cube(storage, n3)
-        name = f"d3q19_256cube_{storage}"
-        gpu_rate(name, d, n3 ** 3, 200)
-        d.close()
-        r = out[name]
-        r["sweep_GBps"] = round(r["gpu_mlups"] * 1e6 * per_node / 1e9, 1)
-        r["hbm_frac"] = round(r["sweep_GBps"] / HBM_PEAK_GBS, 4)
+    for lattice, q in (("d3q19", 19), ("d3q27", 27)):
+        for storage, sb in (("f32", 4), ("f16", 2)):
+            d, _, _ = d3q19_cube(storage, n3, lattice)
+            name = f"{lattice}_256cube_{storage}"
+            gpu_rate(name, d, n3 ** 3, 200)
+            d.close()
+            r = out[name]
+            r["sweep_GBps"] = round(r["gpu_mlups"] * 1e6 * 2 * q * sb / 1e9, 1)
+            r["hbm_frac"] = round(r["sweep_GBps"] / HBM_PEAK_GBS, 4)
     torch.cuda.empty_cache()
     return out
 
@@ -487,11 +488,11 @@ def powerlaw_channel(storage="f32"):
     return d, [d], 4096 * 256
 
 
-def d3q19_cube(storage="f32", n=256):
-    """The D3Q19 lattice: 256^3 periodic, tau = 0.8, at rest (16-bit storage
-    with stochastic rounding)."""
+def d3q19_cube(storage="f32", n=256, lattice="d3q19"):
+    """The 3D lattice (D3Q19, or D3Q27): 256^3 periodic, tau = 0.8, at rest
+    (16-bit storage with stochastic rounding)."""
     from paper_2006_12910_amd import lb
-    d = lb.Domain3(n, n, n, tau=0.8, storage=storage, seed=3)
+    d = lb.Domain3(n, n, n, tau=0.8, storage=storage, seed=3, lattice=lattice)
     return d, [d], n ** 3
 
 
@@ -501,7 +502,9 @@ def only_workload(name, steps, warmup):
     import torch
     make = {"fluct-ensemble": fluct_ensemble, "fluct-ensemble-f16": lambda: fluct_ensemble("f16"),
             "porous": porous_discs, "powerlaw": powerlaw_channel, "d3q19": d3q19_cube,
-            "d3q19-f16": lambda: d3q19_cube("f16")}[name]
+            "d3q19-f16": lambda: d3q19_cube("f16"),
+            "d3q27": lambda: d3q19_cube("f32", lattice="d3q27"),
+            "d3q27-f16": lambda: d3q19_cube("f16", lattice="d3q27")}[name]
     runner, doms, sites = make()
     runner.step(max(warmup, 1))
     torch.cuda.synchronize()
@@ -659,6 +662,8 @@ def cpu_baseline_other_workloads():
          Oracle(OracleParams(nx=4096, ny=256, bc_y=WALL, gx=2.648e-6, power_law=True, n_index=0.5,
                              K=0.01)), 4096 * 256, 20)
     rate("d3q19_256cube_f32", Oracle3(64, 64, 64, tau=0.8), 64 ** 3, 10, oracle_lattice="64^3")
+    rate("d3q27_256cube_f32", Oracle3(64, 64, 64, tau=0.8, lattice="d3q27"), 64 ** 3, 10,
+         oracle_lattice="64^3")
     mask, centres = inputs.replica_b1()
     o = Oracle(OracleParams(nx=1020, ny=1620, bc_x=WALL, tau=0.636, gx=1e-6, gy=-1e-5,
                             force_average=True), mask)
@@ -716,7 +721,7 @@ def main():
                          'earlier line (to profile the configuration that line measured)')
     ap.add_argument("--only", default=None,
                     choices=["fluct-ensemble", "fluct-ensemble-f16", "porous", "powerlaw", "d3q19",
-                             "d3q19-f16"],
+                             "d3q19-f16", "d3q27", "d3q27-f16"],
                     help="time one other workload alone (GPU only; for profiling) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="before the workload, copy a buffer of this size 5 times (a kernel of "

@@ -374,32 +374,37 @@ lb_status lb_autotune(lb_domain *d, int32_t steps, double *best_ms);
 lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms);
 
 /* ---------------------------------------------------------------------------
- * D3Q19 domains: the three-dimensional lattice the paper names as its next
- * step (Sec. 8), with the same BGK collision and velocity-shift body force
- * (Sec. 2, Eqs. LB1-LB2 on D3Q19: weights 1/3, 1/18, 1/36, c_s^2 = 1/3), pull
- * streaming with periodic wrap and halfway bounce-back on solid nodes.  The
- * velocity set: rest; (+-1,0,0), (0,+-1,0), (0,0,+-1); then (1,1,0),
- * (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1),
- * (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1) (opposites in consecutive pairs).
- * Host node arrays are [nz][ny][nx] (x fastest), populations
- * [19][nz][ny][nx].  Storage: deviations f_i - w_i rho0 as LB_F64, LB_F32,
- * or the 16-bit LB_F16_DELTA / LB_BF16_DELTA (Sec. 3's reduced-precision
- * storage carried to D3Q19: the stored value is the deviation times 2, 16,
- * 32 for the rest, axis and edge directions, rounded to nearest or
- * stochastically with bits hashed from (node, step, seed)); arithmetic FP64
- * for LB_F64 and FP32 otherwise, the FP32 increment holding exactly the
- * collision's mass and momentum change before the one rounding to storage.  Collision: BGK, or the
- * two-relaxation-time (TRT) variant, in which the parts of each population
- * pair symmetric and antisymmetric under e -> -e relax with 1/tau and
- * 1/tau_minus, (tau - 1/2)(tau_minus - 1/2) = magic, and the body force
- * shifts the equilibrium velocity by tau_minus g (the antisymmetric parts
- * carry the momentum); magic = 3/16 puts halfway bounce-back walls of a
- * channel exactly halfway whatever tau, magic = (tau - 1/2)^2 is BGK.  Same
- * conventions as above: caller-owned 256-byte aligned workspace,
- * stream-ordered calls, errors through lb_last_error.  No particles, noise
- * or power law. */
+ * 3D domains, D3Q19 or D3Q27: the three-dimensional lattices the paper names
+ * as its next step (Sec. 8), with the same BGK collision and velocity-shift
+ * body force (Sec. 2, Eqs. LB1-LB2 with c_s^2 = 1/3; D3Q19 weights 1/3, 1/18,
+ * 1/36; D3Q27 weights 8/27, 2/27, 1/54, 1/216), pull streaming with
+ * periodic wrap and halfway bounce-back on solid nodes.  The velocity set:
+ * rest; (+-1,0,0), (0,+-1,0), (0,0,+-1); then (1,1,0), (-1,-1,0), (1,-1,0),
+ * (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1),
+ * (0,1,-1), (0,-1,1); on D3Q27 also (1,1,1), (-1,-1,-1), (1,1,-1),
+ * (-1,-1,1), (1,-1,1), (-1,1,-1), (-1,1,1), (1,-1,-1) (opposites in
+ * consecutive pairs).  Host node arrays are [nz][ny][nx] (x fastest),
+ * populations [q][nz][ny][nx] (q = 19 or 27).  Storage: deviations
+ * f_i - w_i rho0 as LB_F64, LB_F32, or the 16-bit LB_F16_DELTA /
+ * LB_BF16_DELTA (Sec. 3's reduced-precision storage carried to 3D: the
+ * stored value is the deviation times 2, 16, 32 (D3Q19) or 4, 16, 64, 256
+ * (D3Q27) for the rest, axis, edge and corner directions, rounded to nearest
+ * or stochastically with bits hashed from (node, step, seed)); arithmetic
+ * FP64 for LB_F64 and FP32 otherwise, the FP32 increment holding exactly the
+ * collision's mass and momentum change before the one rounding to storage.
+ * Collision: BGK, or the two-relaxation-time (TRT) variant, in which the
+ * parts of each population pair symmetric and antisymmetric under e -> -e
+ * relax with 1/tau and 1/tau_minus, (tau - 1/2)(tau_minus - 1/2) = magic,
+ * and the body force shifts the equilibrium velocity by tau_minus g (the
+ * antisymmetric parts carry the momentum); magic = 3/16 puts halfway
+ * bounce-back walls of a channel exactly halfway whatever tau,
+ * magic = (tau - 1/2)^2 is BGK.  Same conventions as above: caller-owned
+ * 256-byte aligned workspace, stream-ordered calls, errors through
+ * lb_last_error.  No particles, noise or power law. */
 #define LB3_BGK 0
 #define LB3_TRT 1
+#define LB3_D3Q19 0
+#define LB3_D3Q27 1
 typedef struct lb3_domain_desc {
   uint32_t abi_version;        /* LB_ABI_VERSION                                  */
   int32_t nx, ny, nz;          /* each in [3, 4096]; rows padded to a pitch of nx */
@@ -415,6 +420,7 @@ typedef struct lb3_domain_desc {
   double magic;                /* TRT: (tau - 1/2)(tau_minus - 1/2), > 0          */
   int32_t rounding;            /* LB_ROUND_NEAREST | LB_ROUND_STOCHASTIC (16-bit) */
   uint64_t seed;               /* stochastic-rounding key                         */
+  int32_t lattice;             /* LB3_D3Q19 | LB3_D3Q27                           */
 } lb3_domain_desc;
 typedef struct lb3_domain lb3_domain;
 
@@ -429,7 +435,7 @@ lb_status lb3_step(lb3_domain *d, int64_t nsteps);
 /* rho and u = j/rho + g/2 at every node (zero on solids), host FP64
  * [nz][ny][nx] each.  Synchronises; LB_EUNSTABLE after a non-finite state. */
 lb_status lb3_moments(lb3_domain *d, double *rho, double *ux, double *uy, double *uz);
-/* Post-collision deviations, host FP64 [19][nz][ny][nx].  Synchronises. */
+/* Post-collision deviations, host FP64 [q][nz][ny][nx].  Synchronises. */
 lb_status lb3_get_populations(lb3_domain *d, double *host_dev_f);
 /* FP64 sum of rho over the non-solid nodes (fixed order).  Synchronises. */
 lb_status lb3_mass(lb3_domain *d, double *total);

@@ -1,4 +1,4 @@
-// lb3_api.hip -- C ABI of the D3Q19 domains (declared in include/lb.h):
+// lb3_api.hip -- C ABI of the D3Q19 / D3Q27 domains (declared in include/lb.h):
 // validation, workspace layout, launch sequence, host transfers.
 #include <hip/hip_runtime.h>
 
@@ -49,11 +49,14 @@ struct Layout3 {
   bool solids = false;
 };
 
+int q_of(const lb3_domain_desc *d) { return d->lattice == LB3_D3Q27 ? 27 : 19; }
+size_t elem_of(int storage) { return storage == LB_F64 ? 8 : storage == LB_F32 ? 4 : 2; }
+
 Layout3 layout3(const lb3_domain_desc *d) {
   Layout3 L;
   L.pitch = (d->nx + 63) / 64 * 64;
   const size_t nodes = (size_t)d->nz * d->ny * L.pitch;
-  const size_t fbytes = 19 * nodes * (d->storage == LB_F64 ? 8 : d->storage == LB_F32 ? 4 : 2);
+  const size_t fbytes = (size_t)q_of(d) * nodes * elem_of(d->storage);
   L.solids = d->obstacles || d->wall_x || d->wall_y || d->wall_z;
   size_t o = 0;
   L.desc = o; o += al256(sizeof(Dom3));
@@ -63,7 +66,7 @@ Layout3 layout3(const lb3_domain_desc *d) {
   L.nodew = o; if (L.solids) o += al256(nodes * 4);
   L.mask = o; if (L.solids) o += al256(nodes);
   L.partials = o; o += al256((size_t)d->nz * 8);
-  L.stage = o; o += al256((size_t)19 * BAND * 8);
+  L.stage = o; o += al256((size_t)q_of(d) * BAND * 8);
   L.total = o;
   return L;
 }
@@ -76,6 +79,8 @@ lb_status validate3(const lb3_domain_desc *d) {
   if (d->storage != LB_F64 && d->storage != LB_F32 && d->storage != LB_F16_DELTA &&
       d->storage != LB_BF16_DELTA)
     return fail3(LB_EINVAL, "storage must be LB_F64, LB_F32, LB_F16_DELTA or LB_BF16_DELTA");
+  if (d->lattice != LB3_D3Q19 && d->lattice != LB3_D3Q27)
+    return fail3(LB_EINVAL, "lattice must be LB3_D3Q19 or LB3_D3Q27");
   if (d->rounding != LB_ROUND_NEAREST && d->rounding != LB_ROUND_STOCHASTIC)
     return fail3(LB_EINVAL, "rounding must be LB_ROUND_NEAREST or LB_ROUND_STOCHASTIC");
   if (d->rounding == LB_ROUND_STOCHASTIC && d->storage != LB_F16_DELTA &&
@@ -98,15 +103,21 @@ lb_status validate3(const lb3_domain_desc *d) {
 
 unsigned blocks_of(long long n) { return (unsigned)((n + 255) / 256); }
 
-// launches kernel template K instantiated for storage format st (validated)
-#define LB3_DISPATCH(st, K, ...)                                                  \
+// launches kernel template K<storage, q> for storage format st and lattice
+// size q (both validated)
+#define LB3_DISPATCH_Q(st, Qv, K, ...)                                            \
   do {                                                                            \
     switch (st) {                                                                 \
-      case LB_F64: hipLaunchKernelGGL(K<0>, __VA_ARGS__); break;                  \
-      case LB_F32: hipLaunchKernelGGL(K<1>, __VA_ARGS__); break;                  \
-      case LB_F16_DELTA: hipLaunchKernelGGL(K<2>, __VA_ARGS__); break;            \
-      default: hipLaunchKernelGGL(K<3>, __VA_ARGS__); break;                      \
+      case LB_F64: hipLaunchKernelGGL((K<0, Qv>), __VA_ARGS__); break;            \
+      case LB_F32: hipLaunchKernelGGL((K<1, Qv>), __VA_ARGS__); break;            \
+      case LB_F16_DELTA: hipLaunchKernelGGL((K<2, Qv>), __VA_ARGS__); break;      \
+      default: hipLaunchKernelGGL((K<3, Qv>), __VA_ARGS__); break;                \
     }                                                                             \
+  } while (0)
+#define LB3_DISPATCH(d, K, ...)                                                   \
+  do {                                                                            \
+    if ((d)->q == 27) LB3_DISPATCH_Q((d)->desc.storage, 27, K, __VA_ARGS__);      \
+    else LB3_DISPATCH_Q((d)->desc.storage, 19, K, __VA_ARGS__);                   \
   } while (0)
 
 }  // namespace
@@ -119,6 +130,7 @@ struct lb3_domain {
   Dom3 hd{};
   int64_t t = 0;
   bool wide = false;               // the sweep takes 64-bit byte offsets
+  int q = 19;                      // lattice velocities
   std::vector<uint8_t> host_mask;  // [nz][ny][pitch]: walls and obstacles
   Dom3 *ddesc() const { return (Dom3 *)(ws + L.desc); }
   Header3 *dhdr() const { return (Header3 *)(ws + L.hdr); }
@@ -139,8 +151,13 @@ lb_status check_health3(lb3_domain *d) {
 lb_status upload_solids(lb3_domain *d) {
   HIPCHK3(hipMemcpyAsync(d->ws + d->L.mask, d->host_mask.data(), d->host_mask.size(),
                          hipMemcpyHostToDevice, d->stream));
-  hipLaunchKernelGGL(k_words3, dim3(blocks_of(d->nodes())), dim3(256), 0, d->stream, d->ddesc(),
-                     (const uint8_t *)(d->ws + d->L.mask));
+  const uint8_t *dm = (const uint8_t *)(d->ws + d->L.mask);
+  if (d->q == 27)
+    hipLaunchKernelGGL(k_words3<27>, dim3(blocks_of(d->nodes())), dim3(256), 0, d->stream, d->ddesc(),
+                       dm);
+  else
+    hipLaunchKernelGGL(k_words3<19>, dim3(blocks_of(d->nodes())), dim3(256), 0, d->stream, d->ddesc(),
+                       dm);
   HIPCHK3(hipGetLastError());
   HIPCHK3(hipStreamSynchronize(d->stream));
   return LB_OK;
@@ -162,7 +179,7 @@ lb_status init3(lb3_domain *d, const double *rho, const double *ux, const double
         a[k] = st + k * BAND;
       }
     }
-    LB3_DISPATCH(d->desc.storage, k_init3, dim3(blocks_of(cnt)), dim3(256), 0, d->stream,
+    LB3_DISPATCH(d, k_init3, dim3(blocks_of(cnt)), dim3(256), 0, d->stream,
                  d->ddesc(), a[0], a[1], a[2], a[3], n0, cnt);
     HIPCHK3(hipGetLastError());
     HIPCHK3(hipStreamSynchronize(d->stream));
@@ -191,19 +208,23 @@ lb_status push_desc3(lb3_domain *d) {
 
 namespace {
 
-template <int ST> void launch_sweep3_st(const lb3_domain *d, unsigned blocks, int k) {
+template <int ST, int Q> void launch_sweep3_q(const lb3_domain *d, unsigned blocks, int k) {
   const dim3 g(blocks), b(256);
   if (d->L.solids) {
     if (d->wide)
-      hipLaunchKernelGGL((k_sweep3<ST, true, true>), g, b, 0, d->stream, d->ddesc(), k);
+      hipLaunchKernelGGL((k_sweep3<ST, true, true, Q>), g, b, 0, d->stream, d->ddesc(), k);
     else
-      hipLaunchKernelGGL((k_sweep3<ST, true, false>), g, b, 0, d->stream, d->ddesc(), k);
+      hipLaunchKernelGGL((k_sweep3<ST, true, false, Q>), g, b, 0, d->stream, d->ddesc(), k);
   } else {
     if (d->wide)
-      hipLaunchKernelGGL((k_sweep3<ST, false, true>), g, b, 0, d->stream, d->ddesc(), k);
+      hipLaunchKernelGGL((k_sweep3<ST, false, true, Q>), g, b, 0, d->stream, d->ddesc(), k);
     else
-      hipLaunchKernelGGL((k_sweep3<ST, false, false>), g, b, 0, d->stream, d->ddesc(), k);
+      hipLaunchKernelGGL((k_sweep3<ST, false, false, Q>), g, b, 0, d->stream, d->ddesc(), k);
   }
+}
+template <int ST> void launch_sweep3_st(const lb3_domain *d, unsigned blocks, int k) {
+  if (d->q == 27) launch_sweep3_q<ST, 27>(d, blocks, k);
+  else launch_sweep3_q<ST, 19>(d, blocks, k);
 }
 
 void launch_sweep3(const lb3_domain *d, unsigned blocks, int k) {
@@ -260,8 +281,9 @@ static lb_status lb3_create_domain_impl(const lb3_domain_desc *desc, void *dev_w
   h.nz = desc->nz;
   h.pitch = L.pitch;
   h.storage = desc->storage;
-  // 32-bit byte offsets while the 19 population planes stay below 2^32 bytes
-  d->wide = 19.0 * (double)d->desc.nz * d->desc.ny * L.pitch *
+  // 32-bit byte offsets while the q population planes stay below 2^32 bytes
+  d->q = q_of(desc);
+  d->wide = (double)d->q * d->desc.nz * d->desc.ny * L.pitch *
                 (desc->storage == LB_F64 ? 8 : desc->storage == LB_F32 ? 4 : 2) >=
             4294967296.0;
   h.sr = desc->rounding == LB_ROUND_STOCHASTIC ? 1 : 0;
@@ -278,11 +300,13 @@ static lb_status lb3_create_domain_impl(const lb3_domain_desc *desc, void *dev_w
   h.tau_m_f = (float)h.tau_m;
   h.omega_m_f = (float)h.omega_m;
   {
-    // 16-bit storage: coefficients in the stored scaling (K w = 8/9)
+    // 16-bit storage: coefficients in the stored scaling (K w of every
+    // moving direction: 8/9 on D3Q19, 32/27 on D3Q27)
     const double f = h.trt ? 1.0 : h.omega;
-    h.s_cw = (float)(f * 8.0 / 9.0);
-    h.s_cq = (float)(f * 4.0);
-    h.s_cl = (float)(f * 8.0 / 3.0);
+    const double kw = d->q == 27 ? 32.0 / 27.0 : 8.0 / 9.0;
+    h.s_cw = (float)(f * kw);
+    h.s_cq = (float)(4.5 * f * kw);
+    h.s_cl = (float)(3.0 * f * kw);
     h.s_om0 = (float)f;
     h.keep_f = (float)(1.0 - h.omega);
   }
@@ -379,7 +403,7 @@ static lb_status lb3_moments_impl(lb3_domain *d, double *rho, double *ux, double
   double *h[4] = {rho, ux, uy, uz};
   for (long long n0 = 0; n0 < n; n0 += BAND) {
     const long long cnt = std::min(BAND, n - n0);
-    LB3_DISPATCH(d->desc.storage, k_moments3, dim3(blocks_of(cnt)), dim3(256), 0, d->stream,
+    LB3_DISPATCH(d, k_moments3, dim3(blocks_of(cnt)), dim3(256), 0, d->stream,
                  d->ddesc(), st, n0, cnt);
     HIPCHK3(hipGetLastError());
     for (int k = 0; k < 4; ++k)
@@ -399,10 +423,10 @@ static lb_status lb3_get_populations_impl(lb3_domain *d, double *f) {
   double *st = (double *)(d->ws + d->L.stage);
   for (long long n0 = 0; n0 < n; n0 += BAND) {
     const long long cnt = std::min(BAND, n - n0);
-    LB3_DISPATCH(d->desc.storage, k_export3, dim3(blocks_of(cnt)), dim3(256), 0, d->stream,
+    LB3_DISPATCH(d, k_export3, dim3(blocks_of(cnt)), dim3(256), 0, d->stream,
                  d->ddesc(), st, n0, cnt);
     HIPCHK3(hipGetLastError());
-    for (int i = 0; i < 19; ++i)
+    for (int i = 0; i < d->q; ++i)
       HIPCHK3(hipMemcpyAsync(f + (size_t)i * n + n0, st + (size_t)i * cnt, cnt * 8,
                              hipMemcpyDeviceToHost, d->stream));
     HIPCHK3(hipStreamSynchronize(d->stream));
@@ -416,7 +440,7 @@ lb_status lb3_get_populations(lb3_domain *d, double *f) {
 
 static lb_status lb3_mass_impl(lb3_domain *d, double *total) {
   if (!d || !total) return fail3(LB_EINVAL, "null argument");
-  LB3_DISPATCH(d->desc.storage, k_mass3_partial, dim3(d->desc.nz), dim3(256), 0, d->stream,
+  LB3_DISPATCH(d, k_mass3_partial, dim3(d->desc.nz), dim3(256), 0, d->stream,
                d->ddesc());
   hipLaunchKernelGGL(k_mass3_final, dim3(1), dim3(64), 0, d->stream, d->ddesc());
   HIPCHK3(hipGetLastError());
@@ -446,14 +470,14 @@ static lb_status lb3_set_option_impl(lb3_domain *d, int32_t option, int64_t valu
       if (value != 0 && value != 1) return fail3(LB_EINVAL, "LB3_OPT_WIDE_OFFSETS takes 0 or 1");
       const Layout3 &L = d->L;
       const size_t e = d->desc.storage == LB_F64 ? 8 : d->desc.storage == LB_F32 ? 4 : 2;
-      const bool need = 19.0 * (double)d->desc.nz * d->desc.ny * L.pitch * e >= 4294967296.0;
+      const bool need = (double)d->q * d->desc.nz * d->desc.ny * L.pitch * e >= 4294967296.0;
       if (!value && need)
         return fail3(LB_EINVAL, "population buffer reaches 2^32 bytes: offsets must stay 64-bit");
       d->wide = value != 0;
       return LB_OK;
     }
   }
-  return fail3(LB_EINVAL, "unknown D3Q19 option");
+  return fail3(LB_EINVAL, "unknown option of a 3D domain");
 }
 
 lb_status lb3_set_option(lb3_domain *d, int32_t option, int64_t value) {

@@ -1,5 +1,6 @@
-// sweep3_impl.h -- the D3Q19 variant of the fused stream-collide sweep (the
-// three-dimensional lattice the paper names as its next step, Sec. 8): BGK
+// sweep3_impl.h -- the D3Q19 and D3Q27 variants of the fused stream-collide
+// sweep (the three-dimensional lattices the paper names as its next step,
+// Sec. 8): BGK
 // or two-relaxation-time collision with the velocity-shift body force of
 // Sec. 2, pull streaming with periodic wrap and halfway bounce-back on solid
 // nodes, FP64, FP32, FP16 or BF16 storage of the deviations
@@ -15,19 +16,34 @@
 
 namespace lbk3 {
 
-// D3Q19: rest, six axis velocities, twelve edge velocities; opposite
-// velocities at (i, i + 1) for odd i.  Weights 1/3, 1/18, 1/36.
+// Rest, six axis velocities, twelve edge velocities (D3Q19), then eight
+// corner velocities (D3Q27); opposite velocities at (i, i + 1) for odd i.
+// Weights: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216 (products of
+// the one-dimensional 2/3, 1/6).
 __host__ __device__ constexpr int ex(int i) {
-  return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
-       : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
+  return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13 || i == 19 || i == 21 || i == 23 ||
+          i == 26) ? 1
+       : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14 || i == 20 || i == 22 || i == 24 ||
+          i == 25) ? -1 : 0;
 }
 __host__ __device__ constexpr int ey(int i) {
-  return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
-       : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
+  return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17 || i == 19 || i == 21 || i == 24 ||
+          i == 25) ? 1
+       : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18 || i == 20 || i == 22 || i == 23 ||
+          i == 26) ? -1 : 0;
 }
 __host__ __device__ constexpr int ez(int i) {
-  return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
-       : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
+  return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18 || i == 19 || i == 22 || i == 23 ||
+          i == 25) ? 1
+       : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17 || i == 20 || i == 21 || i == 24 ||
+          i == 26) ? -1 : 0;
+}
+// velocity class: 0 rest, 1 axis, 2 edge, 3 corner
+__host__ __device__ constexpr int cls3(int i) { return i == 0 ? 0 : (i <= 6 ? 1 : (i <= 18 ? 2 : 3)); }
+template <class R> __host__ __device__ constexpr R w3(int q, int i) {
+  return q == 27 ? (cls3(i) == 0 ? R(8) / R(27) : cls3(i) == 1 ? R(2) / R(27)
+                                                  : cls3(i) == 2 ? R(1) / R(54) : R(1) / R(216))
+                 : (cls3(i) == 0 ? R(1) / R(3) : cls3(i) == 1 ? R(1) / R(18) : R(1) / R(36));
 }
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 static_assert(ex(1) == 1 && ex(2) == -1 && ey(3) == 1 && ey(4) == -1 && ez(5) == 1 && ez(6) == -1,
@@ -35,11 +51,18 @@ static_assert(ex(1) == 1 && ex(2) == -1 && ey(3) == 1 && ey(4) == -1 && ez(5) ==
 static_assert(ex(7) == 1 && ey(7) == 1 && ex(8) == -1 && ey(8) == -1, "edge pair 7/8");
 static_assert(ex(17) == 0 && ey(17) == 1 && ez(17) == -1 && ey(18) == -1 && ez(18) == 1,
               "edge pair 17/18");
+static_assert(ex(19) == 1 && ey(19) == 1 && ez(19) == 1 && ex(21) == 1 && ey(21) == 1 && ez(21) == -1 &&
+                  ex(23) == 1 && ey(23) == -1 && ez(23) == 1 && ex(25) == -1 && ey(25) == 1 &&
+                  ez(25) == 1,
+              "corners 19, 21, 23, 25");
+static_assert(ex(20) == -1 && ey(20) == -1 && ez(20) == -1 && ex(26) == 1 && ey(26) == -1 &&
+                  ez(26) == -1,
+              "corners 20, 26");
 
 constexpr uint32_t NODE_SOLID3 = 0x80000000u;  // node word: the node is solid
 
 struct Dom3 {
-  void *f[2];          // populations [19][nz][ny][pitch], deviations
+  void *f[2];          // populations [Q][nz][ny][pitch], deviations
   uint32_t *nodew;     // [nz][ny][pitch]: NODE_SOLID3, or bit i-1 when the
                        // source x - e_i is solid; null without solids
   uint64_t *tstep;
@@ -70,46 +93,50 @@ __device__ __forceinline__ float fmr(float a, float b, float c) { return __built
 __device__ __forceinline__ double fmr(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Storage of the deviations: FP64 and FP32 as they are; the 16-bit formats
-// hold d_i K_i with K = 2 (rest), 16 (axis), 32 (edge) -- powers of two, so
-// scaling is exact and w_i K_i is 2/3, 8/9, 8/9: the small edge deviations
-// keep clear of the FP16 subnormal range -- converted with round to nearest
-// or the hardware's stochastic rounding.
-__host__ __device__ constexpr float scale3(int i) { return i == 0 ? 2.0f : (i <= 6 ? 16.0f : 32.0f); }
+// hold d_i K_i with powers of two K (so scaling is exact) near 1 / w_i, which
+// keeps the small deviations of the long velocities clear of the FP16
+// subnormal range: D3Q19 K = 2, 16, 32 (w K = 2/3, 8/9, 8/9), D3Q27 K = 4,
+// 16, 64, 256 (w K = 32/27 for every class); converted with round to
+// nearest or the hardware's stochastic rounding.
+__host__ __device__ constexpr float scale3(int q, int i) {
+  return q == 27 ? (cls3(i) == 0 ? 4.0f : cls3(i) == 1 ? 16.0f : cls3(i) == 2 ? 64.0f : 256.0f)
+                 : (cls3(i) == 0 ? 2.0f : cls3(i) == 1 ? 16.0f : 32.0f);
+}
 template <int ST> struct S3;
 template <> struct S3<0> {
   using T = double;
   using R = double;
-  static __device__ __forceinline__ R dec(T v, int) { return v; }
-  static __device__ __forceinline__ T enc(R v, int, bool, uint32_t) { return v; }
+  static __device__ __forceinline__ R dec(T v, int, int) { return v; }
+  static __device__ __forceinline__ T enc(R v, int, int, bool, uint32_t) { return v; }
 };
 template <> struct S3<1> {
   using T = float;
   using R = float;
-  static __device__ __forceinline__ R dec(T v, int) { return v; }
-  static __device__ __forceinline__ T enc(R v, int, bool, uint32_t) { return v; }
+  static __device__ __forceinline__ R dec(T v, int, int) { return v; }
+  static __device__ __forceinline__ T enc(R v, int, int, bool, uint32_t) { return v; }
 };
 template <> struct S3<2> {
   using T = uint16_t;
   using R = float;
-  static __device__ __forceinline__ R dec(T v, int i) { return lbk::f16_to_f32(v) * (1.0f / scale3(i)); }
+  static __device__ __forceinline__ R dec(T v, int q, int i) { return lbk::f16_to_f32(v) * (1.0f / scale3(q, i)); }
   static __device__ __forceinline__ R raw(T v) { return lbk::f16_to_f32(v); }
   static __device__ __forceinline__ T enc_raw(R v, bool sr, uint32_t r) {
     return sr ? lbk::f32_to_f16_sr(v, r) : lbk::f32_to_f16_rn(v);
   }
-  static __device__ __forceinline__ T enc(R v, int i, bool sr, uint32_t r) {
-    return sr ? lbk::f32_to_f16_sr(v * scale3(i), r) : lbk::f32_to_f16_rn(v * scale3(i));
+  static __device__ __forceinline__ T enc(R v, int q, int i, bool sr, uint32_t r) {
+    return sr ? lbk::f32_to_f16_sr(v * scale3(q, i), r) : lbk::f32_to_f16_rn(v * scale3(q, i));
   }
 };
 template <> struct S3<3> {
   using T = uint16_t;
   using R = float;
-  static __device__ __forceinline__ R dec(T v, int i) { return lbk::bf16_to_f32(v) * (1.0f / scale3(i)); }
+  static __device__ __forceinline__ R dec(T v, int q, int i) { return lbk::bf16_to_f32(v) * (1.0f / scale3(q, i)); }
   static __device__ __forceinline__ R raw(T v) { return lbk::bf16_to_f32(v); }
   static __device__ __forceinline__ T enc_raw(R v, bool sr, uint32_t r) {
     return sr ? lbk::f32_to_bf16_sr(v, r) : lbk::f32_to_bf16_rn(v);
   }
-  static __device__ __forceinline__ T enc(R v, int i, bool sr, uint32_t r) {
-    return sr ? lbk::f32_to_bf16_sr(v * scale3(i), r) : lbk::f32_to_bf16_rn(v * scale3(i));
+  static __device__ __forceinline__ T enc(R v, int q, int i, bool sr, uint32_t r) {
+    return sr ? lbk::f32_to_bf16_sr(v * scale3(q, i), r) : lbk::f32_to_bf16_rn(v * scale3(q, i));
   }
 };
 
@@ -122,7 +149,7 @@ __device__ __forceinline__ uint32_t round_bits3(const Dom3 &D, uint32_t node, ui
 // BGK or TRT collision of one node in deviation form.  The equilibrium of
 // Eq. LB2 with u = J / rho, J = j + rho tau_m g (tau_m = tau for BGK):
 // opposite velocities share the even part c and take c +- 3 w (e.J); the
-// rest population is delta rho less the other eighteen.  BGK relaxes every
+// rest population is delta rho less the others.  BGK relaxes every
 // d_i with omega; TRT relaxes the part of (feq - d) symmetric over a pair
 // with omega and the antisymmetric part with omega_m (the rest population is
 // symmetric).  FP32 arithmetic forms the increment and gives it exactly the
@@ -130,13 +157,13 @@ __device__ __forceinline__ uint32_t round_bits3(const Dom3 &D, uint32_t node, ui
 // increments before the one final rounding, as the D2Q9 sweep does (the
 // momentum term of the stored values would otherwise round the body force
 // of slow flows with a bias).
-template <class R> __device__ __forceinline__ void collide3(const Dom3 &D, R d[19]) {
+template <class R, int Q> __device__ __forceinline__ void collide3(const Dom3 &D, R d[Q]) {
   R drho = d[0];
 #pragma unroll
-  for (int i = 1; i < 19; i += 2) drho += d[i] + d[i + 1];
+  for (int i = 1; i < Q; i += 2) drho += d[i] + d[i + 1];
   R jx = R(0), jy = R(0), jz = R(0);
 #pragma unroll
-  for (int i = 1; i < 19; i += 2) {
+  for (int i = 1; i < Q; i += 2) {
     const R o = d[i] - d[i + 1];  // e_{i+1} = -e_i
     if (ex(i)) jx += R(ex(i)) * o;
     if (ey(i)) jy += R(ey(i)) * o;
@@ -152,10 +179,10 @@ template <class R> __device__ __forceinline__ void collide3(const Dom3 &D, R d[1
   const R ux = Jx * irho, uy = Jy * irho, uz = Jz * irho;
   const R q = (R(1.5) * rho) * fmr(ux, ux, fmr(uy, uy, uz * uz));
   const R r45 = R(4.5) * rho;
-  R eq[19];
+  R eq[Q];
 #pragma unroll
-  for (int i = 1; i < 19; i += 2) {
-    const R w = i <= 6 ? R(1) / R(18) : R(1) / R(36);
+  for (int i = 1; i < Q; i += 2) {
+    const R w = w3<R>(Q, i);
     const R eu = R(ex(i)) * ux + R(ey(i)) * uy + R(ez(i)) * uz;
     const R eJ = R(ex(i)) * Jx + R(ey(i)) * Jy + R(ez(i)) * Jz;
     const R c = w * (drho + fmr(r45 * eu, eu, -q));
@@ -164,10 +191,10 @@ template <class R> __device__ __forceinline__ void collide3(const Dom3 &D, R d[1
     eq[i + 1] = c - l;
   }
   if constexpr (sizeof(R) == 4) {
-    R inc[19];
+    R inc[Q];
     if (D.trt) {
 #pragma unroll
-      for (int i = 1; i < 19; i += 2) {
+      for (int i = 1; i < Q; i += 2) {
         const R a = eq[i] - d[i], b = eq[i + 1] - d[i + 1];
         const R sym = R(0.5) * (a + b), anti = R(0.5) * (a - b);
         inc[i] = fmr(om, sym, omm * anti);
@@ -175,11 +202,11 @@ template <class R> __device__ __forceinline__ void collide3(const Dom3 &D, R d[1
       }
     } else {
 #pragma unroll
-      for (int i = 1; i < 19; ++i) inc[i] = om * (eq[i] - d[i]);
+      for (int i = 1; i < Q; ++i) inc[i] = om * (eq[i] - d[i]);
     }
     R sx = R(0), sy = R(0), sz = R(0);
 #pragma unroll
-    for (int i = 1; i < 19; i += 2) {
+    for (int i = 1; i < Q; i += 2) {
       const R o = inc[i] - inc[i + 1];
       if (ex(i)) sx += R(ex(i)) * o;
       if (ey(i)) sy += R(ey(i)) * o;
@@ -195,19 +222,19 @@ template <class R> __device__ __forceinline__ void collide3(const Dom3 &D, R d[1
     inc[6] -= hz;
     R m = R(0);
 #pragma unroll
-    for (int i = 1; i < 19; i += 2) m += inc[i] + inc[i + 1];
+    for (int i = 1; i < Q; i += 2) m += inc[i] + inc[i + 1];
     inc[0] = -m;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = d[i] + inc[i];
+    for (int i = 0; i < Q; ++i) d[i] = d[i] + inc[i];
   } else {
     R s = R(0);
 #pragma unroll
-    for (int i = 1; i < 19; i += 2) s += eq[i] + eq[i + 1];
+    for (int i = 1; i < Q; i += 2) s += eq[i] + eq[i + 1];
     eq[0] = drho - s;
     if (D.trt) {
       d[0] = fmr(om, eq[0] - d[0], d[0]);
 #pragma unroll
-      for (int i = 1; i < 19; i += 2) {
+      for (int i = 1; i < Q; i += 2) {
         const R a = eq[i] - d[i], b = eq[i + 1] - d[i + 1];
         const R sym = R(0.5) * (a + b), anti = R(0.5) * (a - b);
         d[i] += fmr(om, sym, omm * anti);
@@ -215,55 +242,68 @@ template <class R> __device__ __forceinline__ void collide3(const Dom3 &D, R d[1
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < 19; ++i) d[i] = fmr(om, eq[i] - d[i], d[i]);
+      for (int i = 0; i < Q; ++i) d[i] = fmr(om, eq[i] - d[i], d[i]);
     }
   }
 }
 
 // The same collision for the 16-bit formats, on the stored values d_i K_i
-// (K = 2, 16, 32) in FP32.  In that scaling every moving direction has
-// K_i w_i = 8/9, so its even part is cw (drho - q) + cq rho (e.u)^2 and its
-// linear part cl (e.J), one coefficient triple per domain (times omega for
-// BGK, so that the relaxation is one fma a direction); the rest population
-// takes the mass balance, K_0 (omega drho - sum of the others / K_i).  The
-// pair sums and differences of the stored values give drho and j and, for
-// TRT, the symmetric and antisymmetric parts.  Relaxation is applied to the
-// stored values directly (no increment form: the rounding to 16 bits is
-// far coarser than the FP32 arithmetic).
-__device__ __forceinline__ void collide3_scaled(const Dom3 &D, float d[19]) {
-  float ps[10], pd[10];  // pair k: directions 2k - 1 and 2k
+// in FP32.  In that scaling every moving direction has the same K_i w_i
+// (8/9 on D3Q19, 32/27 on D3Q27), so its even part is cw (drho - q) +
+// cq rho (e.u)^2 and its linear part cl (e.J), one coefficient triple per
+// domain (times omega for BGK, so that the relaxation is one fma a
+// direction); the rest population takes the mass balance,
+// K_0 (omega drho - sum of the others / K_i).  The pair sums and
+// differences of the stored values give drho and j and, for TRT, the
+// symmetric and antisymmetric parts.  Relaxation is applied to the stored
+// values directly (no increment form: the rounding to 16 bits is far
+// coarser than the FP32 arithmetic).
+template <int Q> __device__ __forceinline__ void collide3_scaled(const Dom3 &D, float d[Q]) {
+  constexpr int P = (Q - 1) / 2;  // direction pairs: k covers 2k - 1 and 2k
+  float ps[P + 1], pd[P + 1];
 #pragma unroll
-  for (int k = 1; k <= 9; ++k) {
+  for (int k = 1; k <= P; ++k) {
     ps[k] = d[2 * k - 1] + d[2 * k];
     pd[k] = d[2 * k - 1] - d[2 * k];
   }
-  const float sa = (ps[1] + ps[2]) + ps[3];
-  const float se = ((ps[4] + ps[5]) + (ps[6] + ps[7])) + (ps[8] + ps[9]);
-  const float drho = fmr(0.5f, d[0], fmr(1.0f / 16.0f, sa, (1.0f / 32.0f) * se));
-  float ex2 = 0.0f, ey2 = 0.0f, ez2 = 0.0f;  // edge parts of j, times 32
+  // per class (axis, edge, corner): the sums of the pairs' sums, and the
+  // momentum parts sum e pd; scaled back by 1 / K of the class
+  float sc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  float jc[4][3] = {};
 #pragma unroll
-  for (int k = 4; k <= 9; ++k) {
-    const int i = 2 * k - 1;
-    if (ex(i)) ex2 += float(ex(i)) * pd[k];
-    if (ey(i)) ey2 += float(ey(i)) * pd[k];
-    if (ez(i)) ez2 += float(ez(i)) * pd[k];
+  for (int k = 1; k <= P; ++k) {
+    const int i = 2 * k - 1, c = cls3(i);
+    sc[c] += ps[k];
+    if (ex(i)) jc[c][0] += float(ex(i)) * pd[k];
+    if (ey(i)) jc[c][1] += float(ey(i)) * pd[k];
+    if (ez(i)) jc[c][2] += float(ez(i)) * pd[k];
   }
-  const float jx = fmr(1.0f / 16.0f, pd[1], (1.0f / 32.0f) * ex2);
-  const float jy = fmr(1.0f / 16.0f, pd[2], (1.0f / 32.0f) * ey2);
-  const float jz = fmr(1.0f / 16.0f, pd[3], (1.0f / 32.0f) * ez2);
+  constexpr float i0 = 1.0f / scale3(Q, 0), i1 = 1.0f / scale3(Q, 1), i2 = 1.0f / scale3(Q, 7),
+                  i3 = 1.0f / scale3(Q, Q - 1);
+  float drho = fmr(i0, d[0], fmr(i1, sc[1], i2 * sc[2]));
+  float jxyz[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) jxyz[a] = fmr(i1, jc[1][a], i2 * jc[2][a]);
+  if constexpr (Q == 27) {
+    drho = fmr(i3, sc[3], drho);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) jxyz[a] = fmr(i3, jc[3][a], jxyz[a]);
+  }
   const float rho = D.rho0_f + drho;
   const float irho = __builtin_amdgcn_rcpf(rho);  // 1 ulp: enters only the second-order term
   const float rt = rho * D.tau_m_f;
-  const float Jx = fmr(rt, D.gx_f, jx), Jy = fmr(rt, D.gy_f, jy), Jz = fmr(rt, D.gz_f, jz);
+  const float Jx = fmr(rt, D.gx_f, jxyz[0]), Jy = fmr(rt, D.gy_f, jxyz[1]),
+              Jz = fmr(rt, D.gz_f, jxyz[2]);
   const float ux = Jx * irho, uy = Jy * irho, uz = Jz * irho;
   const float q = (1.5f * rho) * fmr(ux, ux, fmr(uy, uy, uz * uz));
   const float b = D.s_cw * (drho - q);
   const float a = D.s_cq * rho;
   const float ax = a * ux, ay = a * uy, az = a * uz;
   const float lx = D.s_cl * Jx, ly = D.s_cl * Jy, lz = D.s_cl * Jz;
-  float c[10], l[10];
+  float c[P + 1], l[P + 1];
+  float cs[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // per class: sum of the even parts
 #pragma unroll
-  for (int k = 1; k <= 9; ++k) {
+  for (int k = 1; k <= P; ++k) {
     const int i = 2 * k - 1;
     float eu = 0.0f, aeu = 0.0f, lin = 0.0f;
     if (ex(i)) { eu += float(ex(i)) * ux; aeu += float(ex(i)) * ax; lin += float(ex(i)) * lx; }
@@ -271,16 +311,18 @@ __device__ __forceinline__ void collide3_scaled(const Dom3 &D, float d[19]) {
     if (ez(i)) { eu += float(ez(i)) * uz; aeu += float(ez(i)) * az; lin += float(ez(i)) * lz; }
     c[k] = fmr(aeu, eu, b);
     l[k] = lin;
+    cs[cls3(i)] += c[k];
   }
-  const float ca = (c[1] + c[2]) + c[3];
-  const float ce = ((c[4] + c[5]) + (c[6] + c[7])) + (c[8] + c[9]);
-  // pair k contributes 2 c_k / K: rest = 2 om0 drho - ca / 4 - ce / 8
-  const float eq0 = fmr(2.0f * D.s_om0, drho, -fmr(0.25f, ca, 0.125f * ce));
+  // pair k contributes 2 c_k / K: rest = K0 om0 drho - 2 K0 sum_class cs / K_class
+  constexpr float K0 = scale3(Q, 0);
+  float others = fmr(i1, cs[1], i2 * cs[2]);
+  if constexpr (Q == 27) others = fmr(i3, cs[3], others);
+  const float eq0 = fmr(K0 * D.s_om0, drho, -(2.0f * K0) * others);
   if (!D.trt) {
     const float keep = D.keep_f;
     d[0] = fmr(keep, d[0], eq0);
 #pragma unroll
-    for (int k = 1; k <= 9; ++k) {
+    for (int k = 1; k <= P; ++k) {
       d[2 * k - 1] = fmr(keep, d[2 * k - 1], c[k] + l[k]);
       d[2 * k] = fmr(keep, d[2 * k], c[k] - l[k]);
     }
@@ -288,7 +330,7 @@ __device__ __forceinline__ void collide3_scaled(const Dom3 &D, float d[19]) {
     const float om = D.omega_f, omm = D.omega_m_f;
     d[0] = fmr(om, eq0 - d[0], d[0]);
 #pragma unroll
-    for (int k = 1; k <= 9; ++k) {
+    for (int k = 1; k <= P; ++k) {
       const float sym = fmr(-0.5f, ps[k], c[k]), anti = fmr(-0.5f, pd[k], l[k]);
       const float t = omm * anti;
       d[2 * k - 1] += fmr(om, sym, t);
@@ -339,18 +381,19 @@ template <class T> __device__ __forceinline__ void st3(Res3 r, uint32_t voff, ui
 
 // One step of every node: 256 threads = a tile of 64 (x) by 4 (y) nodes of
 // one z plane; each wave reads 64 consecutive x of a row per population
-// plane.  Eight waves per SIMD for the FP32 and 16-bit formats (at most 64
-// registers), four for FP64.  A solid node stores zero deviations (every slot is written each
+// plane.  D3Q19: eight waves per SIMD for the FP32 and 16-bit formats (at
+// most 64 registers), four for FP64; D3Q27: at least four, and two for
+// FP64 (no spills).  A solid node stores zero deviations (every slot is written each
 // step and never pulled).  Addressing: each direction pair (i odd, i + 1)
 // loads at the pair's first population plane (a wave-uniform offset) plus a
 // per-lane byte offset, and stores at its own plane plus the node's offset;
-// with WIDE false (19 population planes below 2^32 bytes) these are raw
+// with WIDE false (Q population planes below 2^32 bytes) these are raw
 // buffer accesses, and a pulled population costs one vector add for its
 // address.  A bounced link reads the opposite population of the node itself,
 // from the same pair base.  SOLIDS false: no node words (no walls or
 // obstacles).
-template <int ST, bool SOLIDS, bool WIDE>
-__global__ __launch_bounds__(256, ST == 0 ? 4 : 8) void k_sweep3(const Dom3 *__restrict__ Dp, int kstep) {
+template <int ST, bool SOLIDS, bool WIDE, int Q>
+__global__ __launch_bounds__(256, ST == 0 ? (Q == 27 ? 2 : 4) : (Q == 27 ? 4 : 8)) void k_sweep3(const Dom3 *__restrict__ Dp, int kstep) {
   using S = S3<ST>;
   using T = typename S::T;
   using R = typename S::R;
@@ -376,8 +419,8 @@ __global__ __launch_bounds__(256, ST == 0 ? 4 : 8) void k_sweep3(const Dom3 *__r
   const LBK_GLOBAL char *src = lbk::gbl((const char *)(odd ? D.f[1] : D.f[0]));
   LBK_GLOBAL char *dst = lbk::gbl((char *)(odd ? D.f[0] : D.f[1]));
   const Off rowb = (Off)pitch * E, zb = (Off)ny * rowb, popb = (Off)nz * zb;
-  const Res3 rs = res3((const void *)src, (uint32_t)(19 * popb));
-  const Res3 rd = res3((const void *)dst, (uint32_t)(19 * popb));
+  const Res3 rs = res3((const void *)src, (uint32_t)(Q * popb));
+  const Res3 rd = res3((const void *)dst, (uint32_t)(Q * popb));
   // byte offsets of the source columns and planes x - e_i (rows below)
   const Off xo_m = (Off)(x > 0 ? x - 1 : nx - 1) * E, xo_0 = (Off)x * E,
             xo_p = (Off)(x + 1 < nx ? x + 1 : 0) * E;
@@ -386,16 +429,16 @@ __global__ __launch_bounds__(256, ST == 0 ? 4 : 8) void k_sweep3(const Dom3 *__r
   // 16-bit formats: the stored scaling throughout (collide3_scaled)
   auto in = [](T v, int i) -> R {
     if constexpr (sizeof(T) == 2) return S::raw(v);
-    else return S::dec(v, i);
+    else return S::dec(v, Q, i);
   };
   const Off node = ((Off)z * (Off)ny + (Off)y) * (Off)pitch + (Off)x;
   const Off here = node * E;
   uint32_t w = 0u;
   if constexpr (SOLIDS) w = lbk::gbl(D.nodew)[node];
-  R d[19];
+  R d[Q];
   if (SOLIDS && (w & NODE_SOLID3)) {
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = R(0);
+    for (int i = 0; i < Q; ++i) d[i] = R(0);
   } else {
     const Off yo_m = (Off)(y > 0 ? y - 1 : ny - 1) * rowb, yo_0 = (Off)y * rowb,
               yo_p = (Off)(y + 1 < ny ? y + 1 : 0) * rowb;
@@ -404,7 +447,7 @@ __global__ __launch_bounds__(256, ST == 0 ? 4 : 8) void k_sweep3(const Dom3 *__r
     else
       d[0] = in(ld3<T>(rs, here, 0u), 0);
 #pragma unroll
-    for (int i = 1; i < 19; ++i) {
+    for (int i = 1; i < Q; ++i) {
       const int lo = (i - 1) | 1;  // the pair's first direction: i odd, or i - 1
       const Off zo = ez(i) > 0 ? zo_m : (ez(i) < 0 ? zo_p : zo_0);
       const Off yo = ey(i) > 0 ? yo_m : (ey(i) < 0 ? yo_p : yo_0);
@@ -420,16 +463,16 @@ __global__ __launch_bounds__(256, ST == 0 ? 4 : 8) void k_sweep3(const Dom3 *__r
       else
         d[i] = in(ld3<T>(rs, off, __builtin_amdgcn_readfirstlane((uint32_t)lo * popb)), i);
     }
-    if constexpr (sizeof(T) == 2) collide3_scaled(D, d);
-    else collide3<R>(D, d);
+    if constexpr (sizeof(T) == 2) collide3_scaled<Q>(D, d);
+    else collide3<R, Q>(D, d);
     if (!(fabs((double)d[0]) < 1e30)) atomicOr(D.health, 1u);
   }
   const uint32_t h = sizeof(T) == 2 && D.sr ? round_bits3(D, (uint32_t)node, (uint32_t)T0) : 0u;
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     T v;
     if constexpr (sizeof(T) == 2) v = S::enc_raw(d[i], D.sr, lbk::sr_bits(h, i));
-    else v = S::enc(d[i], i, false, 0u);
+    else v = S::enc(d[i], Q, i, false, 0u);
     if constexpr (WIDE)
       *(LBK_GLOBAL T *)(dst + (Off)i * popb + here) = v;
     else
@@ -438,6 +481,7 @@ __global__ __launch_bounds__(256, ST == 0 ? 4 : 8) void k_sweep3(const Dom3 *__r
 }
 
 // Node words from the solid mask ([nz][ny][pitch] bytes, 1 = solid).
+template <int Q>
 __global__ __launch_bounds__(256) void k_words3(const Dom3 *__restrict__ Dp, const uint8_t *mask) {
   const Dom3 &D = *Dp;
   const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -455,7 +499,7 @@ __global__ __launch_bounds__(256) void k_words3(const Dom3 *__restrict__ Dp, con
     w = NODE_SOLID3;
   } else {
 #pragma unroll
-    for (int i = 1; i < 19; ++i)
+    for (int i = 1; i < Q; ++i)
       if (at(x - ex(i), y - ey(i), z - ez(i))) w |= 1u << (i - 1);
   }
   D.nodew[((size_t)z * D.ny + y) * D.pitch + x] = w;
@@ -464,7 +508,7 @@ __global__ __launch_bounds__(256) void k_words3(const Dom3 *__restrict__ Dp, con
 // Equilibrium of the given fields (or rest) as the initial post-collision
 // state, after one collision (as the D2Q9 domains start).  Nodes n0 .. n0 +
 // cnt - 1; the fields (or null: rest) hold those nodes, [cnt] each.
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(256) void k_init3(const Dom3 *__restrict__ Dp, const double *rho_f,
                                                const double *ux_f, const double *uy_f,
                                                const double *uz_f, long long n0, long long cnt) {
@@ -480,28 +524,28 @@ __global__ __launch_bounds__(256) void k_init3(const Dom3 *__restrict__ Dp, cons
   const size_t here = ((size_t)z * D.ny + y) * D.pitch + x;
   T *dst = (T *)D.f[*D.tstep & 1];
   const bool solid = D.nodew && (D.nodew[here] & NODE_SOLID3);
-  R d[19];
+  R d[Q];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) d[i] = R(0);
+  for (int i = 0; i < Q; ++i) d[i] = R(0);
   if (rho_f && !solid) {
     const double r = rho_f[k], vx = ux_f[k], vy = uy_f[k], vz = uz_f[k];
     const double uu = vx * vx + vy * vy + vz * vz;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      const double w = i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+    for (int i = 0; i < Q; ++i) {
+      const double w = w3<double>(Q, i);
       const double eu = ex(i) * vx + ey(i) * vy + ez(i) * vz;
       d[i] = (R)(w * ((r - D.rho0) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)));
     }
   }
-  if (!solid) collide3<R>(D, d);
+  if (!solid) collide3<R, Q>(D, d);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) dst[(size_t)i * plane + here] = S::enc(d[i], i, false, 0u);
+  for (int i = 0; i < Q; ++i) dst[(size_t)i * plane + here] = S::enc(d[i], Q, i, false, 0u);
 }
 
 // rho and u = j/rho + g/2 of the pre-collision state, recovered from f*:
 // collision keeps rho and adds rho g to j.
 // Nodes n0 .. n0 + cnt - 1 (x fastest) into out [4][cnt].
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(256) void k_moments3(const Dom3 *__restrict__ Dp, double *out,
                                                   long long n0, long long cnt) {
   using S = S3<ST>;
@@ -520,8 +564,8 @@ __global__ __launch_bounds__(256) void k_moments3(const Dom3 *__restrict__ Dp, d
   const T *src = (const T *)D.f[*D.tstep & 1];
   double dr = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    const double v = (double)S::dec(src[(size_t)i * plane + here], i);
+  for (int i = 0; i < Q; ++i) {
+    const double v = (double)S::dec(src[(size_t)i * plane + here], Q, i);
     dr += v;
     jx += ex(i) * v;
     jy += ey(i) * v;
@@ -534,8 +578,8 @@ __global__ __launch_bounds__(256) void k_moments3(const Dom3 *__restrict__ Dp, d
   out[3 * total + k] = jz / rho - 0.5 * D.gz;
 }
 
-// Populations of nodes n0 .. n0 + cnt - 1 as FP64 deviations, out [19][cnt].
-template <int ST>
+// Populations of nodes n0 .. n0 + cnt - 1 as FP64 deviations, out [Q][cnt].
+template <int ST, int Q>
 __global__ __launch_bounds__(256) void k_export3(const Dom3 *__restrict__ Dp, double *out,
                                                  long long n0, long long cnt) {
   using S = S3<ST>;
@@ -549,12 +593,13 @@ __global__ __launch_bounds__(256) void k_export3(const Dom3 *__restrict__ Dp, do
   const size_t here = ((size_t)z * D.ny + y) * D.pitch + x;
   const T *src = (const T *)D.f[*D.tstep & 1];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) out[(size_t)i * cnt + k] = (double)S::dec(src[(size_t)i * plane + here], i);
+  for (int i = 0; i < Q; ++i)
+    out[(size_t)i * cnt + k] = (double)S::dec(src[(size_t)i * plane + here], Q, i);
 }
 
 // FP64 density sum: block z sums plane z in a fixed order; one wave adds the
 // planes.  Latches a non-finite total.
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(256) void k_mass3_partial(const Dom3 *__restrict__ Dp) {
   using S = S3<ST>;
   using T = typename S::T;
@@ -570,7 +615,7 @@ __global__ __launch_bounds__(256) void k_mass3_partial(const Dom3 *__restrict__ 
       if (D.nodew && (D.nodew[here] & NODE_SOLID3)) continue;
       double r = 0.0;
 #pragma unroll
-      for (int i = 0; i < 19; ++i) r += (double)S::dec(src[(size_t)i * plane + here], i);
+      for (int i = 0; i < Q; ++i) r += (double)S::dec(src[(size_t)i * plane + here], Q, i);
       acc += D.rho0 + r;
     }
 #pragma unroll

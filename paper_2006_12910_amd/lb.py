@@ -20,7 +20,8 @@ F64, F32, F16_DELTA, BF16_DELTA = 0, 1, 2, 3
 ROUND_NEAREST, ROUND_STOCHASTIC = 0, 1
 COMPUTE_NATIVE, COMPUTE_F64 = 0, 1
 INIT_REST, INIT_FIELDS = 0, 1
-LB3_BGK, LB3_TRT = 0, 1  # D3Q19 collisions
+LB3_BGK, LB3_TRT = 0, 1  # 3D collisions
+LB3_D3Q19, LB3_D3Q27 = 0, 1
 LB3_OPT_WIDE_OFFSETS = 1
 PARTICLE_FIXED = 1
 OPT_USE_GRAPH, OPT_TILE_WIDTH, OPT_ROWS_PER_THREAD, OPT_GRAPH_CHUNK, OPT_FORCE_AVERAGE = 1, 2, 3, 4, 5
@@ -76,7 +77,7 @@ class Domain3Desc(C.Structure):
         ("init_rho", C.POINTER(C.c_double)), ("init_ux", C.POINTER(C.c_double)),
         ("init_uy", C.POINTER(C.c_double)), ("init_uz", C.POINTER(C.c_double)),
         ("collision", C.c_int32), ("magic", C.c_double),
-        ("rounding", C.c_int32), ("seed", C.c_uint64),
+        ("rounding", C.c_int32), ("seed", C.c_uint64), ("lattice", C.c_int32),
     ]
 
 
@@ -450,20 +451,23 @@ def noise_normals(seed, domain_id, step, node0, count, fp32_arithmetic=False, de
 
 
 class Domain3:
-    """One D3Q19 domain on the GPU (lb3_create_domain ... lb3_destroy_domain).
-    Node arrays are [nz][ny][nx]; populations [19][nz][ny][nx]."""
+    """One D3Q19 or D3Q27 domain on the GPU (lb3_create_domain ...
+    lb3_destroy_domain).  Node arrays are [nz][ny][nx]; populations
+    [q][nz][ny][nx]."""
 
     def __init__(self, nx, ny, nz, *, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0),
                  walls=(False, False, False), storage="f32", obstacles=None, init=None,
-                 collision="bgk", magic=3.0 / 16.0, rounding=None, seed=0, device="cuda",
-                 stream=None):
+                 collision="bgk", magic=3.0 / 16.0, rounding=None, seed=0, lattice="d3q19",
+                 device="cuda", stream=None):
         """collision "trt": two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic.
         storage "f64" | "f32" | "f16" | "bf16"; rounding "nearest" | "stochastic"
-        (16-bit storage only; its default there)."""
+        (16-bit storage only; its default there); lattice "d3q19" | "d3q27"."""
         lib = library()
         d = Domain3Desc()
         d.abi_version = ABI_VERSION
         d.collision = {"bgk": LB3_BGK, "trt": LB3_TRT}[collision]
+        d.lattice = {"d3q19": LB3_D3Q19, "d3q27": LB3_D3Q27}[lattice]
+        self.q = 27 if lattice == "d3q27" else 19
         d.magic = float(magic)
         d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
         d.wall_x, d.wall_y, d.wall_z = (int(bool(w)) for w in walls)
@@ -518,7 +522,7 @@ class Domain3:
         return tuple(out)
 
     def populations(self):
-        f = np.empty((19, self.nz, self.ny, self.nx))
+        f = np.empty((self.q, self.nz, self.ny, self.nx))
         _check(library().lb3_get_populations(self._h, _dptr(f)), "lb3_get_populations")
         return f
 

@@ -113,6 +113,7 @@ def _desc3(**kw):
     (dict(tau=0.5), "tau"), (dict(nz=2), "nz"), (dict(abi_version=3), "abi"),
     (dict(storage=4), "storage"), (dict(init_kind=1), "INIT_FIELDS"), (dict(rho0=0.0), "rho0"),
     (dict(rounding=2), "rounding"), (dict(rounding=1), "stochastic rounding needs"),
+    (dict(lattice=2), "lattice"),
     (dict(collision=2), "collision"), (dict(collision=1, magic=0.0), "magic"),
 ])
 def test_d3q19_validation_errors(bad, msg):
@@ -127,10 +128,11 @@ def test_d3q19_workspace_covers_both_population_buffers():
     from paper_2006_12910_amd import lb
     lib = lb.library()
     for storage, size in ((0, 8), (1, 4), (2, 2), (3, 2)):
-        n = C.c_size_t()
-        assert lib.lb3_workspace_bytes(C.byref(_desc3(storage=storage, nx=100, ny=30, nz=20)),
-                                       C.byref(n)) == 0
-        assert n.value >= 2 * 19 * 128 * 30 * 20 * size
+        for lattice, q in ((0, 19), (1, 27)):
+            n = C.c_size_t()
+            desc = _desc3(storage=storage, nx=100, ny=30, nz=20, lattice=lattice)
+            assert lib.lb3_workspace_bytes(C.byref(desc), C.byref(n)) == 0
+            assert n.value >= 2 * q * 128 * 30 * 20 * size
     assert lib.lb3_step(None, 1) == lb.LB_EINVAL
     assert lib.lb3_set_option(None, lb.LB3_OPT_WIDE_OFFSETS, 1) == lb.LB_EINVAL
     assert lib.lb3_destroy_domain(None) == lb.LB_EINVAL
