@@ -339,6 +339,7 @@ lbo_sim *lbo_create(const lbo_params *p, const uint8_t *mask, const double *rho,
                     const double *ux, const double *uy) {
   if (p->nx < 3 || p->ny < 3 || !(p->tau > 0.5)) return NULL;
   if (p->bc_y == LBO_PRESSURE) return NULL;
+  if (p->trt && (!(p->magic > 0.0) || p->kT > 0.0)) return NULL;
   lbo_sim *s = (lbo_sim *)calloc(1, sizeof(lbo_sim));
   s->p = *p;
   s->nx = p->nx;
@@ -439,6 +440,21 @@ static void collide(lbo_sim *s) {
         jy += fl[i] * EY[i];
       }
       double tau = p->power_law ? powerlaw_tau(p, fl, rho, jx, jy) : p->tau;
+      if (p->trt) {
+        /* two relaxation times: the antisymmetric parts, which carry the
+         * momentum, relax with 1/tau_m, so the body force shifts u_eq by
+         * tau_m g (the momentum input per step stays rho g) */
+        const double tm = 0.5 + p->magic / (tau - 0.5);
+        const double vx = jx / rho + tm * p->gx, vy = jy / rho + tm * p->gy;
+        for (int i = 0; i < 9; ++i) {
+          const int o = OPP[i];
+          const double fsym = 0.5 * (fl[i] + fl[o]), fanti = 0.5 * (fl[i] - fl[o]);
+          const double ei = feq(i, rho, vx, vy), eo = feq(o, rho, vx, vy);
+          const double esym = 0.5 * (ei + eo), eanti = 0.5 * (ei - eo);
+          s->fs[IDX(s, i, x, y)] = fl[i] - (fsym - esym) / tau - (fanti - eanti) / tm;
+        }
+        continue;
+      }
       double ux = jx / rho + tau * p->gx, uy = jy / rho + tau * p->gy;
       double zeta[9] = {0};
       if (p->kT > 0.0) {

@@ -54,7 +54,11 @@ typedef struct lbo_params {
   double lj_psi, lj_rit, lj_floor; /* repulsion stiffness, threshold, gap floor      */
   int32_t force_average;        /* 0: Eqs. MP5-MP6 with F_T(t) (the paper);
                                    1: with (F_T(t) + F_T(t-1)) / 2, F_T(-1) = 0     */
-  int32_t pad_;
+  int32_t trt;                  /* nonzero: two-relaxation-time collision (the parts
+                                   of a population pair symmetric / antisymmetric
+                                   under e -> -e relax with 1/tau and 1/tau_minus,
+                                   (tau - 1/2)(tau_minus - 1/2) = magic); no noise */
+  double magic;
 } lbo_params;
 
 enum { LBO_PARTICLE_FIXED = 1 };   /* position and velocities prescribed */

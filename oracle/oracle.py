@@ -26,7 +26,7 @@ class _Params(C.Structure):
         ("power_law", C.c_int32), ("n_index", C.c_double), ("K", C.c_double),
         ("tau_min", C.c_double), ("tau_max", C.c_double),
         ("lj_psi", C.c_double), ("lj_rit", C.c_double), ("lj_floor", C.c_double),
-        ("force_average", C.c_int32), ("pad_", C.c_int32),
+        ("force_average", C.c_int32), ("trt", C.c_int32), ("magic", C.c_double),
     ]
 
 
@@ -132,6 +132,8 @@ class OracleParams:
     lj_rit: float = 2.5
     lj_floor: float = 0.1
     force_average: bool = False  # mean of this and the previous step's force in Eq. MP5
+    trt: bool = False  # two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic (no noise)
+    magic: float = 3.0 / 16.0
     extra: dict = field(default_factory=dict)
 
 
@@ -146,7 +148,7 @@ class Oracle:
                     prm.rho0, prm.gx, prm.gy, prm.kT, prm.seed & (2**64 - 1),
                     prm.domain_id & 0xFFFFFFFF, int(prm.power_law), prm.n_index, prm.K,
                     prm.tau_min, prm.tau_max, prm.lj_psi, prm.lj_rit, prm.lj_floor,
-                    int(prm.force_average), 0)
+                    int(prm.force_average), int(prm.trt), prm.magic)
         shape = (prm.ny, prm.nx)
         mask = None
         if obstacles is not None:
