@@ -372,7 +372,7 @@ def copy_bandwidth(mib=2048, reps=10):
 
 def other_configs():
     """GPU MLUPS of the other four workloads, of the 8192^2 member alone and
-    of the D3Q19 lattice at their full sizes (timed with HIP events after a
+    of the D3Q19 and D3Q27 lattices at their full sizes (timed with HIP events after a
     warm-up call); the oracle's rates on the same lattices are part of the
     CPU baseline."""
     import torch
@@ -635,7 +635,7 @@ def paper_replicas():
 def cpu_baseline_other_workloads():
     """CPU-baseline leg for the other workloads: the oracle's MLUPS (all
     host threads up to 16) on a few steps of each lattice that other_configs
-    and paper_replicas time on the GPU (D3Q19 on 64^3 instead of 256^3)."""
+    and paper_replicas time on the GPU (the 3D lattices on 64^3 instead of 256^3)."""
     from paper_2006_12910_amd import inputs
     from oracle import Oracle, OracleParams
     from oracle.oracle import PRESSURE, WALL, Oracle3

@@ -116,7 +116,20 @@ typedef struct lb_domain_desc {
   const double *init_rho;     /* LB_INIT_FIELDS: host [ny][nx] fields, copied    */
   const double *init_ux;
   const double *init_uy;
+  int32_t collision;          /* LB_BGK (the paper's, Sec. 2) | LB_TRT           */
+  double magic;               /* LB_TRT: (tau - 1/2)(tau_minus - 1/2), > 0       */
 } lb_domain_desc;
+
+/* Collision.  LB_TRT (an addition to the paper's BGK): the parts of each
+ * population pair symmetric and antisymmetric under e -> -e relax with 1/tau
+ * and 1/tau_minus, (tau - 1/2)(tau_minus - 1/2) = magic, and the body force
+ * shifts the equilibrium velocity by tau_minus g (the antisymmetric parts
+ * carry the momentum, so the input per step stays rho g); with the power law
+ * tau_minus follows the local tau*.  magic = 3/16 puts the halfway
+ * bounce-back walls of a channel exactly halfway whatever tau; magic =
+ * (tau - 1/2)^2 is BGK.  Not with thermal noise (LB_EUNSUPPORTED). */
+#define LB_BGK 0
+#define LB_TRT 1
 
 #define LB_PARTICLE_FIXED 1   /* position and velocities are held fixed          */
 

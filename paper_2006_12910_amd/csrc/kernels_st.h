@@ -110,13 +110,15 @@ template <int BASE, int WIDE> bool pick_power(int feat, int plm, KernelSet *k) {
 }
 
 template <int WIDE> bool pick(int feat, int plm, KernelSet *k) {
-  switch (feat & (F_LABELS | F_NOISE)) {
+  switch (feat & (F_LABELS | F_NOISE | F_TRT)) {
     case 0: return pick_power<0, WIDE>(feat, plm, k);
     case F_LABELS: return pick_power<F_LABELS, WIDE>(feat, plm, k);
     case F_NOISE: return pick_power<F_NOISE, WIDE>(feat, plm, k);
     case F_LABELS | F_NOISE: return pick_power<F_LABELS | F_NOISE, WIDE>(feat, plm, k);
+    case F_TRT: return pick_power<F_TRT, WIDE>(feat, plm, k);
+    case F_LABELS | F_TRT: return pick_power<F_LABELS | F_TRT, WIDE>(feat, plm, k);
   }
-  return false;
+  return false;  // TRT with noise is refused at validation
 }
 
 }  // namespace

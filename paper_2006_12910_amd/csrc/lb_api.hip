@@ -135,6 +135,13 @@ lb_status validate(const lb_domain_desc *d) {
       return fail(LB_EINVAL, "power law needs n > 0, K > 0, 1/2 < tau_min <= tau_max");
   }
   if (!(d->kT >= 0.0)) return fail(LB_EINVAL, "kT must be >= 0");
+  if (d->collision != LB_BGK && d->collision != LB_TRT)
+    return fail(LB_EINVAL, "collision must be LB_BGK or LB_TRT");
+  if (d->collision == LB_TRT && !(d->magic > 0.0 && std::isfinite(d->magic)))
+    return fail(LB_EINVAL, "TRT magic number must be finite and > 0");
+  if (d->collision == LB_TRT && d->kT > 0.0)
+    return fail(LB_EUNSUPPORTED,
+                "TRT with thermal noise: the noise amplitudes follow the BGK relaxation of each mode");
   if (!std::isfinite(d->gx) || !std::isfinite(d->gy)) return fail(LB_EINVAL, "g not finite");
   if (d->bc_x == LB_PRESSURE && (!(d->rho_in > 0.0) || !(d->rho_out > 0.0)))
     return fail(LB_EINVAL, "pressure faces need rho_in, rho_out > 0");
@@ -161,6 +168,7 @@ int feat_of(const lb_domain_desc *d) {
   if (d->power_law) f |= F_POWER;
   if (d->bc_x == LB_PRESSURE) f |= F_PRESSURE;
   if (d->rounding == LB_ROUND_STOCHASTIC) f |= F_STOCH;
+  if (d->collision == LB_TRT) f |= F_TRT;
   return f;
 }
 
@@ -662,6 +670,15 @@ static lb_status lb_create_domain_impl(const lb_domain_desc *desc, void *dev_wor
   h.pl_K_f = (float)h.pl_K;
   h.tau_min_f = (float)h.tau_min;
   h.tau_max_f = (float)h.tau_max;
+  // TRT: tau_m from the magic number (with the power law the device forms
+  // it from the local tau*); BGK: tau_m = tau
+  const bool trt = desc->collision == LB_TRT;
+  h.magic = trt ? desc->magic : 0.0;
+  h.tau_m = trt ? 0.5 + desc->magic / (h.tau - 0.5) : h.tau;
+  h.omega_m = 1.0 / h.tau_m;
+  h.magic_f = (float)h.magic;
+  h.tau_m_f = (float)h.tau_m;
+  h.omega_m_f = (float)h.omega_m;
   set_collision_coefficients(h);
 
   auto bail = [&](lb_status st) {

@@ -54,6 +54,7 @@ enum : int {
   F_PRESSURE = 8,  // Zou-He faces on x
   F_STOCH = 16,    // stochastic rounding of the stored values (FP32 or 16-bit)
   F_FAVG = 32,     // particle update with the mean of two steps' forces (runtime only)
+  F_TRT = 64,      // two-relaxation-time collision (never with F_NOISE)
 };
 // Power-law exponent specialisations.
 enum : int { PL_GENERIC = 0, PL_HALF = 1, PL_3Q = 2, PL_3H = 3 };
@@ -136,10 +137,14 @@ struct alignas(256) DevDomain {
   // and 9/2 times the even-part ones (the second-order term's factor);
   // set by set_collision_coefficients for a fixed relaxation time
   double cw1, cw5, cl1, cl5, cq1, cq5;
+  // two relaxation times: tau_m = 1/2 + magic / (tau - 1/2) and its rate
+  // (with the power law, from the local tau* on the device)
+  double tau_m, omega_m, magic;
   // FP32 copies
   float rho0_f, tau_f, omega_f, gx_f, gy_f, drho_in_f, drho_out_f, kT_f;
   float pl_n_f, pl_K_f, tau_min_f, tau_max_f;
   float cw1_f, cw5_f, cl1_f, cl5_f, cq1_f, cq5_f;
+  float tau_m_f, omega_m_f, magic_f;
 };
 
 // omega-scaled equilibrium coefficients of a domain with a fixed relaxation

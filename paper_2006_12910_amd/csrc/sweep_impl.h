@@ -153,7 +153,8 @@ __device__ __forceinline__ float sr_add_f32(float a, float b, uint32_t r) {
   return (e != 0.0f && fabsf(e) > u * fabsf(t)) ? __uint_as_float(un) : s;
 }
 
-// BGK collision of one node, step `step`, in arithmetic type R.  The values
+// BGK (or, with F_TRT, two-relaxation-time) collision of one node, step
+// `step`, in arithmetic type R.  The values
 // are the deviations d_i = f_i - w_i rho0 in the stored scaling: times K0, K1,
 // K5 for rest, axis and diagonal directions (powers of two: 2, 8, 32 for the
 // 16-bit formats, 1 otherwise).  Scaling by a power of two commutes with every
@@ -178,6 +179,7 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
   const R jy = fmar(i1, d[2] - d[4], i5 * ((d[5] + d[6]) - (d[7] + d[8])));
   const R rho = par<R>(D.rho0, D.rho0_f) + drho;
   const R irho = recip<ST, R>(rho);
+  constexpr bool TRT = (FEAT & F_TRT) != 0;
   R tau, om;
   if constexpr ((FEAT & F_POWER) != 0) {
     tau = powerlaw_tau<R, PLM, ST>(D, d, drho, rho, irho, jx, jy);
@@ -186,7 +188,19 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
     tau = par<R>(D.tau, D.tau_f);
     om = par<R>(D.omega, D.omega_f);
   }
-  const R rt = rho * tau;
+  // TRT: the antisymmetric parts relax with 1/tau_m and carry the momentum,
+  // so the force shifts u_eq by tau_m g (BGK: tau_m = tau)
+  R taum = tau, omm = om;
+  if constexpr (TRT) {
+    if constexpr ((FEAT & F_POWER) != 0) {
+      taum = R(0.5) + par<R>(D.magic, D.magic_f) / (tau - R(0.5));
+      omm = R(1) / taum;
+    } else {
+      taum = par<R>(D.tau_m, D.tau_m_f);
+      omm = par<R>(D.omega_m, D.omega_m_f);
+    }
+  }
+  const R rt = rho * taum;
   const R Jx = fmar(rt, par<R>(D.gx, D.gx_f), jx);
   const R Jy = fmar(rt, par<R>(D.gy, D.gy_f), jy);
   const R ux = Jx * irho, uy = Jy * irho;
@@ -199,7 +213,14 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
   // time is local), so the relaxation below is one fused multiply-add a
   // direction, d (1 - omega) + omega feq, instead of a subtraction and one
   R aw1, aw5, al1, al5, aq1, aq5;
-  if constexpr ((FEAT & F_POWER) != 0) {
+  if constexpr (TRT) {  // feq itself: the two rates act in the relaxation
+    aw1 = K1 * W1;
+    aw5 = K5 * W5;
+    al1 = K1 * L1;
+    al5 = K5 * L5;
+    aq1 = R(4.5) * aw1;
+    aq5 = R(4.5) * aw5;
+  } else if constexpr ((FEAT & F_POWER) != 0) {
     aw1 = om * (K1 * W1);
     aw5 = om * (K5 * W5);
     al1 = om * (K1 * L1);
@@ -224,8 +245,17 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
   const R cmm = fmar(a5 * sm, sm, b5);
   const R lx = al1 * Jx, ly = al1 * Jy;
   const R lp = al5 * (Jx + Jy), lm = al5 * (Jy - Jx);
-  R eq[9];  // omega feq_i
-  eq[0] = K0 * fmar(R(-2), fmar(i1, cxx + cyy, i5 * (cpp + cmm)), om * drho);
+  R eq[9];  // omega feq_i (BGK), feq_i (TRT)
+  eq[0] = K0 * fmar(R(-2), fmar(i1, cxx + cyy, i5 * (cpp + cmm)), TRT ? drho : om * drho);
+  // TRT relaxation of the pair (i, o = opposite): the symmetric part of
+  // feq - d with omega, the antisymmetric part with omega_m
+  auto trt_pair = [&](int i, int o, R &di, R &dout) {
+    const R a = eq[i] - d[i], b = eq[o] - d[o];
+    const R sym = R(0.5) * (a + b), anti = R(0.5) * (a - b);
+    const R t = omm * anti;
+    di = fmar(om, sym, t);
+    dout = fmar(om, sym, -t);
+  };
   eq[1] = cxx + lx;
   eq[3] = cxx - lx;
   eq[2] = cyy + ly;
@@ -282,8 +312,15 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
     // adds no bias beyond the storage rounding itself.  The rest population
     // takes the mass balance, so its equilibrium value is not needed.
     R inc[9];
+    if constexpr (TRT) {
+      trt_pair(1, 3, inc[1], inc[3]);
+      trt_pair(2, 4, inc[2], inc[4]);
+      trt_pair(5, 7, inc[5], inc[7]);
+      trt_pair(6, 8, inc[6], inc[8]);
+    } else {
 #pragma unroll
-    for (int i = 1; i < 9; ++i) inc[i] = fmar(-om, d[i], eq[i]);
+      for (int i = 1; i < 9; ++i) inc[i] = fmar(-om, d[i], eq[i]);
+    }
     if constexpr ((FEAT & F_NOISE) != 0)
       noise([&](int i, R c, R z) { if (i > 0) inc[i] = fmar(c, z, inc[i]); });
     const R sx = ((inc[1] - inc[3]) + (inc[5] - inc[6])) + (inc[8] - inc[7]);
@@ -309,6 +346,15 @@ __device__ __forceinline__ void collide_node(const DevDomain &D, R d[9], uint32_
 #pragma unroll
       for (int i = 0; i < 9; ++i) d[i] = d[i] + inc[i];
     }
+  } else if constexpr (TRT) {
+    R u[9];
+    u[0] = om * (eq[0] - d[0]);
+    trt_pair(1, 3, u[1], u[3]);
+    trt_pair(2, 4, u[2], u[4]);
+    trt_pair(5, 7, u[5], u[7]);
+    trt_pair(6, 8, u[6], u[8]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d[i] = d[i] + u[i];
   } else {
     const R keep = R(1) - om;
 #pragma unroll

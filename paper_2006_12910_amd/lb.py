@@ -20,6 +20,7 @@ F64, F32, F16_DELTA, BF16_DELTA = 0, 1, 2, 3
 ROUND_NEAREST, ROUND_STOCHASTIC = 0, 1
 COMPUTE_NATIVE, COMPUTE_F64 = 0, 1
 INIT_REST, INIT_FIELDS = 0, 1
+BGK, TRT = 0, 1  # collisions of the 2D domains
 LB3_BGK, LB3_TRT = 0, 1  # 3D collisions
 LB3_D3Q19, LB3_D3Q27 = 0, 1
 LB3_OPT_WIDE_OFFSETS = 1
@@ -64,6 +65,7 @@ class DomainDesc(C.Structure):
         ("lj_rit", C.c_double), ("lj_floor", C.c_double),
         ("init_rho", C.POINTER(C.c_double)), ("init_ux", C.POINTER(C.c_double)),
         ("init_uy", C.POINTER(C.c_double)),
+        ("collision", C.c_int32), ("magic", C.c_double),
     ]
 
 
@@ -194,9 +196,13 @@ class Domain:
                  bc_y="periodic", storage="f32", rounding="nearest", compute="native",
                  rho_in=1.0, rho_out=1.0,
                  kT=0.0, seed=0, domain_id=0, power_law=None, obstacles=None, max_particles=0,
-                 lj=(20.0, 2.5, 0.1), init=None, device="cuda", stream=None):
+                 lj=(20.0, 2.5, 0.1), init=None, collision="bgk", magic=3.0 / 16.0, device="cuda",
+                 stream=None):
+        """collision "trt": two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic."""
         lib = library()
         d = DomainDesc()
+        d.collision = {"bgk": BGK, "trt": TRT}[collision]
+        d.magic = float(magic)
         d.abi_version = ABI_VERSION
         d.nx, d.ny = int(nx), int(ny)
         d.bc_x, d.bc_y = _BC[bc_x], _BC[bc_y]

@@ -11,7 +11,8 @@ _BC = {"periodic": PERIODIC, "wall": WALL, "pressure": PRESSURE}
 def make_pair(nx, ny, storage="f64", bc_x="periodic", bc_y="periodic", tau=1.0, g=(0.0, 0.0),
               rho0=1.0, rho_in=1.0, rho_out=1.0, kT=0.0, seed=0, domain_id=0, power_law=None,
               obstacles=None, particles=(), init=None, lj=(20.0, 2.5, 0.1), max_particles=None,
-              rounding="nearest", compute="native", force_average=False):
+              rounding="nearest", compute="native", force_average=False, collision="bgk",
+              magic=3.0 / 16.0):
     """(gpu Domain, Oracle) with identical parameters and inputs."""
     from paper_2006_12910_amd import lb
     plist = list(particles)
@@ -19,7 +20,7 @@ def make_pair(nx, ny, storage="f64", bc_x="periodic", bc_y="periodic", tau=1.0, 
     gpu = lb.Domain(nx, ny, tau=tau, rho0=rho0, g=g, bc_x=bc_x, bc_y=bc_y, storage=storage,
                     rounding=rounding, compute=compute, rho_in=rho_in, rho_out=rho_out, kT=kT, seed=seed,
                     domain_id=domain_id, power_law=power_law, obstacles=obstacles,
-                    max_particles=nmax, lj=lj, init=init)
+                    max_particles=nmax, lj=lj, init=init, collision=collision, magic=magic)
     if force_average:
         gpu.set_option(lb.OPT_FORCE_AVERAGE, 1)
     pl = power_law or {}
@@ -28,7 +29,8 @@ def make_pair(nx, ny, storage="f64", bc_x="periodic", bc_y="periodic", tau=1.0, 
                        domain_id=domain_id, power_law=power_law is not None,
                        n_index=pl.get("n", 1.0), K=pl.get("K", 0.0),
                        tau_min=pl.get("tau_min", 0.51), tau_max=pl.get("tau_max", 2.5),
-                       lj_psi=lj[0], lj_rit=lj[1], lj_floor=lj[2], force_average=force_average)
+                       lj_psi=lj[0], lj_rit=lj[1], lj_floor=lj[2], force_average=force_average,
+                       trt=collision == "trt", magic=magic)
     fields = (None, None, None) if init is None else tuple(
         np.broadcast_to(np.asarray(a, np.float64), (ny, nx)) for a in init)
     ora = Oracle(prm, obstacles, *fields)

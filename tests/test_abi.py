@@ -59,6 +59,20 @@ def test_validation_errors(bad, msg):
     assert msg.lower() in lib.lb_last_error().decode().lower()
 
 
+def test_trt_validation():
+    """The 2D collision option: an unknown collision or a non-positive magic
+    number is LB_EINVAL; TRT with thermal noise is LB_EUNSUPPORTED."""
+    from paper_2006_12910_amd import lb
+    lib = lb.library()
+    n = C.c_size_t()
+    for kw, status, msg in ((dict(collision=2), lb.LB_EINVAL, "collision"),
+                            (dict(collision=1, magic=0.0), lb.LB_EINVAL, "magic"),
+                            (dict(collision=1, magic=0.25, kT=1e-5), lb.LB_EUNSUPPORTED, "noise")):
+        assert lib.lb_workspace_bytes(C.byref(_desc(**kw)), C.byref(n)) == status
+        assert msg in lib.lb_last_error().decode().lower()
+    assert lib.lb_workspace_bytes(C.byref(_desc(collision=1, magic=0.25)), C.byref(n)) == 0
+
+
 def test_largest_buffers_within_the_offset_limit_are_accepted():
     from paper_2006_12910_amd import lb
     lib = lb.library()
