@@ -72,7 +72,11 @@ static double feq(int i, double w, double rho, double ux, double uy, double uz) 
 
 lbo3_sim *lbo3_create(const lbo3_params *p, const uint8_t *mask, const double *rho,
                       const double *ux, const double *uy, const double *uz) {
-  if (p->nx < 3 || p->ny < 3 || p->nz < 3 || !(p->tau > 0.5)) return NULL;
+  if (p->nx < 3 || p->ny < 3 || p->nz < 3) return NULL;
+  if (!p->power_law && !(p->tau > 0.5)) return NULL;
+  if (p->power_law && (!(p->tau_min > 0.5) || !(p->tau_max >= p->tau_min) || !(p->n_index > 0.0) ||
+                       !(p->K > 0.0)))
+    return NULL;
   if (p->trt && !(p->magic > 0.0)) return NULL;
   if (p->q != 19 && p->q != 27) return NULL;
   lbo3_sim *s = (lbo3_sim *)calloc(1, sizeof(lbo3_sim));
@@ -112,14 +116,68 @@ static int wrap(int v, int n) { return ((v % n) + n) % n; }
 
 /* relaxation time of the antisymmetric parts: tau itself for BGK, else the
  * one that makes (tau - 1/2)(tau_minus - 1/2) = magic */
-static double tau_minus(const lbo3_params *p) {
-  return p->trt ? 0.5 + p->magic / (p->tau - 0.5) : p->tau;
+static double tau_minus(const lbo3_params *p, double tau) {
+  return p->trt ? 0.5 + p->magic / (tau - 0.5) : tau;
+}
+
+/* Power-law relaxation time (Sec. 5) on the 3D lattice, the 2D oracle's
+ * reading with the full stress tensor: Pi = sum e e (f - feq(rho, j/rho +
+ * g/2)), A = 3 |Pi|_F / (sqrt(2) rho) (|Pi|_F over all nine components),
+ * gamma_dot = A / tau, nu* = K gamma_dot^(n-1), tau* = 1/2 + 3 nu*: tau*
+ * is the root of h(tau) = tau - 1/2 - 3 K A^(n-1) tau^(1-n), found by
+ * Newton from the bracket end on the side where h keeps its curvature, then
+ * clamped to [tau_min, tau_max]. */
+static double powerlaw_tau3(const lbo3_sim *s, const double *fl, double rho, double jx, double jy,
+                            double jz) {
+  const lbo3_params *p = &s->p;
+  double n = p->n_index, xi = p->K;
+  if (n == 1.0) {
+    double t = 0.5 + 3.0 * xi;
+    return t < p->tau_min ? p->tau_min : (t > p->tau_max ? p->tau_max : t);
+  }
+  double ux = jx / rho + 0.5 * p->gx, uy = jy / rho + 0.5 * p->gy, uz = jz / rho + 0.5 * p->gz;
+  double pi[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int i = 0; i < s->q; ++i) {
+    double d = fl[i] - feq(i, s->w[i], rho, ux, uy, uz);
+    int e[3] = {EX[i], EY[i], EZ[i]};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) pi[a][b] += e[a] * e[b] * d;
+  }
+  double fro2 = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) fro2 += pi[a][b] * pi[a][b];
+  double A = 3.0 * sqrt(fro2) / (sqrt(2.0) * rho);
+  double tmin = p->tau_min, tmax = p->tau_max;
+  if (A == 0.0) return n < 1.0 ? tmax : tmin;
+  double c = 3.0 * xi * pow(A, n - 1.0);
+#define HFUN(tt) ((tt) - 0.5 - c * pow((tt), 1.0 - n))
+  double t;
+  if (n < 1.0) {
+    if (HFUN(tmax) <= 0.0) return tmax;
+    t = tmax;
+  } else {
+    if (HFUN(tmin) >= 0.0) return tmin;
+    t = tmin;
+  }
+  for (int it = 0; it < 200; ++it) {
+    double h = HFUN(t);
+    double dh = 1.0 - c * (1.0 - n) * pow(t, -n);
+    double tn = t - h / dh;
+    if (fabs(tn - t) <= 1e-14 * tn) {
+      t = tn;
+      break;
+    }
+    t = tn;
+  }
+#undef HFUN
+  if (t < tmin) t = tmin;
+  if (t > tmax) t = tmax;
+  return t;
 }
 
 /* collide every fluid node into fs */
 static void collide(lbo3_sim *s) {
   const lbo3_params *p = &s->p;
-  const double tm = tau_minus(p);
 #pragma omp parallel for schedule(static)
   for (int z = 0; z < p->nz; ++z)
     for (int y = 0; y < p->ny; ++y)
@@ -133,13 +191,15 @@ static void collide(lbo3_sim *s) {
           jy += fl[i] * EY[i];
           jz += fl[i] * EZ[i];
         }
+        const double tau = p->power_law ? powerlaw_tau3(s, fl, rho, jx, jy, jz) : p->tau;
+        const double tm = tau_minus(p, tau);
         double ux = jx / rho + tm * p->gx;
         double uy = jy / rho + tm * p->gy;
         double uz = jz / rho + tm * p->gz;
         if (!p->trt) {
           for (int i = 0; i < s->q; ++i)
             s->fs[IDX(s, i, x, y, z)] =
-                fl[i] - (fl[i] - feq(i, s->w[i], rho, ux, uy, uz)) / p->tau;
+                fl[i] - (fl[i] - feq(i, s->w[i], rho, ux, uy, uz)) / tau;
           continue;
         }
         for (int i = 0; i < s->q; ++i) {
@@ -147,7 +207,7 @@ static void collide(lbo3_sim *s) {
           const double fsym = 0.5 * (fl[i] + fl[o]), fanti = 0.5 * (fl[i] - fl[o]);
           const double ei = feq(i, s->w[i], rho, ux, uy, uz), eo = feq(o, s->w[o], rho, ux, uy, uz);
           const double esym = 0.5 * (ei + eo), eanti = 0.5 * (ei - eo);
-          s->fs[IDX(s, i, x, y, z)] = fl[i] - (fsym - esym) / p->tau - (fanti - eanti) / tm;
+          s->fs[IDX(s, i, x, y, z)] = fl[i] - (fsym - esym) / tau - (fanti - eanti) / tm;
         }
       }
 }

@@ -24,6 +24,11 @@ typedef struct {
   int32_t trt;
   double magic;
   int32_t q; /* 19 (D3Q19) or 27 (D3Q27) */
+  /* power_law nonzero: local tau* of the power-law fluid (Sec. 5) from the
+   * non-equilibrium stress, flow index n_index, consistency K, clamped to
+   * [tau_min, tau_max]; tau is then unused (TRT takes tau_minus from tau*) */
+  int32_t power_law;
+  double n_index, K, tau_min, tau_max;
 } lbo3_params;
 
 typedef struct lbo3_sim lbo3_sim;

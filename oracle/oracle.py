@@ -45,6 +45,8 @@ class _Params3(C.Structure):
         ("wall_x", C.c_int32), ("wall_y", C.c_int32), ("wall_z", C.c_int32),
         ("tau", C.c_double), ("rho0", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
         ("gz", C.c_double), ("trt", C.c_int32), ("magic", C.c_double), ("q", C.c_int32),
+        ("power_law", C.c_int32), ("n_index", C.c_double), ("K", C.c_double),
+        ("tau_min", C.c_double), ("tau_max", C.c_double),
     ]
 
 
@@ -272,14 +274,18 @@ class Oracle3:
     are [nz][ny][nx]; populations [q][nz][ny][nx]."""
 
     def __init__(self, nx, ny, nz, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0), walls=(False, False, False),
-                 obstacles=None, init=None, collision="bgk", magic=3.0 / 16.0, lattice="d3q19"):
+                 obstacles=None, init=None, collision="bgk", magic=3.0 / 16.0, lattice="d3q19",
+                 power_law=None):
         """collision "trt": two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic;
-        lattice "d3q19" or "d3q27"."""
+        lattice "d3q19" or "d3q27"; power_law: dict(n, K, tau_min=0.51, tau_max=2.5)."""
         lib = _load()
         self.nx, self.ny, self.nz = nx, ny, nz
         self.q = {"d3q19": 19, "d3q27": 27}[lattice]
+        pl = power_law or {}
         c = _Params3(nx, ny, nz, int(walls[0]), int(walls[1]), int(walls[2]), tau, rho0, *g,
-                     int(collision == "trt"), magic, self.q)
+                     int(collision == "trt"), magic, self.q, int(power_law is not None),
+                     pl.get("n", 1.0), pl.get("K", 0.0), pl.get("tau_min", 0.51),
+                     pl.get("tau_max", 2.5))
         shape = (nz, ny, nx)
         mask = None
         if obstacles is not None:

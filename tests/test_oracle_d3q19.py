@@ -7,9 +7,14 @@ of square-duct flow with second-order convergence, and flows uniform along
 y that equal the independent D2Q9 oracle's step for step (both lattices
 project onto D2Q9); for the two-relaxation-time variant, its reduction to
 BGK, its conservation and the walls exactly halfway at the magic number
-3/16."""
+3/16; for the power law of Sec. 5 on the 3D lattices, n = 1 equal to the
+Newtonian run, a flow uniform along y on D3Q27 equal to the D2Q9 oracle's
+power-law step (the tensor-product lattice leaves the y rows of the stress
+at equilibrium), and the clamped channel against its closed form."""
 import numpy as np
 import pytest
+
+import closed_forms as cf
 
 from oracle.oracle import PERIODIC, WALL, Oracle, Oracle3, OracleParams, lattice3
 
@@ -240,3 +245,59 @@ def test_trt_magic_3_16_puts_the_poiseuille_walls_exactly_halfway(lattice):
     nu = 1.3 / 3
     parabola = g / (2 * nu) * (z - 0.5) * (nz - 1.5 - z)
     assert np.abs(ux[1:-1] - parabola[:, None, None]).max() / parabola.max() > 1e-3
+
+
+# --- power law (Sec. 5) on the 3D lattices ---------------------------------
+
+@pytest.mark.parametrize("lattice", LATTICES)
+def test_power_law_with_n_1_is_the_newtonian_run(lattice):
+    rng = np.random.default_rng(31)
+    n = (9, 7, 6)
+    init = (1 + 0.01 * rng.standard_normal(n[::-1]), 0.02 * rng.standard_normal(n[::-1]), 0.0,
+            0.01 * rng.standard_normal(n[::-1]))
+    kw = dict(g=(1e-5, 0.0, -2e-6), walls=(False, True, False), init=init, lattice=lattice)
+    a = Oracle3(*n, tau=0.5 + 3 * 0.01, **kw)
+    b = Oracle3(*n, power_law=dict(n=1.0, K=0.01), **kw)
+    a.run(30)
+    b.run(30)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+@pytest.mark.parametrize("n", [0.5, 1.5])
+def test_d3q27_y_uniform_power_law_flow_equals_the_d2q9_oracle(n):
+    """D3Q27 summed over e_y is D2Q9 with its weights, and on a flow uniform
+    along y its non-equilibrium stress has no y components, so tau* and the
+    whole step equal the D2Q9 power-law step (D3Q19, not a tensor product,
+    develops a y y stress and differs at O(1e-4) for n = 1/2)."""
+    rng = np.random.default_rng(22)
+    nx, ny, nz = 23, 3, 17
+    rho2 = 1 + 0.01 * rng.standard_normal((nz, nx))
+    ux2, uz2 = 0.02 * rng.standard_normal((2, nz, nx))
+    ext = lambda a: np.repeat(a[:, None, :], ny, axis=1)
+    pl = dict(n=n, K=0.01, tau_min=0.51, tau_max=2.5)
+    o3 = Oracle3(nx, ny, nz, g=(3e-5, 0.0, -2e-5), walls=(False, False, True), lattice="d3q27",
+                 init=(ext(rho2), ext(ux2), 0.0, ext(uz2)), power_law=pl)
+    o2 = Oracle(OracleParams(nx=nx, ny=nz, bc_y=WALL, gx=3e-5, gy=-2e-5, power_law=True,
+                             n_index=n, K=0.01, tau_min=0.51, tau_max=2.5), None, rho2, ux2, uz2)
+    for k in (1, 9, 90):
+        o3.run(k)
+        o2.run(k)
+        r3, u3, v3, w3 = o3.moments()
+        r2, u2, w2 = o2.moments()
+        for a, b in ((r3, r2), (u3, u2), (w3, w2)):
+            for y in range(ny):
+                assert np.abs(a[:, y, :] - b).max() < 1e-13, (n, k)
+
+
+@pytest.mark.parametrize("lattice", LATTICES)
+def test_clamped_power_law_channel(lattice):
+    """Walls at z = 0 and nz - 1, force along x, n = 1/2, K = 0.01, tau* in
+    [0.51, 2.5]: the steady profile against the closed form with the clamp,
+    to the 2D oracle's bound."""
+    nz, g = 66, 1.66e-5
+    o = Oracle3(3, 3, nz, g=(g, 0.0, 0.0), walls=(False, False, True), lattice=lattice,
+                power_law=dict(n=0.5, K=0.01, tau_min=0.51, tau_max=2.5)).run(80000)
+    u = o.moments()[1][1:-1, 0, 0]
+    ref = cf.powerlaw_channel(nz, 0.5, 0.01, g, 0.51, 2.5)
+    err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    assert err < 2e-3, err
