@@ -411,9 +411,12 @@ lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms);
  * and the body force shifts the equilibrium velocity by tau_minus g (the
  * antisymmetric parts carry the momentum); magic = 3/16 puts halfway
  * bounce-back walls of a channel exactly halfway whatever tau,
- * magic = (tau - 1/2)^2 is BGK.  Same conventions as above: caller-owned
- * 256-byte aligned workspace, stream-ordered calls, errors through
- * lb_last_error.  No particles, noise or power law. */
+ * magic = (tau - 1/2)^2 is BGK.  Power law (Sec. 5): the local tau* from the
+ * non-equilibrium stress as on the 2D domains, with all nine components of
+ * the 3D stress in its Frobenius norm (with TRT, tau_minus follows tau*).
+ * Same conventions as above: caller-owned 256-byte aligned workspace,
+ * stream-ordered calls, errors through lb_last_error.  No particles or
+ * noise. */
 #define LB3_BGK 0
 #define LB3_TRT 1
 #define LB3_D3Q19 0
@@ -434,6 +437,9 @@ typedef struct lb3_domain_desc {
   int32_t rounding;            /* LB_ROUND_NEAREST | LB_ROUND_STOCHASTIC (16-bit) */
   uint64_t seed;               /* stochastic-rounding key                         */
   int32_t lattice;             /* LB3_D3Q19 | LB3_D3Q27                           */
+  int32_t power_law;           /* nonzero: local tau* (Sec. 5), tau unused        */
+  double n_index, K;           /* power-law index n and consistency xi            */
+  double tau_min, tau_max;     /* clamp of tau*, 1/2 < tau_min <= tau_max         */
 } lb3_domain_desc;
 typedef struct lb3_domain lb3_domain;
 

@@ -86,7 +86,11 @@ lb_status validate3(const lb3_domain_desc *d) {
   if (d->rounding == LB_ROUND_STOCHASTIC && d->storage != LB_F16_DELTA &&
       d->storage != LB_BF16_DELTA)
     return fail3(LB_EINVAL, "stochastic rounding needs LB_F16_DELTA or LB_BF16_DELTA storage");
-  if (!(d->tau > 0.5)) return fail3(LB_EINVAL, "tau must be > 1/2");
+  if (!d->power_law && !(d->tau > 0.5)) return fail3(LB_EINVAL, "tau must be > 1/2");
+  if (d->power_law && (!(d->tau_min > 0.5) || !(d->tau_max >= d->tau_min) || !(d->n_index > 0.0) ||
+                       !(d->K > 0.0) || !std::isfinite(d->n_index) || !std::isfinite(d->K) ||
+                       !std::isfinite(d->tau_max)))
+    return fail3(LB_EINVAL, "power law needs n > 0, K > 0, 1/2 < tau_min <= tau_max");
   if (d->collision != LB3_BGK && d->collision != LB3_TRT)
     return fail3(LB_EINVAL, "collision must be LB3_BGK or LB3_TRT");
   if (d->collision == LB3_TRT && !(d->magic > 0.0 && std::isfinite(d->magic)))
@@ -208,23 +212,29 @@ lb_status push_desc3(lb3_domain *d) {
 
 namespace {
 
-template <int ST, int Q> void launch_sweep3_q(const lb3_domain *d, unsigned blocks, int k) {
+template <int ST, int Q, bool PL> void launch_sweep3_q(const lb3_domain *d, unsigned blocks, int k) {
   const dim3 g(blocks), b(256);
   if (d->L.solids) {
     if (d->wide)
-      hipLaunchKernelGGL((k_sweep3<ST, true, true, Q>), g, b, 0, d->stream, d->ddesc(), k);
+      hipLaunchKernelGGL((k_sweep3<ST, true, true, Q, PL>), g, b, 0, d->stream, d->ddesc(), k);
     else
-      hipLaunchKernelGGL((k_sweep3<ST, true, false, Q>), g, b, 0, d->stream, d->ddesc(), k);
+      hipLaunchKernelGGL((k_sweep3<ST, true, false, Q, PL>), g, b, 0, d->stream, d->ddesc(), k);
   } else {
     if (d->wide)
-      hipLaunchKernelGGL((k_sweep3<ST, false, true, Q>), g, b, 0, d->stream, d->ddesc(), k);
+      hipLaunchKernelGGL((k_sweep3<ST, false, true, Q, PL>), g, b, 0, d->stream, d->ddesc(), k);
     else
-      hipLaunchKernelGGL((k_sweep3<ST, false, false, Q>), g, b, 0, d->stream, d->ddesc(), k);
+      hipLaunchKernelGGL((k_sweep3<ST, false, false, Q, PL>), g, b, 0, d->stream, d->ddesc(), k);
   }
 }
 template <int ST> void launch_sweep3_st(const lb3_domain *d, unsigned blocks, int k) {
-  if (d->q == 27) launch_sweep3_q<ST, 27>(d, blocks, k);
-  else launch_sweep3_q<ST, 19>(d, blocks, k);
+  const bool pl = d->desc.power_law != 0;
+  if (d->q == 27) {
+    if (pl) launch_sweep3_q<ST, 27, true>(d, blocks, k);
+    else launch_sweep3_q<ST, 27, false>(d, blocks, k);
+  } else {
+    if (pl) launch_sweep3_q<ST, 19, true>(d, blocks, k);
+    else launch_sweep3_q<ST, 19, false>(d, blocks, k);
+  }
 }
 
 void launch_sweep3(const lb3_domain *d, unsigned blocks, int k) {
@@ -292,10 +302,23 @@ static lb_status lb3_create_domain_impl(const lb3_domain_desc *desc, void *dev_w
   h.tiles_x = (desc->nx + 63) / 64;
   h.tiles_y = (desc->ny + 3) / 4;
   h.rho0 = desc->rho0;
-  h.tau = desc->tau;
-  h.omega = 1.0 / desc->tau;
+  // with the power law tau is the local tau*; the domain-wide values below
+  // are those of tau_min (unused by the sweep)
+  h.tau = desc->power_law ? desc->tau_min : desc->tau;
+  h.pl = desc->power_law ? 1 : 0;
+  h.pl_n = desc->n_index;
+  h.pl_K = desc->K;
+  h.tau_min = desc->tau_min;
+  h.tau_max = desc->tau_max;
+  h.magic = desc->magic;
+  h.pl_n_f = (float)h.pl_n;
+  h.pl_K_f = (float)h.pl_K;
+  h.tau_min_f = (float)h.tau_min;
+  h.tau_max_f = (float)h.tau_max;
+  h.magic_f = (float)h.magic;
+  h.omega = 1.0 / h.tau;
   h.trt = desc->collision == LB3_TRT ? 1 : 0;
-  h.tau_m = h.trt ? 0.5 + desc->magic / (desc->tau - 0.5) : desc->tau;
+  h.tau_m = h.trt ? 0.5 + desc->magic / (h.tau - 0.5) : h.tau;
   h.omega_m = 1.0 / h.tau_m;
   h.tau_m_f = (float)h.tau_m;
   h.omega_m_f = (float)h.omega_m;

@@ -84,6 +84,11 @@ struct Dom3 {
   // directions (K w = 8/9 for all of them), times omega for BGK; the rest
   // population's relaxation factor (omega for BGK, 1 for TRT) and 1 - omega
   float s_cw, s_cq, s_cl, s_om0, keep_f;
+  // power law (Sec. 5): flow index, consistency, clamp of tau*, and the TRT
+  // magic number (tau_minus then follows the local tau*)
+  int pl;  // power-law local tau*
+  double pl_n, pl_K, tau_min, tau_max, magic;
+  float pl_n_f, pl_K_f, tau_min_f, tau_max_f, magic_f;
 };
 
 template <class R> __device__ __forceinline__ R par3(double a, float b);
@@ -91,6 +96,84 @@ template <> __device__ __forceinline__ double par3<double>(double a, float) { re
 template <> __device__ __forceinline__ float par3<float>(double, float b) { return b; }
 __device__ __forceinline__ float fmr(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmr(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Local relaxation time of the power-law fluid (Sec. 5) from
+// A = 3 |Pi_neq|_F / (sqrt(2) rho) (all nine stress components): the shear
+// rate is A / tau*, nu* = K gamma_dot^(n-1) and tau* = 1/2 + 3 nu*, so tau*
+// is the root of h(t) = t - 1/2 - c t^(1-n), c = 3 K A^(n-1), clamped to
+// [tau_min, tau_max].  n = 1: 1/2 + 3 K; n = 1/2: t = s^2 with
+// s = (c + sqrt(c^2 + 2)) / 2; otherwise Newton from the bracket end on the
+// side where it converges monotonically (tau_max for n < 1, tau_min above).
+template <class R> __device__ __forceinline__ R powr3(R a, R b) {
+  if constexpr (sizeof(R) == 8) return pow(a, b);
+  else return exp2f(b * log2f(a));
+}
+template <class R> __device__ R tau_power3(const Dom3 &D, R A) {
+  const R n = par3<R>(D.pl_n, D.pl_n_f), xi = par3<R>(D.pl_K, D.pl_K_f);
+  const R tmin = par3<R>(D.tau_min, D.tau_min_f), tmax = par3<R>(D.tau_max, D.tau_max_f);
+  if (n == R(1)) {
+    const R t = R(0.5) + R(3) * xi;
+    return t < tmin ? tmin : (t > tmax ? tmax : t);
+  }
+  const bool thinning = n < R(1);
+  if (!(A > R(0))) return thinning ? tmax : tmin;
+  R t;
+  if (n == R(0.5)) {
+    const R c = R(3) * xi / sqrt(A);
+    const R sr = R(0.5) * (c + sqrt(c * c + R(2)));
+    t = sr * sr;
+  } else {
+    const R c = R(3) * xi * powr3<R>(A, n - R(1));
+    const R t0 = thinning ? tmax : tmin;
+    const R h0 = t0 - R(0.5) - c * powr3<R>(t0, R(1) - n);
+    if (thinning ? !(h0 > R(0)) : !(h0 < R(0))) return t0;
+    constexpr int ITERS = sizeof(R) == 8 ? 40 : 12;
+    const R tol = sizeof(R) == 8 ? R(1e-15) : R(1e-7);
+    t = t0;
+#pragma unroll 1
+    for (int it = 0; it < ITERS; ++it) {
+      const R tp = powr3<R>(t, R(1) - n);
+      const R h = t - R(0.5) - c * tp;
+      const R dh = R(1) - c * (R(1) - n) * tp / t;
+      const R tn = t - h / dh;
+      const bool done = fabs(tn - t) <= tol * tn;
+      t = tn;
+      if (done) break;
+    }
+  }
+  return t < tmin ? tmin : (t > tmax ? tmax : t);
+}
+
+// A = 3 |Pi_neq|_F / (sqrt(2) rho) of a node from the pair sums ps_k of its
+// deviations (the second moments are even under e -> -e), each class scaled
+// back by inv[class]: Pi_neq = sum e e d - drho/3 I - rho u u with
+// u = j / rho + g / 2 (the second moment of the equilibrium is rho/3 I +
+// rho u u on both lattices).
+template <class R, int Q>
+__device__ __forceinline__ R shear_measure3(const Dom3 &D, const R *ps, const R (&inv)[4], R drho,
+                                            R rho, R irho, R jx, R jy, R jz) {
+  R sxx = R(0), syy = R(0), szz = R(0), sxy = R(0), sxz = R(0), syz = R(0);
+#pragma unroll
+  for (int k = 1; k <= (Q - 1) / 2; ++k) {
+    const int i = 2 * k - 1;
+    const R v = inv[cls3(i)] * ps[k];
+    if (ex(i)) sxx += v;
+    if (ey(i)) syy += v;
+    if (ez(i)) szz += v;
+    if (ex(i) && ey(i)) sxy += R(ex(i) * ey(i)) * v;
+    if (ex(i) && ez(i)) sxz += R(ex(i) * ez(i)) * v;
+    if (ey(i) && ez(i)) syz += R(ey(i) * ez(i)) * v;
+  }
+  const R ux = fmr(jx, irho, R(0.5) * par3<R>(D.gx, D.gx_f));
+  const R uy = fmr(jy, irho, R(0.5) * par3<R>(D.gy, D.gy_f));
+  const R uz = fmr(jz, irho, R(0.5) * par3<R>(D.gz, D.gz_f));
+  const R third = drho * (R(1) / R(3));
+  const R pxx = sxx - third - rho * ux * ux, pyy = syy - third - rho * uy * uy,
+          pzz = szz - third - rho * uz * uz;
+  const R pxy = sxy - rho * ux * uy, pxz = sxz - rho * ux * uz, pyz = syz - rho * uy * uz;
+  const R fro2 = pxx * pxx + pyy * pyy + pzz * pzz + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz);
+  return R(2.1213203435596424) * sqrt(fro2) * irho;  // 3 / sqrt(2)
+}
 
 // Storage of the deviations: FP64 and FP32 as they are; the 16-bit formats
 // hold d_i K_i with powers of two K (so scaling is exact) near 1 / w_i, which
@@ -157,7 +240,7 @@ __device__ __forceinline__ uint32_t round_bits3(const Dom3 &D, uint32_t node, ui
 // increments before the one final rounding, as the D2Q9 sweep does (the
 // momentum term of the stored values would otherwise round the body force
 // of slow flows with a bias).
-template <class R, int Q> __device__ __forceinline__ void collide3(const Dom3 &D, R d[Q]) {
+template <class R, int Q, bool PL> __device__ __forceinline__ void collide3(const Dom3 &D, R d[Q]) {
   R drho = d[0];
 #pragma unroll
   for (int i = 1; i < Q; i += 2) drho += d[i] + d[i + 1];
@@ -171,8 +254,24 @@ template <class R, int Q> __device__ __forceinline__ void collide3(const Dom3 &D
   }
   const R rho = par3<R>(D.rho0, D.rho0_f) + drho;
   const R irho = R(1) / rho;
-  const R tau = par3<R>(D.tau_m, D.tau_m_f), om = par3<R>(D.omega, D.omega_f);
-  const R omm = par3<R>(D.omega_m, D.omega_m_f);
+  // tau: the relaxation time of the force shift (tau_minus for TRT)
+  R tau = par3<R>(D.tau_m, D.tau_m_f), om = par3<R>(D.omega, D.omega_f);
+  R omm = par3<R>(D.omega_m, D.omega_m_f);
+  if constexpr (PL) {
+    R ps[(Q - 1) / 2 + 1];
+#pragma unroll
+    for (int k = 1; k <= (Q - 1) / 2; ++k) ps[k] = d[2 * k - 1] + d[2 * k];
+    const R inv[4] = {R(1), R(1), R(1), R(1)};
+    const R ts = tau_power3<R>(D, shear_measure3<R, Q>(D, ps, inv, drho, rho, irho, jx, jy, jz));
+    om = R(1) / ts;
+    if (D.trt) {
+      tau = R(0.5) + par3<R>(D.magic, D.magic_f) / (ts - R(0.5));
+      omm = R(1) / tau;
+    } else {
+      tau = ts;
+      omm = om;
+    }
+  }
   const R gx = par3<R>(D.gx, D.gx_f), gy = par3<R>(D.gy, D.gy_f), gz = par3<R>(D.gz, D.gz_f);
   const R rt = rho * tau;
   const R Jx = fmr(rt, gx, jx), Jy = fmr(rt, gy, jy), Jz = fmr(rt, gz, jz);
@@ -258,7 +357,7 @@ template <class R, int Q> __device__ __forceinline__ void collide3(const Dom3 &D
 // symmetric and antisymmetric parts.  Relaxation is applied to the stored
 // values directly (no increment form: the rounding to 16 bits is far
 // coarser than the FP32 arithmetic).
-template <int Q> __device__ __forceinline__ void collide3_scaled(const Dom3 &D, float d[Q]) {
+template <int Q, bool PL> __device__ __forceinline__ void collide3_scaled(const Dom3 &D, float d[Q]) {
   constexpr int P = (Q - 1) / 2;  // direction pairs: k covers 2k - 1 and 2k
   float ps[P + 1], pd[P + 1];
 #pragma unroll
@@ -291,15 +390,38 @@ template <int Q> __device__ __forceinline__ void collide3_scaled(const Dom3 &D, 
   }
   const float rho = D.rho0_f + drho;
   const float irho = __builtin_amdgcn_rcpf(rho);  // 1 ulp: enters only the second-order term
-  const float rt = rho * D.tau_m_f;
+  // the domain's coefficients, or with the power law those of the local tau*
+  float tm = D.tau_m_f, cw = D.s_cw, cq = D.s_cq, cl = D.s_cl, om0 = D.s_om0, keep = D.keep_f;
+  float om = D.omega_f, omm = D.omega_m_f;
+  if constexpr (PL) {
+    const float inv[4] = {i0, i1, i2, i3};
+    const float ts = tau_power3<float>(
+        D, shear_measure3<float, Q>(D, ps, inv, drho, rho, irho, jxyz[0], jxyz[1], jxyz[2]));
+    om = 1.0f / ts;
+    constexpr float kw = Q == 27 ? 32.0f / 27.0f : 8.0f / 9.0f;
+    if (D.trt) {
+      tm = 0.5f + D.magic_f / (ts - 0.5f);
+      omm = 1.0f / tm;
+      cw = kw;
+      om0 = 1.0f;
+    } else {
+      tm = ts;
+      cw = om * kw;
+      om0 = om;
+      keep = 1.0f - om;
+    }
+    cq = 4.5f * cw;
+    cl = 3.0f * cw;
+  }
+  const float rt = rho * tm;
   const float Jx = fmr(rt, D.gx_f, jxyz[0]), Jy = fmr(rt, D.gy_f, jxyz[1]),
               Jz = fmr(rt, D.gz_f, jxyz[2]);
   const float ux = Jx * irho, uy = Jy * irho, uz = Jz * irho;
   const float q = (1.5f * rho) * fmr(ux, ux, fmr(uy, uy, uz * uz));
-  const float b = D.s_cw * (drho - q);
-  const float a = D.s_cq * rho;
+  const float b = cw * (drho - q);
+  const float a = cq * rho;
   const float ax = a * ux, ay = a * uy, az = a * uz;
-  const float lx = D.s_cl * Jx, ly = D.s_cl * Jy, lz = D.s_cl * Jz;
+  const float lx = cl * Jx, ly = cl * Jy, lz = cl * Jz;
   float c[P + 1], l[P + 1];
   float cs[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // per class: sum of the even parts
 #pragma unroll
@@ -317,9 +439,8 @@ template <int Q> __device__ __forceinline__ void collide3_scaled(const Dom3 &D, 
   constexpr float K0 = scale3(Q, 0);
   float others = fmr(i1, cs[1], i2 * cs[2]);
   if constexpr (Q == 27) others = fmr(i3, cs[3], others);
-  const float eq0 = fmr(K0 * D.s_om0, drho, -(2.0f * K0) * others);
+  const float eq0 = fmr(K0 * om0, drho, -(2.0f * K0) * others);
   if (!D.trt) {
-    const float keep = D.keep_f;
     d[0] = fmr(keep, d[0], eq0);
 #pragma unroll
     for (int k = 1; k <= P; ++k) {
@@ -327,7 +448,6 @@ template <int Q> __device__ __forceinline__ void collide3_scaled(const Dom3 &D, 
       d[2 * k] = fmr(keep, d[2 * k], c[k] - l[k]);
     }
   } else {
-    const float om = D.omega_f, omm = D.omega_m_f;
     d[0] = fmr(om, eq0 - d[0], d[0]);
 #pragma unroll
     for (int k = 1; k <= P; ++k) {
@@ -382,8 +502,8 @@ template <class T> __device__ __forceinline__ void st3(Res3 r, uint32_t voff, ui
 // One step of every node: 256 threads = a tile of 64 (x) by 4 (y) nodes of
 // one z plane; each wave reads 64 consecutive x of a row per population
 // plane.  D3Q19: eight waves per SIMD for the FP32 and 16-bit formats (at
-// most 64 registers), four for FP64; D3Q27: at least four, and two for
-// FP64 (no spills).  A solid node stores zero deviations (every slot is written each
+// most 64 registers), four for FP64; D3Q27 and the power law: at least four,
+// half as many for FP64 (no spills).  A solid node stores zero deviations (every slot is written each
 // step and never pulled).  Addressing: each direction pair (i odd, i + 1)
 // loads at the pair's first population plane (a wave-uniform offset) plus a
 // per-lane byte offset, and stores at its own plane plus the node's offset;
@@ -392,8 +512,8 @@ template <class T> __device__ __forceinline__ void st3(Res3 r, uint32_t voff, ui
 // address.  A bounced link reads the opposite population of the node itself,
 // from the same pair base.  SOLIDS false: no node words (no walls or
 // obstacles).
-template <int ST, bool SOLIDS, bool WIDE, int Q>
-__global__ __launch_bounds__(256, ST == 0 ? (Q == 27 ? 2 : 4) : (Q == 27 ? 4 : 8)) void k_sweep3(const Dom3 *__restrict__ Dp, int kstep) {
+template <int ST, bool SOLIDS, bool WIDE, int Q, bool PL>
+__global__ __launch_bounds__(256, ST == 0 ? (Q == 27 ? 2 : 4) / (PL ? 2 : 1) : (Q == 27 || PL ? 4 : 8)) void k_sweep3(const Dom3 *__restrict__ Dp, int kstep) {
   using S = S3<ST>;
   using T = typename S::T;
   using R = typename S::R;
@@ -463,8 +583,8 @@ __global__ __launch_bounds__(256, ST == 0 ? (Q == 27 ? 2 : 4) : (Q == 27 ? 4 : 8
       else
         d[i] = in(ld3<T>(rs, off, __builtin_amdgcn_readfirstlane((uint32_t)lo * popb)), i);
     }
-    if constexpr (sizeof(T) == 2) collide3_scaled<Q>(D, d);
-    else collide3<R, Q>(D, d);
+    if constexpr (sizeof(T) == 2) collide3_scaled<Q, PL>(D, d);
+    else collide3<R, Q, PL>(D, d);
     if (!(fabs((double)d[0]) < 1e30)) atomicOr(D.health, 1u);
   }
   const uint32_t h = sizeof(T) == 2 && D.sr ? round_bits3(D, (uint32_t)node, (uint32_t)T0) : 0u;
@@ -537,7 +657,10 @@ __global__ __launch_bounds__(256) void k_init3(const Dom3 *__restrict__ Dp, cons
       d[i] = (R)(w * ((r - D.rho0) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)));
     }
   }
-  if (!solid) collide3<R, Q>(D, d);
+  if (!solid) {
+    if (D.pl) collide3<R, Q, true>(D, d);
+    else collide3<R, Q, false>(D, d);
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) dst[(size_t)i * plane + here] = S::enc(d[i], Q, i, false, 0u);
 }

@@ -80,6 +80,8 @@ class Domain3Desc(C.Structure):
         ("init_uy", C.POINTER(C.c_double)), ("init_uz", C.POINTER(C.c_double)),
         ("collision", C.c_int32), ("magic", C.c_double),
         ("rounding", C.c_int32), ("seed", C.c_uint64), ("lattice", C.c_int32),
+        ("power_law", C.c_int32), ("n_index", C.c_double), ("K", C.c_double),
+        ("tau_min", C.c_double), ("tau_max", C.c_double),
     ]
 
 
@@ -464,15 +466,22 @@ class Domain3:
     def __init__(self, nx, ny, nz, *, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0),
                  walls=(False, False, False), storage="f32", obstacles=None, init=None,
                  collision="bgk", magic=3.0 / 16.0, rounding=None, seed=0, lattice="d3q19",
-                 device="cuda", stream=None):
+                 power_law=None, device="cuda", stream=None):
         """collision "trt": two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic.
         storage "f64" | "f32" | "f16" | "bf16"; rounding "nearest" | "stochastic"
-        (16-bit storage only; its default there); lattice "d3q19" | "d3q27"."""
+        (16-bit storage only; its default there); lattice "d3q19" | "d3q27";
+        power_law: dict(n, K, tau_min=0.51, tau_max=2.5)."""
         lib = library()
         d = Domain3Desc()
         d.abi_version = ABI_VERSION
         d.collision = {"bgk": LB3_BGK, "trt": LB3_TRT}[collision]
         d.lattice = {"d3q19": LB3_D3Q19, "d3q27": LB3_D3Q27}[lattice]
+        if power_law is not None:
+            d.power_law = 1
+            d.n_index = float(power_law["n"])
+            d.K = float(power_law["K"])
+            d.tau_min = float(power_law.get("tau_min", 0.51))
+            d.tau_max = float(power_law.get("tau_max", 2.5))
         self.q = 27 if lattice == "d3q27" else 19
         d.magic = float(magic)
         d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
