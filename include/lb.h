@@ -43,7 +43,12 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 1u
+/* Layout version of the descriptor structs: a caller sets abi_version to
+ * the value its header carries, and a library built against another layout
+ * refuses the descriptor (LB_EINVAL).  2: lb_domain_desc gained collision
+ * and magic; lb3_domain_desc gained rounding, seed, lattice and the power
+ * law. */
+#define LB_ABI_VERSION 2u
 
 typedef int32_t lb_status;
 #define LB_OK 0

@@ -30,7 +30,7 @@ OPT_TWO_STEP = 6
 OPT_OVERLAP = 7
 OPT_MASS_INTERVAL = 8
 OPT_TWO_STEP_ROWS = 10
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 _BC = {"periodic": PERIODIC, "wall": WALL, "pressure": PRESSURE}
 _ST = {"f64": F64, "f32": F32, "f16": F16_DELTA, "bf16": BF16_DELTA}

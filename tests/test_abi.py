@@ -34,14 +34,14 @@ def test_library_exports_every_declared_symbol():
 def _desc(**kw):
     from paper_2006_12910_amd import lb
     d = lb.DomainDesc()
-    d.abi_version, d.nx, d.ny, d.tau, d.rho0 = 1, 64, 32, 0.8, 1.0
+    d.abi_version, d.nx, d.ny, d.tau, d.rho0 = lb.ABI_VERSION, 64, 32, 0.8, 1.0
     for k, v in kw.items():
         setattr(d, k, v)
     return d
 
 
 @pytest.mark.parametrize("bad,msg", [
-    (dict(tau=0.5), "tau"), (dict(nx=2), "nx"), (dict(abi_version=7), "abi"),
+    (dict(tau=0.5), "tau"), (dict(nx=2), "nx"), (dict(abi_version=1), "abi"),
     (dict(bc_y=2), "bc_y"), (dict(storage=9), "storage"), (dict(rounding=1), "stochastic"),
     (dict(max_particles=251), "max_particles"), (dict(kT=-1.0), "kT"),
     (dict(power_law=1, n_index=0.5, K=0.01, tau_min=0.4, tau_max=2.5), "power law"),
@@ -57,6 +57,12 @@ def test_validation_errors(bad, msg):
     st = lib.lb_workspace_bytes(C.byref(_desc(**bad)), C.byref(n))
     assert st == lb.LB_EINVAL
     assert msg.lower() in lib.lb_last_error().decode().lower()
+
+
+def test_binding_abi_version_matches_the_header():
+    from paper_2006_12910_amd import lb
+    src = open(os.path.join(ROOT, "include", "lb.h")).read()
+    assert int(re.search(r"^#define LB_ABI_VERSION (\d+)u", src, re.M).group(1)) == lb.ABI_VERSION
 
 
 def test_trt_validation():
@@ -117,14 +123,14 @@ def test_binding_constants_match_the_header():
 def _desc3(**kw):
     from paper_2006_12910_amd import lb
     d = lb.Domain3Desc()
-    d.abi_version, d.nx, d.ny, d.nz, d.tau, d.rho0, d.storage = 1, 32, 16, 8, 0.8, 1.0, 1
+    d.abi_version, d.nx, d.ny, d.nz, d.tau, d.rho0, d.storage = lb.ABI_VERSION, 32, 16, 8, 0.8, 1.0, 1
     for k, v in kw.items():
         setattr(d, k, v)
     return d
 
 
 @pytest.mark.parametrize("bad,msg", [
-    (dict(tau=0.5), "tau"), (dict(nz=2), "nz"), (dict(abi_version=3), "abi"),
+    (dict(tau=0.5), "tau"), (dict(nz=2), "nz"), (dict(abi_version=1), "abi"),
     (dict(storage=4), "storage"), (dict(init_kind=1), "INIT_FIELDS"), (dict(rho0=0.0), "rho0"),
     (dict(rounding=2), "rounding"), (dict(rounding=1), "stochastic rounding needs"),
     (dict(lattice=2), "lattice"),
