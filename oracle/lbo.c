@@ -166,15 +166,15 @@ static void box_muller(uint32_t kr, uint32_t ka, float *z0, float *z1) {
   *z1 = rad * sn;
 }
 
-/* Theta_3..Theta_8 of Eq. NP2 for one node and step.  One Philox4x32-10 block:
- * counter (node, step, 0, 0), key (lo32(seed), hi32(seed) ^ domain_id).  The
+/* Six standard normals from one Philox4x32-10 block: counter
+ * (node, step, block, 0), key (lo32(seed), hi32(seed) ^ domain_id).  The
  * 128 output bits give six 21-bit integers: the top 21 bits of w0..w3, and
  * two built from the low bits, (w0 & 0x7ff) << 10 | (w2 & 0x3ff) and
  * (w1 & 0x7ff) << 10 | (w3 & 0x3ff).  Pairs (w0,w1), (w2,w3) and the two
  * low-bit words feed three Box-Muller transforms (radius, angle). */
-void lbo_normals(uint64_t seed, uint32_t domain_id, uint32_t node, uint32_t step,
-                 float out[6]) {
-  uint32_t ctr[4] = {node, step, 0u, 0u};
+void lbo_normals_block(uint64_t seed, uint32_t domain_id, uint32_t node, uint32_t step,
+                       uint32_t block, float out[6]) {
+  uint32_t ctr[4] = {node, step, block, 0u};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ domain_id};
   uint32_t w[4];
   lbo_philox4x32_10(ctr, key, w);
@@ -184,6 +184,12 @@ void lbo_normals(uint64_t seed, uint32_t domain_id, uint32_t node, uint32_t step
   box_muller(a0, a1, &out[0], &out[1]);
   box_muller(a2, a3, &out[2], &out[3]);
   box_muller(b0, b1, &out[4], &out[5]);
+}
+
+/* Theta_3..Theta_8 of Eq. NP2 for one node and step: block 0. */
+void lbo_normals(uint64_t seed, uint32_t domain_id, uint32_t node, uint32_t step,
+                 float out[6]) {
+  lbo_normals_block(seed, domain_id, node, step, 0u, out);
 }
 
 void lbo_normals_bulk(uint64_t seed, uint32_t domain_id, uint32_t step, uint32_t node0,

@@ -106,7 +106,11 @@ void lbo_link_forces(const lbo_sim *s, double *out);
 void lbo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 float lbo_logf(float u);
 void lbo_sincos2pi(float u, float *s, float *c);
-/* the six standard normals Theta_3..Theta_8 of one node and step */
+/* six standard normals from Philox block `block` of one node and step
+ * (counter (node, step, block, 0)) */
+void lbo_normals_block(uint64_t seed, uint32_t domain_id, uint32_t node, uint32_t step,
+                       uint32_t block, float out[6]);
+/* the six standard normals Theta_3..Theta_8 of one node and step (block 0) */
 void lbo_normals(uint64_t seed, uint32_t domain_id, uint32_t node, uint32_t step,
                  float out[6]);
 /* the same for nodes node0 .. node0+count-1, out [count][6] */

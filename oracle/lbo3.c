@@ -9,7 +9,8 @@
  * rates 1/tau and 1/tau_minus, (tau - 1/2)(tau_minus - 1/2) = magic; the
  * body force then shifts u_eq by tau_minus g, since the antisymmetric part
  * carries the momentum (reading stated in the design notes: the paper uses
- * BGK only).  TEST INFRASTRUCTURE ONLY: used by the tests and the
+ * BGK only).  Optionally thermal noise (Sec. 4) in the form stated at
+ * noise3() below.  TEST INFRASTRUCTURE ONLY: used by the tests and the
  * benchmark's CPU-baseline leg, never by the library.
  *
  * Plain on purpose: full populations f (not deviations), two arrays, one
@@ -17,6 +18,8 @@
  * -ffp-contract=off.
  */
 #include "lbo3.h"
+
+#include "lbo.h" /* the Philox / Box-Muller normals of the D2Q9 oracle */
 
 #include <math.h>
 #include <stdlib.h>
@@ -79,6 +82,8 @@ lbo3_sim *lbo3_create(const lbo3_params *p, const uint8_t *mask, const double *r
     return NULL;
   if (p->trt && !(p->magic > 0.0)) return NULL;
   if (p->q != 19 && p->q != 27) return NULL;
+  if (!(p->kT >= 0.0) || (p->kT > 0.0 && p->trt)) return NULL;
+  if (p->kT > 0.0 && (double)p->nx * p->ny * p->nz > 4294967295.0) return NULL;
   lbo3_sim *s = (lbo3_sim *)calloc(1, sizeof(lbo3_sim));
   s->p = *p;
   s->q = p->q;
@@ -175,6 +180,39 @@ static double powerlaw_tau3(const lbo3_sim *s, const double *fl, double rho, dou
   return t;
 }
 
+/* Thermal noise of one collision (Sec. 4, Eqs. NP1-NP2 carried to 3D).  The
+ * D2Q9 method puts independent unit normals Theta_k on each non-conserved
+ * mode of a basis orthonormal under sum_i w_i chi_ki chi_li, scaled by
+ * sqrt(rho kT omega (2 - omega) / c_s^2) and mapped back with w_i; the noise
+ * then has covariance amp^2 (W - w w^T - 3 (W e)(W e)^T), W = diag(w), the
+ * part of W with the mass and momentum modes removed.  The same Gaussian is
+ * drawn here without a basis: q independent unit normals xi_i, eta_i =
+ * sqrt(w_i) xi_i (covariance W), minus their mass and momentum parts,
+ * zeta_i = amp (eta_i - w_i S - 3 w_i e_i.V), S = sum eta, V = sum e eta.
+ * The xi come from Philox blocks 0, 1, ... of (node, step): block b gives
+ * xi_{6b} .. xi_{6b+5}, the first q are used. */
+static void noise3(const lbo3_sim *s, uint32_t node, double rho, double tau, double *zeta) {
+  const lbo3_params *p = &s->p;
+  const int q = s->q;
+  float xi[30];
+  for (int b = 0; 6 * b < q; ++b)
+    lbo_normals_block(p->seed, 0u, node, (uint32_t)s->t, (uint32_t)b, xi + 6 * b);
+  const double om = 1.0 / tau;
+  const double amp = sqrt(rho * p->kT * om * (2.0 - om) * 3.0); /* 1 / c_s^2 = 3 */
+  double eta[27], S = 0.0, V[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < q; ++i) {
+    eta[i] = sqrt(s->w[i]) * (double)xi[i];
+    S += eta[i];
+    V[0] += EX[i] * eta[i];
+    V[1] += EY[i] * eta[i];
+    V[2] += EZ[i] * eta[i];
+  }
+  for (int i = 0; i < q; ++i) {
+    const double eV = EX[i] * V[0] + EY[i] * V[1] + EZ[i] * V[2];
+    zeta[i] = amp * (eta[i] - s->w[i] * S - 3.0 * s->w[i] * eV);
+  }
+}
+
 /* collide every fluid node into fs */
 static void collide(lbo3_sim *s) {
   const lbo3_params *p = &s->p;
@@ -197,9 +235,11 @@ static void collide(lbo3_sim *s) {
         double uy = jy / rho + tm * p->gy;
         double uz = jz / rho + tm * p->gz;
         if (!p->trt) {
+          double zeta[27] = {0.0};
+          if (p->kT > 0.0) noise3(s, (uint32_t)NODE(s, x, y, z), rho, tau, zeta);
           for (int i = 0; i < s->q; ++i)
             s->fs[IDX(s, i, x, y, z)] =
-                fl[i] - (fl[i] - feq(i, s->w[i], rho, ux, uy, uz)) / tau;
+                fl[i] - (fl[i] - feq(i, s->w[i], rho, ux, uy, uz)) / tau + zeta[i];
           continue;
         }
         for (int i = 0; i < s->q; ++i) {

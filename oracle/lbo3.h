@@ -1,8 +1,9 @@
 /*
  * lbo3.h -- CPU oracle (FP64) of the three-dimensional lattice-Boltzmann step
  * on D3Q19 or D3Q27: BGK with the velocity-shift body force (Sec. 2), or its
- * two-relaxation-time (TRT) variant, pull streaming with periodic wrap,
- * halfway bounce-back on solid nodes.  TEST INFRASTRUCTURE ONLY.
+ * two-relaxation-time (TRT) variant, optionally with thermal noise (BGK),
+ * pull streaming with periodic wrap, halfway bounce-back on solid nodes.
+ * TEST INFRASTRUCTURE ONLY.
  *
  * Arrays: nodes [nz][ny][nx] (x fastest), populations [q][nz][ny][nx].
  * Step order: collide every fluid node, then pull-stream.  The reported
@@ -29,6 +30,10 @@ typedef struct {
    * [tau_min, tau_max]; tau is then unused (TRT takes tau_minus from tau*) */
   int32_t power_law;
   double n_index, K, tau_min, tau_max;
+  /* kT > 0: thermal noise of the fluctuating method (Sec. 4) added to every
+   * collision, BGK only; Philox key (lo32(seed), hi32(seed)) */
+  double kT;
+  uint64_t seed;
 } lbo3_params;
 
 typedef struct lbo3_sim lbo3_sim;

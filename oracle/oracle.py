@@ -46,7 +46,8 @@ class _Params3(C.Structure):
         ("tau", C.c_double), ("rho0", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
         ("gz", C.c_double), ("trt", C.c_int32), ("magic", C.c_double), ("q", C.c_int32),
         ("power_law", C.c_int32), ("n_index", C.c_double), ("K", C.c_double),
-        ("tau_min", C.c_double), ("tau_max", C.c_double),
+        ("tau_min", C.c_double), ("tau_max", C.c_double), ("kT", C.c_double),
+        ("seed", C.c_uint64),
     ]
 
 
@@ -87,6 +88,8 @@ def _load():
     lib.lbo_logf.restype = C.c_float
     lib.lbo_logf.argtypes = [C.c_float]
     lib.lbo_sincos2pi.argtypes = [C.c_float, P(C.c_float), P(C.c_float)]
+    lib.lbo_normals_block.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                      P(C.c_float)]
     lib.lbo_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, P(C.c_float)]
     lib.lbo_normals_bulk.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                      P(C.c_float)]
@@ -250,6 +253,14 @@ def normals(seed, domain_id, node, step):
     return np.array([o[i] for i in range(6)], dtype=np.float32)
 
 
+def normals_block(seed, domain_id, node, step, block):
+    """The six FP32 normals of Philox block `block` of (node, step)."""
+    o = (C.c_float * 6)()
+    _load().lbo_normals_block(seed & (2**64 - 1), domain_id & 0xFFFFFFFF, node & 0xFFFFFFFF,
+                              step & 0xFFFFFFFF, block & 0xFFFFFFFF, o)
+    return np.array([o[i] for i in range(6)], dtype=np.float32)
+
+
 def normals_bulk(seed, domain_id, step, node0, count):
     """[count][6] FP32 normals of nodes node0 .. node0+count-1 at `step`."""
     out = np.empty((count, 6), dtype=np.float32)
@@ -275,9 +286,10 @@ class Oracle3:
 
     def __init__(self, nx, ny, nz, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0), walls=(False, False, False),
                  obstacles=None, init=None, collision="bgk", magic=3.0 / 16.0, lattice="d3q19",
-                 power_law=None):
+                 power_law=None, kT=0.0, seed=0):
         """collision "trt": two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic;
-        lattice "d3q19" or "d3q27"; power_law: dict(n, K, tau_min=0.51, tau_max=2.5)."""
+        lattice "d3q19" or "d3q27"; power_law: dict(n, K, tau_min=0.51, tau_max=2.5);
+        kT > 0: thermal noise (BGK only) keyed by seed."""
         lib = _load()
         self.nx, self.ny, self.nz = nx, ny, nz
         self.q = {"d3q19": 19, "d3q27": 27}[lattice]
@@ -285,7 +297,7 @@ class Oracle3:
         c = _Params3(nx, ny, nz, int(walls[0]), int(walls[1]), int(walls[2]), tau, rho0, *g,
                      int(collision == "trt"), magic, self.q, int(power_law is not None),
                      pl.get("n", 1.0), pl.get("K", 0.0), pl.get("tau_min", 0.51),
-                     pl.get("tau_max", 2.5))
+                     pl.get("tau_max", 2.5), kT, seed)
         shape = (nz, ny, nx)
         mask = None
         if obstacles is not None:
