@@ -448,6 +448,16 @@ def other_configs():
             r = out[name]
             r["sweep_GBps"] = round(r["gpu_mlups"] * 1e6 * 2 * q * sb / 1e9, 1)
             r["hbm_frac"] = round(r["sweep_GBps"] / HBM_PEAK_GBS, 4)
+        # with thermal noise, kT = 1e-4 (q normals a node: Philox blocks and
+        # Box-Muller pairs in the sweep)
+        for storage, sb in (("f32", 4), ("f16", 2)):
+            d, _, _ = d3q19_cube(storage, n3, lattice, kT=1e-4)
+            name = f"{lattice}_256cube_{storage}_noise"
+            gpu_rate(name, d, n3 ** 3, 200)
+            d.close()
+            r = out[name]
+            r["sweep_GBps"] = round(r["gpu_mlups"] * 1e6 * 2 * q * sb / 1e9, 1)
+            r["hbm_frac"] = round(r["sweep_GBps"] / HBM_PEAK_GBS, 4)
     torch.cuda.empty_cache()
     return out
 
@@ -488,11 +498,11 @@ def powerlaw_channel(storage="f32"):
     return d, [d], 4096 * 256
 
 
-def d3q19_cube(storage="f32", n=256, lattice="d3q19"):
+def d3q19_cube(storage="f32", n=256, lattice="d3q19", kT=0.0):
     """The 3D lattice (D3Q19, or D3Q27): 256^3 periodic, tau = 0.8, at rest
-    (16-bit storage with stochastic rounding)."""
+    (16-bit storage with stochastic rounding); kT > 0: thermal noise."""
     from paper_2006_12910_amd import lb
-    d = lb.Domain3(n, n, n, tau=0.8, storage=storage, seed=3, lattice=lattice)
+    d = lb.Domain3(n, n, n, tau=0.8, storage=storage, seed=3, lattice=lattice, kT=kT)
     return d, [d], n ** 3
 
 
@@ -504,7 +514,10 @@ def only_workload(name, steps, warmup):
             "porous": porous_discs, "powerlaw": powerlaw_channel, "d3q19": d3q19_cube,
             "d3q19-f16": lambda: d3q19_cube("f16"),
             "d3q27": lambda: d3q19_cube("f32", lattice="d3q27"),
-            "d3q27-f16": lambda: d3q19_cube("f16", lattice="d3q27")}[name]
+            "d3q27-f16": lambda: d3q19_cube("f16", lattice="d3q27"),
+            "d3q19-noise": lambda: d3q19_cube("f32", kT=1e-4),
+            "d3q19-f16-noise": lambda: d3q19_cube("f16", kT=1e-4),
+            "d3q27-noise": lambda: d3q19_cube("f32", lattice="d3q27", kT=1e-4)}[name]
     runner, doms, sites = make()
     runner.step(max(warmup, 1))
     torch.cuda.synchronize()
@@ -721,7 +734,8 @@ def main():
                          'earlier line (to profile the configuration that line measured)')
     ap.add_argument("--only", default=None,
                     choices=["fluct-ensemble", "fluct-ensemble-f16", "porous", "powerlaw", "d3q19",
-                             "d3q19-f16", "d3q27", "d3q27-f16"],
+                             "d3q19-f16", "d3q27", "d3q27-f16", "d3q19-noise",
+                             "d3q19-f16-noise", "d3q27-noise"],
                     help="time one other workload alone (GPU only; for profiling) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="before the workload, copy a buffer of this size 5 times (a kernel of "

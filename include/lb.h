@@ -47,8 +47,8 @@ extern "C" {
  * the value its header carries, and a library built against another layout
  * refuses the descriptor (LB_EINVAL).  2: lb_domain_desc gained collision
  * and magic; lb3_domain_desc gained rounding, seed, lattice and the power
- * law. */
-#define LB_ABI_VERSION 2u
+ * law.  3: lb3_domain_desc gained kT. */
+#define LB_ABI_VERSION 3u
 
 typedef int32_t lb_status;
 #define LB_OK 0
@@ -419,9 +419,23 @@ lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms);
  * magic = (tau - 1/2)^2 is BGK.  Power law (Sec. 5): the local tau* from the
  * non-equilibrium stress as on the 2D domains, with all nine components of
  * the 3D stress in its Frobenius norm (with TRT, tau_minus follows tau*).
+ * Thermal noise (Sec. 4, Eqs. NP1-NP2 carried to 3D), BGK only: kT > 0 adds
+ * to every collision the Gaussian whose covariance is
+ * 3 rho kT omega (2 - omega) (W - w w^T - 3 (W e)(W e)^T), W = diag(w)
+ * (omega = 1/tau*, local with the power law): independent unit noise on
+ * every mode that is not mass or momentum, as the D2Q9 method has.  It is
+ * drawn as zeta_i = amp (eta_i - w_i S - 3 w_i e_i.V), eta_i = sqrt(w_i) xi_i,
+ * S = sum eta, V = sum e eta, amp = sqrt(3 rho kT omega (2 - omega)), from q
+ * unit normals xi_i: Philox4x32-10 block b of node n = (z ny + y) nx + x at
+ * step t (counter (n, t, b, 0), key (lo32(seed), hi32(seed))) gives
+ * xi_{6b} .. xi_{6b+5} by the D2Q9 domains' Box-Muller recipe
+ * (lb_noise_normals with domain_id 0 is block 0).  Step t is the collision that produces the
+ * state of time t (the one in lb3_create_domain is t = 0).  FP64 storage
+ * evaluates the transforms exactly as that recipe defines them, the others
+ * through the hardware's log2 / sin / cos (within 1e-6 of it).  Not with
+ * TRT (LB_EUNSUPPORTED); the lattice must have fewer than 2^32 nodes.
  * Same conventions as above: caller-owned 256-byte aligned workspace,
- * stream-ordered calls, errors through lb_last_error.  No particles or
- * noise. */
+ * stream-ordered calls, errors through lb_last_error.  No particles. */
 #define LB3_BGK 0
 #define LB3_TRT 1
 #define LB3_D3Q19 0
@@ -440,11 +454,12 @@ typedef struct lb3_domain_desc {
   int32_t collision;           /* LB3_BGK | LB3_TRT                               */
   double magic;                /* TRT: (tau - 1/2)(tau_minus - 1/2), > 0          */
   int32_t rounding;            /* LB_ROUND_NEAREST | LB_ROUND_STOCHASTIC (16-bit) */
-  uint64_t seed;               /* stochastic-rounding key                         */
+  uint64_t seed;               /* stochastic-rounding and noise key               */
   int32_t lattice;             /* LB3_D3Q19 | LB3_D3Q27                           */
   int32_t power_law;           /* nonzero: local tau* (Sec. 5), tau unused        */
   double n_index, K;           /* power-law index n and consistency xi            */
   double tau_min, tau_max;     /* clamp of tau*, 1/2 < tau_min <= tau_max         */
+  double kT;                   /* thermal energy k_B T >= 0; 0 disables noise     */
 } lb3_domain_desc;
 typedef struct lb3_domain lb3_domain;
 

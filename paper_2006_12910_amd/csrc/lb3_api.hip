@@ -95,6 +95,11 @@ lb_status validate3(const lb3_domain_desc *d) {
     return fail3(LB_EINVAL, "collision must be LB3_BGK or LB3_TRT");
   if (d->collision == LB3_TRT && !(d->magic > 0.0 && std::isfinite(d->magic)))
     return fail3(LB_EINVAL, "TRT magic number must be finite and > 0");
+  if (!(d->kT >= 0.0) || !std::isfinite(d->kT)) return fail3(LB_EINVAL, "kT must be finite and >= 0");
+  if (d->kT > 0.0 && d->collision == LB3_TRT)
+    return fail3(LB_EUNSUPPORTED, "thermal noise needs the BGK collision");
+  if (d->kT > 0.0 && (double)d->nx * d->ny * d->nz >= 4294967296.0)
+    return fail3(LB_EUNSUPPORTED, "thermal noise needs fewer than 2^32 nodes");
   if (!(d->rho0 > 0.0) || !std::isfinite(d->rho0)) return fail3(LB_EINVAL, "rho0 must be > 0");
   if (!std::isfinite(d->gx) || !std::isfinite(d->gy) || !std::isfinite(d->gz))
     return fail3(LB_EINVAL, "g not finite");
@@ -212,19 +217,24 @@ lb_status push_desc3(lb3_domain *d) {
 
 namespace {
 
-template <int ST, int Q, bool PL> void launch_sweep3_q(const lb3_domain *d, unsigned blocks, int k) {
+template <int ST, int Q, bool PL, bool NZ>
+void launch_sweep3_qn(const lb3_domain *d, unsigned blocks, int k) {
   const dim3 g(blocks), b(256);
   if (d->L.solids) {
     if (d->wide)
-      hipLaunchKernelGGL((k_sweep3<ST, true, true, Q, PL>), g, b, 0, d->stream, d->ddesc(), k);
+      hipLaunchKernelGGL((k_sweep3<ST, true, true, Q, PL, NZ>), g, b, 0, d->stream, d->ddesc(), k);
     else
-      hipLaunchKernelGGL((k_sweep3<ST, true, false, Q, PL>), g, b, 0, d->stream, d->ddesc(), k);
+      hipLaunchKernelGGL((k_sweep3<ST, true, false, Q, PL, NZ>), g, b, 0, d->stream, d->ddesc(), k);
   } else {
     if (d->wide)
-      hipLaunchKernelGGL((k_sweep3<ST, false, true, Q, PL>), g, b, 0, d->stream, d->ddesc(), k);
+      hipLaunchKernelGGL((k_sweep3<ST, false, true, Q, PL, NZ>), g, b, 0, d->stream, d->ddesc(), k);
     else
-      hipLaunchKernelGGL((k_sweep3<ST, false, false, Q, PL>), g, b, 0, d->stream, d->ddesc(), k);
+      hipLaunchKernelGGL((k_sweep3<ST, false, false, Q, PL, NZ>), g, b, 0, d->stream, d->ddesc(), k);
   }
+}
+template <int ST, int Q, bool PL> void launch_sweep3_q(const lb3_domain *d, unsigned blocks, int k) {
+  if (d->hd.noise) launch_sweep3_qn<ST, Q, PL, true>(d, blocks, k);
+  else launch_sweep3_qn<ST, Q, PL, false>(d, blocks, k);
 }
 template <int ST> void launch_sweep3_st(const lb3_domain *d, unsigned blocks, int k) {
   const bool pl = d->desc.power_law != 0;
@@ -318,6 +328,9 @@ static lb_status lb3_create_domain_impl(const lb3_domain_desc *desc, void *dev_w
   h.magic_f = (float)h.magic;
   h.omega = 1.0 / h.tau;
   h.trt = desc->collision == LB3_TRT ? 1 : 0;
+  h.noise = desc->kT > 0.0 ? 1 : 0;
+  h.kT = desc->kT;
+  h.kT_f = (float)desc->kT;
   h.tau_m = h.trt ? 0.5 + desc->magic / (h.tau - 0.5) : h.tau;
   h.omega_m = 1.0 / h.tau_m;
   h.tau_m_f = (float)h.tau_m;

@@ -89,6 +89,10 @@ struct Dom3 {
   int pl;  // power-law local tau*
   double pl_n, pl_K, tau_min, tau_max, magic;
   float pl_n_f, pl_K_f, tau_min_f, tau_max_f, magic_f;
+  // thermal noise (BGK): k_B T; Philox key (key0, key1)
+  int noise;
+  double kT;
+  float kT_f;
 };
 
 template <class R> __device__ __forceinline__ R par3(double a, float b);
@@ -229,6 +233,68 @@ __device__ __forceinline__ uint32_t round_bits3(const Dom3 &D, uint32_t node, ui
   return lbk::mix32(node ^ (lbk::mix32(step ^ D.key0) ^ D.key1));
 }
 
+// sqrt(w_i): D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216
+template <class R> __device__ __forceinline__ constexpr R sqw3(int q, int i) {
+  return q == 27 ? (cls3(i) == 0   ? R(0.544331053951817355154952016601)
+                    : cls3(i) == 1 ? R(0.272165526975908677577476008301)
+                    : cls3(i) == 2 ? R(0.136082763487954338788738004150)
+                                   : R(0.0680413817439771693943690020752))
+                 : (cls3(i) == 0   ? R(0.577350269189625764509148780502)
+                    : cls3(i) == 1 ? R(0.235702260395515841466948120702)
+                                   : R(0.166666666666666666666666666667));
+}
+
+// Thermal noise of one collision (Sec. 4, Eqs. NP1-NP2, carried to 3D): the
+// D2Q9 method's law, independent unit noise on every mode other than mass
+// and momentum scaled by sqrt(3 rho kT omega (2 - omega)), drawn without a
+// mode basis.  eta_i = sqrt(w_i) xi_i from q unit normals has covariance
+// W = diag(w); taking away its mass and momentum parts, zeta_i = amp (eta_i
+// - w_i (S + 3 e_i.V)), S = sum eta, V = sum e eta, leaves the covariance
+// amp^2 (W - w w^T - 3 (W e)(W e)^T), the same as the mode form.  Philox
+// block b of (node, step) gives xi_{6b} .. xi_{6b+5} (three Box-Muller
+// pairs, the D2Q9 recipe); FP32 arithmetic takes the hardware transform,
+// FP64 the exact one.
+template <class R, int Q>
+__device__ __forceinline__ void noise3(const Dom3 &D, uint32_t node, uint32_t step, R rho, R om,
+                                       R z[Q]) {
+  constexpr int PAIRS = (Q + 1) / 2;
+  float xi[2 * PAIRS];
+#pragma unroll
+  for (int b = 0; 3 * b < PAIRS; ++b) {
+    uint32_t w[4];
+    lbk::philox4x32_10(node, step, (uint32_t)b, 0u, D.key0, D.key1, w);
+    const uint32_t k[6] = {w[0] >> 11, w[1] >> 11, w[2] >> 11, w[3] >> 11,
+                           ((w[0] & 0x7ffu) << 10) | (w[2] & 0x3ffu),
+                           ((w[1] & 0x7ffu) << 10) | (w[3] & 0x3ffu)};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const int j = 3 * b + p;
+      if (j < PAIRS) {
+        if constexpr (sizeof(R) == 4) lbk::noise_pair_hw(k[2 * p], k[2 * p + 1], xi[2 * j], xi[2 * j + 1]);
+        else lbk::noise_pair(k[2 * p], k[2 * p + 1], xi[2 * j], xi[2 * j + 1]);
+      }
+    }
+  }
+  const R amp = sqrt(R(3) * rho * par3<R>(D.kT, D.kT_f) * om * (R(2) - om));
+  R S = R(0), Vx = R(0), Vy = R(0), Vz = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    z[i] = sqw3<R>(Q, i) * R(xi[i]);
+    S += z[i];
+    if (ex(i)) Vx += R(ex(i)) * z[i];
+    if (ey(i)) Vy += R(ey(i)) * z[i];
+    if (ez(i)) Vz += R(ez(i)) * z[i];
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    R m = S;
+    if (ex(i)) m += R(3 * ex(i)) * Vx;
+    if (ey(i)) m += R(3 * ey(i)) * Vy;
+    if (ez(i)) m += R(3 * ez(i)) * Vz;
+    z[i] = amp * fmr(-w3<R>(Q, i), m, z[i]);
+  }
+}
+
 // BGK or TRT collision of one node in deviation form.  The equilibrium of
 // Eq. LB2 with u = J / rho, J = j + rho tau_m g (tau_m = tau for BGK):
 // opposite velocities share the even part c and take c +- 3 w (e.J); the
@@ -240,7 +306,8 @@ __device__ __forceinline__ uint32_t round_bits3(const Dom3 &D, uint32_t node, ui
 // increments before the one final rounding, as the D2Q9 sweep does (the
 // momentum term of the stored values would otherwise round the body force
 // of slow flows with a bias).
-template <class R, int Q, bool PL> __device__ __forceinline__ void collide3(const Dom3 &D, R d[Q]) {
+template <class R, int Q, bool PL, bool NOISE>
+__device__ __forceinline__ void collide3(const Dom3 &D, R d[Q], uint32_t node, uint32_t step) {
   R drho = d[0];
 #pragma unroll
   for (int i = 1; i < Q; i += 2) drho += d[i] + d[i + 1];
@@ -303,6 +370,15 @@ template <class R, int Q, bool PL> __device__ __forceinline__ void collide3(cons
 #pragma unroll
       for (int i = 1; i < Q; ++i) inc[i] = om * (eq[i] - d[i]);
     }
+    if constexpr (NOISE) {
+      // the noise has no mass or momentum: the rest population's share
+      // follows from the mass balance below, its rounding from the momentum
+      // correction
+      R z[Q];
+      noise3<R, Q>(D, node, step, rho, om, z);
+#pragma unroll
+      for (int i = 1; i < Q; ++i) inc[i] += z[i];
+    }
     R sx = R(0), sy = R(0), sz = R(0);
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
@@ -343,6 +419,12 @@ template <class R, int Q, bool PL> __device__ __forceinline__ void collide3(cons
 #pragma unroll
       for (int i = 0; i < Q; ++i) d[i] = fmr(om, eq[i] - d[i], d[i]);
     }
+    if constexpr (NOISE) {
+      R z[Q];
+      noise3<R, Q>(D, node, step, rho, om, z);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) d[i] += z[i];
+    }
   }
 }
 
@@ -357,7 +439,8 @@ template <class R, int Q, bool PL> __device__ __forceinline__ void collide3(cons
 // symmetric and antisymmetric parts.  Relaxation is applied to the stored
 // values directly (no increment form: the rounding to 16 bits is far
 // coarser than the FP32 arithmetic).
-template <int Q, bool PL> __device__ __forceinline__ void collide3_scaled(const Dom3 &D, float d[Q]) {
+template <int Q, bool PL, bool NOISE>
+__device__ __forceinline__ void collide3_scaled(const Dom3 &D, float d[Q], uint32_t node, uint32_t step) {
   constexpr int P = (Q - 1) / 2;  // direction pairs: k covers 2k - 1 and 2k
   float ps[P + 1], pd[P + 1];
 #pragma unroll
@@ -457,6 +540,12 @@ template <int Q, bool PL> __device__ __forceinline__ void collide3_scaled(const 
       d[2 * k] += fmr(om, sym, -t);
     }
   }
+  if constexpr (NOISE) {
+    float z[Q];
+    noise3<float, Q>(D, node, step, rho, om, z);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = fmr(scale3(Q, i), z[i], d[i]);
+  }
 }
 
 // XCD-aware block order: the hardware deals consecutive block ids to the 8
@@ -512,8 +601,16 @@ template <class T> __device__ __forceinline__ void st3(Res3 r, uint32_t voff, ui
 // address.  A bounced link reads the opposite population of the node itself,
 // from the same pair base.  SOLIDS false: no node words (no walls or
 // obstacles).
-template <int ST, bool SOLIDS, bool WIDE, int Q, bool PL>
-__global__ __launch_bounds__(256, ST == 0 ? (Q == 27 ? 2 : 4) / (PL ? 2 : 1) : (Q == 27 || PL ? 4 : 8)) void k_sweep3(const Dom3 *__restrict__ Dp, int kstep) {
+// Waves per SIMD the register budget is sized for (FP64 holds twice the
+// registers; the power law and the noise take more of them).
+constexpr int sweep3_waves(int st, int q, bool pl, bool noise) {
+  const int base = st == 0 ? (q == 27 ? 2 : 4) / (pl ? 2 : 1) : (q == 27 || pl ? 4 : 8);
+  const int cap = st == 0 ? 2 : 4;
+  return noise && base > cap ? cap : base;
+}
+
+template <int ST, bool SOLIDS, bool WIDE, int Q, bool PL, bool NOISE>
+__global__ __launch_bounds__(256, sweep3_waves(ST, Q, PL, NOISE)) void k_sweep3(const Dom3 *__restrict__ Dp, int kstep) {
   using S = S3<ST>;
   using T = typename S::T;
   using R = typename S::R;
@@ -583,8 +680,12 @@ __global__ __launch_bounds__(256, ST == 0 ? (Q == 27 ? 2 : 4) / (PL ? 2 : 1) : (
       else
         d[i] = in(ld3<T>(rs, off, __builtin_amdgcn_readfirstlane((uint32_t)lo * popb)), i);
     }
-    if constexpr (sizeof(T) == 2) collide3_scaled<Q, PL>(D, d);
-    else collide3<R, Q, PL>(D, d);
+    // the noise counter: the unpadded node number and the step this
+    // collision produces
+    const uint32_t nn = ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)nx + (uint32_t)x;
+    const uint32_t step = (uint32_t)(T0 + 1);
+    if constexpr (sizeof(T) == 2) collide3_scaled<Q, PL, NOISE>(D, d, nn, step);
+    else collide3<R, Q, PL, NOISE>(D, d, nn, step);
     if (!(fabs((double)d[0]) < 1e30)) atomicOr(D.health, 1u);
   }
   const uint32_t h = sizeof(T) == 2 && D.sr ? round_bits3(D, (uint32_t)node, (uint32_t)T0) : 0u;
@@ -658,8 +759,14 @@ __global__ __launch_bounds__(256) void k_init3(const Dom3 *__restrict__ Dp, cons
     }
   }
   if (!solid) {
-    if (D.pl) collide3<R, Q, true>(D, d);
-    else collide3<R, Q, false>(D, d);
+    const uint32_t nn = (uint32_t)n, step = (uint32_t)*D.tstep;
+    if (D.noise) {
+      if (D.pl) collide3<R, Q, true, true>(D, d, nn, step);
+      else collide3<R, Q, false, true>(D, d, nn, step);
+    } else {
+      if (D.pl) collide3<R, Q, true, false>(D, d, nn, step);
+      else collide3<R, Q, false, false>(D, d, nn, step);
+    }
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) dst[(size_t)i * plane + here] = S::enc(d[i], Q, i, false, 0u);

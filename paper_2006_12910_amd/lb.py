@@ -30,7 +30,7 @@ OPT_TWO_STEP = 6
 OPT_OVERLAP = 7
 OPT_MASS_INTERVAL = 8
 OPT_TWO_STEP_ROWS = 10
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 _BC = {"periodic": PERIODIC, "wall": WALL, "pressure": PRESSURE}
 _ST = {"f64": F64, "f32": F32, "f16": F16_DELTA, "bf16": BF16_DELTA}
@@ -81,7 +81,7 @@ class Domain3Desc(C.Structure):
         ("collision", C.c_int32), ("magic", C.c_double),
         ("rounding", C.c_int32), ("seed", C.c_uint64), ("lattice", C.c_int32),
         ("power_law", C.c_int32), ("n_index", C.c_double), ("K", C.c_double),
-        ("tau_min", C.c_double), ("tau_max", C.c_double),
+        ("tau_min", C.c_double), ("tau_max", C.c_double), ("kT", C.c_double),
     ]
 
 
@@ -466,11 +466,12 @@ class Domain3:
     def __init__(self, nx, ny, nz, *, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0),
                  walls=(False, False, False), storage="f32", obstacles=None, init=None,
                  collision="bgk", magic=3.0 / 16.0, rounding=None, seed=0, lattice="d3q19",
-                 power_law=None, device="cuda", stream=None):
+                 power_law=None, kT=0.0, device="cuda", stream=None):
         """collision "trt": two relaxation times, (tau - 1/2)(tau_minus - 1/2) = magic.
         storage "f64" | "f32" | "f16" | "bf16"; rounding "nearest" | "stochastic"
         (16-bit storage only; its default there); lattice "d3q19" | "d3q27";
-        power_law: dict(n, K, tau_min=0.51, tau_max=2.5)."""
+        power_law: dict(n, K, tau_min=0.51, tau_max=2.5); kT > 0: thermal noise
+        (BGK), keyed by seed."""
         lib = library()
         d = Domain3Desc()
         d.abi_version = ABI_VERSION
@@ -491,6 +492,7 @@ class Domain3:
             rounding = "stochastic" if storage in ("f16", "bf16") else "nearest"
         d.rounding = _RND[rounding]
         d.seed = int(seed) & (2**64 - 1)
+        d.kT = float(kT)
         d.obstacles = 1 if obstacles is not None else 0
         d.rho0, d.tau = float(rho0), float(tau)
         d.gx, d.gy, d.gz = (float(v) for v in g)

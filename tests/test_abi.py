@@ -135,6 +135,7 @@ def _desc3(**kw):
     (dict(rounding=2), "rounding"), (dict(rounding=1), "stochastic rounding needs"),
     (dict(lattice=2), "lattice"),
     (dict(collision=2), "collision"), (dict(collision=1, magic=0.0), "magic"),
+    (dict(kT=-1e-5), "kT"), (dict(kT=float("nan")), "kT"), (dict(kT=float("inf")), "kT"),
 ])
 def test_d3q19_validation_errors(bad, msg):
     from paper_2006_12910_amd import lb
@@ -142,6 +143,22 @@ def test_d3q19_validation_errors(bad, msg):
     n = C.c_size_t()
     assert lib.lb3_workspace_bytes(C.byref(_desc3(**bad)), C.byref(n)) == lb.LB_EINVAL
     assert msg.lower() in lib.lb_last_error().decode().lower()
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(kT=1e-5, collision=1, magic=0.25), "BGK"),
+    (dict(kT=1e-5, nx=2048, ny=2048, nz=1024), "2^32"),
+])
+def test_d3q19_noise_unsupported_cases(bad, msg):
+    """Thermal noise on the 3D lattices: BGK only, fewer than 2^32 nodes (the
+    node number is the generator's 32-bit counter word)."""
+    from paper_2006_12910_amd import lb
+    lib = lb.library()
+    n = C.c_size_t()
+    assert lib.lb3_workspace_bytes(C.byref(_desc3(**bad)), C.byref(n)) == lb.LB_EUNSUPPORTED
+    assert msg.lower() in lib.lb_last_error().decode().lower()
+    ok = _desc3(kT=1e-5, nx=2048, ny=2048, nz=1023)
+    assert lib.lb3_workspace_bytes(C.byref(ok), C.byref(n)) == 0
 
 
 def test_d3q19_workspace_covers_both_population_buffers():

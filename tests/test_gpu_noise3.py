@@ -1,0 +1,163 @@
+"""GPU vs oracle parity of thermal noise on the 3D lattices (the fluctuating
+method of Sec. 4 carried to D3Q19 and D3Q27): FP64 storage draws the normals
+exactly as the oracle does (the same Philox counter and transform), so the
+states agree to accumulated rounding; FP32 takes the hardware transform
+(within 1e-6 of the exact one) and is held to the 1e-5 target; 16-bit
+deviation storage to the reduced-storage targets.  Ragged lattices with
+spherical obstacles and a wall; the power law (local omega in the noise
+amplitude); equipartition <rho u_a^2> = kT, <drho^2> = 3 kT on the GPU in
+every storage format; the seed keys the noise; and the full 256^3 lattice
+of the benchmark against the oracle at every node."""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle3
+
+pytestmark = pytest.mark.gpu
+
+
+def _spheres(nx, ny, nz, seed):
+    rng = np.random.default_rng(seed)
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx]
+    m = np.zeros((nz, ny, nx), np.uint8)
+    for _ in range(3):
+        c = rng.uniform([0, 0, 0], [nx, ny, nz])
+        r = rng.uniform(2.0, 3.5)
+        m[(x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2 < r * r] = 1
+    return m
+
+
+def _fields(nx, ny, nz, seed):
+    rng = np.random.default_rng(seed)
+    s = (nz, ny, nx)
+    return (1 + 0.005 * rng.standard_normal(s), 0.01 * rng.standard_normal(s),
+            0.01 * rng.standard_normal(s), 0.01 * rng.standard_normal(s))
+
+
+def _errors(gpu, ora):
+    rg, *ug = gpu.moments()
+    ro, *uo = ora.moments()
+    num = np.sqrt(sum(((a - b) ** 2).sum() for a, b in zip(ug, uo)))
+    den = np.sqrt(sum((b ** 2).sum() for b in uo))
+    return np.abs(rg - ro).max(), num / den
+
+
+CASES = [("f64", 1e-11), ("f32", 1e-5)]
+
+
+@pytest.mark.parametrize("storage,tol", CASES)
+@pytest.mark.parametrize("lattice", ["d3q19", "d3q27"])
+@pytest.mark.parametrize("shape", [(70, 9, 6), (64, 5, 4)])
+def test_noise3_against_oracle(storage, tol, lattice, shape):
+    from paper_2006_12910_amd import lb
+    nx, ny, nz = shape
+    mask = _spheres(nx, ny, nz, nx + nz)
+    init = _fields(nx, ny, nz, ny)
+    kw = dict(tau=0.8, g=(1e-5, 0.0, -2e-6), walls=(False, True, False), lattice=lattice,
+              kT=1e-4, seed=0x1234ABCD5678)
+    gpu = lb.Domain3(nx, ny, nz, storage=storage, obstacles=mask, init=init, **kw)
+    ora = Oracle3(nx, ny, nz, obstacles=mask, init=init, **kw)
+    for n in (0, 1, 5, 24):
+        gpu.step(n)
+        ora.run(n)
+        drho, err = _errors(gpu, ora)
+        print(f"noise {lattice} {storage} {shape} t {gpu.time}: drho {drho:.2e} err {err:.2e}")
+        assert drho < (1e-13 if storage == "f64" else 1e-6) and err < tol, (n, drho, err)
+    assert abs(gpu.mass() - ora.mass()) / ora.mass() < (1e-13 if storage == "f64" else 1e-7)
+    gpu.close()
+
+
+@pytest.mark.parametrize("storage,tol", CASES)
+@pytest.mark.parametrize("lattice", ["d3q19", "d3q27"])
+def test_noise3_power_law_against_oracle(storage, tol, lattice):
+    """omega = 1/tau* of the node in the noise amplitude."""
+    from paper_2006_12910_amd import lb
+    nx, ny, nz = 66, 12, 5
+    init = _fields(nx, ny, nz, 4)
+    kw = dict(g=(2e-5, 0.0, 0.0), walls=(False, True, False), lattice=lattice, kT=5e-5, seed=77,
+              power_law=dict(n=0.75, K=0.01, tau_min=0.51, tau_max=2.5))
+    gpu = lb.Domain3(nx, ny, nz, storage=storage, init=init, **kw)
+    ora = Oracle3(nx, ny, nz, init=init, **kw)
+    gpu.step(20)
+    ora.run(20)
+    drho, err = _errors(gpu, ora)
+    print(f"noise power law {lattice} {storage}: drho {drho:.2e} err {err:.2e}")
+    assert drho < (1e-13 if storage == "f64" else 1e-6) and err < tol
+    gpu.close()
+
+
+# relative L2 of the velocity after 30 steps: the reduced-storage targets
+# (FP16 with stochastic rounding 1e-3, BF16 1e-2)
+BOUNDS16 = {"f16": 1e-3, "bf16": 1e-2}
+
+
+@pytest.mark.parametrize("storage", list(BOUNDS16))
+@pytest.mark.parametrize("lattice", ["d3q19", "d3q27"])
+def test_noise3_16bit_against_oracle(storage, lattice):
+    from paper_2006_12910_amd import lb
+    nx, ny, nz = 70, 9, 6
+    mask = _spheres(nx, ny, nz, 5)
+    init = _fields(nx, ny, nz, 6)
+    kw = dict(tau=0.8, lattice=lattice, kT=1e-4, seed=31)
+    gpu = lb.Domain3(nx, ny, nz, storage=storage, obstacles=mask, init=init, **kw)
+    ora = Oracle3(nx, ny, nz, obstacles=mask, init=init, **kw)
+    gpu.step(30)
+    ora.run(30)
+    drho, err = _errors(gpu, ora)
+    print(f"noise {lattice} {storage}: drho {drho:.2e} err {err:.2e}")
+    assert err < BOUNDS16[storage]
+    gpu.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("lattice", ["d3q19", "d3q27"])
+def test_noise3_equipartition(storage, lattice):
+    from paper_2006_12910_amd import lb
+    n, kT = 32, 1e-4
+    gpu = lb.Domain3(n, n, n, tau=1.0, storage=storage, lattice=lattice, kT=kT, seed=9)
+    gpu.step(300)
+    ju, dr = [], []
+    for _ in range(60):
+        gpu.step(5)
+        rho, ux, uy, uz = gpu.moments()
+        ju.append([np.mean(rho * u * u) for u in (ux, uy, uz)])
+        dr.append(np.mean((rho - 1.0) ** 2))
+    t = np.mean(ju, 0) / kT
+    d = np.mean(dr) / (3 * kT)
+    print(f"equipartition {lattice} {storage}: <rho u^2>/kT {t}, <drho^2>/3kT {d:.4f}")
+    assert np.abs(t - 1).max() < 0.03 and abs(d - 1) < 0.03
+    gpu.close()
+
+
+def test_noise3_seed_keys_the_noise():
+    from paper_2006_12910_amd import lb
+    runs = []
+    for seed, kT in ((5, 1e-4), (5, 1e-4), (6, 1e-4), (5, 0.0)):
+        g = lb.Domain3(64, 6, 5, tau=0.9, storage="f32", kT=kT, seed=seed)
+        g.step(4)
+        runs.append(g.populations())
+        g.close()
+    quiet = lb.Domain3(64, 6, 5, tau=0.9, storage="f32")
+    quiet.step(4)
+    assert np.array_equal(runs[0], runs[1])
+    assert not np.array_equal(runs[0], runs[2])
+    assert np.array_equal(runs[3], quiet.populations())
+    quiet.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 1e-3)])
+def test_noise3_256cube_against_oracle(storage, tol):
+    """The benchmark lattice: creation (step 0) and one sweep (step 1), every
+    node against the oracle, so that the noise counter is right up to node
+    256^3 - 1."""
+    from paper_2006_12910_amd import lb
+    n = 256
+    kw = dict(tau=0.8, kT=1e-4, seed=2026)
+    gpu = lb.Domain3(n, n, n, storage=storage, **kw)
+    ora = Oracle3(n, n, n, **kw)
+    gpu.step(1)
+    ora.run(1)
+    drho, err = _errors(gpu, ora)
+    print(f"noise 256^3 {storage}: drho {drho:.2e} err {err:.2e}")
+    assert err < tol
+    gpu.close()
