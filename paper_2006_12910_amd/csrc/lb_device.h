@@ -316,14 +316,25 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 // contracted) in a fixed order, so the host's independent implementation of
 // the same definition reproduces it bit-exactly.
 
+// a ^ b ^ k as one gfx950 v_bitop3_b32 (truth table 0x96, the parity of
+// the three inputs); the compiler splits a three-input XOR into two.  k is
+// the round key, the same for every lane of a wave at every call site (a
+// kernel argument or the domain of the workgroup's tile), so it stays in a
+// scalar register.
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t out[4]) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3_key((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3_key((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;

@@ -246,11 +246,11 @@ template <class R> __device__ __forceinline__ constexpr R sqw3(int q, int i) {
 
 // Thermal noise of one collision (Sec. 4, Eqs. NP1-NP2, carried to 3D): the
 // D2Q9 method's law, independent unit noise on every mode other than mass
-// and momentum scaled by sqrt(3 rho kT omega (2 - omega)), drawn without a
-// mode basis.  eta_i = sqrt(w_i) xi_i from q unit normals has covariance
-// W = diag(w); taking away its mass and momentum parts, zeta_i = amp (eta_i
-// - w_i (S + 3 e_i.V)), S = sum eta, V = sum e eta, leaves the covariance
-// amp^2 (W - w w^T - 3 (W e)(W e)^T), the same as the mode form.  Philox
+// and momentum scaled by amp = sqrt(3 rho kT omega (2 - omega)), drawn
+// without a mode basis.  eta_i = amp sqrt(w_i) xi_i from q unit normals has
+// covariance amp^2 W, W = diag(w); taking away its mass and momentum parts,
+// zeta_i = eta_i - w_i (S + 3 e_i.V), S = sum eta, V = sum e eta, leaves the
+// covariance amp^2 (W - w w^T - 3 (W e)(W e)^T), the same as the mode form.  Philox
 // block b of (node, step) gives xi_{6b} .. xi_{6b+5} (three Box-Muller
 // pairs, the D2Q9 recipe); FP32 arithmetic takes the hardware transform,
 // FP64 the exact one.
@@ -276,10 +276,14 @@ __device__ __forceinline__ void noise3(const Dom3 &D, uint32_t node, uint32_t st
     }
   }
   const R amp = sqrt(R(3) * rho * par3<R>(D.kT, D.kT_f) * om * (R(2) - om));
+  // amp sqrt(w) per velocity class (rest, axis, edge, corner): the
+  // amplitude enters once, through eta
+  const R as[4] = {amp * sqw3<R>(Q, 0), amp * sqw3<R>(Q, 1), amp * sqw3<R>(Q, 7),
+                   amp * sqw3<R>(Q, Q - 1)};
   R S = R(0), Vx = R(0), Vy = R(0), Vz = R(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    z[i] = sqw3<R>(Q, i) * R(xi[i]);
+    z[i] = as[cls3(i)] * R(xi[i]);
     S += z[i];
     if (ex(i)) Vx += R(ex(i)) * z[i];
     if (ey(i)) Vy += R(ey(i)) * z[i];
@@ -291,7 +295,7 @@ __device__ __forceinline__ void noise3(const Dom3 &D, uint32_t node, uint32_t st
     if (ex(i)) m += R(3 * ex(i)) * Vx;
     if (ey(i)) m += R(3 * ey(i)) * Vy;
     if (ez(i)) m += R(3 * ez(i)) * Vz;
-    z[i] = amp * fmr(-w3<R>(Q, i), m, z[i]);
+    z[i] = fmr(-w3<R>(Q, i), m, z[i]);
   }
 }
 

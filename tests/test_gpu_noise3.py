@@ -161,3 +161,21 @@ def test_noise3_256cube_against_oracle(storage, tol):
     print(f"noise 256^3 {storage}: drho {drho:.2e} err {err:.2e}")
     assert err < tol
     gpu.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("lattice", ["d3q19", "d3q27"])
+def test_noise3_wide_offsets_give_identical_states(storage, lattice):
+    """The 64-bit-offset sweep with noise draws the same normals: bit-identical
+    states with obstacles and a wall."""
+    from paper_2006_12910_amd import lb
+    nx, ny, nz = 70, 9, 6
+    kw = dict(tau=0.8, storage=storage, lattice=lattice, kT=1e-4, seed=12, walls=(False, True, False),
+              obstacles=_spheres(nx, ny, nz, 3), init=_fields(nx, ny, nz, 2))
+    a = lb.Domain3(nx, ny, nz, **kw)
+    b = lb.Domain3(nx, ny, nz, **kw).set_option(lb.LB3_OPT_WIDE_OFFSETS, 1)
+    a.step(7)
+    b.step(7)
+    assert np.array_equal(a.populations(), b.populations())
+    a.close()
+    b.close()
