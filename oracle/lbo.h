@@ -25,9 +25,12 @@
  *   9. relabelling of particle interiors, covered/uncovered terms
  *
  * Parity: every function is pinned by the oracle tests against closed
- * forms, invariants, published known-answer vectors or brute force, except the
- * covered/uncovered-node force and the LJ repulsion, whose values are
- * "parity unpinned" (only their symmetry properties are tested).
+ * forms, invariants, published known-answer vectors or brute force, except
+ * two that are "parity unpinned": the magnitude of the repulsion of Eq. MP2
+ * (its antisymmetry, cut-off and direction are tested) and the two-step
+ * mean of the link force in the particle update (only its growth /
+ * no-growth property is tested).  The covered/uncovered-node force is
+ * pinned by the momentum balance it restores.
  */
 #ifndef LBO_H
 #define LBO_H
