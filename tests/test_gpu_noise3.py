@@ -146,19 +146,27 @@ def test_noise3_seed_keys_the_noise():
 
 
 @pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 1e-3)])
-def test_noise3_256cube_against_oracle(storage, tol):
-    """The benchmark lattice: creation (step 0) and one sweep (step 1), every
-    node against the oracle, so that the noise counter is right up to node
-    256^3 - 1."""
+@pytest.mark.parametrize("lattice", ["d3q19", "d3q27"])
+@pytest.mark.parametrize("kT", [1e-4, 0.0])
+def test_noise3_256cube_against_oracle(kT, lattice, storage, tol):
+    """The benchmark lattices, with and without noise: creation (step 0) and
+    one sweep (step 1), every node against the oracle, so that the noise
+    counter is right up to node 256^3 - 1.  Without noise the cube starts
+    from a seeded random flow (a state at rest would compare nothing)."""
     from paper_2006_12910_amd import lb
     n = 256
-    kw = dict(tau=0.8, kT=1e-4, seed=2026)
+    kw = dict(tau=0.8, kT=kT, seed=2026, lattice=lattice)
+    if kT == 0.0:
+        rng = np.random.default_rng(17)
+        s = (n, n, n)
+        kw["init"] = (1 + 0.003 * rng.standard_normal(s),) + tuple(
+            0.01 * rng.standard_normal(s) for _ in range(3))
     gpu = lb.Domain3(n, n, n, storage=storage, **kw)
     ora = Oracle3(n, n, n, **kw)
     gpu.step(1)
     ora.run(1)
     drho, err = _errors(gpu, ora)
-    print(f"noise 256^3 {storage}: drho {drho:.2e} err {err:.2e}")
+    print(f"256^3 {lattice} {storage} kT {kT}: drho {drho:.2e} err {err:.2e}")
     assert err < tol
     gpu.close()
 
