@@ -82,7 +82,7 @@ lbo3_sim *lbo3_create(const lbo3_params *p, const uint8_t *mask, const double *r
     return NULL;
   if (p->trt && !(p->magic > 0.0)) return NULL;
   if (p->q != 19 && p->q != 27) return NULL;
-  if (!(p->kT >= 0.0) || (p->kT > 0.0 && p->trt)) return NULL;
+  if (!(p->kT >= 0.0)) return NULL;
   if (p->kT > 0.0 && (double)p->nx * p->ny * p->nz > 4294967295.0) return NULL;
   lbo3_sim *s = (lbo3_sim *)calloc(1, sizeof(lbo3_sim));
   s->p = *p;
@@ -190,15 +190,22 @@ static double powerlaw_tau3(const lbo3_sim *s, const double *fl, double rho, dou
  * sqrt(w_i) xi_i (covariance W), minus their mass and momentum parts,
  * zeta_i = amp (eta_i - w_i S - 3 w_i e_i.V), S = sum eta, V = sum e eta.
  * The xi come from Philox blocks 0, 1, ... of (node, step): block b gives
- * xi_{6b} .. xi_{6b+5}, the first q are used. */
-static void noise3(const lbo3_sim *s, uint32_t node, double rho, double tau, double *zeta) {
+ * xi_{6b} .. xi_{6b+5}, the first q are used.
+ * With TRT the parts of eta symmetric and antisymmetric under e -> -e relax
+ * with omega = 1/tau and 1/tau_minus; each gets its own amplitude, mass
+ * leaving the symmetric part and momentum the antisymmetric one:
+ * zeta = amp+ (eta_s - w S) + amp- (eta_a - 3 w e.V), the two parts being
+ * orthogonal in the weights (BGK: amp+ = amp-, the form above). */
+static void noise3(const lbo3_sim *s, uint32_t node, double rho, double tau, double tau_m,
+                   double *zeta) {
   const lbo3_params *p = &s->p;
   const int q = s->q;
   float xi[30];
   for (int b = 0; 6 * b < q; ++b)
     lbo_normals_block(p->seed, 0u, node, (uint32_t)s->t, (uint32_t)b, xi + 6 * b);
-  const double om = 1.0 / tau;
-  const double amp = sqrt(rho * p->kT * om * (2.0 - om) * 3.0); /* 1 / c_s^2 = 3 */
+  const double om = 1.0 / tau, omm = 1.0 / tau_m;
+  const double amp = sqrt(rho * p->kT * om * (2.0 - om) * 3.0);     /* 1 / c_s^2 = 3 */
+  const double ampm = sqrt(rho * p->kT * omm * (2.0 - omm) * 3.0);
   double eta[27], S = 0.0, V[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < q; ++i) {
     eta[i] = sqrt(s->w[i]) * (double)xi[i];
@@ -208,8 +215,10 @@ static void noise3(const lbo3_sim *s, uint32_t node, double rho, double tau, dou
     V[2] += EZ[i] * eta[i];
   }
   for (int i = 0; i < q; ++i) {
+    const int o = opposite(i);
+    const double es = 0.5 * (eta[i] + eta[o]), ea = 0.5 * (eta[i] - eta[o]);
     const double eV = EX[i] * V[0] + EY[i] * V[1] + EZ[i] * V[2];
-    zeta[i] = amp * (eta[i] - s->w[i] * S - 3.0 * s->w[i] * eV);
+    zeta[i] = amp * (es - s->w[i] * S) + ampm * (ea - 3.0 * s->w[i] * eV);
   }
 }
 
@@ -236,18 +245,20 @@ static void collide(lbo3_sim *s) {
         double uz = jz / rho + tm * p->gz;
         if (!p->trt) {
           double zeta[27] = {0.0};
-          if (p->kT > 0.0) noise3(s, (uint32_t)NODE(s, x, y, z), rho, tau, zeta);
+          if (p->kT > 0.0) noise3(s, (uint32_t)NODE(s, x, y, z), rho, tau, tau, zeta);
           for (int i = 0; i < s->q; ++i)
             s->fs[IDX(s, i, x, y, z)] =
                 fl[i] - (fl[i] - feq(i, s->w[i], rho, ux, uy, uz)) / tau + zeta[i];
           continue;
         }
+        double zeta[27] = {0.0};
+        if (p->kT > 0.0) noise3(s, (uint32_t)NODE(s, x, y, z), rho, tau, tm, zeta);
         for (int i = 0; i < s->q; ++i) {
           const int o = opposite(i);
           const double fsym = 0.5 * (fl[i] + fl[o]), fanti = 0.5 * (fl[i] - fl[o]);
           const double ei = feq(i, s->w[i], rho, ux, uy, uz), eo = feq(o, s->w[o], rho, ux, uy, uz);
           const double esym = 0.5 * (ei + eo), eanti = 0.5 * (ei - eo);
-          s->fs[IDX(s, i, x, y, z)] = fl[i] - (fsym - esym) / tau - (fanti - eanti) / tm;
+          s->fs[IDX(s, i, x, y, z)] = fl[i] - (fsym - esym) / tau - (fanti - eanti) / tm + zeta[i];
         }
       }
 }

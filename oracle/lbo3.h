@@ -1,7 +1,7 @@
 /*
  * lbo3.h -- CPU oracle (FP64) of the three-dimensional lattice-Boltzmann step
  * on D3Q19 or D3Q27: BGK with the velocity-shift body force (Sec. 2), or its
- * two-relaxation-time (TRT) variant, optionally with thermal noise (BGK),
+ * two-relaxation-time (TRT) variant, optionally with thermal noise,
  * pull streaming with periodic wrap, halfway bounce-back on solid nodes.
  * TEST INFRASTRUCTURE ONLY.
  *
@@ -31,7 +31,8 @@ typedef struct {
   int32_t power_law;
   double n_index, K, tau_min, tau_max;
   /* kT > 0: thermal noise of the fluctuating method (Sec. 4) added to every
-   * collision, BGK only; Philox key (lo32(seed), hi32(seed)) */
+   * collision (with TRT, each of the symmetric and antisymmetric parts at
+   * its own rate's amplitude); Philox key (lo32(seed), hi32(seed)) */
   double kT;
   uint64_t seed;
 } lbo3_params;

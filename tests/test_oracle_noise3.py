@@ -8,7 +8,9 @@ formula: the noise carries no mass or momentum; on an orthonormal basis of
 the non-conserved modes built here (numpy SVD) its coordinates are
 uncorrelated with variance 3 kT omega (2 - omega) at rho = 1; and a periodic
 box relaxes to equipartition, <rho u_a^2> = kT and <drho^2> = rho kT / c_s^2
-= 3 kT.  The normals are the D2Q9 generator's with the Philox counter's third
+= 3 kT; with the two-relaxation-time collision, the even and odd
+non-conserved modes each at their own rate's amplitude, uncorrelated, and
+the same equipartition.  The normals are the D2Q9 generator's with the Philox counter's third
 word as a block index; block 0 is the D2Q9 draw itself."""
 import numpy as np
 import pytest
@@ -114,8 +116,69 @@ def test_equipartition(lattice):
     assert abs(np.mean(dr) / (3 * kT) - 1) < 0.03, np.mean(dr) / (3 * kT)
 
 
-def test_rejects_noise_with_trt_or_negative_kT():
-    with pytest.raises(ValueError):
-        Oracle3(8, 8, 8, collision="trt", kT=1e-4)
+def _parity_bases(q, ex, ey, ez, w):
+    """Orthonormal bases (in zeta / sqrt(w) coordinates) of the non-conserved
+    modes even and odd under e -> -e: the even ones orthogonal to sqrt(w),
+    the odd ones to sqrt(w) e."""
+    pairs = [(i, i + 1) for i in range(1, q, 2)]
+    bs = np.zeros((q, len(pairs) + 1))
+    bs[0, 0] = 1.0
+    ba = np.zeros((q, len(pairs)))
+    for k, (i, j) in enumerate(pairs):
+        bs[i, k + 1] = bs[j, k + 1] = np.sqrt(0.5)
+        ba[i, k], ba[j, k] = np.sqrt(0.5), -np.sqrt(0.5)
+    sw = np.sqrt(w)
+    _, _, v = np.linalg.svd((bs.T @ sw)[None, :])
+    even = bs @ v[1:].T
+    _, _, v = np.linalg.svd((ba.T @ np.stack([sw * ex, sw * ey, sw * ez], 1)).T)
+    odd = ba @ v[3:].T
+    return even, odd
+
+
+@pytest.mark.parametrize("lattice", LATTICES)
+def test_trt_mode_covariance_per_parity(lattice):
+    """With TRT the even non-conserved modes carry omega (2 - omega) at
+    omega = 1/tau and the odd ones at 1/tau_minus: tau = 1.5, magic 0.05
+    (tau_minus = 0.55) makes them 0.889 and 0.331.  One step from rest:
+    f* = w + zeta."""
+    q = Q[lattice]
+    ex, ey, ez, w = lattice3(q)
+    kT, tau, magic = 1e-4, 1.5, 0.05
+    n = 32
+    o = Oracle3(n, n, n, tau=tau, lattice=lattice, kT=kT, seed=77, collision="trt", magic=magic)
+    o.run(1)
+    y = (_post_collision(o, q).reshape(q, -1) - w[:, None]) / np.sqrt(w)[:, None]
+    even, odd = _parity_bases(q, ex, ey, ez, w)
+    assert even.shape[1] + odd.shape[1] == q - 4
+    tm = 0.5 + magic / (tau - 0.5)
+    nsamp = y.shape[1]
+    for basis, om in ((even, 1 / tau), (odd, 1 / tm)):
+        c = basis.T @ y
+        cov = (c @ c.T) / nsamp / (3 * kT * om * (2 - om))
+        assert np.abs(np.diag(cov) - 1).max() < 6 * np.sqrt(2 / nsamp)
+        assert np.abs(cov - np.diag(np.diag(cov))).max() < 6 * np.sqrt(1 / nsamp)
+    cross = (even.T @ y) @ (odd.T @ y).T / nsamp / (3 * kT)
+    assert np.abs(cross).max() < 6 * np.sqrt(1 / nsamp)
+
+
+@pytest.mark.parametrize("lattice", LATTICES)
+def test_trt_equipartition(lattice):
+    n, kT = 12, 1e-4
+    o = Oracle3(n, n, n, tau=1.0, lattice=lattice, kT=kT, seed=11, collision="trt", magic=0.05)
+    o.run(300)
+    ju, dr = [], []
+    for _ in range(100):
+        o.run(4)
+        rho, ux, uy, uz = o.moments()
+        ju.append([np.mean(rho * u * u) for u in (ux, uy, uz)])
+        dr.append(np.mean((rho - 1.0) ** 2))
+    t = np.mean(ju, 0) / kT
+    assert np.abs(t - 1).max() < 0.03, t
+    assert abs(np.mean(dr) / (3 * kT) - 1) < 0.03, np.mean(dr) / (3 * kT)
+
+
+def test_rejects_negative_kT():
     with pytest.raises(ValueError):
         Oracle3(8, 8, 8, kT=-1e-4)
+    with pytest.raises(ValueError):
+        Oracle3(8, 8, 8, collision="trt", kT=-1e-4)
