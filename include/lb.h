@@ -419,7 +419,7 @@ lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms);
  * magic = (tau - 1/2)^2 is BGK.  Power law (Sec. 5): the local tau* from the
  * non-equilibrium stress as on the 2D domains, with all nine components of
  * the 3D stress in its Frobenius norm (with TRT, tau_minus follows tau*).
- * Thermal noise (Sec. 4, Eqs. NP1-NP2 carried to 3D), BGK only: kT > 0 adds
+ * Thermal noise (Sec. 4, Eqs. NP1-NP2 carried to 3D): kT > 0 adds
  * to every collision the Gaussian whose covariance is
  * 3 rho kT omega (2 - omega) (W - w w^T - 3 (W e)(W e)^T), W = diag(w)
  * (omega = 1/tau*, local with the power law): independent unit noise on
@@ -432,8 +432,11 @@ lb_status lb_batch_autotune(lb_batch *b, int32_t steps, double *best_ms);
  * (lb_noise_normals with domain_id 0 is block 0).  Step t is the collision that produces the
  * state of time t (the one in lb3_create_domain is t = 0).  FP64 storage
  * evaluates the transforms exactly as that recipe defines them, the others
- * through the hardware's log2 / sin / cos (within 1e-6 of it).  Not with
- * TRT (LB_EUNSUPPORTED); the lattice must have fewer than 2^32 nodes.
+ * through the hardware's log2 / sin / cos (within 1e-6 of it).  With TRT
+ * the parts of eta even and odd under e -> -e relax at omega = 1/tau and
+ * 1/tau_minus, and each takes its own rate's amplitude:
+ * zeta = amp+ (eta_s - w S) + amp- (eta_a - 3 w e.V).  The lattice must
+ * have fewer than 2^32 nodes (LB_EUNSUPPORTED).
  * Same conventions as above: caller-owned 256-byte aligned workspace,
  * stream-ordered calls, errors through lb_last_error.  No particles. */
 #define LB3_BGK 0

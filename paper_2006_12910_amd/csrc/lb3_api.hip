@@ -96,8 +96,6 @@ lb_status validate3(const lb3_domain_desc *d) {
   if (d->collision == LB3_TRT && !(d->magic > 0.0 && std::isfinite(d->magic)))
     return fail3(LB_EINVAL, "TRT magic number must be finite and > 0");
   if (!(d->kT >= 0.0) || !std::isfinite(d->kT)) return fail3(LB_EINVAL, "kT must be finite and >= 0");
-  if (d->kT > 0.0 && d->collision == LB3_TRT)
-    return fail3(LB_EUNSUPPORTED, "thermal noise needs the BGK collision");
   if (d->kT > 0.0 && (double)d->nx * d->ny * d->nz >= 4294967296.0)
     return fail3(LB_EUNSUPPORTED, "thermal noise needs fewer than 2^32 nodes");
   if (!(d->rho0 > 0.0) || !std::isfinite(d->rho0)) return fail3(LB_EINVAL, "rho0 must be > 0");
@@ -217,7 +215,7 @@ lb_status push_desc3(lb3_domain *d) {
 
 namespace {
 
-template <int ST, int Q, bool PL, bool NZ>
+template <int ST, int Q, bool PL, int NZ>
 void launch_sweep3_qn(const lb3_domain *d, unsigned blocks, int k) {
   const dim3 g(blocks), b(256);
   if (d->L.solids) {
@@ -233,8 +231,10 @@ void launch_sweep3_qn(const lb3_domain *d, unsigned blocks, int k) {
   }
 }
 template <int ST, int Q, bool PL> void launch_sweep3_q(const lb3_domain *d, unsigned blocks, int k) {
-  if (d->hd.noise) launch_sweep3_qn<ST, Q, PL, true>(d, blocks, k);
-  else launch_sweep3_qn<ST, Q, PL, false>(d, blocks, k);
+  // noise kind: none, with BGK, with TRT (the last needs more registers)
+  if (!d->hd.noise) launch_sweep3_qn<ST, Q, PL, 0>(d, blocks, k);
+  else if (d->hd.trt) launch_sweep3_qn<ST, Q, PL, 2>(d, blocks, k);
+  else launch_sweep3_qn<ST, Q, PL, 1>(d, blocks, k);
 }
 template <int ST> void launch_sweep3_st(const lb3_domain *d, unsigned blocks, int k) {
   const bool pl = d->desc.power_law != 0;

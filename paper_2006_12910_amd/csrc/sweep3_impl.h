@@ -253,10 +253,13 @@ template <class R> __device__ __forceinline__ constexpr R sqw3(int q, int i) {
 // covariance amp^2 (W - w w^T - 3 (W e)(W e)^T), the same as the mode form.  Philox
 // block b of (node, step) gives xi_{6b} .. xi_{6b+5} (three Box-Muller
 // pairs, the D2Q9 recipe); FP32 arithmetic takes the hardware transform,
-// FP64 the exact one.
-template <class R, int Q>
+// FP64 the exact one.  With TRT the parts of eta even and odd under
+// e -> -e relax with omega and omega_m; each carries its own amplitude,
+// mass leaving the even part and momentum the odd one:
+// zeta = amp (eta_s - w S) + amp_m (eta_a - 3 w e.V) (orthogonal parts).
+template <class R, int Q, bool TRTN>
 __device__ __forceinline__ void noise3(const Dom3 &D, uint32_t node, uint32_t step, R rho, R om,
-                                       R z[Q]) {
+                                       R omm, R z[Q]) {
   constexpr int PAIRS = (Q + 1) / 2;
   float xi[2 * PAIRS];
 #pragma unroll
@@ -275,7 +278,34 @@ __device__ __forceinline__ void noise3(const Dom3 &D, uint32_t node, uint32_t st
       }
     }
   }
-  const R amp = sqrt(R(3) * rho * par3<R>(D.kT, D.kT_f) * om * (R(2) - om));
+  const R kT3 = R(3) * rho * par3<R>(D.kT, D.kT_f);
+  const R amp = sqrt(kT3 * om * (R(2) - om));
+  if constexpr (TRTN) {
+    const R ampm = sqrt(kT3 * omm * (R(2) - omm));
+    R S = R(0), Vx = R(0), Vy = R(0), Vz = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      z[i] = sqw3<R>(Q, i) * R(xi[i]);
+      S += z[i];
+      if (ex(i)) Vx += R(ex(i)) * z[i];
+      if (ey(i)) Vy += R(ey(i)) * z[i];
+      if (ez(i)) Vz += R(ez(i)) * z[i];
+    }
+    z[0] = amp * fmr(-w3<R>(Q, 0), S, z[0]);
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {  // the pair (i, i + 1), e_{i+1} = -e_i
+      const R w = w3<R>(Q, i);
+      R eV = R(0);
+      if (ex(i)) eV += R(ex(i)) * Vx;
+      if (ey(i)) eV += R(ey(i)) * Vy;
+      if (ez(i)) eV += R(ez(i)) * Vz;
+      const R es = amp * fmr(R(0.5), z[i] + z[i + 1], -w * S);
+      const R ea = ampm * fmr(R(0.5), z[i] - z[i + 1], R(-3) * w * eV);
+      z[i] = es + ea;
+      z[i + 1] = es - ea;
+    }
+    return;
+  }
   // amp sqrt(w) per velocity class (rest, axis, edge, corner): the
   // amplitude enters once, through eta
   const R as[4] = {amp * sqw3<R>(Q, 0), amp * sqw3<R>(Q, 1), amp * sqw3<R>(Q, 7),
@@ -310,7 +340,8 @@ __device__ __forceinline__ void noise3(const Dom3 &D, uint32_t node, uint32_t st
 // increments before the one final rounding, as the D2Q9 sweep does (the
 // momentum term of the stored values would otherwise round the body force
 // of slow flows with a bias).
-template <class R, int Q, bool PL, bool NOISE>
+// NZ: no noise (0), noise with BGK (1) or with TRT (2)
+template <class R, int Q, bool PL, int NZ>
 __device__ __forceinline__ void collide3(const Dom3 &D, R d[Q], uint32_t node, uint32_t step) {
   R drho = d[0];
 #pragma unroll
@@ -374,12 +405,12 @@ __device__ __forceinline__ void collide3(const Dom3 &D, R d[Q], uint32_t node, u
 #pragma unroll
       for (int i = 1; i < Q; ++i) inc[i] = om * (eq[i] - d[i]);
     }
-    if constexpr (NOISE) {
+    if constexpr (NZ != 0) {
       // the noise has no mass or momentum: the rest population's share
       // follows from the mass balance below, its rounding from the momentum
       // correction
       R z[Q];
-      noise3<R, Q>(D, node, step, rho, om, z);
+      noise3<R, Q, NZ == 2>(D, node, step, rho, om, omm, z);
 #pragma unroll
       for (int i = 1; i < Q; ++i) inc[i] += z[i];
     }
@@ -423,9 +454,9 @@ __device__ __forceinline__ void collide3(const Dom3 &D, R d[Q], uint32_t node, u
 #pragma unroll
       for (int i = 0; i < Q; ++i) d[i] = fmr(om, eq[i] - d[i], d[i]);
     }
-    if constexpr (NOISE) {
+    if constexpr (NZ != 0) {
       R z[Q];
-      noise3<R, Q>(D, node, step, rho, om, z);
+      noise3<R, Q, NZ == 2>(D, node, step, rho, om, omm, z);
 #pragma unroll
       for (int i = 0; i < Q; ++i) d[i] += z[i];
     }
@@ -443,7 +474,7 @@ __device__ __forceinline__ void collide3(const Dom3 &D, R d[Q], uint32_t node, u
 // symmetric and antisymmetric parts.  Relaxation is applied to the stored
 // values directly (no increment form: the rounding to 16 bits is far
 // coarser than the FP32 arithmetic).
-template <int Q, bool PL, bool NOISE>
+template <int Q, bool PL, int NZ>
 __device__ __forceinline__ void collide3_scaled(const Dom3 &D, float d[Q], uint32_t node, uint32_t step) {
   constexpr int P = (Q - 1) / 2;  // direction pairs: k covers 2k - 1 and 2k
   float ps[P + 1], pd[P + 1];
@@ -544,9 +575,9 @@ __device__ __forceinline__ void collide3_scaled(const Dom3 &D, float d[Q], uint3
       d[2 * k] += fmr(om, sym, -t);
     }
   }
-  if constexpr (NOISE) {
+  if constexpr (NZ != 0) {
     float z[Q];
-    noise3<float, Q>(D, node, step, rho, om, z);
+    noise3<float, Q, NZ == 2>(D, node, step, rho, om, omm, z);
 #pragma unroll
     for (int i = 0; i < Q; ++i) d[i] = fmr(scale3(Q, i), z[i], d[i]);
   }
@@ -613,8 +644,8 @@ constexpr int sweep3_waves(int st, int q, bool pl, bool noise) {
   return noise && base > cap ? cap : base;
 }
 
-template <int ST, bool SOLIDS, bool WIDE, int Q, bool PL, bool NOISE>
-__global__ __launch_bounds__(256, sweep3_waves(ST, Q, PL, NOISE)) void k_sweep3(const Dom3 *__restrict__ Dp, int kstep) {
+template <int ST, bool SOLIDS, bool WIDE, int Q, bool PL, int NZ>
+__global__ __launch_bounds__(256, sweep3_waves(ST, Q, PL, NZ != 0)) void k_sweep3(const Dom3 *__restrict__ Dp, int kstep) {
   using S = S3<ST>;
   using T = typename S::T;
   using R = typename S::R;
@@ -688,8 +719,8 @@ __global__ __launch_bounds__(256, sweep3_waves(ST, Q, PL, NOISE)) void k_sweep3(
     // collision produces
     const uint32_t nn = ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)nx + (uint32_t)x;
     const uint32_t step = (uint32_t)(T0 + 1);
-    if constexpr (sizeof(T) == 2) collide3_scaled<Q, PL, NOISE>(D, d, nn, step);
-    else collide3<R, Q, PL, NOISE>(D, d, nn, step);
+    if constexpr (sizeof(T) == 2) collide3_scaled<Q, PL, NZ>(D, d, nn, step);
+    else collide3<R, Q, PL, NZ>(D, d, nn, step);
     if (!(fabs((double)d[0]) < 1e30)) atomicOr(D.health, 1u);
   }
   const uint32_t h = sizeof(T) == 2 && D.sr ? round_bits3(D, (uint32_t)node, (uint32_t)T0) : 0u;
@@ -764,12 +795,15 @@ __global__ __launch_bounds__(256) void k_init3(const Dom3 *__restrict__ Dp, cons
   }
   if (!solid) {
     const uint32_t nn = (uint32_t)n, step = (uint32_t)*D.tstep;
-    if (D.noise) {
-      if (D.pl) collide3<R, Q, true, true>(D, d, nn, step);
-      else collide3<R, Q, false, true>(D, d, nn, step);
+    if (D.noise && D.trt) {
+      if (D.pl) collide3<R, Q, true, 2>(D, d, nn, step);
+      else collide3<R, Q, false, 2>(D, d, nn, step);
+    } else if (D.noise) {
+      if (D.pl) collide3<R, Q, true, 1>(D, d, nn, step);
+      else collide3<R, Q, false, 1>(D, d, nn, step);
     } else {
-      if (D.pl) collide3<R, Q, true, false>(D, d, nn, step);
-      else collide3<R, Q, false, false>(D, d, nn, step);
+      if (D.pl) collide3<R, Q, true, 0>(D, d, nn, step);
+      else collide3<R, Q, false, 0>(D, d, nn, step);
     }
   }
 #pragma unroll

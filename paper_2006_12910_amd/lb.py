@@ -471,7 +471,7 @@ class Domain3:
         storage "f64" | "f32" | "f16" | "bf16"; rounding "nearest" | "stochastic"
         (16-bit storage only; its default there); lattice "d3q19" | "d3q27";
         power_law: dict(n, K, tau_min=0.51, tau_max=2.5); kT > 0: thermal noise
-        (BGK), keyed by seed."""
+        (BGK or TRT), keyed by seed."""
         lib = library()
         d = Domain3Desc()
         d.abi_version = ABI_VERSION

@@ -1,7 +1,7 @@
 """The 3D sweeps at degenerate sizes against the oracle: the smallest lattice
 (3 x 3 x 3, where x - 1 and x + 1 both wrap and most lanes of the 64 x 4
 tile are idle), one node past a full tile in x, and a thin z extent; every
-feature (BGK, TRT, thermal noise, power law) on both lattices, FP64 to
+feature (BGK, TRT, thermal noise with either, power law) on both lattices, FP64 to
 accumulated rounding, FP32 to the 1e-5 target, FP16 deviations with
 stochastic rounding to the 1e-3 target."""
 import numpy as np
@@ -16,6 +16,7 @@ FEATURES = {
     "bgk": dict(),
     "trt": dict(collision="trt", magic=3.0 / 16.0),
     "noise": dict(kT=1e-4, seed=8),
+    "trt_noise": dict(collision="trt", magic=0.05, kT=1e-4, seed=9),
     "power": dict(power_law=dict(n=0.75, K=0.01)),
 }
 TOL = {"f64": 1e-11, "f32": 1e-5, "f16": 1e-3}

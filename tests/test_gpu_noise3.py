@@ -187,3 +187,47 @@ def test_noise3_wide_offsets_give_identical_states(storage, lattice):
     assert np.array_equal(a.populations(), b.populations())
     a.close()
     b.close()
+
+
+TRT = dict(collision="trt", magic=0.05)
+
+
+@pytest.mark.parametrize("storage,tol", CASES + [("f16", 1e-3)])
+@pytest.mark.parametrize("lattice", ["d3q19", "d3q27"])
+def test_noise3_trt_against_oracle(storage, tol, lattice):
+    """TRT with noise: the even and odd parts at their own rates' amplitudes
+    (tau = 0.9, magic 0.05: tau_minus = 0.625)."""
+    from paper_2006_12910_amd import lb
+    nx, ny, nz = 70, 9, 6
+    mask = _spheres(nx, ny, nz, 9)
+    init = _fields(nx, ny, nz, 10)
+    kw = dict(tau=0.9, g=(1e-5, 0.0, 2e-6), walls=(False, False, True), lattice=lattice, kT=1e-4,
+              seed=4242, **TRT)
+    gpu = lb.Domain3(nx, ny, nz, storage=storage, obstacles=mask, init=init, **kw)
+    ora = Oracle3(nx, ny, nz, obstacles=mask, init=init, **kw)
+    gpu.step(30)
+    ora.run(30)
+    drho, err = _errors(gpu, ora)
+    print(f"TRT noise {lattice} {storage}: drho {drho:.2e} err {err:.2e}")
+    assert err < tol and drho < {"f64": 1e-13, "f32": 1e-6, "f16": 1e-4}[storage]
+    gpu.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("lattice", ["d3q19", "d3q27"])
+def test_noise3_trt_equipartition(storage, lattice):
+    from paper_2006_12910_amd import lb
+    n, kT = 32, 1e-4
+    gpu = lb.Domain3(n, n, n, tau=1.0, storage=storage, lattice=lattice, kT=kT, seed=19, **TRT)
+    gpu.step(300)
+    ju, dr = [], []
+    for _ in range(60):
+        gpu.step(5)
+        rho, ux, uy, uz = gpu.moments()
+        ju.append([np.mean(rho * u * u) for u in (ux, uy, uz)])
+        dr.append(np.mean((rho - 1.0) ** 2))
+    t = np.mean(ju, 0) / kT
+    d = np.mean(dr) / (3 * kT)
+    print(f"TRT equipartition {lattice} {storage}: <rho u^2>/kT {t}, <drho^2>/3kT {d:.4f}")
+    assert np.abs(t - 1).max() < 0.03 and abs(d - 1) < 0.03
+    gpu.close()
